@@ -1,0 +1,208 @@
+"""Derivatives and solvers of the implicit stage (oracle; test infrastructure only).
+
+* Jacobian actions by the complex step: J dk = Im R(k + i h dk) / h.  Every operation in
+  the residual is analytic (polynomials, division, sqrt, tanh, real powers), so this is
+  the exact directional derivative up to rounding; it replaces the paper's automatic
+  differentiation of the quadrature-point kernel (eq. pa_jac_action).  The oracle holds
+  no hand-written tangent.
+* Jacobi preconditioned CG (Sec. 2.2 mass solves), restarted flexible GMRES and inexact
+  Newton with a backtracking line search that rejects steps producing a non-positive
+  Jacobian determinant (Sec. 3.5, eq. newton_linear).
+* The implicit midpoint rule: k = f(u + dt/2 k), u+ = u + dt k.
+"""
+import numpy as np
+
+CS_H = 1.0e-30
+
+
+def jvp_cs(fun, x, dx, h=CS_H):
+    """Directional derivative of ``fun`` at x along dx by the complex step."""
+    return np.imag(fun(x + 1j * h * dx)) / h
+
+
+def jvp_fd(fun, x, dx, eps=1.0e-7):
+    """Central finite difference (fun(x + eps dx) - fun(x - eps dx)) / (2 eps)."""
+    return (fun(x + eps * dx) - fun(x - eps * dx)) / (2.0 * eps)
+
+
+def dense_jacobian(fun, x):
+    """Dense Jacobian by complex-step columns (brute force; tiny problems only)."""
+    n = x.size
+    cols = []
+    for j in range(n):
+        ej = np.zeros(n)
+        ej[j] = 1.0
+        cols.append(jvp_cs(fun, x, ej))
+    return np.stack(cols, axis=1)
+
+
+def pcg(apply, b, diag, rtol=1e-12, maxit=1000):
+    """Jacobi-preconditioned conjugate gradients on an SPD operator."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = r / diag
+    p = z.copy()
+    rz = np.dot(r, z)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0, 0.0
+    it = 0
+    while it < maxit:
+        if np.linalg.norm(r) <= rtol * nb:
+            break
+        Ap = apply(p)
+        alpha = rz / np.dot(p, Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        z = r / diag
+        rz_new = np.dot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        it += 1
+    return x, it, np.linalg.norm(r) / nb
+
+
+def fgmres(apply, b, precond, restart=30, rtol=1e-6, maxit=60, x0=None):
+    """Right-preconditioned restarted flexible GMRES (Arnoldi with modified Gram-Schmidt).
+
+    Returns (x, iterations, final relative residual estimate).
+    """
+    n = b.size
+    x = np.zeros(n) if x0 is None else x0.copy()
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0, 0.0
+    total = 0
+    rel = 1.0
+    while total < maxit:
+        r = b - apply(x) if total > 0 or x0 is not None else b.copy()
+        beta = np.linalg.norm(r)
+        rel = beta / nb
+        if rel <= rtol:
+            break
+        m = min(restart, maxit - total)
+        V = np.zeros((m + 1, n))
+        Z = np.zeros((m, n))
+        H = np.zeros((m + 1, m))
+        V[0] = r / beta
+        g = np.zeros(m + 1)
+        g[0] = beta
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        j_end = 0
+        for j in range(m):
+            Z[j] = precond(V[j])
+            wv = apply(Z[j])
+            for i in range(j + 1):
+                H[i, j] = np.dot(wv, V[i])
+                wv = wv - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(wv)
+            if H[j + 1, j] > 0:
+                V[j + 1] = wv / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            total += 1
+            j_end = j + 1
+            rel = abs(g[j + 1]) / nb
+            if rel <= rtol or total >= maxit:
+                break
+        y = np.linalg.solve(np.triu(H[:j_end, :j_end]), g[:j_end])
+        x = x + Z[:j_end].T @ y
+        if rel <= rtol:
+            break
+    return x, total, rel
+
+
+class NewtonOptions:
+    def __init__(self, tol=1e-10, max_newton=30, restart=30, gmres_rtol=1e-6,
+                 gmres_maxit=60, max_halvings=10):
+        self.tol, self.max_newton = tol, max_newton
+        self.restart, self.gmres_rtol, self.gmres_maxit = restart, gmres_rtol, gmres_maxit
+        self.max_halvings = max_halvings
+
+
+class NewtonFailure(RuntimeError):
+    def __init__(self, kind, msg):
+        super().__init__(msg)
+        self.kind = kind
+
+
+def block_preconditioner(hyd):
+    """P^-1 = diag(I, Mhat_V^-1, M_E^-1): the mass-only block preconditioner (exact solves)."""
+    def apply(r):
+        rx, rv, re = hyd.split(r)
+        return np.concatenate([rx, hyd.mass_v_solve(rv), hyd.mass_e_inv(re)])
+    return apply
+
+
+def newton_stage(hyd, u, tau, k0, opts=None, stats=None):
+    """Solve R(k; tau, u) = 0 by inexact Newton-FGMRES with the detJ line search.
+
+    Converged when ||R(k)|| <= tol ||R(0; tau, u)||.
+    """
+    opts = opts or NewtonOptions()
+    R = lambda k: hyd.residual(k, u, tau)
+    r0 = np.linalg.norm(R(np.zeros_like(u)))
+    prec = block_preconditioner(hyd)
+    k = k0.copy()
+    hist = []
+    gm_total = 0
+    for it in range(opts.max_newton + 1):
+        r = R(k)
+        nr = np.linalg.norm(r)
+        hist.append(nr / r0)
+        if nr <= opts.tol * r0:
+            break
+        if it == opts.max_newton:
+            raise NewtonFailure("ENOCONV", "Newton did not converge")
+        J = lambda dk, k=k: jvp_cs(R, k, dk)
+        dk, its, _ = fgmres(J, -r, prec, opts.restart, opts.gmres_rtol, opts.gmres_maxit)
+        gm_total += its
+        alpha = 1.0
+        for _ in range(opts.max_halvings + 1):
+            if hyd.min_detj(u + tau * (k + alpha * dk)) > 0.0:
+                break
+            alpha *= 0.5
+        else:
+            raise NewtonFailure("ETANGLED", "line search could not keep detJ > 0")
+        k = k + alpha * dk
+    if stats is not None:
+        stats.update(newton=len(hist) - 1, gmres=gm_total, hist=hist)
+    return k
+
+
+def implicit_midpoint_step(hyd, u, dt, k_guess, opts=None, stats=None):
+    """One implicit midpoint step: k = f(u + dt/2 k), returns (u + dt k, k)."""
+    k = newton_stage(hyd, u, 0.5 * dt, k_guess, opts, stats)
+    return u + dt * k, k
+
+
+def plain_guess(hyd, u, history):
+    """Plain initial iterate: explicit rate at the first step, then k_{n-1}, then 2 k_{n-1} - k_{n-2}."""
+    if len(history) == 0:
+        return hyd.rate(u)
+    if len(history) == 1:
+        return history[-1].copy()
+    return 2.0 * history[-1] - history[-2]
+
+
+def run_midpoint(hyd, u0, dt, steps, opts=None):
+    """Run ``steps`` implicit midpoint steps from u0 with the plain guess; returns states and stats."""
+    u = u0.copy()
+    hist_k, states, allstats = [], [u.copy()], []
+    for _ in range(steps):
+        st = {}
+        g = plain_guess(hyd, u, hist_k)
+        u, k = implicit_midpoint_step(hyd, u, dt, g, opts, st)
+        hist_k.append(k)
+        states.append(u.copy())
+        allstats.append(st)
+    return states, hist_k, allstats
