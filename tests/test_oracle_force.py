@@ -175,3 +175,44 @@ def test_affine_viscous_stress_is_uniform():
     assert np.abs(F1.reshape(2, -1)[:, interior]).max() < 1e-13
     ratio = Ftv / (np.prod(m.h) / 4.0)  # int phi_j = |Omega_e| / k^2
     assert np.allclose(ratio, ratio[0], rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim,k,visc", [(2, 2, False), (2, 3, True), (3, 2, True), (3, 1, False)])
+def test_affinely_deformed_mesh_closed_form(dim, k, visc):
+    """x = B x0 (det B != 1), v = A x with non-symmetric A, constant e.
+
+    The stress is uniform: rho = rho0 / det B (strong mass conservation), p = (g-1) rho e+,
+    grad v = A.  In the strong-expansion limit (div v >> delta_scale) the smoothed
+    viscosity reduces to mu = rho h q2 delta_v with h = h0 (det B)^(1/d), delta_v = h tr A.
+    Then interior (F 1) = 0 and (F^T v)_j = (sigma : A) * |det B| |Omega_e| / k^d.
+    """
+    vo = ViscosityOptions(on=visc, mode="const", width=1e-3)
+    H = Hydro("uniform", (2,) * dim, k, visc=vo)
+    u = H.init_state()
+    x, v, e = H.split(u)
+    rng = np.random.default_rng(11)
+    B = np.eye(dim) + 0.25 * rng.standard_normal((dim, dim))
+    detB = np.linalg.det(B)
+    assert detB > 0.3
+    A = 0.5 * rng.standard_normal((dim, dim))
+    A += (400.0 - np.trace(A)) / dim * np.eye(dim)  # strong expansion, tr A = 400
+    X = B @ x.reshape(dim, -1)
+    V = A @ X
+    w = np.concatenate([X.ravel(), V.ravel(), e])
+    F1, Ftv = H.force(w)
+    m = H.mesh
+    ep = e_plus(np.array(2.5))
+    rho = 1.0 / detB
+    p = 0.4 * rho * ep
+    sigma = -p * np.eye(dim)
+    if visc:
+        h = vo.h0 * detB ** (1.0 / dim)
+        mu = rho * h * 1.0 * (h * np.trace(A))
+        sigma = sigma + mu * 0.5 * (A + A.T)
+    expect = np.sum(sigma * A) * detB * np.prod(m.h) / k ** dim
+    assert np.allclose(Ftv, expect, rtol=1e-9), (Ftv[:3], expect)
+    interior = np.ones(m.N, dtype=bool)
+    for c in range(dim):
+        interior &= ~m.constrained[c]
+    if interior.any():
+        assert np.abs(F1.reshape(dim, -1)[:, interior]).max() < 1e-10 * np.abs(F1).max()
