@@ -1,0 +1,251 @@
+/*
+ * ilh.h -- C ABI of the MI355X (gfx950) implicit high-order Lagrangian hydrodynamics library.
+ *
+ * The library evaluates, matrix-free, the curvilinear finite element force operator of
+ * Andrej et al., "Implicit Lagrangian Hydrodynamics with High-Order Finite Elements"
+ * (Sec. 2.1 eqs. v_semi, e_semi, matrices; Sec. 2.2 partial assembly, eq. decompose),
+ * its Jacobian action (Sec. 3.1 eq. pa_jac_action) as a hand-written tangent, and the
+ * implicit-midpoint Newton-Krylov stage solve (Sec. 3.5 eqs. nonlinear_system,
+ * newton_linear).
+ *
+ * Conventions for every call:
+ *  - Pointer arguments are DEVICE pointers owned by the caller unless marked "host".
+ *    The library never frees or retains them.
+ *  - Work is enqueued on the context's HIP stream (see ilh_create / ilh_set_stream).
+ *    Calls that return host scalars or statistics synchronize that stream; all others
+ *    are asynchronous.
+ *  - Vectors are FP64 unless a precision argument says otherwise.
+ *  - Layouts.  N = number of H1 nodes, Ne = elements, Nl = k^d L2 dofs per element.
+ *      H1 vector  [d][N]   component-major; nodes lexicographic on the (k*n_x+1) x ...
+ *                          grid, first direction fastest.
+ *      L2 vector  [Ne][Nl] element-major; elements lexicographic, first direction fastest;
+ *                          within an element the Bernstein basis is lexicographic.
+ *      block      [x | v | e] = 2 H1 vectors followed by one L2 vector.
+ *  - Boundary conditions: v.n = 0 on every box face.  Component c of a node on a face
+ *    normal to direction c is "constrained".
+ *  - Return value: an ILH_* status code.  No C++ exception crosses the ABI.  On error
+ *    ilh_last_error() describes the failure; outputs are unspecified.
+ */
+#ifndef ILH_H
+#define ILH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ILH_OK = 0,
+  ILH_EINVAL = 1,     /* bad sizes, options or pointers                          */
+  ILH_EHIP = 2,       /* a HIP runtime call failed (message holds the HIP error) */
+  ILH_ENOMEM = 3,     /* device allocation failed                                */
+  ILH_ETANGLED = 4,   /* line search could not keep every det J > 0              */
+  ILH_ENOCONV = 5,    /* Newton reached its iteration limit                      */
+  ILH_ENONFINITE = 6  /* a non-finite residual norm appeared                     */
+};
+
+enum {
+  ILH_PROBLEM_CUSTOM = 0,  /* rho0/gamma/e0 per element from the setup arrays        */
+  ILH_PROBLEM_TG2D = 1,    /* 2D Taylor-Green vortex on [0,1]^2, gamma 5/3, rho 1   */
+  ILH_PROBLEM_TG3D = 2,    /* 3D Taylor-Green vortex on [0,1]^3, gamma 5/3, rho 1   */
+  ILH_PROBLEM_TRIPLE = 3,  /* three-state triple point on [0,7]x[0,3], v = 0         */
+  ILH_PROBLEM_UNIFORM = 4  /* rho 1, gamma 1.4, e 2.5, v 0 (closed-form checks)      */
+};
+
+enum { ILH_DSCALE_CONST = 0, ILH_DSCALE_FORMULA = 1 };
+
+typedef struct ilh_ctx ilh_ctx;
+
+/* Discretisation and physics set-up (all fields host memory).
+ * Sec. 2.1 (Q_k Q_{k-1} spaces), Sec. 3.4 (smoothed viscosity, energy regularisation). */
+typedef struct {
+  int dim;              /* 2 or 3 */
+  int n[3];             /* elements per direction */
+  double lo[3], hi[3];  /* box; ignored for the analytic problems, which fix their box */
+  int order_v;          /* kinematic order k (1..4 in 2D, 1..3 in 3D); energy order k-1 */
+  int nq1d;             /* Gauss-Legendre points per direction; 0 selects 2k (only 2k is built) */
+  int problem;          /* ILH_PROBLEM_* */
+  const double* rho0_elem;  /* host [Ne] or NULL: initial density per element */
+  const double* gamma_elem; /* host [Ne] or NULL: ideal-gas gamma per element */
+  const double* e0_elem;    /* host [Ne] or NULL: initial specific energy per element */
+  int visc_on;          /* smoothed artificial viscosity mu_imp, eq. visc_mu_imp */
+  double q1, q2;        /* eq. visc_mu_imp coefficients (paper default 0.5, 1) */
+  double psi0;          /* switch value at zero compression, eq. visc_imp_switch (0.5) */
+  int dscale_mode;      /* ILH_DSCALE_CONST: delta_scale = dscale_width;
+                           ILH_DSCALE_FORMULA: delta_scale = 2 (h/h_coarse) c_s, eq. visc_imp_scale */
+  double dscale_width;
+  double h0;            /* initial length scale of eq. visc_imp_h; <= 0 selects (|Omega|/Ne)^(1/d)/k */
+  double h_coarse;      /* <= 0 selects h0 */
+  double eps_e;         /* energy regularisation width, eq. energy_regularization (1e-6) */
+  int tg_source;        /* TG2D only: add the energy source that keeps the vortex steady */
+} ilh_setup;
+
+/* Fill *s with the defaults above for the given problem (dim, n, k set by the caller). */
+void ilh_setup_defaults(ilh_setup* s, int problem);
+
+/* Build the mesh, DOF maps, 1D basis tables, quadrature data m_q = rho0 detJ0 w_q
+ * (strong mass conservation, Sec. 2.1) and the L2 mass inverse blocks on the device.
+ * stream: a hipStream_t (NULL = default stream).  *out receives the context. */
+int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out);
+void ilh_destroy(ilh_ctx* ctx);
+int ilh_set_stream(ilh_ctx* ctx, void* stream);
+const char* ilh_last_error(const ilh_ctx* ctx);
+const char* ilh_status_string(int status);
+
+/* Sizes (host outputs, any may be NULL): H1 vector length d*N, L2 length Ne*Nl,
+ * block length, and the number of quadrature points Ne*(2k)^d. */
+int ilh_sizes(const ilh_ctx* ctx, int64_t* n_h1vec, int64_t* n_l2, int64_t* n_block,
+              int64_t* n_qp);
+
+/* Initial state u [block]: x0 = mesh nodes, v0 = nodal interpolation of the problem's
+ * velocity (zero on constrained components), e0 = rho-weighted L2 projection. */
+int ilh_init_state(ilh_ctx* ctx, double* u);
+
+/* Force actions at state w [block] (eq. matrices, eqs. v_semi/e_semi):
+ * f1 [H1] = F(w) 1 (no boundary conditions), ftv [L2] = F(w)^T w_v. */
+int ilh_force(ilh_ctx* ctx, const double* w, double* f1, double* ftv);
+
+/* Tangent of the force actions at w [block, FP64] along dw [block]:
+ * df1 = d(F 1)[dw], dftv = d(F^T v)[dw] (eq. pa_jac_action with the hand-written
+ * derivative of the quadrature-point kernel).  prec = 64: dw/df1/dftv are double;
+ * prec = 32: they are float and the pointwise arithmetic runs in FP32. */
+int ilh_force_jvp(ilh_ctx* ctx, int prec, const double* w, const void* dw, void* df1,
+                  void* dftv);
+
+/* Stage residual R(k; tau, u) at w = u + tau k (eq. nonlinear_system), all [block]:
+ *   R_x = k_x - w_v
+ *   R_v = M_V k_v + F(w) 1          (constrained rows: R_v = k_v)
+ *   R_e = M_E k_e - F(w)^T w_v - b(w_x)   (b: TG energy source, else 0). */
+int ilh_residual(ilh_ctx* ctx, const double* k, const double* u, double tau, double* r);
+
+/* Store the linearisation point of the next ilh_jvp_lin calls: w = u + tau k in FP64 and
+ * its FP32 shadow (velocity and energy) inside the context. */
+int ilh_linearize(ilh_ctx* ctx, const double* k, const double* u, double tau);
+
+/* Jacobian action J dk = dR/dk [dk] at the stored linearisation point (eq. newton_linear):
+ *   (J dk)_x = dk_x - tau dk_v
+ *   (J dk)_v = M_V dk_v + d(F 1)[tau dk]            (constrained rows: dk_v)
+ *   (J dk)_e = M_E dk_e - d(F^T w_v)[tau dk] - db[tau dk_x].
+ * prec = 64: dk, jdk are double [block]; prec = 32: float [block] (FP32 arithmetic,
+ * positions read in FP64 and made element-relative before rounding). */
+int ilh_jvp_lin(ilh_ctx* ctx, int prec, const void* dk, void* jdk);
+
+/* ilh_linearize followed by ilh_jvp_lin. */
+int ilh_jvp(ilh_ctx* ctx, int prec, const double* k, const double* u, double tau,
+            const void* dk, void* jdk);
+
+/* y [H1] = M_V x [H1] (partial assembly, eq. matrices; no boundary conditions). */
+int ilh_mass_v_apply(ilh_ctx* ctx, const double* x, double* y);
+
+/* Solve Mhat x = b, Mhat = P_u M_V P_u + P_c (identity on constrained DOFs), by
+ * Jacobi-preconditioned CG (Sec. 2.2) to ||r|| <= rtol ||b|| or maxit iterations.
+ * iters, relres: host outputs (nullable).  Returns ILH_ENOCONV if rtol was not met. */
+int ilh_mass_v_solve(ilh_ctx* ctx, const double* b, double* x, double rtol, int maxit,
+                     int* iters, double* relres);
+
+/* x [L2] = M_E^{-1} b [L2], exactly, with the per-element inverse blocks. */
+int ilh_mass_e_inv(ilh_ctx* ctx, const double* b, double* x);
+
+/* Kinetic 1/2 v^T M_V v and internal 1^T M_E e energies of u (host outputs). */
+int ilh_energy(ilh_ctx* ctx, const double* u, double* ke, double* ie);
+
+/* Minimum of det J over all quadrature points of the positions of w [block] (host). */
+int ilh_min_detj(ilh_ctx* ctx, const double* w, double* min_detj);
+
+/* Explicit time-step estimate cfl * min_q h_min / (c_s + 2.5 mu / (rho h_min)),
+ * h_min = smallest singular value of J_q / k (host output). */
+int ilh_dt_estimate(ilh_ctx* ctx, const double* u, double cfl, double* dt);
+
+/* TG2D only: int |v_h - v_exact(x)|_2 dx over the current mesh (host output). */
+int ilh_l1_velocity_error(ilh_ctx* ctx, const double* u, double* err);
+
+/* Explicit rate f(u) = [u_v; -Mhat^-1 P_u F(u) 1; M_E^-1 (F(u)^T u_v + b)] [block]. */
+int ilh_rate(ilh_ctx* ctx, const double* u, double* f);
+
+/* Newton-Krylov options (host).  Converged when ||R(k)|| <= tol ||R(0; tau, u)||. */
+typedef struct {
+  double tol;          /* relative nonlinear tolerance (1e-10 for the benchmarks) */
+  int max_newton;      /* Newton iteration cap */
+  int restart;         /* FGMRES restart length (<= 64) */
+  double gmres_rtol;   /* relative tolerance of each linear solve */
+  int gmres_maxit;     /* FGMRES iteration cap per Newton iteration */
+  int jvp_prec;        /* 32 or 64: precision of the Jacobian actions inside FGMRES */
+  int max_halvings;    /* line-search halvings before ILH_ETANGLED */
+  int pcg_iters;       /* Jacobi-PCG iterations of the velocity-mass preconditioner block
+                          (0 = diagonal only) */
+  int prec_coupled;    /* 1: after the mass blocks, set z_x = r_x + tau z_v */
+} ilh_newton_opts;
+
+typedef struct {
+  int status;            /* ILH_* */
+  int newton_iters;
+  int gmres_iters;       /* total over the Newton iterations */
+  int jvp_calls;
+  int halvings;          /* total line-search halvings */
+  double res0;           /* ||R(0; tau, u)|| */
+  double res_init;       /* ||R(k_guess)|| */
+  double res_final;      /* ||R(k)|| at exit */
+  double res_hist[32];   /* ||R(k^m)|| / res0, m = 0..min(newton_iters, 31) */
+} ilh_step_stats;
+
+void ilh_newton_defaults(ilh_newton_opts* o);
+
+/* One implicit midpoint step (Sec. 4.1: MFEM ImplicitMidpointSolver; eq. nonlinear_system
+ * with tau = dt/2): solve R(k; dt/2, u) = 0 from k_guess (NULL: zero), then u <- u + dt k.
+ * u [block] in/out, k_out [block] receives k (may be NULL).  o, st: host.
+ * On ETANGLED/ENOCONV/ENONFINITE u is left unchanged. */
+int ilh_implicit_step(ilh_ctx* ctx, double* u, double dt, const double* k_guess,
+                      double* k_out, const ilh_newton_opts* o, ilh_step_stats* st);
+
+/* One SDIRK stage solve: R(k; tau, ubase) = 0 from k_guess (NULL: zero); k_out receives k.
+ * Higher-order SDIRK steps are built from these stage solves. */
+int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double* k_guess,
+                    double* k_out, const ilh_newton_opts* o, ilh_step_stats* st);
+
+/* ---- learned Newton initial guess (per-element MLP) --------------------------------- */
+/* Feature / target layout per element (2D only): velocity dofs [2][(k+1)^2], energy
+ * dofs [k^2], corner coordinates relative to the element centre [4][2]; targets are the
+ * element-local [k_v (2 (k+1)^2) | k_e (k^2)].  See ilh_guess_* below. */
+
+/* feat [Ne][n_in] (float): element features of the state u, normalised by the scalars
+ * vscale (velocity), escale (energy), xscale (length). n_in must equal 2(k+1)^2 + k^2 + 8. */
+int ilh_guess_features(ilh_ctx* ctx, const double* u, double vscale, double escale,
+                       double xscale, float* feat, int n_in);
+
+/* Element-local stage rates of k [block] -> targ [Ne][n_out] (float), n_out = 2(k+1)^2 + k^2,
+ * divided by kvscale / kescale. */
+int ilh_guess_targets(ilh_ctx* ctx, const double* k, double kvscale, double kescale,
+                      float* targ, int n_out);
+
+/* k [block] = base + assembled correction: the element predictions pred [Ne][n_out]
+ * (times kvscale / kescale) are averaged over the elements sharing each H1 node and added
+ * to base's v and e blocks; the x block is set to u_v + tau k_v.  Constrained v rows are 0. */
+int ilh_guess_assemble(ilh_ctx* ctx, const float* pred, int n_out, double kvscale,
+                       double kescale, const double* base, const double* u, double tau,
+                       double* k);
+
+/* Fused MLP on MFMA (BF16 inputs and weights, FP32 accumulation), GELU (erf form) between
+ * layers: widths w[0] -> w[1] -> ... -> w[nl].  Parameters: W_l [w[l+1]][w[l]] (bf16 as
+ * uint16), b_l [w[l+1]] (float), concatenated over layers in that order.
+ * x [batch][w[0]] float, y [batch][w[nl]] float.  acts (nullable) receives the
+ * pre-activation outputs of every layer [batch][sum w[1..nl]] float for backward. */
+int ilh_mlp_forward(ilh_ctx* ctx, int nl, const int* widths /*host*/, const uint16_t* W,
+                    const float* b, const float* x, int batch, float* y, float* acts);
+
+/* Backward of mean-squared error 0.5/batch sum (y - t)^2 through the MLP: writes
+ * dW (float, same layout as W) and db (float).  acts from ilh_mlp_forward. */
+int ilh_mlp_backward(ilh_ctx* ctx, int nl, const int* widths, const uint16_t* W,
+                     const float* b, const float* x, const float* acts, const float* t,
+                     int batch, float* dW, float* db, double* loss /*host, nullable*/);
+
+/* Adam step on FP32 master weights (mW, mb) with moments, writing the BF16 copy W. */
+int ilh_mlp_adam(ilh_ctx* ctx, int64_t n_w, int64_t n_b, float* mW, float* mb,
+                 const float* dW, const float* db, float* m1, float* m2, int step,
+                 double lr, double beta1, double beta2, double eps, uint16_t* W, float* b_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,289 @@
+"""MI355X (gfx950) implicit high-order Lagrangian hydrodynamics.
+
+Python binding of libilh.so (include/ilh.h): every call marshals torch device tensors to
+the C ABI and runs on the library's HIP kernels.  There is no CPU fallback: if the
+library is not built, or no GPU is present, the calls raise.
+"""
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import NewtonOpts, Setup, StepStats, PROBLEMS
+
+__all__ = ["Hydro", "IlhError", "ForceFn", "newton_options"]
+
+
+class IlhError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("ilh status %d: %s" % (status, msg))
+        self.status = status
+
+
+def newton_options(**kw):
+    lib = _lib.load()
+    o = NewtonOpts()
+    lib.ilh_newton_defaults(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Hydro:
+    """One discretisation context on one GPU (wraps ilh_ctx)."""
+
+    def __init__(self, problem, n, k, visc=False, dscale_mode="const", dscale_width=1e-3, q1=0.5,
+                 q2=1.0, psi0=0.5, h0=0.0, h_coarse=0.0, tg_source=None, rho0=None, gamma=None,
+                 e0=None, lo=None, hi=None, device="cuda"):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("ilh needs a ROCm GPU; none is visible")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        s = Setup()
+        s.dim = len(n)
+        for d in range(len(n)):
+            s.n[d] = int(n[d])
+        s.order_v = int(k)
+        self.lib.ilh_setup_defaults(C.byref(s), PROBLEMS[problem])
+        s.visc_on = int(bool(visc))
+        s.dscale_mode = {"const": 0, "formula": 1}[dscale_mode]
+        s.dscale_width, s.q1, s.q2, s.psi0 = dscale_width, q1, q2, psi0
+        s.h0, s.h_coarse = h0, h_coarse
+        if tg_source is not None:
+            s.tg_source = int(bool(tg_source))
+        if lo is not None:
+            for d in range(len(lo)):
+                s.lo[d] = lo[d]
+        if hi is not None:
+            for d in range(len(hi)):
+                s.hi[d] = hi[d]
+        self._keep = []
+        for name, arr in (("rho0_elem", rho0), ("gamma_elem", gamma), ("e0_elem", e0)):
+            if arr is not None:
+                a = (C.c_double * len(arr))(*[float(x) for x in arr])
+                self._keep.append(a)
+                setattr(s, name, C.cast(a, C.POINTER(C.c_double)))
+        self.setup = s
+        ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.ilh_create(C.byref(s), C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                     C.byref(ctx))
+        if st != 0:
+            raise IlhError(st, "ilh_create failed (see stderr)")
+        self.ctx = ctx
+        nh1, nl2, nb, nq = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        self.lib.ilh_sizes(ctx, C.byref(nh1), C.byref(nl2), C.byref(nb), C.byref(nq))
+        self.nh1, self.nl2, self.nblock, self.nqp = nh1.value, nl2.value, nb.value, nq.value
+        self.dim, self.k, self.n = len(n), int(k), tuple(int(v) for v in n)
+        self.Ne = 1
+        for v in self.n:
+            self.Ne *= v
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            self.lib.ilh_destroy(ctx)
+            self.ctx = None
+
+    # ---- helpers ----
+    def _check(self, st):
+        if st != 0:
+            raise IlhError(st, self.lib.ilh_last_error(self.ctx).decode())
+
+    def _stream(self):
+        self.lib.ilh_set_stream(self.ctx, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _vec(self, t, n, dtype=torch.float64, name="vector"):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != dtype:
+            raise TypeError("%s must be a %s tensor on %s" % (name, dtype, self.device))
+        if not t.is_contiguous() or t.numel() != n:
+            raise ValueError("%s must be contiguous with %d elements (got %d)" % (name, n, t.numel()))
+        return _ptr(t)
+
+    def new(self, n=None, dtype=torch.float64):
+        return torch.zeros(self.nblock if n is None else n, dtype=dtype, device=self.device)
+
+    def split(self, u):
+        return u[:self.nh1], u[self.nh1:2 * self.nh1], u[2 * self.nh1:]
+
+    # ---- ABI wrappers ----
+    def init_state(self):
+        u = self.new()
+        self._stream()
+        self._check(self.lib.ilh_init_state(self.ctx, _ptr(u)))
+        return u
+
+    def force(self, w):
+        f1, ftv = self.new(self.nh1), self.new(self.nl2)
+        self._stream()
+        self._check(self.lib.ilh_force(self.ctx, self._vec(w, self.nblock, name="w"), _ptr(f1), _ptr(ftv)))
+        return f1, ftv
+
+    def force_jvp(self, w, dw, prec=64):
+        dt = torch.float64 if prec == 64 else torch.float32
+        df1, dftv = self.new(self.nh1, dt), self.new(self.nl2, dt)
+        self._stream()
+        self._check(self.lib.ilh_force_jvp(self.ctx, prec, self._vec(w, self.nblock, name="w"),
+                                           self._vec(dw, self.nblock, dt, "dw"), _ptr(df1), _ptr(dftv)))
+        return df1, dftv
+
+    def residual(self, k, u, tau, out=None):
+        r = self.new() if out is None else out
+        self._stream()
+        self._check(self.lib.ilh_residual(self.ctx, self._vec(k, self.nblock, name="k"),
+                                          self._vec(u, self.nblock, name="u"), float(tau), _ptr(r)))
+        return r
+
+    def linearize(self, k, u, tau):
+        self._stream()
+        self._check(self.lib.ilh_linearize(self.ctx, self._vec(k, self.nblock, name="k"),
+                                           self._vec(u, self.nblock, name="u"), float(tau)))
+
+    def jvp_lin(self, dk, prec=64, out=None):
+        dt = torch.float64 if prec == 64 else torch.float32
+        o = self.new(dtype=dt) if out is None else out
+        self._stream()
+        self._check(self.lib.ilh_jvp_lin(self.ctx, prec, self._vec(dk, self.nblock, dt, "dk"),
+                                         self._vec(o, self.nblock, dt, "out")))
+        return o
+
+    def jvp(self, k, u, tau, dk, prec=64):
+        self.linearize(k, u, tau)
+        return self.jvp_lin(dk, prec)
+
+    def mass_v_apply(self, x):
+        y = self.new(self.nh1)
+        self._stream()
+        self._check(self.lib.ilh_mass_v_apply(self.ctx, self._vec(x, self.nh1, name="x"), _ptr(y)))
+        return y
+
+    def mass_v_solve(self, b, rtol=1e-12, maxit=500):
+        x = self.new(self.nh1)
+        it, rel = C.c_int(), C.c_double()
+        self._stream()
+        self._check(self.lib.ilh_mass_v_solve(self.ctx, self._vec(b, self.nh1, name="b"), _ptr(x),
+                                              float(rtol), int(maxit), C.byref(it), C.byref(rel)))
+        return x, it.value, rel.value
+
+    def mass_e_inv(self, b):
+        x = self.new(self.nl2)
+        self._stream()
+        self._check(self.lib.ilh_mass_e_inv(self.ctx, self._vec(b, self.nl2, name="b"), _ptr(x)))
+        return x
+
+    def energy(self, u):
+        ke, ie = C.c_double(), C.c_double()
+        self._stream()
+        self._check(self.lib.ilh_energy(self.ctx, self._vec(u, self.nblock, name="u"), C.byref(ke), C.byref(ie)))
+        return ke.value, ie.value
+
+    def min_detj(self, w):
+        m = C.c_double()
+        self._stream()
+        self._check(self.lib.ilh_min_detj(self.ctx, self._vec(w, self.nblock, name="w"), C.byref(m)))
+        return m.value
+
+    def dt_estimate(self, u, cfl):
+        dt = C.c_double()
+        self._stream()
+        self._check(self.lib.ilh_dt_estimate(self.ctx, self._vec(u, self.nblock, name="u"), float(cfl),
+                                             C.byref(dt)))
+        return dt.value
+
+    def l1_error(self, u):
+        e = C.c_double()
+        self._stream()
+        self._check(self.lib.ilh_l1_velocity_error(self.ctx, self._vec(u, self.nblock, name="u"), C.byref(e)))
+        return e.value
+
+    def rate(self, u):
+        f = self.new()
+        self._stream()
+        self._check(self.lib.ilh_rate(self.ctx, self._vec(u, self.nblock, name="u"), _ptr(f)))
+        return f
+
+    def stage_solve(self, ubase, tau, guess=None, opts=None):
+        opts = opts or newton_options()
+        k = self.new()
+        st = StepStats()
+        self._stream()
+        g = self._vec(guess, self.nblock, name="guess") if guess is not None else None
+        code = self.lib.ilh_stage_solve(self.ctx, self._vec(ubase, self.nblock, name="u"), float(tau), g,
+                                        _ptr(k), C.byref(opts), C.byref(st))
+        return k, _stats(st, code)
+
+    def implicit_step(self, u, dt, guess=None, opts=None, raise_on_fail=True):
+        """u <- u + dt k with k = f(u + dt/2 k) (in place); returns (k, stats dict)."""
+        opts = opts or newton_options()
+        k = self.new()
+        st = StepStats()
+        self._stream()
+        g = self._vec(guess, self.nblock, name="guess") if guess is not None else None
+        code = self.lib.ilh_implicit_step(self.ctx, self._vec(u, self.nblock, name="u"), float(dt), g,
+                                          _ptr(k), C.byref(opts), C.byref(st))
+        stats = _stats(st, code)
+        if code != 0 and raise_on_fail:
+            raise IlhError(code, self.lib.ilh_last_error(self.ctx).decode())
+        return k, stats
+
+
+def _stats(st, code):
+    n = min(st.newton_iters, 31)
+    return dict(status=code, newton=st.newton_iters, gmres=st.gmres_iters, jvp_calls=st.jvp_calls,
+                halvings=st.halvings, res0=st.res0, res_init=st.res_init, res_final=st.res_final,
+                hist=[st.res_hist[i] for i in range(n + 1)])
+
+
+class ForceFn(torch.autograd.Function):
+    """(F(w) 1, F(w)^T w_v) with a forward-mode derivative from the hand-written tangent kernel.
+
+    forward(hydro, w) -> (f1, ftv); jvp(dw) -> (d f1, d ftv) via ilh_force_jvp (FP64).
+    """
+
+    @staticmethod
+    def forward(ctx, hydro, w):
+        ctx.hydro = hydro
+        ctx.save_for_forward(w)
+        return hydro.force(w.detach().contiguous())
+
+    @staticmethod
+    def jvp(ctx, _hydro_t, dw):
+        (w,) = ctx.saved_tensors
+        return ctx.hydro.force_jvp(w.detach().contiguous(), dw.contiguous(), 64)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        raise NotImplementedError("the transpose (VJP) action is not part of this library")
+
+
+class ResidualFn(torch.autograd.Function):
+    """R(k; tau, u) with forward-mode derivative J dk from ilh_jvp (FP64)."""
+
+    @staticmethod
+    def forward(ctx, hydro, k, u, tau):
+        ctx.hydro, ctx.tau = hydro, float(tau)
+        ctx.save_for_forward(k, u)
+        return hydro.residual(k.detach().contiguous(), u.detach().contiguous(), tau)
+
+    @staticmethod
+    def jvp(ctx, _h, dk, du, _t):
+        k, u = ctx.saved_tensors
+        if du is not None and bool(torch.any(du != 0)):
+            raise NotImplementedError("tangents in u are not supported; differentiate in k")
+        return ctx.hydro.jvp(k.detach().contiguous(), u.detach().contiguous(), ctx.tau, dk.contiguous(), 64)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        raise NotImplementedError("the transpose (VJP) action is not part of this library")

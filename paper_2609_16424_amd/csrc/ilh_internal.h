@@ -1,0 +1,144 @@
+// Internal declarations of the ilh library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ilh.h"
+
+namespace ilh {
+
+// Element kernel modes.
+enum Mode { M_FORCE = 0, M_RESID = 1, M_FJVP = 2, M_JVP = 3 };
+
+// Scalar parameters of the quadrature-point kernel and the structured mesh, passed by
+// value to every element kernel.
+struct KParams {
+  int dim, k;
+  int n[3];     // elements per direction
+  int ng[3];    // H1 node grid extents (k n + 1)
+  int Ne;
+  int64_t N;    // H1 nodes
+  const double* tab;   // 1D tables: B [Q1D][D1D], G [Q1D][D1D], BL [Q1D][L1D] (FP64)
+  const float* tabf;   // the same tables rounded to FP32
+  const double* mq;    // [Ne][Q] quadrature mass rho0 detJ0 w_q
+  const double* detJ0; // [Ne][Q]
+  const double* gamma; // [Ne]
+  double eps_e;
+  int visc, dsc_mode, tg_source;
+  double q1, q2, h0, hc_inv, dsc_w, psi_shift;
+};
+
+// Pointers of one element-kernel launch.  The meaning depends on the mode:
+//  FORCE : x, v, e = state w;                      out = F 1 [H1], out2 = F^T v [L2]
+//  RESID : x, v, e = u (FP64);  kk = k block;       out = R [block]
+//  FJVP  : x, v, e = state w;   dk = direction;     out = d(F 1), out2 = d(F^T v)
+//  JVP   : x (FP64), v, e = state; dk = direction;  out = J dk [block]
+template <typename T>
+struct EArgs {
+  const double* x;
+  const T* v;
+  const T* e;
+  const double* kk;
+  const T* dk;
+  double tau;
+  T* out;
+  T* out2;
+};
+
+}  // namespace ilh
+
+struct ilh_ctx {
+  ilh_setup s;
+  hipStream_t stream = nullptr;
+  int dim = 2, k = 1, D1D = 2, Q1D = 2, L1D = 1, Nh = 4, Nl = 1, Q = 4;
+  int n[3] = {1, 1, 1}, ng[3] = {1, 1, 1};
+  int64_t N = 0, Ne = 0, nh1 = 0, nl2 = 0, nblock = 0, nqp = 0;
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  ilh::KParams kp{};
+  // device constant data
+  double* tab = nullptr;
+  float* tabf = nullptr;
+  double* mq = nullptr;
+  double* detJ0 = nullptr;
+  double* gamma = nullptr;
+  double* rho0 = nullptr;
+  double* e0 = nullptr;
+  double* MEinv = nullptr;  // [Ne][Nl][Nl]
+  double* Mdiag = nullptr;  // [nh1] diag(M_V), 1 on constrained rows
+  double* qw = nullptr;     // [Q] reference weights (host copy below)
+  std::vector<double> h_qw, h_B, h_G, h_BL, h_gll, h_qpts;
+  // linearisation point
+  double* w64 = nullptr;    // [nblock]
+  float* w32 = nullptr;     // [nblock] (x part unused)
+  double lin_tau = 0.0;
+  // reduction scratch
+  double* red = nullptr;        // device partials
+  double* red_host = nullptr;   // pinned host
+  int red_blocks = 1024;
+  // solver workspace
+  double* ws = nullptr;         // general FP64 workspace
+  int64_t ws_len = 0;
+  float* ws32 = nullptr;
+  int64_t ws32_len = 0;
+  double* pcgbuf = nullptr;     // [4 nh1 + 16] PCG vectors and device scalars
+  // Krylov / Newton workspace (allocated on first use)
+  int kry_m = 0;
+  double* kry = nullptr;        // V [(m+1)][nblock], Z [m][nblock]
+  double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
+  float* kry32 = nullptr;       // z32, w32 [2][nblock]
+  double* hdev = nullptr;       // [4 * 72] device scalars of the Arnoldi step
+  double* hhost = nullptr;      // pinned mirror of hdev
+  std::string err;
+};
+
+namespace ilh {
+
+// error helpers
+int fail(ilh_ctx* c, int code, const std::string& msg);
+int hip_fail(ilh_ctx* c, hipError_t e, const char* what);
+
+#define ILH_HIP(ctx, call)                               \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) return ilh::hip_fail(ctx, _e, #call); \
+  } while (0)
+
+// kernel launchers (ilh_ops.hip)
+int launch_elem(ilh_ctx* c, int mode, int prec, const EArgs<double>* a64, const EArgs<float>* a32);
+int launch_fill(ilh_ctx* c, double* p, double v, int64_t n);
+int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n);
+int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int64_t n);  // y = a x + b y
+int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double* k, int64_t n);  // w = u + t k
+int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n);
+int launch_cast_f2d(ilh_ctx* c, double* y, const float* x, int64_t n);
+int launch_mass_v(ilh_ctx* c, const double* x, double* y, int zero_first);
+int launch_mass_e_inv(ilh_ctx* c, const double* b, double* x);
+int launch_jacobi(ilh_ctx* c, const double* r, double* z);   // z = r / Mdiag
+int launch_constrain(ilh_ctx* c, const double* src, double* dst, int mode);  // H1 constrained rows
+// reductions: dot products of n-length vectors, result on host (synchronizes)
+int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* out);
+// device-side dot into d_out (no sync)
+int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
+int multidot_dev(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);
+int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
+int min_detj_host(ilh_ctx* c, const double* x, double* out);
+int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);
+int l1_error_host(ilh_ctx* c, const double* u, double* out);
+int energy_host(ilh_ctx* c, const double* u, double* ke, double* ie);
+int init_state_dev(ilh_ctx* c, double* u, const double* rhs_l2);
+// PCG for M_V with device-resident scalars (no host synchronisation).  If check != 0 the
+// residual is tested on the host every `check` iterations.
+int pcg_mass_v(ilh_ctx* c, const double* b, double* x, double rtol, int maxit, int check,
+               int* iters, double* relres);
+
+// MLP and guess (ilh_mlp.hip)
+int guess_features(ilh_ctx* c, const double* u, double vs, double es, double xs, float* f, int nin);
+int guess_targets(ilh_ctx* c, const double* k, double kvs, double kes, float* t, int nout);
+int guess_assemble(ilh_ctx* c, const float* pred, int nout, double kvs, double kes,
+                   const double* base, const double* u, double tau, double* k);
+
+}  // namespace ilh

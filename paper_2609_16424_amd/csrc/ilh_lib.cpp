@@ -1,0 +1,883 @@
+// Host side of the ilh library: discretisation set-up, the C ABI and the host-driven
+// Newton-Krylov stage solver (Sec. 3.5) whose vectors and kernels live on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ilh_internal.h"
+
+using ilh::EArgs;
+
+namespace ilh {
+
+int fail(ilh_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+int hip_fail(ilh_ctx* c, hipError_t e, const char* what) {
+  if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return (e == hipErrorOutOfMemory) ? ILH_ENOMEM : ILH_EHIP;
+}
+
+// ---------------------------------------------------------------- 1D bases (host, FP64)
+// Legendre P_n and its derivative on [-1, 1] by the three-term recurrence.
+static void legendre(int n, double x, double& p, double& dp) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    p = 1.0;
+    dp = 0.0;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = pk;
+  }
+  p = p1;
+  dp = (std::fabs(x) < 1.0) ? n * (x * p1 - p0) / (x * x - 1.0) : 0.5 * n * (n + 1) * std::pow(x, n + 1);
+}
+
+// Gauss-Legendre points/weights on [0, 1] (Newton on P_n from Chebyshev guesses).
+static void gauss(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(n, z, p, dp);
+      const double dz = p / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p, dp;
+    legendre(n, z, p, dp);
+    x[n - 1 - i] = 0.5 * (z + 1.0);
+    w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);  // = 2/((1-z^2) P'^2) on [-1,1], halved
+  }
+}
+
+// Gauss-Lobatto-Legendre points on [0, 1]: endpoints and the roots of P_k'.
+static std::vector<double> gll(int k) {
+  std::vector<double> x(k + 1);
+  x[0] = 0.0;
+  x[k] = 1.0;
+  for (int i = 1; i < k; ++i) {
+    double z = -std::cos(M_PI * i / k);
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(k, z, p, dp);
+      // P'' from the Legendre equation (1 - z^2) P'' = 2 z P' - k (k+1) P
+      const double ddp = (2.0 * z * dp - k * (k + 1.0) * p) / (1.0 - z * z);
+      const double dz = dp / ddp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (z + 1.0);
+  }
+  return x;
+}
+
+static double binom(int n, int k) {
+  double r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+static bool invert(std::vector<double>& A, int n) {  // Gauss-Jordan with partial pivoting
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    for (int j = 0; j < n; ++j) {
+      std::swap(A[c * n + j], A[piv * n + j]);
+      std::swap(I[c * n + j], I[piv * n + j]);
+    }
+    const double d = A[c * n + c];
+    for (int j = 0; j < n; ++j) {
+      A[c * n + j] /= d;
+      I[c * n + j] /= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = A[r * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        A[r * n + j] -= f * A[c * n + j];
+        I[r * n + j] -= f * I[c * n + j];
+      }
+    }
+  }
+  A = I;
+  return true;
+}
+
+template <typename T>
+static int dalloc(ilh_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  ILH_HIP(c, hipMalloc((void**)p, count * sizeof(T)));
+  return ILH_OK;
+}
+
+static int ensure_solver_ws(ilh_ctx* c, int m) {
+  if (c->kry && c->kry_m >= m) return ILH_OK;
+  if (c->kry) hipFree(c->kry);
+  if (c->kry32) hipFree(c->kry32);
+  c->kry = nullptr;
+  c->kry32 = nullptr;
+  int st;
+  if ((st = dalloc(c, &c->kry, (size_t)(2 * m + 1) * c->nblock))) return st;
+  if ((st = dalloc(c, &c->kry32, (size_t)2 * c->nblock))) return st;
+  c->kry_m = m;
+  return ILH_OK;
+}
+
+}  // namespace ilh
+
+using namespace ilh;
+
+extern "C" {
+
+const char* ilh_status_string(int s) {
+  switch (s) {
+    case ILH_OK: return "ok";
+    case ILH_EINVAL: return "invalid argument";
+    case ILH_EHIP: return "HIP error";
+    case ILH_ENOMEM: return "out of device memory";
+    case ILH_ETANGLED: return "mesh tangled (det J <= 0 after line search)";
+    case ILH_ENOCONV: return "Newton did not converge";
+    case ILH_ENONFINITE: return "non-finite residual";
+  }
+  return "unknown status";
+}
+
+void ilh_setup_defaults(ilh_setup* s, int problem) {
+  const int dim = s->dim, n0 = s->n[0], n1 = s->n[1], n2 = s->n[2], k = s->order_v;
+  std::memset(s, 0, sizeof(*s));
+  s->dim = dim;
+  s->n[0] = n0;
+  s->n[1] = n1;
+  s->n[2] = n2;
+  s->order_v = k;
+  s->problem = problem;
+  s->q1 = 0.5;
+  s->q2 = 1.0;
+  s->psi0 = 0.5;
+  s->dscale_mode = ILH_DSCALE_CONST;
+  s->dscale_width = 1e-3;
+  s->eps_e = 1e-6;
+  s->tg_source = (problem == ILH_PROBLEM_TG2D) ? 1 : 0;
+  for (int d = 0; d < 3; ++d) {
+    s->lo[d] = 0.0;
+    s->hi[d] = 1.0;
+  }
+}
+
+void ilh_newton_defaults(ilh_newton_opts* o) {
+  o->tol = 1e-10;
+  o->max_newton = 30;
+  o->restart = 30;
+  o->gmres_rtol = 1e-6;
+  o->gmres_maxit = 60;
+  o->jvp_prec = 32;
+  o->max_halvings = 10;
+  o->pcg_iters = 0;
+  o->prec_coupled = 1;
+}
+
+const char* ilh_last_error(const ilh_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int ilh_set_stream(ilh_ctx* c, void* stream) {
+  if (!c) return ILH_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return ILH_OK;
+}
+
+int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t* nq) {
+  if (!c) return ILH_EINVAL;
+  if (nh1) *nh1 = c->nh1;
+  if (nl2) *nl2 = c->nl2;
+  if (nb) *nb = c->nblock;
+  if (nq) *nq = c->nqp;
+  return ILH_OK;
+}
+
+void ilh_destroy(ilh_ctx* c) {
+  if (!c) return;
+  void* ptrs[] = {c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  if (c->red_host) hipHostFree(c->red_host);
+  if (c->hhost) hipHostFree(c->hhost);
+  delete c;
+}
+
+int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
+  if (!s || !out) return ILH_EINVAL;
+  *out = nullptr;
+  ilh_ctx* c = new ilh_ctx();
+  c->s = *s;
+  c->stream = (hipStream_t)stream;
+  auto bad = [&](const std::string& m) {
+    // creation failures are reported through stderr because no context survives
+    std::fprintf(stderr, "ilh_create: %s\n", m.c_str());
+    ilh_destroy(c);
+    return ILH_EINVAL;
+  };
+  const int dim = s->dim, k = s->order_v;
+  if (dim != 2 && dim != 3) return bad("dim must be 2 or 3");
+  if (k < 1 || (dim == 2 && k > 4) || (dim == 3 && k > 3)) return bad("order_v out of range");
+  if (s->nq1d != 0 && s->nq1d != 2 * k) return bad("only nq1d = 2k is built");
+  for (int d = 0; d < dim; ++d)
+    if (s->n[d] < 1) return bad("n must be >= 1");
+  const int prob = s->problem;
+  if (prob < 0 || prob > ILH_PROBLEM_UNIFORM) return bad("unknown problem");
+  if ((prob == ILH_PROBLEM_TG2D || prob == ILH_PROBLEM_TRIPLE) && dim != 2) return bad("problem is 2D");
+  if (prob == ILH_PROBLEM_TG3D && dim != 3) return bad("problem is 3D");
+  if (s->tg_source && prob != ILH_PROBLEM_TG2D) return bad("tg_source requires TG2D");
+  if (prob == ILH_PROBLEM_CUSTOM && (!s->rho0_elem || !s->gamma_elem || !s->e0_elem))
+    return bad("custom problem needs rho0/gamma/e0 arrays");
+  if (s->eps_e <= 0) return bad("eps_e must be > 0");
+  if (s->visc_on && s->dscale_mode == ILH_DSCALE_CONST && !(s->dscale_width > 0)) return bad("dscale_width must be > 0");
+  if (s->visc_on && (s->psi0 <= 0 || s->psi0 >= 1)) return bad("psi0 must lie in (0, 1)");
+
+  c->dim = dim;
+  c->k = k;
+  c->D1D = k + 1;
+  c->Q1D = 2 * k;
+  c->L1D = k;
+  c->Nh = (int)std::pow(k + 1, dim);
+  c->Nl = (int)std::pow(k, dim);
+  c->Q = (int)std::pow(2 * k, dim);
+  // box
+  if (prob == ILH_PROBLEM_TG2D || prob == ILH_PROBLEM_TG3D) {
+    for (int d = 0; d < 3; ++d) {
+      c->lo[d] = 0.0;
+      c->hi[d] = 1.0;
+    }
+  } else if (prob == ILH_PROBLEM_TRIPLE) {
+    c->lo[0] = 0;
+    c->lo[1] = 0;
+    c->hi[0] = 7;
+    c->hi[1] = 3;
+  } else {
+    for (int d = 0; d < dim; ++d) {
+      c->lo[d] = s->lo[d];
+      c->hi[d] = s->hi[d];
+      if (!(c->hi[d] > c->lo[d])) return bad("box must have hi > lo");
+    }
+  }
+  c->Ne = 1;
+  c->N = 1;
+  for (int d = 0; d < dim; ++d) {
+    c->n[d] = s->n[d];
+    c->ng[d] = k * s->n[d] + 1;
+    c->Ne *= s->n[d];
+    c->N *= c->ng[d];
+  }
+  if (c->Ne > 2147483647LL / c->Q) return bad("mesh too large for 32-bit element indexing");
+  c->nh1 = dim * c->N;
+  c->nl2 = c->Ne * c->Nl;
+  c->nblock = 2 * c->nh1 + c->nl2;
+  c->nqp = c->Ne * c->Q;
+  const int D1D = c->D1D, Q1D = c->Q1D, L1D = c->L1D;
+
+  // 1D tables
+  std::vector<double> xg, wg;
+  gauss(Q1D, xg, wg);
+  const std::vector<double> xn = gll(k);
+  std::vector<double> B(Q1D * D1D), G(Q1D * D1D), BL(Q1D * L1D);
+  for (int q = 0; q < Q1D; ++q) {
+    const double t = xg[q];
+    for (int a = 0; a < D1D; ++a) {
+      double num = 1, den = 1, der = 0;
+      for (int b = 0; b < D1D; ++b) {
+        if (b == a) continue;
+        num *= t - xn[b];
+        den *= xn[a] - xn[b];
+      }
+      for (int m = 0; m < D1D; ++m) {
+        if (m == a) continue;
+        double pr = 1;
+        for (int b = 0; b < D1D; ++b)
+          if (b != a && b != m) pr *= t - xn[b];
+        der += pr;
+      }
+      B[q * D1D + a] = num / den;
+      G[q * D1D + a] = der / den;
+    }
+    for (int j = 0; j < L1D; ++j)
+      BL[q * L1D + j] = binom(k - 1, j) * std::pow(t, j) * std::pow(1 - t, k - 1 - j);
+  }
+  std::vector<double> tab;
+  tab.insert(tab.end(), B.begin(), B.end());
+  tab.insert(tab.end(), G.begin(), G.end());
+  tab.insert(tab.end(), BL.begin(), BL.end());
+  tab.insert(tab.end(), wg.begin(), wg.end());
+  tab.insert(tab.end(), xg.begin(), xg.end());
+  tab.insert(tab.end(), xn.begin(), xn.end());
+  std::vector<float> tabf(tab.begin(), tab.end());
+  c->h_B = B;
+  c->h_G = G;
+  c->h_BL = BL;
+  c->h_gll = xn;
+
+  // per-element material data
+  std::vector<double> rho0(c->Ne, 1.0), gam(c->Ne, 5.0 / 3.0), e0(c->Ne, 0.0);
+  double h[3] = {1, 1, 1};
+  for (int d = 0; d < dim; ++d) h[d] = (c->hi[d] - c->lo[d]) / c->n[d];
+  if (prob == ILH_PROBLEM_TRIPLE) {
+    for (int64_t e = 0; e < c->Ne; ++e) {
+      const int ex = (int)(e % c->n[0]), ey = (int)(e / c->n[0]);
+      const double xc = c->lo[0] + h[0] * (ex + 0.5), yc = c->lo[1] + h[1] * (ey + 0.5);
+      double r, p, g;
+      if (xc < 1.0) { r = 1.0; p = 1.0; g = 1.5; }
+      else if (yc < 1.5) { r = 1.0; p = 0.1; g = 1.4; }
+      else { r = 0.125; p = 0.1; g = 1.5; }
+      rho0[e] = r;
+      gam[e] = g;
+      e0[e] = p / ((g - 1.0) * r);
+    }
+  } else if (prob == ILH_PROBLEM_UNIFORM) {
+    std::fill(gam.begin(), gam.end(), 1.4);
+    std::fill(e0.begin(), e0.end(), 2.5);
+  }
+  if (s->rho0_elem) std::copy(s->rho0_elem, s->rho0_elem + c->Ne, rho0.begin());
+  if (s->gamma_elem) std::copy(s->gamma_elem, s->gamma_elem + c->Ne, gam.begin());
+  if (s->e0_elem) std::copy(s->e0_elem, s->e0_elem + c->Ne, e0.begin());
+  for (int64_t e = 0; e < c->Ne; ++e)
+    if (!(rho0[e] > 0) || !(gam[e] > 1)) return bad("rho0 must be > 0 and gamma > 1");
+
+  // quadrature data: affine Cartesian elements, det J0 = prod h_d
+  double detJ0 = 1;
+  for (int d = 0; d < dim; ++d) detJ0 *= h[d];
+  const int Q = c->Q;
+  std::vector<double> qw(Q);
+  for (int q = 0; q < Q; ++q) {
+    double w = 1;
+    int r = q;
+    for (int d = 0; d < dim; ++d) {
+      w *= wg[r % Q1D];
+      r /= Q1D;
+    }
+    qw[q] = w;
+  }
+  c->h_qw = qw;
+  std::vector<double> mq(c->nqp), dj0(c->nqp, detJ0);
+  for (int64_t e = 0; e < c->Ne; ++e)
+    for (int q = 0; q < Q; ++q) mq[e * Q + q] = rho0[e] * detJ0 * qw[q];
+  // L2 mass: M_E,e = rho0_e detJ0 (M1 x M1 [x M1]) with the 1D Bernstein mass M1
+  std::vector<double> M1(L1D * L1D, 0.0);
+  for (int i = 0; i < L1D; ++i)
+    for (int j = 0; j < L1D; ++j)
+      for (int q = 0; q < Q1D; ++q) M1[i * L1D + j] += wg[q] * BL[q * L1D + i] * BL[q * L1D + j];
+  if (!invert(M1, L1D)) return bad("singular L2 mass");
+  const int Nl = c->Nl;
+  std::vector<double> me(Nl * Nl + c->Ne);
+  for (int i = 0; i < Nl; ++i)
+    for (int j = 0; j < Nl; ++j) {
+      double v = 1;
+      int ri = i, rj = j;
+      for (int d = 0; d < dim; ++d) {
+        v *= M1[(ri % L1D) * L1D + (rj % L1D)];
+        ri /= L1D;
+        rj /= L1D;
+      }
+      me[i * Nl + j] = v;
+    }
+  for (int64_t e = 0; e < c->Ne; ++e) me[Nl * Nl + e] = 1.0 / (rho0[e] * detJ0);
+  // H1 mass diagonal (tensor product of 1D sums) with ones on constrained rows
+  std::vector<double> d1(D1D, 0.0);
+  for (int a = 0; a < D1D; ++a)
+    for (int q = 0; q < Q1D; ++q) d1[a] += wg[q] * B[q * D1D + a] * B[q * D1D + a];
+  std::vector<double> diag(c->N, 0.0);
+  const int Nh = c->Nh;
+  const int64_t s1 = c->ng[0], s2 = (int64_t)c->ng[0] * c->ng[1];
+  for (int64_t e = 0; e < c->Ne; ++e) {
+    const int ex = (int)(e % c->n[0]), ey = (int)((e / c->n[0]) % c->n[1]),
+              ez = dim == 3 ? (int)(e / ((int64_t)c->n[0] * c->n[1])) : 0;
+    for (int li = 0; li < Nh; ++li) {
+      const int a = li % D1D, b = (li / D1D) % D1D, cc = dim == 3 ? li / (D1D * D1D) : 0;
+      double v = rho0[e] * detJ0 * d1[a] * d1[b] * (dim == 3 ? d1[cc] : 1.0);
+      diag[(k * ex + a) + s1 * (k * ey + b) + s2 * (k * ez + cc)] += v;
+    }
+  }
+  std::vector<double> Md(c->nh1);
+  for (int cc = 0; cc < dim; ++cc)
+    for (int64_t node = 0; node < c->N; ++node) {
+      int64_t r = node;
+      int gi[3] = {0, 0, 0};
+      for (int d = 0; d < dim; ++d) {
+        gi[d] = (int)(r % c->ng[d]);
+        r /= c->ng[d];
+      }
+      const bool cons = gi[cc] == 0 || gi[cc] == c->ng[cc] - 1;
+      Md[cc * c->N + node] = cons ? 1.0 : diag[node];
+    }
+
+  // viscosity parameters
+  double vol = 1;
+  for (int d = 0; d < dim; ++d) vol *= c->hi[d] - c->lo[d];
+  const double h0 = s->h0 > 0 ? s->h0 : std::pow(vol / c->Ne, 1.0 / dim) / k;
+  const double hc = s->h_coarse > 0 ? s->h_coarse : h0;
+
+  int st;
+  const size_t ntab = tab.size();
+  if ((st = dalloc(c, &c->tab, ntab)) || (st = dalloc(c, &c->tabf, ntab)) || (st = dalloc(c, &c->mq, c->nqp)) ||
+      (st = dalloc(c, &c->detJ0, c->nqp)) || (st = dalloc(c, &c->gamma, c->Ne)) || (st = dalloc(c, &c->rho0, c->Ne)) ||
+      (st = dalloc(c, &c->e0, c->Ne)) || (st = dalloc(c, &c->MEinv, me.size())) || (st = dalloc(c, &c->Mdiag, c->nh1)) ||
+      (st = dalloc(c, &c->w64, c->nblock)) || (st = dalloc(c, &c->w32, c->nblock)) ||
+      (st = dalloc(c, &c->red, (size_t)c->red_blocks * 66 + 256)) || (st = dalloc(c, &c->pcgbuf, 4 * c->nh1 + 16))) {
+    std::fprintf(stderr, "ilh_create: %s\n", c->err.c_str());
+    ilh_destroy(c);
+    return st;
+  }
+  c->ws_len = std::max<int64_t>(c->nl2, (c->nqp + 255) / 256 + 16);
+  if ((st = dalloc(c, &c->ws, c->ws_len))) {
+    ilh_destroy(c);
+    return st;
+  }
+  if (hipHostMalloc((void**)&c->red_host, 64 * sizeof(double)) != hipSuccess) {
+    ilh_destroy(c);
+    return ILH_ENOMEM;
+  }
+  auto up = [&](void* d, const void* h, size_t bytes) { return hipMemcpy(d, h, bytes, hipMemcpyHostToDevice); };
+  if (up(c->tab, tab.data(), ntab * 8) || up(c->tabf, tabf.data(), ntab * 4) || up(c->mq, mq.data(), c->nqp * 8) ||
+      up(c->detJ0, dj0.data(), c->nqp * 8) || up(c->gamma, gam.data(), c->Ne * 8) ||
+      up(c->rho0, rho0.data(), c->Ne * 8) || up(c->e0, e0.data(), c->Ne * 8) ||
+      up(c->MEinv, me.data(), me.size() * 8) || up(c->Mdiag, Md.data(), c->nh1 * 8)) {
+    std::fprintf(stderr, "ilh_create: upload failed\n");
+    ilh_destroy(c);
+    return ILH_EHIP;
+  }
+  KParams& P = c->kp;
+  P.dim = dim;
+  P.k = k;
+  for (int d = 0; d < 3; ++d) {
+    P.n[d] = d < dim ? c->n[d] : 1;
+    P.ng[d] = d < dim ? c->ng[d] : 1;
+  }
+  P.Ne = (int)c->Ne;
+  P.N = c->N;
+  P.tab = c->tab;
+  P.tabf = c->tabf;
+  P.mq = c->mq;
+  P.detJ0 = c->detJ0;
+  P.gamma = c->gamma;
+  P.eps_e = s->eps_e;
+  P.visc = s->visc_on;
+  P.dsc_mode = s->dscale_mode;
+  P.tg_source = s->tg_source;
+  P.q1 = s->q1;
+  P.q2 = s->q2;
+  P.h0 = h0;
+  P.hc_inv = 1.0 / hc;
+  P.dsc_w = s->dscale_width;
+  P.psi_shift = s->visc_on ? std::atanh(1.0 - 2.0 * s->psi0) : 0.0;
+  *out = c;
+  return ILH_OK;
+}
+
+int ilh_init_state(ilh_ctx* c, double* u) {
+  if (!c || !u) return ILH_EINVAL;
+  return init_state_dev(c, u, nullptr);
+}
+
+int ilh_force(ilh_ctx* c, const double* w, double* f1, double* ftv) {
+  if (!c || !w || !f1 || !ftv) return ILH_EINVAL;
+  int st = launch_fill(c, f1, 0.0, c->nh1);
+  if (st) return st;
+  EArgs<double> a{w, w + c->nh1, w + 2 * c->nh1, nullptr, nullptr, 0.0, f1, ftv};
+  return launch_elem(c, M_FORCE, 64, &a, nullptr);
+}
+
+int ilh_force_jvp(ilh_ctx* c, int prec, const double* w, const void* dw, void* df1, void* dftv) {
+  if (!c || !w || !dw || !df1 || !dftv) return ILH_EINVAL;
+  int st;
+  if (prec == 64) {
+    if ((st = launch_fill(c, (double*)df1, 0.0, c->nh1))) return st;
+    EArgs<double> a{w, w + c->nh1, w + 2 * c->nh1, nullptr, (const double*)dw, 1.0, (double*)df1, (double*)dftv};
+    return launch_elem(c, M_FJVP, 64, &a, nullptr);
+  }
+  if (prec == 32) {
+    if ((st = launch_cast_d2f(c, c->w32, w, c->nblock))) return st;
+    if ((st = launch_fillf(c, (float*)df1, 0.0f, c->nh1))) return st;
+    EArgs<float> a{w, c->w32 + c->nh1, c->w32 + 2 * c->nh1, nullptr, (const float*)dw, 1.0, (float*)df1,
+                   (float*)dftv};
+    return launch_elem(c, M_FJVP, 32, nullptr, &a);
+  }
+  return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+}
+
+int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
+  if (!c || !k || !u || !r) return ILH_EINVAL;
+  int st = launch_fill(c, r + c->nh1, 0.0, c->nh1);
+  if (st) return st;
+  EArgs<double> a{u, u + c->nh1, u + 2 * c->nh1, k, nullptr, tau, r, nullptr};
+  return launch_elem(c, M_RESID, 64, &a, nullptr);
+}
+
+int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
+  if (!c || !k || !u) return ILH_EINVAL;
+  int st;
+  if ((st = launch_waxpy(c, c->w64, u, tau, k, c->nblock))) return st;
+  if ((st = launch_cast_d2f(c, c->w32, c->w64, c->nblock))) return st;
+  c->lin_tau = tau;
+  return ILH_OK;
+}
+
+int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
+  if (!c || !dk || !jdk) return ILH_EINVAL;
+  int st;
+  if (prec == 64) {
+    double* o = (double*)jdk;
+    if ((st = launch_fill(c, o + c->nh1, 0.0, c->nh1))) return st;
+    EArgs<double> a{c->w64, c->w64 + c->nh1, c->w64 + 2 * c->nh1, nullptr, (const double*)dk, c->lin_tau, o, nullptr};
+    return launch_elem(c, M_JVP, 64, &a, nullptr);
+  }
+  if (prec == 32) {
+    float* o = (float*)jdk;
+    if ((st = launch_fillf(c, o + c->nh1, 0.0f, c->nh1))) return st;
+    EArgs<float> a{c->w64, c->w32 + c->nh1, c->w32 + 2 * c->nh1, nullptr, (const float*)dk, c->lin_tau, o, nullptr};
+    return launch_elem(c, M_JVP, 32, nullptr, &a);
+  }
+  return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+}
+
+int ilh_jvp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, const void* dk, void* jdk) {
+  int st = ilh_linearize(c, k, u, tau);
+  if (st) return st;
+  return ilh_jvp_lin(c, prec, dk, jdk);
+}
+
+int ilh_mass_v_apply(ilh_ctx* c, const double* x, double* y) {
+  if (!c || !x || !y) return ILH_EINVAL;
+  return launch_mass_v(c, x, y, 0);
+}
+
+int ilh_mass_v_solve(ilh_ctx* c, const double* b, double* x, double rtol, int maxit, int* iters, double* relres) {
+  if (!c || !b || !x || maxit < 0) return ILH_EINVAL;
+  int it = 0;
+  double rel = 0;
+  int st = pcg_mass_v(c, b, x, rtol, maxit, 1, &it, &rel);
+  if (st) return st;
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  if (rel > rtol) return fail(c, ILH_ENOCONV, "PCG did not reach rtol");
+  return ILH_OK;
+}
+
+int ilh_mass_e_inv(ilh_ctx* c, const double* b, double* x) {
+  if (!c || !b || !x) return ILH_EINVAL;
+  return launch_mass_e_inv(c, b, x);
+}
+
+int ilh_energy(ilh_ctx* c, const double* u, double* ke, double* ie) {
+  if (!c || !u || !ke || !ie) return ILH_EINVAL;
+  return energy_host(c, u, ke, ie);
+}
+
+int ilh_min_detj(ilh_ctx* c, const double* w, double* m) {
+  if (!c || !w || !m) return ILH_EINVAL;
+  return min_detj_host(c, w, m);
+}
+
+int ilh_dt_estimate(ilh_ctx* c, const double* u, double cfl, double* dt) {
+  if (!c || !u || !dt || !(cfl > 0)) return ILH_EINVAL;
+  return dt_estimate_host(c, u, cfl, dt);
+}
+
+int ilh_l1_velocity_error(ilh_ctx* c, const double* u, double* err) {
+  if (!c || !u || !err) return ILH_EINVAL;
+  if (c->s.problem != ILH_PROBLEM_TG2D && c->s.problem != ILH_PROBLEM_TG3D)
+    return fail(c, ILH_EINVAL, "L1 error needs an analytic Taylor-Green velocity");
+  return l1_error_host(c, u, err);
+}
+
+int ilh_rate(ilh_ctx* c, const double* u, double* f) {
+  if (!c || !u || !f) return ILH_EINVAL;
+  int st;
+  const int64_t nh1 = c->nh1;
+  // the residual at k = 0, tau = 0 holds F 1 (free rows) and -F^T v - b
+  if ((st = ensure_solver_ws(c, 1))) return st;
+  double* zero = c->kry;
+  double* r = c->kry + c->nblock;
+  if ((st = launch_fill(c, zero, 0.0, c->nblock))) return st;
+  if ((st = ilh_residual(c, zero, u, 0.0, r))) return st;
+  // f_e = M_E^-1 (F^T v + b) = -M_E^-1 R_e(0)
+  if ((st = launch_axpby(c, r + 2 * nh1, 0.0, r, -1.0, c->nl2))) return st;
+  if ((st = launch_mass_e_inv(c, r + 2 * nh1, f + 2 * nh1))) return st;
+  // f_v = -Mhat^-1 P_u F 1 ; R_v(0) = F 1 on free rows and 0 on constrained rows
+  if ((st = launch_axpby(c, r + nh1, 0.0, r, -1.0, nh1))) return st;
+  int it;
+  double rel;
+  if ((st = pcg_mass_v(c, r + nh1, f + nh1, 1e-14, 500, 10, &it, &rel))) return st;
+  ILH_HIP(c, hipMemcpyAsync(f, u + nh1, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return ILH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- Newton-Krylov
+namespace ilh {
+
+static double nrm2(ilh_ctx* c, const double* x, int64_t n, int* st) {
+  double v = 0;
+  *st = dot_host(c, x, x, n, &v);
+  return std::sqrt(v);
+}
+
+__global__ void k_scale_copy(double* y, const double* x, const double* s, int idx, int64_t n) {
+  const double f = 1.0 / s[idx];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i] * f;
+}
+
+struct Solver {
+  ilh_ctx* c;
+  const ilh_newton_opts* o;
+  double tau;
+  int jvp_calls = 0;
+
+  int precond(const double* r, double* z) {
+    const int64_t nh1 = c->nh1;
+    int st;
+    ILH_HIP(c, hipMemcpyAsync(z, r, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (o->pcg_iters > 0) {
+      if ((st = pcg_mass_v(c, r + nh1, z + nh1, 0.0, o->pcg_iters, 0, nullptr, nullptr))) return st;
+    } else {
+      if ((st = launch_jacobi(c, r + nh1, z + nh1))) return st;
+    }
+    if ((st = launch_mass_e_inv(c, r + 2 * nh1, z + 2 * nh1))) return st;
+    if (o->prec_coupled)
+      if ((st = launch_axpby(c, z, tau, z + nh1, 1.0, nh1))) return st;
+    return ILH_OK;
+  }
+
+  int apply(const double* x, double* y) {
+    int st;
+    ++jvp_calls;
+    if (o->jvp_prec == 32) {
+      float* x32 = c->kry32;
+      float* y32 = c->kry32 + c->nblock;
+      if ((st = launch_cast_d2f(c, x32, x, c->nblock))) return st;
+      if ((st = ilh_jvp_lin(c, 32, x32, y32))) return st;
+      return launch_cast_f2d(c, y, y32, c->nblock);
+    }
+    return ilh_jvp_lin(c, 64, x, y);
+  }
+
+  // FGMRES: solve J x = b, x starts at 0.  Returns total iterations in *its.
+  int fgmres(const double* b, double* x, int* its) {
+    const int64_t n = c->nblock;
+    const int m = std::max(1, std::min(o->restart, 64));
+    double* V = c->kry;
+    double* Z = c->kry + (int64_t)(m + 1) * n;
+    double* hd = c->hdev;
+    int st;
+    if ((st = launch_fill(c, x, 0.0, n))) return st;
+    double beta = nrm2(c, b, n, &st);
+    if (st) return st;
+    *its = 0;
+    if (beta == 0.0) return ILH_OK;
+    const double target = o->gmres_rtol * beta;
+    std::vector<double> H((m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+    const double* rhs = b;
+    double* rbuf = c->nwt + 3 * n;  // tmp vector
+    int total = 0;
+    while (true) {
+      // V0 = r / beta
+      c->hhost[240] = beta;
+      ILH_HIP(c, hipMemcpyAsync(hd + 240, &c->hhost[240], sizeof(double), hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, hd, 240, n);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int j_end = 0;
+      bool done = false;
+      for (int j = 0; j < m; ++j) {
+        double* Vj = V + (int64_t)j * n;
+        double* Zj = Z + (int64_t)j * n;
+        double* w = V + (int64_t)(j + 1) * n;
+        if ((st = precond(Vj, Zj))) return st;
+        if ((st = apply(Zj, w))) return st;
+        // classical Gram-Schmidt, twice
+        if ((st = multidot_dev(c, V, n, j + 1, w, n, hd))) return st;
+        if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd, -1.0, n))) return st;
+        if ((st = multidot_dev(c, V, n, j + 1, w, n, hd + 72))) return st;
+        if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd + 72, -1.0, n))) return st;
+        if ((st = dot_dev(c, w, w, n, hd + 144))) return st;
+        ILH_HIP(c, hipMemcpyAsync(c->hhost, hd, 145 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        ILH_HIP(c, hipStreamSynchronize(c->stream));
+        for (int i = 0; i <= j; ++i) H[i * m + j] = c->hhost[i] + c->hhost[72 + i];
+        const double hn = std::sqrt(std::max(c->hhost[144], 0.0));
+        if (!std::isfinite(hn)) return fail(c, ILH_ENONFINITE, "non-finite Krylov vector");
+        H[(j + 1) * m + j] = hn;
+        if (hn > 0) {
+          c->hhost[150] = hn;
+          ILH_HIP(c, hipMemcpyAsync(hd + 150, &c->hhost[150], sizeof(double), hipMemcpyHostToDevice, c->stream));
+          hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, w, w, hd, 150, n);
+        }
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+          H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+          H[i * m + j] = t;
+        }
+        const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+        cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
+        sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
+        H[j * m + j] = den;
+        H[(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++total;
+        j_end = j + 1;
+        if (std::fabs(g[j + 1]) <= target || total >= o->gmres_maxit || hn == 0.0) {
+          done = true;
+          break;
+        }
+      }
+      // y = H^-1 g (upper triangular), x += Z y
+      for (int i = j_end - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int l = i + 1; l < j_end; ++l) acc -= H[i * m + l] * y[l];
+        y[i] = H[i * m + i] != 0 ? acc / H[i * m + i] : 0.0;
+      }
+      for (int i = 0; i < j_end; ++i) c->hhost[160 + i] = y[i];
+      ILH_HIP(c, hipMemcpyAsync(hd + 160, c->hhost + 160, j_end * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      if ((st = multiaxpy_dev(c, x, Z, n, j_end, hd + 160, 1.0, n))) return st;
+      if (done && (std::fabs(g[j_end]) <= target || total >= o->gmres_maxit)) break;
+      // restart: r = b - J x
+      if ((st = apply(x, rbuf))) return st;
+      if ((st = launch_axpby(c, rbuf, 1.0, b, -1.0, n))) return st;
+      rhs = rbuf;
+      beta = nrm2(c, rbuf, n, &st);
+      if (st) return st;
+      if (beta <= target || total >= o->gmres_maxit) break;
+    }
+    *its = total;
+    return ILH_OK;
+  }
+};
+
+static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_guess, double* k_out,
+                       const ilh_newton_opts* o, ilh_step_stats* st_out) {
+  const int64_t n = c->nblock;
+  int st;
+  ilh_step_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  const int m = std::max(1, std::min(o->restart, 64));
+  if ((st = ensure_solver_ws(c, m))) return st;
+  if (!c->nwt && (st = dalloc(c, &c->nwt, 6 * (size_t)n))) return st;
+  if (!c->hdev && (st = dalloc(c, &c->hdev, 4 * 72 + 64))) return st;
+  if (!c->hhost && hipHostMalloc((void**)&c->hhost, (4 * 72 + 64) * sizeof(double)) != hipSuccess)
+    return fail(c, ILH_ENOMEM, "pinned host buffer");
+  double* k = c->nwt;
+  double* r = c->nwt + n;
+  double* dk = c->nwt + 2 * n;
+  double* trial = c->nwt + 4 * n;
+  double* zero = c->nwt + 5 * n;
+  Solver S{c, o, tau};
+  if ((st = launch_fill(c, zero, 0.0, n))) return st;
+  if ((st = ilh_residual(c, zero, u, tau, r))) return st;
+  const double r0 = nrm2(c, r, n, &st);
+  if (st) return st;
+  stats.res0 = r0;
+  if (k_guess) {
+    ILH_HIP(c, hipMemcpyAsync(k, k_guess, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    if ((st = launch_fill(c, k, 0.0, n))) return st;
+  }
+  int status = ILH_OK;
+  int it = 0;
+  for (;; ++it) {
+    if ((st = ilh_residual(c, k, u, tau, r))) return st;
+    const double nr = nrm2(c, r, n, &st);
+    if (st) return st;
+    if (it == 0) stats.res_init = nr;
+    if (it < 32) stats.res_hist[it] = r0 > 0 ? nr / r0 : nr;
+    stats.res_final = nr;
+    if (!std::isfinite(nr)) {
+      status = ILH_ENONFINITE;
+      c->err = "non-finite residual";
+      break;
+    }
+    if (nr <= o->tol * r0) break;
+    if (it >= o->max_newton) {
+      status = ILH_ENOCONV;
+      c->err = "Newton reached max_newton";
+      break;
+    }
+    if ((st = ilh_linearize(c, k, u, tau))) return st;
+    if ((st = launch_axpby(c, r, 0.0, r, -1.0, n))) return st;  // r <- -r
+    int gits = 0;
+    if ((st = S.fgmres(r, dk, &gits))) return st;
+    stats.gmres_iters += gits;
+    // backtracking line search on min det J of the stage positions
+    double alpha = 1.0;
+    bool ok = false;
+    for (int h = 0; h <= o->max_halvings; ++h) {
+      // trial_x = u_x + tau (k_x + alpha dk_x)
+      if ((st = launch_waxpy(c, trial, k, alpha, dk, c->nh1))) return st;
+      if ((st = launch_axpby(c, trial, 1.0, u, tau, c->nh1))) return st;
+      double md;
+      if ((st = min_detj_host(c, trial, &md))) return st;
+      if (md > 0.0) {
+        ok = true;
+        break;
+      }
+      alpha *= 0.5;
+      ++stats.halvings;
+    }
+    if (!ok) {
+      status = ILH_ETANGLED;
+      c->err = "line search could not keep det J > 0";
+      break;
+    }
+    if ((st = launch_axpby(c, k, alpha, dk, 1.0, n))) return st;
+  }
+  stats.newton_iters = it;
+  stats.jvp_calls = S.jvp_calls;
+  stats.status = status;
+  if (k_out) ILH_HIP(c, hipMemcpyAsync(k_out, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  if (st_out) *st_out = stats;
+  return status;
+}
+
+}  // namespace ilh
+
+extern "C" {
+
+int ilh_stage_solve(ilh_ctx* c, const double* ubase, double tau, const double* k_guess, double* k_out,
+                    const ilh_newton_opts* o, ilh_step_stats* st) {
+  if (!c || !ubase || !o) return ILH_EINVAL;
+  if (o->restart < 1 || o->gmres_maxit < 1 || o->max_newton < 0 || (o->jvp_prec != 32 && o->jvp_prec != 64))
+    return fail(c, ILH_EINVAL, "bad Newton options");
+  return stage_solve(c, ubase, tau, k_guess, k_out, o, st);
+}
+
+int ilh_implicit_step(ilh_ctx* c, double* u, double dt, const double* k_guess, double* k_out,
+                      const ilh_newton_opts* o, ilh_step_stats* st) {
+  if (!c || !u || !o || !(dt > 0)) return ILH_EINVAL;
+  if (o->restart < 1 || o->gmres_maxit < 1 || o->max_newton < 0 || (o->jvp_prec != 32 && o->jvp_prec != 64))
+    return fail(c, ILH_EINVAL, "bad Newton options");
+  int status = stage_solve(c, u, 0.5 * dt, k_guess, k_out, o, st);
+  if (status != ILH_OK) return status;
+  // u <- u + dt k
+  int s2 = launch_axpby(c, u, dt, c->nwt, 1.0, c->nblock);
+  if (s2) return s2;
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  return ILH_OK;
+}
+
+}  // extern "C"

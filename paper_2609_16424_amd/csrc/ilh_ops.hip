@@ -1,0 +1,746 @@
+// Mass operators, BLAS-1, reductions, per-quadrature-point diagnostics and the initial
+// state.  The mass matrices M_V = int rho w w^T and M_E = int rho phi phi^T (Sec. 2.1,
+// eq. matrices) are constant in time because rho |J| = rho0 |J0|; they are applied by
+// partial assembly with the quadrature data m_q (Sec. 2.2) and M_V is inverted by
+// Jacobi-preconditioned CG whose scalars stay on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "ilh_internal.h"
+#include "ilh_pointwise.h"
+
+namespace ilh {
+
+static constexpr int TPB = 256;
+
+static inline int nblk(int64_t n, int cap = 65535 * 4) {
+  int64_t b = (n + TPB - 1) / TPB;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+// ------------------------------------------------------------------ BLAS-1
+__global__ void k_fill(double* p, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fillf(float* p, float v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_axpby(double* y, double a, const double* x, double b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+__global__ void k_waxpy(double* w, const double* u, double t, const double* k, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = u[i] + t * k[i];
+}
+__global__ void k_d2f(float* y, const double* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void k_f2d(double* y, const float* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+__global__ void k_jacobi(const double* r, const double* d, double* z, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = r[i] / d[i];
+}
+
+int launch_fill(ilh_ctx* c, double* p, double v, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(TPB), 0, c->stream, p, v, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_fillf, dim3(nblk(n)), dim3(TPB), 0, c->stream, p, v, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(TPB), 0, c->stream, y, a, x, b, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double* k, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_waxpy, dim3(nblk(n)), dim3(TPB), 0, c->stream, w, u, t, k, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_d2f, dim3(nblk(n)), dim3(TPB), 0, c->stream, y, x, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_cast_f2d(ilh_ctx* c, double* y, const float* x, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_f2d, dim3(nblk(n)), dim3(TPB), 0, c->stream, y, x, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_jacobi(ilh_ctx* c, const double* r, double* z) {
+  hipLaunchKernelGGL(k_jacobi, dim3(nblk(c->nh1)), dim3(TPB), 0, c->stream, r, c->Mdiag, z, c->nh1);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// ------------------------------------------------------------------ reductions
+// Deterministic two-pass reductions: a fixed grid writes one partial per block, a single
+// block sums the partials in a fixed order.
+template <int BS>
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[BS / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < BS / 64; ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+template <int BS>
+__device__ __forceinline__ double block_min(double v) {
+  __shared__ double sh[BS / 64];
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = v;
+  if (threadIdx.x == 0) {
+    r = sh[0];
+    for (int i = 1; i < BS / 64; ++i) r = fmin(r, sh[i]);
+  }
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(TPB) k_dot_part(const double* x, const double* y, int64_t n, double* part) {
+  double acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) acc += x[i] * y[i];
+  acc = block_sum<TPB>(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+__global__ void __launch_bounds__(TPB) k_sum_final(const double* part, int np, double* out, int is_min) {
+  double acc = is_min ? 1e300 : 0.0;
+  for (int i = threadIdx.x; i < np; i += TPB) acc = is_min ? fmin(acc, part[i]) : acc + part[i];
+  acc = is_min ? block_min<TPB>(acc) : block_sum<TPB>(acc);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+static int red_blocks(ilh_ctx* c, int64_t n) {
+  int b = (int)std::min<int64_t>((n + TPB - 1) / TPB, c->red_blocks);
+  return b < 1 ? 1 : b;
+}
+
+int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out) {
+  const int nb = red_blocks(c, n);
+  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(TPB), 0, c->stream, x, y, n, c->red);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, d_out, 0);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* out) {
+  double* d_out = c->red + c->red_blocks * 65;  // scalar slots after the partials
+  int st = dot_dev(c, x, y, n, d_out);
+  if (st) return st;
+  ILH_HIP(c, hipMemcpyAsync(c->red_host, d_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  *out = c->red_host[0];
+  return ILH_OK;
+}
+
+// multi-dot: out[j] = sum_i V[j*ldv + i] w[i], j < m (m <= 64)
+__global__ void __launch_bounds__(TPB) k_mdot_part(const double* V, int64_t ldv, int m, const double* w, int64_t n,
+                                                   double* part, int nb) {
+  for (int j = 0; j < m; ++j) {
+    double acc = 0;
+    const double* vj = V + (int64_t)j * ldv;
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) acc += vj[i] * w[i];
+    acc = block_sum<TPB>(acc);
+    if (threadIdx.x == 0) part[(int64_t)j * nb + blockIdx.x] = acc;
+  }
+}
+__global__ void __launch_bounds__(TPB) k_mdot_final(const double* part, int nb, int m, double* out) {
+  const int j = blockIdx.x;
+  double acc = 0;
+  for (int i = threadIdx.x; i < nb; i += TPB) acc += part[(int64_t)j * nb + i];
+  acc = block_sum<TPB>(acc);
+  if (threadIdx.x == 0) out[j] = acc;
+}
+int multidot_dev(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out) {
+  if (m <= 0) return ILH_OK;
+  const int nb = std::min(red_blocks(c, n), 256);
+  hipLaunchKernelGGL(k_mdot_part, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red, nb);
+  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+// w[i] += sign * sum_j h[j] V[j][i]
+__global__ void k_maxpy(double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int j = 0; j < m; ++j) acc += h[j] * V[(int64_t)j * ldv + i];
+    w[i] += sign * acc;
+  }
+}
+int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
+  if (m <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_maxpy, dim3(nblk(n)), dim3(TPB), 0, c->stream, w, V, ldv, m, h, sign, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// ------------------------------------------------------------------ mass operators
+// y += M_V x (values-only partial assembly).  bc != 0: constrained inputs read as zero and
+// constrained outputs receive x (the eliminated operator Mhat).
+template <int DIM, int D1D, int Q1D, int NE>
+__global__ void __launch_bounds__(256) k_mass(const KParams P, const double* x, double* y, int bc) {
+  constexpr int NQ = (DIM == 2) ? Q1D * Q1D : Q1D * Q1D * Q1D;
+  constexpr int ND = (DIM == 2) ? D1D * D1D : D1D * D1D * D1D;
+  constexpr int NT = NQ * NE;
+  constexpr int LBUF = (DIM == 2) ? D1D * Q1D : (D1D * D1D * Q1D + D1D * Q1D * Q1D);
+  __shared__ double sB[Q1D * D1D];
+  __shared__ double sX[NE][DIM][ND];
+  __shared__ double sW[NE][DIM][LBUF > NQ ? LBUF : NQ];
+  __shared__ double sQ[NE][DIM][NQ];
+  const int tid = threadIdx.x, z = tid / NQ, q = tid % NQ;
+  const int qx = q % Q1D, qy = (q / Q1D) % Q1D, qz = (DIM == 3) ? q / (Q1D * Q1D) : 0;
+  const int e0 = blockIdx.x * NE, k = P.k;
+  const int64_t N = P.N, s1 = P.ng[0], s2 = (int64_t)P.ng[0] * P.ng[1];
+  for (int i = tid; i < Q1D * D1D; i += NT) sB[i] = P.tab[i];
+  for (int i = tid; i < NE * DIM * ND; i += NT) {
+    const int li = i % ND, t = i / ND, c = t % DIM, zz = t / DIM, e = e0 + zz;
+    double val = 0;
+    if (e < P.Ne) {
+      const int a = li % D1D, b = (li / D1D) % D1D, cc = (DIM == 3) ? li / (D1D * D1D) : 0;
+      const int ex = e % P.n[0], ey = (e / P.n[0]) % P.n[1], ez = (DIM == 3) ? e / (P.n[0] * P.n[1]) : 0;
+      const int I = k * ex + a, J = k * ey + b, K = k * ez + cc;
+      const int gc = (c == 0) ? I : (c == 1 ? J : K);
+      const bool cons = gc == 0 || gc == P.ng[c] - 1;
+      val = (bc && cons) ? 0.0 : x[c * N + I + s1 * J + s2 * K];
+    }
+    sX[zz][c][li] = val;
+  }
+  __syncthreads();
+  double vq[DIM];
+  if constexpr (DIM == 2) {
+    for (int i = tid; i < NE * 2 * D1D * Q1D; i += NT) {
+      const int qxx = i % Q1D, t = i / Q1D, b = t % D1D, t2 = t / D1D, c = t2 & 1, zz = t2 >> 1;
+      double acc = 0;
+#pragma unroll
+      for (int a = 0; a < D1D; ++a) acc += sB[qxx * D1D + a] * sX[zz][c][a + D1D * b];
+      sW[zz][c][b * Q1D + qxx] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double acc = 0;
+#pragma unroll
+      for (int b = 0; b < D1D; ++b) acc += sB[qy * D1D + b] * sW[z][c][b * Q1D + qx];
+      vq[c] = acc;
+    }
+  } else {
+    for (int i = tid; i < NE * 3 * D1D * D1D * Q1D; i += NT) {
+      const int qxx = i % Q1D, t = i / Q1D, bcc = t % (D1D * D1D), t2 = t / (D1D * D1D), c = t2 % 3, zz = t2 / 3;
+      double acc = 0;
+#pragma unroll
+      for (int a = 0; a < D1D; ++a) acc += sB[qxx * D1D + a] * sX[zz][c][a + D1D * bcc];
+      sW[zz][c][bcc * Q1D + qxx] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < NE * 3 * D1D * Q1D * Q1D; i += NT) {
+      const int qxx = i % Q1D, t = i / Q1D, qyy = t % Q1D, t2 = t / Q1D, cc = t2 % D1D, t3 = t2 / D1D, c = t3 % 3,
+                zz = t3 / 3;
+      double acc = 0;
+#pragma unroll
+      for (int b = 0; b < D1D; ++b) acc += sB[qyy * D1D + b] * sW[zz][c][(cc * D1D + b) * Q1D + qxx];
+      sW[zz][c][D1D * D1D * Q1D + (cc * Q1D + qyy) * Q1D + qxx] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0;
+#pragma unroll
+      for (int cc = 0; cc < D1D; ++cc) acc += sB[qz * D1D + cc] * sW[z][c][D1D * D1D * Q1D + (cc * Q1D + qy) * Q1D + qx];
+      vq[c] = acc;
+    }
+  }
+  const int e = e0 + z;
+  const double mq = (e < P.Ne) ? P.mq[(int64_t)e * NQ + q] : 0.0;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) sQ[z][c][q] = mq * vq[c];
+  __syncthreads();
+  if constexpr (DIM == 2) {
+    for (int i = tid; i < NE * 2 * D1D * Q1D; i += NT) {
+      const int qxx = i % Q1D, t = i / Q1D, b = t % D1D, t2 = t / D1D, c = t2 & 1, zz = t2 >> 1;
+      double acc = 0;
+#pragma unroll
+      for (int qyy = 0; qyy < Q1D; ++qyy) acc += sB[qyy * D1D + b] * sQ[zz][c][qxx + Q1D * qyy];
+      sW[zz][c][b * Q1D + qxx] = acc;
+    }
+  } else {
+    for (int i = tid; i < NE * 3 * D1D * Q1D * Q1D; i += NT) {
+      const int qxx = i % Q1D, t = i / Q1D, qyy = t % Q1D, t2 = t / Q1D, cc = t2 % D1D, t3 = t2 / D1D, c = t3 % 3,
+                zz = t3 / 3;
+      double acc = 0;
+#pragma unroll
+      for (int qzz = 0; qzz < Q1D; ++qzz) acc += sB[qzz * D1D + cc] * sQ[zz][c][qxx + Q1D * (qyy + Q1D * qzz)];
+      sW[zz][c][D1D * D1D * Q1D + (cc * Q1D + qyy) * Q1D + qxx] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < NE * 3 * D1D * D1D * Q1D; i += NT) {
+      const int qxx = i % Q1D, t = i / Q1D, bcc = t % (D1D * D1D), t2 = t / (D1D * D1D), c = t2 % 3, zz = t2 / 3;
+      const int b = bcc % D1D, cc = bcc / D1D;
+      double acc = 0;
+#pragma unroll
+      for (int qyy = 0; qyy < Q1D; ++qyy) acc += sB[qyy * D1D + b] * sW[zz][c][D1D * D1D * Q1D + (cc * Q1D + qyy) * Q1D + qxx];
+      sW[zz][c][bcc * Q1D + qxx] = acc;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < NE * DIM * ND; i += NT) {
+    const int li = i % ND, t = i / ND, c = t % DIM, zz = t / DIM, e2 = e0 + zz;
+    if (e2 >= P.Ne) continue;
+    const int a = li % D1D, bcc = li / D1D;
+    double acc = 0;
+#pragma unroll
+    for (int qxx = 0; qxx < Q1D; ++qxx) acc += sB[qxx * D1D + a] * sW[zz][c][bcc * Q1D + qxx];
+    const int b = bcc % D1D, cc = (DIM == 3) ? bcc / D1D : 0;
+    const int ex = e2 % P.n[0], ey = (e2 / P.n[0]) % P.n[1], ez = (DIM == 3) ? e2 / (P.n[0] * P.n[1]) : 0;
+    const int I = k * ex + a, J = k * ey + b, K = k * ez + cc;
+    const int64_t gi = c * N + I + s1 * J + s2 * K;
+    const int gc = (c == 0) ? I : (c == 1 ? J : K);
+    const bool cons = gc == 0 || gc == P.ng[c] - 1;
+    if (bc && cons) {
+      const bool owner = (a < k || ex == P.n[0] - 1) && (b < k || ey == P.n[1] - 1) &&
+                         (DIM == 2 || cc < k || ez == P.n[2] - 1);
+      if (owner) unsafeAtomicAdd(&y[gi], x[gi]);
+    } else {
+      unsafeAtomicAdd(&y[gi], acc);
+    }
+  }
+}
+
+template <int DIM, int K>
+static void launch_mass_t(ilh_ctx* c, const double* x, double* y, int bc) {
+  constexpr int Q1D = 2 * K;
+  constexpr int NQ = (DIM == 2) ? Q1D * Q1D : Q1D * Q1D * Q1D;
+  constexpr int NE = (256 / NQ) > 0 ? (256 / NQ) : 1;
+  const int grid = (int)((c->Ne + NE - 1) / NE);
+  hipLaunchKernelGGL((k_mass<DIM, K + 1, Q1D, NE>), dim3(grid), dim3(NQ * NE), 0, c->stream, c->kp, x, y, bc);
+}
+
+static int mass_apply(ilh_ctx* c, const double* x, double* y, int bc) {
+  int st = launch_fill(c, y, 0.0, c->nh1);
+  if (st) return st;
+  if (c->dim == 2) {
+    switch (c->k) {
+      case 1: launch_mass_t<2, 1>(c, x, y, bc); break;
+      case 2: launch_mass_t<2, 2>(c, x, y, bc); break;
+      case 3: launch_mass_t<2, 3>(c, x, y, bc); break;
+      case 4: launch_mass_t<2, 4>(c, x, y, bc); break;
+    }
+  } else {
+    switch (c->k) {
+      case 1: launch_mass_t<3, 1>(c, x, y, bc); break;
+      case 2: launch_mass_t<3, 2>(c, x, y, bc); break;
+      case 3: launch_mass_t<3, 3>(c, x, y, bc); break;
+    }
+  }
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+int launch_mass_v(ilh_ctx* c, const double* x, double* y, int bc) { return mass_apply(c, x, y, bc); }
+
+// x_e = s_e Minv_ref b_e  (M_E,e = rho0_e |J0| Mref on the affine initial mesh)
+__global__ void k_me_inv(const double* Minv, const double* scale, const double* b, double* x, int64_t Ne, int Nl) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= Ne * Nl) return;
+  const int64_t e = i / Nl;
+  const int r = (int)(i % Nl);
+  double acc = 0;
+  for (int j = 0; j < Nl; ++j) acc += Minv[r * Nl + j] * b[e * Nl + j];
+  x[i] = scale[e] * acc;
+}
+int launch_mass_e_inv(ilh_ctx* c, const double* b, double* x) {
+  const int64_t n = c->Ne * c->Nl;
+  if (n == 0) return ILH_OK;
+  hipLaunchKernelGGL(k_me_inv, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, c->MEinv,
+                     c->MEinv + c->Nl * c->Nl, b, x, c->Ne, c->Nl);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// ------------------------------------------------------------------ device-scalar PCG
+// scalars s[0] = rz, s[1] = pAp, s[2] = rz_new, s[3] = bb, s[4] = rr
+__global__ void k_pcg_update_xr(double* x, double* r, const double* p, const double* Ap, const double* s, int64_t n) {
+  const double alpha = s[1] != 0.0 ? s[0] / s[1] : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * Ap[i];
+  }
+}
+__global__ void k_pcg_update_p(double* p, const double* z, double* s, int64_t n) {
+  const double beta = s[0] != 0.0 ? s[2] / s[0] : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+__global__ void k_copy_scalar(double* s, int dst, int src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) s[dst] = s[src];
+}
+
+int pcg_mass_v(ilh_ctx* c, const double* b, double* x, double rtol, int maxit, int check, int* iters,
+               double* relres) {
+  const int64_t n = c->nh1;
+  double* r = c->pcgbuf;
+  double* z = r + n;
+  double* p = z + n;
+  double* Ap = p + n;
+  double* s = Ap + n;
+  int st;
+  if ((st = launch_fill(c, x, 0.0, n))) return st;
+  ILH_HIP(c, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if ((st = launch_jacobi(c, r, z))) return st;
+  ILH_HIP(c, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if ((st = dot_dev(c, r, z, n, s + 0))) return st;
+  double bb = 0;
+  if (check > 0) {
+    if ((st = dot_host(c, b, b, n, &bb))) return st;
+    if (bb == 0.0) {
+      if (iters) *iters = 0;
+      if (relres) *relres = 0.0;
+      return ILH_OK;
+    }
+  }
+  int it = 0;
+  double rel = -1.0;
+  for (; it < maxit; ++it) {
+    if ((st = mass_apply(c, p, Ap, 1))) return st;
+    if ((st = dot_dev(c, p, Ap, n, s + 1))) return st;
+    hipLaunchKernelGGL(k_pcg_update_xr, dim3(nblk(n)), dim3(TPB), 0, c->stream, x, r, p, Ap, s, n);
+    if ((st = launch_jacobi(c, r, z))) return st;
+    if ((st = dot_dev(c, r, z, n, s + 2))) return st;
+    hipLaunchKernelGGL(k_pcg_update_p, dim3(nblk(n)), dim3(TPB), 0, c->stream, p, z, s, n);
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->stream, s, 0, 2);
+    ILH_HIP(c, hipGetLastError());
+    if (check > 0 && ((it + 1) % check == 0 || it + 1 == maxit)) {
+      double rr;
+      if ((st = dot_host(c, r, r, n, &rr))) return st;
+      rel = std::sqrt(rr / bb);
+      if (rel <= rtol) {
+        ++it;
+        break;
+      }
+    }
+  }
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  return ILH_OK;
+}
+
+// ------------------------------------------------------------------ per-qp diagnostics
+// Dense (non sum-factorised) evaluation at each quadrature point: used only for
+// diagnostics and set-up, never inside the Newton-Krylov loop.
+enum Diag { D_MINDET = 0, D_DT = 1, D_L1 = 2, D_IE = 3, D_INITE = 4 };
+
+template <int DIM>
+__device__ inline double sigma_min(const double J[DIM][DIM]) {
+  // smallest singular value = sqrt(smallest eigenvalue of J^T J)
+  double A[DIM][DIM];
+  for (int i = 0; i < DIM; ++i)
+    for (int j = 0; j < DIM; ++j) {
+      double acc = 0;
+      for (int c = 0; c < DIM; ++c) acc += J[c][i] * J[c][j];
+      A[i][j] = acc;
+    }
+  if constexpr (DIM == 2) {
+    const double tr = A[0][0] + A[1][1];
+    const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
+    const double lmax = 0.5 * tr + disc;
+    return sqrt(fmax(det / lmax, 0.0));
+  } else {
+    // eigenvalues of a symmetric 3x3 matrix (trigonometric solution of the cubic)
+    const double p1 = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double qq = (A[0][0] + A[1][1] + A[2][2]) / 3.0;
+    if (p1 == 0.0) return sqrt(fmin(A[0][0], fmin(A[1][1], A[2][2])));
+    const double p2 = (A[0][0] - qq) * (A[0][0] - qq) + (A[1][1] - qq) * (A[1][1] - qq) +
+                      (A[2][2] - qq) * (A[2][2] - qq) + 2.0 * p1;
+    const double p = sqrt(p2 / 6.0);
+    double Bm[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Bm[i][j] = (A[i][j] - (i == j ? qq : 0.0)) / p;
+    const double detB = Bm[0][0] * (Bm[1][1] * Bm[2][2] - Bm[1][2] * Bm[2][1]) -
+                        Bm[0][1] * (Bm[1][0] * Bm[2][2] - Bm[1][2] * Bm[2][0]) +
+                        Bm[0][2] * (Bm[1][0] * Bm[2][1] - Bm[1][1] * Bm[2][0]);
+    double rr = fmin(fmax(detB / 2.0, -1.0), 1.0);
+    const double phi = acos(rr) / 3.0;
+    const double l1 = qq + 2.0 * p * cos(phi);
+    const double l3 = qq + 2.0 * p * cos(phi + 2.0943951023931954923);
+    (void)l1;
+    return sqrt(fmax(l3, 0.0));
+  }
+}
+
+__device__ inline double prob_velocity(int prob, int c, const double* X) {
+  const double pi = 3.14159265358979323846;
+  if (prob == ILH_PROBLEM_TG2D) {
+    return c == 0 ? sin(pi * X[0]) * cos(pi * X[1]) : -cos(pi * X[0]) * sin(pi * X[1]);
+  }
+  if (prob == ILH_PROBLEM_TG3D) {
+    if (c == 0) return sin(pi * X[0]) * cos(pi * X[1]) * cos(pi * X[2]);
+    if (c == 1) return -cos(pi * X[0]) * sin(pi * X[1]) * cos(pi * X[2]);
+    return 0.0;
+  }
+  return 0.0;
+}
+
+// tab layout: B [Q1D][D1D], G [Q1D][D1D], BL [Q1D][L1D], w1 [Q1D], xg [Q1D], gll [D1D]
+template <int DIM>
+__global__ void __launch_bounds__(256) k_diag(const KParams P, int mode, int prob, const double* u, double cfl,
+                                              double* part) {
+  __shared__ double sB[64], sG[64], sBL[64], sW1[8];
+  const int k = P.k, D1D = k + 1, Q1D = 2 * k, L1D = k;
+  const int NQ = (DIM == 2) ? Q1D * Q1D : Q1D * Q1D * Q1D;
+  for (int i = threadIdx.x; i < Q1D * D1D; i += blockDim.x) {
+    sB[i] = P.tab[i];
+    sG[i] = P.tab[Q1D * D1D + i];
+  }
+  for (int i = threadIdx.x; i < Q1D * L1D; i += blockDim.x) sBL[i] = P.tab[2 * Q1D * D1D + i];
+  for (int i = threadIdx.x; i < Q1D; i += blockDim.x) sW1[i] = P.tab[2 * Q1D * D1D + Q1D * L1D + i];
+  __syncthreads();
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)P.Ne * NQ;
+  const bool is_min = (mode == D_MINDET || mode == D_DT);
+  double val = is_min ? 1e300 : 0.0;
+  if (gid < total) {
+    const int e = (int)(gid / NQ), q = (int)(gid % NQ);
+    const int qi[3] = {q % Q1D, (q / Q1D) % Q1D, (DIM == 3) ? q / (Q1D * Q1D) : 0};
+    const int ex = e % P.n[0], ey = (e / P.n[0]) % P.n[1], ez = (DIM == 3) ? e / (P.n[0] * P.n[1]) : 0;
+    const int64_t N = P.N, s1 = P.ng[0], s2 = (int64_t)P.ng[0] * P.ng[1];
+    double J[DIM][DIM], Gv[DIM][DIM], xq[DIM], vq[DIM];
+    for (int c = 0; c < DIM; ++c) {
+      xq[c] = vq[c] = 0;
+      for (int a = 0; a < DIM; ++a) J[c][a] = Gv[c][a] = 0;
+    }
+    const int NDn = (DIM == 2) ? D1D * D1D : D1D * D1D * D1D;
+    if (mode != D_IE) {
+      for (int li = 0; li < NDn; ++li) {
+        const int nl[3] = {li % D1D, (li / D1D) % D1D, (DIM == 3) ? li / (D1D * D1D) : 0};
+        double w = 1, g[DIM];
+        for (int d = 0; d < DIM; ++d) g[d] = 1;
+        for (int d = 0; d < DIM; ++d) {
+          const double bv = sB[qi[d] * D1D + nl[d]], gv = sG[qi[d] * D1D + nl[d]];
+          w *= bv;
+          for (int d2 = 0; d2 < DIM; ++d2) g[d2] *= (d2 == d) ? gv : bv;
+        }
+        const int64_t node = (k * ex + nl[0]) + s1 * (k * ey + nl[1]) + s2 * (k * ez + nl[2]);
+        for (int c = 0; c < DIM; ++c) {
+          const double xv = u[c * N + node];
+          const double vv = u[DIM * N + c * N + node];
+          xq[c] += w * xv;
+          vq[c] += w * vv;
+          for (int d = 0; d < DIM; ++d) {
+            J[c][d] += g[d] * xv;
+            Gv[c][d] += g[d] * vv;
+          }
+        }
+      }
+    }
+    double eq = 0;
+    if (mode == D_DT || mode == D_IE) {
+      const int NLn = (DIM == 2) ? L1D * L1D : L1D * L1D * L1D;
+      for (int j = 0; j < NLn; ++j) {
+        const int al = j % L1D, bl = (j / L1D) % L1D, cl = (DIM == 3) ? j / (L1D * L1D) : 0;
+        double ph = sBL[qi[0] * L1D + al] * sBL[qi[1] * L1D + bl];
+        if (DIM == 3) ph *= sBL[qi[2] * L1D + cl];
+        eq += ph * u[2 * DIM * N + (int64_t)e * NLn + j];
+      }
+    }
+    if (mode == D_MINDET) {
+      double Ji[DIM][DIM], det;
+      inv_det<DIM, double>(J, Ji, det);
+      val = det;
+    } else if (mode == D_IE) {
+      val = P.mq[gid] * eq;
+    } else if (mode == D_DT) {
+      double Ji[DIM][DIM], det;
+      inv_det<DIM, double>(J, Ji, det);
+      const double gam = P.gamma[e];
+      double ep, r;
+      e_plus<double>(eq, P.eps_e, ep, r);
+      const double cs = sqrt(gam * (gam - 1) * ep);
+      double nu = 0;  // mu / rho
+      if (P.visc) {
+        double div = 0;
+        for (int c = 0; c < DIM; ++c)
+          for (int a = 0; a < DIM; ++a) div += Gv[c][a] * Ji[a][c];
+        const double h = P.h0 * ((DIM == 2) ? sqrt(det / P.detJ0[gid]) : cbrt(det / P.detJ0[gid]));
+        const double dv = h * div;
+        const double dsc = P.dsc_mode ? 2.0 * h * cs * P.hc_inv : P.dsc_w;
+        const double aabs = sqrt(dv * dv + dsc * dsc);
+        const double psi = 0.5 + 0.5 * tanh(-dv / (2 * dsc) - P.psi_shift);
+        nu = h * (P.q2 * aabs + P.q1 * cs * psi);
+      }
+      const double hmin = sigma_min<DIM>(J) / k;
+      const double inv_dt = cs / hmin + 2.5 * nu / (hmin * hmin);
+      val = cfl / inv_dt;
+    } else if (mode == D_L1) {
+      double Ji[DIM][DIM], det;
+      inv_det<DIM, double>(J, Ji, det);
+      double err2 = 0;
+      for (int c = 0; c < DIM; ++c) {
+        const double d = vq[c] - prob_velocity(prob, c, xq);
+        err2 += d * d;
+      }
+      double wq = 1;
+      for (int d = 0; d < DIM; ++d) wq *= sW1[qi[d]];
+      val = wq * det * sqrt(err2);
+    }
+  }
+  double r = is_min ? block_min<256>(val) : block_sum<256>(val);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+static int diag_host(ilh_ctx* c, int mode, const double* u, double cfl, double* out) {
+  const int NQ = c->Q;
+  const int64_t total = c->Ne * (int64_t)NQ;
+  const int nb = (int)((total + 255) / 256);
+  double* part = c->ws;  // nb doubles
+  if (c->ws_len < nb + 1) return fail(c, ILH_EINVAL, "workspace too small for diagnostics");
+  if (c->dim == 2)
+    hipLaunchKernelGGL(k_diag<2>, dim3(nb), dim3(256), 0, c->stream, c->kp, mode, c->s.problem, u, cfl, part);
+  else
+    hipLaunchKernelGGL(k_diag<3>, dim3(nb), dim3(256), 0, c->stream, c->kp, mode, c->s.problem, u, cfl, part);
+  const bool is_min = (mode == D_MINDET || mode == D_DT);
+  double* d_out = c->red + c->red_blocks * 65 + 1;
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, part, nb, d_out, is_min ? 1 : 0);
+  ILH_HIP(c, hipGetLastError());
+  ILH_HIP(c, hipMemcpyAsync(c->red_host, d_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  *out = c->red_host[0];
+  return ILH_OK;
+}
+
+int min_detj_host(ilh_ctx* c, const double* x, double* out) { return diag_host(c, D_MINDET, x, 0.0, out); }
+int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out) { return diag_host(c, D_DT, u, cfl, out); }
+int l1_error_host(ilh_ctx* c, const double* u, double* out) { return diag_host(c, D_L1, u, 0.0, out); }
+int energy_host(ilh_ctx* c, const double* u, double* ke, double* ie) {
+  int st = diag_host(c, D_IE, u, 0.0, ie);
+  if (st) return st;
+  // KE = 1/2 v^T M_V v
+  double* Mv = c->pcgbuf;
+  const double* v = u + c->nh1;
+  if ((st = mass_apply(c, v, Mv, 0))) return st;
+  double vmv;
+  if ((st = dot_host(c, v, Mv, c->nh1, &vmv))) return st;
+  *ke = 0.5 * vmv;
+  return ILH_OK;
+}
+
+// ------------------------------------------------------------------ initial state
+// nodes: x0 on the affine mesh, v0 = nodal interpolation of the problem velocity
+template <int DIM>
+__global__ void k_init_nodes(const KParams P, int prob, double lo0, double lo1, double lo2, double h0, double h1,
+                             double h2, double* u) {
+  const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (node >= P.N) return;
+  const int k = P.k, Q1D = 2 * k, D1D = k + 1, L1D = k;
+  const double* gll = P.tab + 2 * Q1D * D1D + Q1D * L1D + 2 * Q1D;
+  const double lo[3] = {lo0, lo1, lo2}, hh[3] = {h0, h1, h2};
+  int64_t rem = node;
+  double X[3] = {0, 0, 0};
+  int gi[3];
+  for (int d = 0; d < DIM; ++d) {
+    gi[d] = (int)(rem % P.ng[d]);
+    rem /= P.ng[d];
+    int ex = gi[d] / k;
+    if (ex > P.n[d] - 1) ex = P.n[d] - 1;
+    const int loc = gi[d] - k * ex;
+    X[d] = lo[d] + hh[d] * (ex + gll[loc]);
+  }
+  for (int c = 0; c < DIM; ++c) {
+    u[c * P.N + node] = X[c];
+    const bool cons = gi[c] == 0 || gi[c] == P.ng[c] - 1;
+    u[DIM * P.N + c * P.N + node] = cons ? 0.0 : prob_velocity(prob, c, X);
+  }
+}
+
+__device__ inline double prob_energy(int prob, const double* X, double gam, double e0c) {
+  const double pi = 3.14159265358979323846;
+  if (prob == ILH_PROBLEM_TG2D) {
+    const double p = 0.25 * (cos(2 * pi * X[0]) + cos(2 * pi * X[1])) + 1.0;
+    return p / (gam - 1.0);
+  }
+  if (prob == ILH_PROBLEM_TG3D) {
+    const double p = 1.0 + (cos(2 * pi * X[0]) + cos(2 * pi * X[1])) * (cos(2 * pi * X[2]) + 2.0) / 16.0;
+    return p / (gam - 1.0);
+  }
+  return e0c;
+}
+
+// rhs_j = sum_q m_q e0(x0_q) phi_j(xi_q), one thread per (element, j)
+template <int DIM>
+__global__ void k_init_rhs(const KParams P, int prob, const double* e0, double lo0, double lo1, double lo2,
+                           double h0, double h1, double h2, double* rhs) {
+  const int k = P.k, Q1D = 2 * k, D1D = k + 1, L1D = k;
+  const int NLn = (DIM == 2) ? L1D * L1D : L1D * L1D * L1D;
+  const int NQ = (DIM == 2) ? Q1D * Q1D : Q1D * Q1D * Q1D;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)P.Ne * NLn) return;
+  const int e = (int)(i / NLn), j = (int)(i % NLn);
+  const double* BL = P.tab + 2 * Q1D * D1D;
+  const double* xg = P.tab + 2 * Q1D * D1D + Q1D * L1D + Q1D;
+  const int jl[3] = {j % L1D, (j / L1D) % L1D, (DIM == 3) ? j / (L1D * L1D) : 0};
+  const int ei[3] = {e % P.n[0], (e / P.n[0]) % P.n[1], (DIM == 3) ? e / (P.n[0] * P.n[1]) : 0};
+  const double lo[3] = {lo0, lo1, lo2}, hh[3] = {h0, h1, h2};
+  const double gam = P.gamma[e];
+  double acc = 0;
+  for (int q = 0; q < NQ; ++q) {
+    const int qi[3] = {q % Q1D, (q / Q1D) % Q1D, (DIM == 3) ? q / (Q1D * Q1D) : 0};
+    double X[3] = {0, 0, 0}, ph = 1;
+    for (int d = 0; d < DIM; ++d) {
+      X[d] = lo[d] + hh[d] * (ei[d] + xg[qi[d]]);
+      ph *= BL[qi[d] * L1D + jl[d]];
+    }
+    acc += P.mq[(int64_t)e * NQ + q] * prob_energy(prob, X, gam, e0[e]) * ph;
+  }
+  rhs[i] = acc;
+}
+
+int init_state_dev(ilh_ctx* c, double* u, const double*) {
+  const double h[3] = {(c->hi[0] - c->lo[0]) / c->n[0], (c->hi[1] - c->lo[1]) / c->n[1],
+                       c->dim == 3 ? (c->hi[2] - c->lo[2]) / c->n[2] : 1.0};
+  const int nb = (int)((c->N + 255) / 256);
+  if (c->dim == 2)
+    hipLaunchKernelGGL(k_init_nodes<2>, dim3(nb), dim3(256), 0, c->stream, c->kp, c->s.problem, c->lo[0], c->lo[1],
+                       c->lo[2], h[0], h[1], h[2], u);
+  else
+    hipLaunchKernelGGL(k_init_nodes<3>, dim3(nb), dim3(256), 0, c->stream, c->kp, c->s.problem, c->lo[0], c->lo[1],
+                       c->lo[2], h[0], h[1], h[2], u);
+  const int64_t nl = c->Ne * c->Nl;
+  double* rhs = c->ws;
+  if (c->ws_len < nl) return fail(c, ILH_EINVAL, "workspace too small for the initial state");
+  const int nb2 = (int)((nl + 255) / 256);
+  if (c->dim == 2)
+    hipLaunchKernelGGL(k_init_rhs<2>, dim3(nb2), dim3(256), 0, c->stream, c->kp, c->s.problem, c->e0, c->lo[0],
+                       c->lo[1], c->lo[2], h[0], h[1], h[2], rhs);
+  else
+    hipLaunchKernelGGL(k_init_rhs<3>, dim3(nb2), dim3(256), 0, c->stream, c->kp, c->s.problem, c->e0, c->lo[0],
+                       c->lo[1], c->lo[2], h[0], h[1], h[2], rhs);
+  ILH_HIP(c, hipGetLastError());
+  return launch_mass_e_inv(c, rhs, u + 2 * c->nh1);
+}
+
+}  // namespace ilh

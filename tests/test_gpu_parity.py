@@ -1,0 +1,136 @@
+"""GPU parity of every single-call entry point against the CPU oracle.
+
+Inputs are seeded (seeded_inputs) perturbations of the oracle's initial state; each
+output vector is compared with ||gpu - oracle|| / ||oracle|| against the bounds
+1e-12 (FP64 kernels) and 1e-5 (FP32 Jacobian actions).  Meshes are chosen so that the
+last work-group of every element kernel is partial (ragged tail).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import make_pair, random_dir, random_state, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("tg2d", (8, 8), 2, None),
+    ("tg2d", (13, 11), 3, None),
+    ("tg2d", (6, 5), 1, None),
+    ("tg2d", (5, 4), 4, None),
+    ("triple", (14, 6), 3, "const"),
+    ("triple", (9, 5), 2, "formula"),
+    ("tg3d", (5, 3, 4), 2, None),
+    ("tg3d", (3, 2, 2), 2, "formula"),
+    ("tg3d", (3, 3, 2), 1, None),
+    ("tg3d", (2, 2, 1), 3, "const"),
+]
+IDS = ["%s-%s-k%d-%s" % (p, "x".join(map(str, n)), k, v) for p, n, k, v in CASES]
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", params=CASES, ids=IDS)
+def pair(request):
+    p, n, k, v = request.param
+    O, G = make_pair(p, n, k, v, width=0.05 if v == "const" else 1e-3)
+    return O, G
+
+
+def test_init_state(pair):
+    O, G = pair
+    u = to_np(G.init_state())
+    uo = O.init_state()
+    assert rel(u, uo) <= 1e-13
+
+
+def test_force(pair):
+    O, G = pair
+    w = random_state(O, 1)
+    f1, ftv = G.force(to_dev(w))
+    o1, otv = O.force(w)
+    assert rel(to_np(f1), o1) <= FP64_TOL
+    assert rel(to_np(ftv), otv) <= FP64_TOL
+
+
+def test_residual(pair):
+    O, G = pair
+    u = random_state(O, 2)
+    k = 0.1 * random_dir(O, 3)
+    tau = 0.003
+    r = to_np(G.residual(to_dev(k), to_dev(u), tau))
+    ro = O.residual(k, u, tau)
+    assert rel(r, ro) <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [(64, FP64_TOL), (32, FP32_TOL)])
+def test_jvp(pair, prec, tol):
+    from oracle.krylov import jvp_cs
+    O, G = pair
+    u = random_state(O, 4)
+    k = 0.1 * random_dir(O, 5)
+    dk = random_dir(O, 6)
+    tau = 0.004
+    dt = torch.float64 if prec == 64 else torch.float32
+    j = to_np(G.jvp(to_dev(k), to_dev(u), tau, to_dev(dk, dt), prec))
+    jo = jvp_cs(lambda q: O.residual(q, u, tau), k, dk)
+    assert rel(j, jo) <= tol, rel(j, jo)
+    # block-wise too: the x, v and e rows separately
+    for a, b in ((0, O.nh1), (O.nh1, 2 * O.nh1), (2 * O.nh1, O.nblock)):
+        assert rel(j[a:b], jo[a:b]) <= 10 * tol
+
+
+@pytest.mark.parametrize("prec,tol", [(64, FP64_TOL), (32, FP32_TOL)])
+def test_force_jvp(pair, prec, tol):
+    from oracle.krylov import jvp_cs
+    O, G = pair
+    w = random_state(O, 7)
+    dw = random_dir(O, 8)
+    dt = torch.float64 if prec == 64 else torch.float32
+    d1, dtv = G.force_jvp(to_dev(w), to_dev(dw, dt), prec)
+    o1 = jvp_cs(lambda q: O.force(q)[0], w, dw)
+    otv = jvp_cs(lambda q: O.force(q)[1], w, dw)
+    assert rel(to_np(d1), o1) <= tol
+    assert rel(to_np(dtv), otv) <= tol
+
+
+def test_mass_operators(pair):
+    O, G = pair
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(O.nh1)
+    assert rel(to_np(G.mass_v_apply(to_dev(x))), O.mass_v(x)) <= 1e-13
+    e = rng.standard_normal(O.nl2)
+    assert rel(to_np(G.mass_e_inv(to_dev(e))), O.mass_e_inv(e)) <= 1e-13
+    b = O.mass_v(x)
+    sol, its, rr = G.mass_v_solve(to_dev(b), 1e-13, 1000)
+    assert rr <= 1e-13
+    assert rel(to_np(sol), O.mass_v_solve(b)) <= 1e-11
+
+
+def test_diagnostics(pair):
+    O, G = pair
+    u = random_state(O, 10, amp=0.01)
+    du = to_dev(u)
+    ke, ie = G.energy(du)
+    ko, io = O.energy(u)
+    assert abs(ke - ko) <= 1e-13 * abs(ko) and abs(ie - io) <= 1e-13 * abs(io)
+    assert abs(G.min_detj(du) - O.min_detj(u)) <= 1e-13 * abs(O.min_detj(u))
+    assert abs(G.dt_estimate(du, 0.5) - O.dt_estimate(u, 0.5)) <= 1e-12 * O.dt_estimate(u, 0.5)
+    if O.prob.exact_v is not None:
+        assert abs(G.l1_error(du) - O.l1_velocity_error(u)) <= 1e-12 * O.l1_velocity_error(u)
+
+
+def test_rate(pair):
+    O, G = pair
+    u = random_state(O, 11, amp=0.01)
+    f = to_np(G.rate(to_dev(u)))
+    assert rel(f, O.rate(u)) <= 1e-11
+
+
+def test_zero_direction_gives_zero():
+    O, G = make_pair("tg2d", (4, 3), 3)
+    u = to_dev(O.init_state())
+    k = torch.zeros_like(u)
+    z = G.jvp(k, u, 0.01, torch.zeros_like(u), 64)
+    assert float(z.abs().max()) == 0.0
