@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the implicit Lagrangian hydrodynamics hot path on one MI355X.
+
+Workload (default): 2D Taylor-Green vortex on [0,1]^2, 128 x 128 quadrilaterals, Q3Q2
+(36 quadrature points per element, 589,824 in total), gamma 5/3, no viscosity, implicit
+midpoint steps at 4x the explicit CFL-0.5 time step, FP64 residual / mass solves / Newton
+test, FP32 Jacobian actions inside FGMRES, Newton tolerance 1e-10.
+
+A timed "step" is one implicit midpoint step: plain initial iterate, then Newton-FGMRES
+(residual, Jacobian actions, mass preconditioner, detJ line search) and the update.
+
+Printed JSON line:
+  value       Jacobian-action throughput in quadrature points per second: N_qp divided by
+              the mean duration of the FP32 Jacobian-action kernel launches inside the
+              timed steps (HIP events recorded by the library on its stream);
+  ms_per_step wall time per implicit step (host synchronised at both ends);
+  roofline    algorithmic bytes of one Jacobian-action launch / mean launch time vs 8 TB/s;
+  cpu_baseline the CPU oracle's complex-step Jacobian action on the same state.
+Run with --gpus N, N > 1: exits, this build runs on one GPU only.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128, help="elements per side")
+    ap.add_argument("--order", type=int, default=3)
+    ap.add_argument("--cfl-factor", type=float, default=4.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--roofline-shape", type=int, default=0,
+                    help="also time the JVP on an n x n Q3Q2 state of this size (0 = off)")
+    return ap.parse_args()
+
+
+def jvp_bytes(H, prec):
+    """Algorithmic HBM bytes of one Jacobian-action launch: every vector read/written once."""
+    if prec == 32:
+        state = H.nh1 * 8 + H.nh1 * 4 + H.nl2 * 4   # x FP64, v and e FP32 shadow
+        vec = H.nblock * 4
+    else:
+        state = H.nblock * 8
+        vec = H.nblock * 8
+    return state + 2 * vec + H.nqp * 8 + H.Ne * 8   # + direction, output, m_q, gamma
+
+
+def run_steps(H, u, dt, nsteps, opts, hist, ilh):
+    stats = []
+    for _ in range(nsteps):
+        g = H.plain_guess(u, hist)
+        k, st = H.implicit_step(u, dt, guess=g, opts=opts)
+        hist.append(k)
+        if len(hist) > 2:
+            hist.pop(0)
+        stats.append(st)
+    return stats
+
+
+def cpu_baseline(u_np, n, k, dt, budget_s=30.0):
+    """Oracle complex-step Jacobian action of the residual at the benchmark state."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:
+        limiter = None
+    from oracle.hydro import Hydro as OHydro
+    from oracle.krylov import jvp_cs
+    import seeded_inputs as si
+    O = OHydro("tg2d", (n, n), k)
+    kk = np.zeros(O.nblock)
+    dk = si.block_direction(7, O.nh1, O.nl2, sx=1.0 / (n * k), sv=1.0, se=1.0)
+    times = []
+    t_all = time.time()
+    while True:
+        t0 = time.perf_counter()
+        jvp_cs(lambda q: O.residual(q, u_np, 0.5 * dt), kk, dk)
+        times.append(time.perf_counter() - t0)
+        if time.time() - t_all + times[-1] > budget_s or len(times) >= 3:
+            break
+    nqp = O.mesh.Ne * O.Q
+    return {"value": nqp / float(np.median(times)), "unit": "quad-pts/s", "cores": 1, "kind": "oracle",
+            "sample": "%d complex-step Jacobian action(s) of the stage residual on the full %dx%d Q%dQ%d "
+                      "benchmark state (%d qp), NumPy FP64/complex128, 1 thread; median" %
+                      (len(times), n, n, k, k - 1, nqp)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (no sharding or collectives); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2609_16424_amd as ilh
+
+    n, k = args.n, args.order
+    H = ilh.Hydro("tg2d", (n, n), k)
+    u0 = H.init_state()
+    dt = args.cfl_factor * H.dt_estimate(u0, 0.5)
+    opts32 = ilh.newton_options(tol=1e-10, jvp_prec=32)
+    opts64 = ilh.newton_options(tol=1e-10, jvp_prec=64)
+
+    # warm-up from the initial state
+    u = u0.clone()
+    hist = []
+    run_steps(H, u, dt, args.warmup, opts32, hist, ilh)
+    u_start = u.clone()
+    hist_start = [h.clone() for h in hist]
+    torch.cuda.synchronize()
+
+    # timed FP32-JVP leg
+    H.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = run_steps(H, u, dt, args.steps, opts32, hist, ilh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = H.timing_read()
+    H.timing(False)
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    jvp_ms, jvp_n = tim["jvp"]
+    jvp_avg_s = 1e-3 * jvp_ms / max(jvp_n, 1)
+    value = H.nqp / jvp_avg_s
+    bytes32 = jvp_bytes(H, 32)
+    achieved = bytes32 / jvp_avg_s / 1e9
+    u32 = u.clone()
+    newton = [s["newton"] for s in stats]
+    gmres = [s["gmres"] for s in stats]
+    ke, ie = H.energy(u32)
+
+    extra = {}
+    if not args.no_fp64_leg:
+        u = u_start.clone()
+        hist = [h.clone() for h in hist_start]
+        H.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st64 = run_steps(H, u, dt, args.steps, opts64, hist, ilh)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tim64 = H.timing_read()
+        H.timing(False)
+        j64_ms, j64_n = tim64["jvp"]
+        extra["all_fp64"] = {
+            "ms_per_step": 1e3 * (t1 - t0) / args.steps,
+            "jvp_qps": H.nqp / (1e-3 * j64_ms / max(j64_n, 1)),
+            "jvp_avg_us": 1e3 * j64_ms / max(j64_n, 1),
+            "newton_per_step": float(np.mean([s["newton"] for s in st64])),
+            "gmres_per_step": float(np.mean([s["gmres"] for s in st64])),
+            "rel_state_diff_vs_fp32_jvp": float(torch.linalg.norm(u - u32) / torch.linalg.norm(u)),
+        }
+
+    roof_extra = None
+    if args.roofline_shape:
+        m = args.roofline_shape
+        HR = ilh.Hydro("tg2d", (m, m), 3)
+        uR = HR.init_state()
+        uR[:HR.nh1] += 0.05 * uR[HR.nh1:2 * HR.nh1]
+        kR = torch.zeros_like(uR)
+        HR.linearize(kR, uR, 0.5 * HR.dt_estimate(uR, 2.0))
+        dk = torch.randn(HR.nblock, device=uR.device, dtype=torch.float64,
+                         generator=torch.Generator(device=uR.device).manual_seed(3))
+        dk32 = dk.float()
+        out32 = torch.empty_like(dk32)
+        for _ in range(3):
+            HR.jvp_lin(dk32, 32, out32)
+        HR.timing(True)
+        for _ in range(20):
+            HR.jvp_lin(dk32, 32, out32)
+        tr = HR.timing_read()
+        HR.timing(False)
+        avg = 1e-3 * tr["jvp"][0] / tr["jvp"][1]
+        roof_extra = {"shape": "%dx%d Q3Q2 TG (displaced)" % (m, m), "n_qp": HR.nqp,
+                      "jvp_qps": HR.nqp / avg, "achieved_GBs": jvp_bytes(HR, 32) / avg / 1e9,
+                      "frac": jvp_bytes(HR, 32) / avg / 1e9 / HBM_PEAK_GBS,
+                      "bytes_per_launch": jvp_bytes(HR, 32)}
+        del HR
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(u_start.detach().cpu().numpy(), n, k, dt)
+
+    out = {
+        "metric": "JVP quad-pts/s (% HBM roofline); s/implicit step, learned-guess vs plain",
+        "value": value,
+        "unit": "quad-pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (Jacobian action) / f64 (residual, masses, Newton)",
+        "data": "synthetic (analytic Taylor-Green initial state)",
+        "config": {"workload": "2D Taylor-Green %dx%d Q%dQ%d, gamma 5/3, no viscosity, implicit midpoint at "
+                               "%gx explicit CFL 0.5 (dt=%.4g), Newton tol 1e-10, FP32 GMRES JVP" %
+                               (n, n, k, k - 1, args.cfl_factor, dt),
+                   "n_qp": H.nqp, "n_block": H.nblock},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_elem2d<4,6,JVP,float,7>", "bytes_per_launch": bytes32,
+                     "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n},
+        "cpu_baseline": cpu,
+        "s_per_implicit_step_plain": ms_per_step / 1e3,
+        "newton_per_step": float(np.mean(newton)),
+        "gmres_per_step": float(np.mean(gmres)),
+        "kernel_ms_per_step": {kname: v[0] / args.steps for kname, v in tim.items()},
+        "energy_after": ke + ie,
+    }
+    out.update(extra)
+    if roof_extra:
+        out["roofline_large_shape"] = roof_extra
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

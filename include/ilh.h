@@ -163,6 +163,12 @@ int ilh_l1_velocity_error(ilh_ctx* ctx, const double* u, double* err);
 /* Explicit rate f(u) = [u_v; -Mhat^-1 P_u F(u) 1; M_E^-1 (F(u)^T u_v + b)] [block]. */
 int ilh_rate(ilh_ctx* ctx, const double* u, double* f);
 
+/* Plain initial iterate of a stage solve: nhist = 0 -> out = f(u) (ilh_rate);
+ * nhist = 1 -> out = k1; nhist >= 2 -> out = 2 k1 - k2 (linear extrapolation of the two
+ * previous converged stage rates).  k1, k2 [block] may be NULL when unused. */
+int ilh_plain_guess(ilh_ctx* ctx, const double* u, const double* k1, const double* k2,
+                    int nhist, double* out);
+
 /* Newton-Krylov options (host).  Converged when ||R(k)|| <= tol ||R(0; tau, u)||. */
 typedef struct {
   double tol;          /* relative nonlinear tolerance (1e-10 for the benchmarks) */
@@ -202,6 +208,17 @@ int ilh_implicit_step(ilh_ctx* ctx, double* u, double dt, const double* k_guess,
  * Higher-order SDIRK steps are built from these stage solves. */
 int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double* k_guess,
                     double* k_out, const ilh_newton_opts* o, ilh_step_stats* st);
+
+/* ---- measurement --------------------------------------------------------------------- */
+/* Kernel timing with HIP events recorded on the context stream around each launch of the
+ * timed kernel classes: 0 = Jacobian-action element kernel, 1 = residual element kernel,
+ * 2 = velocity-mass element kernel, 3 = Krylov orthogonalisation (multi-dot / multi-axpy),
+ * 4 = other Newton-Krylov vector kernels.  ilh_timing_enable(ctx, 1) resets the counters;
+ * ilh_timing_read synchronises the stream and returns, per class, the summed kernel time in
+ * milliseconds and the number of timed launches (host arrays of ILH_TIMING_CLASSES). */
+#define ILH_TIMING_CLASSES 5
+int ilh_timing_enable(ilh_ctx* ctx, int on);
+int ilh_timing_read(ilh_ctx* ctx, double* ms, int64_t* launches);
 
 /* ---- learned Newton initial guess (per-element MLP) --------------------------------- */
 /* Feature / target layout per element (2D only): velocity dofs [2][(k+1)^2], energy

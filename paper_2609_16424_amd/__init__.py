@@ -214,6 +214,26 @@ class Hydro:
         self._check(self.lib.ilh_rate(self.ctx, self._vec(u, self.nblock, name="u"), _ptr(f)))
         return f
 
+    def plain_guess(self, u, history):
+        """Explicit rate, last rate, or linear extrapolation of the last two (most recent last)."""
+        out = self.new()
+        k1 = self._vec(history[-1], self.nblock, name="k1") if len(history) >= 1 else None
+        k2 = self._vec(history[-2], self.nblock, name="k2") if len(history) >= 2 else None
+        self._stream()
+        self._check(self.lib.ilh_plain_guess(self.ctx, self._vec(u, self.nblock, name="u"), k1, k2,
+                                             min(len(history), 2), _ptr(out)))
+        return out
+
+    def timing(self, on=True):
+        self._check(self.lib.ilh_timing_enable(self.ctx, int(bool(on))))
+
+    def timing_read(self):
+        ms = (C.c_double * 5)()
+        cnt = (C.c_int64 * 5)()
+        self._check(self.lib.ilh_timing_read(self.ctx, ms, cnt))
+        names = ("jvp", "residual", "mass", "krylov", "precond")
+        return {nm: (ms[i], cnt[i]) for i, nm in enumerate(names)}
+
     def stage_solve(self, ubase, tau, guess=None, opts=None):
         opts = opts or newton_options()
         k = self.new()

@@ -65,9 +65,12 @@ SIGNATURES = {
     "ilh_dt_estimate": (I, [P, P, D, C.POINTER(D)]),
     "ilh_l1_velocity_error": (I, [P, P, C.POINTER(D)]),
     "ilh_rate": (I, [P, P, P]),
+    "ilh_plain_guess": (I, [P, P, P, P, I, P]),
     "ilh_newton_defaults": (None, [C.POINTER(NewtonOpts)]),
     "ilh_implicit_step": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
+    "ilh_timing_enable": (I, [P, I]),
+    "ilh_timing_read": (I, [P, C.POINTER(D), C.POINTER(I64)]),
     "ilh_guess_features": (I, [P, P, D, D, D, P, I]),
     "ilh_guess_targets": (I, [P, P, D, D, P, I]),
     "ilh_guess_assemble": (I, [P, P, I, D, D, P, P, D, P]),

@@ -92,6 +92,13 @@ struct ilh_ctx {
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   double* hdev = nullptr;       // [4 * 72] device scalars of the Arnoldi step
   double* hhost = nullptr;      // pinned mirror of hdev
+  // kernel timing (HIP events)
+  bool timing = false;
+  std::vector<hipEvent_t> tev;  // pairs
+  std::vector<int> tcls;
+  int tused = 0;
+  double tms[ILH_TIMING_CLASSES] = {0, 0, 0, 0, 0};
+  int64_t tcnt[ILH_TIMING_CLASSES] = {0, 0, 0, 0, 0};
   std::string err;
 };
 
@@ -106,6 +113,11 @@ int hip_fail(ilh_ctx* c, hipError_t e, const char* what);
     hipError_t _e = (call);                              \
     if (_e != hipSuccess) return ilh::hip_fail(ctx, _e, #call); \
   } while (0)
+
+// kernel timing: tstart returns a slot (or -1 when timing is off), tstop closes it
+int tstart(ilh_ctx* c, int cls);
+void tstop(ilh_ctx* c, int slot);
+int tflush(ilh_ctx* c);
 
 // kernel launchers (ilh_ops.hip)
 int launch_elem(ilh_ctx* c, int mode, int prec, const EArgs<double>* a64, const EArgs<float>* a32);

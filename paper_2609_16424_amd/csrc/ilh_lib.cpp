@@ -120,6 +120,34 @@ static bool invert(std::vector<double>& A, int n) {  // Gauss-Jordan with partia
   return true;
 }
 
+static constexpr int TPOOL = 4096;  // event pairs
+
+int tflush(ilh_ctx* c) {
+  if (c->tused == 0) return ILH_OK;
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < c->tused; ++i) {
+    float ms = 0.f;
+    ILH_HIP(c, hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]));
+    c->tms[c->tcls[i]] += ms;
+    c->tcnt[c->tcls[i]] += 1;
+  }
+  c->tused = 0;
+  return ILH_OK;
+}
+
+int tstart(ilh_ctx* c, int cls) {
+  if (!c->timing) return -1;
+  if (c->tused == TPOOL && tflush(c) != ILH_OK) return -1;
+  const int slot = c->tused++;
+  c->tcls[slot] = cls;
+  if (hipEventRecord(c->tev[2 * slot], c->stream) != hipSuccess) return -1;
+  return slot;
+}
+
+void tstop(ilh_ctx* c, int slot) {
+  if (slot >= 0) hipEventRecord(c->tev[2 * slot + 1], c->stream);
+}
+
 template <typename T>
 static int dalloc(ilh_ctx* c, T** p, size_t count) {
   *p = nullptr;
@@ -217,6 +245,7 @@ void ilh_destroy(ilh_ctx* c) {
                   c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  for (hipEvent_t e : c->tev) hipEventDestroy(e);
   if (c->red_host) hipHostFree(c->red_host);
   if (c->hhost) hipHostFree(c->hhost);
   delete c;
@@ -524,7 +553,10 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   int st = launch_fill(c, r + c->nh1, 0.0, c->nh1);
   if (st) return st;
   EArgs<double> a{u, u + c->nh1, u + 2 * c->nh1, k, nullptr, tau, r, nullptr};
-  return launch_elem(c, M_RESID, 64, &a, nullptr);
+  const int slot = tstart(c, 1);
+  st = launch_elem(c, M_RESID, 64, &a, nullptr);
+  tstop(c, slot);
+  return st;
 }
 
 int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
@@ -543,13 +575,19 @@ int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
     double* o = (double*)jdk;
     if ((st = launch_fill(c, o + c->nh1, 0.0, c->nh1))) return st;
     EArgs<double> a{c->w64, c->w64 + c->nh1, c->w64 + 2 * c->nh1, nullptr, (const double*)dk, c->lin_tau, o, nullptr};
-    return launch_elem(c, M_JVP, 64, &a, nullptr);
+    const int slot = tstart(c, 0);
+    st = launch_elem(c, M_JVP, 64, &a, nullptr);
+    tstop(c, slot);
+    return st;
   }
   if (prec == 32) {
     float* o = (float*)jdk;
     if ((st = launch_fillf(c, o + c->nh1, 0.0f, c->nh1))) return st;
     EArgs<float> a{c->w64, c->w32 + c->nh1, c->w32 + 2 * c->nh1, nullptr, (const float*)dk, c->lin_tau, o, nullptr};
-    return launch_elem(c, M_JVP, 32, nullptr, &a);
+    const int slot = tstart(c, 0);
+    st = launch_elem(c, M_JVP, 32, nullptr, &a);
+    tstop(c, slot);
+    return st;
   }
   return fail(c, ILH_EINVAL, "prec must be 32 or 64");
 }
@@ -626,6 +664,18 @@ int ilh_rate(ilh_ctx* c, const double* u, double* f) {
   return ILH_OK;
 }
 
+int ilh_plain_guess(ilh_ctx* c, const double* u, const double* k1, const double* k2, int nhist, double* out) {
+  if (!c || !u || !out) return ILH_EINVAL;
+  if (nhist <= 0) return ilh_rate(c, u, out);
+  if (!k1 || (nhist >= 2 && !k2)) return fail(c, ILH_EINVAL, "missing history vector");
+  if (nhist == 1) {
+    ILH_HIP(c, hipMemcpyAsync(out, k1, c->nblock * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return ILH_OK;
+  }
+  ILH_HIP(c, hipMemcpyAsync(out, k1, c->nblock * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return launch_axpby(c, out, -1.0, k2, 2.0, c->nblock);
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- Newton-Krylov
@@ -650,6 +700,15 @@ struct Solver {
   int jvp_calls = 0;
 
   int precond(const double* r, double* z) {
+    const int64_t nh1 = c->nh1;
+    int st;
+    const int slot = tstart(c, 4);
+    st = precond_body(r, z);
+    tstop(c, slot);
+    return st;
+  }
+
+  int precond_body(const double* r, double* z) {
     const int64_t nh1 = c->nh1;
     int st;
     ILH_HIP(c, hipMemcpyAsync(z, r, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -711,11 +770,13 @@ struct Solver {
         if ((st = precond(Vj, Zj))) return st;
         if ((st = apply(Zj, w))) return st;
         // classical Gram-Schmidt, twice
+        const int slot = tstart(c, 3);
         if ((st = multidot_dev(c, V, n, j + 1, w, n, hd))) return st;
         if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd, -1.0, n))) return st;
         if ((st = multidot_dev(c, V, n, j + 1, w, n, hd + 72))) return st;
         if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd + 72, -1.0, n))) return st;
         if ((st = dot_dev(c, w, w, n, hd + 144))) return st;
+        tstop(c, slot);
         ILH_HIP(c, hipMemcpyAsync(c->hhost, hd, 145 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         ILH_HIP(c, hipStreamSynchronize(c->stream));
         for (int i = 0; i <= j; ++i) H[i * m + j] = c->hhost[i] + c->hhost[72 + i];
@@ -857,6 +918,34 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
 }  // namespace ilh
 
 extern "C" {
+
+int ilh_timing_enable(ilh_ctx* c, int on) {
+  if (!c) return ILH_EINVAL;
+  int st = tflush(c);
+  if (st) return st;
+  if (c->tev.empty()) {
+    c->tev.resize(2 * TPOOL);
+    c->tcls.resize(TPOOL);
+    for (auto& e : c->tev) ILH_HIP(c, hipEventCreate(&e));
+  }
+  c->timing = on != 0;
+  for (int i = 0; i < ILH_TIMING_CLASSES; ++i) {
+    c->tms[i] = 0;
+    c->tcnt[i] = 0;
+  }
+  return ILH_OK;
+}
+
+int ilh_timing_read(ilh_ctx* c, double* ms, int64_t* cnt) {
+  if (!c || !ms || !cnt) return ILH_EINVAL;
+  int st = tflush(c);
+  if (st) return st;
+  for (int i = 0; i < ILH_TIMING_CLASSES; ++i) {
+    ms[i] = c->tms[i];
+    cnt[i] = c->tcnt[i];
+  }
+  return ILH_OK;
+}
 
 int ilh_stage_solve(ilh_ctx* c, const double* ubase, double tau, const double* k_guess, double* k_out,
                     const ilh_newton_opts* o, ilh_step_stats* st) {

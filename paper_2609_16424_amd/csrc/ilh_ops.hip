@@ -343,6 +343,7 @@ static void launch_mass_t(ilh_ctx* c, const double* x, double* y, int bc) {
 static int mass_apply(ilh_ctx* c, const double* x, double* y, int bc) {
   int st = launch_fill(c, y, 0.0, c->nh1);
   if (st) return st;
+  const int slot = tstart(c, 2);
   if (c->dim == 2) {
     switch (c->k) {
       case 1: launch_mass_t<2, 1>(c, x, y, bc); break;
@@ -357,6 +358,7 @@ static int mass_apply(ilh_ctx* c, const double* x, double* y, int bc) {
       case 3: launch_mass_t<3, 3>(c, x, y, bc); break;
     }
   }
+  tstop(c, slot);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
