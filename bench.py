@@ -39,20 +39,27 @@ def parse():
     ap.add_argument("--cfl-factor", type=float, default=4.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--generic-jvp", action="store_true", help="use the generic element kernel for J dk")
     ap.add_argument("--roofline-shape", type=int, default=0,
                     help="also time the JVP on an n x n Q3Q2 state of this size (0 = off)")
     return ap.parse_args()
 
 
-def jvp_bytes(H, prec):
-    """Algorithmic HBM bytes of one Jacobian-action launch: every vector read/written once."""
+def jvp_bytes(H, prec, generic=False):
+    """Algorithmic HBM bytes of one Jacobian-action launch: every vector read/written once.
+
+    State x (FP64), v and e (FP32 shadow, or FP64), direction dk and output J dk, and the
+    quadrature data: per-point m_q for the generic kernel, per-element rho0|J0|, |J0| and
+    gamma for the register-resident 2D kernel (affine initial mesh).
+    """
     if prec == 32:
-        state = H.nh1 * 8 + H.nh1 * 4 + H.nl2 * 4   # x FP64, v and e FP32 shadow
+        state = H.nh1 * 8 + H.nh1 * 4 + H.nl2 * 4
         vec = H.nblock * 4
     else:
         state = H.nblock * 8
         vec = H.nblock * 8
-    return state + 2 * vec + H.nqp * 8 + H.Ne * 8   # + direction, output, m_q, gamma
+    qdata = H.nqp * 8 + H.Ne * 8 if generic else 3 * H.Ne * 8
+    return state + 2 * vec + qdata
 
 
 def run_steps(H, u, dt, nsteps, opts, hist, ilh):
@@ -106,6 +113,8 @@ def main():
 
     n, k = args.n, args.order
     H = ilh.Hydro("tg2d", (n, n), k)
+    if args.generic_jvp:
+        H.lib.ilh_set_kernel_variant(H.ctx, 1)
     u0 = H.init_state()
     dt = args.cfl_factor * H.dt_estimate(u0, 0.5)
     opts32 = ilh.newton_options(tol=1e-10, jvp_prec=32)
@@ -132,7 +141,7 @@ def main():
     jvp_ms, jvp_n = tim["jvp"]
     jvp_avg_s = 1e-3 * jvp_ms / max(jvp_n, 1)
     value = H.nqp / jvp_avg_s
-    bytes32 = jvp_bytes(H, 32)
+    bytes32 = jvp_bytes(H, 32, args.generic_jvp)
     achieved = bytes32 / jvp_avg_s / 1e9
     u32 = u.clone()
     newton = [s["newton"] for s in stats]
@@ -165,6 +174,8 @@ def main():
     if args.roofline_shape:
         m = args.roofline_shape
         HR = ilh.Hydro("tg2d", (m, m), 3)
+        if args.generic_jvp:
+            HR.lib.ilh_set_kernel_variant(HR.ctx, 1)
         uR = HR.init_state()
         uR[:HR.nh1] += 0.05 * uR[HR.nh1:2 * HR.nh1]
         kR = torch.zeros_like(uR)
@@ -182,9 +193,9 @@ def main():
         HR.timing(False)
         avg = 1e-3 * tr["jvp"][0] / tr["jvp"][1]
         roof_extra = {"shape": "%dx%d Q3Q2 TG (displaced)" % (m, m), "n_qp": HR.nqp,
-                      "jvp_qps": HR.nqp / avg, "achieved_GBs": jvp_bytes(HR, 32) / avg / 1e9,
-                      "frac": jvp_bytes(HR, 32) / avg / 1e9 / HBM_PEAK_GBS,
-                      "bytes_per_launch": jvp_bytes(HR, 32)}
+                      "jvp_qps": HR.nqp / avg, "achieved_GBs": jvp_bytes(HR, 32, args.generic_jvp) / avg / 1e9,
+                      "frac": jvp_bytes(HR, 32, args.generic_jvp) / avg / 1e9 / HBM_PEAK_GBS,
+                      "bytes_per_launch": jvp_bytes(HR, 32, args.generic_jvp)}
         del HR
 
     cpu = None
@@ -210,7 +221,7 @@ def main():
                    "n_qp": H.nqp, "n_block": H.nblock},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_elem2d<4,6,JVP,float,7>", "bytes_per_launch": bytes32,
+                     "kernel": "k_elem2d<4,6,JVP,float,7>" if args.generic_jvp else "k_jvp2d<4,6,float,visc=0,src=1>", "bytes_per_launch": bytes32,
                      "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n},
         "cpu_baseline": cpu,
         "s_per_implicit_step_plain": ms_per_step / 1e3,

@@ -217,6 +217,10 @@ int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double*
  * ilh_timing_read synchronises the stream and returns, per class, the summed kernel time in
  * milliseconds and the number of timed launches (host arrays of ILH_TIMING_CLASSES). */
 #define ILH_TIMING_CLASSES 5
+/* Select the Jacobian-action kernel: generic = 0 (default) uses the register-resident 2D
+ * kernel where one exists (2D, k = 2, 3), generic = 1 always uses the generic
+ * LDS-staged element kernel.  Both compute the same operator (for cross-checking). */
+int ilh_set_kernel_variant(ilh_ctx* ctx, int generic);
 int ilh_timing_enable(ilh_ctx* ctx, int on);
 int ilh_timing_read(ilh_ctx* ctx, double* ms, int64_t* launches);
 

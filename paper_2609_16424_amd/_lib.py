@@ -70,6 +70,7 @@ SIGNATURES = {
     "ilh_implicit_step": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_timing_enable": (I, [P, I]),
+    "ilh_set_kernel_variant": (I, [P, I]),
     "ilh_timing_read": (I, [P, C.POINTER(D), C.POINTER(I64)]),
     "ilh_guess_features": (I, [P, P, D, D, D, P, I]),
     "ilh_guess_targets": (I, [P, P, D, D, P, I]),

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ilh.h"
+#include "ilh.h"
 
 namespace ilh {
 
@@ -27,6 +27,8 @@ struct KParams {
   const double* mq;    // [Ne][Q] quadrature mass rho0 detJ0 w_q
   const double* detJ0; // [Ne][Q]
   const double* gamma; // [Ne]
+  const double* rj0;   // [Ne] rho0 |J0| per element (affine initial mesh): m_q = rj0 w_q
+  const double* j0e;   // [Ne] |J0| per element
   double eps_e;
   int visc, dsc_mode, tg_source;
   double q1, q2, h0, hc_inv, dsc_w, psi_shift;
@@ -70,7 +72,9 @@ struct ilh_ctx {
   double* MEinv = nullptr;  // [Ne][Nl][Nl]
   double* Mdiag = nullptr;  // [nh1] diag(M_V), 1 on constrained rows
   double* qw = nullptr;     // [Q] reference weights (host copy below)
-  std::vector<double> h_qw, h_B, h_G, h_BL, h_gll, h_qpts;
+  std::vector<double> h_qw, h_B, h_G, h_BL, h_gll, h_qpts, h_w1;
+  double* rj0 = nullptr;    // [Ne]
+  double* j0e = nullptr;    // [Ne]
   // linearisation point
   double* w64 = nullptr;    // [nblock]
   float* w32 = nullptr;     // [nblock] (x part unused)
@@ -92,6 +96,7 @@ struct ilh_ctx {
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   double* hdev = nullptr;       // [4 * 72] device scalars of the Arnoldi step
   double* hhost = nullptr;      // pinned mirror of hdev
+  bool generic_jvp = false;     // force the generic element kernel for Jacobian actions
   // kernel timing (HIP events)
   bool timing = false;
   std::vector<hipEvent_t> tev;  // pairs
@@ -121,6 +126,8 @@ int tflush(ilh_ctx* c);
 
 // kernel launchers (ilh_ops.hip)
 int launch_elem(ilh_ctx* c, int mode, int prec, const EArgs<double>* a64, const EArgs<float>* a32);
+// register-resident 2D Jacobian action (k = 2, 3); ILH_EINVAL when not specialised
+int launch_jvp2d(ilh_ctx* c, int prec, const EArgs<double>* a64, const EArgs<float>* a32);
 int launch_fill(ilh_ctx* c, double* p, double v, int64_t n);
 int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n);
 int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int64_t n);  // y = a x + b y

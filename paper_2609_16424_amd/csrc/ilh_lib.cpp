@@ -241,7 +241,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
-  void* ptrs[] = {c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
+  void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
                   c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -360,6 +360,7 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
   c->h_G = G;
   c->h_BL = BL;
   c->h_gll = xn;
+  c->h_w1 = wg;
 
   // per-element material data
   std::vector<double> rho0(c->Ne, 1.0), gam(c->Ne, 5.0 / 3.0), e0(c->Ne, 0.0);
@@ -402,7 +403,8 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
     qw[q] = w;
   }
   c->h_qw = qw;
-  std::vector<double> mq(c->nqp), dj0(c->nqp, detJ0);
+  std::vector<double> mq(c->nqp), dj0(c->nqp, detJ0), rj0(c->Ne), j0e(c->Ne, detJ0);
+  for (int64_t e = 0; e < c->Ne; ++e) rj0[e] = rho0[e] * detJ0;
   for (int64_t e = 0; e < c->Ne; ++e)
     for (int q = 0; q < Q; ++q) mq[e * Q + q] = rho0[e] * detJ0 * qw[q];
   // L2 mass: M_E,e = rho0_e detJ0 (M1 x M1 [x M1]) with the 1D Bernstein mass M1
@@ -466,7 +468,8 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
       (st = dalloc(c, &c->detJ0, c->nqp)) || (st = dalloc(c, &c->gamma, c->Ne)) || (st = dalloc(c, &c->rho0, c->Ne)) ||
       (st = dalloc(c, &c->e0, c->Ne)) || (st = dalloc(c, &c->MEinv, me.size())) || (st = dalloc(c, &c->Mdiag, c->nh1)) ||
       (st = dalloc(c, &c->w64, c->nblock)) || (st = dalloc(c, &c->w32, c->nblock)) ||
-      (st = dalloc(c, &c->red, (size_t)c->red_blocks * 66 + 256)) || (st = dalloc(c, &c->pcgbuf, 4 * c->nh1 + 16))) {
+      (st = dalloc(c, &c->red, (size_t)c->red_blocks * 66 + 256)) || (st = dalloc(c, &c->pcgbuf, 4 * c->nh1 + 16)) ||
+      (st = dalloc(c, &c->rj0, c->Ne)) || (st = dalloc(c, &c->j0e, c->Ne))) {
     std::fprintf(stderr, "ilh_create: %s\n", c->err.c_str());
     ilh_destroy(c);
     return st;
@@ -484,7 +487,8 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
   if (up(c->tab, tab.data(), ntab * 8) || up(c->tabf, tabf.data(), ntab * 4) || up(c->mq, mq.data(), c->nqp * 8) ||
       up(c->detJ0, dj0.data(), c->nqp * 8) || up(c->gamma, gam.data(), c->Ne * 8) ||
       up(c->rho0, rho0.data(), c->Ne * 8) || up(c->e0, e0.data(), c->Ne * 8) ||
-      up(c->MEinv, me.data(), me.size() * 8) || up(c->Mdiag, Md.data(), c->nh1 * 8)) {
+      up(c->MEinv, me.data(), me.size() * 8) || up(c->Mdiag, Md.data(), c->nh1 * 8) ||
+      up(c->rj0, rj0.data(), c->Ne * 8) || up(c->j0e, j0e.data(), c->Ne * 8)) {
     std::fprintf(stderr, "ilh_create: upload failed\n");
     ilh_destroy(c);
     return ILH_EHIP;
@@ -503,6 +507,8 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
   P.mq = c->mq;
   P.detJ0 = c->detJ0;
   P.gamma = c->gamma;
+  P.rj0 = c->rj0;
+  P.j0e = c->j0e;
   P.eps_e = s->eps_e;
   P.visc = s->visc_on;
   P.dsc_mode = s->dscale_mode;
@@ -576,7 +582,8 @@ int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
     if ((st = launch_fill(c, o + c->nh1, 0.0, c->nh1))) return st;
     EArgs<double> a{c->w64, c->w64 + c->nh1, c->w64 + 2 * c->nh1, nullptr, (const double*)dk, c->lin_tau, o, nullptr};
     const int slot = tstart(c, 0);
-    st = launch_elem(c, M_JVP, 64, &a, nullptr);
+    st = c->generic_jvp ? ILH_EINVAL : launch_jvp2d(c, 64, &a, nullptr);
+    if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 64, &a, nullptr);
     tstop(c, slot);
     return st;
   }
@@ -585,7 +592,8 @@ int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
     if ((st = launch_fillf(c, o + c->nh1, 0.0f, c->nh1))) return st;
     EArgs<float> a{c->w64, c->w32 + c->nh1, c->w32 + 2 * c->nh1, nullptr, (const float*)dk, c->lin_tau, o, nullptr};
     const int slot = tstart(c, 0);
-    st = launch_elem(c, M_JVP, 32, nullptr, &a);
+    st = c->generic_jvp ? ILH_EINVAL : launch_jvp2d(c, 32, nullptr, &a);
+    if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 32, nullptr, &a);
     tstop(c, slot);
     return st;
   }
@@ -918,6 +926,12 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
 }  // namespace ilh
 
 extern "C" {
+
+int ilh_set_kernel_variant(ilh_ctx* c, int generic) {
+  if (!c) return ILH_EINVAL;
+  c->generic_jvp = generic != 0;
+  return ILH_OK;
+}
 
 int ilh_timing_enable(ilh_ctx* c, int on) {
   if (!c) return ILH_EINVAL;

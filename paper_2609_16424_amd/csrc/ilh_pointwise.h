@@ -18,8 +18,12 @@
 
 namespace ilh {
 
+// FP64: IEEE operations.  FP32 (Jacobian actions inside the Krylov solver, tolerance
+// 1e-5): the hardware reciprocal and square root (about 1 ulp), no correction steps.
 __device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float f_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double f_cbrt(double x) { return cbrt(x); }
 __device__ __forceinline__ float f_cbrt(float x) { return cbrtf(x); }
 __device__ __forceinline__ double f_tanh(double x) { return tanh(x); }
@@ -29,7 +33,7 @@ template <int D, typename T>
 __device__ __forceinline__ void inv_det(const T J[D][D], T Ji[D][D], T& det) {
   if constexpr (D == 2) {
     det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const T id = T(1) / det;
+    const T id = f_rcp(det);
     Ji[0][0] = J[1][1] * id;
     Ji[0][1] = -J[0][1] * id;
     Ji[1][0] = -J[1][0] * id;
@@ -39,7 +43,7 @@ __device__ __forceinline__ void inv_det(const T J[D][D], T Ji[D][D], T& det) {
     const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
     const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
     det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    const T id = T(1) / det;
+    const T id = f_rcp(det);
     Ji[0][0] = c00 * id;
     Ji[1][0] = c01 * id;
     Ji[2][0] = c02 * id;
@@ -56,7 +60,7 @@ __device__ __forceinline__ void inv_det(const T J[D][D], T Ji[D][D], T& det) {
 template <typename T>
 __device__ __forceinline__ void e_plus(T e, T eps, T& ep, T& r) {
   r = f_sqrt(e * e + eps * eps);
-  ep = (e >= T(0)) ? T(0.5) * (e + r) : eps * eps / (T(2) * (r - e));
+  ep = (e >= T(0)) ? T(0.5) * (e + r) : eps * eps * f_rcp(T(2) * (r - e));
 }
 
 template <int D, typename T>
@@ -120,8 +124,9 @@ __device__ __forceinline__ void qp_force(const KParams& P, T gam, T mq, T dJ0, c
   s = ss;
 }
 
-// Tangent form: dS and ds along (dJ, dGv, de).
-template <int D, typename T>
+// Tangent form: dS and ds along (dJ, dGv, de).  VISC = 0/1 fixes the viscosity switch at
+// compile time, VISC = -1 reads it from P.
+template <int D, typename T, int VISC = -1>
 __device__ __forceinline__ void qp_tangent(const KParams& P, T gam, T mq, T dJ0, const T J[D][D],
                                            const T Gv[D][D], T e, const T dJ[D][D],
                                            const T dGv[D][D], T de, T dS[D][D], T& ds) {
@@ -163,7 +168,7 @@ __device__ __forceinline__ void qp_tangent(const KParams& P, T gam, T mq, T dJ0,
     }
   T ep, r;
   e_plus<T>(e, T(P.eps_e), ep, r);
-  const T dep = ep / r * de;
+  const T dep = ep * f_rcp(r) * de;
   const T g1 = gam - T(1);
   const T Pq = g1 * mq * ep, dPq = g1 * mq * dep;
   T Sig[D][D], dSig[D][D];
@@ -174,7 +179,7 @@ __device__ __forceinline__ void qp_tangent(const KParams& P, T gam, T mq, T dJ0,
       Sig[c][b] = (c == b) ? -Pq : T(0);
       dSig[c][b] = (c == b) ? -dPq : T(0);
     }
-  if (P.visc) {
+  if ((VISC < 0) ? (P.visc != 0) : (VISC == 1)) {
     T trd = 0, div = 0, ddiv = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -182,11 +187,11 @@ __device__ __forceinline__ void qp_tangent(const KParams& P, T gam, T mq, T dJ0,
       div += gv[a][a];
       ddiv += dgv[a][a];
     }
-    const T h = T(P.h0) * h_scale<D, T>(det / dJ0);
-    const T dh = h * trd / T(D);
+    const T h = T(P.h0) * h_scale<D, T>(det * f_rcp(dJ0));
+    const T dh = h * trd * T(1.0 / D);
     const T dv = h * div, ddv = dh * div + h * ddiv;
     const T cs = f_sqrt(gam * g1 * ep);
-    const T dcs = cs * dep / (T(2) * ep);
+    const T dcs = cs * dep * f_rcp(T(2) * ep);
     T dsc, ddsc;
     if (P.dsc_mode) {
       dsc = T(2) * h * cs * T(P.hc_inv);
@@ -196,9 +201,10 @@ __device__ __forceinline__ void qp_tangent(const KParams& P, T gam, T mq, T dJ0,
       ddsc = T(0);
     }
     const T aabs = f_sqrt(dv * dv + dsc * dsc);
-    const T daabs = (dv * ddv + dsc * ddsc) / aabs;
-    const T t = -dv / (T(2) * dsc) - T(P.psi_shift);
-    const T dt = -(ddv * dsc - dv * ddsc) / (T(2) * dsc * dsc);
+    const T daabs = (dv * ddv + dsc * ddsc) * f_rcp(aabs);
+    const T i2d = f_rcp(T(2) * dsc);
+    const T t = -dv * i2d - T(P.psi_shift);
+    const T dt = -(ddv * dsc - dv * ddsc) * i2d * f_rcp(dsc);
     const T th = f_tanh(t);
     const T psi = T(0.5) + T(0.5) * th;
     const T dpsi = T(0.5) * (T(1) - th * th) * dt;
@@ -238,12 +244,26 @@ __device__ __forceinline__ T tg_source(T x, T y, T gam) {
   return T(pi / 4.0 * (cos(3 * pi * X) * cos(pi * Y) - cos(pi * X) * cos(3 * pi * Y)) /
            (double(gam) - 1.0));
 }
+__device__ __forceinline__ void f_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
+// FP32: hardware sine/cosine (absolute error ~1e-6 for the bounded arguments used here)
+__device__ __forceinline__ void f_sincospi(float x, float* s, float* c) {
+  *s = __sinf(3.14159265358979f * x);
+  *c = __cosf(3.14159265358979f * x);
+}
+
+// Gradient of the source in the working precision T (used by the tangent kernels):
+// sin/cos of pi x and pi y, the triple angles from sin 3a = s (3 - 4 s^2), cos 3a = c (4 c^2 - 3).
 template <typename T>
 __device__ __forceinline__ void tg_source_grad(T x, T y, T gam, T& gx, T& gy) {
-  const double pi = 3.14159265358979323846;
-  const double X = double(x), Y = double(y), c = pi / 4.0 / (double(gam) - 1.0);
-  gx = T(c * (-3 * pi * sin(3 * pi * X) * cos(pi * Y) + pi * sin(pi * X) * cos(3 * pi * Y)));
-  gy = T(c * (-pi * cos(3 * pi * X) * sin(pi * Y) + 3 * pi * cos(pi * X) * sin(3 * pi * Y)));
+  const T pi = T(3.14159265358979323846);
+  const T c = pi * pi * T(0.25) * f_rcp(gam - T(1));
+  T sx, cx, sy, cy;
+  f_sincospi(x, &sx, &cx);
+  f_sincospi(y, &sy, &cy);
+  const T s3x = sx * (T(3) - T(4) * sx * sx), c3x = cx * (T(4) * cx * cx - T(3));
+  const T s3y = sy * (T(3) - T(4) * sy * sy), c3y = cy * (T(4) * cy * cy - T(3));
+  gx = c * (-T(3) * s3x * cy + sx * c3y);
+  gy = c * (-c3x * sy + T(3) * cx * s3y);
 }
 
 }  // namespace ilh

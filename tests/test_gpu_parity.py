@@ -134,3 +134,21 @@ def test_zero_direction_gives_zero():
     k = torch.zeros_like(u)
     z = G.jvp(k, u, 0.01, torch.zeros_like(u), 64)
     assert float(z.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-13), (32, 2e-6)])
+@pytest.mark.parametrize("prob,n,k,visc", [("tg2d", (23, 7), 3, None), ("tg2d", (17, 4), 2, None),
+                                           ("triple", (21, 9), 3, "const"), ("triple", (33, 5), 2, "formula")])
+def test_specialised_jvp_matches_generic(prob, n, k, visc, prec, tol):
+    """The register-resident 2D Jacobian-action kernel against the generic element kernel."""
+    O, G = make_pair(prob, n, k, visc)
+    u = random_state(O, 21)
+    kk = 0.1 * random_dir(O, 22)
+    dk = random_dir(O, 23)
+    dt = torch.float64 if prec == 64 else torch.float32
+    G.linearize(to_dev(kk), to_dev(u), 0.003)
+    a = to_np(G.jvp_lin(to_dev(dk, dt), prec))
+    G.lib.ilh_set_kernel_variant(G.ctx, 1)
+    b = to_np(G.jvp_lin(to_dev(dk, dt), prec))
+    G.lib.ilh_set_kernel_variant(G.ctx, 0)
+    assert rel(a, b) <= tol
