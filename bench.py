@@ -65,7 +65,7 @@ def jvp_bytes(H, prec, generic=False):
 def run_steps(H, u, dt, nsteps, opts, hist, ilh):
     stats = []
     for _ in range(nsteps):
-        g = H.plain_guess(u, hist)
+        g = H.plain_guess(u, hist, 0.5 * dt)
         k, st = H.implicit_step(u, dt, guess=g, opts=opts)
         hist.append(k)
         if len(hist) > 2:

@@ -165,9 +165,11 @@ int ilh_rate(ilh_ctx* ctx, const double* u, double* f);
 
 /* Plain initial iterate of a stage solve: nhist = 0 -> out = f(u) (ilh_rate);
  * nhist = 1 -> out = k1; nhist >= 2 -> out = 2 k1 - k2 (linear extrapolation of the two
- * previous converged stage rates).  k1, k2 [block] may be NULL when unused. */
+ * previous converged stage rates).  If tau > 0 the position block is then made consistent
+ * with the position equation, out_x = u_v + tau out_v (R_x = 0 exactly).
+ * k1, k2 [block] may be NULL when unused. */
 int ilh_plain_guess(ilh_ctx* ctx, const double* u, const double* k1, const double* k2,
-                    int nhist, double* out);
+                    int nhist, double tau, double* out);
 
 /* Newton-Krylov options (host).  Converged when ||R(k)|| <= tol ||R(0; tau, u)||. */
 typedef struct {
@@ -177,10 +179,13 @@ typedef struct {
   double gmres_rtol;   /* relative tolerance of each linear solve */
   int gmres_maxit;     /* FGMRES iteration cap per Newton iteration */
   int jvp_prec;        /* 32 or 64: precision of the Jacobian actions inside FGMRES */
-  int max_halvings;    /* line-search halvings before ILH_ETANGLED */
+  int max_halvings;    /* line-search halvings (det J > 0, residual decrease) */
   int pcg_iters;       /* Jacobi-PCG iterations of the velocity-mass preconditioner block
                           (0 = diagonal only) */
   int prec_coupled;    /* 1: after the mass blocks, set z_x = r_x + tau z_v */
+  int guess_fallback;  /* 1: start from k = 0 when ||R(k_guess)|| > ||R(0)|| */
+  int ls_residual;     /* 1: the line search also requires ||R|| to decrease (Armijo, 1e-4);
+                          0: det J > 0 only */
 } ilh_newton_opts;
 
 typedef struct {
@@ -189,6 +194,7 @@ typedef struct {
   int gmres_iters;       /* total over the Newton iterations */
   int jvp_calls;
   int halvings;          /* total line-search halvings */
+  int guess_rejected;    /* 1 if the initial iterate was replaced by k = 0 */
   double res0;           /* ||R(0; tau, u)|| */
   double res_init;       /* ||R(k_guess)|| */
   double res_final;      /* ||R(k)|| at exit */
@@ -224,46 +230,53 @@ int ilh_set_kernel_variant(ilh_ctx* ctx, int generic);
 int ilh_timing_enable(ilh_ctx* ctx, int on);
 int ilh_timing_read(ilh_ctx* ctx, double* ms, int64_t* launches);
 
-/* ---- learned Newton initial guess (per-element MLP) --------------------------------- */
-/* Feature / target layout per element (2D only): velocity dofs [2][(k+1)^2], energy
- * dofs [k^2], corner coordinates relative to the element centre [4][2]; targets are the
- * element-local [k_v (2 (k+1)^2) | k_e (k^2)].  See ilh_guess_* below. */
-
-/* feat [Ne][n_in] (float): element features of the state u, normalised by the scalars
- * vscale (velocity), escale (energy), xscale (length). n_in must equal 2(k+1)^2 + k^2 + 8. */
-int ilh_guess_features(ilh_ctx* ctx, const double* u, double vscale, double escale,
-                       double xscale, float* feat, int n_in);
-
-/* Element-local stage rates of k [block] -> targ [Ne][n_out] (float), n_out = 2(k+1)^2 + k^2,
- * divided by kvscale / kescale. */
-int ilh_guess_targets(ilh_ctx* ctx, const double* k, double kvscale, double kescale,
-                      float* targ, int n_out);
-
-/* k [block] = base + assembled correction: the element predictions pred [Ne][n_out]
- * (times kvscale / kescale) are averaged over the elements sharing each H1 node and added
- * to base's v and e blocks; the x block is set to u_v + tau k_v.  Constrained v rows are 0. */
-int ilh_guess_assemble(ilh_ctx* ctx, const float* pred, int n_out, double kvscale,
-                       double kescale, const double* base, const double* u, double tau,
+/* ---- learned Newton initial guess (per-element MLP) ------------------------------------ */
+/* Not part of the paper: a per-element MLP predicts the correction of the plain initial
+ * iterate of each implicit stage (2D only).  Element-local layouts, element e with local H1
+ * node (a, b) (index a + (k+1) b) and L2 dof j:
+ *   features [Ne][ld]  float: v_c(a,b)/vscale (c = 0, 1) | e_j/escale |
+ *                      (corner - element centre)/xscale for corners (0,0),(k,0),(0,k),(k,k) |
+ *                      if base != NULL: base_v/kvscale | base_e/kescale;  zero padded to ld.
+ *   targets  [Ne][ld]  float: (k_v - base_v)/kvscale | (k_e - base_e)/kescale (base NULL = 0).
+ * ilh_guess_assemble turns predictions of that layout into a block vector: the velocity
+ * part is averaged over the elements sharing each node and added to base (constrained rows
+ * 0), the energy part is added element-locally, and k_x = u_v + tau k_v. */
+int ilh_guess_features(ilh_ctx* ctx, const double* u, const double* base, double vscale,
+                       double escale, double xscale, double kvscale, double kescale,
+                       const float* mu, const float* sd, float* feat, int ld);
+int ilh_guess_targets(ilh_ctx* ctx, const double* k, const double* base, double kvscale,
+                      double kescale, const float* oscale, float* targ, int ld);
+int ilh_guess_assemble(ilh_ctx* ctx, const float* pred, int ld, double kvscale, double kescale,
+                       const float* oscale, const double* base, const double* u, double tau,
                        double* k);
+/* Optional per-column arrays (device, float, nullable): features are standardised as
+ * (f - mu[i]) / sd[i] after the scalar scaling; targets are divided by oscale[i] and
+ * predictions multiplied by oscale[i] before assembly. */
 
-/* Fused MLP on MFMA (BF16 inputs and weights, FP32 accumulation), GELU (erf form) between
- * layers: widths w[0] -> w[1] -> ... -> w[nl].  Parameters: W_l [w[l+1]][w[l]] (bf16 as
- * uint16), b_l [w[l+1]] (float), concatenated over layers in that order.
- * x [batch][w[0]] float, y [batch][w[nl]] float.  acts (nullable) receives the
- * pre-activation outputs of every layer [batch][sum w[1..nl]] float for backward. */
+/* MLP on MFMA (BF16 operands, FP32 accumulation): widths w[0..nl] (each 1..128), hidden
+ * layers GELU (erf form), last layer linear.  Every width is padded to P(w) = 32 ceil(w/32);
+ * padding entries are zero.  Concatenated over layers l = 0..nl-1:
+ *   W  bf16 (uint16) [P(w_{l+1})][P(w_l)],  WT its transpose,  b float [P(w_{l+1})],
+ *   zs / acts float [batch][P(w_{l+1})]: pre-activations / outputs of each layer.
+ * x float [batch][P(w_0)].  The network output is the last acts block. */
 int ilh_mlp_forward(ilh_ctx* ctx, int nl, const int* widths /*host*/, const uint16_t* W,
-                    const float* b, const float* x, int batch, float* y, float* acts);
+                    const float* b, const float* x, int batch, float* zs, float* acts);
 
-/* Backward of mean-squared error 0.5/batch sum (y - t)^2 through the MLP: writes
- * dW (float, same layout as W) and db (float).  acts from ilh_mlp_forward. */
-int ilh_mlp_backward(ilh_ctx* ctx, int nl, const int* widths, const uint16_t* W,
-                     const float* b, const float* x, const float* acts, const float* t,
-                     int batch, float* dW, float* db, double* loss /*host, nullable*/);
+/* Gradients of the loss 0.5/batch sum_{rows, cols < w_nl} (y - t)^2 (t [batch][P(w_nl)]):
+ * dW (float, layout of W) and db (float), both overwritten.  work: float
+ * [2 * batch * 128] scratch.  loss (host, nullable) receives the loss (synchronises). */
+int ilh_mlp_backward(ilh_ctx* ctx, int nl, const int* widths /*host*/, const uint16_t* WT,
+                     const float* x, const float* zs, const float* acts, const float* target,
+                     int batch, float* dW, float* db, float* work, double* loss);
 
-/* Adam step on FP32 master weights (mW, mb) with moments, writing the BF16 copy W. */
-int ilh_mlp_adam(ilh_ctx* ctx, int64_t n_w, int64_t n_b, float* mW, float* mb,
-                 const float* dW, const float* db, float* m1, float* m2, int step,
-                 double lr, double beta1, double beta2, double eps, uint16_t* W, float* b_out);
+/* Adam step on n FP32 master parameters p with gradient g and moments m1, m2 (step >= 1):
+ * p -= lr mhat / (sqrt(vhat) + eps) with bias-corrected moments mhat, vhat. */
+int ilh_mlp_adam(ilh_ctx* ctx, int64_t n, float* p, const float* g, float* m1, float* m2,
+                 int step, double lr, double beta1, double beta2, double eps);
+
+/* Round the FP32 master weights (layout of W) to BF16 into W and its transpose WT. */
+int ilh_mlp_pack(ilh_ctx* ctx, int nl, const int* widths /*host*/, const float* Wmaster,
+                 uint16_t* W, uint16_t* WT);
 
 #ifdef __cplusplus
 }

@@ -214,14 +214,15 @@ class Hydro:
         self._check(self.lib.ilh_rate(self.ctx, self._vec(u, self.nblock, name="u"), _ptr(f)))
         return f
 
-    def plain_guess(self, u, history):
-        """Explicit rate, last rate, or linear extrapolation of the last two (most recent last)."""
+    def plain_guess(self, u, history, tau=0.0):
+        """Explicit rate, last rate, or linear extrapolation of the last two (most recent last);
+        with tau > 0 the position block is set to u_v + tau k_v."""
         out = self.new()
         k1 = self._vec(history[-1], self.nblock, name="k1") if len(history) >= 1 else None
         k2 = self._vec(history[-2], self.nblock, name="k2") if len(history) >= 2 else None
         self._stream()
         self._check(self.lib.ilh_plain_guess(self.ctx, self._vec(u, self.nblock, name="u"), k1, k2,
-                                             min(len(history), 2), _ptr(out)))
+                                             min(len(history), 2), float(tau), _ptr(out)))
         return out
 
     def timing(self, on=True):
@@ -262,7 +263,7 @@ class Hydro:
 def _stats(st, code):
     n = min(st.newton_iters, 31)
     return dict(status=code, newton=st.newton_iters, gmres=st.gmres_iters, jvp_calls=st.jvp_calls,
-                halvings=st.halvings, res0=st.res0, res_init=st.res_init, res_final=st.res_final,
+                halvings=st.halvings, guess_rejected=st.guess_rejected, res0=st.res0, res_init=st.res_init, res_final=st.res_final,
                 hist=[st.res_hist[i] for i in range(n + 1)])
 
 
@@ -307,3 +308,10 @@ class ResidualFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *grads):
         raise NotImplementedError("the transpose (VJP) action is not part of this library")
+
+
+def __getattr__(name):
+    if name == "learned":
+        import importlib
+        return importlib.import_module(".learned", __name__)
+    raise AttributeError(name)

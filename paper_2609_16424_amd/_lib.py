@@ -26,13 +26,14 @@ class NewtonOpts(C.Structure):
         ("tol", C.c_double), ("max_newton", C.c_int), ("restart", C.c_int),
         ("gmres_rtol", C.c_double), ("gmres_maxit", C.c_int), ("jvp_prec", C.c_int),
         ("max_halvings", C.c_int), ("pcg_iters", C.c_int), ("prec_coupled", C.c_int),
+        ("guess_fallback", C.c_int), ("ls_residual", C.c_int),
     ]
 
 
 class StepStats(C.Structure):
     _fields_ = [
         ("status", C.c_int), ("newton_iters", C.c_int), ("gmres_iters", C.c_int),
-        ("jvp_calls", C.c_int), ("halvings", C.c_int), ("res0", C.c_double),
+        ("jvp_calls", C.c_int), ("halvings", C.c_int), ("guess_rejected", C.c_int), ("res0", C.c_double),
         ("res_init", C.c_double), ("res_final", C.c_double), ("res_hist", C.c_double * 32),
     ]
 
@@ -65,19 +66,20 @@ SIGNATURES = {
     "ilh_dt_estimate": (I, [P, P, D, C.POINTER(D)]),
     "ilh_l1_velocity_error": (I, [P, P, C.POINTER(D)]),
     "ilh_rate": (I, [P, P, P]),
-    "ilh_plain_guess": (I, [P, P, P, P, I, P]),
+    "ilh_plain_guess": (I, [P, P, P, P, I, D, P]),
     "ilh_newton_defaults": (None, [C.POINTER(NewtonOpts)]),
     "ilh_implicit_step": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_timing_enable": (I, [P, I]),
     "ilh_set_kernel_variant": (I, [P, I]),
     "ilh_timing_read": (I, [P, C.POINTER(D), C.POINTER(I64)]),
-    "ilh_guess_features": (I, [P, P, D, D, D, P, I]),
-    "ilh_guess_targets": (I, [P, P, D, D, P, I]),
-    "ilh_guess_assemble": (I, [P, P, I, D, D, P, P, D, P]),
+    "ilh_guess_features": (I, [P, P, P, D, D, D, D, D, P, P, P, I]),
+    "ilh_guess_targets": (I, [P, P, P, D, D, P, P, I]),
+    "ilh_guess_assemble": (I, [P, P, I, D, D, P, P, P, D, P]),
     "ilh_mlp_forward": (I, [P, I, C.POINTER(I), P, P, P, I, P, P]),
-    "ilh_mlp_backward": (I, [P, I, C.POINTER(I), P, P, P, P, P, I, P, P, C.POINTER(D)]),
-    "ilh_mlp_adam": (I, [P, I64, I64, P, P, P, P, P, P, I, D, D, D, D, P, P]),
+    "ilh_mlp_backward": (I, [P, I, C.POINTER(I), P, P, P, P, P, I, P, P, P, C.POINTER(D)]),
+    "ilh_mlp_adam": (I, [P, I64, P, P, P, P, I, D, D, D, D]),
+    "ilh_mlp_pack": (I, [P, I, C.POINTER(I), P, P, P]),
 }
 
 _lib = None

@@ -215,11 +215,13 @@ void ilh_newton_defaults(ilh_newton_opts* o) {
   o->max_newton = 30;
   o->restart = 30;
   o->gmres_rtol = 1e-6;
-  o->gmres_maxit = 60;
+  o->gmres_maxit = 150;
   o->jvp_prec = 32;
   o->max_halvings = 10;
   o->pcg_iters = 0;
   o->prec_coupled = 1;
+  o->guess_fallback = 1;
+  o->ls_residual = 1;
 }
 
 const char* ilh_last_error(const ilh_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -672,16 +674,23 @@ int ilh_rate(ilh_ctx* c, const double* u, double* f) {
   return ILH_OK;
 }
 
-int ilh_plain_guess(ilh_ctx* c, const double* u, const double* k1, const double* k2, int nhist, double* out) {
+int ilh_plain_guess(ilh_ctx* c, const double* u, const double* k1, const double* k2, int nhist, double tau,
+                    double* out) {
   if (!c || !u || !out) return ILH_EINVAL;
-  if (nhist <= 0) return ilh_rate(c, u, out);
-  if (!k1 || (nhist >= 2 && !k2)) return fail(c, ILH_EINVAL, "missing history vector");
-  if (nhist == 1) {
+  int st;
+  if (nhist <= 0) {
+    if ((st = ilh_rate(c, u, out))) return st;
+  } else {
+    if (!k1 || (nhist >= 2 && !k2)) return fail(c, ILH_EINVAL, "missing history vector");
     ILH_HIP(c, hipMemcpyAsync(out, k1, c->nblock * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    return ILH_OK;
+    if (nhist >= 2 && (st = launch_axpby(c, out, -1.0, k2, 2.0, c->nblock))) return st;
   }
-  ILH_HIP(c, hipMemcpyAsync(out, k1, c->nblock * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  return launch_axpby(c, out, -1.0, k2, 2.0, c->nblock);
+  if (tau > 0.0) {
+    // out_x = u_v + tau out_v
+    ILH_HIP(c, hipMemcpyAsync(out, u + c->nh1, c->nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if ((st = launch_axpby(c, out, tau, out + c->nh1, 1.0, c->nh1))) return st;
+  }
+  return ILH_OK;
 }
 
 }  // extern "C"
@@ -846,7 +855,7 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   std::memset(&stats, 0, sizeof(stats));
   const int m = std::max(1, std::min(o->restart, 64));
   if ((st = ensure_solver_ws(c, m))) return st;
-  if (!c->nwt && (st = dalloc(c, &c->nwt, 6 * (size_t)n))) return st;
+  if (!c->nwt && (st = dalloc(c, &c->nwt, 8 * (size_t)n))) return st;
   if (!c->hdev && (st = dalloc(c, &c->hdev, 4 * 72 + 64))) return st;
   if (!c->hhost && hipHostMalloc((void**)&c->hhost, (4 * 72 + 64) * sizeof(double)) != hipSuccess)
     return fail(c, ILH_ENOMEM, "pinned host buffer");
@@ -855,24 +864,35 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   double* dk = c->nwt + 2 * n;
   double* trial = c->nwt + 4 * n;
   double* zero = c->nwt + 5 * n;
+  double* kt = c->nwt + 6 * n;
+  double* rt = c->nwt + 7 * n;
   Solver S{c, o, tau};
   if ((st = launch_fill(c, zero, 0.0, n))) return st;
   if ((st = ilh_residual(c, zero, u, tau, r))) return st;
   const double r0 = nrm2(c, r, n, &st);
   if (st) return st;
   stats.res0 = r0;
+  double nr = r0;
   if (k_guess) {
     ILH_HIP(c, hipMemcpyAsync(k, k_guess, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if ((st = ilh_residual(c, k, u, tau, r))) return st;
+    nr = nrm2(c, r, n, &st);
+    if (st) return st;
+    stats.res_init = nr;
+    if (o->guess_fallback && !(nr <= r0)) {
+      // the initial iterate is worse than k = 0: start from zero instead
+      stats.guess_rejected = 1;
+      if ((st = launch_fill(c, k, 0.0, n))) return st;
+      if ((st = ilh_residual(c, k, u, tau, r))) return st;
+      nr = r0;
+    }
   } else {
     if ((st = launch_fill(c, k, 0.0, n))) return st;
+    stats.res_init = r0;
   }
   int status = ILH_OK;
   int it = 0;
   for (;; ++it) {
-    if ((st = ilh_residual(c, k, u, tau, r))) return st;
-    const double nr = nrm2(c, r, n, &st);
-    if (st) return st;
-    if (it == 0) stats.res_init = nr;
     if (it < 32) stats.res_hist[it] = r0 > 0 ? nr / r0 : nr;
     stats.res_final = nr;
     if (!std::isfinite(nr)) {
@@ -887,37 +907,60 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
       break;
     }
     if ((st = ilh_linearize(c, k, u, tau))) return st;
-    if ((st = launch_axpby(c, r, 0.0, r, -1.0, n))) return st;  // r <- -r
+    if ((st = launch_axpby(c, r, 0.0, r, -1.0, n))) return st;  // r <- -r (right-hand side)
     int gits = 0;
     if ((st = S.fgmres(r, dk, &gits))) return st;
     stats.gmres_iters += gits;
-    // backtracking line search on min det J of the stage positions
-    double alpha = 1.0;
-    bool ok = false;
+    // backtracking: det J > 0 at every quadrature point of the stage positions, and (when
+    // enabled) sufficient decrease ||R(k + a dk)|| <= (1 - 1e-4 a) ||R(k)||
+    double alpha = 1.0, best = INFINITY, best_alpha = 0.0;
+    bool ok = false, any_valid = false;
     for (int h = 0; h <= o->max_halvings; ++h) {
-      // trial_x = u_x + tau (k_x + alpha dk_x)
-      if ((st = launch_waxpy(c, trial, k, alpha, dk, c->nh1))) return st;
-      if ((st = launch_axpby(c, trial, 1.0, u, tau, c->nh1))) return st;
+      if ((st = launch_waxpy(c, kt, k, alpha, dk, n))) return st;
+      if ((st = launch_waxpy(c, trial, u, tau, kt, c->nh1))) return st;
       double md;
       if ((st = min_detj_host(c, trial, &md))) return st;
       if (md > 0.0) {
-        ok = true;
-        break;
+        any_valid = true;
+        if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
+        const double nrt = nrm2(c, rt, n, &st);
+        if (st) return st;
+        if (!o->ls_residual || nrt <= (1.0 - 1e-4 * alpha) * nr) {
+          ok = true;
+          nr = nrt;
+          break;
+        }
+        if (nrt < best) {
+          best = nrt;
+          best_alpha = alpha;
+        }
       }
       alpha *= 0.5;
       ++stats.halvings;
+    }
+    if (!ok && any_valid && std::isfinite(best)) {
+      // no sufficient decrease within the halvings: take the best valid trial
+      alpha = best_alpha;
+      if ((st = launch_waxpy(c, kt, k, alpha, dk, n))) return st;
+      if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
+      nr = nrm2(c, rt, n, &st);
+      if (st) return st;
+      ok = true;
     }
     if (!ok) {
       status = ILH_ETANGLED;
       c->err = "line search could not keep det J > 0";
       break;
     }
-    if ((st = launch_axpby(c, k, alpha, dk, 1.0, n))) return st;
+    std::swap(k, kt);
+    std::swap(r, rt);
   }
   stats.newton_iters = it;
   stats.jvp_calls = S.jvp_calls;
   stats.status = status;
   if (k_out) ILH_HIP(c, hipMemcpyAsync(k_out, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  // leave the final iterate at the head of the Newton workspace for ilh_implicit_step
+  if (k != c->nwt) ILH_HIP(c, hipMemcpyAsync(c->nwt, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   if (st_out) *st_out = stats;
   return status;

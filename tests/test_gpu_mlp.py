@@ -1,0 +1,193 @@
+"""GPU parity of the learned-guess kernels: BF16 MFMA MLP forward/backward, Adam, BF16
+packing, and the element feature / target / assembly kernels."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2609_16424_amd as ilh
+from gpu_common import make_pair, rel, to_dev, to_np
+from oracle.mlp import MLP, adam_step, bf16_round, pad32
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(widths, seed):
+    rng = np.random.default_rng(seed)
+    W, b = [], []
+    for l in range(len(widths) - 1):
+        w = np.zeros((pad32(widths[l + 1]), pad32(widths[l])), dtype=np.float32)
+        w[:widths[l + 1], :widths[l]] = rng.standard_normal((widths[l + 1], widths[l])) / np.sqrt(widths[l])
+        bb = np.zeros(pad32(widths[l + 1]), dtype=np.float32)
+        bb[:widths[l + 1]] = 0.1 * rng.standard_normal(widths[l + 1])
+        W.append(w)
+        b.append(bb)
+    return W, b
+
+
+def _gpu_mlp(widths, W, b):
+    G = ilh.Hydro("tg2d", (2, 2), 2)
+    m = ilh.learned.GuessMLP(G, widths)
+    flat = np.concatenate([w.ravel() for w in W] + [x.ravel() for x in b]).astype(np.float32)
+    m.master.copy_(torch.from_numpy(flat).cuda())
+    m.pack()
+    return G, m
+
+
+def _input(B, w0, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((B, pad32(w0)), dtype=np.float32)
+    x[:, :w0] = rng.standard_normal((B, w0))
+    return x
+
+
+def test_pack_is_bf16_rounding_and_transpose():
+    widths = [49, 128, 41]
+    W, b = _params(widths, 0)
+    G, m = _gpu_mlp(widths, W, b)
+    Wg = m.W.cpu().numpy().view(np.uint16)
+    WTg = m.WT.cpu().numpy().view(np.uint16)
+    off = 0
+    for w in W:
+        bits = bf16_round(w).view(np.uint32) >> 16
+        assert np.array_equal(Wg[off:off + w.size].reshape(w.shape), bits.astype(np.uint16))
+        assert np.array_equal(WTg[off:off + w.size].reshape(w.shape[1], w.shape[0]), bits.T.astype(np.uint16))
+        off += w.size
+
+
+@pytest.mark.parametrize("B", [64, 77, 1000])
+def test_single_layer_forward(B):
+    widths = [49, 128]
+    W, b = _params(widths, 1)
+    G, m = _gpu_mlp(widths, W, b)
+    x = _input(B, 49, 2)
+    zs, acts, out = m.forward(to_dev(x, torch.float32))
+    O = MLP(widths, W, b)
+    ozs, oacts = O.forward(x)
+    assert rel(to_np(out), oacts[-1]) <= 1e-6
+
+
+@pytest.mark.parametrize("B", [256, 300])
+def test_mlp_forward_and_gradients(B):
+    widths = [81, 128, 128, 128, 41]
+    W, b = _params(widths, 3)
+    G, m = _gpu_mlp(widths, W, b)
+    x = _input(B, 81, 4)
+    t = np.zeros((B, pad32(41)), dtype=np.float32)
+    t[:, :41] = np.random.default_rng(5).standard_normal((B, 41))
+    xd, td = to_dev(x, torch.float32), to_dev(t, torch.float32)
+    zs, acts, out = m.forward(xd)
+    O = MLP(widths, W, b)
+    ozs, oacts = O.forward(x)
+    # BF16 rounding of activations computed in FP32 (GPU) vs FP64 (oracle) can differ by one
+    # BF16 ulp at rounding ties; the relative effect on the output is ~1e-4 at most
+    assert rel(to_np(out), oacts[-1]) <= 2e-3
+    work = torch.empty(2 * B * 128, dtype=torch.float32, device="cuda")
+    loss = C.c_double()
+    G._check(G.lib.ilh_mlp_backward(G.ctx, m.nl, m.cw, C.c_void_p(m.WT.data_ptr()), C.c_void_p(xd.data_ptr()),
+                                    C.c_void_p(zs.data_ptr()), C.c_void_p(acts.data_ptr()), C.c_void_p(td.data_ptr()),
+                                    B, C.c_void_p(m.grad.data_ptr()), C.c_void_p(m.grad[m.nW:].data_ptr()),
+                                    C.c_void_p(work.data_ptr()), C.byref(loss)))
+    dW, db, oloss = O.backward(x, ozs, oacts, t.astype(np.float64))
+    assert abs(loss.value - oloss) <= 1e-3 * oloss
+    g = to_np(m.grad)
+    off = 0
+    for l in range(len(dW)):
+        assert rel(g[off:off + dW[l].size], dW[l].ravel()) <= 1e-2, l
+        off += dW[l].size
+    for l in range(len(db)):
+        assert rel(g[off:off + db[l].size], db[l]) <= 1e-2, l
+        off += db[l].size
+
+
+def test_adam_step_matches_oracle():
+    widths = [49, 128, 41]
+    W, b = _params(widths, 6)
+    G, m = _gpu_mlp(widths, W, b)
+    rng = np.random.default_rng(7)
+    p = to_np(m.master)
+    m1 = np.zeros_like(p)
+    m2 = np.zeros_like(p)
+    for step in range(1, 4):
+        gr = rng.standard_normal(p.size).astype(np.float32)
+        m.grad.copy_(torch.from_numpy(gr).cuda())
+        G._check(G.lib.ilh_mlp_adam(G.ctx, m.nparam, C.c_void_p(m.master.data_ptr()), C.c_void_p(m.grad.data_ptr()),
+                                    C.c_void_p(m.m1.data_ptr()), C.c_void_p(m.m2.data_ptr()), step, 1e-3, 0.9, 0.999,
+                                    1e-8))
+        p, m1, m2 = adam_step(p, gr.astype(np.float64), m1, m2, step, 1e-3)
+    assert np.allclose(to_np(m.master), p, rtol=1e-5, atol=1e-7)
+
+
+def _element_views(O, u):
+    """Element-local velocity [Ne, 2, Nh], energy [Ne, Nl], positions [Ne, 2, Nh] (oracle mesh)."""
+    x, v, e = O.split(u)
+    conn = O.mesh.conn
+    return (v.reshape(2, -1)[:, conn].transpose(1, 0, 2), e.reshape(O.mesh.Ne, -1),
+            x.reshape(2, -1)[:, conn].transpose(1, 0, 2))
+
+
+def test_features_targets_assembly():
+    O, G = make_pair("tg2d", (5, 4), 3)
+    rng = np.random.default_rng(8)
+    u = O.init_state()
+    u[O.nh1:] += 0.1 * rng.standard_normal(O.nblock - O.nh1)
+    base = rng.standard_normal(O.nblock)
+    kk = rng.standard_normal(O.nblock)
+    sc = dict(vs=0.7, es=1.3, xs=0.05, kvs=2.0, kes=3.0)
+    k = 3
+    Nh, Nl = (k + 1) ** 2, k * k
+    nin = 2 * Nh + Nl + 8 + 2 * Nh + Nl
+    ld = pad32(nin)
+    f = torch.zeros(O.mesh.Ne, ld, dtype=torch.float32, device="cuda")
+    ud, bd, kd = to_dev(u), to_dev(base), to_dev(kk)  # keep the device copies alive during the calls
+    G._check(G.lib.ilh_guess_features(G.ctx, G._vec(ud, G.nblock), G._vec(bd, G.nblock),
+                                      sc["vs"], sc["es"], sc["xs"], sc["kvs"], sc["kes"], None, None,
+                                      C.c_void_p(f.data_ptr()), ld))
+    ve, ee, xe = _element_views(O, u)
+    bv, be, _ = _element_views(O, base)
+    corners = [0, k, k * (k + 1), k * (k + 1) + k]
+    xc = xe[:, :, corners]  # (Ne, 2, 4)
+    cen = xc.mean(axis=2, keepdims=True)
+    expect = np.concatenate([ve.reshape(O.mesh.Ne, -1) / sc["vs"], ee / sc["es"],
+                             ((xc - cen) / sc["xs"]).transpose(0, 2, 1).reshape(O.mesh.Ne, -1),
+                             bv.reshape(O.mesh.Ne, -1) / sc["kvs"], be / sc["kes"]], axis=1)
+    fg = to_np(f)
+    assert np.allclose(fg[:, :nin], expect, rtol=1e-6, atol=1e-6)
+    assert np.all(fg[:, nin:] == 0)
+    # targets
+    ldo = pad32(2 * Nh + Nl)
+    t = torch.zeros(O.mesh.Ne, ldo, dtype=torch.float32, device="cuda")
+    G._check(G.lib.ilh_guess_targets(G.ctx, G._vec(kd, G.nblock), G._vec(bd, G.nblock),
+                                     sc["kvs"], sc["kes"], None, C.c_void_p(t.data_ptr()), ldo))
+    kv, ke, _ = _element_views(O, kk)
+    exp_t = np.concatenate([(kv - bv).reshape(O.mesh.Ne, -1) / sc["kvs"], (ke - be) / sc["kes"]], axis=1)
+    assert np.allclose(to_np(t)[:, :2 * Nh + Nl], exp_t, rtol=1e-6, atol=1e-6)
+    # assembly of those targets reproduces kk on free velocity rows (nodal average of
+    # identical element copies), kk_e exactly, and x = u_v + tau k_v
+    tau = 0.01
+    kout = G.new()
+    G._check(G.lib.ilh_guess_assemble(G.ctx, C.c_void_p(t.data_ptr()), ldo, sc["kvs"], sc["kes"], None,
+                                      G._vec(bd, G.nblock), G._vec(ud, G.nblock), tau,
+                                      C.c_void_p(kout.data_ptr())))
+    ko = to_np(kout)
+    cons = O.cons
+    kvf = kk[O.nh1:2 * O.nh1]
+    assert np.allclose(ko[O.nh1:2 * O.nh1][~cons], kvf[~cons], rtol=1e-6, atol=1e-6)
+    assert np.all(ko[O.nh1:2 * O.nh1][cons] == 0)
+    assert np.allclose(ko[2 * O.nh1:], kk[2 * O.nh1:], rtol=1e-6, atol=1e-6)
+    assert np.allclose(ko[:O.nh1], u[O.nh1:2 * O.nh1] + tau * ko[O.nh1:2 * O.nh1], rtol=1e-12, atol=1e-14)
+
+
+def test_training_reduces_loss():
+    """A fixed smooth target map is learned by the GPU training loop (loss falls 5x)."""
+    widths = [49, 128, 128, 128, 41]
+    G = ilh.Hydro("tg2d", (2, 2), 2)
+    m = ilh.learned.GuessMLP(G, widths, seed=1)
+    rng = np.random.default_rng(9)
+    X = _input(8192, 49, 10)
+    A = rng.standard_normal((49, 41)) / 7.0
+    T = np.zeros((8192, pad32(41)), dtype=np.float32)
+    T[:, :41] = np.tanh(X[:, :49] @ A)
+    hist = ilh.learned.train(m, to_dev(X, torch.float32), to_dev(T, torch.float32), 30, 512, 3e-3)
+    assert hist[-1] < 0.2 * hist[0], hist
