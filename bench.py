@@ -40,7 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--generic-jvp", action="store_true", help="use the generic element kernel for J dk")
-    ap.add_argument("--roofline-shape", type=int, default=0,
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-seeds", default="1000-1001")
+    ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--roofline-shape", type=int, default=1024,
                     help="also time the JVP on an n x n Q3Q2 state of this size (0 = off)")
     return ap.parse_args()
 
@@ -198,6 +201,22 @@ def main():
                       "bytes_per_launch": jvp_bytes(HR, 32, args.generic_jvp)}
         del HR
 
+    learned = None
+    if not args.no_learned:
+        from paper_2609_16424_amd import learned as L
+        if os.path.exists(L.DEFAULT_MODEL):
+            z = np.load(L.DEFAULT_MODEL)
+            scales = dict(zip(("vs", "es", "xs", "kvs", "kes"), z["scales"].tolist()))
+            lo, hi = [int(v) for v in args.learned_seeds.split("-")]
+            opts_c4 = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150)
+            res = L.evaluate(112, 48, 3, list(range(lo, hi + 1)), args.learned_steps, float(z["cfl_factor"]),
+                             opts_c4, {k: z[k] for k in ("widths", "master", "mu", "sd", "osc")}, scales)
+            learned = {"workload": "2D triple point 112x48 Q3Q2, smoothed viscosity, %gx explicit CFL, "
+                                   "held-out perturbation seeds %s, %d steps each, tol 1e-10"
+                                   % (float(z["cfl_factor"]), args.learned_seeds, args.learned_steps),
+                       "plain": res["plain"], "learned": res["learned"], "zero_output_control": res["zero"],
+                       "speedup_s_per_step": res["plain"]["s_per_step"] / res["learned"]["s_per_step"]}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(u_start.detach().cpu().numpy(), n, k, dt)
@@ -231,6 +250,10 @@ def main():
         "energy_after": ke + ie,
     }
     out.update(extra)
+    if learned:
+        out["learned_guess_c5"] = learned
+        out["s_per_implicit_step_learned_c5"] = learned["learned"]["s_per_step"]
+        out["s_per_implicit_step_plain_c5"] = learned["plain"]["s_per_step"]
     if roof_extra:
         out["roofline_large_shape"] = roof_extra
     print(json.dumps(out))

@@ -221,23 +221,36 @@ class Hydro:
 
     # ---- masses ----
     def _build_masses(self):
-        m, T = self.mesh, self.T
-        # scalar H1 mass M_s(i,j) = sum_e sum_q m_q w_i w_j, eq. (matrices)
-        Me = np.einsum("eq,qi,qj->eij", self.mq, T["W"], T["W"])
-        rows = np.repeat(m.conn, m.Nh, axis=1).ravel()
-        cols = np.tile(m.conn, (1, m.Nh)).ravel()
-        self.Ms = sp.csr_matrix((Me.ravel(), (rows, cols)), shape=(m.N, m.N))
+        T = self.T
         # L2 mass blocks and their inverses (block diagonal: L2 is discontinuous)
         self.MEb = np.einsum("eq,qi,qj->eij", self.mq, T["Phi"], T["Phi"])
         self.MEinv = np.linalg.inv(self.MEb)
-        # BC-eliminated scalar masses per component (identity on constrained DOFs)
-        self.cons = m.constrained.ravel()  # (d*N,)
-        self._Mhat_lu = []
-        for c in range(self.dim):
-            free = ~m.constrained[c]
-            P = sp.diags(free.astype(float))
-            Mhat = P @ self.Ms @ P + sp.diags((~free).astype(float))
-            self._Mhat_lu.append(spla.splu(Mhat.tocsc()))
+        self.cons = self.mesh.constrained.ravel()  # (d*N,)
+        self._Ms = None
+        self._Mhat_lu = None
+
+    @property
+    def Ms(self):
+        """Scalar H1 mass M_s(i,j) = sum_e sum_q m_q w_i w_j, eq. (matrices) (built on first use)."""
+        if self._Ms is None:
+            m, T = self.mesh, self.T
+            Me = np.einsum("eq,qi,qj->eij", self.mq, T["W"], T["W"])
+            rows = np.repeat(m.conn, m.Nh, axis=1).ravel()
+            cols = np.tile(m.conn, (1, m.Nh)).ravel()
+            self._Ms = sp.csr_matrix((Me.ravel(), (rows, cols)), shape=(m.N, m.N))
+        return self._Ms
+
+    def _mhat_lu(self):
+        """LU factors of the BC-eliminated scalar masses (identity on constrained DOFs)."""
+        if self._Mhat_lu is None:
+            m = self.mesh
+            self._Mhat_lu = []
+            for c in range(self.dim):
+                free = ~m.constrained[c]
+                P = sp.diags(free.astype(float))
+                Mhat = P @ self.Ms @ P + sp.diags((~free).astype(float))
+                self._Mhat_lu.append(spla.splu(Mhat.tocsc()))
+        return self._Mhat_lu
 
     def mass_v(self, v):
         """M_V v with M_V = I_d (x) M_s (no boundary conditions)."""
@@ -250,8 +263,9 @@ class Hydro:
         d, N = self.dim, self.mesh.N
         bb = b.reshape(d, N)
         out = []
+        lus = self._mhat_lu()
         for c in range(d):
-            lu = self._Mhat_lu[c]
+            lu = lus[c]
             if np.iscomplexobj(bb):
                 out.append(lu.solve(bb[c].real) + 1j * lu.solve(bb[c].imag))
             else:
@@ -277,8 +291,10 @@ class Hydro:
         d, N = self.dim, self.mesh.N
         return x.reshape(d, N)[:, self.mesh.conn]  # (d, Ne, Nh)
 
-    def geometry(self, wx):
+    def geometry(self, wx, elements=None):
         X = self._gather(wx)
+        if elements is not None:
+            X = X[:, elements]
         J = np.einsum("cen,qna->eqca", X, self.T["dW"])
         return J, np.linalg.det(J)
 
@@ -287,27 +303,32 @@ class Hydro:
         return float(np.min(np.real(detJ)))
 
     # ---- the force operator ----
-    def pointwise(self, w):
-        """Quadrature-point state: J, detJ, J^-1, rho, e+, p, c_s, grad v, sigma, mu."""
+    def pointwise(self, w, elements=None):
+        """Quadrature-point state: J, detJ, J^-1, rho, e+, p, c_s, grad v, sigma, mu.
+
+        ``elements`` restricts the evaluation to a subset of elements (same arithmetic).
+        """
         wx, wv, we = self.split(w)
         d, T, m = self.dim, self.T, self.mesh
-        J, detJ = self.geometry(wx)
+        sel = slice(None) if elements is None else elements
+        J, detJ = self.geometry(wx, elements)
         Jinv = np.linalg.inv(J)
-        rho = self.rho0_e[:, None] * self.detJ0 / detJ
-        E = we.reshape(m.Ne, m.Nl)
+        detJ0 = self.detJ0[sel]
+        rho = self.rho0_e[sel, None] * detJ0 / detJ
+        E = we.reshape(m.Ne, m.Nl)[sel]
         eq = np.einsum("ej,qj->eq", E, T["Phi"])
         ep = e_plus(eq)
-        g = self.gamma_e[:, None]
+        g = self.gamma_e[sel, None]
         p = (g - 1.0) * rho * ep
         cs = np.sqrt(g * (g - 1.0) * ep)
-        V = self._gather(wv)
+        V = self._gather(wv)[:, sel]
         gradv = np.einsum("cen,qnb,eqba->eqca", V, T["dW"], Jinv)  # d v_c / d x_a
         I = np.eye(d)
         sigma = -p[..., None, None] * I
         mu = np.zeros_like(p)
         if self.visc.on:
             vo = self.visc
-            h = vo.h0 * (detJ / self.detJ0) ** (1.0 / d)                      # eq. visc_imp_h
+            h = vo.h0 * (detJ / detJ0) ** (1.0 / d)                          # eq. visc_imp_h
             dv = h * np.trace(gradv, axis1=-2, axis2=-1)                     # eq. visc_imp_dv
             if vo.mode == "const":
                 dsc = vo.width * np.ones_like(h)
@@ -322,31 +343,37 @@ class Hydro:
         return dict(J=J, detJ=detJ, Jinv=Jinv, rho=rho, ep=ep, p=p, cs=cs, gradv=gradv,
                     sigma=sigma, mu=mu)
 
-    def force_matrix(self, w):
+    def force_matrix(self, w, elements=None):
         """Element force matrices F_e[e, c, n, j] = int_{Omega_e(t)} (sigma : grad w_{n,c}) phi_j.
 
         The integral is the reference quadrature sum_q w_q |J_q| (...); the physical
         gradient of the H1 basis function w_n e_c is e_c (x) J^{-T} grad_xi w_n.
+        ``elements`` restricts the evaluation to a subset of elements.
         """
-        pw = self.pointwise(w)
+        pw = self.pointwise(w, elements)
         T = self.T
         gw = np.einsum("qnb,eqba->eqna", T["dW"], pw["Jinv"])  # physical grad of w_n
         return np.einsum("q,eq,eqca,eqna,qj->ecnj", T["qw"], pw["detJ"], pw["sigma"], gw, T["Phi"])
 
-    def force(self, w):
+    def force(self, w, elements=None):
         """(F 1, F^T v): the two actions of the force matrix used in eqs. (v_semi), (e_semi).
 
         F 1 is an H1 vector (component-major, no boundary conditions), F^T v an L2 vector;
-        v is the velocity block of the same state w.
+        v is the velocity block of the same state w.  With ``elements`` only those elements
+        contribute (F 1 is then exact at nodes whose elements are all listed, and F^T v is
+        returned for the listed elements only, shape [len(elements), Nl]).
         """
-        Fe = self.force_matrix(w)
+        Fe = self.force_matrix(w, elements)
         m = self.mesh
-        F1e = Fe.sum(axis=-1)  # (Ne, d, Nh)
+        sel = np.arange(m.Ne) if elements is None else np.asarray(elements)
+        F1e = Fe.sum(axis=-1)  # (ne, d, Nh)
         F1 = np.zeros((self.dim, m.N), dtype=Fe.dtype)
         for c in range(self.dim):
-            np.add.at(F1[c], m.conn, F1e[:, c, :])
-        V = self._gather(self.split(w)[1])
+            np.add.at(F1[c], m.conn[sel], F1e[:, c, :])
+        V = self._gather(self.split(w)[1])[:, sel]
         Ftv = np.einsum("ecnj,cen->ej", Fe, V)
+        if elements is not None:
+            return F1.ravel(), Ftv
         return F1.ravel(), Ftv.ravel()
 
     def energy_source(self, wx):

@@ -351,7 +351,7 @@ def evaluate(nx, ny, k, seeds, steps, cfl_factor, opts, model_state, scales, log
             del h
         out[mode] = {"newton_per_step": float(np.mean(newton)), "gmres_per_step": float(np.mean(gmres)),
                      "s_per_step": float(np.mean(wall)), "steps": len(newton), "learned_used": used,
-                     "median_initial_residual_ratio": float(np.median(ginit))}
+                     "median_initial_residual_ratio": float(np.nanmedian(ginit))}
         if log:
             log("%s: %s" % (mode, out[mode]))
     return out

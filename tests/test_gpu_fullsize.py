@@ -1,0 +1,122 @@
+"""Parity at the benchmark configurations' full sizes, in the launch configuration that
+bench.py times (linearize + FP32 Jacobian action through the register-resident kernel).
+
+C2 (2D TG 128x128 Q3Q2) and C4 (triple point 112x48 Q3Q2, viscosity) are compared with the
+oracle directly.  C3 (3D TG 32^3 Q2Q1 on a displaced mesh) is checked on sampled outputs the
+oracle evaluates element by element, against central finite differences of FP64 residuals
+(eps = 1e-7, seeded random directions), and through identities that hold at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2609_16424_amd as ilh
+import seeded_inputs as si
+from gpu_common import rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(problem, n, k, visc=None, **kw):
+    from oracle.hydro import Hydro as OHydro, ViscosityOptions
+    vo = ViscosityOptions(on=visc is not None, mode=visc or "const", h_coarse=kw.pop("h_coarse", None))
+    O = OHydro(problem, n, k, visc=vo)
+    G = ilh.Hydro(problem, n, k, visc=visc is not None, dscale_mode=visc or "const",
+                  h_coarse=vo.h_coarse or 0.0, tg_source=O.use_source)
+    return O, G
+
+
+@pytest.mark.parametrize("case", ["C2", "C4"])
+def test_full_size_residual_and_jvp(case):
+    from oracle.krylov import jvp_cs
+    if case == "C2":
+        O, G = _pair("tg2d", (128, 128), 3)
+    else:
+        O, G = _pair("triple", (112, 48), 3, visc="formula", h_coarse=1.0 / 3.0)
+    u0 = O.init_state()
+    h = 1.0 / (O.k * max(O.mesh.n))
+    u = si.perturb_state(u0, 11, O.nh1, 0.05 * h, 0.05, 0.02)
+    tau = 0.5 * O.dt_estimate(u, 2.0)
+    k = si.block_direction(12, O.nh1, O.nl2, 0.1 * h, 0.1, 0.1)
+    dk = si.block_direction(13, O.nh1, O.nl2, h, 1.0, 1.0)
+    r = to_np(G.residual(to_dev(k), to_dev(u), tau))
+    assert rel(r, O.residual(k, u, tau)) <= 1e-12
+    jo = jvp_cs(lambda q: O.residual(q, u, tau), k, dk)
+    G.linearize(to_dev(k), to_dev(u), tau)
+    j32 = to_np(G.jvp_lin(to_dev(dk, torch.float32), 32))
+    j64 = to_np(G.jvp_lin(to_dev(dk), 64))
+    assert rel(j32, jo) <= 1e-5, rel(j32, jo)
+    assert rel(j64, jo) <= 1e-12, rel(j64, jo)
+
+
+@pytest.fixture(scope="module", params=[None, "formula"])
+def c3(request):
+    from oracle.hydro import Hydro as OHydro, ViscosityOptions
+    visc = request.param
+    vo = ViscosityOptions(on=visc is not None, mode="formula")
+    O = OHydro("tg3d", (32, 32, 32), 2, visc=vo)
+    G = ilh.Hydro("tg3d", (32, 32, 32), 2, visc=visc is not None, dscale_mode="formula")
+    u0 = O.init_state()
+    w = si.displace_positions(u0, O.nh1, 0.05)  # x = x0 + 0.05 v_TG(x0)
+    return O, G, w
+
+
+def test_c3_sampled_outputs_match_oracle(c3):
+    O, G, w = c3
+    f1, ftv = G.force(to_dev(w))
+    f1, ftv = to_np(f1), to_np(ftv)
+    rng = np.random.default_rng(0)
+    m = O.mesh
+    els = np.sort(rng.choice(m.Ne, 40, replace=False))
+    _, otv = O.force(w, elements=els)
+    assert rel(ftv.reshape(m.Ne, -1)[els], otv) <= 1e-12
+    # F 1 at sampled nodes: evaluate exactly the elements that contain them
+    nodes = rng.choice(m.N, 12, replace=False)
+    adj = np.unique(np.nonzero(np.isin(m.conn, nodes))[0])
+    of1, _ = O.force(w, elements=adj)
+    idx = np.concatenate([c * m.N + nodes for c in range(3)])
+    assert rel(f1[idx], of1[idx]) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-6), (32, 1e-5)])
+def test_c3_jvp_matches_central_fd(c3, prec, tol):
+    O, G, w = c3
+    dev = to_dev(w)
+    tau = 0.5 * G.dt_estimate(dev, 8.0)
+    h = 1.0 / 64
+    for seed in range(3):
+        dk = si.block_direction(100 + seed, O.nh1, O.nl2, sx=h, sv=0.1, se=0.1)
+        dk = si.zero_rows(dk, np.concatenate([np.zeros(O.nh1, bool), O.mesh.constrained.ravel(),
+                                              np.zeros(O.nl2, bool)]))
+        k = torch.zeros_like(dev)
+        eps = 1e-7
+        dkd = to_dev(dk)
+        rp = G.residual(k + eps * dkd, dev, tau)
+        rm = G.residual(k - eps * dkd, dev, tau)
+        fd = to_np((rp - rm) / (2 * eps))
+        dt = torch.float64 if prec == 64 else torch.float32
+        j = to_np(G.jvp(k, dev, tau, to_dev(dk, dt), prec))
+        assert rel(j, fd) <= tol, (seed, rel(j, fd))
+
+
+def test_c3_identities(c3):
+    O, G, w = c3
+    f1, ftv = G.force(to_dev(w))
+    f1 = to_np(f1).reshape(3, -1)
+    v = w[O.nh1:2 * O.nh1]
+    assert np.abs(f1.sum(1)).max() <= 1e-12 * np.abs(f1).sum()
+    assert abs(v @ f1.ravel() - to_np(ftv).sum()) <= 1e-12 * np.abs(v * f1.ravel()).sum()
+
+
+def test_autograd_forward_mode_matches_fd():
+    """ForceFn.jvp (hand-written tangent) against central differences of the forward."""
+    O, G = _pair("tg3d", (6, 5, 4), 2)
+    w = si.displace_positions(O.init_state(), O.nh1, 0.05)
+    dw = si.block_direction(5, O.nh1, O.nl2, 1 / 12, 0.1, 0.1)
+    wd, dwd = to_dev(w), to_dev(dw)
+    (f1, ftv), (df1, dftv) = torch.func.jvp(lambda x: ilh.ForceFn.apply(G, x), (wd,), (dwd,))
+    eps = 1e-7
+    p1, ptv = G.force(wd + eps * dwd)
+    m1, mtv = G.force(wd - eps * dwd)
+    assert rel(to_np(df1), to_np((p1 - m1) / (2 * eps))) <= 1e-6
+    assert rel(to_np(dftv), to_np((ptv - mtv) / (2 * eps))) <= 1e-6
