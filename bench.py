@@ -19,6 +19,7 @@ Printed JSON line:
 Run with --gpus N, N > 1: exits, this build runs on one GPU only.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,32 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of one FP32 Jacobian-action launch at 128x128 Q3Q2 without viscosity, from two
+# rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
+# the same counter reads for a copy-shaped kernel of known size (--copy-probe-mib).  The record
+# holds only while the kernel sources hash to the value it was taken with; otherwise traffic is
+# reported as null.
+TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvp2d.hip", "paper_2609_16424_amd/csrc/ilh_pointwise.h",
+                   "paper_2609_16424_amd/csrc/ilh_internal.h")
+TRAFFIC_RECORD = {"sha256": None, "n": 128, "order": 3,
+                  "fetch_kib": None, "fetch_scale": None, "write_kib": None, "write_scale": None}
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(root, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(n, k, generic):
+    r = TRAFFIC_RECORD
+    if generic or r["sha256"] is None or (n, k) != (r["n"], r["order"]) or sources_sha256() != r["sha256"]:
+        return None
+    return 1024.0 * (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"])
 
 
 def parse():
@@ -43,6 +70,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-seeds", default="1000-1001")
     ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a copy-shaped elementwise kernel (dst = -src) over this many MiB three "
+                         "times: the byte calibration for HBM traffic counters")
     ap.add_argument("--roofline-shape", type=int, default=1024,
                     help="also time the JVP on an n x n Q3Q2 state of this size (0 = off)")
     return ap.parse_args()
@@ -217,6 +247,15 @@ def main():
                        "plain": res["plain"], "learned": res["learned"], "zero_output_control": res["zero"],
                        "speedup_s_per_step": res["plain"]["s_per_step"] / res["learned"]["s_per_step"]}
 
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(u_start.detach().cpu().numpy(), n, k, dt)
@@ -239,7 +278,8 @@ def main():
                                (n, n, k, k - 1, args.cfl_factor, dt),
                    "n_qp": H.nqp, "n_block": H.nblock},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(n, k, args.generic_jvp),
                      "kernel": "k_elem2d<4,6,JVP,float,7>" if args.generic_jvp else "k_jvp2d<4,6,float,visc=0,src=1>", "bytes_per_launch": bytes32,
                      "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n},
         "cpu_baseline": cpu,

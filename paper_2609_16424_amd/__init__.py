@@ -31,8 +31,15 @@ def newton_options(**kw):
     return o
 
 
+def _raw(t):
+    """The plain tensor under functorch wrappers (torch.func transforms hand those to custom rules)."""
+    while torch._C._functorch.is_functorch_wrapped_tensor(t):
+        t = torch._C._functorch.get_unwrapped(t)
+    return t
+
+
 def _ptr(t):
-    return C.c_void_p(t.data_ptr())
+    return C.c_void_p(_raw(t).data_ptr())
 
 
 class Hydro:
@@ -274,10 +281,14 @@ class ForceFn(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, hydro, w):
+    def forward(hydro, w):
+        return hydro.force(w.detach().contiguous())
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        hydro, w = inputs
         ctx.hydro = hydro
         ctx.save_for_forward(w)
-        return hydro.force(w.detach().contiguous())
 
     @staticmethod
     def jvp(ctx, _hydro_t, dw):
@@ -293,16 +304,22 @@ class ResidualFn(torch.autograd.Function):
     """R(k; tau, u) with forward-mode derivative J dk from ilh_jvp (FP64)."""
 
     @staticmethod
-    def forward(ctx, hydro, k, u, tau):
+    def forward(hydro, k, u, tau):
+        return hydro.residual(k.detach().contiguous(), u.detach().contiguous(), float(tau))
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        hydro, k, u, tau = inputs
         ctx.hydro, ctx.tau = hydro, float(tau)
         ctx.save_for_forward(k, u)
-        return hydro.residual(k.detach().contiguous(), u.detach().contiguous(), tau)
 
     @staticmethod
     def jvp(ctx, _h, dk, du, _t):
         k, u = ctx.saved_tensors
         if du is not None and bool(torch.any(du != 0)):
             raise NotImplementedError("tangents in u are not supported; differentiate in k")
+        if dk is None:
+            dk = torch.zeros_like(k)
         return ctx.hydro.jvp(k.detach().contiguous(), u.detach().contiguous(), ctx.tau, dk.contiguous(), 64)
 
     @staticmethod

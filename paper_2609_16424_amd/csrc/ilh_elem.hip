@@ -758,11 +758,10 @@ static int launch_elem_t(ilh_ctx* c, const EArgs<T>& a) {
   constexpr int Q1D = 2 * K;
   const int grid = (int)((c->Ne + NE - 1) / NE);
   if constexpr (DIM == 2) {
-    hipLaunchKernelGGL((k_elem2d<K + 1, Q1D, MODE, T, NE>), dim3(grid), dim3(Q1D * Q1D * NE), 0,
-                       c->stream, c->kp, a);
+    klaunch(c, k_elem2d<K + 1, Q1D, MODE, T, NE>, dim3(grid), dim3(Q1D * Q1D * NE), 0, c->kp, a);
   } else {
-    hipLaunchKernelGGL((k_elem3d<K + 1, Q1D, MODE, T, NE>), dim3(grid), dim3(Q1D * Q1D * Q1D * NE), 0,
-                       c->stream, c->kp, a);
+    klaunch(c, k_elem3d<K + 1, Q1D, MODE, T, NE>, dim3(grid), dim3(Q1D * Q1D * Q1D * NE), 0, c->kp,
+            a);
   }
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;

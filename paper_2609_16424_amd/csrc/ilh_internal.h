@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <string>
@@ -102,6 +103,7 @@ struct ilh_ctx {
   std::vector<hipEvent_t> tev;  // pairs
   std::vector<int> tcls;
   int tused = 0;
+  hipEvent_t xev0 = nullptr, xev1 = nullptr;  // open single-kernel slot, taken by the next klaunch
   double tms[ILH_TIMING_CLASSES] = {0, 0, 0, 0, 0};
   int64_t tcnt[ILH_TIMING_CLASSES] = {0, 0, 0, 0, 0};
   std::string err;
@@ -123,6 +125,19 @@ int hip_fail(ilh_ctx* c, hipError_t e, const char* what);
 int tstart(ilh_ctx* c, int cls);
 void tstop(ilh_ctx* c, int slot);
 int tflush(ilh_ctx* c);
+// Single-kernel slot: the events are not recorded as stream markers but attached to the next
+// kernel launched through klaunch, so they bracket that dispatch alone.  tstop_k records both
+// (an empty interval) if no launch took them.
+int tstart_k(ilh_ctx* c, int cls);
+void tstop_k(ilh_ctx* c, int slot);
+
+// Launch on the ctx stream, handing it the open single-kernel timing events, if any.
+template <typename F, typename... Args>
+inline void klaunch(ilh_ctx* c, F kernel, dim3 grid, dim3 block, uint32_t shm, Args... args) {
+  hipEvent_t e0 = c->xev0, e1 = c->xev1;
+  c->xev0 = c->xev1 = nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, block, shm, c->stream, e0, e1, 0u, args...);
+}
 
 // kernel launchers (ilh_ops.hip)
 int launch_elem(ilh_ctx* c, int mode, int prec, const EArgs<double>* a64, const EArgs<float>* a32);

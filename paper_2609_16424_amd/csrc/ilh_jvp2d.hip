@@ -291,13 +291,13 @@ static int launch_jvp2d_t(ilh_ctx* c, const EArgs<T>& a) {
   dim3 grid((c->n[0] + EPW - 1) / EPW, c->n[1]);
   const int visc = c->kp.visc ? 1 : 0, src = c->kp.tg_source ? 1 : 0;
   if (visc && src)
-    hipLaunchKernelGGL((k_jvp2d<D1D, Q1D, T, 1, 1>), grid, dim3(64), 0, c->stream, c->kp, tb, a);
+    klaunch(c, k_jvp2d<D1D, Q1D, T, 1, 1>, grid, dim3(64), 0, c->kp, tb, a);
   else if (visc)
-    hipLaunchKernelGGL((k_jvp2d<D1D, Q1D, T, 1, 0>), grid, dim3(64), 0, c->stream, c->kp, tb, a);
+    klaunch(c, k_jvp2d<D1D, Q1D, T, 1, 0>, grid, dim3(64), 0, c->kp, tb, a);
   else if (src)
-    hipLaunchKernelGGL((k_jvp2d<D1D, Q1D, T, 0, 1>), grid, dim3(64), 0, c->stream, c->kp, tb, a);
+    klaunch(c, k_jvp2d<D1D, Q1D, T, 0, 1>, grid, dim3(64), 0, c->kp, tb, a);
   else
-    hipLaunchKernelGGL((k_jvp2d<D1D, Q1D, T, 0, 0>), grid, dim3(64), 0, c->stream, c->kp, tb, a);
+    klaunch(c, k_jvp2d<D1D, Q1D, T, 0, 0>, grid, dim3(64), 0, c->kp, tb, a);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }

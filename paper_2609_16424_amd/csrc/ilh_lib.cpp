@@ -148,6 +148,25 @@ void tstop(ilh_ctx* c, int slot) {
   if (slot >= 0) hipEventRecord(c->tev[2 * slot + 1], c->stream);
 }
 
+int tstart_k(ilh_ctx* c, int cls) {
+  if (!c->timing) return -1;
+  if (c->tused == TPOOL && tflush(c) != ILH_OK) return -1;
+  const int slot = c->tused++;
+  c->tcls[slot] = cls;
+  c->xev0 = c->tev[2 * slot];
+  c->xev1 = c->tev[2 * slot + 1];
+  return slot;
+}
+
+void tstop_k(ilh_ctx* c, int slot) {
+  if (slot < 0) return;
+  if (c->xev0) {
+    hipEventRecord(c->xev0, c->stream);
+    hipEventRecord(c->xev1, c->stream);
+    c->xev0 = c->xev1 = nullptr;
+  }
+}
+
 template <typename T>
 static int dalloc(ilh_ctx* c, T** p, size_t count) {
   *p = nullptr;
@@ -561,9 +580,9 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   int st = launch_fill(c, r + c->nh1, 0.0, c->nh1);
   if (st) return st;
   EArgs<double> a{u, u + c->nh1, u + 2 * c->nh1, k, nullptr, tau, r, nullptr};
-  const int slot = tstart(c, 1);
+  const int slot = tstart_k(c, 1);
   st = launch_elem(c, M_RESID, 64, &a, nullptr);
-  tstop(c, slot);
+  tstop_k(c, slot);
   return st;
 }
 
@@ -583,20 +602,20 @@ int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
     double* o = (double*)jdk;
     if ((st = launch_fill(c, o + c->nh1, 0.0, c->nh1))) return st;
     EArgs<double> a{c->w64, c->w64 + c->nh1, c->w64 + 2 * c->nh1, nullptr, (const double*)dk, c->lin_tau, o, nullptr};
-    const int slot = tstart(c, 0);
+    const int slot = tstart_k(c, 0);
     st = c->generic_jvp ? ILH_EINVAL : launch_jvp2d(c, 64, &a, nullptr);
     if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 64, &a, nullptr);
-    tstop(c, slot);
+    tstop_k(c, slot);
     return st;
   }
   if (prec == 32) {
     float* o = (float*)jdk;
     if ((st = launch_fillf(c, o + c->nh1, 0.0f, c->nh1))) return st;
     EArgs<float> a{c->w64, c->w32 + c->nh1, c->w32 + 2 * c->nh1, nullptr, (const float*)dk, c->lin_tau, o, nullptr};
-    const int slot = tstart(c, 0);
+    const int slot = tstart_k(c, 0);
     st = c->generic_jvp ? ILH_EINVAL : launch_jvp2d(c, 32, nullptr, &a);
     if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 32, nullptr, &a);
-    tstop(c, slot);
+    tstop_k(c, slot);
     return st;
   }
   return fail(c, ILH_EINVAL, "prec must be 32 or 64");

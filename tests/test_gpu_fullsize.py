@@ -12,7 +12,7 @@ import torch
 
 import paper_2609_16424_amd as ilh
 import seeded_inputs as si
-from gpu_common import rel, to_dev, to_np
+from gpu_common import rel, to_dev, to_np, random_state, random_dir
 
 pytestmark = pytest.mark.gpu
 
@@ -120,3 +120,18 @@ def test_autograd_forward_mode_matches_fd():
     m1, mtv = G.force(wd - eps * dwd)
     assert rel(to_np(df1), to_np((p1 - m1) / (2 * eps))) <= 1e-6
     assert rel(to_np(dftv), to_np((ptv - mtv) / (2 * eps))) <= 1e-6
+
+
+def test_autograd_dual_residual_matches_oracle():
+    """ResidualFn under torch.autograd.forward_ad equals the oracle's complex-step J dk."""
+    O, G = _pair("tg2d", (7, 5), 3)
+    from oracle.krylov import jvp_cs
+    u, k, dk = random_state(O, 11), 0.1 * random_dir(O, 12), random_dir(O, 13)
+    tau = 2e-3
+    import torch.autograd.forward_ad as fwAD
+    with fwAD.dual_level():
+        kd = fwAD.make_dual(to_dev(k), to_dev(dk))
+        r = ilh.ResidualFn.apply(G, kd, to_dev(u), tau)
+        val, tan = fwAD.unpack_dual(r)
+    assert rel(to_np(val), O.residual(k, u, tau)) <= 1e-12
+    assert rel(to_np(tan), jvp_cs(lambda q: O.residual(q, u, tau), k, dk)) <= 1e-12
