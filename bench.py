@@ -10,11 +10,14 @@ A timed "step" is one implicit midpoint step: plain initial iterate, then Newton
 (residual, Jacobian actions, mass preconditioner, detJ line search) and the update.
 
 Printed JSON line:
-  value       Jacobian-action throughput in quadrature points per second: N_qp divided by
-              the mean duration of the FP32 Jacobian-action kernel launches inside the
-              timed steps (HIP events recorded by the library on its stream);
+  value       Jacobian-action throughput in quadrature points per second: N_qp times the
+              number of FP32 Jacobian actions inside the timed steps, divided by their summed
+              kernel time plus that of the linearisation launches they used (HIP events
+              attached by the library to each dispatch on its stream);
   ms_per_step wall time per implicit step (host synchronised at both ends);
-  roofline    algorithmic bytes of one Jacobian-action launch / mean launch time vs 8 TB/s;
+  roofline    algorithmic bytes of one Jacobian-action (apply) launch / its mean launch time,
+              vs 8 TB/s; traffic = counter-measured bytes per launch when recorded for the
+              current kernel sources;
   cpu_baseline the CPU oracle's complex-step Jacobian action on the same state.
 Run with --gpus N, N > 1: exits, this build runs on one GPU only.
 """
@@ -34,10 +37,12 @@ HBM_PEAK_GBS = 8000.0
 # the same counter reads for a copy-shaped kernel of known size (--copy-probe-mib).  The record
 # holds only while the kernel sources hash to the value it was taken with; otherwise traffic is
 # reported as null.
-TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvp2d.hip", "paper_2609_16424_amd/csrc/ilh_pointwise.h",
+TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_pointwise.h",
                    "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": None, "n": 128, "order": 3,
-                  "fetch_kib": None, "fetch_scale": None, "write_kib": None, "write_scale": None}
+TRAFFIC_RECORD = {"sha256": "174974a5a12198e6d69ad873f06db4213aa6867051e2bb7e4e6f66aeb7ba3f53",
+                  "variant": "lin", "n": 128, "order": 3,
+                  "fetch_kib": 18786.48, "fetch_scale": 262144.0 / 131079.60,
+                  "write_kib": 6771.94, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
@@ -49,9 +54,9 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(n, k, generic):
+def recorded_traffic(n, k, variant):
     r = TRAFFIC_RECORD
-    if generic or r["sha256"] is None or (n, k) != (r["n"], r["order"]) or sources_sha256() != r["sha256"]:
+    if variant != r["variant"] or r["sha256"] is None or (n, k) != (r["n"], r["order"]) or sources_sha256() != r["sha256"]:
         return None
     return 1024.0 * (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"])
 
@@ -66,7 +71,9 @@ def parse():
     ap.add_argument("--cfl-factor", type=float, default=4.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
-    ap.add_argument("--generic-jvp", action="store_true", help="use the generic element kernel for J dk")
+    ap.add_argument("--jvp-variant", choices=("lin", "generic", "recompute"), default="lin",
+                    help="Jacobian-action kernels: linearised (stored tangent coefficients), generic element "
+                         "kernel, or register-resident recompute kernel")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-seeds", default="1000-1001")
     ap.add_argument("--learned-steps", type=int, default=20)
@@ -78,21 +85,37 @@ def parse():
     return ap.parse_args()
 
 
-def jvp_bytes(H, prec, generic=False):
-    """Algorithmic HBM bytes of one Jacobian-action launch: every vector read/written once.
+def n_coef(H):
+    """Stored tangent coefficients per quadrature point of the linearised 2D kernels."""
+    return (16 if H.setup.visc_on else 10) + (2 if H.setup.tg_source else 0)
 
-    State x (FP64), v and e (FP32 shadow, or FP64), direction dk and output J dk, and the
-    quadrature data: per-point m_q for the generic kernel, per-element rho0|J0|, |J0| and
-    gamma for the register-resident 2D kernel (affine initial mesh).
+
+def jvp_bytes(H, prec, variant="lin"):
+    """Algorithmic HBM bytes of one Jacobian-action launch: every array read or written once.
+
+    lin:       direction dk and output J dk, the stored tangent coefficients (n_coef per point)
+               and the per-element rho0 |J0| (quadrature-mass factor).
+    recompute: state x (FP64), v and e (FP32 shadow, or FP64), dk, J dk and per-element
+               rho0 |J0|, |J0| and gamma (affine initial mesh).
+    generic:   as recompute, with per-point m_q instead of the per-element factors.
     """
-    if prec == 32:
-        state = H.nh1 * 8 + H.nh1 * 4 + H.nl2 * 4
-        vec = H.nblock * 4
-    else:
-        state = H.nblock * 8
-        vec = H.nblock * 8
-    qdata = H.nqp * 8 + H.Ne * 8 if generic else 3 * H.Ne * 8
+    w = 4 if prec == 32 else 8
+    vec = H.nblock * w
+    if variant == "lin":
+        return 2 * vec + n_coef(H) * H.nqp * w + H.Ne * 8
+    state = H.nh1 * 8 + (H.nh1 + H.nl2) * w
+    qdata = H.nqp * 8 + H.Ne * 8 if variant == "generic" else 3 * H.Ne * 8
     return state + 2 * vec + qdata
+
+
+def lin_bytes(H, prec):
+    """Algorithmic bytes of one linearisation launch: state w (FP64) read, coefficients written,
+    per-element rho0 |J0|, |J0|, gamma read."""
+    return H.nblock * 8 + n_coef(H) * H.nqp * (4 if prec == 32 else 8) + 3 * H.Ne * 8
+
+
+KERNEL_NAMES = {"lin": "k_jvp2d_q<4,6,float,visc=0,src=1>", "generic": "k_elem2d<4,6,JVP,float,7>",
+                "recompute": "k_jvp2d<4,6,float,visc=0,src=1>"}
 
 
 def run_steps(H, u, dt, nsteps, opts, hist, ilh):
@@ -146,8 +169,7 @@ def main():
 
     n, k = args.n, args.order
     H = ilh.Hydro("tg2d", (n, n), k)
-    if args.generic_jvp:
-        H.lib.ilh_set_kernel_variant(H.ctx, 1)
+    H.set_kernel_variant(args.jvp_variant)
     u0 = H.init_state()
     dt = args.cfl_factor * H.dt_estimate(u0, 0.5)
     opts32 = ilh.newton_options(tol=1e-10, jvp_prec=32)
@@ -172,9 +194,11 @@ def main():
     H.timing(False)
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     jvp_ms, jvp_n = tim["jvp"]
+    lin_ms, lin_n = tim["linearize"]
     jvp_avg_s = 1e-3 * jvp_ms / max(jvp_n, 1)
-    value = H.nqp / jvp_avg_s
-    bytes32 = jvp_bytes(H, 32, args.generic_jvp)
+    # Jacobian actions per second of kernel time, the linearisation launches charged to them
+    value = H.nqp * jvp_n / (1e-3 * (jvp_ms + lin_ms))
+    bytes32 = jvp_bytes(H, 32, args.jvp_variant)
     achieved = bytes32 / jvp_avg_s / 1e9
     u32 = u.clone()
     newton = [s["newton"] for s in stats]
@@ -194,10 +218,12 @@ def main():
         tim64 = H.timing_read()
         H.timing(False)
         j64_ms, j64_n = tim64["jvp"]
+        l64_ms, l64_n = tim64["linearize"]
         extra["all_fp64"] = {
             "ms_per_step": 1e3 * (t1 - t0) / args.steps,
-            "jvp_qps": H.nqp / (1e-3 * j64_ms / max(j64_n, 1)),
-            "jvp_avg_us": 1e3 * j64_ms / max(j64_n, 1),
+            "jvp_qps": H.nqp * j64_n / (1e-3 * (j64_ms + l64_ms)),
+            "jvp_apply_avg_us": 1e3 * j64_ms / max(j64_n, 1),
+            "linearize_avg_us": 1e3 * l64_ms / max(l64_n, 1),
             "newton_per_step": float(np.mean([s["newton"] for s in st64])),
             "gmres_per_step": float(np.mean([s["gmres"] for s in st64])),
             "rel_state_diff_vs_fp32_jvp": float(torch.linalg.norm(u - u32) / torch.linalg.norm(u)),
@@ -207,8 +233,7 @@ def main():
     if args.roofline_shape:
         m = args.roofline_shape
         HR = ilh.Hydro("tg2d", (m, m), 3)
-        if args.generic_jvp:
-            HR.lib.ilh_set_kernel_variant(HR.ctx, 1)
+        HR.set_kernel_variant(args.jvp_variant)
         uR = HR.init_state()
         uR[:HR.nh1] += 0.05 * uR[HR.nh1:2 * HR.nh1]
         kR = torch.zeros_like(uR)
@@ -222,13 +247,20 @@ def main():
         HR.timing(True)
         for _ in range(20):
             HR.jvp_lin(dk32, 32, out32)
+        for _ in range(5):  # re-linearise: one linearisation launch each (linearised variant)
+            HR.linearize(kR, uR, 0.5 * HR.dt_estimate(uR, 2.0))
+            HR.jvp_lin(dk32, 32, out32)
         tr = HR.timing_read()
         HR.timing(False)
         avg = 1e-3 * tr["jvp"][0] / tr["jvp"][1]
+        bR = jvp_bytes(HR, 32, args.jvp_variant)
         roof_extra = {"shape": "%dx%d Q3Q2 TG (displaced)" % (m, m), "n_qp": HR.nqp,
-                      "jvp_qps": HR.nqp / avg, "achieved_GBs": jvp_bytes(HR, 32, args.generic_jvp) / avg / 1e9,
-                      "frac": jvp_bytes(HR, 32, args.generic_jvp) / avg / 1e9 / HBM_PEAK_GBS,
-                      "bytes_per_launch": jvp_bytes(HR, 32, args.generic_jvp)}
+                      "jvp_qps": HR.nqp / avg, "achieved_GBs": bR / avg / 1e9,
+                      "frac": bR / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": bR, "avg_launch_us": 1e6 * avg}
+        if tr["linearize"][1]:
+            lavg = 1e-3 * tr["linearize"][0] / tr["linearize"][1]
+            roof_extra["linearize"] = {"avg_launch_us": 1e6 * lavg, "bytes_per_launch": lin_bytes(HR, 32),
+                                       "achieved_GBs": lin_bytes(HR, 32) / lavg / 1e9}
         del HR
 
     learned = None
@@ -279,9 +311,14 @@ def main():
                    "n_qp": H.nqp, "n_block": H.nblock},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(n, k, args.generic_jvp),
-                     "kernel": "k_elem2d<4,6,JVP,float,7>" if args.generic_jvp else "k_jvp2d<4,6,float,visc=0,src=1>", "bytes_per_launch": bytes32,
+                     "traffic": recorded_traffic(n, k, args.jvp_variant),
+                     "kernel": KERNEL_NAMES[args.jvp_variant], "bytes_per_launch": bytes32,
                      "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n},
+        "jvp_variant": args.jvp_variant,
+        "jvp_apply_qps": H.nqp / jvp_avg_s,
+        "linearize": {"launches": lin_n, "avg_launch_us": 1e3 * lin_ms / max(lin_n, 1),
+                      "bytes_per_launch": lin_bytes(H, 32) if lin_n else None,
+                      "jvp_launches_per_linearization": jvp_n / lin_n if lin_n else None},
         "cpu_baseline": cpu,
         "s_per_implicit_step_plain": ms_per_step / 1e3,
         "newton_per_step": float(np.mean(newton)),

@@ -119,16 +119,22 @@ int ilh_force_jvp(ilh_ctx* ctx, int prec, const double* w, const void* dw, void*
  *   R_e = M_E k_e - F(w)^T w_v - b(w_x)   (b: TG energy source, else 0). */
 int ilh_residual(ilh_ctx* ctx, const double* k, const double* u, double tau, double* r);
 
-/* Store the linearisation point of the next ilh_jvp_lin calls: w = u + tau k in FP64 and
- * its FP32 shadow (velocity and energy) inside the context. */
+/* Store the linearisation point of the next ilh_jvp_lin calls: w = u + tau k in FP64 inside
+ * the context (and, for the recomputing kernel variants, its FP32 shadow of velocity and
+ * energy).  Stored tangent coefficients of an earlier point are invalidated; the first
+ * ilh_jvp_lin of each precision recomputes them. */
 int ilh_linearize(ilh_ctx* ctx, const double* k, const double* u, double tau);
 
 /* Jacobian action J dk = dR/dk [dk] at the stored linearisation point (eq. newton_linear):
  *   (J dk)_x = dk_x - tau dk_v
  *   (J dk)_v = M_V dk_v + d(F 1)[tau dk]            (constrained rows: dk_v)
  *   (J dk)_e = M_E dk_e - d(F^T w_v)[tau dk] - db[tau dk_x].
- * prec = 64: dk, jdk are double [block]; prec = 32: float [block] (FP32 arithmetic,
- * positions read in FP64 and made element-relative before rounding). */
+ * prec = 64: dk, jdk are double [block]; prec = 32: float [block], FP32 arithmetic (the
+ * linearised variant applies FP64-evaluated coefficients rounded to FP32; the recomputing
+ * variants read positions in FP64 and make them element-relative before rounding).  The first
+ * call of a precision after ilh_linearize evaluates and stores that precision's tangent
+ * coefficients (linearised variant: 2D, k = 2, 3; 12 to 18 values per quadrature point,
+ * allocated on first use and kept until ilh_destroy). */
 int ilh_jvp_lin(ilh_ctx* ctx, int prec, const void* dk, void* jdk);
 
 /* ilh_linearize followed by ilh_jvp_lin. */
@@ -219,14 +225,20 @@ int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double*
 /* Kernel timing with HIP events recorded on the context stream around each launch of the
  * timed kernel classes: 0 = Jacobian-action element kernel, 1 = residual element kernel,
  * 2 = velocity-mass element kernel, 3 = Krylov orthogonalisation (multi-dot / multi-axpy),
- * 4 = other Newton-Krylov vector kernels.  ilh_timing_enable(ctx, 1) resets the counters;
- * ilh_timing_read synchronises the stream and returns, per class, the summed kernel time in
- * milliseconds and the number of timed launches (host arrays of ILH_TIMING_CLASSES). */
-#define ILH_TIMING_CLASSES 5
-/* Select the Jacobian-action kernel: generic = 0 (default) uses the register-resident 2D
- * kernel where one exists (2D, k = 2, 3), generic = 1 always uses the generic
- * LDS-staged element kernel.  Both compute the same operator (for cross-checking). */
-int ilh_set_kernel_variant(ilh_ctx* ctx, int generic);
+ * 4 = other Newton-Krylov vector kernels, 5 = linearisation kernel of the linearised
+ * Jacobian action (once per linearisation point and precision).  For classes 0, 1 and 5 the
+ * events are attached to the kernel dispatch itself.  ilh_timing_enable(ctx, 1) resets the
+ * counters; ilh_timing_read synchronises the stream and returns, per class, the summed kernel
+ * time in milliseconds and the number of timed launches (host arrays of ILH_TIMING_CLASSES). */
+#define ILH_TIMING_CLASSES 6
+/* Select the Jacobian-action kernels (all compute the same operator, for cross-checking):
+ *   0 (default) linearised: where one exists (2D, k = 2, 3), the tangent coefficients of every
+ *     quadrature point are evaluated once per linearisation point and precision (FP64
+ *     arithmetic, stored in the precision of the action) and each action applies them;
+ *   1 generic LDS-staged element kernel recomputing the state's quadrature data;
+ *   2 register-resident 2D kernel recomputing the state's quadrature data (2D, k = 2, 3).
+ * Other values: ILH_EINVAL. */
+int ilh_set_kernel_variant(ilh_ctx* ctx, int variant);
 int ilh_timing_enable(ilh_ctx* ctx, int on);
 int ilh_timing_read(ilh_ctx* ctx, double* ms, int64_t* launches);
 

@@ -232,14 +232,22 @@ class Hydro:
                                              min(len(history), 2), float(tau), _ptr(out)))
         return out
 
+    JVP_VARIANTS = {"lin": 0, "generic": 1, "recompute": 2}
+
+    def set_kernel_variant(self, variant):
+        """Jacobian-action kernels: "lin" (default), "generic" or "recompute" (or 0, 1, 2)."""
+        v = self.JVP_VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self._stream()
+        self._check(self.lib.ilh_set_kernel_variant(self.ctx, v))
+
     def timing(self, on=True):
         self._check(self.lib.ilh_timing_enable(self.ctx, int(bool(on))))
 
     def timing_read(self):
-        ms = (C.c_double * 5)()
-        cnt = (C.c_int64 * 5)()
+        names = ("jvp", "residual", "mass", "krylov", "precond", "linearize")
+        ms = (C.c_double * len(names))()
+        cnt = (C.c_int64 * len(names))()
         self._check(self.lib.ilh_timing_read(self.ctx, ms, cnt))
-        names = ("jvp", "residual", "mass", "krylov", "precond")
         return {nm: (ms[i], cnt[i]) for i, nm in enumerate(names)}
 
     def stage_solve(self, ubase, tau, guess=None, opts=None):

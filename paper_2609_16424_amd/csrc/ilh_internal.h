@@ -52,6 +52,15 @@ struct EArgs {
   T* out2;
 };
 
+// 1D tables of the 2D element kernels, passed by value (kernel-argument memory).
+template <typename T, int D1D, int Q1D>
+struct Tab2 {
+  T B[Q1D][D1D];
+  T G[Q1D][D1D];
+  T BL[Q1D][D1D - 1];
+  T W[Q1D];
+};
+
 }  // namespace ilh
 
 struct ilh_ctx {
@@ -97,15 +106,17 @@ struct ilh_ctx {
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   double* hdev = nullptr;       // [4 * 72] device scalars of the Arnoldi step
   double* hhost = nullptr;      // pinned mirror of hdev
-  bool generic_jvp = false;     // force the generic element kernel for Jacobian actions
+  int jvp_variant = 0;          // 0 linearised (where available), 1 generic, 2 register-resident recompute
+  void* qd[2] = {nullptr, nullptr};  // stored tangent coefficients, FP32 / FP64 (linearised variant)
+  bool qd_ok[2] = {false, false};    // valid for the current linearisation point
   // kernel timing (HIP events)
   bool timing = false;
   std::vector<hipEvent_t> tev;  // pairs
   std::vector<int> tcls;
   int tused = 0;
   hipEvent_t xev0 = nullptr, xev1 = nullptr;  // open single-kernel slot, taken by the next klaunch
-  double tms[ILH_TIMING_CLASSES] = {0, 0, 0, 0, 0};
-  int64_t tcnt[ILH_TIMING_CLASSES] = {0, 0, 0, 0, 0};
+  double tms[ILH_TIMING_CLASSES] = {};
+  int64_t tcnt[ILH_TIMING_CLASSES] = {};
   std::string err;
 };
 
@@ -143,6 +154,12 @@ inline void klaunch(ilh_ctx* c, F kernel, dim3 grid, dim3 block, uint32_t shm, A
 int launch_elem(ilh_ctx* c, int mode, int prec, const EArgs<double>* a64, const EArgs<float>* a32);
 // register-resident 2D Jacobian action (k = 2, 3); ILH_EINVAL when not specialised
 int launch_jvp2d(ilh_ctx* c, int prec, const EArgs<double>* a64, const EArgs<float>* a32);
+// linearised 2D Jacobian action (k = 2, 3): coefficients at (w64, lin_tau), then apply
+bool lin2d_available(const ilh_ctx* c);
+int launch_lin2d(ilh_ctx* c, int prec);
+int launch_jvp2d_q(ilh_ctx* c, int prec, const void* dk, void* out);
+int lin2d_nqd(const ilh_ctx* c);
+int64_t lin2d_stride(const ilh_ctx* c);
 int launch_fill(ilh_ctx* c, double* p, double v, int64_t n);
 int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n);
 int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int64_t n);  // y = a x + b y

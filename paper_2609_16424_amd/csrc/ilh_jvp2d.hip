@@ -19,14 +19,6 @@
 
 namespace ilh {
 
-template <typename T, int D1D, int Q1D>
-struct Tab2 {
-  T B[Q1D][D1D];
-  T G[Q1D][D1D];
-  T BL[Q1D][D1D - 1];
-  T W[Q1D];
-};
-
 template <int D1D, int Q1D, typename T, int VISC, int SRC>
 __global__ void __launch_bounds__(64) k_jvp2d(const KParams P, const Tab2<T, D1D, Q1D> tb, const EArgs<T> A) {
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;

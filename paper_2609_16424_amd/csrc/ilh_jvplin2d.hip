@@ -1,0 +1,637 @@
+// Linearised 2D Jacobian action of the stage residual (eq. pa_jac_action at a fixed Newton
+// iterate), split into a linearisation launched once per iterate and an apply launched by
+// every Krylov iteration.
+//
+// At a quadrature point the tangent of (S, s) (Sec. 3.4: forward derivative of the stress
+// kernel) is linear in the direction's (dJ, d(dv/dxi), de), with coefficients that depend on
+// the state w alone.  k_lin2d evaluates those coefficients at w in FP64 and stores them in the
+// working precision; k_jvp2d_q then reads the direction, the stored coefficients and the
+// per-element mass factor only: geometry, inverse Jacobian, equation of state and viscosity
+// of the state are not re-evaluated by each Krylov iteration.
+//
+// With gv = (dv/dxi) J^-1, U = dJ J^-1, dJ^-1 = -J^-1 U and dgv = d(dv/dxi) J^-1 - gv U:
+//   Sig  = -P I  [+ m_q nu eps(gv)],                      P  = (gamma - 1) m_q e+
+//   dSig = -cP de I  [+ dnu eps(gv) + m_q nu eps(dgv)],   cP = P / sqrt(e^2 + eps^2)
+//   dnu  = a0 tr(U) + a1 tr(dgv) + a2 de   (viscosity; m_q folded into a)
+//   dS = dSig J^-T + Sig dJ^-T,   ds = dSig : gv + Sig : dgv,
+//   TG source row: db = m_q grad s(x_q) . dx_q.
+// Stored per point, in this order: J^-1 (4), gv (4); then P, cP without viscosity, or
+// Sig00, Sig01, Sig11, cP, m_q nu, a0, a1, a2 with it; then m_q grad s (2) with the source.
+// Every coefficient after the first eight multiplies the direction exactly once, so the stage
+// factor tau (the direction enters as tau dk) is folded into them at linearisation.
+//
+// Layout of the stored data: field f of lane l at quadrature row qy of work-group b sits at
+// qd[f * qs + (b * Q1D + qy) * 64 + l] (one 64-lane row per wave and row: coalesced).  Both
+// kernels use the work-group / lane map of the register-resident kernel: one wave = EPW
+// consecutive elements of one element row, lane (z, qx) = quadrature column qx of element z.
+#include <hip/hip_runtime.h>
+
+#include "ilh_internal.h"
+#include "ilh_pointwise.h"
+
+namespace ilh {
+
+template <int VISC, int SRC>
+struct LinLayout {
+  static constexpr int NPT = VISC ? 16 : 10;  // pointwise coefficients
+  static constexpr int NQD = NPT + (SRC ? 2 : 0);
+};
+
+// Coefficients of the stress tangent at one point, FP64 (see the file comment).
+template <int VISC>
+__device__ __forceinline__ void lin_coefs2(const KParams& P, double gam, double mq, double dJ0,
+                                           const double J[2][2], const double Gv[2][2], double e,
+                                           double* c) {
+  double Ji[2][2], det;
+  inv_det<2, double>(J, Ji, det);
+  double gv[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) gv[r][b] = Gv[r][0] * Ji[0][b] + Gv[r][1] * Ji[1][b];
+  double ep, rr;
+  e_plus<double>(e, P.eps_e, ep, rr);
+  const double g1 = gam - 1.0;
+  const double Pq = g1 * mq * ep, cP = Pq / rr;
+  c[0] = Ji[0][0];
+  c[1] = Ji[0][1];
+  c[2] = Ji[1][0];
+  c[3] = Ji[1][1];
+  c[4] = gv[0][0];
+  c[5] = gv[0][1];
+  c[6] = gv[1][0];
+  c[7] = gv[1][1];
+  if constexpr (!VISC) {
+    c[8] = Pq;
+    c[9] = cP;
+  } else {
+    const double div = gv[0][0] + gv[1][1];
+    const double h = P.h0 * sqrt(det / dJ0);
+    const double dv = h * div;
+    const double cs = sqrt(gam * g1 * ep);
+    // derivatives as combinations of (tr U, tr dgv, de)
+    const double dh[3] = {0.5 * h, 0.0, 0.0};
+    const double ddv[3] = {0.5 * h * div, h, 0.0};
+    const double dcs[3] = {0.0, 0.0, cs / (2.0 * rr)};
+    double dsc, ddsc[3];
+    if (P.dsc_mode) {
+      dsc = 2.0 * h * cs * P.hc_inv;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ddsc[i] = 2.0 * P.hc_inv * (dh[i] * cs + h * dcs[i]);
+    } else {
+      dsc = P.dsc_w;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ddsc[i] = 0.0;
+    }
+    const double aabs = sqrt(dv * dv + dsc * dsc);
+    const double t = -dv / (2.0 * dsc) - P.psi_shift;
+    const double th = tanh(t);
+    const double psi = 0.5 + 0.5 * th;
+    const double base = P.q2 * aabs + P.q1 * cs * psi;
+    const double mnu = mq * h * base;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double daabs = (dv * ddv[i] + dsc * ddsc[i]) / aabs;
+      const double dt = -(ddv[i] * dsc - dv * ddsc[i]) / (2.0 * dsc * dsc);
+      const double dpsi = 0.5 * (1.0 - th * th) * dt;
+      const double dnu = dh[i] * base + h * (P.q2 * daabs + P.q1 * (dcs[i] * psi + cs * dpsi));
+      c[13 + i] = mq * dnu;
+    }
+    c[8] = -Pq + mnu * gv[0][0];
+    c[9] = mnu * 0.5 * (gv[0][1] + gv[1][0]);
+    c[10] = -Pq + mnu * gv[1][1];
+    c[11] = cP;
+    c[12] = mnu;
+  }
+}
+
+// Apply the stored coefficients to one point's (dJ, dGv, de): dS (2 x 2) and ds.
+template <typename T, int VISC>
+__device__ __forceinline__ void lin_apply2(const T* c, const T dJ[2][2], const T dGv[2][2], T de,
+                                           T dS[2][2], T& ds) {
+  const T Ji[2][2] = {{c[0], c[1]}, {c[2], c[3]}};
+  const T gv[2][2] = {{c[4], c[5]}, {c[6], c[7]}};
+  T U[2][2], dJi[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) U[a][b] = dJ[a][0] * Ji[0][b] + dJ[a][1] * Ji[1][b];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) dJi[a][b] = -(Ji[a][0] * U[0][b] + Ji[a][1] * U[1][b]);
+  if constexpr (!VISC) {
+    const T Pq = c[8], dP = c[9] * de;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) dS[r][a] = -dP * Ji[a][r] - Pq * dJi[a][r];
+    T trdgv = 0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) trdgv += dGv[r][a] * Ji[a][r] - gv[r][a] * U[a][r];
+    ds = -dP * (gv[0][0] + gv[1][1]) - Pq * trdgv;
+  } else {
+    T dgv[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        dgv[r][b] = dGv[r][0] * Ji[0][b] + dGv[r][1] * Ji[1][b] - gv[r][0] * U[0][b] - gv[r][1] * U[1][b];
+    const T dnu = c[13] * (U[0][0] + U[1][1]) + c[14] * (dgv[0][0] + dgv[1][1]) + c[15] * de;
+    const T dP = c[11] * de, mnu = c[12];
+    const T Sig[2][2] = {{c[8], c[9]}, {c[9], c[10]}};
+    const T eps01 = T(0.5) * (gv[0][1] + gv[1][0]), deps01 = T(0.5) * (dgv[0][1] + dgv[1][0]);
+    T dSig[2][2];
+    dSig[0][0] = -dP + dnu * gv[0][0] + mnu * dgv[0][0];
+    dSig[1][1] = -dP + dnu * gv[1][1] + mnu * dgv[1][1];
+    dSig[0][1] = dSig[1][0] = dnu * eps01 + mnu * deps01;
+    T dss = 0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        dS[r][a] = dSig[r][0] * Ji[a][0] + dSig[r][1] * Ji[a][1] + Sig[r][0] * dJi[a][0] + Sig[r][1] * dJi[a][1];
+        dss += dSig[r][a] * gv[r][a] + Sig[r][a] * dgv[r][a];
+      }
+    ds = dss;
+  }
+}
+
+// ---- linearisation: state w (FP64) -> stored coefficients (T) ----------------------------
+template <int D1D, int Q1D, typename T, int VISC, int SRC>
+__global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double, D1D, Q1D> tb,
+                                              const double* __restrict__ w, double tau, T* __restrict__ qd,
+                                              int64_t qs) {
+  constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
+  constexpr int EPW = 64 / Q1D;
+  constexpr int NS = K * EPW + 1;
+  constexpr int NQD = LinLayout<VISC, SRC>::NQD;
+
+  __shared__ double sS[4][D1D][NS];  // x0 x1 v0 v1
+  __shared__ double sE[EPW * NLD];
+  __shared__ double sBG[2][Q1D][D1D];
+  __shared__ double sBLt[Q1D][L1D];
+
+  const int lane = threadIdx.x;
+  const int ey = blockIdx.y, ex0 = blockIdx.x * EPW;
+  const int nx = P.n[0];
+  const int E = min(EPW, nx - ex0);
+  const int ns = K * E + 1;
+  const int64_t ng0 = P.ng[0];
+  const int64_t N = P.N, nh1 = 2 * P.N;
+  const int64_t ebase = (int64_t)ey * nx + ex0;
+
+  constexpr int NTS = 4 * D1D * NS, RT = (NTS + 63) / 64;
+  double tr[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = lane + 64 * r, si = i % NS, t = i / NS, b = t % D1D, f = t / D1D;
+    tr[r] = 0.0;
+    if (i < NTS && si < ns) {
+      const int64_t node = (int64_t)(K * ey + b) * ng0 + (int64_t)K * ex0 + si;
+      tr[r] = w[(f < 2 ? f * N : nh1 + (f - 2) * N) + node];
+    }
+  }
+  for (int i = lane; i < EPW * NLD; i += 64) sE[i] = (i < E * NLD) ? w[2 * nh1 + ebase * NLD + i] : 0.0;
+  for (int i = lane; i < Q1D * D1D; i += 64) {
+    sBG[0][i / D1D][i % D1D] = tb.B[i / D1D][i % D1D];
+    sBG[1][i / D1D][i % D1D] = tb.G[i / D1D][i % D1D];
+  }
+  for (int i = lane; i < Q1D * L1D; i += 64) sBLt[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = lane + 64 * r;
+    if (i < NTS) (&sS[0][0][0])[i] = tr[r];
+  }
+  __syncthreads();
+
+  const int z = lane / Q1D, qx = lane - z * Q1D;
+  if (z >= E) return;  // no barrier follows
+  const int s0 = K * z;
+  const int64_t e = ebase + z;
+  double Bq[D1D], Gq[D1D], BLq[L1D];
+#pragma unroll
+  for (int a = 0; a < D1D; ++a) {
+    Bq[a] = sBG[0][qx][a];
+    Gq[a] = sBG[1][qx][a];
+  }
+#pragma unroll
+  for (int a = 0; a < L1D; ++a) BLq[a] = sBLt[qx][a];
+  double AB[4][D1D], AG[4][D1D];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int b = 0; b < D1D; ++b) {
+      double ab = 0, ag = 0;
+#pragma unroll
+      for (int a = 0; a < D1D; ++a) {
+        const double xv = sS[f][b][s0 + a];
+        ab += Bq[a] * xv;
+        ag += Gq[a] * xv;
+      }
+      AB[f][b] = ab;
+      AG[f][b] = ag;
+    }
+  double ALe[L1D];
+#pragma unroll
+  for (int bl = 0; bl < L1D; ++bl) {
+    double a0 = 0;
+#pragma unroll
+    for (int al = 0; al < L1D; ++al) a0 += BLq[al] * sE[z * NLD + al + L1D * bl];
+    ALe[bl] = a0;
+  }
+  const double gam = P.gamma[e], dJ0 = P.j0e[e];
+  const double wx = tb.W[qx] * P.rj0[e];
+  const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll 1
+  for (int qy = 0; qy < Q1D; ++qy) {
+    double J[2][2], Gv[2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double j0 = 0, j1 = 0, g0 = 0, g1 = 0;
+#pragma unroll
+      for (int b = 0; b < D1D; ++b) {
+        const double By = tb.B[qy][b], Gy = tb.G[qy][b];
+        j0 += By * AG[c][b];
+        j1 += Gy * AB[c][b];
+        g0 += By * AG[2 + c][b];
+        g1 += Gy * AB[2 + c][b];
+      }
+      J[c][0] = j0;
+      J[c][1] = j1;
+      Gv[c][0] = g0;
+      Gv[c][1] = g1;
+    }
+    double eq = 0;
+#pragma unroll
+    for (int bl = 0; bl < L1D; ++bl) eq += tb.BL[qy][bl] * ALe[bl];
+    const double mq = wx * tb.W[qy];
+    double cf[NQD];
+    lin_coefs2<VISC>(P, gam, mq, dJ0, J, Gv, eq, cf);
+    if constexpr (SRC != 0) {
+      double xq0 = 0, xq1 = 0;
+#pragma unroll
+      for (int b = 0; b < D1D; ++b) {
+        xq0 += tb.B[qy][b] * AB[0][b];
+        xq1 += tb.B[qy][b] * AB[1][b];
+      }
+      double gx, gy;
+      tg_source_grad<double>(xq0, xq1, gam, gx, gy);
+      cf[NQD - 2] = mq * gx;
+      cf[NQD - 1] = mq * gy;
+    }
+    // tau folded into every coefficient that multiplies the direction
+#pragma unroll
+    for (int f = 8; f < NQD; ++f) cf[f] *= tau;
+    T* q = qd + (blk * Q1D + qy) * 64 + lane;
+#pragma unroll
+    for (int f = 0; f < NQD; ++f) q[f * qs] = T(cf[f]);
+  }
+}
+
+// ---- apply: direction dk (T) -> J dk (T) --------------------------------------------------
+// 32-bit element offset from a uniform base (byte offsets below 4 GiB, checked on the host).
+typedef const char __attribute__((address_space(1))) * gbytes;
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i) {
+  const gbytes p = (gbytes)base + (uint64_t)(i * (uint32_t)sizeof(T));
+  return *(const T __attribute__((address_space(1)))*)p;
+}
+
+// A wave-uniform pointer made opaque to the compiler (scalar registers): loads from it take the
+// scalar-base + 32-bit vector-offset form instead of per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ const T* sbase(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
+template <int D1D, int Q1D, typename T, int VISC, int SRC>
+__global__ void __launch_bounds__(64) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
+                                                const T* __restrict__ dk, const T* __restrict__ qd,
+                                                int64_t qs, double tau_, T* __restrict__ out) {
+  constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
+  constexpr int EPW = 64 / Q1D;
+  constexpr int NS = K * EPW + 1;
+  constexpr int NQD = LinLayout<VISC, SRC>::NQD;
+  constexpr int NOUT = 2 * D1D * D1D + NLD;  // outputs per element
+  constexpr int NOP = NOUT | 1;              // odd LDS row length (bank spread)
+  static_assert(Q1D % 2 == 0, "the quadrature rows are processed in pairs");
+
+  __shared__ T sS[4][D1D][NS];  // dkx0 dkx1 dkv0 dkv1 strips
+  __shared__ T sE[EPW * NLD];   // dk_e
+  __shared__ T sO[64][NOP];     // per-lane contributions to the element's outputs
+  __shared__ T sBG[2][Q1D][D1D];
+  __shared__ T sBLt[Q1D][L1D];
+
+  const int lane = threadIdx.x;
+  const int ey = blockIdx.y, ex0 = blockIdx.x * EPW;
+  const int nx = P.n[0];
+  const int E = min(EPW, nx - ex0);
+  const int ns = K * E + 1;
+  const uint32_t ng0 = P.ng[0], ng1 = P.ng[1];
+  const uint32_t N = (uint32_t)P.N, nh1 = 2 * N;
+  const uint32_t ebase = (uint32_t)ey * nx + ex0;
+  const uint32_t row0 = (uint32_t)(K * ey) * ng0 + (uint32_t)(K * ex0);  // first node of the strip
+
+  constexpr int NTS = 4 * D1D * NS, RT = (NTS + 63) / 64;
+  constexpr int NLS = EPW * NLD, RL = (NLS + 63) / 64;
+  T tr[RT], lr[RL];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = lane + 64 * r, si = i % NS, t = i / NS, b = t % D1D, f = t / D1D;
+    tr[r] = T(0);
+    if (i < NTS && si < ns)
+      tr[r] = ld32(dk, (f < 2 ? f * N : nh1 + (f - 2) * N) + row0 + (uint32_t)b * ng0 + si);
+  }
+#pragma unroll
+  for (int r = 0; r < RL; ++r) {
+    const int i = lane + 64 * r;
+    lr[r] = T(0);
+    if (i < E * NLD) lr[r] = ld32(dk, 2 * nh1 + ebase * NLD + i);
+  }
+  const int zl = lane / Q1D;
+  const double rj_l = P.rj0[ebase + (zl < E ? zl : 0)];
+  for (int i = lane; i < Q1D * D1D; i += 64) {
+    sBG[0][i / D1D][i % D1D] = tb.B[i / D1D][i % D1D];
+    sBG[1][i / D1D][i % D1D] = tb.G[i / D1D][i % D1D];
+  }
+  for (int i = lane; i < Q1D * L1D; i += 64) sBLt[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = lane + 64 * r;
+    if (i < NTS) (&sS[0][0][0])[i] = tr[r];
+  }
+#pragma unroll
+  for (int r = 0; r < RL; ++r) {
+    const int i = lane + 64 * r;
+    if (i < NLS) sE[i] = lr[r];
+  }
+  __syncthreads();
+
+  const T tau = T(tau_);
+  const bool last_x = (ex0 + E == nx), last_y = (ey == P.n[1] - 1);
+  const int z = lane / Q1D, qx = lane - z * Q1D;
+  const bool active = z < E;
+  if (active) {
+    const int s0 = K * z;
+    T Bq[D1D], Gq[D1D], BLq[L1D];
+#pragma unroll
+    for (int a = 0; a < D1D; ++a) {
+      Bq[a] = sBG[0][qx][a];
+      Gq[a] = sBG[1][qx][a];
+    }
+#pragma unroll
+    for (int a = 0; a < L1D; ++a) BLq[a] = sBLt[qx][a];
+    T AB[4][D1D], AG[4][D1D];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int b = 0; b < D1D; ++b) {
+        T ab = 0, ag = 0;
+#pragma unroll
+        for (int a = 0; a < D1D; ++a) {
+          const T xv = sS[f][b][s0 + a];
+          ab += Bq[a] * xv;
+          ag += Gq[a] * xv;
+        }
+        AB[f][b] = ab;
+        AG[f][b] = ag;
+      }
+    T ALd[L1D];
+#pragma unroll
+    for (int bl = 0; bl < L1D; ++bl) {
+      T a1 = 0;
+#pragma unroll
+      for (int al = 0; al < L1D; ++al) a1 += BLq[al] * sE[z * NLD + al + L1D * bl];
+      ALd[bl] = a1;
+    }
+    T T0[2][D1D], T1[2][D1D], TL[L1D];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < D1D; ++b) T0[c][b] = T1[c][b] = T(0);
+#pragma unroll
+    for (int bl = 0; bl < L1D; ++bl) TL[bl] = T(0);
+    const T wx = tb.W[qx] * T(rj_l);
+    // coefficient rows of this wave: field f at qd[f qs + (blk Q1D + qy) 64 + lane]
+    const T* __restrict__ qb = qd + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (Q1D * 64);
+    const T* qf[NQD];
+#pragma unroll
+    for (int f = 0; f < NQD; ++f) qf[f] = sbase(qb + f * qs);
+    auto row = [&](const int qy, const T* cf) {
+      // tau is folded into the coefficients: the contractions enter unscaled
+      T dJ[2][2], dGv[2][2], dkv[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T d0 = 0, d1 = 0, h0 = 0, h1 = 0, mv = 0;
+#pragma unroll
+        for (int b = 0; b < D1D; ++b) {
+          const T By = tb.B[qy][b], Gy = tb.G[qy][b];
+          d0 += By * AG[c][b];
+          d1 += Gy * AB[c][b];
+          h0 += By * AG[2 + c][b];
+          h1 += Gy * AB[2 + c][b];
+          mv += By * AB[2 + c][b];
+        }
+        dJ[c][0] = d0;
+        dJ[c][1] = d1;
+        dGv[c][0] = h0;
+        dGv[c][1] = h1;
+        dkv[c] = mv;
+      }
+      T dke = 0;
+#pragma unroll
+      for (int bl = 0; bl < L1D; ++bl) dke += tb.BL[qy][bl] * ALd[bl];
+      const T mq = wx * tb.W[qy];
+      T dS[2][2], ds;
+      lin_apply2<T, VISC>(cf, dJ, dGv, dke, dS, ds);
+      T cl = mq * dke - ds;
+      if constexpr (SRC != 0) {
+        T dx0 = 0, dx1 = 0;
+#pragma unroll
+        for (int b = 0; b < D1D; ++b) {
+          dx0 += tb.B[qy][b] * AB[0][b];
+          dx1 += tb.B[qy][b] * AB[1][b];
+        }
+        cl -= cf[NQD - 2] * dx0 + cf[NQD - 1] * dx1;
+      }
+      const T mv0 = mq * dkv[0], mv1 = mq * dkv[1];
+#pragma unroll
+      for (int b = 0; b < D1D; ++b) {
+        const T By = tb.B[qy][b], Gy = tb.G[qy][b];
+        T0[0][b] += By * dS[0][0];
+        T0[1][b] += By * dS[1][0];
+        T1[0][b] += Gy * dS[0][1] + By * mv0;
+        T1[1][b] += Gy * dS[1][1] + By * mv1;
+      }
+#pragma unroll
+      for (int bl = 0; bl < L1D; ++bl) TL[bl] += tb.BL[qy][bl] * cl;
+    };
+    // two coefficient buffers: the loads of one row are in flight during the other's arithmetic
+    T ca[NQD], cb[NQD];
+#pragma unroll
+    for (int f = 0; f < NQD; ++f) ca[f] = ld32(qf[f], (uint32_t)lane);
+#pragma unroll 1
+    for (int qy = 0; qy < Q1D; qy += 2) {
+#pragma unroll
+      for (int f = 0; f < NQD; ++f) cb[f] = ld32(qf[f], (uint32_t)((qy + 1) * 64 + lane));
+      row(qy, ca);
+      if (qy + 2 < Q1D) {
+#pragma unroll
+        for (int f = 0; f < NQD; ++f) ca[f] = ld32(qf[f], (uint32_t)((qy + 2) * 64 + lane));
+      }
+      row(qy + 1, cb);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < D1D; ++b)
+#pragma unroll
+        for (int a = 0; a < D1D; ++a) sO[lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
+#pragma unroll
+    for (int bl = 0; bl < L1D; ++bl)
+#pragma unroll
+      for (int al = 0; al < L1D; ++al) sO[lane][2 * D1D * D1D + bl * L1D + al] = BLq[al] * TL[bl];
+  } else {
+    for (int t = 0; t < NOUT; ++t) sO[lane][t] = T(0);
+  }
+  __syncthreads();
+  // combine the Q1D column contributions of each element and scatter (atomics: shared nodes)
+  if (active) {
+    const int ex = ex0 + z;
+    const uint32_t e = ebase + z;
+    for (int t = qx; t < NOUT; t += Q1D) {
+      T o = 0;
+#pragma unroll
+      for (int q = 0; q < Q1D; ++q) o += sO[z * Q1D + q][t];
+      if (t < 2 * D1D * D1D) {
+        const int c = t / (D1D * D1D), r = t % (D1D * D1D), b = r / D1D, a = r % D1D;
+        const uint32_t I = K * ex + a, J = K * ey + b;
+        const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
+        if (!cons) unsafeAtomicAdd(&out[nh1 + c * N + J * ng0 + I], o);
+      } else {
+        out[2 * nh1 + e * NLD + (t - 2 * D1D * D1D)] = o;
+      }
+    }
+  }
+  // position rows (dk_x - tau dk_v) and constrained velocity rows (dk_v), by node owner
+  for (int i = lane; i < 2 * D1D * NS; i += 64) {
+    const int s = i % NS, t = i / NS, b = t % D1D, c = t / D1D;
+    if (s >= ns || !((s < K * E || last_x) && (b < K || last_y))) continue;
+    const uint32_t I = K * ex0 + s, J = K * ey + b;
+    const uint32_t gi = c * N + row0 + (uint32_t)b * ng0 + s;
+    const T dkv = sS[2 + c][b][s];
+    out[gi] = sS[c][b][s] - tau * dkv;
+    const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
+    if (cons) unsafeAtomicAdd(&out[nh1 + gi], dkv);
+  }
+}
+
+// ---- host side ---------------------------------------------------------------------------
+template <typename T, int D1D, int Q1D>
+static Tab2<T, D1D, Q1D> make_tab2(const ilh_ctx* c) {
+  Tab2<T, D1D, Q1D> tb;
+  for (int q = 0; q < Q1D; ++q) {
+    for (int d = 0; d < D1D; ++d) {
+      tb.B[q][d] = T(c->h_B[q * D1D + d]);
+      tb.G[q][d] = T(c->h_G[q * D1D + d]);
+    }
+    for (int d = 0; d < D1D - 1; ++d) tb.BL[q][d] = T(c->h_BL[q * (D1D - 1) + d]);
+    tb.W[q] = T(c->h_w1[q]);
+  }
+  return tb;
+}
+
+// 32-bit element offsets into the block vectors (byte offsets below 4 GiB in FP64)
+static bool lin2d_supported(const ilh_ctx* c) {
+  return c->dim == 2 && (c->k == 2 || c->k == 3) && c->nblock < (int64_t(1) << 29);
+}
+
+static dim3 lin2d_grid(const ilh_ctx* c) {
+  const int Q1D = 2 * c->k, EPW = 64 / Q1D;
+  return dim3((c->n[0] + EPW - 1) / EPW, c->n[1]);
+}
+
+int lin2d_nqd(const ilh_ctx* c) { return (c->kp.visc ? 16 : 10) + (c->kp.tg_source ? 2 : 0); }
+
+int64_t lin2d_stride(const ilh_ctx* c) {
+  const dim3 g = lin2d_grid(c);
+  return (int64_t)g.x * g.y * (2 * c->k) * 64;
+}
+
+template <int K, typename T, int VISC, int SRC>
+static void lin_t(ilh_ctx* c, T* qd) {
+  constexpr int D1D = K + 1, Q1D = 2 * K;
+  klaunch(c, k_lin2d<D1D, Q1D, T, VISC, SRC>, lin2d_grid(c), dim3(64), 0, c->kp, make_tab2<double, D1D, Q1D>(c),
+          (const double*)c->w64, c->lin_tau, qd, lin2d_stride(c));
+}
+
+template <int K, typename T, int VISC, int SRC>
+static void apply_t(ilh_ctx* c, const T* dk, const T* qd, T* out) {
+  constexpr int D1D = K + 1, Q1D = 2 * K;
+  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC>, lin2d_grid(c), dim3(64), 0, c->kp, make_tab2<T, D1D, Q1D>(c), dk,
+          qd, lin2d_stride(c), c->lin_tau, out);
+}
+
+template <typename T>
+static int dispatch_lin(ilh_ctx* c, T* qd) {
+  const int v = c->kp.visc ? 1 : 0, s = c->kp.tg_source ? 1 : 0, code = 4 * c->k + 2 * v + s;
+  switch (code) {
+    case 8: lin_t<2, T, 0, 0>(c, qd); break;
+    case 9: lin_t<2, T, 0, 1>(c, qd); break;
+    case 10: lin_t<2, T, 1, 0>(c, qd); break;
+    case 11: lin_t<2, T, 1, 1>(c, qd); break;
+    case 12: lin_t<3, T, 0, 0>(c, qd); break;
+    case 13: lin_t<3, T, 0, 1>(c, qd); break;
+    case 14: lin_t<3, T, 1, 0>(c, qd); break;
+    case 15: lin_t<3, T, 1, 1>(c, qd); break;
+    default: return ILH_EINVAL;
+  }
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+template <typename T>
+static int dispatch_apply(ilh_ctx* c, const T* dk, const T* qd, T* out) {
+  const int v = c->kp.visc ? 1 : 0, s = c->kp.tg_source ? 1 : 0, code = 4 * c->k + 2 * v + s;
+  switch (code) {
+    case 8: apply_t<2, T, 0, 0>(c, dk, qd, out); break;
+    case 9: apply_t<2, T, 0, 1>(c, dk, qd, out); break;
+    case 10: apply_t<2, T, 1, 0>(c, dk, qd, out); break;
+    case 11: apply_t<2, T, 1, 1>(c, dk, qd, out); break;
+    case 12: apply_t<3, T, 0, 0>(c, dk, qd, out); break;
+    case 13: apply_t<3, T, 0, 1>(c, dk, qd, out); break;
+    case 14: apply_t<3, T, 1, 0>(c, dk, qd, out); break;
+    case 15: apply_t<3, T, 1, 1>(c, dk, qd, out); break;
+    default: return ILH_EINVAL;
+  }
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// Linearisation of precision prec at the current point (w64, lin_tau); the buffer is
+// allocated on first use.  ILH_EINVAL when no linearised kernel exists for this context.
+int launch_lin2d(ilh_ctx* c, int prec) {
+  if (!lin2d_supported(c)) return ILH_EINVAL;
+  const int p = prec == 64 ? 1 : 0;
+  const int64_t len = (int64_t)lin2d_nqd(c) * lin2d_stride(c) * (p ? 8 : 4);
+  if (!c->qd[p]) ILH_HIP(c, hipMalloc(&c->qd[p], len));
+  return p ? dispatch_lin<double>(c, (double*)c->qd[p]) : dispatch_lin<float>(c, (float*)c->qd[p]);
+}
+
+int launch_jvp2d_q(ilh_ctx* c, int prec, const void* dk, void* out) {
+  if (!lin2d_supported(c)) return ILH_EINVAL;
+  const int p = prec == 64 ? 1 : 0;
+  if (!c->qd[p]) return fail(c, ILH_EINVAL, "linearised Jacobian action before its linearisation");
+  return p ? dispatch_apply<double>(c, (const double*)dk, (const double*)c->qd[p], (double*)out)
+           : dispatch_apply<float>(c, (const float*)dk, (const float*)c->qd[p], (float*)out);
+}
+
+bool lin2d_available(const ilh_ctx* c) { return lin2d_supported(c); }
+
+}  // namespace ilh

@@ -145,7 +145,7 @@ int tstart(ilh_ctx* c, int cls) {
 }
 
 void tstop(ilh_ctx* c, int slot) {
-  if (slot >= 0) hipEventRecord(c->tev[2 * slot + 1], c->stream);
+  if (slot >= 0) (void)hipEventRecord(c->tev[2 * slot + 1], c->stream);
 }
 
 int tstart_k(ilh_ctx* c, int cls) {
@@ -161,8 +161,8 @@ int tstart_k(ilh_ctx* c, int cls) {
 void tstop_k(ilh_ctx* c, int slot) {
   if (slot < 0) return;
   if (c->xev0) {
-    hipEventRecord(c->xev0, c->stream);
-    hipEventRecord(c->xev1, c->stream);
+    (void)hipEventRecord(c->xev0, c->stream);
+    (void)hipEventRecord(c->xev1, c->stream);
     c->xev0 = c->xev1 = nullptr;
   }
 }
@@ -177,8 +177,8 @@ static int dalloc(ilh_ctx* c, T** p, size_t count) {
 
 static int ensure_solver_ws(ilh_ctx* c, int m) {
   if (c->kry && c->kry_m >= m) return ILH_OK;
-  if (c->kry) hipFree(c->kry);
-  if (c->kry32) hipFree(c->kry32);
+  if (c->kry) (void)hipFree(c->kry);
+  if (c->kry32) (void)hipFree(c->kry32);
   c->kry = nullptr;
   c->kry32 = nullptr;
   int st;
@@ -265,10 +265,12 @@ void ilh_destroy(ilh_ctx* c) {
   void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
                   c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev};
   for (void* p : ptrs)
-    if (p) hipFree(p);
-  for (hipEvent_t e : c->tev) hipEventDestroy(e);
-  if (c->red_host) hipHostFree(c->red_host);
-  if (c->hhost) hipHostFree(c->hhost);
+    if (p) (void)hipFree(p);
+  for (void* p : c->qd)
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  if (c->red_host) (void)hipHostFree(c->red_host);
+  if (c->hhost) (void)hipHostFree(c->hhost);
   delete c;
 }
 
@@ -590,35 +592,51 @@ int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
   if (!c || !k || !u) return ILH_EINVAL;
   int st;
   if ((st = launch_waxpy(c, c->w64, u, tau, k, c->nblock))) return st;
-  if ((st = launch_cast_d2f(c, c->w32, c->w64, c->nblock))) return st;
   c->lin_tau = tau;
-  return ILH_OK;
+  c->qd_ok[0] = c->qd_ok[1] = false;
+  if (c->jvp_variant == 0 && lin2d_available(c)) return ILH_OK;  // the linearised kernels read w64 only
+  return launch_cast_d2f(c, c->w32, c->w64, c->nblock);
 }
 
 int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
   if (!c || !dk || !jdk) return ILH_EINVAL;
+  if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
   int st;
   if (prec == 64) {
-    double* o = (double*)jdk;
-    if ((st = launch_fill(c, o + c->nh1, 0.0, c->nh1))) return st;
-    EArgs<double> a{c->w64, c->w64 + c->nh1, c->w64 + 2 * c->nh1, nullptr, (const double*)dk, c->lin_tau, o, nullptr};
+    if ((st = launch_fill(c, (double*)jdk + c->nh1, 0.0, c->nh1))) return st;
+  } else {
+    if ((st = launch_fillf(c, (float*)jdk + c->nh1, 0.0f, c->nh1))) return st;
+  }
+  if (c->jvp_variant == 0 && lin2d_available(c)) {
+    const int p = prec == 64 ? 1 : 0;
+    if (!c->qd_ok[p]) {
+      const int ls = tstart_k(c, 5);
+      st = launch_lin2d(c, prec);
+      tstop_k(c, ls);
+      if (st) return st;
+      c->qd_ok[p] = true;
+    }
     const int slot = tstart_k(c, 0);
-    st = c->generic_jvp ? ILH_EINVAL : launch_jvp2d(c, 64, &a, nullptr);
+    st = launch_jvp2d_q(c, prec, dk, jdk);
+    tstop_k(c, slot);
+    return st;
+  }
+  if (prec == 64) {
+    EArgs<double> a{c->w64, c->w64 + c->nh1, c->w64 + 2 * c->nh1, nullptr, (const double*)dk, c->lin_tau,
+                    (double*)jdk, nullptr};
+    const int slot = tstart_k(c, 0);
+    st = c->jvp_variant == 1 ? ILH_EINVAL : launch_jvp2d(c, 64, &a, nullptr);
     if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 64, &a, nullptr);
     tstop_k(c, slot);
     return st;
   }
-  if (prec == 32) {
-    float* o = (float*)jdk;
-    if ((st = launch_fillf(c, o + c->nh1, 0.0f, c->nh1))) return st;
-    EArgs<float> a{c->w64, c->w32 + c->nh1, c->w32 + 2 * c->nh1, nullptr, (const float*)dk, c->lin_tau, o, nullptr};
-    const int slot = tstart_k(c, 0);
-    st = c->generic_jvp ? ILH_EINVAL : launch_jvp2d(c, 32, nullptr, &a);
-    if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 32, nullptr, &a);
-    tstop_k(c, slot);
-    return st;
-  }
-  return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+  EArgs<float> a{c->w64, c->w32 + c->nh1, c->w32 + 2 * c->nh1, nullptr, (const float*)dk, c->lin_tau,
+                 (float*)jdk, nullptr};
+  const int slot = tstart_k(c, 0);
+  st = c->jvp_variant == 1 ? ILH_EINVAL : launch_jvp2d(c, 32, nullptr, &a);
+  if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 32, nullptr, &a);
+  tstop_k(c, slot);
+  return st;
 }
 
 int ilh_jvp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, const void* dk, void* jdk) {
@@ -989,9 +1007,16 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
 
 extern "C" {
 
-int ilh_set_kernel_variant(ilh_ctx* c, int generic) {
+int ilh_set_kernel_variant(ilh_ctx* c, int variant) {
   if (!c) return ILH_EINVAL;
-  c->generic_jvp = generic != 0;
+  if (variant < 0 || variant > 2) return fail(c, ILH_EINVAL, "kernel variant must be 0, 1 or 2");
+  if (variant != c->jvp_variant) c->qd_ok[0] = c->qd_ok[1] = false;
+  // the recompute kernels read the FP32 shadow of w, which the linearised variant does not keep
+  if (variant != 0 && c->w64) {
+    const int st = launch_cast_d2f(c, c->w32, c->w64, c->nblock);
+    if (st) return st;
+  }
+  c->jvp_variant = variant;
   return ILH_OK;
 }
 
