@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # reported as null.
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_pointwise.h",
                    "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": "174974a5a12198e6d69ad873f06db4213aa6867051e2bb7e4e6f66aeb7ba3f53",
+TRAFFIC_RECORD = {"sha256": "1ff6f9be970798e683e7ec6501e655a38bc10adbd3914fb566ef8652a9c66ae3",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 18786.48, "fetch_scale": 262144.0 / 131079.60,
+                  "fetch_kib": 18786.12, "fetch_scale": 262144.0 / 131079.52,
                   "write_kib": 6771.94, "write_scale": 262144.0 / 262144.0}
 
 
@@ -82,6 +82,8 @@ def parse():
                          "times: the byte calibration for HBM traffic counters")
     ap.add_argument("--roofline-shape", type=int, default=1024,
                     help="also time the JVP on an n x n Q3Q2 state of this size (0 = off)")
+    ap.add_argument("--roofline-shape-3d", type=int, default=128,
+                    help="also time the JVP on an n^3 Q2Q1 3D Taylor-Green state of this size (0 = off)")
     return ap.parse_args()
 
 
@@ -200,6 +202,17 @@ def main():
     value = H.nqp * jvp_n / (1e-3 * (jvp_ms + lin_ms))
     bytes32 = jvp_bytes(H, 32, args.jvp_variant)
     achieved = bytes32 / jvp_avg_s / 1e9
+    # the same kernel back to back at the last linearisation point (no other kernels between)
+    dkb = torch.randn(H.nblock, device=u.device, dtype=torch.float32,
+                      generator=torch.Generator(device=u.device).manual_seed(7))
+    outb = torch.empty_like(dkb)
+    H.jvp_lin(dkb, 32, outb)
+    H.timing(True)
+    for _ in range(50):
+        H.jvp_lin(dkb, 32, outb)
+    tb_ = H.timing_read()
+    H.timing(False)
+    burst_us = 1e3 * tb_["jvp"][0] / max(tb_["jvp"][1], 1)
     u32 = u.clone()
     newton = [s["newton"] for s in stats]
     gmres = [s["gmres"] for s in stats]
@@ -261,7 +274,49 @@ def main():
             lavg = 1e-3 * tr["linearize"][0] / tr["linearize"][1]
             roof_extra["linearize"] = {"avg_launch_us": 1e6 * lavg, "bytes_per_launch": lin_bytes(HR, 32),
                                        "achieved_GBs": lin_bytes(HR, 32) / lavg / 1e9}
-        del HR
+        # FP64 action at the same shape
+        out64 = torch.empty_like(dk)
+        for _ in range(3):
+            HR.jvp_lin(dk, 64, out64)
+        HR.timing(True)
+        for _ in range(10):
+            HR.jvp_lin(dk, 64, out64)
+        t64 = HR.timing_read()
+        HR.timing(False)
+        a64 = 1e-3 * t64["jvp"][0] / t64["jvp"][1]
+        b64 = jvp_bytes(HR, 64, args.jvp_variant)
+        roof_extra["fp64"] = {"avg_launch_us": 1e6 * a64, "jvp_qps": HR.nqp / a64, "bytes_per_launch": b64,
+                              "achieved_GBs": b64 / a64 / 1e9, "frac": b64 / a64 / 1e9 / HBM_PEAK_GBS}
+        del HR, uR, kR, dk, dk32, out32, out64
+        torch.cuda.empty_cache()
+
+    roof_3d = None
+    if args.roofline_shape_3d:
+        m = args.roofline_shape_3d
+        H3 = ilh.Hydro("tg3d", (m, m, m), 2)
+        H3.set_kernel_variant(args.jvp_variant)
+        u3 = H3.init_state()
+        u3[:H3.nh1] += 0.05 * u3[H3.nh1:2 * H3.nh1]
+        k3 = torch.zeros_like(u3)
+        H3.linearize(k3, u3, 0.5 * H3.dt_estimate(u3, 2.0))
+        d3 = torch.randn(H3.nblock, device=u3.device, dtype=torch.float32,
+                         generator=torch.Generator(device=u3.device).manual_seed(5))
+        o3 = torch.empty_like(d3)
+        for _ in range(2):
+            H3.jvp_lin(d3, 32, o3)
+        H3.timing(True)
+        for _ in range(10):
+            H3.jvp_lin(d3, 32, o3)
+        t3 = H3.timing_read()
+        H3.timing(False)
+        a3 = 1e-3 * t3["jvp"][0] / t3["jvp"][1]
+        kind = "lin" if t3["linearize"][1] else "generic"
+        b3 = jvp_bytes(H3, 32, kind)
+        roof_3d = {"shape": "%d^3 Q2Q1 3D TG (displaced)" % m, "n_qp": H3.nqp, "kernel_variant": kind,
+                   "avg_launch_us": 1e6 * a3, "jvp_qps": H3.nqp / a3, "bytes_per_launch": b3,
+                   "achieved_GBs": b3 / a3 / 1e9, "frac": b3 / a3 / 1e9 / HBM_PEAK_GBS}
+        del H3, u3, k3, d3, o3
+        torch.cuda.empty_cache()
 
     learned = None
     if not args.no_learned:
@@ -313,7 +368,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(n, k, args.jvp_variant),
                      "kernel": KERNEL_NAMES[args.jvp_variant], "bytes_per_launch": bytes32,
-                     "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n},
+                     "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n,
+                     "avg_launch_us_back_to_back": burst_us},
         "jvp_variant": args.jvp_variant,
         "jvp_apply_qps": H.nqp / jvp_avg_s,
         "linearize": {"launches": lin_n, "avg_launch_us": 1e3 * lin_ms / max(lin_n, 1),
@@ -333,6 +389,8 @@ def main():
         out["s_per_implicit_step_plain_c5"] = learned["plain"]["s_per_step"]
     if roof_extra:
         out["roofline_large_shape"] = roof_extra
+    if roof_3d:
+        out["roofline_3d"] = roof_3d
     print(json.dumps(out))
 
 

@@ -176,6 +176,12 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
 int multidot_dev(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);
 int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
+// fused versions: w read once per 8 basis vectors; the axpy also returns |w|^2
+int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);
+int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign,
+                  int64_t n, double* d_nrm2);
+int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n);
+int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);
 int l1_error_host(ilh_ctx* c, const double* u, double* out);

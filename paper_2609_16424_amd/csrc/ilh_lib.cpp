@@ -762,9 +762,18 @@ struct Solver {
     return st;
   }
 
+  const double* z32_of = nullptr;  // the vector whose FP32 copy is in kry32 (written by precond)
+
   int precond_body(const double* r, double* z) {
     const int64_t nh1 = c->nh1;
     int st;
+    z32_of = nullptr;
+    if (o->pcg_iters <= 0) {
+      float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
+      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled))) return st;
+      if (z32) z32_of = z;
+      return ILH_OK;
+    }
     ILH_HIP(c, hipMemcpyAsync(z, r, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (o->pcg_iters > 0) {
       if ((st = pcg_mass_v(c, r + nh1, z + nh1, 0.0, o->pcg_iters, 0, nullptr, nullptr))) return st;
@@ -783,7 +792,10 @@ struct Solver {
     if (o->jvp_prec == 32) {
       float* x32 = c->kry32;
       float* y32 = c->kry32 + c->nblock;
-      if ((st = launch_cast_d2f(c, x32, x, c->nblock))) return st;
+      // the preconditioner leaves the FP32 copy of its output in x32; it is used once
+      const bool have32 = (x == z32_of);
+      z32_of = nullptr;
+      if (!have32 && (st = launch_cast_d2f(c, x32, x, c->nblock))) return st;
       if ((st = ilh_jvp_lin(c, 32, x32, y32))) return st;
       return launch_cast_f2d(c, y, y32, c->nblock);
     }
@@ -825,23 +837,19 @@ struct Solver {
         if ((st = apply(Zj, w))) return st;
         // classical Gram-Schmidt, twice
         const int slot = tstart(c, 3);
-        if ((st = multidot_dev(c, V, n, j + 1, w, n, hd))) return st;
+        if ((st = multidot_fused(c, V, n, j + 1, w, n, hd))) return st;
         if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd, -1.0, n))) return st;
-        if ((st = multidot_dev(c, V, n, j + 1, w, n, hd + 72))) return st;
-        if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd + 72, -1.0, n))) return st;
-        if ((st = dot_dev(c, w, w, n, hd + 144))) return st;
+        if ((st = multidot_fused(c, V, n, j + 1, w, n, hd + 72))) return st;
+        if ((st = multiaxpy_nrm(c, w, V, n, j + 1, hd + 72, -1.0, n, hd + 144))) return st;
         tstop(c, slot);
+        // normalise on the device (no-op for a zero or non-finite norm), then fetch the scalars
+        if ((st = launch_scale_by_norm(c, w, w, hd + 144, n))) return st;
         ILH_HIP(c, hipMemcpyAsync(c->hhost, hd, 145 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         ILH_HIP(c, hipStreamSynchronize(c->stream));
         for (int i = 0; i <= j; ++i) H[i * m + j] = c->hhost[i] + c->hhost[72 + i];
         const double hn = std::sqrt(std::max(c->hhost[144], 0.0));
         if (!std::isfinite(hn)) return fail(c, ILH_ENONFINITE, "non-finite Krylov vector");
         H[(j + 1) * m + j] = hn;
-        if (hn > 0) {
-          c->hhost[150] = hn;
-          ILH_HIP(c, hipMemcpyAsync(hd + 150, &c->hhost[150], sizeof(double), hipMemcpyHostToDevice, c->stream));
-          hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, w, w, hd, 150, n);
-        }
         for (int i = 0; i < j; ++i) {
           const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
           H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];

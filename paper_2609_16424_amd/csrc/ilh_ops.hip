@@ -200,6 +200,126 @@ int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, co
   return ILH_OK;
 }
 
+// ------------------------------------------------------------------ fused Krylov kernels
+// Partial sums per block, then one small kernel adds them in a fixed order (deterministic).
+// A single-launch variant with a last-block arrival counter was measured slower: the
+// device-scope release fence it needs writes back each XCD's L2 once per block.
+static constexpr int MDOT_JC = 8;  // basis vectors per pass over w
+
+// part[j][b] = block b's share of V_j . w, j < m (w read once per MDOT_JC vectors)
+__global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V, int64_t ldv, int m,
+                                                    const double* __restrict__ w, int64_t n, double* part) {
+  const int nb = gridDim.x;
+  for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
+    const int jn = min(MDOT_JC, m - j0);
+    double acc[MDOT_JC];
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj) acc[jj] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)nb * TPB) {
+      const double wi = w[i];
+#pragma unroll
+      for (int jj = 0; jj < MDOT_JC; ++jj)
+        if (jj < jn) acc[jj] += V[(int64_t)(j0 + jj) * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj) {
+      if (jj < jn) {
+        const double t = block_sum<TPB>(acc[jj]);
+        if (threadIdx.x == 0) part[(int64_t)(j0 + jj) * nb + blockIdx.x] = t;
+      }
+    }
+  }
+}
+
+// w += sign sum_j h[j] V_j; part[b] = block b's share of |w|^2 of the result
+__global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(double* __restrict__ w, const double* __restrict__ V,
+                                                        int64_t ldv, int m, const double* __restrict__ h,
+                                                        double sign, int64_t n, double* part) {
+  double ss = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += h[j] * V[(int64_t)j * ldv + i];
+    const double wn = w[i] + sign * acc;
+    w[i] = wn;
+    ss += wn * wn;
+  }
+  ss = block_sum<TPB>(ss);
+  if (threadIdx.x == 0) part[blockIdx.x] = ss;
+}
+
+static int fused_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4 * TPB - 1) / (4 * TPB)));
+}
+
+int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out) {
+  if (m <= 0) return ILH_OK;
+  if (m > 64) return fail(c, ILH_EINVAL, "multidot: at most 64 vectors");
+  const int nb = fused_blocks(n);
+  hipLaunchKernelGGL(k_mdot_part8, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red);
+  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign,
+                  int64_t n, double* d_nrm2) {
+  const int nb = fused_blocks(n);
+  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, h, sign, n, c->red);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, d_nrm2, 0);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// y = x / sqrt(*nrm2) when the norm is positive (the next Arnoldi vector)
+__global__ void k_scale_by_norm(double* y, const double* x, const double* nrm2, int64_t n) {
+  const double s = sqrt(fmax(*nrm2, 0.0));
+  if (!(s > 0.0)) return;
+  const double f = 1.0 / s;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i] * f;
+}
+
+int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n) {
+  hipLaunchKernelGGL(k_scale_by_norm, dim3(nblk(n, 4096)), dim3(TPB), 0, c->stream, y, x, d_nrm2, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// Block preconditioner of the Newton-Krylov solve (eq. blockdiag_prec with a Jacobi M_V):
+// z_v = r_v / diag(M_V) (1 on constrained rows), z_x = r_x + tau z_v (coupled) or r_x,
+// z_e = M_E^-1 r_e; z32 (nullable) receives the FP32 copy of z.
+__global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
+                          const double* __restrict__ Minv, const double* __restrict__ escale, double* z, float* z32,
+                          double tau, int coupled, int64_t nh1, int64_t Ne, int Nl) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nh1) {
+    const double zv = r[nh1 + i] / Mdiag[i];
+    const double zx = coupled ? tau * zv + r[i] : r[i];
+    z[i] = zx;
+    z[nh1 + i] = zv;
+    if (z32) {
+      z32[i] = (float)zx;
+      z32[nh1 + i] = (float)zv;
+    }
+  } else if (i < nh1 + Ne * Nl) {
+    const int64_t k = i - nh1, e = k / Nl;
+    const int rr = (int)(k % Nl);
+    double acc = 0;
+    for (int j = 0; j < Nl; ++j) acc += Minv[rr * Nl + j] * r[2 * nh1 + e * Nl + j];
+    const double x = escale[e] * acc;
+    z[2 * nh1 + k] = x;
+    if (z32) z32[2 * nh1 + k] = (float)x;
+  }
+}
+
+int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled) {
+  const int64_t n = c->nh1 + c->Ne * c->Nl;
+  hipLaunchKernelGGL(k_precond, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv,
+                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
 // ------------------------------------------------------------------ mass operators
 // y += M_V x (values-only partial assembly).  bc != 0: constrained inputs read as zero and
 // constrained outputs receive x (the eliminated operator Mhat).
