@@ -133,8 +133,8 @@ int ilh_linearize(ilh_ctx* ctx, const double* k, const double* u, double tau);
  * linearised variant applies FP64-evaluated coefficients rounded to FP32; the recomputing
  * variants read positions in FP64 and make them element-relative before rounding).  The first
  * call of a precision after ilh_linearize evaluates and stores that precision's tangent
- * coefficients (linearised variant: 2D, k = 2, 3; 12 to 18 values per quadrature point,
- * allocated on first use and kept until ilh_destroy). */
+ * coefficients (linearised variant: 2D, k = 2, 3, 12 to 18 values per quadrature point;
+ * 3D, k = 2, 20 or 29; allocated on first use and kept until ilh_destroy). */
 int ilh_jvp_lin(ilh_ctx* ctx, int prec, const void* dk, void* jdk);
 
 /* ilh_linearize followed by ilh_jvp_lin. */
@@ -232,7 +232,8 @@ int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double*
  * time in milliseconds and the number of timed launches (host arrays of ILH_TIMING_CLASSES). */
 #define ILH_TIMING_CLASSES 6
 /* Select the Jacobian-action kernels (all compute the same operator, for cross-checking):
- *   0 (default) linearised: where one exists (2D, k = 2, 3), the tangent coefficients of every
+ *   0 (default) linearised: where one exists (2D, k = 2, 3; 3D, k = 2 without the TG source),
+ *     the tangent coefficients of every
  *     quadrature point are evaluated once per linearisation point and precision (FP64
  *     arithmetic, stored in the precision of the action) and each action applies them;
  *   1 generic LDS-staged element kernel recomputing the state's quadrature data;

@@ -160,6 +160,10 @@ int launch_lin2d(ilh_ctx* c, int prec);
 int launch_jvp2d_q(ilh_ctx* c, int prec, const void* dk, void* out);
 int lin2d_nqd(const ilh_ctx* c);
 int64_t lin2d_stride(const ilh_ctx* c);
+// linearised 3D Jacobian action (Q2Q1, no source)
+bool lin3d_available(const ilh_ctx* c);
+int launch_lin3d(ilh_ctx* c, int prec);
+int launch_jvp3d_q(ilh_ctx* c, int prec, const void* dk, void* out);
 int launch_fill(ilh_ctx* c, double* p, double v, int64_t n);
 int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n);
 int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int64_t n);  // y = a x + b y

@@ -2,23 +2,12 @@
 // iterate), split into a linearisation launched once per iterate and an apply launched by
 // every Krylov iteration.
 //
-// At a quadrature point the tangent of (S, s) (Sec. 3.4: forward derivative of the stress
-// kernel) is linear in the direction's (dJ, d(dv/dxi), de), with coefficients that depend on
-// the state w alone.  k_lin2d evaluates those coefficients at w in FP64 and stores them in the
-// working precision; k_jvp2d_q then reads the direction, the stored coefficients and the
+// The tangent of the quadrature-point stress map is linear in the direction with coefficients
+// that depend on the state alone (ilh_lin.h).  k_lin2d evaluates them at w in FP64 and stores
+// them in the working precision (2D: 12 values per point without viscosity and with the TG
+// source, 18 with both); k_jvp2d_q then reads the direction, the stored coefficients and the
 // per-element mass factor only: geometry, inverse Jacobian, equation of state and viscosity
 // of the state are not re-evaluated by each Krylov iteration.
-//
-// With gv = (dv/dxi) J^-1, U = dJ J^-1, dJ^-1 = -J^-1 U and dgv = d(dv/dxi) J^-1 - gv U:
-//   Sig  = -P I  [+ m_q nu eps(gv)],                      P  = (gamma - 1) m_q e+
-//   dSig = -cP de I  [+ dnu eps(gv) + m_q nu eps(dgv)],   cP = P / sqrt(e^2 + eps^2)
-//   dnu  = a0 tr(U) + a1 tr(dgv) + a2 de   (viscosity; m_q folded into a)
-//   dS = dSig J^-T + Sig dJ^-T,   ds = dSig : gv + Sig : dgv,
-//   TG source row: db = m_q grad s(x_q) . dx_q.
-// Stored per point, in this order: J^-1 (4), gv (4); then P, cP without viscosity, or
-// Sig00, Sig01, Sig11, cP, m_q nu, a0, a1, a2 with it; then m_q grad s (2) with the source.
-// Every coefficient after the first eight multiplies the direction exactly once, so the stage
-// factor tau (the direction enters as tau dk) is folded into them at linearisation.
 //
 // Layout of the stored data: field f of lane l at quadrature row qy of work-group b sits at
 // qd[f * qs + (b * Q1D + qy) * 64 + l] (one 64-lane row per wave and row: coalesced).  Both
@@ -27,137 +16,10 @@
 #include <hip/hip_runtime.h>
 
 #include "ilh_internal.h"
+#include "ilh_lin.h"
 #include "ilh_pointwise.h"
 
 namespace ilh {
-
-template <int VISC, int SRC>
-struct LinLayout {
-  static constexpr int NPT = VISC ? 16 : 10;  // pointwise coefficients
-  static constexpr int NQD = NPT + (SRC ? 2 : 0);
-};
-
-// Coefficients of the stress tangent at one point, FP64 (see the file comment).
-template <int VISC>
-__device__ __forceinline__ void lin_coefs2(const KParams& P, double gam, double mq, double dJ0,
-                                           const double J[2][2], const double Gv[2][2], double e,
-                                           double* c) {
-  double Ji[2][2], det;
-  inv_det<2, double>(J, Ji, det);
-  double gv[2][2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) gv[r][b] = Gv[r][0] * Ji[0][b] + Gv[r][1] * Ji[1][b];
-  double ep, rr;
-  e_plus<double>(e, P.eps_e, ep, rr);
-  const double g1 = gam - 1.0;
-  const double Pq = g1 * mq * ep, cP = Pq / rr;
-  c[0] = Ji[0][0];
-  c[1] = Ji[0][1];
-  c[2] = Ji[1][0];
-  c[3] = Ji[1][1];
-  c[4] = gv[0][0];
-  c[5] = gv[0][1];
-  c[6] = gv[1][0];
-  c[7] = gv[1][1];
-  if constexpr (!VISC) {
-    c[8] = Pq;
-    c[9] = cP;
-  } else {
-    const double div = gv[0][0] + gv[1][1];
-    const double h = P.h0 * sqrt(det / dJ0);
-    const double dv = h * div;
-    const double cs = sqrt(gam * g1 * ep);
-    // derivatives as combinations of (tr U, tr dgv, de)
-    const double dh[3] = {0.5 * h, 0.0, 0.0};
-    const double ddv[3] = {0.5 * h * div, h, 0.0};
-    const double dcs[3] = {0.0, 0.0, cs / (2.0 * rr)};
-    double dsc, ddsc[3];
-    if (P.dsc_mode) {
-      dsc = 2.0 * h * cs * P.hc_inv;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) ddsc[i] = 2.0 * P.hc_inv * (dh[i] * cs + h * dcs[i]);
-    } else {
-      dsc = P.dsc_w;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) ddsc[i] = 0.0;
-    }
-    const double aabs = sqrt(dv * dv + dsc * dsc);
-    const double t = -dv / (2.0 * dsc) - P.psi_shift;
-    const double th = tanh(t);
-    const double psi = 0.5 + 0.5 * th;
-    const double base = P.q2 * aabs + P.q1 * cs * psi;
-    const double mnu = mq * h * base;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double daabs = (dv * ddv[i] + dsc * ddsc[i]) / aabs;
-      const double dt = -(ddv[i] * dsc - dv * ddsc[i]) / (2.0 * dsc * dsc);
-      const double dpsi = 0.5 * (1.0 - th * th) * dt;
-      const double dnu = dh[i] * base + h * (P.q2 * daabs + P.q1 * (dcs[i] * psi + cs * dpsi));
-      c[13 + i] = mq * dnu;
-    }
-    c[8] = -Pq + mnu * gv[0][0];
-    c[9] = mnu * 0.5 * (gv[0][1] + gv[1][0]);
-    c[10] = -Pq + mnu * gv[1][1];
-    c[11] = cP;
-    c[12] = mnu;
-  }
-}
-
-// Apply the stored coefficients to one point's (dJ, dGv, de): dS (2 x 2) and ds.
-template <typename T, int VISC>
-__device__ __forceinline__ void lin_apply2(const T* c, const T dJ[2][2], const T dGv[2][2], T de,
-                                           T dS[2][2], T& ds) {
-  const T Ji[2][2] = {{c[0], c[1]}, {c[2], c[3]}};
-  const T gv[2][2] = {{c[4], c[5]}, {c[6], c[7]}};
-  T U[2][2], dJi[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) U[a][b] = dJ[a][0] * Ji[0][b] + dJ[a][1] * Ji[1][b];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) dJi[a][b] = -(Ji[a][0] * U[0][b] + Ji[a][1] * U[1][b]);
-  if constexpr (!VISC) {
-    const T Pq = c[8], dP = c[9] * de;
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) dS[r][a] = -dP * Ji[a][r] - Pq * dJi[a][r];
-    T trdgv = 0;
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) trdgv += dGv[r][a] * Ji[a][r] - gv[r][a] * U[a][r];
-    ds = -dP * (gv[0][0] + gv[1][1]) - Pq * trdgv;
-  } else {
-    T dgv[2][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        dgv[r][b] = dGv[r][0] * Ji[0][b] + dGv[r][1] * Ji[1][b] - gv[r][0] * U[0][b] - gv[r][1] * U[1][b];
-    const T dnu = c[13] * (U[0][0] + U[1][1]) + c[14] * (dgv[0][0] + dgv[1][1]) + c[15] * de;
-    const T dP = c[11] * de, mnu = c[12];
-    const T Sig[2][2] = {{c[8], c[9]}, {c[9], c[10]}};
-    const T eps01 = T(0.5) * (gv[0][1] + gv[1][0]), deps01 = T(0.5) * (dgv[0][1] + dgv[1][0]);
-    T dSig[2][2];
-    dSig[0][0] = -dP + dnu * gv[0][0] + mnu * dgv[0][0];
-    dSig[1][1] = -dP + dnu * gv[1][1] + mnu * dgv[1][1];
-    dSig[0][1] = dSig[1][0] = dnu * eps01 + mnu * deps01;
-    T dss = 0;
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        dS[r][a] = dSig[r][0] * Ji[a][0] + dSig[r][1] * Ji[a][1] + Sig[r][0] * dJi[a][0] + Sig[r][1] * dJi[a][1];
-        dss += dSig[r][a] * gv[r][a] + Sig[r][a] * dgv[r][a];
-      }
-    ds = dss;
-  }
-}
 
 // ---- linearisation: state w (FP64) -> stored coefficients (T) ----------------------------
 template <int D1D, int Q1D, typename T, int VISC, int SRC>
@@ -167,7 +29,7 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
-  constexpr int NQD = LinLayout<VISC, SRC>::NQD;
+  constexpr int NQD = LinLayout<2, VISC, SRC>::NQD;
 
   __shared__ double sS[4][D1D][NS];  // x0 x1 v0 v1
   __shared__ double sE[EPW * NLD];
@@ -269,7 +131,7 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
     for (int bl = 0; bl < L1D; ++bl) eq += tb.BL[qy][bl] * ALe[bl];
     const double mq = wx * tb.W[qy];
     double cf[NQD];
-    lin_coefs2<VISC>(P, gam, mq, dJ0, J, Gv, eq, cf);
+    lin_coefs<2, VISC>(P, gam, mq, dJ0, J, Gv, eq, cf);
     if constexpr (SRC != 0) {
       double xq0 = 0, xq1 = 0;
 #pragma unroll
@@ -292,24 +154,6 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
 }
 
 // ---- apply: direction dk (T) -> J dk (T) --------------------------------------------------
-// 32-bit element offset from a uniform base (byte offsets below 4 GiB, checked on the host).
-typedef const char __attribute__((address_space(1))) * gbytes;
-template <typename T>
-__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i) {
-  const gbytes p = (gbytes)base + (uint64_t)(i * (uint32_t)sizeof(T));
-  return *(const T __attribute__((address_space(1)))*)p;
-}
-
-// A wave-uniform pointer made opaque to the compiler (scalar registers): loads from it take the
-// scalar-base + 32-bit vector-offset form instead of per-lane 64-bit address arithmetic.
-template <typename T>
-__device__ __forceinline__ const T* sbase(const T* p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
-}
-
 template <int D1D, int Q1D, typename T, int VISC, int SRC>
 __global__ void __launch_bounds__(64) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
                                                 const T* __restrict__ dk, const T* __restrict__ qd,
@@ -317,7 +161,7 @@ __global__ void __launch_bounds__(64) k_jvp2d_q(const KParams P, const Tab2<T, D
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
-  constexpr int NQD = LinLayout<VISC, SRC>::NQD;
+  constexpr int NQD = LinLayout<2, VISC, SRC>::NQD;
   constexpr int NOUT = 2 * D1D * D1D + NLD;  // outputs per element
   constexpr int NOP = NOUT | 1;              // odd LDS row length (bank spread)
   static_assert(Q1D % 2 == 0, "the quadrature rows are processed in pairs");
@@ -449,7 +293,7 @@ __global__ void __launch_bounds__(64) k_jvp2d_q(const KParams P, const Tab2<T, D
       for (int bl = 0; bl < L1D; ++bl) dke += tb.BL[qy][bl] * ALd[bl];
       const T mq = wx * tb.W[qy];
       T dS[2][2], ds;
-      lin_apply2<T, VISC>(cf, dJ, dGv, dke, dS, ds);
+      lin_apply<2, T, VISC>(cf, dJ, dGv, dke, dS, ds);
       T cl = mq * dke - ds;
       if constexpr (SRC != 0) {
         T dx0 = 0, dx1 = 0;

@@ -594,7 +594,7 @@ int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
   if ((st = launch_waxpy(c, c->w64, u, tau, k, c->nblock))) return st;
   c->lin_tau = tau;
   c->qd_ok[0] = c->qd_ok[1] = false;
-  if (c->jvp_variant == 0 && lin2d_available(c)) return ILH_OK;  // the linearised kernels read w64 only
+  if (c->jvp_variant == 0 && (lin2d_available(c) || lin3d_available(c))) return ILH_OK;  // they read w64 only
   return launch_cast_d2f(c, c->w32, c->w64, c->nblock);
 }
 
@@ -607,17 +607,18 @@ int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
   } else {
     if ((st = launch_fillf(c, (float*)jdk + c->nh1, 0.0f, c->nh1))) return st;
   }
-  if (c->jvp_variant == 0 && lin2d_available(c)) {
+  if (c->jvp_variant == 0 && (lin2d_available(c) || lin3d_available(c))) {
+    const bool d3 = c->dim == 3;
     const int p = prec == 64 ? 1 : 0;
     if (!c->qd_ok[p]) {
       const int ls = tstart_k(c, 5);
-      st = launch_lin2d(c, prec);
+      st = d3 ? launch_lin3d(c, prec) : launch_lin2d(c, prec);
       tstop_k(c, ls);
       if (st) return st;
       c->qd_ok[p] = true;
     }
     const int slot = tstart_k(c, 0);
-    st = launch_jvp2d_q(c, prec, dk, jdk);
+    st = d3 ? launch_jvp3d_q(c, prec, dk, jdk) : launch_jvp2d_q(c, prec, dk, jdk);
     tstop_k(c, slot);
     return st;
   }

@@ -1,0 +1,227 @@
+// Linearised Jacobian action of the stage residual: coefficients of the quadrature-point
+// stress tangent (shared by the 2D and 3D kernels).
+//
+// At a quadrature point the tangent of (S, s) (Sec. 3.4: forward derivative of the stress
+// kernel) is linear in the direction's (dJ, d(dv/dxi), de), with coefficients that depend on
+// the state w alone.  With gv = (dv/dxi) J^-1, U = dJ J^-1, dJ^-1 = -J^-1 U and
+// dgv = d(dv/dxi) J^-1 - gv U:
+//   Sig  = -P I  [+ m_q nu eps(gv)],                      P  = (gamma - 1) m_q e+
+//   dSig = -cP de I  [+ dnu eps(gv) + m_q nu eps(dgv)],   cP = P / sqrt(e^2 + eps^2)
+//   dnu  = a0 tr(U) + a1 tr(dgv) + a2 de   (viscosity; m_q folded into a)
+//   dS = dSig J^-T + Sig dJ^-T,   ds = dSig : gv + Sig : dgv,
+//   TG source row: db = m_q grad s(x_q) . dx_q.
+// Every coefficient after J^-1 and gv multiplies the direction exactly once, so the stage
+// factor tau (the direction enters as tau dk) is folded into them at linearisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ilh_internal.h"
+#include "ilh_pointwise.h"
+
+namespace ilh {
+
+// Stored coefficients per point in D dimensions: J^-1 (D^2), gv (D^2); then P, cP without
+// viscosity, or Sig (D(D+1)/2, upper triangle row by row), cP, m_q nu, a0, a1, a2 with it;
+// then m_q grad s (D) with the source.
+template <int D, int VISC, int SRC>
+struct LinLayout {
+  static constexpr int NSYM = D * (D + 1) / 2;
+  static constexpr int BASE = 2 * D * D;
+  static constexpr int NPT = BASE + (VISC ? NSYM + 5 : 2);
+  static constexpr int NQD = NPT + (SRC ? D : 0);
+};
+
+// index of (r, c), r <= c, in the row-by-row upper triangle
+template <int D>
+__device__ __forceinline__ constexpr int sym_idx(int r, int c) {
+  return r <= c ? r * D - r * (r - 1) / 2 + (c - r) : c * D - c * (c - 1) / 2 + (r - c);
+}
+
+// Coefficients of the stress tangent at one point, FP64 (see the file comment).
+template <int D, int VISC>
+__device__ __forceinline__ void lin_coefs(const KParams& P, double gam, double mq, double dJ0,
+                                          const double J[D][D], const double Gv[D][D], double e, double* c) {
+  constexpr int B = 2 * D * D;
+  double Ji[D][D], det;
+  inv_det<D, double>(J, Ji, det);
+  double gv[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      double acc = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc += Gv[r][a] * Ji[a][b];
+      gv[r][b] = acc;
+    }
+  double ep, rr;
+  e_plus<double>(e, P.eps_e, ep, rr);
+  const double g1 = gam - 1.0;
+  const double Pq = g1 * mq * ep, cP = Pq / rr;
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      c[r * D + b] = Ji[r][b];
+      c[D * D + r * D + b] = gv[r][b];
+    }
+  if constexpr (!VISC) {
+    c[B] = Pq;
+    c[B + 1] = cP;
+  } else {
+    constexpr int NSYM = D * (D + 1) / 2;
+    double div = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) div += gv[r][r];
+    const double h = P.h0 * h_scale<D, double>(det / dJ0);
+    const double dv = h * div;
+    const double cs = sqrt(gam * g1 * ep);
+    // derivatives as combinations of (tr U, tr dgv, de)
+    const double dh[3] = {h / D, 0.0, 0.0};
+    const double ddv[3] = {h * div / D, h, 0.0};
+    const double dcs[3] = {0.0, 0.0, cs / (2.0 * rr)};
+    double dsc, ddsc[3];
+    if (P.dsc_mode) {
+      dsc = 2.0 * h * cs * P.hc_inv;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ddsc[i] = 2.0 * P.hc_inv * (dh[i] * cs + h * dcs[i]);
+    } else {
+      dsc = P.dsc_w;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ddsc[i] = 0.0;
+    }
+    const double aabs = sqrt(dv * dv + dsc * dsc);
+    const double t = -dv / (2.0 * dsc) - P.psi_shift;
+    const double th = tanh(t);
+    const double psi = 0.5 + 0.5 * th;
+    const double base = P.q2 * aabs + P.q1 * cs * psi;
+    const double mnu = mq * h * base;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double daabs = (dv * ddv[i] + dsc * ddsc[i]) / aabs;
+      const double dt = -(ddv[i] * dsc - dv * ddsc[i]) / (2.0 * dsc * dsc);
+      const double dpsi = 0.5 * (1.0 - th * th) * dt;
+      const double dnu = dh[i] * base + h * (P.q2 * daabs + P.q1 * (dcs[i] * psi + cs * dpsi));
+      c[B + NSYM + 2 + i] = mq * dnu;
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int q = r; q < D; ++q) c[B + sym_idx<D>(r, q)] = (r == q ? -Pq : 0.0) + mnu * 0.5 * (gv[r][q] + gv[q][r]);
+    c[B + NSYM] = cP;
+    c[B + NSYM + 1] = mnu;
+  }
+}
+
+// Apply the stored coefficients to one point's (dJ, dGv, de): dS (D x D) and ds.
+template <int D, typename T, int VISC>
+__device__ __forceinline__ void lin_apply(const T* c, const T dJ[D][D], const T dGv[D][D], T de, T dS[D][D],
+                                          T& ds) {
+  constexpr int B = 2 * D * D;
+  T Ji[D][D], gv[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      Ji[r][b] = c[r * D + b];
+      gv[r][b] = c[D * D + r * D + b];
+    }
+  T U[D][D], dJi[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T acc = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc += dJ[a][q] * Ji[q][b];
+      U[a][b] = acc;
+    }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T acc = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc += Ji[a][q] * U[q][b];
+      dJi[a][b] = -acc;
+    }
+  if constexpr (!VISC) {
+    const T Pq = c[B], dP = c[B + 1] * de;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int a = 0; a < D; ++a) dS[r][a] = -dP * Ji[a][r] - Pq * dJi[a][r];
+    T trdgv = 0, trgv = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      trgv += gv[r][r];
+#pragma unroll
+      for (int a = 0; a < D; ++a) trdgv += dGv[r][a] * Ji[a][r] - gv[r][a] * U[a][r];
+    }
+    ds = -dP * trgv - Pq * trdgv;
+  } else {
+    constexpr int NSYM = D * (D + 1) / 2;
+    T dgv[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) acc += dGv[r][q] * Ji[q][b] - gv[r][q] * U[q][b];
+        dgv[r][b] = acc;
+      }
+    T trU = 0, trdgv = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      trU += U[r][r];
+      trdgv += dgv[r][r];
+    }
+    const T dnu = c[B + NSYM + 2] * trU + c[B + NSYM + 3] * trdgv + c[B + NSYM + 4] * de;
+    const T dP = c[B + NSYM] * de, mnu = c[B + NSYM + 1];
+    T Sig[D][D], dSig[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        Sig[r][q] = c[B + sym_idx<D>(r, q)];
+        dSig[r][q] = (r == q ? -dP : T(0)) + dnu * (T(0.5) * (gv[r][q] + gv[q][r])) +
+                     mnu * (T(0.5) * (dgv[r][q] + dgv[q][r]));
+      }
+    T dss = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T acc = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) acc += dSig[r][b] * Ji[a][b] + Sig[r][b] * dJi[a][b];
+        dS[r][a] = acc;
+        dss += dSig[r][a] * gv[r][a] + Sig[r][a] * dgv[r][a];
+      }
+    ds = dss;
+  }
+}
+
+// 32-bit element offset from a uniform base (byte offsets below 4 GiB, checked on the host).
+typedef const char __attribute__((address_space(1))) * gbytes;
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i) {
+  const gbytes p = (gbytes)base + (uint64_t)(i * (uint32_t)sizeof(T));
+  return *(const T __attribute__((address_space(1)))*)p;
+}
+
+// A wave-uniform pointer made opaque to the compiler (scalar registers): loads from it take the
+// scalar-base + 32-bit vector-offset form instead of per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ const T* sbase(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
+}  // namespace ilh

@@ -139,9 +139,11 @@ def test_zero_direction_gives_zero():
 @pytest.mark.parametrize("prec,tol", [(64, 1e-13), (32, 5e-6)])
 @pytest.mark.parametrize("prob,n,k,visc", [("tg2d", (23, 7), 3, None), ("tg2d", (17, 4), 2, None),
                                            ("triple", (21, 9), 3, "const"), ("triple", (33, 5), 2, "formula"),
-                                           ("tg2d", (12, 11), 3, "formula")])
+                                           ("tg2d", (12, 11), 3, "formula"), ("tg3d", (9, 5, 4), 2, None),
+                                           ("tg3d", (6, 4, 3), 2, "formula")])
 def test_jvp_variants_agree(prob, n, k, visc, prec, tol):
-    """Linearised (0), generic (1) and register-resident recompute (2) Jacobian-action kernels."""
+    """Linearised (0), generic (1) and register-resident recompute (2) Jacobian-action kernels
+    (variant 2 is the generic kernel in 3D)."""
     O, G = make_pair(prob, n, k, visc)
     u = random_state(O, 21)
     kk = 0.1 * random_dir(O, 22)
