@@ -232,10 +232,10 @@ int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double*
  * time in milliseconds and the number of timed launches (host arrays of ILH_TIMING_CLASSES). */
 #define ILH_TIMING_CLASSES 6
 /* Select the Jacobian-action kernels (all compute the same operator, for cross-checking):
- *   0 (default) linearised: where one exists (2D, k = 2, 3; 3D, k = 2 without the TG source),
- *     the tangent coefficients of every
- *     quadrature point are evaluated once per linearisation point and precision (FP64
- *     arithmetic, stored in the precision of the action) and each action applies them;
+ *   0 (default) linearised: where one exists (2D, k = 2, 3; 3D, k = 2 without the TG
+ *     source), the tangent coefficients of every quadrature point are evaluated once per
+ *     linearisation point and precision (FP64 arithmetic, stored in the precision of the
+ *     action) and each action applies them;
  *   1 generic LDS-staged element kernel recomputing the state's quadrature data;
  *   2 register-resident 2D kernel recomputing the state's quadrature data (2D, k = 2, 3).
  * Other values: ILH_EINVAL. */

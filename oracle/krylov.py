@@ -8,7 +8,9 @@
 * Jacobi preconditioned CG (Sec. 2.2 mass solves), restarted flexible GMRES and inexact
   Newton with a backtracking line search that rejects steps producing a non-positive
   Jacobian determinant (Sec. 3.5, eq. newton_linear).
-* The implicit midpoint rule: k = f(u + dt/2 k), u+ = u + dt k.
+* The implicit midpoint rule: k = f(u + dt/2 k), u+ = u + dt k, and the singly diagonally
+  implicit Runge-Kutta steps SD3 / SD4 of Sec. 4 (each implicit stage is one solve of the
+  same stage residual with tau = gamma dt).
 """
 import numpy as np
 
@@ -206,3 +208,59 @@ def run_midpoint(hyd, u0, dt, steps, opts=None):
         states.append(u.copy())
         allstats.append(st)
     return states, hist_k, allstats
+
+
+# ---- SDIRK steps (Sec. 4: SD2 = implicit midpoint, SD3, SD4) ------------------------------
+
+def sdirk_tableau(scheme):
+    """Butcher tableau (A, b) of the singly diagonally implicit schemes named in Sec. 4.
+
+    sd2: implicit midpoint, one stage with gamma = 1/2.
+    sd3: three-stage, third-order, L-stable SDIRK of Alexander (1977): gamma is the root in
+         (1/6, 1/2) of gamma^3 - 3 gamma^2 + 3/2 gamma - 1/6 = 0, c2 = (1 + gamma)/2, and the
+         last row (stiffly accurate) b1 = -(6 gamma^2 - 16 gamma + 1)/4,
+         b2 = (6 gamma^2 - 20 gamma + 5)/4, b3 = gamma.
+    sd4: three-stage, fourth-order SDIRK of Crouzeix (1975): gamma = 1/2 + cos(pi/18)/sqrt(3),
+         c = (gamma, 1/2, 1 - gamma), a21 = 1/2 - gamma, a31 = 2 gamma, a32 = 1 - 4 gamma,
+         b1 = b3 = 1/(6 (1 - 2 gamma)^2), b2 = 1 - 2 b1.
+    """
+    if scheme == "sd2":
+        return np.array([[0.5]]), np.array([1.0])
+    if scheme == "sd3":
+        roots = np.roots([1.0, -3.0, 1.5, -1.0 / 6.0])
+        g = float([r.real for r in roots if abs(r.imag) < 1e-12 and 1.0 / 6.0 < r.real < 0.5][0])
+        c2 = 0.5 * (1.0 + g)
+        b1 = -(6.0 * g * g - 16.0 * g + 1.0) / 4.0
+        b2 = (6.0 * g * g - 20.0 * g + 5.0) / 4.0
+        A = np.array([[g, 0.0, 0.0], [c2 - g, g, 0.0], [b1, b2, g]])
+        return A, np.array([b1, b2, g])
+    if scheme == "sd4":
+        g = 0.5 + np.cos(np.pi / 18.0) / np.sqrt(3.0)
+        b1 = 1.0 / (6.0 * (1.0 - 2.0 * g) ** 2)
+        A = np.array([[g, 0.0, 0.0], [0.5 - g, g, 0.0], [2.0 * g, 1.0 - 4.0 * g, g]])
+        return A, np.array([b1, 1.0 - 2.0 * b1, b1])
+    raise ValueError(scheme)
+
+
+def sdirk_step(hyd, u, dt, scheme, k_guess=None, opts=None, stats=None):
+    """One SDIRK step: stage i solves k_i = f(u + dt sum_{j<i} a_ij k_j + dt a_ii k_i), i.e.
+    R(k_i; a_ii dt, u + dt sum_{j<i} a_ij k_j) = 0; then u+ = u + dt sum_i b_i k_i.
+
+    Newton starts stage 1 from k_guess (None: the explicit rate at u) and stage i > 1 from
+    k_{i-1}.  Returns (u+, [k_1, ...])."""
+    A, b = sdirk_tableau(scheme)
+    ks = []
+    for i in range(len(b)):
+        ubase = u + dt * sum(A[i, j] * ks[j] for j in range(i)) if i else u.copy()
+        if i:
+            g0 = ks[-1]
+        else:
+            g0 = hyd.rate(u) if k_guess is None else k_guess
+        st = {} if stats is not None else None
+        k = newton_stage(hyd, ubase, A[i, i] * dt, g0, opts, st)
+        if stats is not None:
+            for key, v in st.items():
+                if isinstance(v, (int, float)):
+                    stats[key] = stats.get(key, 0) + v
+        ks.append(k)
+    return u + dt * sum(bi * ki for bi, ki in zip(b, ks)), ks
