@@ -221,6 +221,17 @@ int ilh_implicit_step(ilh_ctx* ctx, double* u, double dt, const double* k_guess,
 int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double* k_guess,
                     double* k_out, const ilh_newton_opts* o, ilh_step_stats* st);
 
+/* One SDIRK step of Sec. 4 (scheme 2 = SD2, the implicit midpoint rule; 3 = SD3, the
+ * three-stage L-stable third-order method of Alexander; 4 = SD4, the three-stage fourth-order
+ * method of Crouzeix).  Stage i solves R(k_i; a_ii dt, u + dt sum_{j<i} a_ij k_j) = 0 by the
+ * same Newton-Krylov stage solve as ilh_stage_solve, from k_guess (NULL: zero) for stage 1
+ * and from k_{i-1} for later stages; then u <- u + dt sum_i b_i k_i.  k_out (nullable)
+ * receives the last stage rate.  st (host) sums the iteration counts over the stages and
+ * keeps the residual history of the last stage.  On failure u is left unchanged.  Stage
+ * storage (4 block vectors) is allocated on first use. */
+int ilh_sdirk_step(ilh_ctx* ctx, double* u, double dt, int scheme, const double* k_guess, double* k_out,
+                   const ilh_newton_opts* o, ilh_step_stats* st);
+
 /* ---- measurement --------------------------------------------------------------------- */
 /* Kernel timing with HIP events recorded on the context stream around each launch of the
  * timed kernel classes: 0 = Jacobian-action element kernel, 1 = residual element kernel,

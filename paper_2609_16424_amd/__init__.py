@@ -274,6 +274,22 @@ class Hydro:
             raise IlhError(code, self.lib.ilh_last_error(self.ctx).decode())
         return k, stats
 
+    SDIRK = {"sd2": 2, "sd3": 3, "sd4": 4}
+
+    def sdirk_step(self, u, dt, scheme="sd3", guess=None, opts=None, raise_on_fail=True):
+        """One SDIRK step (SD2 / SD3 / SD4) in place on u; returns (last stage rate, stats)."""
+        opts = opts or newton_options()
+        k = self.new()
+        st = StepStats()
+        self._stream()
+        g = self._vec(guess, self.nblock, name="guess") if guess is not None else None
+        code = self.lib.ilh_sdirk_step(self.ctx, self._vec(u, self.nblock, name="u"), float(dt),
+                                       self.SDIRK[scheme], g, _ptr(k), C.byref(opts), C.byref(st))
+        stats = _stats(st, code)
+        if code != 0 and raise_on_fail:
+            raise IlhError(code, self.lib.ilh_last_error(self.ctx).decode())
+        return k, stats
+
 
 def _stats(st, code):
     n = min(st.newton_iters, 31)

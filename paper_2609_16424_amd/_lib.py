@@ -70,6 +70,7 @@ SIGNATURES = {
     "ilh_newton_defaults": (None, [C.POINTER(NewtonOpts)]),
     "ilh_implicit_step": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
+    "ilh_sdirk_step": (I, [P, P, D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_timing_enable": (I, [P, I]),
     "ilh_set_kernel_variant": (I, [P, I]),
     "ilh_timing_read": (I, [P, C.POINTER(D), C.POINTER(I64)]),

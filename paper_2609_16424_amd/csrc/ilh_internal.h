@@ -102,6 +102,7 @@ struct ilh_ctx {
   // Krylov / Newton workspace (allocated on first use)
   int kry_m = 0;
   double* kry = nullptr;        // V [(m+1)][nblock], Z [m][nblock]
+  double* sdk = nullptr;        // SDIRK stage rates and stage base [4][nblock] (allocated on first use)
   double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   double* hdev = nullptr;       // [4 * 72] device scalars of the Arnoldi step

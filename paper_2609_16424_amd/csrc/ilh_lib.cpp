@@ -263,7 +263,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
-                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev};
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : c->qd)
@@ -1076,6 +1076,103 @@ int ilh_implicit_step(ilh_ctx* c, double* u, double dt, const double* k_guess, d
   int s2 = launch_axpby(c, u, dt, c->nwt, 1.0, c->nblock);
   if (s2) return s2;
   ILH_HIP(c, hipStreamSynchronize(c->stream));
+  return ILH_OK;
+}
+
+// SDIRK tableaux of Sec. 4 from their published closed forms.  SD2: implicit midpoint.  SD3:
+// Alexander's three-stage, L-stable, third-order method; gamma is the root in (1/6, 1/2) of
+// g^3 - 3 g^2 + 3/2 g - 1/6 (Newton's method from 0.44), c2 = (1 + gamma)/2, last row
+// -(6g^2 - 16g + 1)/4, (6g^2 - 20g + 5)/4, gamma.  SD4: Crouzeix's three-stage fourth-order
+// method; gamma = 1/2 + cos(pi/18)/sqrt(3), rows (gamma), (1/2 - gamma, gamma),
+// (2 gamma, 1 - 4 gamma, gamma), weights b1 = b3 = 1/(6 (1 - 2 gamma)^2), b2 = 1 - 2 b1.
+struct SdirkTab {
+  int s = 0;
+  double a[3][3] = {};
+  double b[3] = {};
+};
+
+static bool sdirk_tab(int scheme, SdirkTab* t) {
+  *t = SdirkTab{};
+  if (scheme == 2) {
+    t->s = 1;
+    t->a[0][0] = 0.5;
+    t->b[0] = 1.0;
+    return true;
+  }
+  if (scheme == 3) {
+    double g = 0.44;
+    for (int i = 0; i < 60; ++i) g -= (((g - 3.0) * g + 1.5) * g - 1.0 / 6.0) / ((3.0 * g - 6.0) * g + 1.5);
+    const double b1 = -(6.0 * g * g - 16.0 * g + 1.0) / 4.0, b2 = (6.0 * g * g - 20.0 * g + 5.0) / 4.0;
+    t->s = 3;
+    t->a[0][0] = t->a[1][1] = t->a[2][2] = g;
+    t->a[1][0] = 0.5 * (1.0 + g) - g;
+    t->a[2][0] = b1;
+    t->a[2][1] = b2;
+    t->b[0] = b1;
+    t->b[1] = b2;
+    t->b[2] = g;
+    return true;
+  }
+  if (scheme == 4) {
+    const double g = 0.5 + std::cos(M_PI / 18.0) / std::sqrt(3.0);
+    const double b1 = 1.0 / (6.0 * (1.0 - 2.0 * g) * (1.0 - 2.0 * g));
+    t->s = 3;
+    t->a[0][0] = t->a[1][1] = t->a[2][2] = g;
+    t->a[1][0] = 0.5 - g;
+    t->a[2][0] = 2.0 * g;
+    t->a[2][1] = 1.0 - 4.0 * g;
+    t->b[0] = t->b[2] = b1;
+    t->b[1] = 1.0 - 2.0 * b1;
+    return true;
+  }
+  return false;
+}
+
+int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k_guess, double* k_out,
+                   const ilh_newton_opts* o, ilh_step_stats* st) {
+  if (!c || !u || !o || !(dt > 0)) return ILH_EINVAL;
+  if (o->restart < 1 || o->gmres_maxit < 1 || o->max_newton < 0 || (o->jvp_prec != 32 && o->jvp_prec != 64))
+    return fail(c, ILH_EINVAL, "bad Newton options");
+  SdirkTab T;
+  if (!sdirk_tab(scheme, &T)) return fail(c, ILH_EINVAL, "scheme must be 2 (SD2), 3 (SD3) or 4 (SD4)");
+  const int64_t n = c->nblock;
+  int rc;
+  if (!c->sdk && (rc = dalloc(c, &c->sdk, 4 * (size_t)n))) return rc;
+  double* ub = c->sdk + 3 * n;
+  ilh_step_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  for (int i = 0; i < T.s; ++i) {
+    double* ki = c->sdk + (int64_t)i * n;
+    // stage base u + dt sum_{j<i} a_ij k_j
+    ILH_HIP(c, hipMemcpyAsync(ub, u, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    for (int j = 0; j < i; ++j)
+      if ((rc = launch_axpby(c, ub, dt * T.a[i][j], c->sdk + (int64_t)j * n, 1.0, n))) return rc;
+    const double* guess = i ? c->sdk + (int64_t)(i - 1) * n : k_guess;
+    ilh_step_stats sst;
+    std::memset(&sst, 0, sizeof(sst));
+    const int status = stage_solve(c, ub, T.a[i][i] * dt, guess, ki, o, &sst);
+    acc.newton_iters += sst.newton_iters;
+    acc.gmres_iters += sst.gmres_iters;
+    acc.jvp_calls += sst.jvp_calls;
+    acc.halvings += sst.halvings;
+    acc.guess_rejected += sst.guess_rejected;
+    acc.res0 = sst.res0;
+    acc.res_init = sst.res_init;
+    acc.res_final = sst.res_final;
+    std::memcpy(acc.res_hist, sst.res_hist, sizeof(acc.res_hist));
+    acc.status = status;
+    if (status != ILH_OK) {
+      if (st) *st = acc;
+      return status;  // u unchanged
+    }
+  }
+  for (int i = 0; i < T.s; ++i)
+    if ((rc = launch_axpby(c, u, dt * T.b[i], c->sdk + (int64_t)i * n, 1.0, n))) return rc;
+  if (k_out)
+    ILH_HIP(c, hipMemcpyAsync(k_out, c->sdk + (int64_t)(T.s - 1) * n, n * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  if (st) *st = acc;
   return ILH_OK;
 }
 

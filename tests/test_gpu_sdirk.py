@@ -1,0 +1,90 @@
+"""SDIRK steps on the GPU (ilh_sdirk_step: SD2 / SD3 / SD4 of Sec. 4) against the oracle's
+steps and against the paper's Table tab_TG_rates (Q3Q2 + SD3, Q4Q3 + SD4)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2609_16424_amd as ilh
+from gpu_common import make_pair, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "tg_table_sdirk.txt")
+
+
+def _table():
+    rows = []
+    for line in open(GOLD):
+        if line.strip() and not line.startswith("#"):
+            h, n, k, scheme, cfl, err, steps = line.split()
+            rows.append((int(n), int(k), scheme, float(cfl), float(err), int(steps)))
+    return rows
+
+
+@pytest.mark.parametrize("prob,n,k,scheme,steps,cfl", [("tg2d", (4, 4), 3, "sd3", 3, 2.0),
+                                                       ("tg2d", (3, 3), 2, "sd4", 3, 0.5),
+                                                       ("tg2d", (3, 2), 2, "sd2", 3, 2.0)])
+def test_sdirk_trajectory_matches_oracle(prob, n, k, scheme, steps, cfl):
+    from oracle import krylov
+    O, G = make_pair(prob, n, k)
+    u = O.init_state()
+    dt = O.dt_estimate(u, cfl)
+    ug = to_dev(u)
+    ko, kg = O.rate(u), G.rate(ug)
+    opts = ilh.newton_options(tol=1e-12, jvp_prec=64)
+    oopts = krylov.NewtonOptions()
+    oopts.tol = 1e-12
+    for _ in range(steps):
+        u, ks = krylov.sdirk_step(O, u, dt, scheme, ko, oopts)
+        ko = ks[-1]
+        kg, st = G.sdirk_step(ug, dt, scheme, guess=kg, opts=opts)
+        assert st["status"] == 0
+    assert rel(to_np(ug), u) <= 1e-9, rel(to_np(ug), u)
+
+
+def _run(G, scheme, cfl, opts):
+    u = G.init_state()
+    dt0 = G.dt_estimate(u, cfl)
+    t, steps, kg = 0.0, 0, None
+    while t < 0.5 - 1e-12:
+        dt = min(dt0, 0.5 - t)
+        kg, st = G.sdirk_step(u, dt, scheme, guess=kg if kg is not None else G.rate(u), opts=opts)
+        t += dt
+        steps += 1
+    return u, steps
+
+
+@pytest.mark.parametrize("k,scheme,cfl", [(3, "sd3", 0.5), (3, "sd3", 2.0), (4, "sd4", 0.5), (4, "sd4", 2.0)])
+def test_tg_sdirk_table(k, scheme, cfl):
+    """L1 errors and step counts of the table on 4x4, 8x8 and 16x16 meshes (paper rows
+    h = 1/16, 1/32, 1/64), and the convergence rate between the two finer meshes.
+
+    Step counts match exactly with the fixed step ceil-matched to the explicit estimate; the
+    errors are bounded by 6 %: the paper's implicit runs control the step by Newton behaviour,
+    so the steps within a run of the same count may differ from the fixed step (measured
+    ratios 0.976 - 1.054 over the twelve cells, on both sides of 1)."""
+    tol = 0.06
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32)
+    errs = []
+    for n, kk, sc, c, err, steps in _table():
+        if (kk, sc, c) != (k, scheme, cfl):
+            continue
+        G = ilh.Hydro("tg2d", (n, n), k)
+        u, s = _run(G, scheme, cfl, opts)
+        e = G.l1_error(u)
+        errs.append((n, e, err))
+        assert s == steps, (n, s, steps)
+        assert abs(e - err) <= tol * err, (n, e, err)
+    (n1, e1, p1), (n2, e2, p2) = errs[-2:]
+    rate, prate = np.log2(e1 / e2), np.log2(p1 / p2)
+    assert abs(rate - prate) <= 0.15, (rate, prate)
+
+
+def test_sdirk_rejects_unknown_scheme():
+    G = ilh.Hydro("tg2d", (2, 2), 2)
+    u = G.init_state()
+    code = G.lib.ilh_sdirk_step(G.ctx, G._vec(u, G.nblock, name="u"), 0.01, 5, None, None,
+                                ilh.newton_options(), None)
+    assert code == 1  # EINVAL
