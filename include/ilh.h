@@ -205,6 +205,7 @@ typedef struct {
   double res_init;       /* ||R(k_guess)|| */
   double res_final;      /* ||R(k)|| at exit */
   double res_hist[32];   /* ||R(k^m)|| / res0, m = 0..min(newton_iters, 31) */
+  int newton_max;        /* most Newton iterations of any stage of the step */
 } ilh_step_stats;
 
 void ilh_newton_defaults(ilh_newton_opts* o);
@@ -231,6 +232,22 @@ int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double*
  * storage (4 block vectors) is allocated on first use. */
 int ilh_sdirk_step(ilh_ctx* ctx, double* u, double dt, int scheme, const double* k_guess, double* k_out,
                    const ilh_newton_opts* o, ilh_step_stats* st);
+
+/* One accepted step under the Newton-based step-size control of Sec. 4 ("Implicit time step
+ * control"), with the SDIRK scheme of ilh_sdirk_step.
+ *   dt (host, in/out): in, the proposed step; out, the proposed next step: 1.05 x the accepted
+ *     step when every stage needed at most one Newton iteration, the accepted step otherwise.
+ *   dt_max: upper bound of this step (for instance the time left).
+ *   A trial whose stages need four or more Newton iterations, or whose solve fails, is rejected:
+ *   u is restored and the trial repeats with 85 % of its size, at most max_reject times (then
+ *   the failure status, or ILH_ENOCONV, is returned with u unchanged).
+ *   rejected, dt_taken (host, out, nullable): rejected trials and the accepted step.
+ *   st (host, nullable) describes the accepted trial.
+ * Every trial starts stage 1 from k_guess (NULL: zero).  Uses one more block vector of stage
+ * storage than ilh_sdirk_step. */
+int ilh_adaptive_step(ilh_ctx* ctx, double* u, double* dt, double dt_max, int scheme, const double* k_guess,
+                      double* k_out, const ilh_newton_opts* o, ilh_step_stats* st, int max_reject,
+                      int* rejected, double* dt_taken);
 
 /* ---- measurement --------------------------------------------------------------------- */
 /* Kernel timing with HIP events recorded on the context stream around each launch of the

@@ -264,3 +264,44 @@ def sdirk_step(hyd, u, dt, scheme, k_guess=None, opts=None, stats=None):
                     stats[key] = stats.get(key, 0) + v
         ks.append(k)
     return u + dt * sum(bi * ki for bi, ki in zip(b, ks)), ks
+
+
+# ---- Newton-based step-size control (Sec. 4, "Implicit time step control") ------------------
+
+def adaptive_run(hyd, u0, tf, fscfl, scheme="sd2", opts=None, max_reject=60):
+    """Integrate to tf with the paper's step control: the first step is fscfl times the explicit
+    estimate; after a step whose stages needed at most one Newton iteration each the next step
+    grows by 5 %; two or three keep it; a step needing four or more in some stage (or failing)
+    is rejected and repeated with 85 % of its size.  Newton iterations are counted as updates
+    (the maximum over the stages).  Stage 1 of every step starts from the explicit rate (first
+    step) or the last stage rate of the previous step.  Returns (u, accepted steps, rejected)."""
+    u = u0.copy()
+    dt = hyd.dt_estimate(u, fscfl)
+    t, steps, rejected, kg = 0.0, 0, 0, None
+    while t < tf - 1e-12:
+        dtt = min(dt, tf - t)
+        g = hyd.rate(u) if kg is None else kg
+        st = {}
+        try:
+            A, b = sdirk_tableau(scheme)
+            ks, nmax = [], 0
+            for i in range(len(b)):
+                ubase = u + dtt * sum(A[i, j] * ks[j] for j in range(i)) if i else u
+                sti = {}
+                ks.append(newton_stage(hyd, ubase, A[i, i] * dtt, ks[-1] if i else g, opts, sti))
+                nmax = max(nmax, sti["newton"])
+            ok = nmax < 4
+        except NewtonFailure:
+            ok = False
+        if not ok:
+            rejected += 1
+            if rejected > max_reject:
+                raise NewtonFailure("ENOCONV", "step size control: too many rejections")
+            dt = 0.85 * dtt
+            continue
+        u = u + dtt * sum(bi * ki for bi, ki in zip(b, ks))
+        kg = ks[-1]
+        t += dtt
+        steps += 1
+        dt = 1.05 * dtt if nmax <= 1 else dtt
+    return u, steps, rejected

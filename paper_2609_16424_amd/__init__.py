@@ -290,10 +290,29 @@ class Hydro:
             raise IlhError(code, self.lib.ilh_last_error(self.ctx).decode())
         return k, stats
 
+    def adaptive_step(self, u, dt, dt_max, scheme="sd2", guess=None, opts=None, max_reject=30):
+        """One accepted step of the Newton-based step-size control (in place on u).
+        Returns (last stage rate, stats, accepted step, proposed next step, rejected trials)."""
+        opts = opts or newton_options()
+        k = self.new()
+        st = StepStats()
+        h = C.c_double(float(dt))
+        taken = C.c_double(0.0)
+        nrej = C.c_int(0)
+        self._stream()
+        g = self._vec(guess, self.nblock, name="guess") if guess is not None else None
+        code = self.lib.ilh_adaptive_step(self.ctx, self._vec(u, self.nblock, name="u"), C.byref(h),
+                                          float(dt_max), self.SDIRK[scheme], g, _ptr(k), C.byref(opts),
+                                          C.byref(st), int(max_reject), C.byref(nrej), C.byref(taken))
+        if code != 0:
+            raise IlhError(code, self.lib.ilh_last_error(self.ctx).decode())
+        return k, _stats(st, code), taken.value, h.value, nrej.value
+
 
 def _stats(st, code):
     n = min(st.newton_iters, 31)
-    return dict(status=code, newton=st.newton_iters, gmres=st.gmres_iters, jvp_calls=st.jvp_calls,
+    return dict(status=code, newton=st.newton_iters, newton_max=st.newton_max, gmres=st.gmres_iters,
+                jvp_calls=st.jvp_calls,
                 halvings=st.halvings, guess_rejected=st.guess_rejected, res0=st.res0, res_init=st.res_init, res_final=st.res_final,
                 hist=[st.res_hist[i] for i in range(n + 1)])
 

@@ -35,6 +35,7 @@ class StepStats(C.Structure):
         ("status", C.c_int), ("newton_iters", C.c_int), ("gmres_iters", C.c_int),
         ("jvp_calls", C.c_int), ("halvings", C.c_int), ("guess_rejected", C.c_int), ("res0", C.c_double),
         ("res_init", C.c_double), ("res_final", C.c_double), ("res_hist", C.c_double * 32),
+        ("newton_max", C.c_int),
     ]
 
 
@@ -71,6 +72,8 @@ SIGNATURES = {
     "ilh_implicit_step": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_sdirk_step": (I, [P, P, D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
+    "ilh_adaptive_step": (I, [P, P, C.POINTER(D), D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats), I,
+                              C.POINTER(I), C.POINTER(D)]),
     "ilh_timing_enable": (I, [P, I]),
     "ilh_set_kernel_variant": (I, [P, I]),
     "ilh_timing_read": (I, [P, C.POINTER(D), C.POINTER(I64)]),

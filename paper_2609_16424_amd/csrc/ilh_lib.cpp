@@ -1002,6 +1002,7 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
     std::swap(r, rt);
   }
   stats.newton_iters = it;
+  stats.newton_max = it;
   stats.jvp_calls = S.jvp_calls;
   stats.status = status;
   if (k_out) ILH_HIP(c, hipMemcpyAsync(k_out, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1137,7 +1138,7 @@ int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k
   if (!sdirk_tab(scheme, &T)) return fail(c, ILH_EINVAL, "scheme must be 2 (SD2), 3 (SD3) or 4 (SD4)");
   const int64_t n = c->nblock;
   int rc;
-  if (!c->sdk && (rc = dalloc(c, &c->sdk, 4 * (size_t)n))) return rc;
+  if (!c->sdk && (rc = dalloc(c, &c->sdk, 5 * (size_t)n))) return rc;
   double* ub = c->sdk + 3 * n;
   ilh_step_stats acc;
   std::memset(&acc, 0, sizeof(acc));
@@ -1152,6 +1153,7 @@ int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k
     std::memset(&sst, 0, sizeof(sst));
     const int status = stage_solve(c, ub, T.a[i][i] * dt, guess, ki, o, &sst);
     acc.newton_iters += sst.newton_iters;
+    acc.newton_max = std::max(acc.newton_max, sst.newton_iters);
     acc.gmres_iters += sst.gmres_iters;
     acc.jvp_calls += sst.jvp_calls;
     acc.halvings += sst.halvings;
@@ -1174,6 +1176,46 @@ int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   if (st) *st = acc;
   return ILH_OK;
+}
+
+int ilh_adaptive_step(ilh_ctx* c, double* u, double* dt, double dt_max, int scheme, const double* k_guess,
+                      double* k_out, const ilh_newton_opts* o, ilh_step_stats* st, int max_reject, int* rejected,
+                      double* dt_taken) {
+  if (!c || !u || !dt || !o || !(*dt > 0) || !(dt_max > 0) || max_reject < 0) return ILH_EINVAL;
+  SdirkTab T;
+  if (!sdirk_tab(scheme, &T)) return fail(c, ILH_EINVAL, "scheme must be 2 (SD2), 3 (SD3) or 4 (SD4)");
+  const int64_t n = c->nblock;
+  int rc;
+  if (!c->sdk && (rc = dalloc(c, &c->sdk, 5 * (size_t)n))) return rc;
+  double* backup = c->sdk + 4 * n;
+  ILH_HIP(c, hipMemcpyAsync(backup, u, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double h = std::min(*dt, dt_max);
+  int nrej = 0, last = ILH_ENOCONV;
+  for (;;) {
+    ilh_step_stats s1;
+    std::memset(&s1, 0, sizeof(s1));
+    const int status = ilh_sdirk_step(c, u, h, scheme, k_guess, k_out, o, &s1);
+    if (status == ILH_OK && s1.newton_max < 4) {
+      *dt = s1.newton_max <= 1 ? 1.05 * h : h;
+      if (dt_taken) *dt_taken = h;
+      if (rejected) *rejected = nrej;
+      if (st) *st = s1;
+      return ILH_OK;
+    }
+    if (status != ILH_OK && status != ILH_ENOCONV && status != ILH_ETANGLED && status != ILH_ENONFINITE)
+      return status;  // an error of the library or the device, not of the step
+    if (status == ILH_OK)  // accepted by Newton but too many iterations: undo the update
+      ILH_HIP(c, hipMemcpyAsync(u, backup, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    else
+      last = status;
+    if (++nrej > max_reject) {
+      ILH_HIP(c, hipStreamSynchronize(c->stream));
+      if (rejected) *rejected = nrej;
+      if (st) *st = s1;
+      return fail(c, last, "step-size control: too many rejected trials");
+    }
+    h *= 0.85;
+  }
 }
 
 }  // extern "C"

@@ -88,3 +88,43 @@ def test_sdirk_rejects_unknown_scheme():
     code = G.lib.ilh_sdirk_step(G.ctx, G._vec(u, G.nblock, name="u"), 0.01, 5, None, None,
                                 ilh.newton_options(), None)
     assert code == 1  # EINVAL
+
+
+@pytest.mark.parametrize("n,cfl,tol", [(4, 0.5, 0.01), (8, 0.5, 0.01), (4, 2.0, 0.02), (8, 2.0, 0.02)])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_adaptive_step_control_matches_paper_table(n, cfl, tol, prec):
+    """ilh_adaptive_step (Sec. 4 step control) on Q2Q1 + SD2 from FS-CFL 0.5 and 2: the table's
+    step counts and L1 errors, as the oracle's adaptive run reproduces them."""
+    gold = os.path.join(os.path.dirname(__file__), "golden", "tg_table_q2q1_sd2.txt")
+    rows = [l.split() for l in open(gold) if l.strip() and not l.startswith("#")]
+    ref_err, ref_steps = [(float(r[3]), int(r[4])) for r in rows if int(r[1]) == n and float(r[2]) == cfl][0]
+    G = ilh.Hydro("tg2d", (n, n), 2)
+    u = G.init_state()
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=prec)
+    dt = G.dt_estimate(u, cfl)
+    t, steps, kg = 0.0, 0, G.rate(u)
+    while t < 0.5 - 1e-12:
+        kg, st, taken, dt, nrej = G.adaptive_step(u, dt, 0.5 - t, "sd2", guess=kg, opts=opts)
+        assert st["newton_max"] < 4
+        t += taken
+        steps += 1
+    assert abs(t - 0.5) < 1e-12
+    assert steps == ref_steps, (steps, ref_steps)
+    err = G.l1_error(u)
+    assert abs(err - ref_err) <= tol * ref_err, (err, ref_err)
+
+
+def test_adaptive_step_rejects_and_restores():
+    """A first step far beyond what Newton handles in three iterations is rejected and shrunk;
+    the accepted step is 0.85^m of the proposal and the state equals a plain SD2 step of it."""
+    G = ilh.Hydro("tg2d", (6, 6), 2)
+    u = G.init_state()
+    u_ref = u.clone()
+    dt0 = 40.0 * G.dt_estimate(u, 0.5)
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=64)
+    k, st, taken, dt_next, nrej = G.adaptive_step(u, dt0, 10.0, "sd2", guess=G.rate(u_ref), opts=opts)
+    assert nrej >= 1
+    assert abs(taken - dt0 * 0.85 ** nrej) <= 1e-12 * dt0
+    assert dt_next == pytest.approx(taken * (1.05 if st["newton_max"] <= 1 else 1.0), rel=1e-15)
+    G.sdirk_step(u_ref, taken, "sd2", guess=G.rate(u_ref.clone()), opts=opts)
+    assert rel(to_np(u), to_np(u_ref)) <= 1e-12

@@ -114,3 +114,19 @@ def test_tg_q3q2_sd3_matches_paper_table(cfl, tol):
     assert steps == ref[5]
     err = H.l1_velocity_error(u)
     assert abs(err - ref[4]) <= tol * ref[4], (err, ref[4])
+
+
+@pytest.mark.parametrize("n,cfl,tol", [(4, 0.5, 0.01), (8, 0.5, 0.01), (4, 2.0, 0.02), (8, 2.0, 0.02)])
+def test_tg_adaptive_step_control_matches_paper_table(n, cfl, tol):
+    """Q2Q1 + SD2 with the paper's Newton-based step control from FS-CFL 0.5 and 2: the
+    table's step counts (13 / 26 and 4 / 7) and L1 errors (tests/golden/tg_table_q2q1_sd2.txt).
+    FS-CFL 8 is not pinned: there the first steps need four or more Newton iterations from the
+    explicit-rate guess and are rejected, while the paper's runs accepted them."""
+    gold = os.path.join(os.path.dirname(__file__), "golden", "tg_table_q2q1_sd2.txt")
+    rows = [l.split() for l in open(gold) if l.strip() and not l.startswith("#")]
+    ref = [(float(r[3]), int(r[4])) for r in rows if int(r[1]) == n and float(r[2]) == cfl][0]
+    H = Hydro("tg2d", (n, n), 2)
+    u, steps, rejected = krylov.adaptive_run(H, H.init_state(), 0.5, cfl, "sd2")
+    assert steps == ref[1], (steps, ref)
+    err = H.l1_velocity_error(u)
+    assert abs(err - ref[0]) <= tol * ref[0], (err, ref)
