@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-seeds", default="1000-1001")
     ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--no-c4", action="store_true", help="skip the triple-point precision and step-control legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a copy-shaped elementwise kernel (dst = -src) over this many MiB three "
                          "times: the byte calibration for HBM traffic counters")
@@ -133,6 +134,54 @@ def run_steps(H, u, dt, nsteps, opts, hist, ilh):
             hist.pop(0)
         stats.append(st)
     return stats
+
+
+def triple_point_legs(ilh, torch):
+    """C4 (triple point 112x48 Q3Q2, smoothed viscosity): (i) 8 fixed steps at 8x the explicit
+    step with FP32 and with FP64 Jacobian actions, probed block preconditioner (Newton and GMRES
+    counts, state difference);
+    (ii) the Newton-based step-size control of Sec. 4 started from 8x the explicit step, SD2,
+    10 accepted steps."""
+    from paper_2609_16424_amd import learned as L
+    res = {}
+    states = {}
+    for prec in (32, 64):
+        h = L.make_triple(112, 48, 3)
+        u = h.init_state()
+        dt = 8.0 * h.dt_estimate(u, 0.5)
+        opts = ilh.newton_options(tol=1e-10, jvp_prec=prec, max_newton=30, restart=30, gmres_maxit=150,
+                                  prec_probe=2, prec_lag=1)
+        hist, newton, gmres = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(8):
+            g = h.plain_guess(u, hist, 0.5 * dt)
+            k, st = h.implicit_step(u, dt, guess=g, opts=opts)
+            hist = (hist + [k])[-2:]
+            newton.append(st["newton"])
+            gmres.append(st["gmres"])
+        torch.cuda.synchronize()
+        states[prec] = u
+        res["fixed_8x_fp%d" % prec] = {"newton_per_step": float(np.mean(newton)), "gmres_per_step": float(np.mean(gmres)),
+                                       "s_per_step": (time.perf_counter() - t0) / 8}
+    res["fixed_8x_rel_state_diff_fp32_vs_fp64"] = float(torch.linalg.norm(states[32] - states[64]) /
+                                                         torch.linalg.norm(states[64]))
+    h = L.make_triple(112, 48, 3)
+    u = h.init_state()
+    dt_exp = h.dt_estimate(u, 0.5)
+    dt = 8.0 * dt_exp
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150)
+    hist, rej, ratios, newton = [], [], [], []
+    for _ in range(10):
+        g = h.plain_guess(u, hist, 0.5 * dt)
+        k, st, taken, dt, nrej = h.adaptive_step(u, dt, 10.0, "sd2", guess=g, opts=opts, max_reject=40)
+        hist = (hist + [k])[-2:]
+        rej.append(nrej)
+        ratios.append(taken / dt_exp)
+        newton.append(st["newton_max"])
+    res["step_control_from_8x"] = {"rejected_trials": rej, "accepted_dt_over_explicit": ratios[-1],
+                                   "newton_per_step": float(np.mean(newton))}
+    return res
 
 
 def cpu_baseline(u_np, n, k, dt, budget_s=30.0):
@@ -329,30 +378,29 @@ def main():
         del H3, u3, k3, d3, o3
         torch.cuda.empty_cache()
 
-    learned = None
+    learned = {}
     if not args.no_learned:
         from paper_2609_16424_amd import learned as L
-        if os.path.exists(L.DEFAULT_MODEL):
-            z = np.load(L.DEFAULT_MODEL)
+        lo, hi = [int(v) for v in args.learned_seeds.split("-")]
+        for key, path in (("learned_guess_c5", L.DEFAULT_MODEL), ("learned_guess_c5_4x", L.MODEL_4X)):
+            if not os.path.exists(path):
+                continue
+            z = np.load(path)
             scales = dict(zip(("vs", "es", "xs", "kvs", "kes"), z["scales"].tolist()))
-            lo, hi = [int(v) for v in args.learned_seeds.split("-")]
-            opts_c4 = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150)
+            opts_c4 = L.model_newton_options(z)
             res = L.evaluate(112, 48, 3, list(range(lo, hi + 1)), args.learned_steps, float(z["cfl_factor"]),
                              opts_c4, {k: z[k] for k in ("widths", "master", "mu", "sd", "osc")}, scales)
-            learned = {"workload": "2D triple point 112x48 Q3Q2, smoothed viscosity, %gx explicit CFL, "
-                                   "held-out perturbation seeds %s, %d steps each, tol 1e-10"
-                                   % (float(z["cfl_factor"]), args.learned_seeds, args.learned_steps),
-                       "plain": res["plain"], "learned": res["learned"], "zero_output_control": res["zero"],
-                       "speedup_s_per_step": res["plain"]["s_per_step"] / res["learned"]["s_per_step"]}
+            learned[key] = {
+                "workload": "2D triple point 112x48 Q3Q2, smoothed viscosity, %gx explicit CFL, held-out "
+                            "perturbation seeds %s, %d steps each, tol 1e-10, block preconditioner mode %d "
+                            "(lag %d)" % (float(z["cfl_factor"]), args.learned_seeds, args.learned_steps,
+                                          opts_c4.prec_probe, opts_c4.prec_lag),
+                "plain": res["plain"], "learned": res["learned"], "zero_output_control": res["zero"],
+                "speedup_s_per_step": res["plain"]["s_per_step"] / res["learned"]["s_per_step"]}
 
-    if args.copy_probe_mib:
-        nb = args.copy_probe_mib << 20
-        src = torch.ones(nb // 4, device="cuda", dtype=torch.float32)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
+    c4 = None
+    if not args.no_c4:
+        c4 = triple_point_legs(ilh, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -394,14 +442,16 @@ def main():
         "energy_after": ke + ie,
     }
     out.update(extra)
-    if learned:
-        out["learned_guess_c5"] = learned
-        out["s_per_implicit_step_learned_c5"] = learned["learned"]["s_per_step"]
-        out["s_per_implicit_step_plain_c5"] = learned["plain"]["s_per_step"]
+    out.update(learned)
+    if "learned_guess_c5" in learned:
+        out["s_per_implicit_step_learned_c5"] = learned["learned_guess_c5"]["learned"]["s_per_step"]
+        out["s_per_implicit_step_plain_c5"] = learned["learned_guess_c5"]["plain"]["s_per_step"]
     if roof_extra:
         out["roofline_large_shape"] = roof_extra
     if roof_3d:
         out["roofline_3d"] = roof_3d
+    if c4:
+        out["c4_triple_point"] = c4
     print(json.dumps(out))
 
 

@@ -192,6 +192,15 @@ typedef struct {
   int guess_fallback;  /* 1: start from k = 0 when ||R(k_guess)|| > ||R(0)|| */
   int ls_residual;     /* 1: the line search also requires ||R|| to decrease (Armijo, 1e-4);
                           0: det J > 0 only */
+  int prec_probe;      /* 0: block preconditioner with the masses (Jacobi of M_V, exact M_E^-1);
+                          1, 2: with the exact diagonal blocks of the Jacobian, read off by
+                          Jacobian actions on coloured unit directions once per Newton iterate
+                          (eq. blockdiag_prec): the exact element blocks M_E - tau dF^T/de,
+                          inverted per element, and Jacobi of M_V + tau dF/dv + tau^2 dF/dx
+                          (1: position block eliminated) or of M_V + tau dF/dv (2);
+                          d (k+1)^d + k^d extra actions per iterate */
+  int prec_lag;        /* with prec_probe: 0 rebuild the blocks at every Newton iterate, 1 only
+                          at the first iterate of each stage solve (lagged, Sec. 3.5) */
 } ilh_newton_opts;
 
 typedef struct {
@@ -221,6 +230,14 @@ int ilh_implicit_step(ilh_ctx* ctx, double* u, double dt, const double* k_guess,
  * Higher-order SDIRK steps are built from these stage solves. */
 int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double* k_guess,
                     double* k_out, const ilh_newton_opts* o, ilh_step_stats* st);
+
+/* The diagonal blocks of eq. blockdiag_prec at the stored linearisation point (ilh_linearize),
+ * as the preconditioner option prec_probe = mode (1 or 2) builds them from FP32 Jacobian
+ * actions on coloured unit directions: dv [N_h1] receives the diagonal of the velocity block
+ * M_V + tau dF/dv (mode 2), with tau^2 dF/dx added (mode 1: position block eliminated);
+ * constrained rows 1.  einv [N_e][N_l][N_l] receives the inverses of the element blocks
+ * M_E - tau dF^T/de (row-major).  Device pointers, nullable.  Other modes: ILH_EINVAL. */
+int ilh_probe_blocks(ilh_ctx* ctx, int mode, double* dv, double* einv);
 
 /* One SDIRK step of Sec. 4 (scheme 2 = SD2, the implicit midpoint rule; 3 = SD3, the
  * three-stage L-stable third-order method of Alexander; 4 = SD4, the three-stage fourth-order

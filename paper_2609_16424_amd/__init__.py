@@ -232,6 +232,16 @@ class Hydro:
                                              min(len(history), 2), float(tau), _ptr(out)))
         return out
 
+    def probe_blocks(self, mode=1):
+        """(velocity-block diagonal [nh1], inverted energy blocks [Ne, Nl, Nl]) at the stored
+        linearisation point; mode 1 eliminates the position block, mode 2 does not."""
+        nl = self.nl2 // self.Ne
+        dv = self.new(self.nh1)
+        einv = self.new(self.Ne * nl * nl)
+        self._stream()
+        self._check(self.lib.ilh_probe_blocks(self.ctx, int(mode), _ptr(dv), _ptr(einv)))
+        return dv, einv.view(self.Ne, nl, nl)
+
     JVP_VARIANTS = {"lin": 0, "generic": 1, "recompute": 2}
 
     def set_kernel_variant(self, variant):

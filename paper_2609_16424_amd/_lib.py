@@ -26,7 +26,8 @@ class NewtonOpts(C.Structure):
         ("tol", C.c_double), ("max_newton", C.c_int), ("restart", C.c_int),
         ("gmres_rtol", C.c_double), ("gmres_maxit", C.c_int), ("jvp_prec", C.c_int),
         ("max_halvings", C.c_int), ("pcg_iters", C.c_int), ("prec_coupled", C.c_int),
-        ("guess_fallback", C.c_int), ("ls_residual", C.c_int),
+        ("guess_fallback", C.c_int), ("ls_residual", C.c_int), ("prec_probe", C.c_int),
+        ("prec_lag", C.c_int),
     ]
 
 
@@ -72,6 +73,7 @@ SIGNATURES = {
     "ilh_implicit_step": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_sdirk_step": (I, [P, P, D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
+    "ilh_probe_blocks": (I, [P, I, P, P]),
     "ilh_adaptive_step": (I, [P, P, C.POINTER(D), D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats), I,
                               C.POINTER(I), C.POINTER(D)]),
     "ilh_timing_enable": (I, [P, I]),

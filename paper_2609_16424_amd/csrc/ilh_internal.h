@@ -102,6 +102,8 @@ struct ilh_ctx {
   // Krylov / Newton workspace (allocated on first use)
   int kry_m = 0;
   double* kry = nullptr;        // V [(m+1)][nblock], Z [m][nblock]
+  double* pdv = nullptr;        // probed diagonal of the velocity block [nh1]
+  double* peinv = nullptr;      // inverted probed energy blocks [Ne][Nl][Nl]
   double* sdk = nullptr;        // SDIRK stage rates and stage base [4][nblock] (allocated on first use)
   double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
@@ -187,6 +189,13 @@ int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, co
                   int64_t n, double* d_nrm2);
 int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n);
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled);
+// probed diagonal blocks of the Jacobian (preconditioner option prec_probe)
+int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau);
+int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D);
+int launch_probe_e_dir(ilh_ctx* c, float* d, int j);
+int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
+int launch_invert_blocks(ilh_ctx* c, double* B);
+int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);
 int l1_error_host(ilh_ctx* c, const double* u, double* out);

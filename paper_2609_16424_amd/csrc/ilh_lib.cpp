@@ -241,6 +241,8 @@ void ilh_newton_defaults(ilh_newton_opts* o) {
   o->prec_coupled = 1;
   o->guess_fallback = 1;
   o->ls_residual = 1;
+  o->prec_probe = 0;
+  o->prec_lag = 0;
 }
 
 const char* ilh_last_error(const ilh_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -263,7 +265,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
-                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk};
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk, c->pdv, c->peinv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : c->qd)
@@ -748,6 +750,32 @@ __global__ void k_scale_copy(double* y, const double* x, const double* s, int id
     y[i] = x[i] * f;
 }
 
+// Exact diagonal blocks of the Jacobian at the current linearisation point, read off by FP32
+// Jacobian actions on coloured unit directions: the diagonal of the velocity block (mode 2:
+// directions (0, e, 0)) or of the velocity block with the position block eliminated (mode 1:
+// directions (tau e, e, 0)), and every element's energy block.
+static int build_probe_prec(ilh_ctx* c, int mode) {
+  int st;
+  if (!c->pdv && (st = dalloc(c, &c->pdv, (size_t)c->nh1))) return st;
+  if (!c->peinv && (st = dalloc(c, &c->peinv, (size_t)c->Ne * c->Nl * c->Nl))) return st;
+  float* d = c->kry32;
+  float* y = c->kry32 + c->nblock;
+  const int M = c->k + 1;
+  const int ncol = c->dim == 3 ? M * M * M : M * M;
+  for (int comp = 0; comp < c->dim; ++comp)
+    for (int col = 0; col < ncol; ++col) {
+      if ((st = launch_probe_v_dir(c, d, comp, col, mode == 1 ? c->lin_tau : 0.0))) return st;
+      if ((st = ilh_jvp_lin(c, 32, d, y))) return st;
+      if ((st = launch_probe_v_take(c, y, comp, col, c->pdv))) return st;
+    }
+  for (int j = 0; j < c->Nl; ++j) {
+    if ((st = launch_probe_e_dir(c, d, j))) return st;
+    if ((st = ilh_jvp_lin(c, 32, d, y))) return st;
+    if ((st = launch_probe_e_take(c, y, j, c->peinv))) return st;
+  }
+  return launch_invert_blocks(c, c->peinv);
+}
+
 struct Solver {
   ilh_ctx* c;
   const ilh_newton_opts* o;
@@ -769,6 +797,12 @@ struct Solver {
     const int64_t nh1 = c->nh1;
     int st;
     z32_of = nullptr;
+    if (o->prec_probe) {
+      float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
+      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled))) return st;
+      if (z32) z32_of = z;
+      return ILH_OK;
+    }
     if (o->pcg_iters <= 0) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
       if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled))) return st;
@@ -953,6 +987,7 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
       break;
     }
     if ((st = ilh_linearize(c, k, u, tau))) return st;
+    if (o->prec_probe && (it == 0 || !o->prec_lag) && (st = build_probe_prec(c, o->prec_probe))) return st;
     if ((st = launch_axpby(c, r, 0.0, r, -1.0, n))) return st;  // r <- -r (right-hand side)
     int gits = 0;
     if ((st = S.fgmres(r, dk, &gits))) return st;
@@ -1127,6 +1162,18 @@ static bool sdirk_tab(int scheme, SdirkTab* t) {
     return true;
   }
   return false;
+}
+
+int ilh_probe_blocks(ilh_ctx* c, int mode, double* dv, double* einv) {
+  if (!c || (mode != 1 && mode != 2)) return ILH_EINVAL;
+  int st;
+  if ((st = ensure_solver_ws(c, 1))) return st;
+  if ((st = build_probe_prec(c, mode))) return st;
+  if (dv) ILH_HIP(c, hipMemcpyAsync(dv, c->pdv, c->nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (einv)
+    ILH_HIP(c, hipMemcpyAsync(einv, c->peinv, (size_t)c->Ne * c->Nl * c->Nl * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+  return ILH_OK;
 }
 
 int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k_guess, double* k_out,

@@ -320,6 +320,176 @@ int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double ta
   return ILH_OK;
 }
 
+// ------------------------------------------------------------------ probed block preconditioner
+// Node colours: (I mod M, J mod M[, K mod M]) with M = k + 1 -- two nodes of one colour never
+// share an element, so a Jacobian action on the sum of the unit directions of one colour
+// returns each node's diagonal entry at that node.
+__device__ __forceinline__ int node_colour(int64_t i, int dim, const int* ng, int M) {
+  const int64_t I = i % ng[0], J = (i / ng[0]) % ng[1], K = dim == 3 ? i / ((int64_t)ng[0] * ng[1]) : 0;
+  return (int)((I % M) + M * ((J % M) + M * (K % M)));
+}
+
+struct NodeGrid {
+  int ng[3];
+};
+
+// direction: v component comp at the nodes of colour col = 1, x component comp there = tau
+__global__ void k_probe_v_dir(float* d, int64_t N, int dim, NodeGrid g, int M, int comp, int col, float tau,
+                              int64_t nblock) {
+  const int64_t nh1 = (int64_t)dim * N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblock; i += (int64_t)gridDim.x * blockDim.x) {
+    float v = 0.f;
+    if (i < 2 * nh1) {
+      const int64_t j = i < nh1 ? i : i - nh1;
+      const int c = (int)(j / N);
+      if (c == comp && node_colour(j - c * N, dim, g.ng, M) == col) v = i < nh1 ? tau : 1.f;
+    }
+    d[i] = v;
+  }
+}
+
+__global__ void k_probe_v_take(const float* y, int64_t N, int dim, NodeGrid g, int M, int comp, int col, double* D) {
+  const int64_t nh1 = (int64_t)dim * N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    if (node_colour(i, dim, g.ng, M) == col) D[comp * N + i] = (double)y[nh1 + comp * N + i];
+}
+
+// direction: energy DOF j of every element = 1
+__global__ void k_probe_e_dir(float* d, int64_t nh1x2, int64_t nl2, int Nl, int j, int64_t nblock) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblock; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (i >= nh1x2 && (i - nh1x2) % Nl == j) ? 1.f : 0.f;
+}
+
+// column j of every element's energy block
+__global__ void k_probe_e_take(const float* y, int64_t nh1x2, int64_t Ne, int Nl, int j, double* B) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < Ne * Nl; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / Nl;
+    const int r = (int)(t % Nl);
+    B[(e * Nl + r) * Nl + j] = (double)y[nh1x2 + t];
+  }
+}
+
+// In-place inverse of every element block (Gauss-Jordan, partial pivoting), one thread each.
+// A singular block is replaced by the identity (the preconditioner then leaves those rows).
+__global__ void k_invert_blocks(double* B, int64_t Ne, int Nl) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= Ne) return;
+  double* A = B + e * Nl * Nl;
+  int piv[32];
+  for (int i = 0; i < Nl; ++i) piv[i] = i;
+  bool ok = true;
+  for (int c = 0; c < Nl && ok; ++c) {
+    int p = c;
+    double best = fabs(A[c * Nl + c]);
+    for (int r = c + 1; r < Nl; ++r)
+      if (fabs(A[r * Nl + c]) > best) {
+        best = fabs(A[r * Nl + c]);
+        p = r;
+      }
+    if (!(best > 0.0)) {
+      ok = false;
+      break;
+    }
+    if (p != c) {
+      for (int q = 0; q < Nl; ++q) {
+        const double t = A[c * Nl + q];
+        A[c * Nl + q] = A[p * Nl + q];
+        A[p * Nl + q] = t;
+      }
+      const int t = piv[c];
+      piv[c] = piv[p];
+      piv[p] = t;
+    }
+    const double inv = 1.0 / A[c * Nl + c];
+    A[c * Nl + c] = 1.0;
+    for (int q = 0; q < Nl; ++q) A[c * Nl + q] *= inv;
+    for (int r = 0; r < Nl; ++r) {
+      if (r == c) continue;
+      const double f = A[r * Nl + c];
+      A[r * Nl + c] = 0.0;
+      for (int q = 0; q < Nl; ++q) A[r * Nl + q] -= f * A[c * Nl + q];
+    }
+  }
+  if (!ok) {
+    for (int r = 0; r < Nl; ++r)
+      for (int q = 0; q < Nl; ++q) A[r * Nl + q] = r == q ? 1.0 : 0.0;
+    return;
+  }
+  // the loop inverted the row-permuted block P A (row q of it is row piv[q] of A):
+  // A^-1 = (P A)^-1 P, i.e. column q of the result moves to column piv[q]
+  double tmp[32];
+  for (int r = 0; r < Nl; ++r) {
+    for (int q = 0; q < Nl; ++q) tmp[piv[q]] = A[r * Nl + q];
+    for (int q = 0; q < Nl; ++q) A[r * Nl + q] = tmp[q];
+  }
+}
+
+int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau) {
+  NodeGrid g{{c->ng[0], c->ng[1], c->ng[2]}};
+  hipLaunchKernelGGL(k_probe_v_dir, dim3(nblk(c->nblock, 8192)), dim3(TPB), 0, c->stream, d, c->N, c->dim, g,
+                     c->k + 1, comp, col, (float)tau, c->nblock);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D) {
+  NodeGrid g{{c->ng[0], c->ng[1], c->ng[2]}};
+  hipLaunchKernelGGL(k_probe_v_take, dim3(nblk(c->N, 8192)), dim3(TPB), 0, c->stream, y, c->N, c->dim, g, c->k + 1,
+                     comp, col, D);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_probe_e_dir(ilh_ctx* c, float* d, int j) {
+  hipLaunchKernelGGL(k_probe_e_dir, dim3(nblk(c->nblock, 8192)), dim3(TPB), 0, c->stream, d, 2 * c->nh1, c->nl2, c->Nl,
+                     j, c->nblock);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B) {
+  hipLaunchKernelGGL(k_probe_e_take, dim3(nblk(c->Ne * c->Nl, 8192)), dim3(TPB), 0, c->stream, y, 2 * c->nh1, c->Ne,
+                     c->Nl, j, B);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_invert_blocks(ilh_ctx* c, double* B) {
+  if (c->Nl > 32) return fail(c, ILH_EINVAL, "energy blocks larger than 32");
+  hipLaunchKernelGGL(k_invert_blocks, dim3((unsigned)((c->Ne + 63) / 64)), dim3(64), 0, c->stream, B, c->Ne, c->Nl);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// z_v = r_v / D (probed diagonal), z_x = r_x + tau z_v (coupled) or r_x, z_e = Binv r_e per element
+__global__ void k_precond_probe(const double* __restrict__ r, const double* __restrict__ D,
+                                const double* __restrict__ Binv, double* z, float* z32, double tau, int coupled,
+                                int64_t nh1, int64_t Ne, int Nl) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nh1) {
+    const double zv = r[nh1 + i] / D[i];
+    const double zx = coupled ? tau * zv + r[i] : r[i];
+    z[i] = zx;
+    z[nh1 + i] = zv;
+    if (z32) {
+      z32[i] = (float)zx;
+      z32[nh1 + i] = (float)zv;
+    }
+  } else if (i < nh1 + Ne * Nl) {
+    const int64_t k = i - nh1, e = k / Nl;
+    const int rr = (int)(k % Nl);
+    const double* Bi = Binv + (e * Nl + rr) * Nl;
+    double acc = 0;
+    for (int j = 0; j < Nl; ++j) acc += Bi[j] * r[2 * nh1 + e * Nl + j];
+    z[2 * nh1 + k] = acc;
+    if (z32) z32[2 * nh1 + k] = (float)acc;
+  }
+}
+
+int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled) {
+  const int64_t n = c->nh1 + c->Ne * c->Nl;
+  hipLaunchKernelGGL(k_precond_probe, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->pdv,
+                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
 // ------------------------------------------------------------------ mass operators
 // y += M_V x (values-only partial assembly).  bc != 0: constrained inputs read as zero and
 // constrained outputs receive x (the eliminated operator Mhat).

@@ -28,7 +28,8 @@ import torch
 from . import Hydro, IlhError, _lib, newton_options
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_MODEL = os.path.join(HERE, "models", "guess_triple_q3q2.npz")
+DEFAULT_MODEL = os.path.join(HERE, "models", "guess_triple_q3q2.npz")        # 8x explicit step
+MODEL_4X = os.path.join(HERE, "models", "guess_triple_q3q2_4x.npz")          # 4x explicit step
 
 # triple-point regions: (rho, p, gamma) for x < 1; x > 1, y < 1.5; x > 1, y > 1.5
 TRIPLE = ((1.0, 1.0, 1.5), (1.0, 0.1, 1.4), (0.125, 0.1, 1.5))
@@ -69,6 +70,14 @@ def perturbation(seed):
 
 
 VISC = {"mode": "formula", "width": 1e-3, "h_coarse": 1.0 / 3.0}
+
+
+def model_newton_options(z):
+    """Newton-Krylov options a committed model was trained and is evaluated with."""
+    pp = int(z["prec_probe"]) if "prec_probe" in z else 0
+    pl = int(z["prec_lag"]) if "prec_lag" in z else 0
+    return newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150,
+                          prec_probe=pp, prec_lag=pl)
 
 
 def make_triple(nx, ny, k, seed=None):
@@ -213,7 +222,9 @@ class LearnedGuess:
         rl = self.h.residual(kl, u, tau)
         rb = self.h.residual(base, u, tau)
         nl, nb = float(torch.linalg.norm(rl)), float(torch.linalg.norm(rb))
-        if math.isfinite(nl) and nl < nb:
+        # a plain iterate whose stage state is tangled has a non-finite residual: any finite
+        # learned iterate is better
+        if math.isfinite(nl) and (nl < nb or not math.isfinite(nb)):
             self.used += 1
             return kl, True
         return base, False
@@ -365,7 +376,7 @@ def main(argv=None):
     ap.add_argument("--order", type=int, default=3)
     ap.add_argument("--runs", type=int, default=200)
     ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--cfl-factor", type=float, default=4.0)
+    ap.add_argument("--cfl-factor", type=float, default=8.0)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -377,11 +388,14 @@ def main(argv=None):
     ap.add_argument("--zero-guess", action="store_true")
     ap.add_argument("--dscale", choices=["formula", "const"], default="formula")
     ap.add_argument("--pcg-iters", type=int, default=0)
+    ap.add_argument("--prec-probe", type=int, default=2,
+                    help="block preconditioner: 0 masses, 1/2 probed diagonal Jacobian blocks")
+    ap.add_argument("--prec-lag", type=int, default=1, help="rebuild probed blocks once per stage solve")
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     VISC["mode"] = a.dscale
     opts = newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150,
-                          pcg_iters=a.pcg_iters)
+                          pcg_iters=a.pcg_iters, prec_probe=a.prec_probe, prec_lag=a.prec_lag)
     lo, hi = [int(v) for v in a.eval_seeds.split("-")]
     eval_seeds = list(range(lo, hi + 1))
     if a.cmd == "probe":
@@ -427,7 +441,7 @@ def main(argv=None):
         np.savez(a.out, widths=st["widths"], master=st["master"], mu=st["mu"], sd=st["sd"], osc=st["osc"],
                  scales=np.array([scales[k] for k in ("vs", "es", "xs", "kvs", "kes")]),
                  loss=np.array(hist), cfl_factor=np.array(a.cfl_factor), runs=np.array(a.runs),
-                 steps=np.array(a.steps))
+                 steps=np.array(a.steps), prec_probe=np.array(a.prec_probe), prec_lag=np.array(a.prec_lag))
         log("saved %s" % a.out)
         del X, T
         res = evaluate(a.nx, a.ny, a.order, eval_seeds, a.steps, a.cfl_factor, opts, st, scales, log=log)
