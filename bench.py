@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # the same counter reads for a copy-shaped kernel of known size (--copy-probe-mib).  The record
 # holds only while the kernel sources hash to the value it was taken with; otherwise traffic is
 # reported as null.
-TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_pointwise.h",
-                   "paper_2609_16424_amd/csrc/ilh_internal.h")
+TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
+                   "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
 TRAFFIC_RECORD = {"sha256": "1ff6f9be970798e683e7ec6501e655a38bc10adbd3914fb566ef8652a9c66ae3",
                   "variant": "lin", "n": 128, "order": 3,
                   "fetch_kib": 18786.12, "fetch_scale": 262144.0 / 131079.52,
@@ -75,8 +75,8 @@ def parse():
                     help="Jacobian-action kernels: linearised (stored tangent coefficients), generic element "
                          "kernel, or register-resident recompute kernel")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--learned-seeds", default="1000-1001")
-    ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--learned-seeds", default="1000-1004")
+    ap.add_argument("--learned-steps", type=int, default=30)
     ap.add_argument("--no-c4", action="store_true", help="skip the triple-point precision and step-control legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a copy-shaped elementwise kernel (dst = -src) over this many MiB three "
@@ -153,6 +153,7 @@ def triple_point_legs(ilh, torch):
                                   prec_probe=2, prec_lag=1)
         hist, newton, gmres = [], [], []
         torch.cuda.synchronize()
+        h.timing(True)
         t0 = time.perf_counter()
         for _ in range(8):
             g = h.plain_guess(u, hist, 0.5 * dt)
@@ -161,9 +162,15 @@ def triple_point_legs(ilh, torch):
             newton.append(st["newton"])
             gmres.append(st["gmres"])
         torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 8
+        tm = h.timing_read()
+        h.timing(False)
         states[prec] = u
+        jms, jn = tm["jvp"]
         res["fixed_8x_fp%d" % prec] = {"newton_per_step": float(np.mean(newton)), "gmres_per_step": float(np.mean(gmres)),
-                                       "s_per_step": (time.perf_counter() - t0) / 8}
+                                       "s_per_step": el,
+                                       "jvp_qps_shocked_state": h.nqp * jn / (1e-3 * (jms + tm["linearize"][0])),
+                                       "jvp_apply_avg_us": 1e3 * jms / max(jn, 1)}
     res["fixed_8x_rel_state_diff_fp32_vs_fp64"] = float(torch.linalg.norm(states[32] - states[64]) /
                                                          torch.linalg.norm(states[64]))
     h = L.make_triple(112, 48, 3)
@@ -210,6 +217,17 @@ def cpu_baseline(u_np, n, k, dt, budget_s=30.0):
             "sample": "%d complex-step Jacobian action(s) of the stage residual on the full %dx%d Q%dQ%d "
                       "benchmark state (%d qp), NumPy FP64/complex128, 1 thread; median" %
                       (len(times), n, n, k, k - 1, nqp)}
+
+
+def _finite(v):
+    """JSON has no NaN or infinity: a non-finite figure is reported as null."""
+    if isinstance(v, dict):
+        return {k: _finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(x) for x in v]
+    if isinstance(v, float) and not np.isfinite(v):
+        return None
+    return v
 
 
 def main():
@@ -344,39 +362,42 @@ def main():
 
     roof_3d = None
     if args.roofline_shape_3d:
-        m = args.roofline_shape_3d
-        H3 = ilh.Hydro("tg3d", (m, m, m), 2)
-        H3.set_kernel_variant(args.jvp_variant)
-        u3 = H3.init_state()
-        u3[:H3.nh1] += 0.05 * u3[H3.nh1:2 * H3.nh1]
-        k3 = torch.zeros_like(u3)
-        H3.linearize(k3, u3, 0.5 * H3.dt_estimate(u3, 2.0))
-        d3 = torch.randn(H3.nblock, device=u3.device, dtype=torch.float32,
-                         generator=torch.Generator(device=u3.device).manual_seed(5))
-        o3 = torch.empty_like(d3)
-        H3.timing(True)
-        for _ in range(2):
-            H3.jvp_lin(d3, 32, o3)
-        tw = H3.timing_read()  # did the warm-up launch a linearisation?
-        kind = "lin" if tw["linearize"][1] else "generic"
-        H3.timing(True)
-        for _ in range(10):
-            H3.jvp_lin(d3, 32, o3)
-        t3 = H3.timing_read()
-        H3.timing(False)
-        a3 = 1e-3 * t3["jvp"][0] / t3["jvp"][1]
-        b3 = jvp_bytes(H3, 32, kind)
-        if kind == "lin":
-            lin3 = {"avg_launch_us": 1e3 * tw["linearize"][0] / tw["linearize"][1],
-                    "bytes_per_launch": lin_bytes(H3, 32)}
-        else:
-            lin3 = None
-        roof_3d = {"shape": "%d^3 Q2Q1 3D TG (displaced)" % m, "n_qp": H3.nqp, "kernel_variant": kind,
-                   "linearize": lin3,
-                   "avg_launch_us": 1e6 * a3, "jvp_qps": H3.nqp / a3, "bytes_per_launch": b3,
-                   "achieved_GBs": b3 / a3 / 1e9, "frac": b3 / a3 / 1e9 / HBM_PEAK_GBS}
-        del H3, u3, k3, d3, o3
-        torch.cuda.empty_cache()
+        roof_3d = {}
+        for m, visc in ((args.roofline_shape_3d, False), (args.roofline_shape_3d, True), (32, False)):
+            H3 = ilh.Hydro("tg3d", (m, m, m), 2, visc=visc, dscale_mode="formula" if visc else "const",
+                           h_coarse=1.0 / 2.0)
+            H3.set_kernel_variant(args.jvp_variant)
+            u3 = H3.init_state()
+            u3[:H3.nh1] += 0.05 * u3[H3.nh1:2 * H3.nh1]
+            k3 = torch.zeros_like(u3)
+            H3.linearize(k3, u3, 0.5 * H3.dt_estimate(u3, 2.0))
+            entry = {"shape": "%d^3 Q2Q1 3D TG (displaced)%s" % (m, ", viscosity" if visc else ""), "n_qp": H3.nqp}
+            for prec in (32, 64):
+                dt_ = torch.float32 if prec == 32 else torch.float64
+                d3 = torch.randn(H3.nblock, device=u3.device, dtype=torch.float64,
+                                 generator=torch.Generator(device=u3.device).manual_seed(5)).to(dt_)
+                o3 = torch.empty_like(d3)
+                H3.timing(True)
+                for _ in range(2):
+                    H3.jvp_lin(d3, prec, o3)
+                tw = H3.timing_read()  # did the warm-up launch a linearisation?
+                kind = "lin" if tw["linearize"][1] else "generic"
+                H3.timing(True)
+                for _ in range(10):
+                    H3.jvp_lin(d3, prec, o3)
+                t3 = H3.timing_read()
+                H3.timing(False)
+                a3 = 1e-3 * t3["jvp"][0] / t3["jvp"][1]
+                b3 = jvp_bytes(H3, prec, kind)
+                entry["fp%d" % prec] = {"kernel_variant": kind, "avg_launch_us": 1e6 * a3, "jvp_qps": H3.nqp / a3,
+                                        "bytes_per_launch": b3, "achieved_GBs": b3 / a3 / 1e9,
+                                        "frac": b3 / a3 / 1e9 / HBM_PEAK_GBS,
+                                        "linearize_avg_us": (1e3 * tw["linearize"][0] / tw["linearize"][1]
+                                                             if tw["linearize"][1] else None)}
+                del d3, o3
+            roof_3d["%d%s" % (m, "_visc" if visc else "")] = entry
+            del H3, u3, k3
+            torch.cuda.empty_cache()
 
     learned = {}
     if not args.no_learned:
@@ -452,7 +473,7 @@ def main():
         out["roofline_3d"] = roof_3d
     if c4:
         out["c4_triple_point"] = c4
-    print(json.dumps(out))
+    print(json.dumps(_finite(out), allow_nan=False))
 
 
 if __name__ == "__main__":

@@ -311,6 +311,30 @@ int ilh_guess_assemble(ilh_ctx* ctx, const float* pred, int ld, double kvscale, 
  * (f - mu[i]) / sd[i] after the scalar scaling; targets are divided by oscale[i] and
  * predictions multiplied by oscale[i] before assembly. */
 
+/* A trained per-element guess model: device pointers owned by the caller.  Layouts as for
+ * ilh_mlp_forward (W, b) and ilh_guess_features / ilh_guess_assemble (mu, sd, osc, scales). */
+typedef struct {
+  int nl;               /* layers (1..7) */
+  int widths[8];        /* widths[0..nl], each 1..128 */
+  const uint16_t* W;    /* BF16 weights */
+  const float* b;       /* biases */
+  const float* mu;      /* feature standardisation (nullable) */
+  const float* sd;      /* (nullable) */
+  const float* osc;     /* output scale (nullable) */
+  double vscale, escale, xscale, kvscale, kescale;
+  int with_base;        /* the features include the plain iterate's element rates */
+} ilh_guess_model;
+
+/* Learned initial iterate of a stage (callers that run the learned guess before each Newton
+ * solve): features of (u, base), MLP forward, assembly (k_x = u_v + tau k_v); the stage
+ * residual R(.; tau, u) judges the result against base, and k receives the learned iterate if
+ * its residual norm is finite and smaller than base's (or base's is not finite), else a copy
+ * of base.  u, base, k: device [block]; m, used (1 if learned, nullable): host.  Scratch for
+ * the features, activations and one residual is kept in the context (allocated on first
+ * use).  Synchronises (the judge reads two norms). */
+int ilh_guess_infer(ilh_ctx* ctx, const ilh_guess_model* m, const double* u, const double* base, double tau,
+                    double* k, int* used);
+
 /* MLP on MFMA (BF16 operands, FP32 accumulation): widths w[0..nl] (each 1..128), hidden
  * layers GELU (erf form), last layer linear.  Every width is padded to P(w) = 32 ceil(w/32);
  * padding entries are zero.  Concatenated over layers l = 0..nl-1:

@@ -40,6 +40,14 @@ class StepStats(C.Structure):
     ]
 
 
+class GuessModel(C.Structure):
+    _fields_ = [
+        ("nl", C.c_int), ("widths", C.c_int * 8), ("W", C.c_void_p), ("b", C.c_void_p), ("mu", C.c_void_p),
+        ("sd", C.c_void_p), ("osc", C.c_void_p), ("vscale", C.c_double), ("escale", C.c_double),
+        ("xscale", C.c_double), ("kvscale", C.c_double), ("kescale", C.c_double), ("with_base", C.c_int),
+    ]
+
+
 P = C.c_void_p
 D = C.c_double
 I = C.c_int
@@ -74,6 +82,7 @@ SIGNATURES = {
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_sdirk_step": (I, [P, P, D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_probe_blocks": (I, [P, I, P, P]),
+    "ilh_guess_infer": (I, [P, C.POINTER(GuessModel), P, P, D, P, C.POINTER(I)]),
     "ilh_adaptive_step": (I, [P, P, C.POINTER(D), D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats), I,
                               C.POINTER(I), C.POINTER(D)]),
     "ilh_timing_enable": (I, [P, I]),

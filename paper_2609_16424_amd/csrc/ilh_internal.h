@@ -102,6 +102,9 @@ struct ilh_ctx {
   // Krylov / Newton workspace (allocated on first use)
   int kry_m = 0;
   double* kry = nullptr;        // V [(m+1)][nblock], Z [m][nblock]
+  float* gscr = nullptr;        // learned-guess features and activations (allocated on first use)
+  int64_t gscr_len = 0;
+  double* gres = nullptr;       // learned-guess judge residual [nblock]
   double* pdv = nullptr;        // probed diagonal of the velocity block [nh1]
   double* peinv = nullptr;      // inverted probed energy blocks [Ne][Nl][Nl]
   double* sdk = nullptr;        // SDIRK stage rates and stage base [4][nblock] (allocated on first use)

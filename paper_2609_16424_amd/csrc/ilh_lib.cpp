@@ -265,7 +265,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
-                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk, c->pdv, c->peinv};
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk, c->pdv, c->peinv, c->gscr, c->gres};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : c->qd)
@@ -1162,6 +1162,51 @@ static bool sdirk_tab(int scheme, SdirkTab* t) {
     return true;
   }
   return false;
+}
+
+int ilh_guess_infer(ilh_ctx* c, const ilh_guess_model* m, const double* u, const double* base, double tau,
+                    double* k, int* used) {
+  if (!c || !m || !u || !base || !k || m->nl < 1 || m->nl > 7 || !m->W || !m->b) return ILH_EINVAL;
+  auto pad = [](int w) { return (w + 31) / 32 * 32; };
+  for (int l = 0; l <= m->nl; ++l)
+    if (m->widths[l] < 1 || m->widths[l] > 128) return fail(c, ILH_EINVAL, "guess model widths must be 1..128");
+  const int64_t ne = c->Ne;
+  const int p0 = pad(m->widths[0]), pl = pad(m->widths[m->nl]);
+  int64_t tot = 0;
+  for (int l = 1; l <= m->nl; ++l) tot += ne * pad(m->widths[l]);
+  const int64_t need = ne * p0 + 2 * tot;
+  int st;
+  if (c->gscr_len < need) {
+    if (c->gscr) (void)hipFree(c->gscr);
+    c->gscr = nullptr;
+    c->gscr_len = 0;
+    if ((st = dalloc(c, &c->gscr, (size_t)need))) return st;
+    c->gscr_len = need;
+  }
+  if (!c->gres && (st = dalloc(c, &c->gres, (size_t)c->nblock))) return st;
+  // the features are written for all p0 columns; zero them once so padding stays zero
+  float* feat = c->gscr;
+  float* zs = feat + ne * p0;
+  float* acts = zs + tot;
+  ILH_HIP(c, hipMemsetAsync(feat, 0, ne * p0 * sizeof(float), c->stream));
+  if ((st = ilh_guess_features(c, u, m->with_base ? base : nullptr, m->vscale, m->escale, m->xscale, m->kvscale,
+                               m->kescale, m->mu, m->sd, feat, p0)))
+    return st;
+  if ((st = ilh_mlp_forward(c, m->nl, m->widths, m->W, m->b, feat, (int)ne, zs, acts))) return st;
+  const float* out = acts + tot - ne * pl;
+  if ((st = ilh_guess_assemble(c, out, pl, m->kvscale, m->kescale, m->osc, base, u, tau, k))) return st;
+  // judge: residual norms of the learned and the plain iterate
+  if ((st = ilh_residual(c, k, u, tau, c->gres))) return st;
+  const double nl = nrm2(c, c->gres, c->nblock, &st);
+  if (st) return st;
+  if ((st = ilh_residual(c, base, u, tau, c->gres))) return st;
+  const double nb = nrm2(c, c->gres, c->nblock, &st);
+  if (st) return st;
+  const bool use = std::isfinite(nl) && (nl < nb || !std::isfinite(nb));
+  if (!use) ILH_HIP(c, hipMemcpyAsync(k, base, c->nblock * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  if (used) *used = use ? 1 : 0;
+  return ILH_OK;
 }
 
 int ilh_probe_blocks(ilh_ctx* c, int mode, double* dv, double* einv) {

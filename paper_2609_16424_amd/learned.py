@@ -214,20 +214,34 @@ class LearnedGuess:
                                                     self.h._vec(u, self.h.nblock), float(tau), C.c_void_p(k.data_ptr())))
         return k
 
+    def model(self):
+        """Descriptor of this guess for ilh_guess_infer (device pointers stay owned here)."""
+        m = _lib.GuessModel()
+        m.nl = self.mlp.nl
+        for i, w in enumerate(self.mlp.widths):
+            m.widths[i] = int(w)
+        m.W = self.mlp.W.data_ptr()
+        m.b = self.mlp.bias.data_ptr()
+        if self.norm:
+            m.mu, m.sd, m.osc = (self.norm[k].data_ptr() for k in ("mu", "sd", "osc"))
+        s = self.sc
+        m.vscale, m.escale, m.xscale, m.kvscale, m.kescale = s["vs"], s["es"], s["xs"], s["kvs"], s["kes"]
+        m.with_base = int(self.with_base)
+        return m
+
     def guess(self, u, hist, tau):
-        """Returns (k_guess, used_learned)."""
+        """Returns (k_guess, used_learned): one fused library call (features, MLP, assembly,
+        residual judge against the plain iterate)."""
         base = self.h.plain_guess(u, hist, tau)
-        kl = self.predict(u, base, tau)
+        k = self.h.new()
+        used = C.c_int(0)
+        self.h._stream()
+        self.h._check(self.h.lib.ilh_guess_infer(self.h.ctx, C.byref(self.model()), self.h._vec(u, self.h.nblock),
+                                                 self.h._vec(base, self.h.nblock), float(tau),
+                                                 C.c_void_p(k.data_ptr()), C.byref(used)))
         self.calls += 1
-        rl = self.h.residual(kl, u, tau)
-        rb = self.h.residual(base, u, tau)
-        nl, nb = float(torch.linalg.norm(rl)), float(torch.linalg.norm(rb))
-        # a plain iterate whose stage state is tangled has a non-finite residual: any finite
-        # learned iterate is better
-        if math.isfinite(nl) and (nl < nb or not math.isfinite(nb)):
-            self.used += 1
-            return kl, True
-        return base, False
+        self.used += used.value
+        return k, bool(used.value)
 
 
 def default_scales(hydro, u0):
@@ -360,9 +374,12 @@ def evaluate(nx, ny, k, seeds, steps, cfl_factor, opts, model_state, scales, log
                 hist = (hist + [k_])[-2:]
             used += lg.used
             del h
+        finite = [g for g in ginit if np.isfinite(g)]
         out[mode] = {"newton_per_step": float(np.mean(newton)), "gmres_per_step": float(np.mean(gmres)),
                      "s_per_step": float(np.mean(wall)), "steps": len(newton), "learned_used": used,
-                     "median_initial_residual_ratio": float(np.nanmedian(ginit))}
+                     # the plain iterate's residual is not finite when its stage state is tangled
+                     "median_initial_residual_ratio": float(np.median(finite)) if finite else None,
+                     "non_finite_initial_residuals": len(ginit) - len(finite)}
         if log:
             log("%s: %s" % (mode, out[mode]))
     return out
