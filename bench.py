@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # reported as null.
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": "1ff6f9be970798e683e7ec6501e655a38bc10adbd3914fb566ef8652a9c66ae3",
+TRAFFIC_RECORD = {"sha256": "3cd541241beb7fcacee3f14c182630b36e524fda83b2d9f3a376e6459fe5f213",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 18786.12, "fetch_scale": 262144.0 / 131079.52,
-                  "write_kib": 6771.94, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 18787.1, "fetch_scale": 262144.0 / 131079.6,
+                  "write_kib": 6775.5, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
@@ -418,6 +418,15 @@ def main():
                                           opts_c4.prec_probe, opts_c4.prec_lag),
                 "plain": res["plain"], "learned": res["learned"], "zero_output_control": res["zero"],
                 "speedup_s_per_step": res["plain"]["s_per_step"] / res["learned"]["s_per_step"]}
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     c4 = None
     if not args.no_c4:

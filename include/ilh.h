@@ -285,6 +285,13 @@ int ilh_adaptive_step(ilh_ctx* ctx, double* u, double* dt, double dt_max, int sc
  *   2 register-resident 2D kernel recomputing the state's quadrature data (2D, k = 2, 3).
  * Other values: ILH_EINVAL. */
 int ilh_set_kernel_variant(ilh_ctx* ctx, int variant);
+/* Work split of the linearised apply kernels: one wave walks `rows` consecutive element rows
+ * (2D) or element layers (3D) of its strip, so that node sums shared between those rows stay on
+ * chip and only nodes shared with other waves are added atomically.  rows = 0 (default) picks
+ * the count from the mesh size: 1 on meshes whose one-row grid has few waves per SIMD, up to 8
+ * on large meshes.  The result does not depend on it beyond the order of FP additions.
+ * rows < 0: ILH_EINVAL. */
+int ilh_set_apply_rows(ilh_ctx* ctx, int rows);
 int ilh_timing_enable(ilh_ctx* ctx, int on);
 int ilh_timing_read(ilh_ctx* ctx, double* ms, int64_t* launches);
 

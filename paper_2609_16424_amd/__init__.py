@@ -250,6 +250,11 @@ class Hydro:
         self._stream()
         self._check(self.lib.ilh_set_kernel_variant(self.ctx, v))
 
+    def set_apply_rows(self, rows):
+        """Element rows (2D) or layers (3D) walked by one wave of the linearised apply kernels;
+        0 chooses by mesh size."""
+        self._check(self.lib.ilh_set_apply_rows(self.ctx, int(rows)))
+
     def timing(self, on=True):
         self._check(self.lib.ilh_timing_enable(self.ctx, int(bool(on))))
 

@@ -87,6 +87,7 @@ SIGNATURES = {
                               C.POINTER(I), C.POINTER(D)]),
     "ilh_timing_enable": (I, [P, I]),
     "ilh_set_kernel_variant": (I, [P, I]),
+    "ilh_set_apply_rows": (I, [P, I]),
     "ilh_timing_read": (I, [P, C.POINTER(D), C.POINTER(I64)]),
     "ilh_guess_features": (I, [P, P, P, D, D, D, D, D, P, P, P, I]),
     "ilh_guess_targets": (I, [P, P, P, D, D, P, P, I]),

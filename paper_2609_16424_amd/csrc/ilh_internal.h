@@ -112,6 +112,7 @@ struct ilh_ctx {
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   double* hdev = nullptr;       // [4 * 72] device scalars of the Arnoldi step
   double* hhost = nullptr;      // pinned mirror of hdev
+  int apply_rows = 0;           // element rows per apply wave of the linearised kernels (0: by mesh size)
   int jvp_variant = 0;          // 0 linearised (where available), 1 generic, 2 register-resident recompute
   void* qd[2] = {nullptr, nullptr};  // stored tangent coefficients, FP32 / FP64 (linearised variant)
   bool qd_ok[2] = {false, false};    // valid for the current linearisation point

@@ -10,7 +10,8 @@
 // of the state are not re-evaluated by each Krylov iteration.
 //
 // Layout of the stored data: field f of lane l at quadrature row qy of work-group b sits at
-// qd[f * qs + (b * Q1D + qy) * 64 + l] (one 64-lane row per wave and row: coalesced).  Both
+// qd[((b * Q1D + qy) * NQD + f) * 64 + l]: the NQD fields of one wave's quadrature row form
+// one contiguous block of 64-lane rows (coalesced, one base address per row).  Both
 // kernels use the work-group / lane map of the register-resident kernel: one wave = EPW
 // consecutive elements of one element row, lane (z, qx) = quadrature column qx of element z.
 #include <hip/hip_runtime.h>
@@ -37,7 +38,8 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
   __shared__ double sBLt[Q1D][L1D];
 
   const int lane = threadIdx.x;
-  const int ey = blockIdx.y, ex0 = blockIdx.x * EPW;
+  const uint32_t tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int sx = tile % gridDim.x, ey = tile / gridDim.x, ex0 = sx * EPW;
   const int nx = P.n[0];
   const int E = min(EPW, nx - ex0);
   const int ns = K * E + 1;
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
   }
   const double gam = P.gamma[e], dJ0 = P.j0e[e];
   const double wx = tb.W[qx] * P.rj0[e];
-  const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const int64_t blk = tile;
 #pragma unroll 1
   for (int qy = 0; qy < Q1D; ++qy) {
     double J[2][2], Gv[2][2];
@@ -147,232 +149,273 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
     // tau folded into every coefficient that multiplies the direction
 #pragma unroll
     for (int f = 8; f < NQD; ++f) cf[f] *= tau;
-    T* q = qd + (blk * Q1D + qy) * 64 + lane;
+    T* q = qd + (blk * Q1D + qy) * (NQD * 64) + lane;
 #pragma unroll
-    for (int f = 0; f < NQD; ++f) q[f * qs] = T(cf[f]);
+    for (int f = 0; f < NQD; ++f) q[f * 64] = T(cf[f]);
   }
 }
 
 // ---- apply: direction dk (T) -> J dk (T) --------------------------------------------------
+// One wave walks R consecutive element rows of its strip.  Per element row: the direction's
+// node strips go to LDS, each lane contracts its quadrature column, and the per-lane
+// contributions are summed per node in LDS (the vertical edges shared by neighbouring elements
+// of the strip included).  Node row K of an element row is node row 0 of the next one: while the
+// next row belongs to the same wave its partial sums are carried in LDS.  Each velocity row of
+// the strip then takes one atomic add (one per node and strip instead of one per node and
+// element); energy rows are element-owned, position rows and constrained velocity rows are
+// written by the node's owner.  The velocity part of out must be zero on entry.
 template <int D1D, int Q1D, typename T, int VISC, int SRC>
-__global__ void __launch_bounds__(64) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC && sizeof(T) == 8 ? 1 : 2))) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
                                                 const T* __restrict__ dk, const T* __restrict__ qd,
-                                                int64_t qs, double tau_, T* __restrict__ out) {
+                                                int64_t qs, double tau_, T* __restrict__ out, int R) {
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
   constexpr int NQD = LinLayout<2, VISC, SRC>::NQD;
-  constexpr int NOUT = 2 * D1D * D1D + NLD;  // outputs per element
-  constexpr int NOP = NOUT | 1;              // odd LDS row length (bank spread)
+  constexpr int NVO = 2 * D1D * D1D;  // velocity outputs per element (energy: NLD < NVO, later)
+  constexpr int NOP = NVO | 1;        // odd LDS row length (bank spread)
   static_assert(Q1D % 2 == 0, "the quadrature rows are processed in pairs");
 
   __shared__ T sS[4][D1D][NS];  // dkx0 dkx1 dkv0 dkv1 strips
   __shared__ T sE[EPW * NLD];   // dk_e
-  __shared__ T sO[64][NOP];     // per-lane contributions to the element's outputs
+  __shared__ T sO[64][NOP];     // per-lane contributions to the element's outputs (velocity, then energy)
+  __shared__ T sC[2][2][NS];    // carried velocity sums of node row K (parity of the element row)
   __shared__ T sBG[2][Q1D][D1D];
   __shared__ T sBLt[Q1D][L1D];
 
   const int lane = threadIdx.x;
-  const int ey = blockIdx.y, ex0 = blockIdx.x * EPW;
-  const int nx = P.n[0];
+  const uint32_t tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int sx = tile % gridDim.x, sy = tile / gridDim.x;
+  const int ex0 = sx * EPW;
+  const int nx = P.n[0], ny = P.n[1];
   const int E = min(EPW, nx - ex0);
   const int ns = K * E + 1;
   const uint32_t ng0 = P.ng[0], ng1 = P.ng[1];
   const uint32_t N = (uint32_t)P.N, nh1 = 2 * N;
-  const uint32_t ebase = (uint32_t)ey * nx + ex0;
-  const uint32_t row0 = (uint32_t)(K * ey) * ng0 + (uint32_t)(K * ex0);  // first node of the strip
+  const T tau = T(tau_);
+  const bool last_x = (ex0 + E == nx);
+  const int ey0 = sy * R, ey1 = min(ey0 + R, ny);
+  const int z = lane / Q1D, qx = lane - z * Q1D;
+  const bool active = z < E;
 
-  constexpr int NTS = 4 * D1D * NS, RT = (NTS + 63) / 64;
-  constexpr int NLS = EPW * NLD, RL = (NLS + 63) / 64;
-  T tr[RT], lr[RL];
-#pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const int i = lane + 64 * r, si = i % NS, t = i / NS, b = t % D1D, f = t / D1D;
-    tr[r] = T(0);
-    if (i < NTS && si < ns)
-      tr[r] = ld32(dk, (f < 2 ? f * N : nh1 + (f - 2) * N) + row0 + (uint32_t)b * ng0 + si);
-  }
-#pragma unroll
-  for (int r = 0; r < RL; ++r) {
-    const int i = lane + 64 * r;
-    lr[r] = T(0);
-    if (i < E * NLD) lr[r] = ld32(dk, 2 * nh1 + ebase * NLD + i);
-  }
-  const int zl = lane / Q1D;
-  const double rj_l = P.rj0[ebase + (zl < E ? zl : 0)];
   for (int i = lane; i < Q1D * D1D; i += 64) {
     sBG[0][i / D1D][i % D1D] = tb.B[i / D1D][i % D1D];
     sBG[1][i / D1D][i % D1D] = tb.G[i / D1D][i % D1D];
   }
   for (int i = lane; i < Q1D * L1D; i += 64) sBLt[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
-#pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const int i = lane + 64 * r;
-    if (i < NTS) (&sS[0][0][0])[i] = tr[r];
-  }
-#pragma unroll
-  for (int r = 0; r < RL; ++r) {
-    const int i = lane + 64 * r;
-    if (i < NLS) sE[i] = lr[r];
-  }
-  __syncthreads();
 
-  const T tau = T(tau_);
-  const bool last_x = (ex0 + E == nx), last_y = (ey == P.n[1] - 1);
-  const int z = lane / Q1D, qx = lane - z * Q1D;
-  const bool active = z < E;
-  if (active) {
-    const int s0 = K * z;
-    T Bq[D1D], Gq[D1D], BLq[L1D];
+#pragma unroll 1
+  for (int ey = ey0; ey < ey1; ++ey) {
+    const int r = ey - ey0;
+    const bool last_y = (ey == ny - 1);
+    const uint32_t ebase = (uint32_t)ey * nx + ex0;
+    const uint32_t row0 = (uint32_t)(K * ey) * ng0 + (uint32_t)(K * ex0);  // first node of the strip
+
+    constexpr int NTS = 4 * D1D * NS, RT = (NTS + 63) / 64;
+    constexpr int NLS = EPW * NLD, RL = (NLS + 63) / 64;
+    // branch-free gathers: lanes past the strip re-read its last node (their LDS slots feed no
+    // output), so all loads of the element row are in flight together
+    T tr[RT], lr[RL];
 #pragma unroll
-    for (int a = 0; a < D1D; ++a) {
-      Bq[a] = sBG[0][qx][a];
-      Gq[a] = sBG[1][qx][a];
+    for (int q = 0; q < RT; ++q) {
+      const int i = lane + 64 * q, si = min(i % NS, ns - 1), t = min(i / NS, 4 * D1D - 1), b = t % D1D,
+                f = t / D1D;
+      tr[q] = ld32(dk, (f < 2 ? f * N : nh1 + (f - 2) * N) + row0 + (uint32_t)b * ng0 + si);
     }
 #pragma unroll
-    for (int a = 0; a < L1D; ++a) BLq[a] = sBLt[qx][a];
-    T AB[4][D1D], AG[4][D1D];
+    for (int q = 0; q < RL; ++q) lr[q] = ld32(dk, 2 * nh1 + ebase * NLD + min(lane + 64 * q, E * NLD - 1));
+    const double rj_l = P.rj0[ebase + (active ? z : 0)];
+    __syncthreads();  // the previous element row's readers of sS, sE and sO are done
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int b = 0; b < D1D; ++b) {
-        T ab = 0, ag = 0;
-#pragma unroll
-        for (int a = 0; a < D1D; ++a) {
-          const T xv = sS[f][b][s0 + a];
-          ab += Bq[a] * xv;
-          ag += Gq[a] * xv;
-        }
-        AB[f][b] = ab;
-        AG[f][b] = ag;
-      }
-    T ALd[L1D];
-#pragma unroll
-    for (int bl = 0; bl < L1D; ++bl) {
-      T a1 = 0;
-#pragma unroll
-      for (int al = 0; al < L1D; ++al) a1 += BLq[al] * sE[z * NLD + al + L1D * bl];
-      ALd[bl] = a1;
+    for (int q = 0; q < RT; ++q) {
+      const int i = lane + 64 * q;
+      if (i < NTS) (&sS[0][0][0])[i] = tr[q];
     }
-    T T0[2][D1D], T1[2][D1D], TL[L1D];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int b = 0; b < D1D; ++b) T0[c][b] = T1[c][b] = T(0);
+    for (int q = 0; q < RL; ++q) {
+      const int i = lane + 64 * q;
+      if (i < NLS) sE[i] = lr[q];
+    }
+    __syncthreads();
+
+    T TL[L1D];  // energy sums of the lane's column
 #pragma unroll
     for (int bl = 0; bl < L1D; ++bl) TL[bl] = T(0);
-    const T wx = tb.W[qx] * T(rj_l);
-    // coefficient rows of this wave: field f at qd[f qs + (blk Q1D + qy) 64 + lane]
-    const T* __restrict__ qb = qd + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (Q1D * 64);
-    const T* qf[NQD];
+    if (active) {
+      const int s0 = K * z;
+      T Bq[D1D], Gq[D1D], BLq[L1D];
 #pragma unroll
-    for (int f = 0; f < NQD; ++f) qf[f] = sbase(qb + f * qs);
-    auto row = [&](const int qy, const T* cf) {
-      // tau is folded into the coefficients: the contractions enter unscaled
-      T dJ[2][2], dGv[2][2], dkv[2];
+      for (int a = 0; a < D1D; ++a) {
+        Bq[a] = sBG[0][qx][a];
+        Gq[a] = sBG[1][qx][a];
+      }
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        T d0 = 0, d1 = 0, h0 = 0, h1 = 0, mv = 0;
+      for (int a = 0; a < L1D; ++a) BLq[a] = sBLt[qx][a];
+      T AB[4][D1D], AG[4][D1D];
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int b = 0; b < D1D; ++b) {
+          T ab = 0, ag = 0;
+#pragma unroll
+          for (int a = 0; a < D1D; ++a) {
+            const T xv = sS[f][b][s0 + a];
+            ab += Bq[a] * xv;
+            ag += Gq[a] * xv;
+          }
+          AB[f][b] = ab;
+          AG[f][b] = ag;
+        }
+      T ALd[L1D];
+#pragma unroll
+      for (int bl = 0; bl < L1D; ++bl) {
+        T a1 = 0;
+#pragma unroll
+        for (int al = 0; al < L1D; ++al) a1 += BLq[al] * sE[z * NLD + al + L1D * bl];
+        ALd[bl] = a1;
+      }
+      T T0[2][D1D], T1[2][D1D];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < D1D; ++b) T0[c][b] = T1[c][b] = T(0);
+      const T wx = tb.W[qx] * T(rj_l);
+      // coefficient rows of this element row: field f at qd[((blk Q1D + qy) NQD + f) 64 + lane]
+      const T* __restrict__ qb = qd + ((int64_t)ey * gridDim.x + sx) * (Q1D * NQD * 64);
+      auto ldrow = [&](const int qy, T* cf) {
+        const T* rb = sbase(qb + qy * (NQD * 64));
+#pragma unroll
+        for (int f = 0; f < NQD; ++f) cf[f] = ld32(rb, (uint32_t)(f * 64 + lane));
+      };
+      auto row = [&](const int qy, const T* cf) {
+        // tau is folded into the coefficients: the contractions enter unscaled
+        T dJ[2][2], dGv[2][2], dkv[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          T d0 = 0, d1 = 0, h0 = 0, h1 = 0, mv = 0;
+#pragma unroll
+          for (int b = 0; b < D1D; ++b) {
+            const T By = tb.B[qy][b], Gy = tb.G[qy][b];
+            d0 += By * AG[c][b];
+            d1 += Gy * AB[c][b];
+            h0 += By * AG[2 + c][b];
+            h1 += Gy * AB[2 + c][b];
+            mv += By * AB[2 + c][b];
+          }
+          dJ[c][0] = d0;
+          dJ[c][1] = d1;
+          dGv[c][0] = h0;
+          dGv[c][1] = h1;
+          dkv[c] = mv;
+        }
+        T dke = 0;
+#pragma unroll
+        for (int bl = 0; bl < L1D; ++bl) dke += tb.BL[qy][bl] * ALd[bl];
+        const T mq = wx * tb.W[qy];
+        T dS[2][2], ds;
+        lin_apply<2, T, VISC>(cf, dJ, dGv, dke, dS, ds);
+        T cl = mq * dke - ds;
+        if constexpr (SRC != 0) {
+          T dx0 = 0, dx1 = 0;
+#pragma unroll
+          for (int b = 0; b < D1D; ++b) {
+            dx0 += tb.B[qy][b] * AB[0][b];
+            dx1 += tb.B[qy][b] * AB[1][b];
+          }
+          cl -= cf[NQD - 2] * dx0 + cf[NQD - 1] * dx1;
+        }
+        const T mv0 = mq * dkv[0], mv1 = mq * dkv[1];
 #pragma unroll
         for (int b = 0; b < D1D; ++b) {
           const T By = tb.B[qy][b], Gy = tb.G[qy][b];
-          d0 += By * AG[c][b];
-          d1 += Gy * AB[c][b];
-          h0 += By * AG[2 + c][b];
-          h1 += Gy * AB[2 + c][b];
-          mv += By * AB[2 + c][b];
+          T0[0][b] += By * dS[0][0];
+          T0[1][b] += By * dS[1][0];
+          T1[0][b] += Gy * dS[0][1] + By * mv0;
+          T1[1][b] += Gy * dS[1][1] + By * mv1;
         }
-        dJ[c][0] = d0;
-        dJ[c][1] = d1;
-        dGv[c][0] = h0;
-        dGv[c][1] = h1;
-        dkv[c] = mv;
-      }
-      T dke = 0;
 #pragma unroll
-      for (int bl = 0; bl < L1D; ++bl) dke += tb.BL[qy][bl] * ALd[bl];
-      const T mq = wx * tb.W[qy];
-      T dS[2][2], ds;
-      lin_apply<2, T, VISC>(cf, dJ, dGv, dke, dS, ds);
-      T cl = mq * dke - ds;
-      if constexpr (SRC != 0) {
-        T dx0 = 0, dx1 = 0;
-#pragma unroll
-        for (int b = 0; b < D1D; ++b) {
-          dx0 += tb.B[qy][b] * AB[0][b];
-          dx1 += tb.B[qy][b] * AB[1][b];
-        }
-        cl -= cf[NQD - 2] * dx0 + cf[NQD - 1] * dx1;
-      }
-      const T mv0 = mq * dkv[0], mv1 = mq * dkv[1];
-#pragma unroll
-      for (int b = 0; b < D1D; ++b) {
-        const T By = tb.B[qy][b], Gy = tb.G[qy][b];
-        T0[0][b] += By * dS[0][0];
-        T0[1][b] += By * dS[1][0];
-        T1[0][b] += Gy * dS[0][1] + By * mv0;
-        T1[1][b] += Gy * dS[1][1] + By * mv1;
-      }
-#pragma unroll
-      for (int bl = 0; bl < L1D; ++bl) TL[bl] += tb.BL[qy][bl] * cl;
-    };
-    // two coefficient buffers: the loads of one row are in flight during the other's arithmetic
-    T ca[NQD], cb[NQD];
-#pragma unroll
-    for (int f = 0; f < NQD; ++f) ca[f] = ld32(qf[f], (uint32_t)lane);
+        for (int bl = 0; bl < L1D; ++bl) TL[bl] += tb.BL[qy][bl] * cl;
+      };
+      // two coefficient buffers: the loads of one row are in flight during the other's arithmetic
+      T ca[NQD], cb[NQD];
+      ldrow(0, ca);
 #pragma unroll 1
-    for (int qy = 0; qy < Q1D; qy += 2) {
-#pragma unroll
-      for (int f = 0; f < NQD; ++f) cb[f] = ld32(qf[f], (uint32_t)((qy + 1) * 64 + lane));
-      row(qy, ca);
-      if (qy + 2 < Q1D) {
-#pragma unroll
-        for (int f = 0; f < NQD; ++f) ca[f] = ld32(qf[f], (uint32_t)((qy + 2) * 64 + lane));
+      for (int qy = 0; qy < Q1D; qy += 2) {
+        ldrow(qy + 1, cb);
+        row(qy, ca);
+        if (qy + 2 < Q1D) ldrow(qy + 2, ca);
+        row(qy + 1, cb);
       }
-      row(qy + 1, cb);
+#pragma unroll
+      for (int a = 0; a < D1D; ++a) {  // reloaded: not kept live through the row loop
+        Bq[a] = sBG[0][qx][a];
+        Gq[a] = sBG[1][qx][a];
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < D1D; ++b)
+#pragma unroll
+          for (int a = 0; a < D1D; ++a)
+            sO[lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
     }
+    __syncthreads();
+
+    // node rows of the strip: position rows (dk_x - tau dk_v) and constrained velocity rows
+    // (dk_v) by the node's single owner; every other velocity row sums the Q1D columns of the
+    // (one or two) elements of the strip that hold the node
+    T* const cw = &sC[r & 1][0][0];
+    const T* const cr = &sC[(r + 1) & 1][0][0];
+#pragma unroll 1
+    for (int i = lane; i < 2 * D1D * NS; i += 64) {
+      const int s = i % NS, t = i / NS, b = t % D1D, c = t / D1D;
+      if (s >= ns) continue;
+      const uint32_t I = K * ex0 + s, J = K * ey + b;
+      const uint32_t gi = c * N + row0 + (uint32_t)b * ng0 + s;
+      const bool own = (s < K * E || last_x) && (b < K || last_y);
+      const T dkv = sS[2 + c][b][s];
+      if (own) out[gi] = sS[c][b][s] - tau * dkv;
+      const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
+      if (cons) {
+        if (own) out[nh1 + gi] = dkv;
+        continue;
+      }
+      const int zz = s / K, a = s - K * zz;
+      T f = T(0);
+      if (zz < E) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+        for (int q = 0; q < Q1D; ++q) f += sO[zz * Q1D + q][c * D1D * D1D + b * D1D + a];
+      }
+      if (a == 0 && zz > 0) {
 #pragma unroll
-      for (int b = 0; b < D1D; ++b)
+        for (int q = 0; q < Q1D; ++q) f += sO[(zz - 1) * Q1D + q][c * D1D * D1D + b * D1D + K];
+      }
+      if (b == K && !last_y && ey + 1 < ey1) {  // completed by the next element row of this wave
+        cw[c * NS + s] = f;
+        continue;
+      }
+      if (b == 0 && r > 0) f += cr[c * NS + s];
+      // atomics also where no other wave adds to the node: plain stores of the partial cache
+      // lines of a strip cost more than the atomic updates on this chip
+      unsafeAtomicAdd(&out[nh1 + gi], f);
+    }
+    // energy rows (element-owned): the column sums go through sO once the velocity is done
+    __syncthreads();
+    if (active) {
 #pragma unroll
-        for (int a = 0; a < D1D; ++a) sO[lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
+      for (int bl = 0; bl < L1D; ++bl)
 #pragma unroll
-    for (int bl = 0; bl < L1D; ++bl)
-#pragma unroll
-      for (int al = 0; al < L1D; ++al) sO[lane][2 * D1D * D1D + bl * L1D + al] = BLq[al] * TL[bl];
-  } else {
-    for (int t = 0; t < NOUT; ++t) sO[lane][t] = T(0);
-  }
-  __syncthreads();
-  // combine the Q1D column contributions of each element and scatter (atomics: shared nodes)
-  if (active) {
-    const int ex = ex0 + z;
-    const uint32_t e = ebase + z;
-    for (int t = qx; t < NOUT; t += Q1D) {
+        for (int al = 0; al < L1D; ++al) sO[lane][bl * L1D + al] = sBLt[qx][al] * TL[bl];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int i = lane; i < E * NLD; i += 64) {
+      const int zz = i / NLD, t = i % NLD;
       T o = 0;
 #pragma unroll
-      for (int q = 0; q < Q1D; ++q) o += sO[z * Q1D + q][t];
-      if (t < 2 * D1D * D1D) {
-        const int c = t / (D1D * D1D), r = t % (D1D * D1D), b = r / D1D, a = r % D1D;
-        const uint32_t I = K * ex + a, J = K * ey + b;
-        const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
-        if (!cons) unsafeAtomicAdd(&out[nh1 + c * N + J * ng0 + I], o);
-      } else {
-        out[2 * nh1 + e * NLD + (t - 2 * D1D * D1D)] = o;
-      }
+      for (int q = 0; q < Q1D; ++q) o += sO[zz * Q1D + q][t];
+      out[2 * nh1 + ebase * NLD + i] = o;
     }
-  }
-  // position rows (dk_x - tau dk_v) and constrained velocity rows (dk_v), by node owner
-  for (int i = lane; i < 2 * D1D * NS; i += 64) {
-    const int s = i % NS, t = i / NS, b = t % D1D, c = t / D1D;
-    if (s >= ns || !((s < K * E || last_x) && (b < K || last_y))) continue;
-    const uint32_t I = K * ex0 + s, J = K * ey + b;
-    const uint32_t gi = c * N + row0 + (uint32_t)b * ng0 + s;
-    const T dkv = sS[2 + c][b][s];
-    out[gi] = sS[c][b][s] - tau * dkv;
-    const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
-    if (cons) unsafeAtomicAdd(&out[nh1 + gi], dkv);
   }
 }
 
@@ -401,6 +444,18 @@ static dim3 lin2d_grid(const ilh_ctx* c) {
   return dim3((c->n[0] + EPW - 1) / EPW, c->n[1]);
 }
 
+// Element rows walked by one apply wave: 1 while the one-row grid has few waves per SIMD
+// (small meshes are latency-bound), more on large meshes, where fewer wave-shared nodes mean
+// fewer atomics.  c->apply_rows > 0 overrides the choice.
+static int apply_rows(const ilh_ctx* c) {
+  if (c->apply_rows > 0) return std::min(c->apply_rows, c->n[1]);
+  const dim3 g = lin2d_grid(c);
+  const int64_t waves = (int64_t)g.x * g.y;
+  int R = 1;
+  while (R < 8 && waves / (2 * R) >= 16384) R *= 2;
+  return R;
+}
+
 int lin2d_nqd(const ilh_ctx* c) { return (c->kp.visc ? 16 : 10) + (c->kp.tg_source ? 2 : 0); }
 
 int64_t lin2d_stride(const ilh_ctx* c) {
@@ -418,8 +473,10 @@ static void lin_t(ilh_ctx* c, T* qd) {
 template <int K, typename T, int VISC, int SRC>
 static void apply_t(ilh_ctx* c, const T* dk, const T* qd, T* out) {
   constexpr int D1D = K + 1, Q1D = 2 * K;
-  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC>, lin2d_grid(c), dim3(64), 0, c->kp, make_tab2<T, D1D, Q1D>(c), dk,
-          qd, lin2d_stride(c), c->lin_tau, out);
+  const int R = apply_rows(c);
+  const dim3 g = lin2d_grid(c);
+  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC>, dim3(g.x, (g.y + R - 1) / R), dim3(64), 0, c->kp,
+          make_tab2<T, D1D, Q1D>(c), dk, qd, lin2d_stride(c), c->lin_tau, out, R);
 }
 
 template <typename T>

@@ -1052,6 +1052,13 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
 
 extern "C" {
 
+int ilh_set_apply_rows(ilh_ctx* c, int rows) {
+  if (!c) return ILH_EINVAL;
+  if (rows < 0) return fail(c, ILH_EINVAL, "apply rows must be >= 0");
+  c->apply_rows = rows;
+  return ILH_OK;
+}
+
 int ilh_set_kernel_variant(ilh_ctx* c, int variant) {
   if (!c) return ILH_EINVAL;
   if (variant < 0 || variant > 2) return fail(c, ILH_EINVAL, "kernel variant must be 0, 1 or 2");

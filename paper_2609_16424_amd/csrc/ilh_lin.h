@@ -214,6 +214,18 @@ __device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i) {
   return *(const T __attribute__((address_space(1)))*)p;
 }
 
+// Work-group -> tile map for a chip of 8 XCDs, each with its own L2: work-groups are handed to
+// the XCDs in turn (w mod 8), so neighbouring tiles would sit on different L2s and the cache
+// lines they share (node rows at strip ends, the direction's overlapping strips) would be
+// fetched and partially written back once per XCD.  The map gives XCD x the contiguous tile
+// range [x nb/8, (x+1) nb/8) instead: a band of the mesh per L2.  It is a bijection of [0, nb),
+// so results never depend on how the hardware actually distributes the work-groups.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t w, uint32_t nb) {
+  constexpr uint32_t NX = 8;
+  const uint32_t x = w % NX, slot = w / NX, q = nb / NX, rem = nb % NX;
+  return x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
+}
+
 // A wave-uniform pointer made opaque to the compiler (scalar registers): loads from it take the
 // scalar-base + 32-bit vector-offset form instead of per-lane 64-bit address arithmetic.
 template <typename T>

@@ -159,6 +159,32 @@ def test_jvp_variants_agree(prob, n, k, visc, prec, tol):
     assert rel(out[2], out[1]) <= tol
 
 
+@pytest.mark.parametrize("prob,n,k,visc", [("tg2d", (23, 7), 3, None), ("triple", (21, 9), 3, "const"),
+                                           ("triple", (33, 5), 2, "formula"), ("tg2d", (12, 11), 3, "formula"),
+                                           ("tg2d", (10, 1), 3, None)])
+def test_apply_rows_match_oracle(prob, n, k, visc):
+    """The linearised apply with one wave walking R element rows (partial last walk, partial last
+    strip) against the oracle's complex-step Jacobian action, FP64 and FP32."""
+    from oracle.krylov import jvp_cs
+    O, G = make_pair(prob, n, k, visc)
+    u = random_state(O, 51)
+    kk = 0.1 * random_dir(O, 52)
+    dk = random_dir(O, 53)
+    tau = 0.003
+    ref = jvp_cs(lambda q: O.residual(q, u, tau), kk, dk)
+    G.linearize(to_dev(kk), to_dev(u), tau)
+    for R in (1, 2, 3, 4, 8):
+        G.set_apply_rows(R)
+        a64 = to_np(G.jvp_lin(to_dev(dk), 64))
+        a32 = to_np(G.jvp_lin(to_dev(dk, torch.float32), 32))
+        assert rel(a64, ref) <= 1e-12, R
+        assert rel(a32, ref) <= 1e-5, R
+    G.set_apply_rows(0)
+    from paper_2609_16424_amd import IlhError
+    with pytest.raises(IlhError):
+        G.set_apply_rows(-1)
+
+
 def test_linearised_coefficients_follow_the_point():
     """Stored tangent coefficients are re-evaluated after each linearisation, per precision."""
     from oracle.krylov import jvp_cs
@@ -197,11 +223,13 @@ def test_linearised_large_mesh(n, k):
     # cancellation at this perturbation, so the two kernels' rounding differs by up to ~3e-13
     for prec, tol in ((64, 1e-12), (32, 5e-6)):
         d = dk if prec == 64 else dk.float()
-        G.set_kernel_variant("lin")
-        a = G.jvp_lin(d, prec).double()
         G.set_kernel_variant("generic")
         b = G.jvp_lin(d, prec).double()
         G.set_kernel_variant("lin")
-        for lo, hi in ((0, G.nh1), (G.nh1, 2 * G.nh1), (2 * G.nh1, G.nblock)):
-            err = float(torch.linalg.norm(a[lo:hi] - b[lo:hi]) / torch.linalg.norm(b[lo:hi]))
-            assert err <= tol, (prec, lo, err)
+        for R in (0, 1, 4, 8):  # by mesh size, then forced walks of 1, 4 and 8 element rows
+            G.set_apply_rows(R)
+            a = G.jvp_lin(d, prec).double()
+            for lo, hi in ((0, G.nh1), (G.nh1, 2 * G.nh1), (2 * G.nh1, G.nblock)):
+                err = float(torch.linalg.norm(a[lo:hi] - b[lo:hi]) / torch.linalg.norm(b[lo:hi]))
+                assert err <= tol, (prec, R, lo, err)
+        G.set_apply_rows(0)
