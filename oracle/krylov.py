@@ -5,6 +5,8 @@
   the exact directional derivative up to rounding; it replaces the paper's automatic
   differentiation of the quadrature-point kernel (eq. pa_jac_action).  The oracle holds
   no hand-written tangent.
+* Transpose actions J^T y from complex-step columns, compressed by a colouring of the
+  columns that reach disjoint rows (vjp_colored).
 * Jacobi preconditioned CG (Sec. 2.2 mass solves), restarted flexible GMRES and inexact
   Newton with a backtracking line search that rejects steps producing a non-positive
   Jacobian determinant (Sec. 3.5, eq. newton_linear).
@@ -305,3 +307,90 @@ def adaptive_run(hyd, u0, tf, fscfl, scheme="sd2", opts=None, max_reject=60):
         steps += 1
         dt = 1.05 * dtt if nmax <= 1 else dtt
     return u, steps, rejected
+
+
+def vjp_colored(hyd, fun, x, y, h=CS_H):
+    """Transpose action J^T y of the Jacobian of ``fun`` (the stage residual of ``hyd``) at x.
+
+    The Jacobian of the partial-assembly residual couples a column only to the rows of the
+    elements that hold it (eq. pa_jac_action and its transpose): H1 node p reaches the H1 rows
+    of nodes within k grid steps of p in every direction and the L2 rows of the elements whose
+    node box contains p; an L2 degree of freedom of element e reaches the H1 rows of e's nodes
+    and e's own L2 rows.  Columns whose node indices agree modulo 2k+1 (H1), or whose element
+    indices agree modulo 3 with the same local index (L2), reach disjoint sets of rows, so one
+    complex-step Jacobian action along their sum returns each of their columns intact
+    (Curtis-Powell-Reid compression).  Entry j of J^T y is then the sum over j's rows of
+    (J e_class)_i y_i.  Exact to rounding, like the columns it is built from.
+    """
+    m = hyd.mesh
+    d, k, N = hyd.dim, m.k, m.N
+    ng = np.array(m.ng)
+    ne = np.array(m.n)
+    P = 2 * k + 1
+    nh = hyd.nh1
+    stride = np.cumprod([1] + list(ng[:-1]))
+    qg = m.node_grid_index                    # (d, N): grid coordinates of every node
+    eg = m.elem_index                         # (d, Ne): element coordinates
+    # every block row: H1 rows (x, then v; component-major) carry a node, L2 rows an element
+    h1_node = np.tile(np.arange(N), 2 * d)    # node of H1 row r
+    l2_elem = np.repeat(np.arange(m.Ne), m.Nl)
+    out = np.zeros(x.size)
+    y_h1, y_l2 = y[:2 * nh], y[2 * nh:]
+
+    def accumulate(g, col_h1, col_l2):
+        """Add g_i y_i to the column associated with each row (-1: row reached by none)."""
+        g_h1, g_l2 = g[:2 * nh], g[2 * nh:]
+        assert np.all(g_h1[col_h1 < 0] == 0.0) and np.all(g_l2[col_l2 < 0] == 0.0)
+        sel = col_h1 >= 0
+        np.add.at(out, col_h1[sel], g_h1[sel] * y_h1[sel])
+        sel = col_l2 >= 0
+        np.add.at(out, col_l2[sel], g_l2[sel] * y_l2[sel])
+
+    # H1 columns: field f (0 = x, 1 = v), component c, node residues o modulo P
+    for f in range(2):
+        for c in range(d):
+            for o in np.ndindex(*([P] * d)):
+                o = np.array(o)
+                members = np.all(qg % P == o[:, None], axis=0)
+                if not members.any():
+                    continue
+                base = (f * d + c) * N
+                dx = np.zeros(x.size)
+                dx[base + np.nonzero(members)[0]] = 1.0
+                g = jvp_cs(fun, x, dx, h)
+                # H1 rows: the class member nearest to the row's node in every direction
+                q = qg[:, h1_node]
+                p = o[:, None] + P * np.round((q - o[:, None]) / P).astype(np.int64)
+                ok = np.all((np.abs(q - p) <= k) & (p >= 0) & (p < ng[:, None]), axis=0)
+                col_h1 = np.where(ok, base + (p * stride[:, None]).sum(axis=0), -1)
+                # L2 rows: the class member inside the row element's node box
+                lo = k * eg[:, l2_elem]
+                p = lo + (o[:, None] - lo) % P
+                ok = np.all((p - lo <= k) & (p < ng[:, None]), axis=0)
+                col_l2 = np.where(ok, base + (p * stride[:, None]).sum(axis=0), -1)
+                accumulate(g, col_h1, col_l2)
+    # L2 columns: local index l, element residues o modulo 3
+    for l in range(m.Nl):
+        for o in np.ndindex(*([3] * d)):
+            o = np.array(o)
+            members = np.all(eg % 3 == o[:, None], axis=0)
+            if not members.any():
+                continue
+            dx = np.zeros(x.size)
+            dx[2 * nh + np.nonzero(members)[0] * m.Nl + l] = 1.0
+            g = jvp_cs(fun, x, dx, h)
+            # H1 rows: along each direction the elements holding the node are
+            # floor(q/k) and, on an element boundary, the one before; one of them is in the class
+            q = qg[:, h1_node]
+            e_hi = np.minimum(q // k, ne[:, None] - 1)
+            e_lo = np.maximum((q + k - 1) // k - 1, 0)
+            e_pick = np.where(e_hi % 3 == o[:, None], e_hi, np.where(e_lo % 3 == o[:, None], e_lo, -1))
+            ok = np.all((e_pick >= 0) & (k * e_pick <= q) & (q <= k * e_pick + k), axis=0)
+            estr = np.cumprod([1] + list(ne[:-1]))
+            e_col = (np.where(e_pick >= 0, e_pick, 0) * estr[:, None]).sum(axis=0)
+            col_h1 = np.where(ok, 2 * nh + e_col * m.Nl + l, -1)
+            # L2 rows: only the element's own
+            ok = np.all(eg[:, l2_elem] % 3 == o[:, None], axis=0)
+            col_l2 = np.where(ok, 2 * nh + l2_elem * m.Nl + l, -1)
+            accumulate(g, col_h1, col_l2)
+    return out
