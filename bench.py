@@ -283,6 +283,14 @@ def main():
     tb_ = H.timing_read()
     H.timing(False)
     burst_us = 1e3 * tb_["jvp"][0] / max(tb_["jvp"][1], 1)
+    # the transpose action J^T y at the same point, back to back (same bytes moved)
+    H.vjp_lin(dkb, 32, outb)
+    H.timing(True)
+    for _ in range(50):
+        H.vjp_lin(dkb, 32, outb)
+    tv_ = H.timing_read()
+    H.timing(False)
+    vjp_us = 1e3 * tv_["transpose"][0] / max(tv_["transpose"][1], 1)
     u32 = u.clone()
     newton = [s["newton"] for s in stats]
     gmres = [s["gmres"] for s in stats]
@@ -459,6 +467,9 @@ def main():
                      "kernel": KERNEL_NAMES[args.jvp_variant], "bytes_per_launch": bytes32,
                      "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n,
                      "avg_launch_us_back_to_back": burst_us},
+        "transpose_action": {"kernel": "k_vjp2d_q<4,6,float,visc=0,src=1>", "avg_launch_us_back_to_back": vjp_us,
+                             "qps": H.nqp / (1e-6 * vjp_us), "bytes_per_launch": bytes32,
+                             "frac": bytes32 / (1e-6 * vjp_us) / 1e9 / HBM_PEAK_GBS},
         "jvp_variant": args.jvp_variant,
         "jvp_apply_qps": H.nqp / jvp_avg_s,
         "linearize": {"launches": lin_n, "avg_launch_us": 1e3 * lin_ms / max(lin_n, 1),

@@ -141,6 +141,24 @@ int ilh_jvp_lin(ilh_ctx* ctx, int prec, const void* dk, void* jdk);
 int ilh_jvp(ilh_ctx* ctx, int prec, const double* k, const double* u, double tau,
             const void* dk, void* jdk);
 
+/* Transpose Jacobian action J^T y at the stored linearisation point (the transpose of
+ * eq. pa_jac_action; Sec. 3.4 notes that transpose actions keep the gather - pointwise -
+ * scatter structure):
+ *   (J^T y)_x = y_x + d(F 1)^T[y~_v] + (terms of d(F^T w_v) and db along dk_x)^T[y_e]
+ *   (J^T y)_v = M_V y~_v - tau y_x + d(F 1)^T[y~_v] + d(F^T w_v)^T[y_e] + y_v on constrained rows
+ *   (J^T y)_e = M_E y_e + (derivatives along dk_e)^T[y~_v, y_e]
+ * where y~_v is y_v with its constrained rows set to zero (those rows of R are the identity)
+ * and every derivative carries the stage factor tau as in ilh_jvp_lin.  It uses the same
+ * stored tangent coefficients as ilh_jvp_lin (evaluated on the first call of a precision after
+ * ilh_linearize) and satisfies <y, J dk> = <J^T y, dk> to rounding.  prec = 64: y, jty double
+ * [block]; prec = 32: float [block], FP32 arithmetic.  Built for 2D meshes with k = 2, 3
+ * (otherwise ILH_EINVAL). */
+int ilh_vjp_lin(ilh_ctx* ctx, int prec, const void* y, void* jty);
+
+/* ilh_linearize followed by ilh_vjp_lin. */
+int ilh_vjp(ilh_ctx* ctx, int prec, const double* k, const double* u, double tau,
+            const void* y, void* jty);
+
 /* y [H1] = M_V x [H1] (partial assembly, eq. matrices; no boundary conditions). */
 int ilh_mass_v_apply(ilh_ctx* ctx, const double* x, double* y);
 
@@ -271,11 +289,11 @@ int ilh_adaptive_step(ilh_ctx* ctx, double* u, double* dt, double dt_max, int sc
  * timed kernel classes: 0 = Jacobian-action element kernel, 1 = residual element kernel,
  * 2 = velocity-mass element kernel, 3 = Krylov orthogonalisation (multi-dot / multi-axpy),
  * 4 = other Newton-Krylov vector kernels, 5 = linearisation kernel of the linearised
- * Jacobian action (once per linearisation point and precision).  For classes 0, 1 and 5 the
- * events are attached to the kernel dispatch itself.  ilh_timing_enable(ctx, 1) resets the
+ * Jacobian action (once per linearisation point and precision), 6 = transpose-action kernel.
+ * For classes 0, 1, 5 and 6 the events are attached to the kernel dispatch itself.  ilh_timing_enable(ctx, 1) resets the
  * counters; ilh_timing_read synchronises the stream and returns, per class, the summed kernel
  * time in milliseconds and the number of timed launches (host arrays of ILH_TIMING_CLASSES). */
-#define ILH_TIMING_CLASSES 6
+#define ILH_TIMING_CLASSES 7
 /* Select the Jacobian-action kernels (all compute the same operator, for cross-checking):
  *   0 (default) linearised: where one exists (2D, k = 2, 3; 3D, k = 2 without the TG
  *     source), the tangent coefficients of every quadrature point are evaluated once per

@@ -170,6 +170,19 @@ class Hydro:
         self.linearize(k, u, tau)
         return self.jvp_lin(dk, prec)
 
+    def vjp_lin(self, y, prec=64, out=None):
+        """Transpose Jacobian action J^T y at the stored linearisation point (2D, k = 2, 3)."""
+        dt = torch.float64 if prec == 64 else torch.float32
+        o = self.new(dtype=dt) if out is None else out
+        self._stream()
+        self._check(self.lib.ilh_vjp_lin(self.ctx, prec, self._vec(y, self.nblock, dt, "y"),
+                                         self._vec(o, self.nblock, dt, "out")))
+        return o
+
+    def vjp(self, k, u, tau, y, prec=64):
+        self.linearize(k, u, tau)
+        return self.vjp_lin(y, prec)
+
     def mass_v_apply(self, x):
         y = self.new(self.nh1)
         self._stream()
@@ -259,7 +272,7 @@ class Hydro:
         self._check(self.lib.ilh_timing_enable(self.ctx, int(bool(on))))
 
     def timing_read(self):
-        names = ("jvp", "residual", "mass", "krylov", "precond", "linearize")
+        names = ("jvp", "residual", "mass", "krylov", "precond", "linearize", "transpose")
         ms = (C.c_double * len(names))()
         cnt = (C.c_int64 * len(names))()
         self._check(self.lib.ilh_timing_read(self.ctx, ms, cnt))
@@ -359,7 +372,8 @@ class ForceFn(torch.autograd.Function):
 
 
 class ResidualFn(torch.autograd.Function):
-    """R(k; tau, u) with forward-mode derivative J dk from ilh_jvp (FP64)."""
+    """R(k; tau, u) with forward-mode derivative J dk from ilh_jvp and reverse-mode derivative
+    J^T g from ilh_vjp (FP64; the reverse mode is built for 2D meshes with k = 2, 3)."""
 
     @staticmethod
     def forward(hydro, k, u, tau):
@@ -370,6 +384,7 @@ class ResidualFn(torch.autograd.Function):
         hydro, k, u, tau = inputs
         ctx.hydro, ctx.tau = hydro, float(tau)
         ctx.save_for_forward(k, u)
+        ctx.save_for_backward(k, u)
 
     @staticmethod
     def jvp(ctx, _h, dk, du, _t):
@@ -381,8 +396,12 @@ class ResidualFn(torch.autograd.Function):
         return ctx.hydro.jvp(k.detach().contiguous(), u.detach().contiguous(), ctx.tau, dk.contiguous(), 64)
 
     @staticmethod
-    def backward(ctx, *grads):
-        raise NotImplementedError("the transpose (VJP) action is not part of this library")
+    def backward(ctx, g):
+        if ctx.needs_input_grad[2]:
+            raise NotImplementedError("gradients in u are not supported; differentiate in k")
+        k, u = ctx.saved_tensors
+        gk = ctx.hydro.vjp(k.detach().contiguous(), u.detach().contiguous(), ctx.tau, g.contiguous(), 64)
+        return None, gk, None, None
 
 
 def __getattr__(name):

@@ -648,6 +648,36 @@ int ilh_jvp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, 
   return ilh_jvp_lin(c, prec, dk, jdk);
 }
 
+int ilh_vjp_lin(ilh_ctx* c, int prec, const void* y, void* jty) {
+  if (!c || !y || !jty) return ILH_EINVAL;
+  if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+  if (!lin2d_available(c)) return fail(c, ILH_EINVAL, "the transpose action is built for 2D meshes with k = 2, 3");
+  int st;
+  if (prec == 64) {
+    if ((st = launch_fill(c, (double*)jty, 0.0, 2 * c->nh1))) return st;
+  } else {
+    if ((st = launch_fillf(c, (float*)jty, 0.0f, 2 * c->nh1))) return st;
+  }
+  const int p = prec == 64 ? 1 : 0;
+  if (!c->qd_ok[p]) {
+    const int ls = tstart_k(c, 5);
+    st = launch_lin2d(c, prec);
+    tstop_k(c, ls);
+    if (st) return st;
+    c->qd_ok[p] = true;
+  }
+  const int slot = tstart_k(c, 6);
+  st = launch_vjp2d_q(c, prec, y, jty);
+  tstop_k(c, slot);
+  return st;
+}
+
+int ilh_vjp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, const void* y, void* jty) {
+  int st = ilh_linearize(c, k, u, tau);
+  if (st) return st;
+  return ilh_vjp_lin(c, prec, y, jty);
+}
+
 int ilh_mass_v_apply(ilh_ctx* c, const double* x, double* y) {
   if (!c || !x || !y) return ILH_EINVAL;
   return launch_mass_v(c, x, y, 0);

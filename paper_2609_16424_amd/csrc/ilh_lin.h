@@ -206,6 +206,101 @@ __device__ __forceinline__ void lin_apply(const T* c, const T dJ[D][D], const T 
   }
 }
 
+// Transpose of lin_apply at one point: given the weights A (D x D) of dS and a_s of ds, the
+// weights GJ, GGv, ge of (dJ, dGv, de) such that <A, dS> + a_s ds = <GJ, dJ> + <GGv, dGv> + ge de
+// for every direction.  Reverse sweep of the forward formulas (file comment):
+//   Gsig = A J^-1 + a_s gv,   Gdji = A^T Sig,   Gdgv = a_s Sig + m_q nu sym(Gsig) + nub a1 I,
+//   Pb = -tr Gsig,  nub = <Gsig, sym gv>,       ge = cP Pb + nub a2,
+//   Ub = nub a0 I - gv^T Gdgv - J^-T Gdji,      GJ = Ub J^-T,  GGv = Gdgv J^-T.
+// Without viscosity Sig = -P I and the nu terms vanish.
+template <int D, typename T, int VISC>
+__device__ __forceinline__ void lin_apply_t(const T* c, const T A[D][D], T as, T GJ[D][D], T GGv[D][D], T& ge) {
+  constexpr int B = 2 * D * D;
+  constexpr int NSYM = D * (D + 1) / 2;
+  T Ji[D][D], gv[D][D], Sig[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      Ji[r][b] = c[r * D + b];
+      gv[r][b] = c[D * D + r * D + b];
+    }
+  T cP, mnu = T(0), a0 = T(0), a1 = T(0), a2 = T(0);
+  if constexpr (!VISC) {
+    const T Pq = c[B];
+    cP = c[B + 1];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int q = 0; q < D; ++q) Sig[r][q] = r == q ? -Pq : T(0);
+  } else {
+    cP = c[B + NSYM];
+    mnu = c[B + NSYM + 1];
+    a0 = c[B + NSYM + 2];
+    a1 = c[B + NSYM + 3];
+    a2 = c[B + NSYM + 4];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int q = 0; q < D; ++q) Sig[r][q] = c[B + sym_idx<D>(r, q)];
+  }
+  T Gs[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T acc = as * gv[r][b];
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc += A[r][a] * Ji[a][b];
+      Gs[r][b] = acc;
+    }
+  T trGs = 0, nub = 0;
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    trGs += Gs[r][r];
+#pragma unroll
+    for (int q = 0; q < D; ++q) nub += Gs[r][q] * (T(0.5) * (gv[r][q] + gv[q][r]));
+  }
+  if constexpr (!VISC) nub = T(0);
+  ge = -cP * trGs + nub * a2;
+  T Gdgv[D][D], Gdji[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T g = as * Sig[r][b] + (r == b ? nub * a1 : T(0));
+      if constexpr (VISC) g += mnu * (T(0.5) * (Gs[r][b] + Gs[b][r]));
+      Gdgv[r][b] = g;
+      T acc = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc += A[q][r] * Sig[q][b];
+      Gdji[r][b] = acc;
+    }
+  T Ub[D][D];
+#pragma unroll
+  for (int q = 0; q < D; ++q)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T acc = q == b ? nub * a0 : T(0);
+#pragma unroll
+      for (int r = 0; r < D; ++r) acc -= gv[r][q] * Gdgv[r][b] + Ji[r][q] * Gdji[r][b];
+      Ub[q][b] = acc;
+    }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T gj = 0, gg = 0;
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        gj += Ub[a][b] * Ji[q][b];
+        gg += Gdgv[a][b] * Ji[q][b];
+      }
+      GJ[a][q] = gj;
+      GGv[a][q] = gg;
+    }
+}
+
 // 32-bit element offset from a uniform base (byte offsets below 4 GiB, checked on the host).
 typedef const char __attribute__((address_space(1))) * gbytes;
 template <typename T>

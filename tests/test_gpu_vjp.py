@@ -1,0 +1,85 @@
+"""GPU parity of the transpose Jacobian action J^T y (ilh_vjp_lin) against the oracle.
+
+The oracle's transpose action is built from complex-step columns (oracle.krylov.vjp_colored,
+pinned to the dense transpose and the adjoint identity).  Meshes span two work-group strips
+with a partial last strip (10 elements per wave at k = 3, 16 at k = 2).  At full benchmark size
+the GPU pair is checked by the adjoint identity <y, J dk> = <J^T y, dk>.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import make_pair, random_dir, random_state, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("tg2d", (12, 3), 3, None), ("tg2d", (18, 2), 2, None), ("triple", (11, 3), 3, "const"),
+         ("triple", (7, 3), 2, "formula")]
+
+
+@pytest.mark.parametrize("prob,n,k,visc", CASES)
+def test_vjp_matches_oracle(prob, n, k, visc):
+    from oracle.krylov import vjp_colored
+    O, G = make_pair(prob, n, k, visc, width=0.05 if visc == "const" else 1e-3)
+    u = random_state(O, 61)
+    kk = 0.1 * random_dir(O, 62)
+    y = random_dir(O, 63)
+    tau = 0.003
+    ref = vjp_colored(O, lambda q: O.residual(q, u, tau), kk, y)
+    G.linearize(to_dev(kk), to_dev(u), tau)
+    a64 = to_np(G.vjp_lin(to_dev(y), 64))
+    a32 = to_np(G.vjp_lin(to_dev(y, torch.float32), 32))
+    assert rel(a64, ref) <= 1e-12
+    assert rel(a32, ref) <= 1e-5
+    # the forward action keeps working after the transpose (same stored coefficients)
+    dk = random_dir(O, 64)
+    j64 = to_np(G.jvp_lin(to_dev(dk), 64))
+    assert abs(float(y @ j64) - float(a64 @ dk)) <= 1e-12 * np.linalg.norm(y) * np.linalg.norm(j64)
+
+
+@pytest.mark.parametrize("n,k", [((128, 128), 3), ((96, 80), 2)])
+def test_vjp_adjoint_identity_full_size(n, k):
+    """<y, J dk> = <J^T y, dk> with both actions from the GPU, FP64 and FP32."""
+    import paper_2609_16424_amd as ilh
+    G = ilh.Hydro("tg2d", n, k)
+    u = G.init_state()
+    g = torch.Generator(device=u.device).manual_seed(5)
+    u[:G.nh1] += 0.05 * u[G.nh1:2 * G.nh1]
+    kk = 0.1 * torch.randn(G.nblock, device=u.device, dtype=torch.float64, generator=g)
+    G.linearize(kk, u, 0.5 * G.dt_estimate(u, 2.0))
+    for prec, tol in ((64, 1e-12), (32, 1e-5)):
+        dt = torch.float64 if prec == 64 else torch.float32
+        for _ in range(3):
+            y = torch.randn(G.nblock, device=u.device, dtype=torch.float64, generator=g)
+            dk = torch.randn(G.nblock, device=u.device, dtype=torch.float64, generator=g)
+            jdk = G.jvp_lin(dk.to(dt), prec).double()
+            jty = G.vjp_lin(y.to(dt), prec).double()
+            lhs, rhs = float(y @ jdk), float(jty @ dk)
+            scale = float(torch.linalg.norm(y) * torch.linalg.norm(jdk))
+            assert abs(lhs - rhs) <= tol * scale, (prec, lhs, rhs)
+
+
+def test_residual_autograd_backward():
+    """torch.autograd through ResidualFn: the gradient of <g, R(k)> in k is J^T g."""
+    import paper_2609_16424_amd as ilh
+    from oracle.krylov import vjp_colored
+    O, G = make_pair("tg2d", (12, 3), 3)
+    u = random_state(O, 71)
+    kk = 0.1 * random_dir(O, 72)
+    gy = random_dir(O, 73)
+    tau = 0.002
+    k_t = to_dev(kk).requires_grad_(True)
+    r = ilh.ResidualFn.apply(G, k_t, to_dev(u), tau)
+    (grad,) = torch.autograd.grad(r, k_t, grad_outputs=to_dev(gy))
+    ref = vjp_colored(O, lambda q: O.residual(q, u, tau), kk, gy)
+    assert rel(to_np(grad), ref) <= 1e-12
+    _, fn = torch.func.vjp(lambda q: ilh.ResidualFn.apply(G, q, to_dev(u), tau), to_dev(kk))
+    assert rel(to_np(fn(to_dev(gy))[0]), ref) <= 1e-12
+
+
+def test_vjp_rejected_in_3d():
+    from paper_2609_16424_amd import IlhError
+    O, G = make_pair("tg3d", (3, 2, 2), 2)
+    u = to_dev(O.init_state())
+    with pytest.raises(IlhError):
+        G.vjp(torch.zeros_like(u), u, 0.01, torch.ones_like(u), 64)
