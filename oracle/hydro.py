@@ -376,6 +376,12 @@ class Hydro:
             return F1.ravel(), Ftv
         return F1.ravel(), Ftv.ravel()
 
+    def force_transpose(self, w, vt):
+        """F(w)^T vt: the force matrix of state w applied to another velocity field vt (H1)."""
+        Fe = self.force_matrix(w)
+        Vt = self._gather(vt)
+        return np.einsum("ecnj,cen->ej", Fe, Vt).ravel()
+
     def energy_source(self, wx):
         """TG energy source b_j = sum_q m_q s(x_q) phi_j at the current positions x_q."""
         if not self.use_source:

@@ -7,6 +7,7 @@
   no hand-written tangent.
 * Transpose actions J^T y from complex-step columns, compressed by a colouring of the
   columns that reach disjoint rows (vjp_colored).
+* The explicit RK2-average step that Sec. 4 uses as its RK2 reference (rk2avg_step).
 * Jacobi preconditioned CG (Sec. 2.2 mass solves), restarted flexible GMRES and inexact
   Newton with a backtracking line search that rejects steps producing a non-positive
   Jacobian determinant (Sec. 3.5, eq. newton_linear).
@@ -394,3 +395,35 @@ def vjp_colored(hyd, fun, x, y, h=CS_H):
             col_l2 = np.where(ok, 2 * nh + l2_elem * m.Nl + l, -1)
             accumulate(g, col_h1, col_l2)
     return out
+
+
+def rk2avg_step(hyd, u, dt):
+    """One explicit step of the RK2-average scheme (Sec. 4 names it RK2 and defines it by
+    reference to Dobrev et al. 2012, Sec. 7.1; restated here from that published method).
+
+    For dv/dt = -M_V^-1 F 1, de/dt = M_E^-1 (F^T v + b), dx/dt = v:
+      half step:  v_h = v + dt/2 a(u),  e_h = e + dt/2 M_E^-1 (F(u)^T v_h + b(x)),
+                  x_h = x + dt/2 v_h;
+      full step:  v+ = v + dt a(u_h),  vbar = (v + v+)/2,
+                  e+ = e + dt M_E^-1 (F(u_h)^T vbar + b(x_h)),  x+ = x + dt vbar,
+    where a(w) = -Mhat^-1 P_u F(w) 1 (wall rows held at zero).  Using the averaged velocity in
+    the full step makes the total energy change exactly dt 1^T b(x_h).
+    """
+    x, v, e = hyd.split(u)
+
+    def accel(w):
+        F1, _ = hyd.force(w)
+        return -hyd.mass_v_solve(np.where(hyd.cons, 0.0, F1))
+
+    def erate(w, vt):
+        return hyd.mass_e_inv(hyd.force_transpose(w, vt) + hyd.energy_source(hyd.split(w)[0]))
+
+    vh = v + 0.5 * dt * accel(u)
+    eh = e + 0.5 * dt * erate(u, vh)
+    xh = x + 0.5 * dt * vh
+    uh = np.concatenate([xh, vh, eh])
+    v1 = v + dt * accel(uh)
+    vb = 0.5 * (v + v1)
+    e1 = e + dt * erate(uh, vb)
+    x1 = x + dt * vb
+    return np.concatenate([x1, v1, e1])
