@@ -90,7 +90,7 @@ class Problem:
 
 
 def make_problem(name, mesh, perturb=None):
-    """Build a Problem for ``name`` in {'tg2d', 'tg3d', 'triple', 'uniform'} on ``mesh``.
+    """Build a Problem for ``name`` in {'tg2d', 'tg3d', 'triple', 'sedov', 'uniform'} on ``mesh``.
 
     ``perturb`` (triple point only) = dict(scale={'left':(sr,sp),...}, shift=dx) multiplies
     the per-region rho and p and shifts the region interfaces; used for the learned-guess
@@ -126,6 +126,15 @@ def make_problem(name, mesh, perturb=None):
             rho[e], pe[e], gam[e] = r * sr, p * spp, g
         e0v = pe / ((gam - 1.0) * rho)
         return Problem(name, 2, (0, 0), (7, 3), rho, gam,
+                       v0=lambda x: np.zeros_like(x),
+                       e0=lambda x, e_idx: e0v[e_idx])
+    if name == "sedov":
+        # Sec. 4.2: unit square, walls, gamma 1.4, rho 1, v 0; the delta-like energy source at
+        # the origin is read as all of the deposited energy 0.25 in the element at the origin
+        # (constant specific energy there, zero elsewhere)
+        e0v = np.zeros(Ne)
+        e0v[0] = 0.25 / (1.0 * float(np.prod(mesh.h)))
+        return Problem(name, 2, (0, 0), (1, 1), np.ones(Ne), np.full(Ne, 1.4),
                        v0=lambda x: np.zeros_like(x),
                        e0=lambda x, e_idx: e0v[e_idx])
     if name == "uniform":
@@ -174,10 +183,10 @@ class Hydro:
     """Q_k Q_{k-1} Lagrangian hydrodynamics on a Cartesian box (paper Sec. 2.1, 2.2)."""
 
     def __init__(self, problem_name, n, k, visc=None, source=True, perturb=None, nq1d=None):
-        dims = {"tg2d": 2, "tg3d": 3, "triple": 2, "uniform": len(n)}
+        dims = {"tg2d": 2, "tg3d": 3, "triple": 2, "sedov": 2, "uniform": len(n)}
         dim = dims[problem_name]
         boxes = {"tg2d": ((0, 0), (1, 1)), "tg3d": ((0, 0, 0), (1, 1, 1)),
-                 "triple": ((0, 0), (7, 3)), "uniform": ((0,) * dim, (1,) * dim)}
+                 "triple": ((0, 0), (7, 3)), "sedov": ((0, 0), (1, 1)), "uniform": ((0,) * dim, (1,) * dim)}
         lo, hi = boxes[problem_name]
         self.mesh = m = BoxMesh(dim, n, lo, hi, k)
         self.prob = make_problem(problem_name, m, perturb)
