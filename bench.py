@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--learned-seeds", default="1000-1004")
     ap.add_argument("--learned-steps", type=int, default=30)
     ap.add_argument("--no-c4", action="store_true", help="skip the triple-point precision and step-control legs")
+    ap.add_argument("--no-sedov", action="store_true", help="skip the Sedov explicit-vs-implicit leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a copy-shaped elementwise kernel (dst = -src) over this many MiB three "
                          "times: the byte calibration for HBM traffic counters")
@@ -189,6 +190,69 @@ def triple_point_legs(ilh, torch):
     res["step_control_from_8x"] = {"rejected_trials": rej, "accepted_dt_over_explicit": ratios[-1],
                                    "newton_per_step": float(np.mean(newton))}
     return res
+
+
+def _peak_density_radius(H, u):
+    """Radius of the element with the largest mass / area (area from its boundary nodes)."""
+    n, k = H.n[0], H.k
+    x = u[:H.nh1].view(2, -1).cpu().numpy()
+    ng = k * n + 1
+    X, Y = x[0].reshape(ng, ng), x[1].reshape(ng, ng)
+    best = (0.0, 0.0)
+    for ey in range(n):
+        for ex in range(n):
+            idx = ([(ex * k + a, ey * k) for a in range(k)] + [(ex * k + k, ey * k + b) for b in range(k)] +
+                   [(ex * k + k - a, ey * k + k) for a in range(k)] + [(ex * k, ey * k + k - b) for b in range(k)])
+            px = np.array([X[j, i] for i, j in idx])
+            py = np.array([Y[j, i] for i, j in idx])
+            area = 0.5 * abs(np.dot(px, np.roll(py, -1)) - np.dot(py, np.roll(px, -1)))
+            rho = (1.0 / (n * n)) / area
+            if rho > best[0]:
+                best = (rho, float(np.hypot(px.mean(), py.mean())))
+    return best
+
+
+def sedov_leg(ilh, torch, n=16, k=3, T=0.8):
+    """2D Sedov blast (Sec. 4.2), n x n Q3Q2, to T = 0.8: the explicit RK2-average scheme at
+    CFL 0.5 against implicit midpoint at FS-CFL 2 (dt = 2 x the explicit estimate, each step),
+    wall time, steps, energy, shock position (radius of the densest element; the exact
+    self-similar shock is at 0.898)."""
+    out = {}
+    for mode in ("explicit_rk2_cfl0.5", "implicit_midpoint_fscfl2"):
+        H = ilh.make_sedov(n, k)
+        u = H.init_state()
+        e0 = sum(H.energy(u))
+        opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150,
+                                  prec_probe=2, prec_lag=1)
+        t, steps, hist, newton, gmres = 0.0, 0, [], 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while t < T - 1e-12:
+            if mode.startswith("explicit"):
+                dt = min(0.5 * H.dt_estimate(u, 1.0), T - t)
+                H.rk2avg_step(u, dt)
+            else:
+                dt = min(2.0 * H.dt_estimate(u, 1.0), T - t)
+                g = H.plain_guess(u, hist, 0.5 * dt)
+                kk, st = H.implicit_step(u, dt, guess=g, opts=opts)
+                hist = (hist + [kk])[-2:]
+                newton += st["newton"]
+                gmres += st["gmres"]
+            t += dt
+            steps += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        peak, r = _peak_density_radius(H, u)
+        entry = {"steps": steps, "wall_s": wall, "s_per_step": wall / steps,
+                 "rel_energy_change": (sum(H.energy(u)) - e0) / e0, "peak_density": peak, "peak_radius": r}
+        if newton:
+            entry.update(newton_per_step=newton / steps, gmres_per_step=gmres / steps)
+        out[mode] = entry
+        del H, u
+    out["implicit_speedup_wall"] = out["explicit_rk2_cfl0.5"]["wall_s"] / out["implicit_midpoint_fscfl2"]["wall_s"]
+    out["workload"] = "2D Sedov %dx%d Q%dQ%d, gamma 1.4, smoothed viscosity, T = %g; exact shock radius 0.898" % (
+        n, n, k, k - 1, T)
+    return out
 
 
 def cpu_baseline(u_np, n, k, dt, budget_s=30.0):
@@ -439,6 +503,9 @@ def main():
     c4 = None
     if not args.no_c4:
         c4 = triple_point_legs(ilh, torch)
+    sedov = None
+    if not args.no_sedov:
+        sedov = sedov_leg(ilh, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -493,6 +560,8 @@ def main():
         out["roofline_3d"] = roof_3d
     if c4:
         out["c4_triple_point"] = c4
+    if sedov:
+        out["sedov_2d"] = sedov
     print(json.dumps(_finite(out), allow_nan=False))
 
 

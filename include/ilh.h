@@ -268,6 +268,17 @@ int ilh_probe_blocks(ilh_ctx* ctx, int mode, double* dv, double* einv);
 int ilh_sdirk_step(ilh_ctx* ctx, double* u, double dt, int scheme, const double* k_guess, double* k_out,
                    const ilh_newton_opts* o, ilh_step_stats* st);
 
+/* One explicit step of the RK2-average scheme, the explicit RK2 reference of Sec. 4 (defined
+ * there by reference to Dobrev et al. 2012, Sec. 7.1):
+ *   v_h = v + dt/2 a(u),  e_h = e + dt/2 M_E^-1 (F(u)^T v_h + b(x)),  x_h = x + dt/2 v_h,
+ *   v+ = v + dt a(u_h),   vbar = (v + v+)/2,
+ *   e+ = e + dt M_E^-1 (F(u_h)^T vbar + b(x_h)),  x+ = x + dt vbar,
+ * with a(w) = -Mhat^-1 P_u F(w) 1 (velocity mass solve with the wall rows held at zero, PCG to
+ * 1e-14) and b the TG energy source (else 0).  The averaged velocity makes the total energy
+ * change exactly dt 1^T b(x_h).  u [block] is updated in place.  2D only (ILH_EINVAL in 3D);
+ * uses 3 block vectors of workspace (allocated on first use). */
+int ilh_rk2avg_step(ilh_ctx* ctx, double* u, double dt);
+
 /* One accepted step under the Newton-based step-size control of Sec. 4 ("Implicit time step
  * control"), with the SDIRK scheme of ilh_sdirk_step.
  *   dt (host, in/out): in, the proposed step; out, the proposed next step: 1.05 x the accepted

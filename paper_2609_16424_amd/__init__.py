@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import NewtonOpts, Setup, StepStats, PROBLEMS
 
-__all__ = ["Hydro", "IlhError", "ForceFn", "newton_options"]
+__all__ = ["Hydro", "IlhError", "ForceFn", "ResidualFn", "newton_options", "make_sedov"]
 
 
 class IlhError(RuntimeError):
@@ -183,6 +183,12 @@ class Hydro:
         self.linearize(k, u, tau)
         return self.vjp_lin(y, prec)
 
+    def rk2avg_step(self, u, dt):
+        """One explicit RK2-average step, u updated in place (2D)."""
+        self._stream()
+        self._check(self.lib.ilh_rk2avg_step(self.ctx, self._vec(u, self.nblock, name="u"), float(dt)))
+        return u
+
     def mass_v_apply(self, x):
         y = self.new(self.nh1)
         self._stream()
@@ -343,6 +349,19 @@ def _stats(st, code):
                 jvp_calls=st.jvp_calls,
                 halvings=st.halvings, guess_rejected=st.guess_rejected, res0=st.res0, res_init=st.res_init, res_final=st.res_final,
                 hist=[st.res_hist[i] for i in range(n + 1)])
+
+
+def make_sedov(n, k, visc=True, h_coarse=None):
+    """2D Sedov blast (Sec. 4.2): unit square, walls, gamma 1.4, rho 1, v 0, the deposited
+    energy 0.25 as a constant specific energy in the element at the origin (zero elsewhere),
+    the smoothed viscosity with delta_scale = 2 (h / h_coarse) c_s.  h_coarse defaults to the
+    isotropic length of a 1 x 1 base mesh of the same order (1/k)."""
+    ne = int(n) * int(n)
+    e0 = [0.0] * ne
+    e0[0] = 0.25 * n * n
+    hc = 1.0 / k if h_coarse is None else h_coarse
+    return Hydro("custom", (n, n), k, visc=visc, dscale_mode="formula", h_coarse=hc, rho0=[1.0] * ne,
+                 gamma=[1.4] * ne, e0=e0, lo=(0.0, 0.0), hi=(1.0, 1.0), tg_source=False)
 
 
 class ForceFn(torch.autograd.Function):

@@ -90,6 +90,7 @@ SIGNATURES = {
     "ilh_set_apply_rows": (I, [P, I]),
     "ilh_vjp_lin": (I, [P, I, P, P]),
     "ilh_vjp": (I, [P, I, P, P, D, P, P]),
+    "ilh_rk2avg_step": (I, [P, P, D]),
     "ilh_timing_read": (I, [P, C.POINTER(D), C.POINTER(I64)]),
     "ilh_guess_features": (I, [P, P, P, D, D, D, D, D, P, P, P, I]),
     "ilh_guess_targets": (I, [P, P, P, D, D, P, P, I]),

@@ -36,9 +36,9 @@ template <int D1D, int Q1D, int MODE, typename T, int NE>
 __global__ void __launch_bounds__(Q1D* Q1D* NE) k_elem2d(const KParams P, const EArgs<T> A) {
   constexpr int L1D = D1D - 1, ND = D1D * D1D, NLD = L1D * L1D, NQ = Q1D * Q1D, NT = NQ * NE;
   constexpr bool TAN = (MODE == M_FJVP || MODE == M_JVP);
-  constexpr int NF = (MODE == M_FORCE) ? 2 : (MODE == M_RESID ? 3 : 4);
-  constexpr int NFL = (MODE == M_FORCE) ? 1 : 2;
-  constexpr bool WITH_SRC_OK = (MODE == M_RESID || MODE == M_JVP);
+  constexpr int NF = (MODE == M_FORCE) ? 2 : (MODE == M_RESID || MODE == M_ERATE ? 3 : 4);
+  constexpr int NFL = (MODE == M_FORCE || MODE == M_ERATE) ? 1 : 2;
+  constexpr bool WITH_SRC_OK = (MODE == M_RESID || MODE == M_JVP || MODE == M_ERATE);
 
   __shared__ T sB[Q1D * D1D], sG[Q1D * D1D], sBL[Q1D * L1D];
   __shared__ T sX[NE][NF][2][ND];
@@ -208,6 +208,10 @@ __global__ void __launch_bounds__(Q1D* Q1D* NE) k_elem2d(const KParams P, const 
       cy[1] = S[1][1];
       if constexpr (MODE == M_FORCE) {
         cl = s;
+      } else if constexpr (MODE == M_ERATE) {
+        // S : grad_xi vt = w |J| sigma : grad vt (field 2 holds the test velocity's gradient)
+        cl = S[0][0] * dJ[0][0] + S[0][1] * dJ[0][1] + S[1][0] * dJ[1][0] + S[1][1] * dJ[1][1];
+        if (src) cl += mq * tg_source<T>(T(sAnc[z][0] + double(xval[0])), T(sAnc[z][1] + double(xval[1])), gam);
       } else {
         cm[0] = mq * mval[0];
         cm[1] = mq * mval[1];
@@ -281,6 +285,7 @@ __global__ void __launch_bounds__(Q1D* Q1D* NE) k_elem2d(const KParams P, const 
   __syncthreads();
   // transpose along xi and scatter
   for (int i = tid; i < NE * 2 * ND; i += NT) {
+    if constexpr (MODE == M_ERATE) break;  // energy rows only
     const int a = i % D1D;
     int t = i / D1D;
     const int b = t % D1D;
@@ -318,7 +323,7 @@ __global__ void __launch_bounds__(Q1D* Q1D* NE) k_elem2d(const KParams P, const 
     T o = 0;
 #pragma unroll
     for (int qxx = 0; qxx < Q1D; ++qxx) o += sBL[qxx * L1D + al] * sAL[zz][0][bl * Q1D + qxx];
-    if constexpr (MODE == M_FORCE || MODE == M_FJVP) A.out2[(int64_t)ee * NLD + j] = o;
+    if constexpr (MODE == M_FORCE || MODE == M_FJVP || MODE == M_ERATE) A.out2[(int64_t)ee * NLD + j] = o;
     else A.out[2 * nh1 + (int64_t)ee * NLD + j] = o;
   }
 }
@@ -775,6 +780,9 @@ static int launch_elem_k(ilh_ctx* c, int mode, int prec, const EArgs<double>* a6
       case M_RESID: return launch_elem_t<DIM, K, M_RESID, double>(c, *a64);
       case M_FJVP: return launch_elem_t<DIM, K, M_FJVP, double>(c, *a64);
       case M_JVP: return launch_elem_t<DIM, K, M_JVP, double>(c, *a64);
+      case M_ERATE:
+        if constexpr (DIM == 2) return launch_elem_t<DIM, K, M_ERATE, double>(c, *a64);
+        break;
     }
   } else {
     switch (mode) {

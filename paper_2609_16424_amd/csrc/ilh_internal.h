@@ -13,7 +13,7 @@
 namespace ilh {
 
 // Element kernel modes.
-enum Mode { M_FORCE = 0, M_RESID = 1, M_FJVP = 2, M_JVP = 3 };
+enum Mode { M_FORCE = 0, M_RESID = 1, M_FJVP = 2, M_JVP = 3, M_ERATE = 4 };
 
 // Scalar parameters of the quadrature-point kernel and the structured mesh, passed by
 // value to every element kernel.
@@ -40,6 +40,7 @@ struct KParams {
 //  RESID : x, v, e = u (FP64);  kk = k block;       out = R [block]
 //  FJVP  : x, v, e = state w;   dk = direction;     out = d(F 1), out2 = d(F^T v)
 //  JVP   : x (FP64), v, e = state; dk = direction;  out = J dk [block]
+//  ERATE : x, v, e = state w;   dk = test velocity vt [H1];  out2 = F(w)^T vt + b(x) [L2] (2D)
 template <typename T>
 struct EArgs {
   const double* x;
@@ -107,6 +108,7 @@ struct ilh_ctx {
   double* gres = nullptr;       // learned-guess judge residual [nblock]
   double* pdv = nullptr;        // probed diagonal of the velocity block [nh1]
   double* peinv = nullptr;      // inverted probed energy blocks [Ne][Nl][Nl]
+  double* rkw = nullptr;        // explicit RK2-average workspace [2 nblock] (allocated on first use)
   double* sdk = nullptr;        // SDIRK stage rates and stage base [4][nblock] (allocated on first use)
   double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
@@ -181,7 +183,7 @@ int launch_cast_f2d(ilh_ctx* c, double* y, const float* x, int64_t n);
 int launch_mass_v(ilh_ctx* c, const double* x, double* y, int zero_first);
 int launch_mass_e_inv(ilh_ctx* c, const double* b, double* x);
 int launch_jacobi(ilh_ctx* c, const double* r, double* z);   // z = r / Mdiag
-int launch_constrain(ilh_ctx* c, const double* src, double* dst, int mode);  // H1 constrained rows
+int launch_scale_free(ilh_ctx* c, double* y, double a, const double* x);  // H1: y = a x, constrained rows 0
 // reductions: dot products of n-length vectors, result on host (synchronizes)
 int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* out);
 // device-side dot into d_out (no sync)

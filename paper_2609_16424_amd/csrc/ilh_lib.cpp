@@ -265,7 +265,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
-                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk, c->pdv, c->peinv, c->gscr, c->gres};
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : c->qd)
@@ -742,6 +742,54 @@ int ilh_rate(ilh_ctx* c, const double* u, double* f) {
   if ((st = pcg_mass_v(c, r + nh1, f + nh1, 1e-14, 500, 10, &it, &rel))) return st;
   ILH_HIP(c, hipMemcpyAsync(f, u + nh1, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return ILH_OK;
+}
+
+// a = -Mhat^-1 P_u F(w) 1 (the velocity rate, wall rows zero), using f1 [nh1] as scratch
+static int velocity_rate(ilh_ctx* c, const double* w, double* f1, double* ftv, double* a) {
+  int st;
+  if ((st = ilh_force(c, w, f1, ftv))) return st;
+  if ((st = launch_scale_free(c, f1, -1.0, f1))) return st;
+  int it;
+  double rel;
+  return pcg_mass_v(c, f1, a, 1e-14, 500, 10, &it, &rel);
+}
+
+// de = M_E^-1 (F(w)^T vt + b(x_w)) using r [nl2] as scratch
+static int energy_rate(ilh_ctx* c, const double* w, const double* vt, double* r, double* de) {
+  EArgs<double> a{w, w + c->nh1, w + 2 * c->nh1, nullptr, vt, 0.0, nullptr, r};
+  int st = launch_elem(c, M_ERATE, 64, &a, nullptr);
+  if (st) return st;
+  return launch_mass_e_inv(c, r, de);
+}
+
+int ilh_rk2avg_step(ilh_ctx* c, double* u, double dt) {
+  if (!c || !u || !(dt > 0)) return ILH_EINVAL;
+  if (c->dim != 2) return fail(c, ILH_EINVAL, "the explicit RK2-average step is built for 2D");
+  int st;
+  const int64_t nh1 = c->nh1, nl2 = c->nl2, nb = c->nblock;
+  if (!c->rkw && (st = dalloc(c, &c->rkw, 3 * nb))) return st;
+  double* uh = c->rkw;           // half-step state [block]
+  double* a = c->rkw + nb;       // velocity rate [nh1]
+  double* f1 = a + nh1;          // F 1 scratch [nh1]
+  double* vb = f1 + nh1;         // averaged velocity [nh1]
+  double* r = vb + nh1;          // energy scratch [nl2]
+  double* de = r + nl2;          // energy rate [nl2]
+  double *x = u, *v = u + nh1, *e = u + 2 * nh1;
+  double *xh = uh, *vh = uh + nh1, *eh = uh + 2 * nh1;
+  // half step: v_h = v + dt/2 a(u), e_h = e + dt/2 M_E^-1 (F(u)^T v_h + b(x)), x_h = x + dt/2 v_h
+  if ((st = velocity_rate(c, u, f1, r, a))) return st;
+  if ((st = launch_waxpy(c, vh, v, 0.5 * dt, a, nh1))) return st;
+  if ((st = energy_rate(c, u, vh, r, de))) return st;
+  if ((st = launch_waxpy(c, eh, e, 0.5 * dt, de, nl2))) return st;
+  if ((st = launch_waxpy(c, xh, x, 0.5 * dt, vh, nh1))) return st;
+  // full step: v+ = v + dt a(u_h), vbar = (v + v+)/2, e+ = e + dt M_E^-1 (F(u_h)^T vbar + b(x_h)),
+  // x+ = x + dt vbar
+  if ((st = velocity_rate(c, uh, f1, r, a))) return st;
+  if ((st = launch_waxpy(c, vb, v, 0.5 * dt, a, nh1))) return st;
+  if ((st = energy_rate(c, uh, vb, r, de))) return st;
+  if ((st = launch_axpby(c, e, dt, de, 1.0, nl2))) return st;
+  if ((st = launch_axpby(c, x, dt, vb, 1.0, nh1))) return st;
+  return launch_axpby(c, v, dt, a, 1.0, nh1);
 }
 
 int ilh_plain_guess(ilh_ctx* c, const double* u, const double* k1, const double* k2, int nhist, double tau,

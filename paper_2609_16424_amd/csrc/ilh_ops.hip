@@ -79,6 +79,29 @@ int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n) {
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
+// y = a x on the free rows of an H1 vector, 0 on the constrained (wall) rows
+__global__ void k_scale_free(double* y, double a, const double* x, KParams P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.dim * P.N) return;
+  const int c = (int)(i / P.N);
+  int64_t node = i - (int64_t)c * P.N;
+  int64_t g = node % P.ng[0];
+  if (c >= 1) {
+    node /= P.ng[0];
+    g = node % P.ng[1];
+  }
+  if (c == 2) g = node / P.ng[1];
+  const bool cons = g == 0 || g == P.ng[c] - 1;
+  y[i] = cons ? 0.0 : a * x[i];
+}
+
+int launch_scale_free(ilh_ctx* c, double* y, double a, const double* x) {
+  const int64_t n = c->nh1;
+  hipLaunchKernelGGL(k_scale_free, dim3(nblk(n)), dim3(TPB), 0, c->stream, y, a, x, c->kp);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
 int launch_cast_f2d(ilh_ctx* c, double* y, const float* x, int64_t n) {
   if (n <= 0) return ILH_OK;
   hipLaunchKernelGGL(k_f2d, dim3(nblk(n)), dim3(TPB), 0, c->stream, y, x, n);
