@@ -10,7 +10,9 @@
 // element outputs are combined in LDS over the element's lanes, one velocity component at a
 // time, before the atomic scatter of the shared nodes.
 //
-// Stored data: field f of lane l at step qz of work-group b sits at qd[f qs + (b Q1D + qz) 64 + l].
+// Stored data: field f of lane l at step qz of strip b sits at qd[((b Q1D + qz) NQD + f) 64 + l]
+// (the NQD fields of one wave's step form one contiguous block).  Strips are dealt to the XCDs
+// in contiguous bands (xcd_tile).
 #include <hip/hip_runtime.h>
 
 #include "ilh_internal.h"
@@ -37,7 +39,9 @@ __global__ void __launch_bounds__(64) k_lin3d(const KParams P, const Tab2<double
   __shared__ double sBL[Q1D][L1D];
 
   const int lane = threadIdx.x;
-  const int ex0 = blockIdx.x * EPW, ey = blockIdx.y, ez = blockIdx.z;
+  const uint32_t tile = xcd_tile((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x,
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int ex0 = (tile % gridDim.x) * EPW, ey = (tile / gridDim.x) % gridDim.y, ez = tile / (gridDim.x * gridDim.y);
   const int nx = P.n[0], ny = P.n[1];
   const int E = min(EPW, nx - ex0);
   const int ns = K * E + 1;
@@ -120,7 +124,7 @@ __global__ void __launch_bounds__(64) k_lin3d(const KParams P, const Tab2<double
   }
   const double gam = P.gamma[e], dJ0 = P.j0e[e];
   const double wxy = tb.W[qx] * tb.W[qy] * P.rj0[e];
-  const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int64_t blk = tile;
 #pragma unroll 1
   for (int qz = 0; qz < Q1D; ++qz) {
     double J[3][3], Gv[3][3];
@@ -152,9 +156,15 @@ __global__ void __launch_bounds__(64) k_lin3d(const KParams P, const Tab2<double
     lin_coefs<3, VISC>(P, gam, mq, dJ0, J, Gv, eq, cf);
 #pragma unroll
     for (int f = NPRE; f < NQD; ++f) cf[f] *= tau;
-    T* q = qd + (blk * Q1D + qz) * 64 + lane;
+    if constexpr (sizeof(T) == 4) {  // row-interleaved (FP32)
+      T* q = qd + (blk * Q1D + qz) * (NQD * 64) + lane;
 #pragma unroll
-    for (int f = 0; f < NQD; ++f) q[f * qs] = T(cf[f]);
+      for (int f = 0; f < NQD; ++f) q[f * 64] = T(cf[f]);
+    } else {  // field-major (FP64)
+      T* q = qd + (blk * Q1D + qz) * 64 + lane;
+#pragma unroll
+      for (int f = 0; f < NQD; ++f) q[f * qs] = T(cf[f]);
+    }
   }
 }
 
@@ -178,7 +188,9 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
   __shared__ T sBL[Q1D][L1D];
 
   const int lane = threadIdx.x;
-  const int ex0 = blockIdx.x * EPW, ey = blockIdx.y, ez = blockIdx.z;
+  const uint32_t tile = xcd_tile((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x,
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int ex0 = (tile % gridDim.x) * EPW, ey = (tile / gridDim.x) % gridDim.y, ez = tile / (gridDim.x * gridDim.y);
   const int nx = P.n[0], ny = P.n[1];
   const int E = min(EPW, nx - ex0);
   const int ns = K * E + 1;
@@ -190,19 +202,16 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
   constexpr int NTS = NF * D1D * D1D * NS, RT = (NTS + 63) / 64;
   constexpr int NLS = EPW * NLD, RL = (NLS + 63) / 64;
   T tr[RT], lr[RL];
+  // branch-free gathers: lanes past the strip re-read its last node (their LDS slots feed no
+  // output), so every load is in flight before the first LDS store
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
-    const int i = lane + 64 * r, s = i % NS, t = i / NS, b = t % D1D, cz = (t / D1D) % D1D, f = t / (D1D * D1D);
-    tr[r] = T(0);
-    if (i < NTS && s < ns)
-      tr[r] = ld32(dk, (f < 3 ? f * N : nh1 + (f - 3) * N) + row0 + (uint32_t)cz * ng01 + (uint32_t)b * ng0 + s);
+    const int i = lane + 64 * r, s = min(i % NS, ns - 1), t = min(i / NS, NF * D1D * D1D - 1), b = t % D1D,
+              cz = (t / D1D) % D1D, f = t / (D1D * D1D);
+    tr[r] = ld32(dk, (f < 3 ? f * N : nh1 + (f - 3) * N) + row0 + (uint32_t)cz * ng01 + (uint32_t)b * ng0 + s);
   }
 #pragma unroll
-  for (int r = 0; r < RL; ++r) {
-    const int i = lane + 64 * r;
-    lr[r] = T(0);
-    if (i < E * NLD) lr[r] = ld32(dk, 2 * nh1 + ebase * NLD + i);
-  }
+  for (int r = 0; r < RL; ++r) lr[r] = ld32(dk, 2 * nh1 + ebase * NLD + min(lane + 64 * r, E * NLD - 1));
   const int zl = lane / LPE;
   const double rj_l = P.rj0[ebase + (zl < E ? zl : 0)];
   for (int i = lane; i < Q1D * D1D; i += 64) {
@@ -282,11 +291,23 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
       EL[cl] = acc;
     }
     const T wxy = tb.W[qx] * tb.W[qy] * T(rj_l);
-    const T* __restrict__ qb =
-        qd + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * (Q1D * 64);
-    const T* qf[NQD];
+    constexpr bool ROWS = sizeof(T) == 4;  // coefficient layout: row-interleaved (FP32), field-major (FP64)
+    const T* __restrict__ qb = qd + (int64_t)tile * (Q1D * (ROWS ? NQD : 1) * 64);
+    const T* qf[ROWS ? 1 : NQD];
+    if constexpr (!ROWS) {
 #pragma unroll
-    for (int f = 0; f < NQD; ++f) qf[f] = sbase(qb + f * qs);
+      for (int f = 0; f < NQD; ++f) qf[f] = sbase(qb + f * qs);
+    }
+    auto ldstep = [&](const int qz, T* c) {
+      if constexpr (ROWS) {
+        const T* rb = sbase(qb + qz * (NQD * 64));
+#pragma unroll
+        for (int f = 0; f < NQD; ++f) c[f] = ld32(rb, (uint32_t)(f * 64 + lane));
+      } else {
+#pragma unroll
+        for (int f = 0; f < NQD; ++f) c[f] = ld32(qf[f], (uint32_t)(qz * 64 + lane));
+      }
+    };
     auto step = [&](const int qz, const T* cf) {
       // tau is folded into the coefficients: the contractions enter unscaled
       T dJ[3][3], dGv[3][3], dkv[3];
@@ -335,19 +356,69 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
     };
     // the next step's coefficients are requested before this step's arithmetic
     T cf[NQD];
-#pragma unroll
-    for (int f = 0; f < NQD; ++f) cf[f] = ld32(qf[f], (uint32_t)lane);
+    ldstep(0, cf);
 #pragma unroll 1
     for (int qz = 0; qz < Q1D; ++qz) {
       T cn[NQD];
-      const uint32_t qn = (qz + 1 < Q1D ? qz + 1 : qz) * 64 + lane;
-#pragma unroll
-      for (int f = 0; f < NQD; ++f) cn[f] = ld32(qf[f], qn);
+      ldstep(qz + 1 < Q1D ? qz + 1 : qz, cn);
       step(qz, cf);
 #pragma unroll
       for (int f = 0; f < NQD; ++f) cf[f] = cn[f];
     }
   }
+  if constexpr (sizeof(T) == 4) {
+  // velocity rows, one component at a time: each lane's column contributions to its element's
+  // nodes (factored: out(a,b) = By_b (Gx_a Tx + Bx_a Tz) + Gy_b Bx_a Ty per z-layer) go to LDS;
+  // one thread per node of the strip sums the columns of the (one or two) elements holding it
+  // and issues one atomic add (constrained rows are set by the owner below)
+#pragma unroll
+  for (int a = 0; a < D1D; ++a) {  // reloaded: not kept live through the column loop
+    Bx[a] = sBG[0][qx][a];
+    Gx[a] = sBG[1][qx][a];
+    By[a] = sBG[0][qy][a];
+    Gy[a] = sBG[1][qy][a];
+  }
+#pragma unroll 1
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int cz = 0; cz < D1D; ++cz) {
+      T tx = 0, ty = 0, tz = 0;
+#pragma unroll
+      for (int rq = 0; rq < 3; ++rq)
+        if (rq == r) {
+          tx = Tx[rq][cz];
+          ty = Ty[rq][cz];
+          tz = Tz[rq][cz];
+        }
+#pragma unroll
+      for (int a = 0; a < D1D; ++a) {
+        const T q1 = Gx[a] * tx + Bx[a] * tz, q2 = Bx[a] * ty;
+#pragma unroll
+        for (int b = 0; b < D1D; ++b) sO[lane][(cz * D1D + b) * D1D + a] = By[b] * q1 + Gy[b] * q2;
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i < D1D * D1D * NS; i += 64) {
+      const int s = i % NS, t = i / NS, b = t % D1D, cz = t / D1D;
+      if (s >= ns) continue;
+      const uint32_t I = K * ex0 + s, J = K * ey + b, Kz = K * ez + cz;
+      const uint32_t idx = r == 0 ? I : (r == 1 ? J : Kz), ngr = r == 0 ? ng0 : (r == 1 ? ng1 : ng2);
+      if (idx == 0 || idx == ngr - 1) continue;
+      const int zz = s / K, a = s - K * zz;
+      T o = 0;
+      if (zz < E) {
+#pragma unroll
+        for (int q = 0; q < LPE; ++q) o += sO[zz * LPE + q][(cz * D1D + b) * D1D + a];
+      }
+      if (a == 0 && zz > 0) {
+#pragma unroll
+        for (int q = 0; q < LPE; ++q) o += sO[(zz - 1) * LPE + q][(cz * D1D + b) * D1D + K];
+      }
+      unsafeAtomicAdd(&out[nh1 + r * N + row0 + cz * ng01 + b * ng0 + s], o);
+    }
+    __syncthreads();
+  }
+  } else {  // FP64: per-element sums over the element's lanes, one atomic per node and element
   // velocity rows, one component at a time: column contributions to the element's nodes,
   // summed over the element's LPE lanes, scattered with atomics (shared nodes)
   const int ex = ex0 + z;
@@ -390,6 +461,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
     }
     __syncthreads();
   }
+  }
   // energy rows (element-owned)
 #pragma unroll
   for (int cl = 0; cl < L1D; ++cl)
@@ -417,7 +489,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
     const T dkv = sS[3 + c][cz][b][s];
     out[gi] = sS[c][cz][b][s] - tau * dkv;
     const uint32_t idx = c == 0 ? I : (c == 1 ? J : Kz), ngc = c == 0 ? ng0 : (c == 1 ? ng1 : ng2);
-    if (idx == 0 || idx == ngc - 1) unsafeAtomicAdd(&out[nh1 + gi], dkv);
+    if (idx == 0 || idx == ngc - 1) out[nh1 + gi] = dkv;  // the owner is the only writer
   }
 }
 
