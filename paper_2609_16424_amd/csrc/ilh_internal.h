@@ -112,8 +112,10 @@ struct ilh_ctx {
   double* sdk = nullptr;        // SDIRK stage rates and stage base [4][nblock] (allocated on first use)
   double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
-  double* hdev = nullptr;       // [4 * 72] device scalars of the Arnoldi step
+  double* hdev = nullptr;       // [HDEV_LEN] device scalars of the Arnoldi step
   double* hhost = nullptr;      // pinned mirror of hdev
+  double* gmd = nullptr;        // device Givens state of FGMRES: H [64][64], cs, sn [64], g [65]
+  hipEvent_t gev[2] = {nullptr, nullptr};  // FGMRES: residual estimates of alternate steps ready
   int apply_rows = 0;           // element rows per apply wave of the linearised kernels (0: by mesh size)
   int jvp_variant = 0;          // 0 linearised (where available), 1 generic, 2 register-resident recompute
   void* qd[2] = {nullptr, nullptr};  // stored tangent coefficients, FP32 / FP64 (linearised variant)
@@ -189,6 +191,11 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
 // device-side dot into d_out (no sync)
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
 int multidot_dev(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);
+// Arnoldi scalars: [0, 72) and [72, 144) the two Gram-Schmidt passes, 144 the norm, [160, 224)
+// the update coefficients, 240 beta, [352, 480) (|g_j+1|, h_j+1,j) per step
+constexpr int HDEV_LEN = 480;
+int launch_givens(ilh_ctx* c, double* h, double* G, int j, int m);
+int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
 int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
 // fused versions: w read once per 8 basis vectors; the axpy also returns |w|^2
 int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);

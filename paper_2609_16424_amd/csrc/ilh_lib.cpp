@@ -265,12 +265,14 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
-                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres};
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : c->qd)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->gev)
+    if (e) (void)hipEventDestroy(e);
   if (c->red_host) (void)hipHostFree(c->red_host);
   if (c->hhost) (void)hipHostFree(c->hhost);
   delete c;
@@ -916,12 +918,18 @@ struct Solver {
   }
 
   // FGMRES: solve J x = b, x starts at 0.  Returns total iterations in *its.
+  // The Givens rotations, the residual estimate and the triangular solve run on the device;
+  // the host enqueues Arnoldi step j before it reads step j-1's residual estimate (pinned copy
+  // behind an event), so the stream never drains between steps.  A step enqueued after the
+  // one that converged is discarded: it only touches V_{j+1}, Z_j, column j and g_j, g_{j+1},
+  // none of which the solution over the first j columns reads.
   int fgmres(const double* b, double* x, int* its) {
     const int64_t n = c->nblock;
     const int m = std::max(1, std::min(o->restart, 64));
     double* V = c->kry;
     double* Z = c->kry + (int64_t)(m + 1) * n;
     double* hd = c->hdev;
+    double* G = c->gmd;
     int st;
     if ((st = launch_fill(c, x, 0.0, n))) return st;
     double beta = nrm2(c, b, n, &st);
@@ -929,7 +937,6 @@ struct Solver {
     *its = 0;
     if (beta == 0.0) return ILH_OK;
     const double target = o->gmres_rtol * beta;
-    std::vector<double> H((m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
     const double* rhs = b;
     double* rbuf = c->nwt + 3 * n;  // tmp vector
     int total = 0;
@@ -938,11 +945,20 @@ struct Solver {
       c->hhost[240] = beta;
       ILH_HIP(c, hipMemcpyAsync(hd + 240, &c->hhost[240], sizeof(double), hipMemcpyHostToDevice, c->stream));
       hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, hd, 240, n);
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
       int j_end = 0;
-      bool done = false;
-      for (int j = 0; j < m; ++j) {
+      bool stop = false;  // converged or out of iterations
+      // read step jj's estimate; true when the cycle ends after it
+      auto check = [&](int jj, bool& end) -> int {
+        ILH_HIP(c, hipEventSynchronize(c->gev[jj & 1]));
+        const double res = c->hhost[352 + 2 * jj], hn = c->hhost[353 + 2 * jj];
+        if (!std::isfinite(hn) || !std::isfinite(res)) return fail(c, ILH_ENONFINITE, "non-finite Krylov vector");
+        ++total;
+        stop = res <= target || total >= o->gmres_maxit;
+        end = stop || hn == 0.0;
+        return ILH_OK;
+      };
+      bool end = false;
+      for (int j = 0; j < m && !end; ++j) {
         double* Vj = V + (int64_t)j * n;
         double* Zj = Z + (int64_t)j * n;
         double* w = V + (int64_t)(j + 1) * n;
@@ -955,43 +971,25 @@ struct Solver {
         if ((st = multidot_fused(c, V, n, j + 1, w, n, hd + 72))) return st;
         if ((st = multiaxpy_nrm(c, w, V, n, j + 1, hd + 72, -1.0, n, hd + 144))) return st;
         tstop(c, slot);
-        // normalise on the device (no-op for a zero or non-finite norm), then fetch the scalars
+        // normalise on the device (no-op for a zero or non-finite norm), rotate, publish the estimate
         if ((st = launch_scale_by_norm(c, w, w, hd + 144, n))) return st;
-        ILH_HIP(c, hipMemcpyAsync(c->hhost, hd, 145 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        ILH_HIP(c, hipStreamSynchronize(c->stream));
-        for (int i = 0; i <= j; ++i) H[i * m + j] = c->hhost[i] + c->hhost[72 + i];
-        const double hn = std::sqrt(std::max(c->hhost[144], 0.0));
-        if (!std::isfinite(hn)) return fail(c, ILH_ENONFINITE, "non-finite Krylov vector");
-        H[(j + 1) * m + j] = hn;
-        for (int i = 0; i < j; ++i) {
-          const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-          H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-          H[i * m + j] = t;
+        if ((st = launch_givens(c, hd, G, j, m))) return st;
+        ILH_HIP(c, hipMemcpyAsync(c->hhost + 352 + 2 * j, hd + 352 + 2 * j, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+        ILH_HIP(c, hipEventRecord(c->gev[j & 1], c->stream));
+        if (j >= 1) {
+          if ((st = check(j - 1, end))) return st;
+          if (end) j_end = j;  // step j was speculative
         }
-        const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-        cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
-        sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
-        H[j * m + j] = den;
-        H[(j + 1) * m + j] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        ++total;
-        j_end = j + 1;
-        if (std::fabs(g[j + 1]) <= target || total >= o->gmres_maxit || hn == 0.0) {
-          done = true;
-          break;
-        }
+      }
+      if (!end) {  // the cycle filled the basis: read its last step
+        if ((st = check(m - 1, end))) return st;
+        j_end = m;
       }
       // y = H^-1 g (upper triangular), x += Z y
-      for (int i = j_end - 1; i >= 0; --i) {
-        double acc = g[i];
-        for (int l = i + 1; l < j_end; ++l) acc -= H[i * m + l] * y[l];
-        y[i] = H[i * m + i] != 0 ? acc / H[i * m + i] : 0.0;
-      }
-      for (int i = 0; i < j_end; ++i) c->hhost[160 + i] = y[i];
-      ILH_HIP(c, hipMemcpyAsync(hd + 160, c->hhost + 160, j_end * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      if ((st = launch_trisolve(c, G, m, j_end, hd + 160))) return st;
       if ((st = multiaxpy_dev(c, x, Z, n, j_end, hd + 160, 1.0, n))) return st;
-      if (done && (std::fabs(g[j_end]) <= target || total >= o->gmres_maxit)) break;
+      if (stop) break;
       // restart: r = b - J x
       if ((st = apply(x, rbuf))) return st;
       if ((st = launch_axpby(c, rbuf, 1.0, b, -1.0, n))) return st;
@@ -1014,9 +1012,12 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   const int m = std::max(1, std::min(o->restart, 64));
   if ((st = ensure_solver_ws(c, m))) return st;
   if (!c->nwt && (st = dalloc(c, &c->nwt, 8 * (size_t)n))) return st;
-  if (!c->hdev && (st = dalloc(c, &c->hdev, 4 * 72 + 64))) return st;
-  if (!c->hhost && hipHostMalloc((void**)&c->hhost, (4 * 72 + 64) * sizeof(double)) != hipSuccess)
+  if (!c->hdev && (st = dalloc(c, &c->hdev, HDEV_LEN))) return st;
+  if (!c->hhost && hipHostMalloc((void**)&c->hhost, HDEV_LEN * sizeof(double)) != hipSuccess)
     return fail(c, ILH_ENOMEM, "pinned host buffer");
+  if (!c->gmd && (st = dalloc(c, &c->gmd, 64 * 64 + 3 * 65))) return st;
+  for (hipEvent_t& e : c->gev)
+    if (!e) ILH_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   double* k = c->nwt;
   double* r = c->nwt + n;
   double* dk = c->nwt + 2 * n;

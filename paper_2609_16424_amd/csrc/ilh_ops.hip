@@ -294,6 +294,65 @@ int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, co
 }
 
 // y = x / sqrt(*nrm2) when the norm is positive (the next Arnoldi vector)
+// Givens update of Arnoldi step j on the device (one thread; j < m <= 64).  Column j of the
+// Hessenberg matrix is the sum of the two Gram-Schmidt passes (h[0..j], h[72..72+j]) with
+// h_{j+1,j} = sqrt(h[144]); the earlier rotations are applied to it, the new one is formed and
+// applied to the right-hand side g (g = beta e_1 at j = 0, beta in h[240]); the residual
+// estimate |g_{j+1}| and h_{j+1,j} go to h[352 + 2j], h[353 + 2j].
+// G layout: H [64][64] row-major (upper triangle after the rotations), cs [64], sn [64], g [65].
+__global__ void k_givens(double* h, double* G, int j, int m) {
+  if (threadIdx.x != 0) return;
+  double* H = G;
+  double* cs = G + 64 * 64;
+  double* sn = cs + 64;
+  double* g = sn + 64;
+  if (j == 0) {
+    g[0] = h[240];
+    for (int i = 1; i <= m; ++i) g[i] = 0.0;
+  }
+  const double hn = sqrt(fmax(h[144], 0.0));
+  double cur = h[0] + h[72];
+  for (int i = 0; i < j; ++i) {
+    const double nx = h[i + 1] + h[72 + i + 1];
+    H[i * 64 + j] = cs[i] * cur + sn[i] * nx;
+    cur = -sn[i] * cur + cs[i] * nx;
+  }
+  const double den = hypot(cur, hn);
+  const double c_ = den > 0 ? cur / den : 1.0, s_ = den > 0 ? hn / den : 0.0;
+  cs[j] = c_;
+  sn[j] = s_;
+  H[j * 64 + j] = den;
+  g[j + 1] = -s_ * g[j];
+  g[j] = c_ * g[j];
+  h[352 + 2 * j] = fabs(g[j + 1]);
+  h[353 + 2 * j] = hn;
+}
+
+// y = H(0:n, 0:n)^-1 g(0:n) by back substitution (one thread)
+__global__ void k_trisolve(const double* G, int n, double* y) {
+  if (threadIdx.x != 0) return;
+  const double* H = G;
+  const double* g = G + 64 * 64 + 128;
+  for (int i = n - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int l = i + 1; l < n; ++l) acc -= H[i * 64 + l] * y[l];
+    y[i] = H[i * 64 + i] != 0 ? acc / H[i * 64 + i] : 0.0;
+  }
+}
+
+int launch_givens(ilh_ctx* c, double* h, double* G, int j, int m) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, c->stream, h, G, j, m);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
+  (void)m;
+  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, c->stream, G, n, y);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
 __global__ void k_scale_by_norm(double* y, const double* x, const double* nrm2, int64_t n) {
   const double s = sqrt(fmax(*nrm2, 0.0));
   if (!(s > 0.0)) return;

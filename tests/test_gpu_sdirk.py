@@ -127,4 +127,6 @@ def test_adaptive_step_rejects_and_restores():
     assert abs(taken - dt0 * 0.85 ** nrej) <= 1e-12 * dt0
     assert dt_next == pytest.approx(taken * (1.05 if st["newton_max"] <= 1 else 1.0), rel=1e-15)
     G.sdirk_step(u_ref, taken, "sd2", guess=G.rate(u_ref.clone()), opts=opts)
-    assert rel(to_np(u), to_np(u_ref)) <= 1e-12
+    # two independent solves agree to the Newton tolerance (atomic summation orders differ
+    # between runs); a state not restored after a rejection would differ by O(dt * rate)
+    assert rel(to_np(u), to_np(u_ref)) <= 1e-9
