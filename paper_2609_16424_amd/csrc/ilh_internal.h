@@ -202,14 +202,19 @@ int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double
 int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign,
                   int64_t n, double* d_nrm2);
 int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n);
-int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled);
+int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
+                   double* zero_v = nullptr);
 // probed diagonal blocks of the Jacobian (preconditioner option prec_probe)
 int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau);
 int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D);
 int launch_probe_e_dir(ilh_ctx* c, float* d, int j);
 int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
 int launch_invert_blocks(ilh_ctx* c, double* B);
-int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled);
+int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
+                         double* zero_v = nullptr);
+int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, double* h, double sign,
+                         int64_t n, double* G, int j, int mm);
+int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);
 int l1_error_host(ilh_ctx* c, const double* u, double* out);

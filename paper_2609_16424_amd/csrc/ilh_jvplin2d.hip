@@ -164,10 +164,10 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
 // the strip then takes one atomic add (one per node and strip instead of one per node and
 // element); energy rows are element-owned, position rows and constrained velocity rows are
 // written by the node's owner.  The velocity part of out must be zero on entry.
-template <int D1D, int Q1D, typename T, int VISC, int SRC>
+template <int D1D, int Q1D, typename T, int VISC, int SRC, typename TO>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC && sizeof(T) == 8 ? 1 : 2))) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
                                                 const T* __restrict__ dk, const T* __restrict__ qd,
-                                                int64_t qs, double tau_, T* __restrict__ out, int R) {
+                                                int64_t qs, double tau_, TO* __restrict__ out, int R) {
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
@@ -374,10 +374,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
       const uint32_t gi = c * N + row0 + (uint32_t)b * ng0 + s;
       const bool own = (s < K * E || last_x) && (b < K || last_y);
       const T dkv = sS[2 + c][b][s];
-      if (own) out[gi] = sS[c][b][s] - tau * dkv;
+      if (own) out[gi] = TO(sS[c][b][s] - tau * dkv);
       const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
       if (cons) {
-        if (own) out[nh1 + gi] = dkv;
+        if (own) out[nh1 + gi] = TO(dkv);
         continue;
       }
       const int zz = s / K, a = s - K * zz;
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
       if (b == 0 && r > 0) f += cr[c * NS + s];
       // atomics also where no other wave adds to the node: plain stores of the partial cache
       // lines of a strip cost more than the atomic updates on this chip
-      unsafeAtomicAdd(&out[nh1 + gi], f);
+      unsafeAtomicAdd(&out[nh1 + gi], TO(f));
     }
     // energy rows (element-owned): the column sums go through sO once the velocity is done
     __syncthreads();
@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
       T o = 0;
 #pragma unroll
       for (int q = 0; q < Q1D; ++q) o += sO[zz * Q1D + q][t];
-      out[2 * nh1 + ebase * NLD + i] = o;
+      out[2 * nh1 + ebase * NLD + i] = TO(o);
     }
   }
 }
@@ -470,12 +470,12 @@ static void lin_t(ilh_ctx* c, T* qd) {
           (const double*)c->w64, c->lin_tau, qd, lin2d_stride(c));
 }
 
-template <int K, typename T, int VISC, int SRC>
-static void apply_t(ilh_ctx* c, const T* dk, const T* qd, T* out) {
+template <int K, typename T, int VISC, int SRC, typename TO>
+static void apply_t(ilh_ctx* c, const T* dk, const T* qd, TO* out) {
   constexpr int D1D = K + 1, Q1D = 2 * K;
   const int R = apply_rows(c);
   const dim3 g = lin2d_grid(c);
-  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC>, dim3(g.x, (g.y + R - 1) / R), dim3(64), 0, c->kp,
+  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO>, dim3(g.x, (g.y + R - 1) / R), dim3(64), 0, c->kp,
           make_tab2<T, D1D, Q1D>(c), dk, qd, lin2d_stride(c), c->lin_tau, out, R);
 }
 
@@ -497,18 +497,18 @@ static int dispatch_lin(ilh_ctx* c, T* qd) {
   return ILH_OK;
 }
 
-template <typename T>
-static int dispatch_apply(ilh_ctx* c, const T* dk, const T* qd, T* out) {
+template <typename T, typename TO>
+static int dispatch_apply(ilh_ctx* c, const T* dk, const T* qd, TO* out) {
   const int v = c->kp.visc ? 1 : 0, s = c->kp.tg_source ? 1 : 0, code = 4 * c->k + 2 * v + s;
   switch (code) {
-    case 8: apply_t<2, T, 0, 0>(c, dk, qd, out); break;
-    case 9: apply_t<2, T, 0, 1>(c, dk, qd, out); break;
-    case 10: apply_t<2, T, 1, 0>(c, dk, qd, out); break;
-    case 11: apply_t<2, T, 1, 1>(c, dk, qd, out); break;
-    case 12: apply_t<3, T, 0, 0>(c, dk, qd, out); break;
-    case 13: apply_t<3, T, 0, 1>(c, dk, qd, out); break;
-    case 14: apply_t<3, T, 1, 0>(c, dk, qd, out); break;
-    case 15: apply_t<3, T, 1, 1>(c, dk, qd, out); break;
+    case 8: apply_t<2, T, 0, 0, TO>(c, dk, qd, out); break;
+    case 9: apply_t<2, T, 0, 1, TO>(c, dk, qd, out); break;
+    case 10: apply_t<2, T, 1, 0, TO>(c, dk, qd, out); break;
+    case 11: apply_t<2, T, 1, 1, TO>(c, dk, qd, out); break;
+    case 12: apply_t<3, T, 0, 0, TO>(c, dk, qd, out); break;
+    case 13: apply_t<3, T, 0, 1, TO>(c, dk, qd, out); break;
+    case 14: apply_t<3, T, 1, 0, TO>(c, dk, qd, out); break;
+    case 15: apply_t<3, T, 1, 1, TO>(c, dk, qd, out); break;
     default: return ILH_EINVAL;
   }
   ILH_HIP(c, hipGetLastError());
@@ -529,8 +529,16 @@ int launch_jvp2d_q(ilh_ctx* c, int prec, const void* dk, void* out) {
   if (!lin2d_supported(c)) return ILH_EINVAL;
   const int p = prec == 64 ? 1 : 0;
   if (!c->qd[p]) return fail(c, ILH_EINVAL, "linearised Jacobian action before its linearisation");
-  return p ? dispatch_apply<double>(c, (const double*)dk, (const double*)c->qd[p], (double*)out)
-           : dispatch_apply<float>(c, (const float*)dk, (const float*)c->qd[p], (float*)out);
+  return p ? dispatch_apply<double, double>(c, (const double*)dk, (const double*)c->qd[p], (double*)out)
+           : dispatch_apply<float, float>(c, (const float*)dk, (const float*)c->qd[p], (float*)out);
+}
+
+// FP32 action written straight into an FP64 vector (the Krylov basis): the velocity rows of out
+// must be zero on entry, the FP32 coefficients current.
+int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out) {
+  if (!lin2d_supported(c)) return ILH_EINVAL;
+  if (!c->qd[0] || !c->qd_ok[0]) return fail(c, ILH_EINVAL, "linearised Jacobian action before its linearisation");
+  return dispatch_apply<float, double>(c, dk, (const float*)c->qd[0], out);
 }
 
 bool lin2d_available(const ilh_ctx* c) { return lin2d_supported(c); }

@@ -862,31 +862,40 @@ struct Solver {
   double tau;
   int jvp_calls = 0;
 
-  int precond(const double* r, double* z) {
-    const int64_t nh1 = c->nh1;
+  // next_out (nullable): the FP64 output of the Jacobian action that will read z; when the
+  // FP32 action can write it directly, the preconditioner kernel also zeroes its velocity rows
+  int precond(const double* r, double* z, double* next_out = nullptr) {
     int st;
     const int slot = tstart(c, 4);
-    st = precond_body(r, z);
+    st = precond_body(r, z, next_out);
     tstop(c, slot);
     return st;
   }
 
   const double* z32_of = nullptr;  // the vector whose FP32 copy is in kry32 (written by precond)
+  const double* zeroed_v = nullptr;  // the FP64 vector whose velocity rows precond zeroed
 
-  int precond_body(const double* r, double* z) {
+  // FP32 linearised 2D actions write the FP64 Krylov vector directly
+  bool direct64() const { return o->jvp_prec == 32 && c->jvp_variant == 0 && lin2d_available(c); }
+
+  int precond_body(const double* r, double* z, double* next_out) {
     const int64_t nh1 = c->nh1;
     int st;
     z32_of = nullptr;
+    zeroed_v = nullptr;
+    double* zv = (next_out && direct64()) ? next_out + nh1 : nullptr;
     if (o->prec_probe) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled))) return st;
+      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv))) return st;
       if (z32) z32_of = z;
+      if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
     if (o->pcg_iters <= 0) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled))) return st;
+      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv))) return st;
       if (z32) z32_of = z;
+      if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
     ILH_HIP(c, hipMemcpyAsync(z, r, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -909,7 +918,22 @@ struct Solver {
       float* y32 = c->kry32 + c->nblock;
       // the preconditioner leaves the FP32 copy of its output in x32; it is used once
       const bool have32 = (x == z32_of);
+      const bool zeroed = (y == zeroed_v);
       z32_of = nullptr;
+      zeroed_v = nullptr;
+      if (have32 && zeroed && direct64()) {
+        if (!c->qd_ok[0]) {
+          const int ls = tstart_k(c, 5);
+          st = launch_lin2d(c, 32);
+          tstop_k(c, ls);
+          if (st) return st;
+          c->qd_ok[0] = true;
+        }
+        const int slot = tstart_k(c, 0);
+        st = launch_jvp2d_q_f32to64(c, x32, y);
+        tstop_k(c, slot);
+        return st;
+      }
       if (!have32 && (st = launch_cast_d2f(c, x32, x, c->nblock))) return st;
       if ((st = ilh_jvp_lin(c, 32, x32, y32))) return st;
       return launch_cast_f2d(c, y, y32, c->nblock);
@@ -962,18 +986,18 @@ struct Solver {
         double* Vj = V + (int64_t)j * n;
         double* Zj = Z + (int64_t)j * n;
         double* w = V + (int64_t)(j + 1) * n;
-        if ((st = precond(Vj, Zj))) return st;
+        if ((st = precond(Vj, Zj, w))) return st;
         if ((st = apply(Zj, w))) return st;
         // classical Gram-Schmidt, twice
         const int slot = tstart(c, 3);
         if ((st = multidot_fused(c, V, n, j + 1, w, n, hd))) return st;
         if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd, -1.0, n))) return st;
         if ((st = multidot_fused(c, V, n, j + 1, w, n, hd + 72))) return st;
-        if ((st = multiaxpy_nrm(c, w, V, n, j + 1, hd + 72, -1.0, n, hd + 144))) return st;
+        // second pass with the norm of w and the Givens update of step j in its final reduction
+        if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd, -1.0, n, G, j, m))) return st;
         tstop(c, slot);
-        // normalise on the device (no-op for a zero or non-finite norm), rotate, publish the estimate
+        // normalise on the device (no-op for a zero or non-finite norm), publish the estimate
         if ((st = launch_scale_by_norm(c, w, w, hd + 144, n))) return st;
-        if ((st = launch_givens(c, hd, G, j, m))) return st;
         ILH_HIP(c, hipMemcpyAsync(c->hhost + 352 + 2 * j, hd + 352 + 2 * j, 2 * sizeof(double),
                                   hipMemcpyDeviceToHost, c->stream));
         ILH_HIP(c, hipEventRecord(c->gev[j & 1], c->stream));

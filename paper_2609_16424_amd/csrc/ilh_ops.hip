@@ -284,6 +284,28 @@ int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double
   return ILH_OK;
 }
 
+__device__ void givens_update(double* h, double* G, int j, int m);
+
+// final sum of the norm partials into h[144], then the Givens update of Arnoldi step j
+__global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, double* h, double* G, int j, int m) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += TPB) acc += part[i];
+  acc = block_sum<TPB>(acc);
+  if (threadIdx.x == 0) {
+    h[144] = acc;
+    givens_update(h, G, j, m);
+  }
+}
+
+int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, double* h, double sign,
+                         int64_t n, double* G, int j, int mm) {
+  const int nb = fused_blocks(n);
+  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, h + 72, sign, n, c->red);
+  hipLaunchKernelGGL(k_sum_givens, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, h, G, j, mm);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
 int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign,
                   int64_t n, double* d_nrm2) {
   const int nb = fused_blocks(n);
@@ -300,8 +322,7 @@ int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, co
 // applied to the right-hand side g (g = beta e_1 at j = 0, beta in h[240]); the residual
 // estimate |g_{j+1}| and h_{j+1,j} go to h[352 + 2j], h[353 + 2j].
 // G layout: H [64][64] row-major (upper triangle after the rotations), cs [64], sn [64], g [65].
-__global__ void k_givens(double* h, double* G, int j, int m) {
-  if (threadIdx.x != 0) return;
+__device__ void givens_update(double* h, double* G, int j, int m) {
   double* H = G;
   double* cs = G + 64 * 64;
   double* sn = cs + 64;
@@ -326,6 +347,10 @@ __global__ void k_givens(double* h, double* G, int j, int m) {
   g[j] = c_ * g[j];
   h[352 + 2 * j] = fabs(g[j + 1]);
   h[353 + 2 * j] = hn;
+}
+
+__global__ void k_givens(double* h, double* G, int j, int m) {
+  if (threadIdx.x == 0) givens_update(h, G, j, m);
 }
 
 // y = H(0:n, 0:n)^-1 g(0:n) by back substitution (one thread)
@@ -372,8 +397,9 @@ int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d
 // z_e = M_E^-1 r_e; z32 (nullable) receives the FP32 copy of z.
 __global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
                           const double* __restrict__ Minv, const double* __restrict__ escale, double* z, float* z32,
-                          double tau, int coupled, int64_t nh1, int64_t Ne, int Nl) {
+                          double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (i < nh1) {
     const double zv = r[nh1 + i] / Mdiag[i];
     const double zx = coupled ? tau * zv + r[i] : r[i];
@@ -394,10 +420,10 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
   }
 }
 
-int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled) {
+int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled, double* zero_v) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   hipLaunchKernelGGL(k_precond, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv,
-                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl);
+                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -542,8 +568,9 @@ int launch_invert_blocks(ilh_ctx* c, double* B) {
 // z_v = r_v / D (probed diagonal), z_x = r_x + tau z_v (coupled) or r_x, z_e = Binv r_e per element
 __global__ void k_precond_probe(const double* __restrict__ r, const double* __restrict__ D,
                                 const double* __restrict__ Binv, double* z, float* z32, double tau, int coupled,
-                                int64_t nh1, int64_t Ne, int Nl) {
+                                int64_t nh1, int64_t Ne, int Nl, double* zero_v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (i < nh1) {
     const double zv = r[nh1 + i] / D[i];
     const double zx = coupled ? tau * zv + r[i] : r[i];
@@ -564,10 +591,11 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
   }
 }
 
-int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled) {
+int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
+                         double* zero_v) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   hipLaunchKernelGGL(k_precond_probe, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->pdv,
-                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl);
+                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
