@@ -116,6 +116,9 @@ struct ilh_ctx {
   double* hhost = nullptr;      // pinned mirror of hdev
   double* gmd = nullptr;        // device Givens state of FGMRES: H [64][64], cs, sn [64], g [65]
   hipEvent_t gev[2] = {nullptr, nullptr};  // FGMRES: residual estimates of alternate steps ready
+  hipStream_t capstream = nullptr;         // stream the Arnoldi-step graphs are captured on
+  std::vector<hipGraphExec_t> gexec;       // captured Arnoldi step per basis index
+  uint64_t gkey = 0;                       // configuration the graphs were captured for
   int apply_rows = 0;           // element rows per apply wave of the linearised kernels (0: by mesh size)
   int jvp_variant = 0;          // 0 linearised (where available), 1 generic, 2 register-resident recompute
   void* qd[2] = {nullptr, nullptr};  // stored tangent coefficients, FP32 / FP64 (linearised variant)
@@ -203,7 +206,7 @@ int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, co
                   int64_t n, double* d_nrm2);
 int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n);
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                   double* zero_v = nullptr);
+                   double* zero_v = nullptr, const double* tau_dev = nullptr);
 // probed diagonal blocks of the Jacobian (preconditioner option prec_probe)
 int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau);
 int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D);
@@ -211,10 +214,10 @@ int launch_probe_e_dir(ilh_ctx* c, float* d, int j);
 int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
 int launch_invert_blocks(ilh_ctx* c, double* B);
 int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v = nullptr);
+                         double* zero_v = nullptr, const double* tau_dev = nullptr);
 int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, double* h, double sign,
                          int64_t n, double* G, int j, int mm);
-int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out);
+int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);
 int l1_error_host(ilh_ctx* c, const double* u, double* out);

@@ -243,6 +243,7 @@ void ilh_newton_defaults(ilh_newton_opts* o) {
   o->ls_residual = 1;
   o->prec_probe = 0;
   o->prec_lag = 0;
+  o->graphs = 0;
 }
 
 const char* ilh_last_error(const ilh_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -273,6 +274,9 @@ void ilh_destroy(ilh_ctx* c) {
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->gev)
     if (e) (void)hipEventDestroy(e);
+  for (hipGraphExec_t e : c->gexec)
+    if (e) (void)hipGraphExecDestroy(e);
+  if (c->capstream) (void)hipStreamDestroy(c->capstream);
   if (c->red_host) (void)hipHostFree(c->red_host);
   if (c->hhost) (void)hipHostFree(c->hhost);
   delete c;
@@ -884,16 +888,17 @@ struct Solver {
     z32_of = nullptr;
     zeroed_v = nullptr;
     double* zv = (next_out && direct64()) ? next_out + nh1 : nullptr;
+    const double* tdev = c->hdev + 250;  // tau on the device (set at the start of each solve)
     if (o->prec_probe) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv))) return st;
+      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv, tdev))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
     if (o->pcg_iters <= 0) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv))) return st;
+      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv, tdev))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
@@ -930,7 +935,7 @@ struct Solver {
           c->qd_ok[0] = true;
         }
         const int slot = tstart_k(c, 0);
-        st = launch_jvp2d_q_f32to64(c, x32, y);
+        st = launch_jvp2d_q_f32to64(c, x32, y, c->hdev + 250);
         tstop_k(c, slot);
         return st;
       }
@@ -939,6 +944,88 @@ struct Solver {
       return launch_cast_f2d(c, y, y32, c->nblock);
     }
     return ilh_jvp_lin(c, 64, x, y);
+  }
+
+  // One Arnoldi step j: z_j = P v_j, w = J z_j, two Gram-Schmidt passes with the Givens
+  // update, normalisation, and the pinned copy of the residual estimate.
+  int arnoldi_step(int j, int m) {
+    const int64_t n = c->nblock;
+    double* V = c->kry;
+    double* Z = c->kry + (int64_t)(m + 1) * n;
+    double* hd = c->hdev;
+    double* Vj = V + (int64_t)j * n;
+    double* Zj = Z + (int64_t)j * n;
+    double* w = V + (int64_t)(j + 1) * n;
+    int st;
+    if ((st = precond(Vj, Zj, w))) return st;
+    if ((st = apply(Zj, w))) return st;
+    // classical Gram-Schmidt, twice
+    const int slot = tstart(c, 3);
+    if ((st = multidot_fused(c, V, n, j + 1, w, n, hd))) return st;
+    if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd, -1.0, n))) return st;
+    if ((st = multidot_fused(c, V, n, j + 1, w, n, hd + 72))) return st;
+    // second pass with the norm of w and the Givens update of step j in its final reduction
+    if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd, -1.0, n, c->gmd, j, m))) return st;
+    tstop(c, slot);
+    // normalise on the device (no-op for a zero or non-finite norm), publish the estimate
+    if ((st = launch_scale_by_norm(c, w, w, hd + 144, n))) return st;
+    ILH_HIP(c, hipMemcpyAsync(c->hhost + 352 + 2 * j, hd + 352 + 2 * j, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    return ILH_OK;
+  }
+
+  // Graph replay applies when every kernel of the step reads its varying inputs from device
+  // memory (tau) and no kernel of it synchronises: linearised FP32 2D actions with the mass or
+  // probed preconditioner, kernel timing off.
+  bool graphable() const { return o->graphs && !c->timing && direct64() && o->pcg_iters <= 0; }
+
+  uint64_t graph_key(int m) const {
+    uint64_t k = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
+    const void* ptrs[] = {c->kry, c->kry32, c->hdev, c->hhost, c->gmd, c->red, c->qd[0], c->Mdiag, c->MEinv,
+                          c->pdv, c->peinv, c->rj0};
+    for (const void* q : ptrs) mix((uint64_t)(uintptr_t)q);
+    mix((uint64_t)m);
+    mix((uint64_t)o->prec_probe);
+    mix((uint64_t)o->prec_coupled);
+    mix((uint64_t)c->apply_rows);
+    mix((uint64_t)c->nblock);
+    return k;
+  }
+
+  // The captured step j (captured on first use for this configuration).
+  int graph_for(int j, int m, hipGraphExec_t* out) {
+    const uint64_t key = graph_key(m);
+    if (key != c->gkey) {
+      for (hipGraphExec_t e : c->gexec)
+        if (e) (void)hipGraphExecDestroy(e);
+      c->gexec.assign(64, nullptr);
+      c->gkey = key;
+    }
+    if (!c->gexec[j]) {
+      if (!c->capstream) ILH_HIP(c, hipStreamCreateWithFlags(&c->capstream, hipStreamNonBlocking));
+      hipStream_t saved = c->stream;
+      c->stream = c->capstream;
+      ILH_HIP(c, hipStreamBeginCapture(c->capstream, hipStreamCaptureModeThreadLocal));
+      const int calls = jvp_calls;  // the replays count the action
+      const int st = arnoldi_step(j, m);
+      jvp_calls = calls;
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(c->capstream, &g);
+      c->stream = saved;
+      if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      ILH_HIP(c, e);
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      ILH_HIP(c, ei);
+      c->gexec[j] = ex;
+    }
+    *out = c->gexec[j];
+    return ILH_OK;
   }
 
   // FGMRES: solve J x = b, x starts at 0.  Returns total iterations in *its.
@@ -964,6 +1051,13 @@ struct Solver {
     const double* rhs = b;
     double* rbuf = c->nwt + 3 * n;  // tmp vector
     int total = 0;
+    c->hhost[250] = tau;
+    ILH_HIP(c, hipMemcpyAsync(hd + 250, &c->hhost[250], sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const bool use_graph = graphable();
+    if (use_graph && !c->qd_ok[0]) {  // the linearisation stays outside the captured steps
+      if ((st = launch_lin2d(c, 32))) return st;
+      c->qd_ok[0] = true;
+    }
     while (true) {
       // V0 = r / beta
       c->hhost[240] = beta;
@@ -983,23 +1077,14 @@ struct Solver {
       };
       bool end = false;
       for (int j = 0; j < m && !end; ++j) {
-        double* Vj = V + (int64_t)j * n;
-        double* Zj = Z + (int64_t)j * n;
-        double* w = V + (int64_t)(j + 1) * n;
-        if ((st = precond(Vj, Zj, w))) return st;
-        if ((st = apply(Zj, w))) return st;
-        // classical Gram-Schmidt, twice
-        const int slot = tstart(c, 3);
-        if ((st = multidot_fused(c, V, n, j + 1, w, n, hd))) return st;
-        if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd, -1.0, n))) return st;
-        if ((st = multidot_fused(c, V, n, j + 1, w, n, hd + 72))) return st;
-        // second pass with the norm of w and the Givens update of step j in its final reduction
-        if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd, -1.0, n, G, j, m))) return st;
-        tstop(c, slot);
-        // normalise on the device (no-op for a zero or non-finite norm), publish the estimate
-        if ((st = launch_scale_by_norm(c, w, w, hd + 144, n))) return st;
-        ILH_HIP(c, hipMemcpyAsync(c->hhost + 352 + 2 * j, hd + 352 + 2 * j, 2 * sizeof(double),
-                                  hipMemcpyDeviceToHost, c->stream));
+        if (use_graph) {
+          hipGraphExec_t ex;
+          if ((st = graph_for(j, m, &ex))) return st;
+          ILH_HIP(c, hipGraphLaunch(ex, c->stream));
+          ++jvp_calls;
+        } else if ((st = arnoldi_step(j, m))) {
+          return st;
+        }
         ILH_HIP(c, hipEventRecord(c->gev[j & 1], c->stream));
         if (j >= 1) {
           if ((st = check(j - 1, end))) return st;

@@ -397,9 +397,11 @@ int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d
 // z_e = M_E^-1 r_e; z32 (nullable) receives the FP32 copy of z.
 __global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
                           const double* __restrict__ Minv, const double* __restrict__ escale, double* z, float* z32,
-                          double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v) {
+                          double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v,
+                          const double* tau_dev) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
+  if (tau_dev) tau = *tau_dev;
   if (i < nh1) {
     const double zv = r[nh1 + i] / Mdiag[i];
     const double zx = coupled ? tau * zv + r[i] : r[i];
@@ -420,10 +422,11 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
   }
 }
 
-int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled, double* zero_v) {
+int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled, double* zero_v,
+                   const double* tau_dev) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   hipLaunchKernelGGL(k_precond, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv,
-                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v);
+                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -568,9 +571,10 @@ int launch_invert_blocks(ilh_ctx* c, double* B) {
 // z_v = r_v / D (probed diagonal), z_x = r_x + tau z_v (coupled) or r_x, z_e = Binv r_e per element
 __global__ void k_precond_probe(const double* __restrict__ r, const double* __restrict__ D,
                                 const double* __restrict__ Binv, double* z, float* z32, double tau, int coupled,
-                                int64_t nh1, int64_t Ne, int Nl, double* zero_v) {
+                                int64_t nh1, int64_t Ne, int Nl, double* zero_v, const double* tau_dev) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
+  if (tau_dev) tau = *tau_dev;
   if (i < nh1) {
     const double zv = r[nh1 + i] / D[i];
     const double zx = coupled ? tau * zv + r[i] : r[i];
@@ -592,10 +596,10 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
 }
 
 int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v) {
+                         double* zero_v, const double* tau_dev) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   hipLaunchKernelGGL(k_precond_probe, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->pdv,
-                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v);
+                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }

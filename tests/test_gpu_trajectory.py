@@ -47,3 +47,34 @@ def test_stage_failure_paths():
     k, st = G.implicit_step(uu, 50.0, opts=opts, raise_on_fail=False)
     assert st["status"] in (ilh._lib.ILH_ETANGLED, ilh._lib.ILH_ENOCONV)
     assert torch.equal(uu, u)  # state untouched on failure
+
+
+@pytest.mark.parametrize("case", ["tg2d", "triple"])
+def test_graph_replay_matches_eager_launches(case):
+    """Arnoldi steps replayed as captured HIP graphs give the trajectory of the kernel-by-kernel
+    path (graphs = 0) over many steps, each graph replayed many times with eager work between."""
+    if case == "tg2d":
+        mk = lambda: ilh.Hydro("tg2d", (24, 20), 3)
+        opts_kw = dict(tol=1e-10, jvp_prec=32)
+        fac = 4.0
+    else:
+        from paper_2609_16424_amd import learned as L
+        mk = lambda: L.make_triple(28, 12, 3)
+        opts_kw = dict(tol=1e-10, jvp_prec=32, prec_probe=2, prec_lag=1)
+        fac = 2.0
+    states = {}
+    for graphs in (0, 1):
+        G = mk()
+        u = G.init_state()
+        dt = fac * G.dt_estimate(u, 0.5)
+        opts = ilh.newton_options(graphs=graphs, **opts_kw)
+        hist, traj = [], []
+        for _ in range(6):
+            g = G.plain_guess(u, hist, 0.5 * dt)
+            k, st = G.implicit_step(u, dt, guess=g, opts=opts)
+            assert st["status"] == 0
+            hist = (hist + [k])[-2:]
+            traj.append(to_np(u))
+        states[graphs] = traj
+    for a, b in zip(states[0], states[1]):
+        assert rel(a, b) <= 1e-9
