@@ -152,7 +152,7 @@ int ilh_jvp(ilh_ctx* ctx, int prec, const double* k, const double* u, double tau
  * stored tangent coefficients as ilh_jvp_lin (evaluated on the first call of a precision after
  * ilh_linearize) and satisfies <y, J dk> = <J^T y, dk> to rounding.  prec = 64: y, jty double
  * [block]; prec = 32: float [block], FP32 arithmetic.  Built for 2D meshes with k = 2, 3
- * (otherwise ILH_EINVAL). */
+ * and 3D meshes with k = 2 without the TG source (otherwise ILH_EINVAL). */
 int ilh_vjp_lin(ilh_ctx* ctx, int prec, const void* y, void* jty);
 
 /* ilh_linearize followed by ilh_vjp_lin. */

@@ -171,7 +171,7 @@ class Hydro:
         return self.jvp_lin(dk, prec)
 
     def vjp_lin(self, y, prec=64, out=None):
-        """Transpose Jacobian action J^T y at the stored linearisation point (2D, k = 2, 3)."""
+        """Transpose Jacobian action J^T y at the stored linearisation point (2D k = 2, 3; 3D k = 2)."""
         dt = torch.float64 if prec == 64 else torch.float32
         o = self.new(dtype=dt) if out is None else out
         self._stream()
@@ -392,7 +392,7 @@ class ForceFn(torch.autograd.Function):
 
 class ResidualFn(torch.autograd.Function):
     """R(k; tau, u) with forward-mode derivative J dk from ilh_jvp and reverse-mode derivative
-    J^T g from ilh_vjp (FP64; the reverse mode is built for 2D meshes with k = 2, 3)."""
+    J^T g from ilh_vjp (FP64; the reverse mode is built for 2D meshes with k = 2, 3 and 3D with k = 2)."""
 
     @staticmethod
     def forward(hydro, k, u, tau):

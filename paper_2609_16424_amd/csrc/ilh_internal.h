@@ -173,6 +173,7 @@ bool lin2d_available(const ilh_ctx* c);
 int launch_lin2d(ilh_ctx* c, int prec);
 int launch_jvp2d_q(ilh_ctx* c, int prec, const void* dk, void* out);
 int launch_vjp2d_q(ilh_ctx* c, int prec, const void* y, void* out);
+int launch_vjp3d_q(ilh_ctx* c, int prec, const void* y, void* out);
 int lin2d_nqd(const ilh_ctx* c);
 int64_t lin2d_stride(const ilh_ctx* c);
 // linearised 3D Jacobian action (Q2Q1, no source)

@@ -657,7 +657,9 @@ int ilh_jvp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, 
 int ilh_vjp_lin(ilh_ctx* c, int prec, const void* y, void* jty) {
   if (!c || !y || !jty) return ILH_EINVAL;
   if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
-  if (!lin2d_available(c)) return fail(c, ILH_EINVAL, "the transpose action is built for 2D meshes with k = 2, 3");
+  const bool d3 = c->dim == 3;
+  if (!(d3 ? lin3d_available(c) : lin2d_available(c)))
+    return fail(c, ILH_EINVAL, "the transpose action is built for 2D meshes with k = 2, 3 and 3D with k = 2");
   int st;
   if (prec == 64) {
     if ((st = launch_fill(c, (double*)jty, 0.0, 2 * c->nh1))) return st;
@@ -667,13 +669,13 @@ int ilh_vjp_lin(ilh_ctx* c, int prec, const void* y, void* jty) {
   const int p = prec == 64 ? 1 : 0;
   if (!c->qd_ok[p]) {
     const int ls = tstart_k(c, 5);
-    st = launch_lin2d(c, prec);
+    st = d3 ? launch_lin3d(c, prec) : launch_lin2d(c, prec);
     tstop_k(c, ls);
     if (st) return st;
     c->qd_ok[p] = true;
   }
   const int slot = tstart_k(c, 6);
-  st = launch_vjp2d_q(c, prec, y, jty);
+  st = d3 ? launch_vjp3d_q(c, prec, y, jty) : launch_vjp2d_q(c, prec, y, jty);
   tstop_k(c, slot);
   return st;
 }

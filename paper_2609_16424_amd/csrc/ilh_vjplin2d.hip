@@ -257,6 +257,265 @@ __global__ void __launch_bounds__(64) k_vjp2d_q(const KParams P, const Tab2<T, D
   }
 }
 
+// ---- 3D, Q2Q1: the transpose of k_jvp3d_q ------------------------------------------------
+// One wave = EPW = 4 consecutive elements of an element row, lane (element, q_x, q_y) owns a
+// quadrature column and walks q_z, as in the 3D forward kernels; the coefficients are read in
+// the layout k_lin3d stores them (row-interleaved in FP32, field-major in FP64).
+template <int D1D, int Q1D, typename T, int VISC>
+__global__ void __launch_bounds__(64) k_vjp3d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
+                                                const T* __restrict__ y, const T* __restrict__ qd, int64_t qs,
+                                                double tau_, T* __restrict__ out) {
+  constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D * L1D;
+  constexpr int LPE = Q1D * Q1D, EPW = 64 / LPE;
+  constexpr int NS = K * EPW + 1;
+  constexpr int NQD = LinLayout<3, VISC, 0>::NQD;
+  constexpr int NF = 6;  // y_x0 y_x1 y_x2, y~_v0 y~_v1 y~_v2 (constrained velocity rows zeroed)
+  constexpr int NND = D1D * D1D * D1D;
+  constexpr int NOP = (NND > NLD ? NND : NLD) | 1;
+
+  __shared__ T sS[NF][D1D][D1D][NS];
+  __shared__ T sE[EPW * NLD];
+  __shared__ T sO[64][NOP];
+  __shared__ T sBG[2][Q1D][D1D];
+  __shared__ T sBL[Q1D][L1D];
+
+  const int lane = threadIdx.x;
+  const uint32_t tile = xcd_tile((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x,
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int ex0 = (tile % gridDim.x) * EPW, ey = (tile / gridDim.x) % gridDim.y, ez = tile / (gridDim.x * gridDim.y);
+  const int nx = P.n[0], ny = P.n[1];
+  const int E = min(EPW, nx - ex0);
+  const int ns = K * E + 1;
+  const uint32_t ng0 = P.ng[0], ng1 = P.ng[1], ng2 = P.ng[2], ng01 = ng0 * ng1;
+  const uint32_t N = (uint32_t)P.N, nh1 = 3 * N;
+  const uint32_t ebase = ((uint32_t)ez * ny + ey) * nx + ex0;
+  const uint32_t row0 = (uint32_t)(K * ez) * ng01 + (uint32_t)(K * ey) * ng0 + (uint32_t)(K * ex0);
+  const T tau = T(tau_);
+
+  constexpr int NTS = NF * D1D * D1D * NS, RT = (NTS + 63) / 64;
+  constexpr int NLS = EPW * NLD, RL = (NLS + 63) / 64;
+  T tr[RT], lr[RL];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = lane + 64 * r, s = min(i % NS, ns - 1), t = min(i / NS, NF * D1D * D1D - 1), b = t % D1D,
+              cz = (t / D1D) % D1D, f = t / (D1D * D1D);
+    const T v = ld32(y, (f < 3 ? f * N : nh1 + (f - 3) * N) + row0 + (uint32_t)cz * ng01 + (uint32_t)b * ng0 + s);
+    const uint32_t I = K * ex0 + s, J = K * ey + b, Kz = K * ez + cz;
+    const uint32_t idx = f == 3 ? I : (f == 4 ? J : Kz), ngf = f == 3 ? ng0 : (f == 4 ? ng1 : ng2);
+    tr[r] = (f >= 3 && (idx == 0 || idx == ngf - 1)) ? T(0) : v;
+  }
+#pragma unroll
+  for (int r = 0; r < RL; ++r) lr[r] = ld32(y, 2 * nh1 + ebase * NLD + min(lane + 64 * r, E * NLD - 1));
+  const int zl = lane / LPE;
+  const double rj_l = P.rj0[ebase + (zl < E ? zl : 0)];
+  for (int i = lane; i < Q1D * D1D; i += 64) {
+    sBG[0][i / D1D][i % D1D] = tb.B[i / D1D][i % D1D];
+    sBG[1][i / D1D][i % D1D] = tb.G[i / D1D][i % D1D];
+  }
+  for (int i = lane; i < Q1D * L1D; i += 64) sBL[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = lane + 64 * r;
+    if (i < NTS) (&sS[0][0][0][0])[i] = tr[r];
+  }
+#pragma unroll
+  for (int r = 0; r < RL; ++r) {
+    const int i = lane + 64 * r;
+    if (i < NLS) sE[i] = lr[r];
+  }
+  __syncthreads();
+
+  const int z = lane / LPE, rr = lane - z * LPE, qy = rr / Q1D, qx = rr - qy * Q1D;
+  const bool active = z < E;
+  // per-lane sums over the column for the position (X*) and velocity (V*) rows: coefficients of
+  // G_x B_y (x), B_x G_y (y), B_x B_y (z: derivative along z plus the value terms) per layer
+  T Xx[3][D1D], Xy[3][D1D], Xz[3][D1D], Vx[3][D1D], Vy[3][D1D], Vz[3][D1D], TL[L1D];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < D1D; ++c) Xx[r][c] = Xy[r][c] = Xz[r][c] = Vx[r][c] = Vy[r][c] = Vz[r][c] = T(0);
+#pragma unroll
+  for (int cl = 0; cl < L1D; ++cl) TL[cl] = T(0);
+  if (active) {
+    const int s0 = K * z;
+    T Bx[D1D], Gx[D1D], By[D1D], Gy[D1D];
+#pragma unroll
+    for (int a = 0; a < D1D; ++a) {
+      Bx[a] = sBG[0][qx][a];
+      Gx[a] = sBG[1][qx][a];
+      By[a] = sBG[0][qy][a];
+      Gy[a] = sBG[1][qy][a];
+    }
+    T BB[3][D1D], GB[3][D1D], BG[3][D1D];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int cz = 0; cz < D1D; ++cz) {
+        T bb = 0, gb = 0, bg = 0;
+#pragma unroll
+        for (int b = 0; b < D1D; ++b) {
+          T ab = 0, ag = 0;
+#pragma unroll
+          for (int a = 0; a < D1D; ++a) {
+            const T xv = sS[3 + f][cz][b][s0 + a];
+            ab += Bx[a] * xv;
+            ag += Gx[a] * xv;
+          }
+          bb += By[b] * ab;
+          gb += By[b] * ag;
+          bg += Gy[b] * ab;
+        }
+        BB[f][cz] = bb;
+        GB[f][cz] = gb;
+        BG[f][cz] = bg;
+      }
+    T EL[L1D];
+#pragma unroll
+    for (int cl = 0; cl < L1D; ++cl) {
+      T acc = 0;
+#pragma unroll
+      for (int bl = 0; bl < L1D; ++bl)
+#pragma unroll
+        for (int al = 0; al < L1D; ++al)
+          acc += sBL[qy][bl] * sBL[qx][al] * sE[z * NLD + al + L1D * (bl + L1D * cl)];
+      EL[cl] = acc;
+    }
+    const T wxy = tb.W[qx] * tb.W[qy] * T(rj_l);
+    constexpr bool ROWS = sizeof(T) == 4;
+    const T* __restrict__ qb = qd + (int64_t)tile * (Q1D * (ROWS ? NQD : 1) * 64);
+#pragma unroll 1
+    for (int qz = 0; qz < Q1D; ++qz) {
+      T cf[NQD];
+      if constexpr (ROWS) {
+        const T* rb = sbase(qb + qz * (NQD * 64));
+#pragma unroll
+        for (int f = 0; f < NQD; ++f) cf[f] = ld32(rb, (uint32_t)(f * 64 + lane));
+      } else {
+#pragma unroll
+        for (int f = 0; f < NQD; ++f) cf[f] = ld32(sbase(qb + f * qs), (uint32_t)(qz * 64 + lane));
+      }
+      T A[3][3], yv[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        T a0 = 0, a1 = 0, a2 = 0, m = 0;
+#pragma unroll
+        for (int c = 0; c < D1D; ++c) {
+          const T Bz = tb.B[qz][c], Gz = tb.G[qz][c];
+          a0 += Bz * GB[r][c];
+          a1 += Bz * BG[r][c];
+          a2 += Gz * BB[r][c];
+          m += Bz * BB[r][c];
+        }
+        A[r][0] = a0;
+        A[r][1] = a1;
+        A[r][2] = a2;
+        yv[r] = m;
+      }
+      T ye = 0;
+#pragma unroll
+      for (int cl = 0; cl < L1D; ++cl) ye += tb.BL[qz][cl] * EL[cl];
+      const T mq = wxy * tb.W[qz];
+      T GJ[3][3], GGv[3][3], ge;
+      lin_apply_t<3, T, VISC>(cf, A, -ye, GJ, GGv, ge);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < D1D; ++c) {
+          const T Bz = tb.B[qz][c], Gz = tb.G[qz][c];
+          Xx[r][c] += Bz * GJ[r][0];
+          Xy[r][c] += Bz * GJ[r][1];
+          Xz[r][c] += Gz * GJ[r][2];
+          Vx[r][c] += Bz * GGv[r][0];
+          Vy[r][c] += Bz * GGv[r][1];
+          Vz[r][c] += Gz * GGv[r][2] + Bz * (mq * yv[r]);
+        }
+      }
+      const T te = ge + mq * ye;
+#pragma unroll
+      for (int cl = 0; cl < L1D; ++cl) TL[cl] += tb.BL[qz][cl] * te;
+    }
+  }
+  // H1 rows (position part, then velocity part), one component at a time: factored expansion of
+  // each lane's column sums into sO, node sums over the (one or two) elements of the strip
+  // holding the node, the owner's identity terms, one atomic per node and strip
+  const T Bxl[D1D] = {sBG[0][qx][0], sBG[0][qx][1], sBG[0][qx][2]};
+  const T Gxl[D1D] = {sBG[1][qx][0], sBG[1][qx][1], sBG[1][qx][2]};
+  const T Byl[D1D] = {sBG[0][qy][0], sBG[0][qy][1], sBG[0][qy][2]};
+  const T Gyl[D1D] = {sBG[1][qy][0], sBG[1][qy][1], sBG[1][qy][2]};
+  const bool last_x = (ex0 + E == nx), last_y = (ey == ny - 1), last_z = (ez == P.n[2] - 1);
+#pragma unroll 1
+  for (int pr = 0; pr < 6; ++pr) {
+    const int part = pr / 3, r = pr % 3;
+    if (active) {
+#pragma unroll
+      for (int cz = 0; cz < D1D; ++cz) {
+        T tx = 0, ty = 0, tzv = 0;
+#pragma unroll
+        for (int rq = 0; rq < 3; ++rq)
+          if (rq == r) {
+            tx = part == 0 ? Xx[rq][cz] : Vx[rq][cz];
+            ty = part == 0 ? Xy[rq][cz] : Vy[rq][cz];
+            tzv = part == 0 ? Xz[rq][cz] : Vz[rq][cz];
+          }
+#pragma unroll
+        for (int a = 0; a < D1D; ++a) {
+          const T q1 = Gxl[a] * tx + Bxl[a] * tzv, q2 = Bxl[a] * ty;
+#pragma unroll
+          for (int b = 0; b < D1D; ++b) sO[lane][(cz * D1D + b) * D1D + a] = Byl[b] * q1 + Gyl[b] * q2;
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i < D1D * D1D * NS; i += 64) {
+      const int s = i % NS, t = i / NS, b = t % D1D, cz = t / D1D;
+      if (s >= ns) continue;
+      const int zz = s / K, a = s - K * zz;
+      T o = 0;
+      if (zz < E) {
+#pragma unroll
+        for (int q = 0; q < LPE; ++q) o += sO[zz * LPE + q][(cz * D1D + b) * D1D + a];
+      }
+      if (a == 0 && zz > 0) {
+#pragma unroll
+        for (int q = 0; q < LPE; ++q) o += sO[(zz - 1) * LPE + q][(cz * D1D + b) * D1D + K];
+      }
+      const uint32_t gi = r * N + row0 + cz * ng01 + b * ng0 + s;
+      const bool own = (s < K * E || last_x) && (b < K || last_y) && (cz < K || last_z);
+      if (own) {
+        const T yx = sS[r][cz][b][s];
+        if (part == 0) {
+          o += yx;
+        } else {
+          o -= tau * yx;
+          const uint32_t I = K * ex0 + s, J = K * ey + b, Kz = K * ez + cz;
+          const uint32_t idx = r == 0 ? I : (r == 1 ? J : Kz), ngr = r == 0 ? ng0 : (r == 1 ? ng1 : ng2);
+          if (idx == 0 || idx == ngr - 1) o += y[nh1 + gi];
+        }
+      }
+      unsafeAtomicAdd(&out[part * nh1 + gi], o);
+    }
+    __syncthreads();
+  }
+  // energy rows (element-owned)
+  if (active) {
+#pragma unroll
+    for (int cl = 0; cl < L1D; ++cl)
+#pragma unroll
+      for (int bl = 0; bl < L1D; ++bl)
+#pragma unroll
+        for (int al = 0; al < L1D; ++al) sO[lane][al + L1D * (bl + L1D * cl)] = sBL[qx][al] * sBL[qy][bl] * TL[cl];
+  }
+  __syncthreads();
+  if (active) {
+    for (int t = rr; t < NLD; t += LPE) {
+      T o = 0;
+#pragma unroll
+      for (int q = 0; q < LPE; ++q) o += sO[z * LPE + q][t];
+      out[2 * nh1 + (ebase + z) * NLD + t] = o;
+    }
+  }
+}
+
 // ---- host side ---------------------------------------------------------------------------
 template <typename T, int D1D, int Q1D>
 static Tab2<T, D1D, Q1D> vjp_tab2(const ilh_ctx* c) {
@@ -296,6 +555,28 @@ static int dispatch_vjp(ilh_ctx* c, const T* y, const T* qd, T* out) {
   }
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
+}
+
+template <typename T>
+static int dispatch_vjp3(ilh_ctx* c, const T* y, const T* qd, T* out) {
+  constexpr int EPW = 4;
+  const dim3 g((c->n[0] + EPW - 1) / EPW, c->n[1], c->n[2]);
+  const int64_t qs = (int64_t)g.x * g.y * g.z * 4 * 64;
+  if (c->kp.visc)
+    klaunch(c, k_vjp3d_q<3, 4, T, 1>, g, dim3(64), 0, c->kp, vjp_tab2<T, 3, 4>(c), y, qd, qs, c->lin_tau, out);
+  else
+    klaunch(c, k_vjp3d_q<3, 4, T, 0>, g, dim3(64), 0, c->kp, vjp_tab2<T, 3, 4>(c), y, qd, qs, c->lin_tau, out);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+// Transpose action with the stored coefficients of precision prec (they must be current).
+int launch_vjp3d_q(ilh_ctx* c, int prec, const void* y, void* out) {
+  if (!lin3d_available(c)) return ILH_EINVAL;
+  const int p = prec == 64 ? 1 : 0;
+  if (!c->qd[p] || !c->qd_ok[p]) return fail(c, ILH_EINVAL, "transpose action before its linearisation");
+  return p ? dispatch_vjp3<double>(c, (const double*)y, (const double*)c->qd[p], (double*)out)
+           : dispatch_vjp3<float>(c, (const float*)y, (const float*)c->qd[p], (float*)out);
 }
 
 // Transpose action with the stored coefficients of precision prec (they must be current).

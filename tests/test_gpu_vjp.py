@@ -77,9 +77,43 @@ def test_residual_autograd_backward():
     assert rel(to_np(fn(to_dev(gy))[0]), ref) <= 1e-12
 
 
-def test_vjp_rejected_in_3d():
+@pytest.mark.parametrize("n,visc", [((5, 2, 1), None), ((6, 1, 2), "formula")])
+def test_vjp_3d_matches_oracle(n, visc):
+    """3D Q2Q1 (4 elements per wave: two strips, the second partial)."""
+    from oracle.krylov import vjp_colored
+    O, G = make_pair("tg3d", n, 2, visc)
+    u = random_state(O, 81)
+    kk = 0.1 * random_dir(O, 82)
+    y = random_dir(O, 83)
+    tau = 0.003
+    ref = vjp_colored(O, lambda q: O.residual(q, u, tau), kk, y)
+    G.linearize(to_dev(kk), to_dev(u), tau)
+    assert rel(to_np(G.vjp_lin(to_dev(y), 64)), ref) <= 1e-12
+    assert rel(to_np(G.vjp_lin(to_dev(y, torch.float32), 32)), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("visc", [False, True])
+def test_vjp_3d_adjoint_identity(visc):
+    import paper_2609_16424_amd as ilh
+    G = ilh.Hydro("tg3d", (24, 20, 18), 2, visc=visc, dscale_mode="formula" if visc else "const", h_coarse=0.5)
+    u = G.init_state()
+    g = torch.Generator(device=u.device).manual_seed(6)
+    u[:G.nh1] += 0.05 * u[G.nh1:2 * G.nh1]
+    kk = 0.1 * torch.randn(G.nblock, device=u.device, dtype=torch.float64, generator=g)
+    G.linearize(kk, u, 0.5 * G.dt_estimate(u, 2.0))
+    for prec, tol in ((64, 1e-12), (32, 1e-5)):
+        dt = torch.float64 if prec == 64 else torch.float32
+        y = torch.randn(G.nblock, device=u.device, dtype=torch.float64, generator=g)
+        dk = torch.randn(G.nblock, device=u.device, dtype=torch.float64, generator=g)
+        jdk = G.jvp_lin(dk.to(dt), prec).double()
+        jty = G.vjp_lin(y.to(dt), prec).double()
+        scale = float(torch.linalg.norm(y) * torch.linalg.norm(jdk))
+        assert abs(float(y @ jdk) - float(jty @ dk)) <= tol * scale
+
+
+def test_vjp_rejected_without_kernel():
     from paper_2609_16424_amd import IlhError
-    O, G = make_pair("tg3d", (3, 2, 2), 2)
+    O, G = make_pair("tg3d", (3, 2, 2), 1)  # no linearised 3D kernel at k = 1
     u = to_dev(O.init_state())
     with pytest.raises(IlhError):
         G.vjp(torch.zeros_like(u), u, 0.01, torch.ones_like(u), 64)
