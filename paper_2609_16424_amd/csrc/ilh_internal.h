@@ -194,17 +194,13 @@ int launch_scale_free(ilh_ctx* c, double* y, double a, const double* x);  // H1:
 int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* out);
 // device-side dot into d_out (no sync)
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
-int multidot_dev(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);
 // Arnoldi scalars: [0, 72) and [72, 144) the two Gram-Schmidt passes, 144 the norm, [160, 224)
 // the update coefficients, 240 beta, [352, 480) (|g_j+1|, h_j+1,j) per step
 constexpr int HDEV_LEN = 480;
-int launch_givens(ilh_ctx* c, double* h, double* G, int j, int m);
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
 int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
 // fused versions: w read once per 8 basis vectors; the axpy also returns |w|^2
 int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);
-int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign,
-                  int64_t n, double* d_nrm2);
 int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n);
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
                    double* zero_v = nullptr, const double* tau_dev = nullptr);

@@ -182,31 +182,12 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
   return ILH_OK;
 }
 
-// multi-dot: out[j] = sum_i V[j*ldv + i] w[i], j < m (m <= 64)
-__global__ void __launch_bounds__(TPB) k_mdot_part(const double* V, int64_t ldv, int m, const double* w, int64_t n,
-                                                   double* part, int nb) {
-  for (int j = 0; j < m; ++j) {
-    double acc = 0;
-    const double* vj = V + (int64_t)j * ldv;
-    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) acc += vj[i] * w[i];
-    acc = block_sum<TPB>(acc);
-    if (threadIdx.x == 0) part[(int64_t)j * nb + blockIdx.x] = acc;
-  }
-}
 __global__ void __launch_bounds__(TPB) k_mdot_final(const double* part, int nb, int m, double* out) {
   const int j = blockIdx.x;
   double acc = 0;
   for (int i = threadIdx.x; i < nb; i += TPB) acc += part[(int64_t)j * nb + i];
   acc = block_sum<TPB>(acc);
   if (threadIdx.x == 0) out[j] = acc;
-}
-int multidot_dev(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out) {
-  if (m <= 0) return ILH_OK;
-  const int nb = std::min(red_blocks(c, n), 256);
-  hipLaunchKernelGGL(k_mdot_part, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red, nb);
-  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out);
-  ILH_HIP(c, hipGetLastError());
-  return ILH_OK;
 }
 // w[i] += sign * sum_j h[j] V[j][i]
 __global__ void k_maxpy(double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
@@ -306,14 +287,6 @@ int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, in
   return ILH_OK;
 }
 
-int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign,
-                  int64_t n, double* d_nrm2) {
-  const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, h, sign, n, c->red);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, d_nrm2, 0);
-  ILH_HIP(c, hipGetLastError());
-  return ILH_OK;
-}
 
 // y = x / sqrt(*nrm2) when the norm is positive (the next Arnoldi vector)
 // Givens update of Arnoldi step j on the device (one thread; j < m <= 64).  Column j of the
@@ -349,9 +322,6 @@ __device__ void givens_update(double* h, double* G, int j, int m) {
   h[353 + 2 * j] = hn;
 }
 
-__global__ void k_givens(double* h, double* G, int j, int m) {
-  if (threadIdx.x == 0) givens_update(h, G, j, m);
-}
 
 // y = H(0:n, 0:n)^-1 g(0:n) by back substitution (one thread)
 __global__ void k_trisolve(const double* G, int n, double* y) {
@@ -365,11 +335,6 @@ __global__ void k_trisolve(const double* G, int n, double* y) {
   }
 }
 
-int launch_givens(ilh_ctx* c, double* h, double* G, int j, int m) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, c->stream, h, G, j, m);
-  ILH_HIP(c, hipGetLastError());
-  return ILH_OK;
-}
 
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
   (void)m;
