@@ -195,15 +195,23 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
 // device-side dot into d_out (no sync)
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
 // Arnoldi scalars: [0, 72) and [72, 144) the two Gram-Schmidt passes, 144 the norm, [160, 224)
-// the update coefficients, 240 beta, [352, 480) (|g_j+1|, h_j+1,j) per step
-constexpr int HDEV_LEN = 480;
+// the update coefficients, 240 beta, 250 tau, [256, 321) the basis scales s_j (basis vector j =
+// s_j x the stored vector), [352, 480) (|g_j+1|, h_j+1,j) per step, [480, 545) and [560, 625)
+// the two passes' coefficients times s_j (the coefficients of the stored vectors)
+constexpr int HDEV_LEN = 640;
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
 int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
-// fused versions: w read once per 8 basis vectors; the axpy also returns |w|^2
-int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out);
-int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n);
+// fused versions: w read once per 8 basis vectors.  d_out[j] = s_j V_j . w (s nullable: 1),
+// d_outs (nullable) [j] = s_j d_out[j]
+int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out,
+                   const double* s = nullptr, double* d_outs = nullptr);
+// w -= sum_j cf[j] V_j, then the products of the updated w as in multidot_fused
+int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, int64_t n,
+                   const double* s, double* d_out, double* d_outs);
+int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n);  // y *= *s
+// rs (nullable): the input vector is *rs times r
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                   double* zero_v = nullptr, const double* tau_dev = nullptr);
+                   double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr);
 // probed diagonal blocks of the Jacobian (preconditioner option prec_probe)
 int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau);
 int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D);
@@ -211,9 +219,11 @@ int launch_probe_e_dir(ilh_ctx* c, float* d, int j);
 int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
 int launch_invert_blocks(ilh_ctx* c, double* B);
 int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v = nullptr, const double* tau_dev = nullptr);
-int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, double* h, double sign,
-                         int64_t n, double* G, int j, int mm);
+                         double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr);
+// w += sign sum_j cf[j] V_j and |w|^2 into h[144], then the Givens update of step j (from the
+// pass coefficients h[0..j], h[72..72+j]) and the next basis scale h[256 + j + 1] = 1 / |w|
+int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double* h,
+                         double sign, int64_t n, double* G, int j, int mm);
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);

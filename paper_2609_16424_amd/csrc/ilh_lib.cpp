@@ -830,8 +830,10 @@ static double nrm2(ilh_ctx* c, const double* x, int64_t n, int* st) {
   return std::sqrt(v);
 }
 
-__global__ void k_scale_copy(double* y, const double* x, const double* s, int idx, int64_t n) {
+// y = x / s[idx]; s0 (nullable) is set to 1 (the scale of the stored vector y)
+__global__ void k_scale_copy(double* y, const double* x, const double* s, int idx, int64_t n, double* s0) {
   const double f = 1.0 / s[idx];
+  if (s0 && blockIdx.x == 0 && threadIdx.x == 0) *s0 = 1.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = x[i] * f;
 }
@@ -870,10 +872,11 @@ struct Solver {
 
   // next_out (nullable): the FP64 output of the Jacobian action that will read z; when the
   // FP32 action can write it directly, the preconditioner kernel also zeroes its velocity rows
-  int precond(const double* r, double* z, double* next_out = nullptr) {
+  // rs (nullable, device): the input vector is *rs times r
+  int precond(const double* r, double* z, double* next_out = nullptr, const double* rs = nullptr) {
     int st;
     const int slot = tstart(c, 4);
-    st = precond_body(r, z, next_out);
+    st = precond_body(r, z, next_out, rs);
     tstop(c, slot);
     return st;
   }
@@ -884,7 +887,7 @@ struct Solver {
   // FP32 linearised 2D actions write the FP64 Krylov vector directly
   bool direct64() const { return o->jvp_prec == 32 && c->jvp_variant == 0 && lin2d_available(c); }
 
-  int precond_body(const double* r, double* z, double* next_out) {
+  int precond_body(const double* r, double* z, double* next_out, const double* rs) {
     const int64_t nh1 = c->nh1;
     int st;
     z32_of = nullptr;
@@ -893,14 +896,14 @@ struct Solver {
     const double* tdev = c->hdev + 250;  // tau on the device (set at the start of each solve)
     if (o->prec_probe) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv, tdev))) return st;
+      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
     if (o->pcg_iters <= 0) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv, tdev))) return st;
+      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
@@ -914,6 +917,7 @@ struct Solver {
     if ((st = launch_mass_e_inv(c, r + 2 * nh1, z + 2 * nh1))) return st;
     if (o->prec_coupled)
       if ((st = launch_axpby(c, z, tau, z + nh1, 1.0, nh1))) return st;
+    if (rs && (st = launch_scale_dev(c, z, rs, c->nblock))) return st;  // the operator is linear
     return ILH_OK;
   }
 
@@ -949,28 +953,28 @@ struct Solver {
   }
 
   // One Arnoldi step j: z_j = P v_j, w = J z_j, two Gram-Schmidt passes with the Givens
-  // update, normalisation, and the pinned copy of the residual estimate.
+  // update, and the pinned copy of the residual estimate.  The basis vectors are stored
+  // unnormalised: v_j = s_j x (stored V_j), s_j = 1 / |w| set by step j-1's norm reduction; the
+  // preconditioner and the pass coefficients take the scale, so no pass rescales the vector.
   int arnoldi_step(int j, int m) {
     const int64_t n = c->nblock;
     double* V = c->kry;
     double* Z = c->kry + (int64_t)(m + 1) * n;
     double* hd = c->hdev;
+    double* s = hd + 256;
     double* Vj = V + (int64_t)j * n;
     double* Zj = Z + (int64_t)j * n;
     double* w = V + (int64_t)(j + 1) * n;
     int st;
-    if ((st = precond(Vj, Zj, w))) return st;
+    if ((st = precond(Vj, Zj, w, s + j))) return st;
     if ((st = apply(Zj, w))) return st;
-    // classical Gram-Schmidt, twice
+    // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1 fused with h2 = V^T w; w -= V h2
     const int slot = tstart(c, 3);
-    if ((st = multidot_fused(c, V, n, j + 1, w, n, hd))) return st;
-    if ((st = multiaxpy_dev(c, w, V, n, j + 1, hd, -1.0, n))) return st;
-    if ((st = multidot_fused(c, V, n, j + 1, w, n, hd + 72))) return st;
-    // second pass with the norm of w and the Givens update of step j in its final reduction
-    if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd, -1.0, n, c->gmd, j, m))) return st;
+    if ((st = multidot_fused(c, V, n, j + 1, w, n, hd, s, hd + 480))) return st;
+    if ((st = maxpy_multidot(c, w, V, n, j + 1, hd + 480, n, s, hd + 72, hd + 560))) return st;
+    // second update with the norm of w, the Givens update of step j and s_{j+1} in its final reduction
+    if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd + 560, hd, -1.0, n, c->gmd, j, m))) return st;
     tstop(c, slot);
-    // normalise on the device (no-op for a zero or non-finite norm), publish the estimate
-    if ((st = launch_scale_by_norm(c, w, w, hd + 144, n))) return st;
     ILH_HIP(c, hipMemcpyAsync(c->hhost + 352 + 2 * j, hd + 352 + 2 * j, 2 * sizeof(double), hipMemcpyDeviceToHost,
                               c->stream));
     return ILH_OK;
@@ -1064,7 +1068,7 @@ struct Solver {
       // V0 = r / beta
       c->hhost[240] = beta;
       ILH_HIP(c, hipMemcpyAsync(hd + 240, &c->hhost[240], sizeof(double), hipMemcpyHostToDevice, c->stream));
-      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, hd, 240, n);
+      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, hd, 240, n, hd + 256);
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
       // read step jj's estimate; true when the cycle ends after it

@@ -182,12 +182,19 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
   return ILH_OK;
 }
 
-__global__ void __launch_bounds__(TPB) k_mdot_final(const double* part, int nb, int m, double* out) {
+// out[j] = s_j sum_b part[j][b] (s = null: s_j = 1); outs (nullable) receives s_j out[j], the
+// coefficient of the stored vector when V_j = s_j x (stored vector)
+__global__ void __launch_bounds__(TPB) k_mdot_final(const double* part, int nb, int m, double* out,
+                                                    const double* s, double* outs) {
   const int j = blockIdx.x;
   double acc = 0;
   for (int i = threadIdx.x; i < nb; i += TPB) acc += part[(int64_t)j * nb + i];
   acc = block_sum<TPB>(acc);
-  if (threadIdx.x == 0) out[j] = acc;
+  if (threadIdx.x == 0) {
+    const double sj = s ? s[j] : 1.0;
+    out[j] = sj * acc;
+    if (outs) outs[j] = sj * sj * acc;
+  }
 }
 // w[i] += sign * sum_j h[j] V[j][i]
 __global__ void k_maxpy(double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
@@ -235,6 +242,42 @@ __global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V
   }
 }
 
+// w -= sum_j c[j] V_j, then part[j][b] = block b's share of V_j . w (the updated w), j < m:
+// the first Gram-Schmidt pass's update and the second pass's products in one sweep.  Every
+// thread revisits only its own indices, so the later chunks read back its own updates.
+__global__ void __launch_bounds__(TPB) k_maxpy_mdot_part(double* __restrict__ w, const double* __restrict__ V,
+                                                         int64_t ldv, int m, const double* __restrict__ cf,
+                                                         int64_t n, double* part) {
+  const int nb = gridDim.x;
+  for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
+    const int jn = min(MDOT_JC, m - j0);
+    double acc[MDOT_JC];
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj) acc[jj] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)nb * TPB) {
+      double wi;
+      if (j0 == 0) {
+        double a = 0.0;
+        for (int j = 0; j < m; ++j) a += cf[j] * V[(int64_t)j * ldv + i];
+        wi = w[i] - a;
+        w[i] = wi;
+      } else {
+        wi = w[i];
+      }
+#pragma unroll
+      for (int jj = 0; jj < MDOT_JC; ++jj)
+        if (jj < jn) acc[jj] += V[(int64_t)(j0 + jj) * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj) {
+      if (jj < jn) {
+        const double t = block_sum<TPB>(acc[jj]);
+        if (threadIdx.x == 0) part[(int64_t)(j0 + jj) * nb + blockIdx.x] = t;
+      }
+    }
+  }
+}
+
 // w += sign sum_j h[j] V_j; part[b] = block b's share of |w|^2 of the result
 __global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(double* __restrict__ w, const double* __restrict__ V,
                                                         int64_t ldv, int m, const double* __restrict__ h,
@@ -255,19 +298,33 @@ static int fused_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4 * TPB - 1) / (4 * TPB)));
 }
 
-int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out) {
+int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out,
+                   const double* s, double* d_outs) {
   if (m <= 0) return ILH_OK;
   if (m > 64) return fail(c, ILH_EINVAL, "multidot: at most 64 vectors");
   const int nb = fused_blocks(n);
   hipLaunchKernelGGL(k_mdot_part8, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red);
-  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out);
+  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, int64_t n,
+                   const double* s, double* d_out, double* d_outs) {
+  if (m <= 0) return ILH_OK;
+  if (m > 64) return fail(c, ILH_EINVAL, "multidot: at most 64 vectors");
+  const int nb = fused_blocks(n);
+  hipLaunchKernelGGL(k_maxpy_mdot_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, n, c->red);
+  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
 
 __device__ void givens_update(double* h, double* G, int j, int m);
 
-// final sum of the norm partials into h[144], then the Givens update of Arnoldi step j
+// final sum of the norm partials into h[144], the Givens update of Arnoldi step j, and the
+// scale of the next basis vector, h[256 + j + 1] = 1 / |w| (1 for a zero or non-finite norm:
+// the cycle ends at that step)
 __global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, double* h, double* G, int j, int m) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += TPB) acc += part[i];
@@ -275,20 +332,21 @@ __global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, 
   if (threadIdx.x == 0) {
     h[144] = acc;
     givens_update(h, G, j, m);
+    const double hn = sqrt(fmax(acc, 0.0));
+    h[256 + j + 1] = (hn > 0.0 && hn <= 1.7e308) ? 1.0 / hn : 1.0;
   }
 }
 
-int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, double* h, double sign,
-                         int64_t n, double* G, int j, int mm) {
+int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double* h,
+                         double sign, int64_t n, double* G, int j, int mm) {
   const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, h + 72, sign, n, c->red);
+  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, sign, n, c->red);
   hipLaunchKernelGGL(k_sum_givens, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, h, G, j, mm);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
 
 
-// y = x / sqrt(*nrm2) when the norm is positive (the next Arnoldi vector)
 // Givens update of Arnoldi step j on the device (one thread; j < m <= 64).  Column j of the
 // Hessenberg matrix is the sum of the two Gram-Schmidt passes (h[0..j], h[72..72+j]) with
 // h_{j+1,j} = sqrt(h[144]); the earlier rotations are applied to it, the new one is formed and
@@ -343,16 +401,15 @@ int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
   return ILH_OK;
 }
 
-__global__ void k_scale_by_norm(double* y, const double* x, const double* nrm2, int64_t n) {
-  const double s = sqrt(fmax(*nrm2, 0.0));
-  if (!(s > 0.0)) return;
-  const double f = 1.0 / s;
+// y *= *s
+__global__ void k_scale_dev(double* y, const double* s, int64_t n) {
+  const double f = *s;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = x[i] * f;
+    y[i] *= f;
 }
 
-int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d_nrm2, int64_t n) {
-  hipLaunchKernelGGL(k_scale_by_norm, dim3(nblk(n, 4096)), dim3(TPB), 0, c->stream, y, x, d_nrm2, n);
+int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n) {
+  hipLaunchKernelGGL(k_scale_dev, dim3(nblk(n, 4096)), dim3(TPB), 0, c->stream, y, s, n);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -363,13 +420,14 @@ int launch_scale_by_norm(ilh_ctx* c, double* y, const double* x, const double* d
 __global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
                           const double* __restrict__ Minv, const double* __restrict__ escale, double* z, float* z32,
                           double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v,
-                          const double* tau_dev) {
+                          const double* tau_dev, const double* rs) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
+  const double sc = rs ? *rs : 1.0;  // the input is sc * r
   if (i < nh1) {
-    const double zv = r[nh1 + i] / Mdiag[i];
-    const double zx = coupled ? tau * zv + r[i] : r[i];
+    const double zv = sc * r[nh1 + i] / Mdiag[i];
+    const double zx = coupled ? tau * zv + sc * r[i] : sc * r[i];
     z[i] = zx;
     z[nh1 + i] = zv;
     if (z32) {
@@ -381,17 +439,17 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
     const int rr = (int)(k % Nl);
     double acc = 0;
     for (int j = 0; j < Nl; ++j) acc += Minv[rr * Nl + j] * r[2 * nh1 + e * Nl + j];
-    const double x = escale[e] * acc;
+    const double x = sc * escale[e] * acc;
     z[2 * nh1 + k] = x;
     if (z32) z32[2 * nh1 + k] = (float)x;
   }
 }
 
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled, double* zero_v,
-                   const double* tau_dev) {
+                   const double* tau_dev, const double* rs) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   hipLaunchKernelGGL(k_precond, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv,
-                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev);
+                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -536,13 +594,15 @@ int launch_invert_blocks(ilh_ctx* c, double* B) {
 // z_v = r_v / D (probed diagonal), z_x = r_x + tau z_v (coupled) or r_x, z_e = Binv r_e per element
 __global__ void k_precond_probe(const double* __restrict__ r, const double* __restrict__ D,
                                 const double* __restrict__ Binv, double* z, float* z32, double tau, int coupled,
-                                int64_t nh1, int64_t Ne, int Nl, double* zero_v, const double* tau_dev) {
+                                int64_t nh1, int64_t Ne, int Nl, double* zero_v, const double* tau_dev,
+                                const double* rs) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
+  const double sc = rs ? *rs : 1.0;  // the input is sc * r
   if (i < nh1) {
-    const double zv = r[nh1 + i] / D[i];
-    const double zx = coupled ? tau * zv + r[i] : r[i];
+    const double zv = sc * r[nh1 + i] / D[i];
+    const double zx = coupled ? tau * zv + sc * r[i] : sc * r[i];
     z[i] = zx;
     z[nh1 + i] = zv;
     if (z32) {
@@ -555,16 +615,17 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
     const double* Bi = Binv + (e * Nl + rr) * Nl;
     double acc = 0;
     for (int j = 0; j < Nl; ++j) acc += Bi[j] * r[2 * nh1 + e * Nl + j];
+    acc *= sc;
     z[2 * nh1 + k] = acc;
     if (z32) z32[2 * nh1 + k] = (float)acc;
   }
 }
 
 int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v, const double* tau_dev) {
+                         double* zero_v, const double* tau_dev, const double* rs) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   hipLaunchKernelGGL(k_precond_probe, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->pdv,
-                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev);
+                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
