@@ -216,65 +216,131 @@ int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, co
 // A single-launch variant with a last-block arrival counter was measured slower: the
 // device-scope release fence it needs writes back each XCD's L2 once per block.
 static constexpr int MDOT_JC = 8;  // basis vectors per pass over w
+static constexpr int KU = 4;       // elements per thread and tile
+static constexpr int64_t KTILE = (int64_t)TPB * KU;
 
-// part[j][b] = block b's share of V_j . w, j < m (w read once per MDOT_JC vectors)
-__global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V, int64_t ldv, int m,
-                                                    const double* __restrict__ w, int64_t n, double* part) {
-  const int nb = gridDim.x;
+// The sweeps below take the basis in chunks of MDOT_JC vectors and the elements in tiles of
+// KU per thread; every load of a chunk and tile is issued before its first use (row and element
+// indices are clamped in range, out-of-range terms enter with weight zero), so a wave keeps
+// MDOT_JC x KU loads in flight instead of one row at a time.
+
+// a[u] += sum_{j < m} cf[j] V_j[i_u] over one tile (i_u clamped to n - 1)
+__device__ __forceinline__ void tile_combo(const double* __restrict__ V, int64_t ldv, int m,
+                                           const double* __restrict__ cf, const int64_t (&ic)[KU],
+                                           double (&a)[KU]) {
   for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
-    const int jn = min(MDOT_JC, m - j0);
-    double acc[MDOT_JC];
-#pragma unroll
-    for (int jj = 0; jj < MDOT_JC; ++jj) acc[jj] = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)nb * TPB) {
-      const double wi = w[i];
-#pragma unroll
-      for (int jj = 0; jj < MDOT_JC; ++jj)
-        if (jj < jn) acc[jj] += V[(int64_t)(j0 + jj) * ldv + i] * wi;
-    }
+    double v[MDOT_JC][KU];
+    double cj[MDOT_JC];
 #pragma unroll
     for (int jj = 0; jj < MDOT_JC; ++jj) {
-      if (jj < jn) {
-        const double t = block_sum<TPB>(acc[jj]);
-        if (threadIdx.x == 0) part[(int64_t)(j0 + jj) * nb + blockIdx.x] = t;
-      }
+      const int j = min(j0 + jj, m - 1);
+      cj[jj] = (j0 + jj < m) ? cf[j] : 0.0;
+#pragma unroll
+      for (int u = 0; u < KU; ++u) v[jj][u] = V[(int64_t)j * ldv + ic[u]];
+    }
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj)
+#pragma unroll
+      for (int u = 0; u < KU; ++u) a[u] += cj[jj] * v[jj][u];
+  }
+}
+
+// acc[jj] += sum_u V_{j0+jj}[i_u] wv[u] for jj < MDOT_JC (rows past m - 1 clamped; the caller
+// discards their sums)
+__device__ __forceinline__ void tile_dots(const double* __restrict__ V, int64_t ldv, int m, int j0,
+                                          const int64_t (&ic)[KU], const double (&wv)[KU],
+                                          double (&acc)[MDOT_JC]) {
+  double v[MDOT_JC][KU];
+#pragma unroll
+  for (int jj = 0; jj < MDOT_JC; ++jj) {
+    const int j = min(j0 + jj, m - 1);
+#pragma unroll
+    for (int u = 0; u < KU; ++u) v[jj][u] = V[(int64_t)j * ldv + ic[u]];
+  }
+#pragma unroll
+  for (int jj = 0; jj < MDOT_JC; ++jj)
+#pragma unroll
+    for (int u = 0; u < KU; ++u) acc[jj] += v[jj][u] * wv[u];
+}
+
+__device__ __forceinline__ void tile_index(int64_t t0, int64_t n, int64_t (&ic)[KU], bool (&in)[KU]) {
+#pragma unroll
+  for (int u = 0; u < KU; ++u) {
+    const int64_t i = t0 + (int64_t)u * TPB + threadIdx.x;
+    in[u] = i < n;
+    ic[u] = in[u] ? i : n - 1;
+  }
+}
+
+template <int JC>
+__device__ __forceinline__ void store_block_sums(const double (&acc)[JC], int j0, int jn, double* part) {
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    if (jj < jn) {
+      const double t = block_sum<TPB>(acc[jj]);
+      if (threadIdx.x == 0) part[(int64_t)(j0 + jj) * gridDim.x + blockIdx.x] = t;
     }
   }
 }
 
-// w -= sum_j c[j] V_j, then part[j][b] = block b's share of V_j . w (the updated w), j < m:
+// part[j][b] = block b's share of V_j . w, j < m (w read once per MDOT_JC vectors)
+__global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V, int64_t ldv, int m,
+                                                    const double* __restrict__ w, int64_t n, double* part) {
+  const int64_t stride = (int64_t)gridDim.x * KTILE;
+  for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
+    double acc[MDOT_JC];
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj) acc[jj] = 0.0;
+    for (int64_t t0 = (int64_t)blockIdx.x * KTILE; t0 < n; t0 += stride) {
+      int64_t ic[KU];
+      bool in[KU];
+      tile_index(t0, n, ic, in);
+      double wv[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) wv[u] = in[u] ? w[ic[u]] : 0.0;
+      tile_dots(V, ldv, m, j0, ic, wv, acc);
+    }
+    store_block_sums(acc, j0, min(MDOT_JC, m - j0), part);
+  }
+}
+
+// w -= sum_j cf[j] V_j, then part[j][b] = block b's share of V_j . w (the updated w), j < m:
 // the first Gram-Schmidt pass's update and the second pass's products in one sweep.  Every
 // thread revisits only its own indices, so the later chunks read back its own updates.
 __global__ void __launch_bounds__(TPB) k_maxpy_mdot_part(double* __restrict__ w, const double* __restrict__ V,
                                                          int64_t ldv, int m, const double* __restrict__ cf,
                                                          int64_t n, double* part) {
-  const int nb = gridDim.x;
+  const int64_t stride = (int64_t)gridDim.x * KTILE;
   for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
-    const int jn = min(MDOT_JC, m - j0);
     double acc[MDOT_JC];
 #pragma unroll
     for (int jj = 0; jj < MDOT_JC; ++jj) acc[jj] = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)nb * TPB) {
-      double wi;
+    for (int64_t t0 = (int64_t)blockIdx.x * KTILE; t0 < n; t0 += stride) {
+      int64_t ic[KU];
+      bool in[KU];
+      tile_index(t0, n, ic, in);
+      double wv[KU];
       if (j0 == 0) {
-        double a = 0.0;
-        for (int j = 0; j < m; ++j) a += cf[j] * V[(int64_t)j * ldv + i];
-        wi = w[i] - a;
-        w[i] = wi;
+        double a[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) a[u] = 0.0;
+        tile_combo(V, ldv, m, cf, ic, a);
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+          if (in[u]) {
+            wv[u] = w[ic[u]] - a[u];
+            w[ic[u]] = wv[u];
+          } else {
+            wv[u] = 0.0;
+          }
+        }
       } else {
-        wi = w[i];
-      }
 #pragma unroll
-      for (int jj = 0; jj < MDOT_JC; ++jj)
-        if (jj < jn) acc[jj] += V[(int64_t)(j0 + jj) * ldv + i] * wi;
-    }
-#pragma unroll
-    for (int jj = 0; jj < MDOT_JC; ++jj) {
-      if (jj < jn) {
-        const double t = block_sum<TPB>(acc[jj]);
-        if (threadIdx.x == 0) part[(int64_t)(j0 + jj) * nb + blockIdx.x] = t;
+        for (int u = 0; u < KU; ++u) wv[u] = in[u] ? w[ic[u]] : 0.0;
       }
+      tile_dots(V, ldv, m, j0, ic, wv, acc);
     }
+    store_block_sums(acc, j0, min(MDOT_JC, m - j0), part);
   }
 }
 
@@ -283,19 +349,30 @@ __global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(double* __restrict__ w, 
                                                         int64_t ldv, int m, const double* __restrict__ h,
                                                         double sign, int64_t n, double* part) {
   double ss = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
-    double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += h[j] * V[(int64_t)j * ldv + i];
-    const double wn = w[i] + sign * acc;
-    w[i] = wn;
-    ss += wn * wn;
+  const int64_t stride = (int64_t)gridDim.x * KTILE;
+  for (int64_t t0 = (int64_t)blockIdx.x * KTILE; t0 < n; t0 += stride) {
+    int64_t ic[KU];
+    bool in[KU];
+    tile_index(t0, n, ic, in);
+    double a[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) a[u] = 0.0;
+    tile_combo(V, ldv, m, h, ic, a);
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (in[u]) {
+        const double wn = w[ic[u]] + sign * a[u];
+        w[ic[u]] = wn;
+        ss += wn * wn;
+      }
+    }
   }
   ss = block_sum<TPB>(ss);
   if (threadIdx.x == 0) part[blockIdx.x] = ss;
 }
 
 static int fused_blocks(int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4 * TPB - 1) / (4 * TPB)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + KTILE - 1) / KTILE));
 }
 
 int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out,
