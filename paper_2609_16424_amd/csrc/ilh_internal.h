@@ -226,6 +226,7 @@ int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, in
                          double sign, int64_t n, double* G, int j, int mm);
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
+int min_detj_dev(ilh_ctx* c, const double* x, double* d_out);  // result stays on the device (no sync)
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);
 int l1_error_host(ilh_ctx* c, const double* u, double* out);
 int energy_host(ilh_ctx* c, const double* u, double* ke, double* ie);

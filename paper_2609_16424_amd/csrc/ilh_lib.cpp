@@ -830,6 +830,17 @@ static double nrm2(ilh_ctx* c, const double* x, int64_t n, int* st) {
   return std::sqrt(v);
 }
 
+// two adjacent device scalars (in the reduction buffer's scalar area) and their host copies:
+// results enqueued one after the other are read with a single synchronisation
+static double* dev_pair(ilh_ctx* c) { return c->red + (int64_t)c->red_blocks * 65 + 8; }
+static int read_pair(ilh_ctx* c, double* a, double* b) {
+  ILH_HIP(c, hipMemcpyAsync(c->red_host + 4, dev_pair(c), 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  ILH_HIP(c, hipStreamSynchronize(c->stream));
+  *a = c->red_host[4];
+  *b = c->red_host[5];
+  return ILH_OK;
+}
+
 // y = x / s[idx]; s0 (nullable) is set to 1 (the scale of the stored vector y)
 __global__ void k_scale_copy(double* y, const double* x, const double* s, int idx, int64_t n, double* s0) {
   const double f = 1.0 / s[idx];
@@ -1034,13 +1045,14 @@ struct Solver {
     return ILH_OK;
   }
 
-  // FGMRES: solve J x = b, x starts at 0.  Returns total iterations in *its.
+  // FGMRES: solve J x = b, x starts at 0.  Returns total iterations in *its.  beta_b >= 0 is
+  // |b| when the caller already has it (no reduction and synchronisation for it).
   // The Givens rotations, the residual estimate and the triangular solve run on the device;
   // the host enqueues Arnoldi step j before it reads step j-1's residual estimate (pinned copy
   // behind an event), so the stream never drains between steps.  A step enqueued after the
   // one that converged is discarded: it only touches V_{j+1}, Z_j, column j and g_j, g_{j+1},
   // none of which the solution over the first j columns reads.
-  int fgmres(const double* b, double* x, int* its) {
+  int fgmres(const double* b, double* x, int* its, double beta_b = -1.0) {
     const int64_t n = c->nblock;
     const int m = std::max(1, std::min(o->restart, 64));
     double* V = c->kry;
@@ -1049,8 +1061,11 @@ struct Solver {
     double* G = c->gmd;
     int st;
     if ((st = launch_fill(c, x, 0.0, n))) return st;
-    double beta = nrm2(c, b, n, &st);
-    if (st) return st;
+    double beta = beta_b;
+    if (!(beta >= 0.0)) {
+      beta = nrm2(c, b, n, &st);
+      if (st) return st;
+    }
     *its = 0;
     if (beta == 0.0) return ILH_OK;
     const double target = o->gmres_rtol * beta;
@@ -1141,17 +1156,20 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   double* kt = c->nwt + 6 * n;
   double* rt = c->nwt + 7 * n;
   Solver S{c, o, tau};
+  double* dsc = dev_pair(c);
   if ((st = launch_fill(c, zero, 0.0, n))) return st;
   if ((st = ilh_residual(c, zero, u, tau, r))) return st;
-  const double r0 = nrm2(c, r, n, &st);
-  if (st) return st;
-  stats.res0 = r0;
-  double nr = r0;
+  if ((st = dot_dev(c, r, r, n, dsc))) return st;
+  double r0 = 0.0, nr = 0.0;
   if (k_guess) {
+    // |R(0)| and |R(k_guess)| read together
     ILH_HIP(c, hipMemcpyAsync(k, k_guess, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if ((st = ilh_residual(c, k, u, tau, r))) return st;
-    nr = nrm2(c, r, n, &st);
-    if (st) return st;
+    if ((st = dot_dev(c, r, r, n, dsc + 1))) return st;
+    if ((st = read_pair(c, &r0, &nr))) return st;
+    r0 = std::sqrt(r0);
+    nr = std::sqrt(nr);
+    stats.res0 = r0;
     stats.res_init = nr;
     if (o->guess_fallback && !(nr <= r0)) {
       // the initial iterate is worse than k = 0: start from zero instead
@@ -1161,6 +1179,11 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
       nr = r0;
     }
   } else {
+    double unused;
+    if ((st = read_pair(c, &r0, &unused))) return st;
+    r0 = std::sqrt(r0);
+    nr = r0;
+    stats.res0 = r0;
     if ((st = launch_fill(c, k, 0.0, n))) return st;
     stats.res_init = r0;
   }
@@ -1184,7 +1207,7 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
     if (o->prec_probe && (it == 0 || !o->prec_lag) && (st = build_probe_prec(c, o->prec_probe))) return st;
     if ((st = launch_axpby(c, r, 0.0, r, -1.0, n))) return st;  // r <- -r (right-hand side)
     int gits = 0;
-    if ((st = S.fgmres(r, dk, &gits))) return st;
+    if ((st = S.fgmres(r, dk, &gits, nr))) return st;  // |-r| = nr
     stats.gmres_iters += gits;
     // backtracking: det J > 0 at every quadrature point of the stage positions, and (when
     // enabled) sufficient decrease ||R(k + a dk)|| <= (1 - 1e-4 a) ||R(k)||
@@ -1193,13 +1216,16 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
     for (int h = 0; h <= o->max_halvings; ++h) {
       if ((st = launch_waxpy(c, kt, k, alpha, dk, n))) return st;
       if ((st = launch_waxpy(c, trial, u, tau, kt, c->nh1))) return st;
-      double md;
-      if ((st = min_detj_host(c, trial, &md))) return st;
+      // the trial residual is formed before det J > 0 is known (it is discarded otherwise), so
+      // that one synchronisation reads both
+      if ((st = min_detj_dev(c, trial, dsc))) return st;
+      if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
+      if ((st = dot_dev(c, rt, rt, n, dsc + 1))) return st;
+      double md, nrt2;
+      if ((st = read_pair(c, &md, &nrt2))) return st;
       if (md > 0.0) {
         any_valid = true;
-        if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
-        const double nrt = nrm2(c, rt, n, &st);
-        if (st) return st;
+        const double nrt = std::sqrt(nrt2);
         if (!o->ls_residual || nrt <= (1.0 - 1e-4 * alpha) * nr) {
           ok = true;
           nr = nrt;

@@ -1122,7 +1122,7 @@ __global__ void __launch_bounds__(256) k_diag(const KParams P, int mode, int pro
   if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
-static int diag_host(ilh_ctx* c, int mode, const double* u, double cfl, double* out) {
+static int diag_dev(ilh_ctx* c, int mode, const double* u, double cfl, double* d_out) {
   const int NQ = c->Q;
   const int64_t total = c->Ne * (int64_t)NQ;
   const int nb = (int)((total + 255) / 256);
@@ -1133,9 +1133,15 @@ static int diag_host(ilh_ctx* c, int mode, const double* u, double cfl, double* 
   else
     hipLaunchKernelGGL(k_diag<3>, dim3(nb), dim3(256), 0, c->stream, c->kp, mode, c->s.problem, u, cfl, part);
   const bool is_min = (mode == D_MINDET || mode == D_DT);
-  double* d_out = c->red + c->red_blocks * 65 + 1;
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, part, nb, d_out, is_min ? 1 : 0);
   ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+static int diag_host(ilh_ctx* c, int mode, const double* u, double cfl, double* out) {
+  double* d_out = c->red + c->red_blocks * 65 + 1;
+  int st = diag_dev(c, mode, u, cfl, d_out);
+  if (st) return st;
   ILH_HIP(c, hipMemcpyAsync(c->red_host, d_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   *out = c->red_host[0];
@@ -1143,6 +1149,7 @@ static int diag_host(ilh_ctx* c, int mode, const double* u, double cfl, double* 
 }
 
 int min_detj_host(ilh_ctx* c, const double* x, double* out) { return diag_host(c, D_MINDET, x, 0.0, out); }
+int min_detj_dev(ilh_ctx* c, const double* x, double* d_out) { return diag_dev(c, D_MINDET, x, 0.0, d_out); }
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out) { return diag_host(c, D_DT, u, cfl, out); }
 int l1_error_host(ilh_ctx* c, const double* u, double* out) { return diag_host(c, D_L1, u, 0.0, out); }
 int energy_host(ilh_ctx* c, const double* u, double* ke, double* ie) {
