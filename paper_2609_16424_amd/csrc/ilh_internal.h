@@ -113,7 +113,8 @@ struct ilh_ctx {
   double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   double* hdev = nullptr;       // [HDEV_LEN] device scalars of the Arnoldi step
-  double* hhost = nullptr;      // pinned mirror of hdev
+  double* hest = nullptr;       // pinned, coherent: (|g_j+1|, h_j+1,j) of each Arnoldi step, stored by
+  double* hest_dev = nullptr;   // the device through its mapped address hest_dev
   double* gmd = nullptr;        // device Givens state of FGMRES: H [64][64], cs, sn [64], g [65]
   hipEvent_t gev[2] = {nullptr, nullptr};  // FGMRES: residual estimates of alternate steps ready
   hipStream_t capstream = nullptr;         // stream the Arnoldi-step graphs are captured on
@@ -221,9 +222,10 @@ int launch_invert_blocks(ilh_ctx* c, double* B);
 int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
                          double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr);
 // w += sign sum_j cf[j] V_j and |w|^2 into h[144], then the Givens update of step j (from the
-// pass coefficients h[0..j], h[72..72+j]) and the next basis scale h[256 + j + 1] = 1 / |w|
+// pass coefficients h[0..j], h[72..72+j]) and the next basis scale h[256 + j + 1] = 1 / |w|;
+// hest (nullable, host-mapped) receives the step's (|g_j+1|, h_j+1,j) at [2j, 2j + 1]
 int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double* h,
-                         double sign, int64_t n, double* G, int j, int mm);
+                         double sign, int64_t n, double* G, int j, int mm, double* hest);
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int min_detj_dev(ilh_ctx* c, const double* x, double* d_out);  // result stays on the device (no sync)

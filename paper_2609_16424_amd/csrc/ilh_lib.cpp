@@ -278,7 +278,7 @@ void ilh_destroy(ilh_ctx* c) {
     if (e) (void)hipGraphExecDestroy(e);
   if (c->capstream) (void)hipStreamDestroy(c->capstream);
   if (c->red_host) (void)hipHostFree(c->red_host);
-  if (c->hhost) (void)hipHostFree(c->hhost);
+  if (c->hest) (void)hipHostFree(c->hest);
   delete c;
 }
 
@@ -841,10 +841,13 @@ static int read_pair(ilh_ctx* c, double* a, double* b) {
   return ILH_OK;
 }
 
-// y = x / s[idx]; s0 (nullable) is set to 1 (the scale of the stored vector y)
-__global__ void k_scale_copy(double* y, const double* x, const double* s, int idx, int64_t n, double* s0) {
-  const double f = 1.0 / s[idx];
-  if (s0 && blockIdx.x == 0 && threadIdx.x == 0) *s0 = 1.0;
+// y = x / beta; beta is also stored to *beta_out and the scale of the stored vector y, 1, to *s0
+__global__ void k_scale_copy(double* y, const double* x, double beta, int64_t n, double* beta_out, double* s0) {
+  const double f = 1.0 / beta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *beta_out = beta;
+    *s0 = 1.0;
+  }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = x[i] * f;
 }
@@ -984,10 +987,9 @@ struct Solver {
     if ((st = multidot_fused(c, V, n, j + 1, w, n, hd, s, hd + 480))) return st;
     if ((st = maxpy_multidot(c, w, V, n, j + 1, hd + 480, n, s, hd + 72, hd + 560))) return st;
     // second update with the norm of w, the Givens update of step j and s_{j+1} in its final reduction
-    if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd + 560, hd, -1.0, n, c->gmd, j, m))) return st;
+    // (the residual estimate goes to the mapped host buffer hest from that reduction)
+    if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd + 560, hd, -1.0, n, c->gmd, j, m, c->hest_dev))) return st;
     tstop(c, slot);
-    ILH_HIP(c, hipMemcpyAsync(c->hhost + 352 + 2 * j, hd + 352 + 2 * j, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                              c->stream));
     return ILH_OK;
   }
 
@@ -999,7 +1001,7 @@ struct Solver {
   uint64_t graph_key(int m) const {
     uint64_t k = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
-    const void* ptrs[] = {c->kry, c->kry32, c->hdev, c->hhost, c->gmd, c->red, c->qd[0], c->Mdiag, c->MEinv,
+    const void* ptrs[] = {c->kry, c->kry32, c->hdev, c->hest_dev, c->gmd, c->red, c->qd[0], c->Mdiag, c->MEinv,
                           c->pdv, c->peinv, c->rj0};
     for (const void* q : ptrs) mix((uint64_t)(uintptr_t)q);
     mix((uint64_t)m);
@@ -1072,24 +1074,22 @@ struct Solver {
     const double* rhs = b;
     double* rbuf = c->nwt + 3 * n;  // tmp vector
     int total = 0;
-    c->hhost[250] = tau;
-    ILH_HIP(c, hipMemcpyAsync(hd + 250, &c->hhost[250], sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if ((st = launch_fill(c, hd + 250, tau, 1))) return st;  // tau on the device for the step kernels
     const bool use_graph = graphable();
     if (use_graph && !c->qd_ok[0]) {  // the linearisation stays outside the captured steps
       if ((st = launch_lin2d(c, 32))) return st;
       c->qd_ok[0] = true;
     }
     while (true) {
-      // V0 = r / beta
-      c->hhost[240] = beta;
-      ILH_HIP(c, hipMemcpyAsync(hd + 240, &c->hhost[240], sizeof(double), hipMemcpyHostToDevice, c->stream));
-      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, hd, 240, n, hd + 256);
+      // V0 = r / beta (beta to hd[240] for the Givens update, s_0 = 1)
+      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd + 240, hd + 256);
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
       // read step jj's estimate; true when the cycle ends after it
       auto check = [&](int jj, bool& end) -> int {
         ILH_HIP(c, hipEventSynchronize(c->gev[jj & 1]));
-        const double res = c->hhost[352 + 2 * jj], hn = c->hhost[353 + 2 * jj];
+        const volatile double* est = c->hest;
+        const double res = est[2 * jj], hn = est[2 * jj + 1];
         if (!std::isfinite(hn) || !std::isfinite(res)) return fail(c, ILH_ENONFINITE, "non-finite Krylov vector");
         ++total;
         stop = res <= target || total >= o->gmres_maxit;
@@ -1143,8 +1143,12 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   if ((st = ensure_solver_ws(c, m))) return st;
   if (!c->nwt && (st = dalloc(c, &c->nwt, 8 * (size_t)n))) return st;
   if (!c->hdev && (st = dalloc(c, &c->hdev, HDEV_LEN))) return st;
-  if (!c->hhost && hipHostMalloc((void**)&c->hhost, HDEV_LEN * sizeof(double)) != hipSuccess)
-    return fail(c, ILH_ENOMEM, "pinned host buffer");
+  if (!c->hest) {
+    if (hipHostMalloc((void**)&c->hest, 128 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+      return fail(c, ILH_ENOMEM, "pinned host buffer");
+    ILH_HIP(c, hipHostGetDevicePointer((void**)&c->hest_dev, c->hest, 0));
+  }
   if (!c->gmd && (st = dalloc(c, &c->gmd, 64 * 64 + 3 * 65))) return st;
   for (hipEvent_t& e : c->gev)
     if (!e) ILH_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));

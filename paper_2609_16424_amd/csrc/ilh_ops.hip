@@ -401,8 +401,10 @@ __device__ void givens_update(double* h, double* G, int j, int m);
 
 // final sum of the norm partials into h[144], the Givens update of Arnoldi step j, and the
 // scale of the next basis vector, h[256 + j + 1] = 1 / |w| (1 for a zero or non-finite norm:
-// the cycle ends at that step)
-__global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, double* h, double* G, int j, int m) {
+// the cycle ends at that step).  The residual estimate also goes straight to host memory
+// (hest, mapped and coherent), so no copy is enqueued behind the step.
+__global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, double* h, double* G, int j, int m,
+                                                    double* hest) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += TPB) acc += part[i];
   acc = block_sum<TPB>(acc);
@@ -411,14 +413,19 @@ __global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, 
     givens_update(h, G, j, m);
     const double hn = sqrt(fmax(acc, 0.0));
     h[256 + j + 1] = (hn > 0.0 && hn <= 1.7e308) ? 1.0 / hn : 1.0;
+    if (hest) {
+      hest[2 * j] = h[352 + 2 * j];
+      hest[2 * j + 1] = h[353 + 2 * j];
+      __threadfence_system();  // visible to the host once the step's event has completed
+    }
   }
 }
 
 int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double* h,
-                         double sign, int64_t n, double* G, int j, int mm) {
+                         double sign, int64_t n, double* G, int j, int mm, double* hest) {
   const int nb = fused_blocks(n);
   hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, sign, n, c->red);
-  hipLaunchKernelGGL(k_sum_givens, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, h, G, j, mm);
+  hipLaunchKernelGGL(k_sum_givens, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, h, G, j, mm, hest);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
