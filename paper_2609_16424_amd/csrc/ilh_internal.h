@@ -113,10 +113,10 @@ struct ilh_ctx {
   double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   double* hdev = nullptr;       // [HDEV_LEN] device scalars of the Arnoldi step
-  double* hest = nullptr;       // pinned, coherent: (|g_j+1|, h_j+1,j) of each Arnoldi step, stored by
-  double* hest_dev = nullptr;   // the device through its mapped address hest_dev
+  double* hest = nullptr;       // pinned, coherent: (|g_j+1|, h_j+1,j) of each Arnoldi step at [2j, 2j+1]
+  double* hest_dev = nullptr;   // and the cycle's tag at [128 + j], stored by the device (mapped address)
+  double est_tag = 0.0;         // tag of the current FGMRES cycle (host counter)
   double* gmd = nullptr;        // device Givens state of FGMRES: H [64][64], cs, sn [64], g [65]
-  hipEvent_t gev[2] = {nullptr, nullptr};  // FGMRES: residual estimates of alternate steps ready
   hipStream_t capstream = nullptr;         // stream the Arnoldi-step graphs are captured on
   std::vector<hipGraphExec_t> gexec;       // captured Arnoldi step per basis index
   uint64_t gkey = 0;                       // configuration the graphs were captured for

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -272,8 +274,6 @@ void ilh_destroy(ilh_ctx* c) {
   for (void* p : c->qd)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
-  for (hipEvent_t e : c->gev)
-    if (e) (void)hipEventDestroy(e);
   for (hipGraphExec_t e : c->gexec)
     if (e) (void)hipGraphExecDestroy(e);
   if (c->capstream) (void)hipStreamDestroy(c->capstream);
@@ -841,12 +841,15 @@ static int read_pair(ilh_ctx* c, double* a, double* b) {
   return ILH_OK;
 }
 
-// y = x / beta; beta is also stored to *beta_out and the scale of the stored vector y, 1, to *s0
-__global__ void k_scale_copy(double* y, const double* x, double beta, int64_t n, double* beta_out, double* s0) {
+// y = x / beta; beta is also stored to *beta_out, the scale of the stored vector y, 1, to *s0
+// and the FGMRES cycle's tag to *tag_out
+__global__ void k_scale_copy(double* y, const double* x, double beta, int64_t n, double* beta_out, double* s0,
+                             double tag, double* tag_out) {
   const double f = 1.0 / beta;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *beta_out = beta;
     *s0 = 1.0;
+    *tag_out = tag;
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = x[i] * f;
@@ -1081,14 +1084,30 @@ struct Solver {
       c->qd_ok[0] = true;
     }
     while (true) {
-      // V0 = r / beta (beta to hd[240] for the Givens update, s_0 = 1)
-      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd + 240, hd + 256);
+      // V0 = r / beta (beta to hd[240] for the Givens update, s_0 = 1, the cycle's tag to hd[255])
+      const double tag = (c->est_tag += 1.0);
+      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd + 240, hd + 256, tag,
+                         hd + 255);
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
       // read step jj's estimate; true when the cycle ends after it
       auto check = [&](int jj, bool& end) -> int {
-        ILH_HIP(c, hipEventSynchronize(c->gev[jj & 1]));
+        // wait for the tag the step's reduction stores after its estimate; the stream running
+        // dry without it (every enqueued kernel done) is an error, so the wait always ends
         const volatile double* est = c->hest;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spins = 1; !(est[128 + jj] == tag); ++spins) {
+          __builtin_ia32_pause();
+          if ((spins & 1023) == 0) {
+            const hipError_t q = hipStreamQuery(c->stream);
+            if (q != hipSuccess && q != hipErrorNotReady) ILH_HIP(c, q);
+            if (q == hipSuccess && !(est[128 + jj] == tag))
+              return fail(c, ILH_EHIP, "FGMRES: a finished step left no residual estimate");
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
+              return fail(c, ILH_EHIP, "FGMRES: timed out waiting for a residual estimate");
+          }
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
         const double res = est[2 * jj], hn = est[2 * jj + 1];
         if (!std::isfinite(hn) || !std::isfinite(res)) return fail(c, ILH_ENONFINITE, "non-finite Krylov vector");
         ++total;
@@ -1106,7 +1125,6 @@ struct Solver {
         } else if ((st = arnoldi_step(j, m))) {
           return st;
         }
-        ILH_HIP(c, hipEventRecord(c->gev[j & 1], c->stream));
         if (j >= 1) {
           if ((st = check(j - 1, end))) return st;
           if (end) j_end = j;  // step j was speculative
@@ -1144,14 +1162,13 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   if (!c->nwt && (st = dalloc(c, &c->nwt, 8 * (size_t)n))) return st;
   if (!c->hdev && (st = dalloc(c, &c->hdev, HDEV_LEN))) return st;
   if (!c->hest) {
-    if (hipHostMalloc((void**)&c->hest, 128 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+    if (hipHostMalloc((void**)&c->hest, 256 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
         hipSuccess)
       return fail(c, ILH_ENOMEM, "pinned host buffer");
+    std::memset(c->hest, 0, 256 * sizeof(double));  // no tag (tags start at 1)
     ILH_HIP(c, hipHostGetDevicePointer((void**)&c->hest_dev, c->hest, 0));
   }
   if (!c->gmd && (st = dalloc(c, &c->gmd, 64 * 64 + 3 * 65))) return st;
-  for (hipEvent_t& e : c->gev)
-    if (!e) ILH_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   double* k = c->nwt;
   double* r = c->nwt + n;
   double* dk = c->nwt + 2 * n;

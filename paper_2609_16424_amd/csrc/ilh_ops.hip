@@ -402,7 +402,8 @@ __device__ void givens_update(double* h, double* G, int j, int m);
 // final sum of the norm partials into h[144], the Givens update of Arnoldi step j, and the
 // scale of the next basis vector, h[256 + j + 1] = 1 / |w| (1 for a zero or non-finite norm:
 // the cycle ends at that step).  The residual estimate also goes straight to host memory
-// (hest, mapped and coherent), so no copy is enqueued behind the step.
+// (hest, mapped and coherent), followed by the cycle's tag h[255] at hest[128 + j], which the
+// host polls: no copy and no event are enqueued behind the step.
 __global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, double* h, double* G, int j, int m,
                                                     double* hest) {
   double acc = 0.0;
@@ -416,7 +417,9 @@ __global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, 
     if (hest) {
       hest[2 * j] = h[352 + 2 * j];
       hest[2 * j + 1] = h[353 + 2 * j];
-      __threadfence_system();  // visible to the host once the step's event has completed
+      __threadfence_system();  // the estimate reaches the host before the tag
+      hest[128 + j] = h[255];
+      __threadfence_system();
     }
   }
 }
