@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V
 // w -= sum_j cf[j] V_j, then part[j][b] = block b's share of V_j . w (the updated w), j < m:
 // the first Gram-Schmidt pass's update and the second pass's products in one sweep.  Every
 // thread revisits only its own indices, so the later chunks read back its own updates.
-__global__ void __launch_bounds__(TPB) k_maxpy_mdot_part(double* __restrict__ w, const double* __restrict__ V,
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k_maxpy_mdot_part(double* __restrict__ w, const double* __restrict__ V,
                                                          int64_t ldv, int m, const double* __restrict__ cf,
                                                          int64_t n, double* part) {
   const int64_t stride = (int64_t)gridDim.x * KTILE;
@@ -321,10 +321,23 @@ __global__ void __launch_bounds__(TPB) k_maxpy_mdot_part(double* __restrict__ w,
       tile_index(t0, n, ic, in);
       double wv[KU];
       if (j0 == 0) {
-        double a[KU];
+        // the first chunk's rows stay in registers for its products with the updated w
+        double v0[MDOT_JC][KU], a[KU];
+#pragma unroll
+        for (int jj = 0; jj < MDOT_JC; ++jj) {
+          const int j = min(jj, m - 1);
+#pragma unroll
+          for (int u = 0; u < KU; ++u) v0[jj][u] = V[(int64_t)j * ldv + ic[u]];
+        }
 #pragma unroll
         for (int u = 0; u < KU; ++u) a[u] = 0.0;
-        tile_combo(V, ldv, m, cf, ic, a);
+#pragma unroll
+        for (int jj = 0; jj < MDOT_JC; ++jj) {
+          const double cj = jj < m ? cf[min(jj, m - 1)] : 0.0;
+#pragma unroll
+          for (int u = 0; u < KU; ++u) a[u] += cj * v0[jj][u];
+        }
+        if (m > MDOT_JC) tile_combo(V + MDOT_JC * ldv, ldv, m - MDOT_JC, cf + MDOT_JC, ic, a);
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
           if (in[u]) {
@@ -334,11 +347,15 @@ __global__ void __launch_bounds__(TPB) k_maxpy_mdot_part(double* __restrict__ w,
             wv[u] = 0.0;
           }
         }
+#pragma unroll
+        for (int jj = 0; jj < MDOT_JC; ++jj)
+#pragma unroll
+          for (int u = 0; u < KU; ++u) acc[jj] += v0[jj][u] * wv[u];
       } else {
 #pragma unroll
         for (int u = 0; u < KU; ++u) wv[u] = in[u] ? w[ic[u]] : 0.0;
+        tile_dots(V, ldv, m, j0, ic, wv, acc);
       }
-      tile_dots(V, ldv, m, j0, ic, wv, acc);
     }
     store_block_sums(acc, j0, min(MDOT_JC, m - j0), part);
   }
@@ -419,7 +436,6 @@ __global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, 
       hest[2 * j + 1] = h[353 + 2 * j];
       __threadfence_system();  // the estimate reaches the host before the tag
       hest[128 + j] = h[255];
-      __threadfence_system();
     }
   }
 }
