@@ -78,3 +78,23 @@ def test_graph_replay_matches_eager_launches(case):
         states[graphs] = traj
     for a, b in zip(states[0], states[1]):
         assert rel(a, b) <= 1e-9
+
+
+@pytest.mark.parametrize("restart,graphs", [(3, 0), (1, 0), (3, 1)])
+def test_short_restart_cycles_match_oracle(restart, graphs):
+    """FGMRES restarted every `restart` Arnoldi steps (many cycles per Newton iteration, each
+    with its own residual-estimate tag) reaches the oracle's trajectory to the Newton tolerance."""
+    from oracle import krylov
+    O, G = make_pair("tg2d", (8, 8), 2)
+    u0 = O.init_state()
+    states, _, _ = krylov.run_midpoint(O, u0, 0.01, 4)
+    u = to_dev(u0)
+    hist = []
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, restart=restart, gmres_maxit=400, graphs=graphs)
+    for n in range(4):
+        g = G.plain_guess(u, hist)
+        k, st = G.implicit_step(u, 0.01, guess=g, opts=opts)
+        assert st["status"] == 0 and st["res_final"] <= 1e-10 * st["res0"]
+        assert st["gmres"] > restart  # more than one cycle per step
+        hist = (hist + [k])[-2:]
+        assert rel(to_np(u), states[n + 1]) <= 1e-8, (n, rel(to_np(u), states[n + 1]))
