@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # reported as null.
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": "c05e2b4e01d5072e29ade64291bd106fee9345d609c5a9c7c1580ee3ca2d5885",
+TRAFFIC_RECORD = {"sha256": "23dfcbc494f3ee43f45f12a985a08adfa6138d1ce8e604a699f2227426f74f16",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16585.4, "fetch_scale": 262144.0 / 131079.4,
-                  "write_kib": 7084.5, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 16585.5, "fetch_scale": 262144.0 / 131079.7,
+                  "write_kib": 7084.3, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
