@@ -220,11 +220,11 @@ typedef struct {
   int prec_lag;        /* with prec_probe: 0 rebuild the blocks at every Newton iterate, 1 only
                           at the first iterate of each stage solve (lagged, Sec. 3.5) */
   int graphs;          /* 1: replay each Arnoldi step (preconditioner, FP32 linearised 2D
-                          action, Gram-Schmidt, normalisation) as a HIP graph captured once
-                          per context and basis index (not while kernel timing is enabled,
+                          action, Gram-Schmidt with the Givens update) as a HIP graph captured
+                          once per context and basis index (not while kernel timing is enabled,
                           nor with pcg_iters > 0); 0 (default): launch its kernels one by one,
                           measured faster on this stack (graph launch costs more than the
-                          ten kernel launches it replaces) */
+                          kernel launches it replaces) */
 } ilh_newton_opts;
 
 typedef struct {

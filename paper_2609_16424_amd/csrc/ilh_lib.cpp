@@ -970,7 +970,8 @@ struct Solver {
   }
 
   // One Arnoldi step j: z_j = P v_j, w = J z_j, two Gram-Schmidt passes with the Givens
-  // update, and the pinned copy of the residual estimate.  The basis vectors are stored
+  // update; the last reduction also stores the residual estimate and the cycle's tag in mapped
+  // host memory (c->hest), which the host polls.  The basis vectors are stored
   // unnormalised: v_j = s_j x (stored V_j), s_j = 1 / |w| set by step j-1's norm reduction; the
   // preconditioner and the pass coefficients take the scale, so no pass rescales the vector.
   int arnoldi_step(int j, int m) {
@@ -1053,8 +1054,9 @@ struct Solver {
   // FGMRES: solve J x = b, x starts at 0.  Returns total iterations in *its.  beta_b >= 0 is
   // |b| when the caller already has it (no reduction and synchronisation for it).
   // The Givens rotations, the residual estimate and the triangular solve run on the device;
-  // the host enqueues Arnoldi step j before it reads step j-1's residual estimate (pinned copy
-  // behind an event), so the stream never drains between steps.  A step enqueued after the
+  // the host enqueues Arnoldi step j before it reads step j-1's residual estimate (stored by
+  // the device in mapped host memory and tagged per cycle), so the stream never drains between
+  // steps.  A step enqueued after the
   // one that converged is discarded: it only touches V_{j+1}, Z_j, column j and g_j, g_{j+1},
   // none of which the solution over the first j columns reads.
   int fgmres(const double* b, double* x, int* its, double beta_b = -1.0) {
