@@ -589,9 +589,13 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   if (!c || !k || !u || !r) return ILH_EINVAL;
   int st = launch_fill(c, r + c->nh1, 0.0, c->nh1);
   if (st) return st;
-  EArgs<double> a{u, u + c->nh1, u + 2 * c->nh1, k, nullptr, tau, r, nullptr};
   const int slot = tstart_k(c, 1);
-  st = launch_elem(c, M_RESID, 64, &a, nullptr);
+  if (c->jvp_variant != 1 && res2d_available(c)) {
+    st = launch_res2d(c, k, u, tau, r);
+  } else {
+    EArgs<double> a{u, u + c->nh1, u + 2 * c->nh1, k, nullptr, tau, r, nullptr};
+    st = launch_elem(c, M_RESID, 64, &a, nullptr);
+  }
   tstop_k(c, slot);
   return st;
 }
