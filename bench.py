@@ -16,8 +16,9 @@ Printed JSON line:
               attached by the library to each dispatch on its stream);
   ms_per_step wall time per implicit step (host synchronised at both ends);
   roofline    algorithmic bytes of one Jacobian-action (apply) launch / its mean launch time,
-              vs 8 TB/s; traffic = counter-measured bytes per launch when recorded for the
-              current kernel sources;
+              vs 8 TB/s; traffic = counter-measured bytes per launch, and valu = counted VALU
+              instructions per launch with the fraction of the issue peak they occupy at the
+              measured launch time, when recorded for the current kernel sources;
   cpu_baseline the CPU oracle's complex-step Jacobian action on the same state.
 Run with --gpus N, N > 1: exits, this build runs on one GPU only.
 """
@@ -52,6 +53,21 @@ def sources_sha256():
         with open(os.path.join(root, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+# VALU instructions per launch of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU, same sources):
+# the issue peak of wave64 FP32 (unpacked) / FP64 VALU instructions is 1024 SIMDs x 2.4 GHz / 4.
+VALU_RECORD = {"sha256": TRAFFIC_RECORD["sha256"], "variant": "lin", "n": 128, "order": 3,
+               "instructions": 2620405.0}
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
+
+
+def recorded_valu(n, k, variant, launch_s):
+    r = VALU_RECORD
+    if variant != r["variant"] or (n, k) != (r["n"], r["order"]) or sources_sha256() != r["sha256"]:
+        return None
+    return {"instructions_per_launch": r["instructions"], "issue_peak_per_s": VALU_ISSUE_PEAK,
+            "busy": r["instructions"] / (launch_s * VALU_ISSUE_PEAK)}
 
 
 def recorded_traffic(n, k, variant):
@@ -546,7 +562,8 @@ def main():
                      "traffic": recorded_traffic(n, k, args.jvp_variant),
                      "kernel": KERNEL_NAMES[args.jvp_variant], "bytes_per_launch": bytes_loop,
                      "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n,
-                     "avg_launch_us_back_to_back_fp32_output": burst_us},
+                     "avg_launch_us_back_to_back_fp32_output": burst_us,
+                     "valu": recorded_valu(n, k, args.jvp_variant, jvp_avg_s)},
         "transpose_action": {"kernel": "k_vjp2d_q<4,6,float,visc=0,src=1>", "avg_launch_us_back_to_back": vjp_us,
                              "qps": H.nqp / (1e-6 * vjp_us), "bytes_per_launch": bytes32,
                              "frac": bytes32 / (1e-6 * vjp_us) / 1e9 / HBM_PEAK_GBS},
