@@ -236,7 +236,8 @@ def test_linearised_large_mesh(n, k):
 
 
 @pytest.mark.parametrize("prob,n,k", [("tg2d", (23, 7), 3), ("tg2d", (9, 1), 3), ("tg2d", (33, 5), 2),
-                                      ("triple", (21, 9), 3), ("triple", (17, 4), 2), ("uniform", (12, 3), 3)])
+                                      ("triple", (21, 9), 3), ("triple", (17, 4), 2), ("uniform", (12, 3), 3),
+                                      ("tg2d", (1, 1), 3), ("tg2d", (2, 2), 2), ("uniform", (1, 5), 2)])
 def test_strip_residual_matches_oracle_and_generic(prob, n, k):
     """The 2D strip residual kernel (no viscosity) against the oracle and against the generic
     element kernel (kernel variant 1): partial strips, one-row meshes, per-element gamma and rho
