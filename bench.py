@@ -166,7 +166,7 @@ def triple_point_legs(ilh, torch):
         h = L.make_triple(112, 48, 3)
         u = h.init_state()
         dt = 8.0 * h.dt_estimate(u, 0.5)
-        opts = ilh.newton_options(tol=1e-10, jvp_prec=prec, max_newton=30, restart=30, gmres_maxit=150,
+        opts = ilh.newton_options(tol=1e-10, jvp_prec=prec, max_newton=30, restart=15, gmres_maxit=150,
                                   prec_probe=2, prec_lag=1)
         hist, newton, gmres = [], [], []
         torch.cuda.synchronize()
@@ -197,7 +197,7 @@ def triple_point_legs(ilh, torch):
     u = h.init_state()
     dt_exp = h.dt_estimate(u, 0.5)
     dt = 8.0 * dt_exp
-    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150)
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=15, gmres_maxit=150)
     hist, rej, ratios, newton = [], [], [], []
     for _ in range(10):
         g = h.plain_guess(u, hist, 0.5 * dt)
@@ -241,7 +241,7 @@ def sedov_leg(ilh, torch, n=16, k=3, T=0.8):
         H = ilh.make_sedov(n, k)
         u = H.init_state()
         e0 = sum(H.energy(u))
-        opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150,
+        opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=15, gmres_maxit=150,
                                   prec_probe=2, prec_lag=1)
         t, steps, hist, newton, gmres = 0.0, 0, [], 0, 0
         torch.cuda.synchronize()

@@ -201,7 +201,7 @@ int ilh_plain_guess(ilh_ctx* ctx, const double* u, const double* k1, const doubl
 typedef struct {
   double tol;          /* relative nonlinear tolerance (1e-10 for the benchmarks) */
   int max_newton;      /* Newton iteration cap */
-  int restart;         /* FGMRES restart length (<= 64) */
+  int restart;         /* FGMRES restart length (<= 64; default 15) */
   double gmres_rtol;   /* relative tolerance of each linear solve */
   int gmres_maxit;     /* FGMRES iteration cap per Newton iteration */
   int jvp_prec;        /* 32 or 64: precision of the Jacobian actions inside FGMRES */

@@ -234,7 +234,7 @@ void ilh_setup_defaults(ilh_setup* s, int problem) {
 void ilh_newton_defaults(ilh_newton_opts* o) {
   o->tol = 1e-10;
   o->max_newton = 30;
-  o->restart = 30;
+  o->restart = 15;
   o->gmres_rtol = 1e-6;
   o->gmres_maxit = 150;
   o->jvp_prec = 32;

@@ -73,10 +73,11 @@ VISC = {"mode": "formula", "width": 1e-3, "h_coarse": 1.0 / 3.0}
 
 
 def model_newton_options(z):
-    """Newton-Krylov options a committed model was trained and is evaluated with."""
+    """Newton-Krylov options a committed model is evaluated with (its preconditioner settings;
+    the GMRES restart length only changes how the inexact Newton steps are reached)."""
     pp = int(z["prec_probe"]) if "prec_probe" in z else 0
     pl = int(z["prec_lag"]) if "prec_lag" in z else 0
-    return newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150,
+    return newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=15, gmres_maxit=150,
                           prec_probe=pp, prec_lag=pl)
 
 
@@ -411,7 +412,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     VISC["mode"] = a.dscale
-    opts = newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=30, gmres_maxit=150,
+    opts = newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=15, gmres_maxit=150,
                           pcg_iters=a.pcg_iters, prec_probe=a.prec_probe, prec_lag=a.prec_lag)
     lo, hi = [int(v) for v in a.eval_seeds.split("-")]
     eval_seeds = list(range(lo, hi + 1))
