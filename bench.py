@@ -40,9 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # reported as null.
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": "23dfcbc494f3ee43f45f12a985a08adfa6138d1ce8e604a699f2227426f74f16",
+TRAFFIC_RECORD = {"sha256": "3e973d11cabe3023099f1c104b687ee29a923738a8e46c054716a78b75822c3a",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16585.5, "fetch_scale": 262144.0 / 131079.7,
+                  "fetch_kib": 16585.5, "fetch_scale": 262144.0 / 131081.1,
                   "write_kib": 7084.3, "write_scale": 262144.0 / 262144.0}
 
 
