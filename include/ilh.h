@@ -330,6 +330,14 @@ int ilh_set_kernel_variant(ilh_ctx* ctx, int variant);
  * on large meshes.  The result does not depend on it beyond the order of FP additions.
  * rows < 0: ILH_EINVAL. */
 int ilh_set_apply_rows(ilh_ctx* ctx, int rows);
+/* Waves per strip of the 2D FP32 linearised Jacobian-action kernel: 1 (one wave takes every
+ * quadrature row of its strip of elements) or 2 (the two waves of a work-group share the strip:
+ * each takes half of the quadrature rows, and the direction's gathers and the node sums are
+ * spread over both, which halves each wave's chain of dependent row steps on meshes whose
+ * one-wave grid leaves SIMDs idle).  waves = 0 (default) picks 2 on meshes whose one-wave grid
+ * has fewer than 1,024 waves (one per SIMD), else 1.  FP64 actions always use one wave.  The
+ * result does not depend on it beyond the order of FP additions.  Other values: ILH_EINVAL. */
+int ilh_set_apply_waves(ilh_ctx* ctx, int waves);
 int ilh_timing_enable(ilh_ctx* ctx, int on);
 int ilh_timing_read(ilh_ctx* ctx, double* ms, int64_t* launches);
 

@@ -274,6 +274,11 @@ class Hydro:
         0 chooses by mesh size."""
         self._check(self.lib.ilh_set_apply_rows(self.ctx, int(rows)))
 
+    def set_apply_waves(self, waves):
+        """Waves per element strip of the 2D FP32 linearised apply kernel (1 or 2); 0 chooses by
+        mesh size."""
+        self._check(self.lib.ilh_set_apply_waves(self.ctx, int(waves)))
+
     def timing(self, on=True):
         self._check(self.lib.ilh_timing_enable(self.ctx, int(bool(on))))
 

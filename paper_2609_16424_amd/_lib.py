@@ -88,6 +88,7 @@ SIGNATURES = {
     "ilh_timing_enable": (I, [P, I]),
     "ilh_set_kernel_variant": (I, [P, I]),
     "ilh_set_apply_rows": (I, [P, I]),
+    "ilh_set_apply_waves": (I, [P, I]),
     "ilh_vjp_lin": (I, [P, I, P, P]),
     "ilh_vjp": (I, [P, I, P, P, D, P, P]),
     "ilh_rk2avg_step": (I, [P, P, D]),

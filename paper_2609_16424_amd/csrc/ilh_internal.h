@@ -121,6 +121,7 @@ struct ilh_ctx {
   std::vector<hipGraphExec_t> gexec;       // captured Arnoldi step per basis index
   uint64_t gkey = 0;                       // configuration the graphs were captured for
   int apply_rows = 0;           // element rows per apply wave of the linearised kernels (0: by mesh size)
+  int apply_waves = 0;          // waves per strip of the 2D FP32 linearised apply (0: by mesh size)
   int jvp_variant = 0;          // 0 linearised (where available), 1 generic, 2 register-resident recompute
   void* qd[2] = {nullptr, nullptr};  // stored tangent coefficients, FP32 / FP64 (linearised variant)
   bool qd_ok[2] = {false, false};    // valid for the current linearisation point

@@ -164,8 +164,11 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
 // the strip then takes one atomic add (one per node and strip instead of one per node and
 // element); energy rows are element-owned, position rows and constrained velocity rows are
 // written by the node's owner.  The velocity part of out must be zero on entry.
-template <int D1D, int Q1D, typename T, int VISC, int SRC, typename TO>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC && sizeof(T) == 8 ? 1 : 2))) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
+// W = 2 (FP32, small meshes): the two waves of a work-group share the strip, each takes half
+// of the quadrature rows; the gathers and the node sums are spread over both, which halves the
+// wave's chain of dependent row steps where the one-wave grid leaves most SIMDs idle.
+template <int D1D, int Q1D, typename T, int VISC, int SRC, typename TO, int W>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VISC && sizeof(T) == 8 ? 1 : 2))) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
                                                 const T* __restrict__ dk, const T* __restrict__ qd,
                                                 int64_t qs, double tau_, TO* __restrict__ out, int R,
                                                 const double* __restrict__ tau_dev) {
@@ -175,16 +178,18 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
   constexpr int NQD = LinLayout<2, VISC, SRC>::NQD;
   constexpr int NVO = 2 * D1D * D1D;  // velocity outputs per element (energy: NLD < NVO, later)
   constexpr int NOP = NVO | 1;        // odd LDS row length (bank spread)
-  static_assert(Q1D % 2 == 0, "the quadrature rows are processed in pairs");
+  static_assert(Q1D % W == 0, "the quadrature rows split evenly over the waves");
+  constexpr int NT = 64 * W;          // threads of the work-group
+  constexpr int QW = Q1D / W;         // quadrature rows per wave
 
   __shared__ T sS[4][D1D][NS];  // dkx0 dkx1 dkv0 dkv1 strips
   __shared__ T sE[EPW * NLD];   // dk_e
-  __shared__ T sO[64][NOP];     // per-lane contributions to the element's outputs (velocity, then energy)
+  __shared__ T sO[W][64][NOP];  // per-lane contributions to the element's outputs (velocity, then energy)
   __shared__ T sC[2][2][NS];    // carried velocity sums of node row K (parity of the element row)
   __shared__ T sBG[2][Q1D][D1D];
   __shared__ T sBLt[Q1D][L1D];
 
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, hw = W == 1 ? 0 : tid / 64, lane = tid - 64 * hw;
   const uint32_t tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int sx = tile % gridDim.x, sy = tile / gridDim.x;
   const int ex0 = sx * EPW;
@@ -199,11 +204,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
   const int z = lane / Q1D, qx = lane - z * Q1D;
   const bool active = z < E;
 
-  for (int i = lane; i < Q1D * D1D; i += 64) {
+  for (int i = tid; i < Q1D * D1D; i += NT) {
     sBG[0][i / D1D][i % D1D] = tb.B[i / D1D][i % D1D];
     sBG[1][i / D1D][i % D1D] = tb.G[i / D1D][i % D1D];
   }
-  for (int i = lane; i < Q1D * L1D; i += 64) sBLt[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
+  for (int i = tid; i < Q1D * L1D; i += NT) sBLt[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
 
 #pragma unroll 1
   for (int ey = ey0; ey < ey1; ++ey) {
@@ -212,29 +217,29 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
     const uint32_t ebase = (uint32_t)ey * nx + ex0;
     const uint32_t row0 = (uint32_t)(K * ey) * ng0 + (uint32_t)(K * ex0);  // first node of the strip
 
-    constexpr int NTS = 4 * D1D * NS, RT = (NTS + 63) / 64;
-    constexpr int NLS = EPW * NLD, RL = (NLS + 63) / 64;
+    constexpr int NTS = 4 * D1D * NS, RT = (NTS + NT - 1) / NT;
+    constexpr int NLS = EPW * NLD, RL = (NLS + NT - 1) / NT;
     // branch-free gathers: lanes past the strip re-read its last node (their LDS slots feed no
     // output), so all loads of the element row are in flight together
     T tr[RT], lr[RL];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
-      const int i = lane + 64 * q, si = min(i % NS, ns - 1), t = min(i / NS, 4 * D1D - 1), b = t % D1D,
+      const int i = tid + NT * q, si = min(i % NS, ns - 1), t = min(i / NS, 4 * D1D - 1), b = t % D1D,
                 f = t / D1D;
       tr[q] = ld32(dk, (f < 2 ? f * N : nh1 + (f - 2) * N) + row0 + (uint32_t)b * ng0 + si);
     }
 #pragma unroll
-    for (int q = 0; q < RL; ++q) lr[q] = ld32(dk, 2 * nh1 + ebase * NLD + min(lane + 64 * q, E * NLD - 1));
+    for (int q = 0; q < RL; ++q) lr[q] = ld32(dk, 2 * nh1 + ebase * NLD + min(tid + NT * q, E * NLD - 1));
     const double rj_l = P.rj0[ebase + (active ? z : 0)];
     __syncthreads();  // the previous element row's readers of sS, sE and sO are done
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
-      const int i = lane + 64 * q;
+      const int i = tid + NT * q;
       if (i < NTS) (&sS[0][0][0])[i] = tr[q];
     }
 #pragma unroll
     for (int q = 0; q < RL; ++q) {
-      const int i = lane + 64 * q;
+      const int i = tid + NT * q;
       if (i < NLS) sE[i] = lr[q];
     }
     __syncthreads();
@@ -337,15 +342,18 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
 #pragma unroll
         for (int bl = 0; bl < L1D; ++bl) TL[bl] += tb.BL[qy][bl] * cl;
       };
-      // two coefficient buffers: the loads of one row are in flight during the other's arithmetic
+      // this wave's quadrature rows [q0, q0 + QW); two coefficient buffers: the loads of one
+      // row are in flight during the other's arithmetic
+      const int q0 = hw * QW, q1 = q0 + QW;
       T ca[NQD], cb[NQD];
-      ldrow(0, ca);
+      ldrow(q0, ca);
 #pragma unroll 1
-      for (int qy = 0; qy < Q1D; qy += 2) {
-        ldrow(qy + 1, cb);
+      for (int qy = q0; qy < q1; qy += 2) {
+        constexpr bool ODD = QW % 2 != 0;  // the last pass of an odd count has one row
+        if (!ODD || qy + 1 < q1) ldrow(qy + 1, cb);
         row(qy, ca);
-        if (qy + 2 < Q1D) ldrow(qy + 2, ca);
-        row(qy + 1, cb);
+        if (qy + 2 < q1) ldrow(qy + 2, ca);
+        if (!ODD || qy + 1 < q1) row(qy + 1, cb);
       }
 #pragma unroll
       for (int a = 0; a < D1D; ++a) {  // reloaded: not kept live through the row loop
@@ -358,7 +366,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
         for (int b = 0; b < D1D; ++b)
 #pragma unroll
           for (int a = 0; a < D1D; ++a)
-            sO[lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
+            sO[hw][lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
     }
     __syncthreads();
 
@@ -368,7 +376,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
     T* const cw = &sC[r & 1][0][0];
     const T* const cr = &sC[(r + 1) & 1][0][0];
 #pragma unroll 1
-    for (int i = lane; i < 2 * D1D * NS; i += 64) {
+    for (int i = tid; i < 2 * D1D * NS; i += NT) {
       const int s = i % NS, t = i / NS, b = t % D1D, c = t / D1D;
       if (s >= ns) continue;
       const uint32_t I = K * ex0 + s, J = K * ey + b;
@@ -385,11 +393,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
       T f = T(0);
       if (zz < E) {
 #pragma unroll
-        for (int q = 0; q < Q1D; ++q) f += sO[zz * Q1D + q][c * D1D * D1D + b * D1D + a];
+        for (int h = 0; h < W; ++h)
+#pragma unroll
+          for (int q = 0; q < Q1D; ++q) f += sO[h][zz * Q1D + q][c * D1D * D1D + b * D1D + a];
       }
       if (a == 0 && zz > 0) {
 #pragma unroll
-        for (int q = 0; q < Q1D; ++q) f += sO[(zz - 1) * Q1D + q][c * D1D * D1D + b * D1D + K];
+        for (int h = 0; h < W; ++h)
+#pragma unroll
+          for (int q = 0; q < Q1D; ++q) f += sO[h][(zz - 1) * Q1D + q][c * D1D * D1D + b * D1D + K];
       }
       if (b == K && !last_y && ey + 1 < ey1) {  // completed by the next element row of this wave
         cw[c * NS + s] = f;
@@ -406,15 +418,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VISC &&
 #pragma unroll
       for (int bl = 0; bl < L1D; ++bl)
 #pragma unroll
-        for (int al = 0; al < L1D; ++al) sO[lane][bl * L1D + al] = sBLt[qx][al] * TL[bl];
+        for (int al = 0; al < L1D; ++al) sO[hw][lane][bl * L1D + al] = sBLt[qx][al] * TL[bl];
     }
     __syncthreads();
 #pragma unroll 1
-    for (int i = lane; i < E * NLD; i += 64) {
+    for (int i = tid; i < E * NLD; i += NT) {
       const int zz = i / NLD, t = i % NLD;
       T o = 0;
 #pragma unroll
-      for (int q = 0; q < Q1D; ++q) o += sO[zz * Q1D + q][t];
+      for (int h = 0; h < W; ++h)
+#pragma unroll
+        for (int q = 0; q < Q1D; ++q) o += sO[h][zz * Q1D + q][t];
       out[2 * nh1 + ebase * NLD + i] = TO(o);
     }
   }
@@ -471,13 +485,30 @@ static void lin_t(ilh_ctx* c, T* qd) {
           (const double*)c->w64, c->lin_tau, qd, lin2d_stride(c));
 }
 
+// Waves per strip of the FP32 apply: 2 while the one-row, one-wave grid gives the SIMDs fewer
+// than one wave each (1,024 SIMDs), else 1; FP64 always 1 (its register budget is full).
+// c->apply_waves > 0 overrides the choice for FP32.
+static int apply_waves(const ilh_ctx* c, bool fp32) {
+  if (!fp32) return 1;
+  if (c->apply_waves > 0) return c->apply_waves;
+  const dim3 g = lin2d_grid(c);
+  return (int64_t)g.x * g.y < 1024 ? 2 : 1;
+}
+
 template <int K, typename T, int VISC, int SRC, typename TO>
 static void apply_t(ilh_ctx* c, const T* dk, const T* qd, TO* out, const double* tau_dev) {
   constexpr int D1D = K + 1, Q1D = 2 * K;
   const int R = apply_rows(c);
-  const dim3 g = lin2d_grid(c);
-  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO>, dim3(g.x, (g.y + R - 1) / R), dim3(64), 0, c->kp,
-          make_tab2<T, D1D, Q1D>(c), dk, qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev);
+  const dim3 g = lin2d_grid(c), grid(g.x, (g.y + R - 1) / R);
+  if constexpr (sizeof(T) == 4) {
+    if (apply_waves(c, true) == 2) {
+      klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 2>, grid, dim3(128), 0, c->kp, make_tab2<T, D1D, Q1D>(c),
+              dk, qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev);
+      return;
+    }
+  }
+  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 1>, grid, dim3(64), 0, c->kp, make_tab2<T, D1D, Q1D>(c), dk,
+          qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev);
 }
 
 template <typename T>

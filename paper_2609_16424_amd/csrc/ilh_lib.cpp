@@ -1016,6 +1016,7 @@ struct Solver {
     mix((uint64_t)o->prec_probe);
     mix((uint64_t)o->prec_coupled);
     mix((uint64_t)c->apply_rows);
+    mix((uint64_t)c->apply_waves);
     mix((uint64_t)c->nblock);
     return k;
   }
@@ -1303,6 +1304,13 @@ int ilh_set_apply_rows(ilh_ctx* c, int rows) {
   if (!c) return ILH_EINVAL;
   if (rows < 0) return fail(c, ILH_EINVAL, "apply rows must be >= 0");
   c->apply_rows = rows;
+  return ILH_OK;
+}
+
+int ilh_set_apply_waves(ilh_ctx* c, int waves) {
+  if (!c) return ILH_EINVAL;
+  if (waves < 0 || waves > 2) return fail(c, ILH_EINVAL, "apply waves must be 0, 1 or 2");
+  c->apply_waves = waves;
   return ILH_OK;
 }
 

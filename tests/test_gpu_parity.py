@@ -163,8 +163,9 @@ def test_jvp_variants_agree(prob, n, k, visc, prec, tol):
                                            ("triple", (33, 5), 2, "formula"), ("tg2d", (12, 11), 3, "formula"),
                                            ("tg2d", (10, 1), 3, None)])
 def test_apply_rows_match_oracle(prob, n, k, visc):
-    """The linearised apply with one wave walking R element rows (partial last walk, partial last
-    strip) against the oracle's complex-step Jacobian action, FP64 and FP32."""
+    """The linearised apply with one or two waves per strip (FP32) walking R element rows (partial
+    last walk, partial last strip) against the oracle's complex-step Jacobian action, FP64 and
+    FP32."""
     from oracle.krylov import jvp_cs
     O, G = make_pair(prob, n, k, visc)
     u = random_state(O, 51)
@@ -173,16 +174,22 @@ def test_apply_rows_match_oracle(prob, n, k, visc):
     tau = 0.003
     ref = jvp_cs(lambda q: O.residual(q, u, tau), kk, dk)
     G.linearize(to_dev(kk), to_dev(u), tau)
-    for R in (1, 2, 3, 4, 8):
-        G.set_apply_rows(R)
-        a64 = to_np(G.jvp_lin(to_dev(dk), 64))
-        a32 = to_np(G.jvp_lin(to_dev(dk, torch.float32), 32))
-        assert rel(a64, ref) <= 1e-12, R
-        assert rel(a32, ref) <= 1e-5, R
+    for W in (1, 2):
+        G.set_apply_waves(W)
+        for R in (1, 2, 3, 4, 8):
+            G.set_apply_rows(R)
+            a64 = to_np(G.jvp_lin(to_dev(dk), 64))
+            a32 = to_np(G.jvp_lin(to_dev(dk, torch.float32), 32))
+            assert rel(a64, ref) <= 1e-12, (W, R)
+            assert rel(a32, ref) <= 1e-5, (W, R)
     G.set_apply_rows(0)
+    G.set_apply_waves(0)
     from paper_2609_16424_amd import IlhError
     with pytest.raises(IlhError):
         G.set_apply_rows(-1)
+    for bad in (-1, 3):
+        with pytest.raises(IlhError):
+            G.set_apply_waves(bad)
 
 
 def test_linearised_coefficients_follow_the_point():
@@ -226,13 +233,16 @@ def test_linearised_large_mesh(n, k):
         G.set_kernel_variant("generic")
         b = G.jvp_lin(d, prec).double()
         G.set_kernel_variant("lin")
-        for R in (0, 1, 4, 8):  # by mesh size, then forced walks of 1, 4 and 8 element rows
+        # by mesh size, then forced walks of 1, 4 and 8 element rows; one and two waves per strip
+        for R, W in ((0, 0), (1, 1), (4, 1), (8, 1), (1, 2), (4, 2)):
             G.set_apply_rows(R)
+            G.set_apply_waves(W)
             a = G.jvp_lin(d, prec).double()
             for lo, hi in ((0, G.nh1), (G.nh1, 2 * G.nh1), (2 * G.nh1, G.nblock)):
                 err = float(torch.linalg.norm(a[lo:hi] - b[lo:hi]) / torch.linalg.norm(b[lo:hi]))
-                assert err <= tol, (prec, R, lo, err)
+                assert err <= tol, (prec, R, W, lo, err)
         G.set_apply_rows(0)
+        G.set_apply_waves(0)
 
 
 @pytest.mark.parametrize("prob,n,k", [("tg2d", (23, 7), 3), ("tg2d", (9, 1), 3), ("tg2d", (33, 5), 2),
