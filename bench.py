@@ -137,6 +137,29 @@ def lin_bytes(H, prec):
     return H.nblock * 8 + n_coef(H) * H.nqp * (4 if prec == 32 else 8) + 3 * H.Ne * 8
 
 
+def res_bytes(H):
+    """Algorithmic bytes of one stage-residual launch: u and k read, R written (FP64 block
+    vectors), per-element rho0 |J0|, |J0| and gamma read (2D strip kernel; the generic kernel
+    reads per-point masses instead)."""
+    return 3 * H.nblock * 8 + 3 * H.Ne * 8
+
+
+def residual_rate(H, k, u, tau, launches):
+    """Mean launch time of the stage residual (library kernel events) -> dict."""
+    r = H.new()
+    for _ in range(2):
+        H.residual(k, u, tau, out=r)
+    H.timing(True)
+    for _ in range(launches):
+        H.residual(k, u, tau, out=r)
+    t = H.timing_read()
+    H.timing(False)
+    avg = 1e-3 * t["residual"][0] / max(t["residual"][1], 1)
+    b = res_bytes(H)
+    return {"avg_launch_us": 1e6 * avg, "qps": H.nqp / avg, "bytes_per_launch": b,
+            "achieved_GBs": b / avg / 1e9, "frac": b / avg / 1e9 / HBM_PEAK_GBS}
+
+
 KERNEL_NAMES = {"lin": "k_jvp2d_q<4,6,float,visc=0,src=1,out=double>", "generic": "k_elem2d<4,6,JVP,float,7>",
                 "recompute": "k_jvp2d<4,6,float,visc=0,src=1>"}
 
@@ -302,6 +325,26 @@ def cpu_baseline(u_np, n, k, dt, budget_s=30.0):
                       (len(times), n, n, k, k - 1, nqp)}
 
 
+def cpu_residual(u_np, k_np, n, k, dt, reps=3):
+    """The oracle's stage residual on the same state (NumPy FP64, one thread), median of reps."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:
+        limiter = None
+    from oracle.hydro import Hydro as OHydro
+    O = OHydro("tg2d", (n, n), k)
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        O.residual(k_np, u_np, 0.5 * dt)
+        times.append(time.perf_counter() - t0)
+    nqp = O.mesh.Ne * O.Q
+    return {"value": nqp / float(np.median(times)), "unit": "quad-pts/s", "cores": 1, "kind": "oracle",
+            "sample": "%d stage residual(s) on the %dx%d Q%dQ%d benchmark state (%d qp), NumPy FP64, 1 thread; "
+                      "median" % (reps, n, n, k, k - 1, nqp)}
+
+
 def _finite(v):
     """JSON has no NaN or infinity: a non-finite figure is reported as null."""
     if isinstance(v, dict):
@@ -384,6 +427,8 @@ def main():
     tv_ = H.timing_read()
     H.timing(False)
     vjp_us = 1e3 * tv_["transpose"][0] / max(tv_["transpose"][1], 1)
+    # the stage residual at the last stage increment, back to back
+    res_c2 = dict(residual_rate(H, hist[-1], u, 0.5 * dt, 20), kernel="k_res2d<4,6,src=1> (FP64)")
     u32 = u.clone()
     newton = [s["newton"] for s in stats]
     gmres = [s["gmres"] for s in stats]
@@ -458,7 +503,10 @@ def main():
         b64 = jvp_bytes(HR, 64, args.jvp_variant)
         roof_extra["fp64"] = {"avg_launch_us": 1e6 * a64, "jvp_qps": HR.nqp / a64, "bytes_per_launch": b64,
                               "achieved_GBs": b64 / a64 / 1e9, "frac": b64 / a64 / 1e9 / HBM_PEAK_GBS}
-        del HR, uR, kR, dk, dk32, out32, out64
+        kres = 1e-3 * dk  # a small stage increment for the residual
+        roof_extra["residual"] = dict(residual_rate(HR, kres, uR, 0.5 * HR.dt_estimate(uR, 2.0), 10),
+                                      kernel="k_res2d<4,6,src=1> (FP64)")
+        del HR, uR, kR, dk, dk32, out32, out64, kres
         torch.cuda.empty_cache()
 
     roof_3d = None
@@ -496,6 +544,17 @@ def main():
                                         "linearize_avg_us": (1e3 * tw["linearize"][0] / tw["linearize"][1]
                                                              if tw["linearize"][1] else None)}
                 del d3, o3
+            if not visc:  # the stage residual (generic FP64 element kernel in 3D)
+                k3r = 1e-3 * torch.randn(H3.nblock, device=u3.device, dtype=torch.float64,
+                                         generator=torch.Generator(device=u3.device).manual_seed(6))
+                rr = residual_rate(H3, k3r, u3, 0.5 * H3.dt_estimate(u3, 2.0), 5)
+                # generic kernel: per-point m_q instead of the per-element factors
+                b = 3 * H3.nblock * 8 + H3.nqp * 8 + H3.Ne * 8
+                a = 1e-6 * rr["avg_launch_us"]
+                rr.update(bytes_per_launch=b, achieved_GBs=b / a / 1e9, frac=b / a / 1e9 / HBM_PEAK_GBS,
+                          kernel="k_elem3d<3,4,RESID,double> (FP64)")
+                entry["residual"] = rr
+                del k3r
             roof_3d["%d%s" % (m, "_visc" if visc else "")] = entry
             del H3, u3, k3
             torch.cuda.empty_cache()
@@ -537,8 +596,10 @@ def main():
         sedov = sedov_leg(ilh, torch)
 
     cpu = None
+    cpu_res = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(u_start.detach().cpu().numpy(), n, k, dt)
+        cpu_res = cpu_residual(u_start.detach().cpu().numpy(), hist[-1].detach().cpu().numpy(), n, k, dt)
 
     out = {
         "metric": "JVP quad-pts/s (% HBM roofline); s/implicit step, learned-guess vs plain",
@@ -569,6 +630,8 @@ def main():
                              "frac": bytes32 / (1e-6 * vjp_us) / 1e9 / HBM_PEAK_GBS},
         "jvp_variant": args.jvp_variant,
         "jvp_apply_qps": H.nqp / jvp_avg_s,
+        "residual": res_c2,
+        "cpu_oracle_residual": cpu_res,
         "linearize": {"launches": lin_n, "avg_launch_us": 1e3 * lin_ms / max(lin_n, 1),
                       "bytes_per_launch": lin_bytes(H, 32) if lin_n else None,
                       "jvp_launches_per_linearization": jvp_n / lin_n if lin_n else None},
