@@ -139,8 +139,7 @@ def lin_bytes(H, prec):
 
 def res_bytes(H):
     """Algorithmic bytes of one stage-residual launch: u and k read, R written (FP64 block
-    vectors), per-element rho0 |J0|, |J0| and gamma read (2D strip kernel; the generic kernel
-    reads per-point masses instead)."""
+    vectors), per-element rho0 |J0|, |J0| and gamma read (strip kernels)."""
     return 3 * H.nblock * 8 + 3 * H.Ne * 8
 
 
@@ -544,17 +543,12 @@ def main():
                                         "linearize_avg_us": (1e3 * tw["linearize"][0] / tw["linearize"][1]
                                                              if tw["linearize"][1] else None)}
                 del d3, o3
-            if not visc:  # the stage residual (generic FP64 element kernel in 3D)
-                k3r = 1e-3 * torch.randn(H3.nblock, device=u3.device, dtype=torch.float64,
-                                         generator=torch.Generator(device=u3.device).manual_seed(6))
-                rr = residual_rate(H3, k3r, u3, 0.5 * H3.dt_estimate(u3, 2.0), 5)
-                # generic kernel: per-point m_q instead of the per-element factors
-                b = 3 * H3.nblock * 8 + H3.nqp * 8 + H3.Ne * 8
-                a = 1e-6 * rr["avg_launch_us"]
-                rr.update(bytes_per_launch=b, achieved_GBs=b / a / 1e9, frac=b / a / 1e9 / HBM_PEAK_GBS,
-                          kernel="k_elem3d<3,4,RESID,double> (FP64)")
-                entry["residual"] = rr
-                del k3r
+            # the stage residual (FP64 strip kernel)
+            k3r = 1e-3 * torch.randn(H3.nblock, device=u3.device, dtype=torch.float64,
+                                     generator=torch.Generator(device=u3.device).manual_seed(6))
+            entry["residual"] = dict(residual_rate(H3, k3r, u3, 0.5 * H3.dt_estimate(u3, 2.0), 5),
+                                     kernel="k_res3d<3,4> (FP64)")
+            del k3r
             roof_3d["%d%s" % (m, "_visc" if visc else "")] = entry
             del H3, u3, k3
             torch.cuda.empty_cache()

@@ -117,8 +117,8 @@ int ilh_force_jvp(ilh_ctx* ctx, int prec, const double* w, const void* dw, void*
  *   R_x = k_x - w_v
  *   R_v = M_V k_v + F(w) 1          (constrained rows: R_v = k_v)
  *   R_e = M_E k_e - F(w)^T w_v - b(w_x)   (b: TG energy source, else 0).
- * 2D, k = 2, 3 without viscosity: a strip kernel on the lane map of the linearised kernels
- * (unless kernel variant 1 is selected); otherwise the generic element kernel. */
+ * 2D (k = 2, 3) and 3D (k = 2, no TG source): strip kernels on the lane maps of the linearised
+ * kernels (unless kernel variant 1 is selected); otherwise the generic element kernel. */
 int ilh_residual(ilh_ctx* ctx, const double* k, const double* u, double tau, double* r);
 
 /* Store the linearisation point of the next ilh_jvp_lin calls: w = u + tau k in FP64 inside
@@ -319,7 +319,7 @@ int ilh_adaptive_step(ilh_ctx* ctx, double* u, double* dt, double dt_max, int sc
  *     linearisation point and precision (FP64 arithmetic, stored in the precision of the
  *     action) and each action applies them;
  *   1 generic LDS-staged element kernel recomputing the state's quadrature data (it also
- *     takes over the 2D residual, which otherwise runs on the strip kernel);
+ *     takes over the residual, which otherwise runs on the strip kernels where they exist);
  *   2 register-resident 2D kernel recomputing the state's quadrature data (2D, k = 2, 3).
  * Other values: ILH_EINVAL. */
 int ilh_set_kernel_variant(ilh_ctx* ctx, int variant);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libilh.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["ilh_lib.cpp", "ilh_elem.hip", "ilh_jvp2d.hip", "ilh_jvplin2d.hip", "ilh_jvplin3d.hip", "ilh_vjplin2d.hip", "ilh_res2d.hip", "ilh_ops.hip", "ilh_mlp.hip"]
+SOURCES = ["ilh_lib.cpp", "ilh_elem.hip", "ilh_jvp2d.hip", "ilh_jvplin2d.hip", "ilh_jvplin3d.hip", "ilh_vjplin2d.hip", "ilh_res.hip", "ilh_ops.hip", "ilh_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

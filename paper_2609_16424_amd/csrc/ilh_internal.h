@@ -228,10 +228,12 @@ int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, dou
 int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double* h,
                          double sign, int64_t n, double* G, int j, int mm, double* hest);
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev);
-// 2D stage residual on the strip lane map (no viscosity; k = 2, 3): r = R(k; u, tau), the
-// velocity rows of r zero on entry
+// Stage residual on the strip lane maps (2D k = 2, 3; 3D k = 2 without the TG source):
+// r = R(k; u, tau), the velocity rows of r zero on entry
 bool res2d_available(const ilh_ctx* c);
 int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r);
+bool res3d_available(const ilh_ctx* c);
+int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, double* r);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int min_detj_dev(ilh_ctx* c, const double* x, double* d_out);  // result stays on the device (no sync)
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);

@@ -592,6 +592,8 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   const int slot = tstart_k(c, 1);
   if (c->jvp_variant != 1 && res2d_available(c)) {
     st = launch_res2d(c, k, u, tau, r);
+  } else if (c->jvp_variant != 1 && res3d_available(c)) {
+    st = launch_res3d(c, k, u, tau, r);
   } else {
     EArgs<double> a{u, u + c->nh1, u + 2 * c->nh1, k, nullptr, tau, r, nullptr};
     st = launch_elem(c, M_RESID, 64, &a, nullptr);

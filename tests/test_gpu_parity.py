@@ -245,15 +245,20 @@ def test_linearised_large_mesh(n, k):
         G.set_apply_waves(0)
 
 
-@pytest.mark.parametrize("prob,n,k", [("tg2d", (23, 7), 3), ("tg2d", (9, 1), 3), ("tg2d", (33, 5), 2),
-                                      ("triple", (21, 9), 3), ("triple", (17, 4), 2), ("uniform", (12, 3), 3),
-                                      ("tg2d", (1, 1), 3), ("tg2d", (2, 2), 2), ("uniform", (1, 5), 2)])
-def test_strip_residual_matches_oracle_and_generic(prob, n, k):
-    """The 2D strip residual kernel (no viscosity) against the oracle and against the generic
-    element kernel (kernel variant 1): partial strips, one-row meshes, per-element gamma and rho
-    (triple point), with and without the TG source."""
+@pytest.mark.parametrize("prob,n,k,visc", [("tg2d", (23, 7), 3, None), ("tg2d", (9, 1), 3, None),
+                                           ("tg2d", (33, 5), 2, None), ("triple", (21, 9), 3, None),
+                                           ("triple", (17, 4), 2, None), ("uniform", (12, 3), 3, None),
+                                           ("tg2d", (1, 1), 3, None), ("tg2d", (2, 2), 2, None),
+                                           ("uniform", (1, 5), 2, None), ("triple", (21, 9), 3, "formula"),
+                                           ("triple", (13, 5), 2, "const"), ("tg3d", (5, 3, 4), 2, None),
+                                           ("tg3d", (9, 2, 3), 2, "formula"), ("tg3d", (1, 1, 1), 2, None),
+                                           ("tg3d", (4, 1, 2), 2, "const")])
+def test_strip_residual_matches_oracle_and_generic(prob, n, k, visc):
+    """The strip residual kernels (2D k = 2, 3; 3D Q2Q1) against the oracle and against the
+    generic element kernel (kernel variant 1): partial strips, one-row meshes, per-element gamma
+    and rho (triple point), with and without the TG source and the artificial viscosity."""
     import paper_2609_16424_amd as ilh
-    O, G = make_pair(prob, n, k, None)
+    O, G = make_pair(prob, n, k, visc, width=0.05 if visc == "const" else 1e-3)
     u = random_state(O, 61)
     kk = 0.1 * random_dir(O, 62)
     tau = 0.004
@@ -267,12 +272,12 @@ def test_strip_residual_matches_oracle_and_generic(prob, n, k):
     assert rel(r_strip, r_gen) <= FP64_TOL
 
 
-@pytest.mark.parametrize("n,k", [((130, 330), 3), ((64, 1040), 2)])
+@pytest.mark.parametrize("n,k", [((130, 330), 3), ((64, 1040), 2), ((40, 24, 16), 2)])
 def test_strip_residual_large_mesh(n, k):
     """Strip and generic residual kernels agree block by block on meshes of several thousand
     waves at a randomly perturbed state."""
     import paper_2609_16424_amd as ilh
-    G = ilh.Hydro("tg2d", n, k)
+    G = ilh.Hydro("tg2d" if len(n) == 2 else "tg3d", n, k)
     u = G.init_state()
     rng = np.random.default_rng(43)
     h = 1.0 / (k * max(n))
