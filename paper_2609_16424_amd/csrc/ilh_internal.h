@@ -201,7 +201,24 @@ int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_o
 // s_j x the stored vector), [352, 480) (|g_j+1|, h_j+1,j) per step, [480, 545) and [560, 625)
 // the two passes' coefficients times s_j (the coefficients of the stored vectors)
 constexpr int HDEV_LEN = 640;
+// y = H(0:n, 0:n)^-1 g
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
+// Norm reduction and Givens update of Arnoldi step j: the partial sums of |w|^2 (part, np blocks),
+// the Arnoldi scalars h, the rotations G (layout at givens_update), and the mapped host buffer of
+// residual estimates (hest, nullable).  Runs as its own one-block kernel, or as the extra last
+// block of the next preconditioner launch.
+struct GivensJob {
+  const double* part = nullptr;
+  int np = 0;
+  double* h = nullptr;
+  double* G = nullptr;
+  int j = 0;
+  int m = 0;
+  double* hest = nullptr;
+};
+int launch_sum_givens(ilh_ctx* c, const GivensJob& job);
+// y *= *s (s on the device)
+int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n);
 int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
 // fused versions: w read once per 8 basis vectors.  d_out[j] = s_j V_j . w (s nullable: 1),
 // d_outs (nullable) [j] = s_j d_out[j]
@@ -210,10 +227,11 @@ int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double
 // w -= sum_j cf[j] V_j, then the products of the updated w as in multidot_fused
 int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, int64_t n,
                    const double* s, double* d_out, double* d_outs);
-int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n);  // y *= *s
-// rs (nullable): the input vector is *rs times r
+// input *rs r (rs nullable: 1); job (nullable): run that Givens update in an extra block of the
+// same launch, the other blocks then form the scale it stores (1 / |r|) from its partial sums
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                   double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr);
+                   double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
+                   const GivensJob* job = nullptr);
 // probed diagonal blocks of the Jacobian (preconditioner option prec_probe)
 int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau);
 int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D);
@@ -221,12 +239,14 @@ int launch_probe_e_dir(ilh_ctx* c, float* d, int j);
 int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
 int launch_invert_blocks(ilh_ctx* c, double* B);
 int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr);
-// w += sign sum_j cf[j] V_j and |w|^2 into h[144], then the Givens update of step j (from the
-// pass coefficients h[0..j], h[72..72+j]) and the next basis scale h[256 + j + 1] = 1 / |w|;
-// hest (nullable, host-mapped) receives the step's (|g_j+1|, h_j+1,j) at [2j, 2j + 1]
-int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double* h,
-                         double sign, int64_t n, double* G, int j, int mm, double* hest);
+                         double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
+                         const GivensJob* job = nullptr);
+// w += sign sum_j cf[j] V_j with the partial sums of |w|^2 of the result; *job receives the Givens
+// update of step j that finishes it (into h[144], then from the pass coefficients h[0..j],
+// h[72..72+j], and the next basis scale h[256 + j + 1] = 1 / |w|; hest (nullable, host-mapped)
+// receives the step's (|g_j+1|, h_j+1,j) at [2j, 2j + 1] and the cycle's tag at [128 + j])
+int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double sign,
+                  int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job);
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev);
 // Stage residual on the strip lane maps (2D k = 2, 3; 3D k = 2 without the TG source):
 // r = R(k; u, tau), the velocity rows of r zero on entry

@@ -894,12 +894,17 @@ struct Solver {
   int jvp_calls = 0;
 
   // next_out (nullable): the FP64 output of the Jacobian action that will read z; when the
-  // FP32 action can write it directly, the preconditioner kernel also zeroes its velocity rows
-  // rs (nullable, device): the input vector is *rs times r
-  int precond(const double* r, double* z, double* next_out = nullptr, const double* rs = nullptr) {
+  // FP32 action can write it directly, the preconditioner kernel also zeroes its velocity rows.
+  // rs (nullable, device): the input vector is *rs times r.
+  // job (nullable): the Givens update of the Arnoldi step that produced r, run by an extra block
+  // of the preconditioner launch (or, for the PCG form, as its own launch first); *rs is the
+  // scale that update stores, which the other blocks of the launch form from the same partial
+  // sums, so the preconditioned vector is that of the normalised basis vector.
+  int precond(const double* r, double* z, double* next_out = nullptr, const double* rs = nullptr,
+              const GivensJob* job = nullptr) {
     int st;
     const int slot = tstart(c, 4);
-    st = precond_body(r, z, next_out, rs);
+    st = precond_body(r, z, next_out, rs, job);
     tstop(c, slot);
     return st;
   }
@@ -910,7 +915,7 @@ struct Solver {
   // FP32 linearised 2D actions write the FP64 Krylov vector directly
   bool direct64() const { return o->jvp_prec == 32 && c->jvp_variant == 0 && lin2d_available(c); }
 
-  int precond_body(const double* r, double* z, double* next_out, const double* rs) {
+  int precond_body(const double* r, double* z, double* next_out, const double* rs, const GivensJob* job) {
     const int64_t nh1 = c->nh1;
     int st;
     z32_of = nullptr;
@@ -919,18 +924,19 @@ struct Solver {
     const double* tdev = c->hdev + 250;  // tau on the device (set at the start of each solve)
     if (o->prec_probe) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs))) return st;
+      if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs, job))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
     if (o->pcg_iters <= 0) {
       float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
-      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs))) return st;
+      if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs, job))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
+    if (job && (st = launch_sum_givens(c, *job))) return st;
     ILH_HIP(c, hipMemcpyAsync(z, r, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (o->pcg_iters > 0) {
       if ((st = pcg_mass_v(c, r + nh1, z + nh1, 0.0, o->pcg_iters, 0, nullptr, nullptr))) return st;
@@ -975,32 +981,35 @@ struct Solver {
     return ilh_jvp_lin(c, 64, x, y);
   }
 
-  // One Arnoldi step j: z_j = P v_j, w = J z_j, two Gram-Schmidt passes with the Givens
-  // update; the last reduction also stores the residual estimate and the cycle's tag in mapped
-  // host memory (c->hest), which the host polls.  The basis vectors are stored
-  // unnormalised: v_j = s_j x (stored V_j), s_j = 1 / |w| set by step j-1's norm reduction; the
-  // preconditioner and the pass coefficients take the scale, so no pass rescales the vector.
+  // One Arnoldi step j: w = J z_j, two Gram-Schmidt passes, then the Givens update of step j,
+  // run by an extra block of the preconditioner launch for the next basis vector (z_{j+1} =
+  // P v_{j+1}) or, at the last basis index, on its own; its reduction also stores the residual
+  // estimate and the cycle's tag in mapped host memory (c->hest), which the host polls.  The basis
+  // vectors are stored unnormalised: v_j = s_j x (stored V_j), s_j = 1 / |w| set by step j-1's
+  // norm reduction; the preconditioner and the pass coefficients take the scale, so no pass
+  // rescales the vector.  On entry Z_j holds z_j (from the previous step, or the cycle start).
   int arnoldi_step(int j, int m) {
     const int64_t n = c->nblock;
     double* V = c->kry;
     double* Z = c->kry + (int64_t)(m + 1) * n;
     double* hd = c->hdev;
     double* s = hd + 256;
-    double* Vj = V + (int64_t)j * n;
     double* Zj = Z + (int64_t)j * n;
     double* w = V + (int64_t)(j + 1) * n;
     int st;
-    if ((st = precond(Vj, Zj, w, s + j))) return st;
     if ((st = apply(Zj, w))) return st;
     // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1 fused with h2 = V^T w; w -= V h2
     const int slot = tstart(c, 3);
     if ((st = multidot_fused(c, V, n, j + 1, w, n, hd, s, hd + 480))) return st;
     if ((st = maxpy_multidot(c, w, V, n, j + 1, hd + 480, n, s, hd + 72, hd + 560))) return st;
-    // second update with the norm of w, the Givens update of step j and s_{j+1} in its final reduction
-    // (the residual estimate goes to the mapped host buffer hest from that reduction)
-    if ((st = multiaxpy_nrm_givens(c, w, V, n, j + 1, hd + 560, hd, -1.0, n, c->gmd, j, m, c->hest_dev))) return st;
+    GivensJob job;
+    if ((st = multiaxpy_nrm(c, w, V, n, j + 1, hd + 560, -1.0, n, hd, c->gmd, j, m, c->hest_dev, &job))) return st;
     tstop(c, slot);
-    return ILH_OK;
+    if (j + 1 < m) {
+      double* next = V + (int64_t)(j + 2) * n;
+      return precond(w, Z + (int64_t)(j + 1) * n, next, s + j + 1, &job);
+    }
+    return launch_sum_givens(c, job);
   }
 
   // Graph replay applies when every kernel of the step reads its varying inputs from device
@@ -1093,10 +1102,12 @@ struct Solver {
       c->qd_ok[0] = true;
     }
     while (true) {
-      // V0 = r / beta (beta to hd[240] for the Givens update, s_0 = 1, the cycle's tag to hd[255])
+      // V0 = r / beta (beta to hd[240] for the Givens update, s_0 = 1, the cycle's tag to hd[255]),
+      // z_0 = P V0
       const double tag = (c->est_tag += 1.0);
       hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd + 240, hd + 256, tag,
                          hd + 255);
+      if ((st = precond(V, Z, V + n))) return st;
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
       // read step jj's estimate; true when the cycle ends after it

@@ -421,30 +421,67 @@ __device__ void givens_update(double* h, double* G, int j, int m);
 // the cycle ends at that step).  The residual estimate also goes straight to host memory
 // (hest, mapped and coherent), followed by the cycle's tag h[255] at hest[128 + j], which the
 // host polls: no copy and no event are enqueued behind the step.
-__global__ void __launch_bounds__(TPB) k_sum_givens(const double* part, int np, double* h, double* G, int j, int m,
-                                                    double* hest) {
+__device__ __forceinline__ void sum_givens_block(const GivensJob& g) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < np; i += TPB) acc += part[i];
+  for (int i = threadIdx.x; i < g.np; i += TPB) acc += g.part[i];
   acc = block_sum<TPB>(acc);
   if (threadIdx.x == 0) {
+    double* h = g.h;
+    const int j = g.j;
     h[144] = acc;
-    givens_update(h, G, j, m);
+    givens_update(h, g.G, j, g.m);
     const double hn = sqrt(fmax(acc, 0.0));
     h[256 + j + 1] = (hn > 0.0 && hn <= 1.7e308) ? 1.0 / hn : 1.0;
-    if (hest) {
-      hest[2 * j] = h[352 + 2 * j];
-      hest[2 * j + 1] = h[353 + 2 * j];
+    if (g.hest) {
+      g.hest[2 * j] = h[352 + 2 * j];
+      g.hest[2 * j + 1] = h[353 + 2 * j];
       __threadfence_system();  // the estimate reaches the host before the tag
-      hest[128 + j] = h[255];
+      g.hest[128 + j] = h[255];
     }
   }
 }
 
-int multiaxpy_nrm_givens(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double* h,
-                         double sign, int64_t n, double* G, int j, int mm, double* hest) {
+__global__ void __launch_bounds__(TPB) k_sum_givens(const GivensJob g) { sum_givens_block(g); }
+
+// The scale 1 / |w| that sum_givens_block stores for the next basis vector, formed by a whole
+// block from the same partial sums in the same order (so every block obtains the same value)
+__device__ __forceinline__ double scale_from_partials(const double* part, int np) {
+  __shared__ double sh_sc;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += TPB) acc += part[i];
+  acc = block_sum<TPB>(acc);
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(fmax(acc, 0.0));
+    sh_sc = (hn > 0.0 && hn <= 1.7e308) ? 1.0 / hn : 1.0;
+  }
+  __syncthreads();
+  return sh_sc;
+}
+
+// y *= *s
+__global__ void k_scale_dev(double* y, const double* s, int64_t n) {
+  const double f = *s;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] *= f;
+}
+
+int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n) {
+  hipLaunchKernelGGL(k_scale_dev, dim3(nblk(n, 4096)), dim3(TPB), 0, c->stream, y, s, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double sign,
+                  int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job) {
   const int nb = fused_blocks(n);
   hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, sign, n, c->red);
-  hipLaunchKernelGGL(k_sum_givens, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, h, G, j, mm, hest);
+  ILH_HIP(c, hipGetLastError());
+  *job = GivensJob{c->red, nb, h, G, j, mm, hest};
+  return ILH_OK;
+}
+
+int launch_sum_givens(ilh_ctx* c, const GivensJob& job) {
+  hipLaunchKernelGGL(k_sum_givens, dim3(1), dim3(TPB), 0, c->stream, job);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -504,30 +541,24 @@ int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
   return ILH_OK;
 }
 
-// y *= *s
-__global__ void k_scale_dev(double* y, const double* s, int64_t n) {
-  const double f = *s;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] *= f;
-}
-
-int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n) {
-  hipLaunchKernelGGL(k_scale_dev, dim3(nblk(n, 4096)), dim3(TPB), 0, c->stream, y, s, n);
-  ILH_HIP(c, hipGetLastError());
-  return ILH_OK;
-}
-
 // Block preconditioner of the Newton-Krylov solve (eq. blockdiag_prec with a Jacobi M_V):
 // z_v = r_v / diag(M_V) (1 on constrained rows), z_x = r_x + tau z_v (coupled) or r_x,
-// z_e = M_E^-1 r_e; z32 (nullable) receives the FP32 copy of z.
+// z_e = M_E^-1 r_e; z32 (nullable) receives the FP32 copy of z.  The input is sc r with
+// sc = *rs (rs nullable: 1).  With g.part set, the grid has one block more, which runs the norm
+// reduction and Givens update of the previous Arnoldi step, and every other block forms the
+// scale that reduction stores, sc = 1 / |r|, from the same partial sums.
 __global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
                           const double* __restrict__ Minv, const double* __restrict__ escale, double* z, float* z32,
                           double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v,
-                          const double* tau_dev, const double* rs) {
+                          const double* tau_dev, const double* rs, const GivensJob g) {
+  if (g.part && blockIdx.x == gridDim.x - 1) {
+    sum_givens_block(g);
+    return;
+  }
+  const double sc = g.part ? scale_from_partials(g.part, g.np) : (rs ? *rs : 1.0);
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
-  const double sc = rs ? *rs : 1.0;  // the input is sc * r
   if (i < nh1) {
     const double zv = sc * r[nh1 + i] / Mdiag[i];
     const double zx = coupled ? tau * zv + sc * r[i] : sc * r[i];
@@ -549,10 +580,12 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
 }
 
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled, double* zero_v,
-                   const double* tau_dev, const double* rs) {
+                   const double* tau_dev, const double* rs, const GivensJob* job) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
-  hipLaunchKernelGGL(k_precond, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv,
-                     c->MEinv + c->Nl * c->Nl, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs);
+  const GivensJob g = job ? *job : GivensJob{};
+  const unsigned nb = (unsigned)((n + TPB - 1) / TPB) + (job ? 1u : 0u);
+  hipLaunchKernelGGL(k_precond, dim3(nb), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv, c->MEinv + c->Nl * c->Nl, z,
+                     z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs, g);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -694,15 +727,20 @@ int launch_invert_blocks(ilh_ctx* c, double* B) {
   return ILH_OK;
 }
 
-// z_v = r_v / D (probed diagonal), z_x = r_x + tau z_v (coupled) or r_x, z_e = Binv r_e per element
+// z_v = r_v / D (probed diagonal), z_x = r_x + tau z_v (coupled) or r_x, z_e = Binv r_e per element;
+// input scale and the extra last block as in k_precond
 __global__ void k_precond_probe(const double* __restrict__ r, const double* __restrict__ D,
                                 const double* __restrict__ Binv, double* z, float* z32, double tau, int coupled,
                                 int64_t nh1, int64_t Ne, int Nl, double* zero_v, const double* tau_dev,
-                                const double* rs) {
+                                const double* rs, const GivensJob g) {
+  if (g.part && blockIdx.x == gridDim.x - 1) {
+    sum_givens_block(g);
+    return;
+  }
+  const double sc = g.part ? scale_from_partials(g.part, g.np) : (rs ? *rs : 1.0);
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
-  const double sc = rs ? *rs : 1.0;  // the input is sc * r
   if (i < nh1) {
     const double zv = sc * r[nh1 + i] / D[i];
     const double zx = coupled ? tau * zv + sc * r[i] : sc * r[i];
@@ -725,10 +763,12 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
 }
 
 int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v, const double* tau_dev, const double* rs) {
+                         double* zero_v, const double* tau_dev, const double* rs, const GivensJob* job) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
-  hipLaunchKernelGGL(k_precond_probe, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, r, c->pdv,
-                     c->peinv, z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs);
+  const GivensJob g = job ? *job : GivensJob{};
+  const unsigned nb = (unsigned)((n + TPB - 1) / TPB) + (job ? 1u : 0u);
+  hipLaunchKernelGGL(k_precond_probe, dim3(nb), dim3(TPB), 0, c->stream, r, c->pdv, c->peinv, z, z32, tau, coupled,
+                     c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs, g);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
