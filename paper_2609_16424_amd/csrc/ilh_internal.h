@@ -130,6 +130,7 @@ struct ilh_ctx {
   std::vector<hipEvent_t> tev;  // pairs
   std::vector<int> tcls;
   int tused = 0;
+  int64_t tgen = 0;  // flushes so far (a pending slot index is valid within one generation)
   hipEvent_t xev0 = nullptr, xev1 = nullptr;  // open single-kernel slot, taken by the next klaunch
   double tms[ILH_TIMING_CLASSES] = {};
   int64_t tcnt[ILH_TIMING_CLASSES] = {};
@@ -152,6 +153,8 @@ int hip_fail(ilh_ctx* c, hipError_t e, const char* what);
 int tstart(ilh_ctx* c, int cls);
 void tstop(ilh_ctx* c, int slot);
 int tflush(ilh_ctx* c);
+// forget pending slot `slot` of generation `gen` (a launch that did no work), if still pending
+void tdrop(ilh_ctx* c, int slot, int64_t gen);
 // Single-kernel slot: the events are not recorded as stream markers but attached to the next
 // kernel launched through klaunch, so they bracket that dispatch alone.  tstop_k records both
 // (an empty interval) if no launch took them.
@@ -197,10 +200,14 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
 // device-side dot into d_out (no sync)
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
 // Arnoldi scalars: [0, 72) and [72, 144) the two Gram-Schmidt passes, 144 the norm, [160, 224)
-// the update coefficients, 240 beta, 250 tau, [256, 321) the basis scales s_j (basis vector j =
-// s_j x the stored vector), [352, 480) (|g_j+1|, h_j+1,j) per step, [480, 545) and [560, 625)
-// the two passes' coefficients times s_j (the coefficients of the stored vectors)
-constexpr int HDEV_LEN = 640;
+// the update coefficients, 240 beta, 250 tau, 252 the cycle's residual target, 255 the cycle's
+// tag, [256, 321) the basis scales s_j (basis vector j = s_j x the stored vector), [352, 480)
+// (|g_j+1|, h_j+1,j) per step, [480, 545) and [560, 625) the two passes' coefficients times s_j
+// (the coefficients of the stored vectors), [640, 704) the step-end flags: flag j (HDEV_FLAG + j)
+// is 1 when step j ended the cycle (residual estimate at most the target, or a zero norm), and
+// every kernel of step j + 1 then returns at once
+constexpr int HDEV_FLAG = 640;
+constexpr int HDEV_LEN = 704;
 // y = H(0:n, 0:n)^-1 g
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
 // Norm reduction and Givens update of Arnoldi step j: the partial sums of |w|^2 (part, np blocks),
@@ -215,6 +222,7 @@ struct GivensJob {
   int j = 0;
   int m = 0;
   double* hest = nullptr;
+  const double* skip = nullptr;  // nullable: nonzero *skip (the previous step's flag) skips the launch
 };
 int launch_sum_givens(ilh_ctx* c, const GivensJob& job);
 // y *= *s (s on the device)
@@ -222,11 +230,12 @@ int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n);
 int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
 // fused versions: w read once per 8 basis vectors.  d_out[j] = s_j V_j . w (s nullable: 1),
 // d_outs (nullable) [j] = s_j d_out[j]
+// skip (nullable, device): the launches return at once when *skip is nonzero
 int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out,
-                   const double* s = nullptr, double* d_outs = nullptr);
+                   const double* s = nullptr, double* d_outs = nullptr, const double* skip = nullptr);
 // w -= sum_j cf[j] V_j, then the products of the updated w as in multidot_fused
 int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, int64_t n,
-                   const double* s, double* d_out, double* d_outs);
+                   const double* s, double* d_out, double* d_outs, const double* skip = nullptr);
 // input *rs r (rs nullable: 1); job (nullable): run that Givens update in an extra block of the
 // same launch, the other blocks then form the scale it stores (1 / |r|) from its partial sums
 int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
@@ -246,8 +255,11 @@ int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, dou
 // h[72..72+j], and the next basis scale h[256 + j + 1] = 1 / |w|; hest (nullable, host-mapped)
 // receives the step's (|g_j+1|, h_j+1,j) at [2j, 2j + 1] and the cycle's tag at [128 + j])
 int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double sign,
-                  int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job);
-int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev);
+                  int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job,
+                  const double* skip = nullptr);
+// (skip nullable: the kernel returns at once when *skip is nonzero)
+int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev,
+                           const double* skip = nullptr);
 // Stage residual on the strip lane maps (2D k = 2, 3; 3D k = 2 without the TG source):
 // r = R(k; u, tau), the velocity rows of r zero on entry
 bool res2d_available(const ilh_ctx* c);

@@ -171,7 +171,9 @@ template <int D1D, int Q1D, typename T, int VISC, int SRC, typename TO, int W>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VISC && sizeof(T) == 8 ? 1 : 2))) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
                                                 const T* __restrict__ dk, const T* __restrict__ qd,
                                                 int64_t qs, double tau_, TO* __restrict__ out, int R,
-                                                const double* __restrict__ tau_dev) {
+                                                const double* __restrict__ tau_dev,
+                                                const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;  // the Krylov cycle ended at the previous step
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
@@ -496,19 +498,19 @@ static int apply_waves(const ilh_ctx* c, bool fp32) {
 }
 
 template <int K, typename T, int VISC, int SRC, typename TO>
-static void apply_t(ilh_ctx* c, const T* dk, const T* qd, TO* out, const double* tau_dev) {
+static void apply_t(ilh_ctx* c, const T* dk, const T* qd, TO* out, const double* tau_dev, const double* skip) {
   constexpr int D1D = K + 1, Q1D = 2 * K;
   const int R = apply_rows(c);
   const dim3 g = lin2d_grid(c), grid(g.x, (g.y + R - 1) / R);
   if constexpr (sizeof(T) == 4) {
     if (apply_waves(c, true) == 2) {
       klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 2>, grid, dim3(128), 0, c->kp, make_tab2<T, D1D, Q1D>(c),
-              dk, qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev);
+              dk, qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev, skip);
       return;
     }
   }
   klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 1>, grid, dim3(64), 0, c->kp, make_tab2<T, D1D, Q1D>(c), dk,
-          qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev);
+          qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev, skip);
 }
 
 template <typename T>
@@ -530,17 +532,18 @@ static int dispatch_lin(ilh_ctx* c, T* qd) {
 }
 
 template <typename T, typename TO>
-static int dispatch_apply(ilh_ctx* c, const T* dk, const T* qd, TO* out, const double* tau_dev = nullptr) {
+static int dispatch_apply(ilh_ctx* c, const T* dk, const T* qd, TO* out, const double* tau_dev = nullptr,
+                          const double* skip = nullptr) {
   const int v = c->kp.visc ? 1 : 0, s = c->kp.tg_source ? 1 : 0, code = 4 * c->k + 2 * v + s;
   switch (code) {
-    case 8: apply_t<2, T, 0, 0, TO>(c, dk, qd, out, tau_dev); break;
-    case 9: apply_t<2, T, 0, 1, TO>(c, dk, qd, out, tau_dev); break;
-    case 10: apply_t<2, T, 1, 0, TO>(c, dk, qd, out, tau_dev); break;
-    case 11: apply_t<2, T, 1, 1, TO>(c, dk, qd, out, tau_dev); break;
-    case 12: apply_t<3, T, 0, 0, TO>(c, dk, qd, out, tau_dev); break;
-    case 13: apply_t<3, T, 0, 1, TO>(c, dk, qd, out, tau_dev); break;
-    case 14: apply_t<3, T, 1, 0, TO>(c, dk, qd, out, tau_dev); break;
-    case 15: apply_t<3, T, 1, 1, TO>(c, dk, qd, out, tau_dev); break;
+    case 8: apply_t<2, T, 0, 0, TO>(c, dk, qd, out, tau_dev, skip); break;
+    case 9: apply_t<2, T, 0, 1, TO>(c, dk, qd, out, tau_dev, skip); break;
+    case 10: apply_t<2, T, 1, 0, TO>(c, dk, qd, out, tau_dev, skip); break;
+    case 11: apply_t<2, T, 1, 1, TO>(c, dk, qd, out, tau_dev, skip); break;
+    case 12: apply_t<3, T, 0, 0, TO>(c, dk, qd, out, tau_dev, skip); break;
+    case 13: apply_t<3, T, 0, 1, TO>(c, dk, qd, out, tau_dev, skip); break;
+    case 14: apply_t<3, T, 1, 0, TO>(c, dk, qd, out, tau_dev, skip); break;
+    case 15: apply_t<3, T, 1, 1, TO>(c, dk, qd, out, tau_dev, skip); break;
     default: return ILH_EINVAL;
   }
   ILH_HIP(c, hipGetLastError());
@@ -567,10 +570,10 @@ int launch_jvp2d_q(ilh_ctx* c, int prec, const void* dk, void* out) {
 
 // FP32 action written straight into an FP64 vector (the Krylov basis): the velocity rows of out
 // must be zero on entry, the FP32 coefficients current.
-int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev) {
+int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev, const double* skip) {
   if (!lin2d_supported(c)) return ILH_EINVAL;
   if (!c->qd[0] || !c->qd_ok[0]) return fail(c, ILH_EINVAL, "linearised Jacobian action before its linearisation");
-  return dispatch_apply<float, double>(c, dk, (const float*)c->qd[0], out, tau_dev);
+  return dispatch_apply<float, double>(c, dk, (const float*)c->qd[0], out, tau_dev, skip);
 }
 
 bool lin2d_available(const ilh_ctx* c) { return lin2d_supported(c); }

@@ -128,13 +128,19 @@ int tflush(ilh_ctx* c) {
   if (c->tused == 0) return ILH_OK;
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   for (int i = 0; i < c->tused; ++i) {
+    if (c->tcls[i] < 0) continue;  // dropped
     float ms = 0.f;
     ILH_HIP(c, hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]));
     c->tms[c->tcls[i]] += ms;
     c->tcnt[c->tcls[i]] += 1;
   }
   c->tused = 0;
+  ++c->tgen;
   return ILH_OK;
+}
+
+void tdrop(ilh_ctx* c, int slot, int64_t gen) {
+  if (slot >= 0 && gen == c->tgen && slot < c->tused) c->tcls[slot] = -1;
 }
 
 int tstart(ilh_ctx* c, int cls) {
@@ -849,13 +855,16 @@ static int read_pair(ilh_ctx* c, double* a, double* b) {
 
 // y = x / beta; beta is also stored to *beta_out, the scale of the stored vector y, 1, to *s0
 // and the FGMRES cycle's tag to *tag_out
-__global__ void k_scale_copy(double* y, const double* x, double beta, int64_t n, double* beta_out, double* s0,
-                             double tag, double* tag_out) {
+// y = x / beta with the cycle's Arnoldi scalars: h[240] = beta, h[252] = the residual target,
+// h[255] = the cycle's tag, s_0 = h[256] = 1
+__global__ void k_scale_copy(double* y, const double* x, double beta, int64_t n, double* h, double target,
+                             double tag) {
   const double f = 1.0 / beta;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *beta_out = beta;
-    *s0 = 1.0;
-    *tag_out = tag;
+    h[240] = beta;
+    h[252] = target;
+    h[255] = tag;
+    h[256] = 1.0;
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = x[i] * f;
@@ -950,9 +959,22 @@ struct Solver {
     return ILH_OK;
   }
 
-  int apply(const double* x, double* y) {
+  // skip (nullable, device): used by the FP32 action written straight into the Krylov basis,
+  // which returns at once when *skip is nonzero
+  bool skippable = false;  // the last action was one that a set flag turns into no work
+  int skip_slot = -1;      // its timer slot and generation
+  int64_t skip_gen = -1;
+  // the last action did no work (its step's flag was set): neither counted nor timed
+  void drop_skipped() {
+    if (!skippable) return;
+    --jvp_calls;
+    tdrop(c, skip_slot, skip_gen);
+    skippable = false;
+  }
+  int apply(const double* x, double* y, const double* skip = nullptr) {
     int st;
     ++jvp_calls;
+    skippable = false;
     if (o->jvp_prec == 32) {
       float* x32 = c->kry32;
       float* y32 = c->kry32 + c->nblock;
@@ -970,8 +992,11 @@ struct Solver {
           c->qd_ok[0] = true;
         }
         const int slot = tstart_k(c, 0);
-        st = launch_jvp2d_q_f32to64(c, x32, y, c->hdev + 250);
+        st = launch_jvp2d_q_f32to64(c, x32, y, c->hdev + 250, skip);
         tstop_k(c, slot);
+        skippable = skip != nullptr;
+        skip_slot = slot;
+        skip_gen = c->tgen;
         return st;
       }
       if (!have32 && (st = launch_cast_d2f(c, x32, x, c->nblock))) return st;
@@ -988,6 +1013,8 @@ struct Solver {
   // vectors are stored unnormalised: v_j = s_j x (stored V_j), s_j = 1 / |w| set by step j-1's
   // norm reduction; the preconditioner and the pass coefficients take the scale, so no pass
   // rescales the vector.  On entry Z_j holds z_j (from the previous step, or the cycle start).
+  // Every launch of step j > 0 reads step j-1's end flag and does nothing when it is set (the
+  // host enqueues step j before it reads step j-1's estimate).
   int arnoldi_step(int j, int m) {
     const int64_t n = c->nblock;
     double* V = c->kry;
@@ -996,14 +1023,16 @@ struct Solver {
     double* s = hd + 256;
     double* Zj = Z + (int64_t)j * n;
     double* w = V + (int64_t)(j + 1) * n;
+    const double* skip = j > 0 ? hd + HDEV_FLAG + j - 1 : nullptr;
     int st;
-    if ((st = apply(Zj, w))) return st;
+    if ((st = apply(Zj, w, skip))) return st;
     // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1 fused with h2 = V^T w; w -= V h2
     const int slot = tstart(c, 3);
-    if ((st = multidot_fused(c, V, n, j + 1, w, n, hd, s, hd + 480))) return st;
-    if ((st = maxpy_multidot(c, w, V, n, j + 1, hd + 480, n, s, hd + 72, hd + 560))) return st;
+    if ((st = multidot_fused(c, V, n, j + 1, w, n, hd, s, hd + 480, skip))) return st;
+    if ((st = maxpy_multidot(c, w, V, n, j + 1, hd + 480, n, s, hd + 72, hd + 560, skip))) return st;
     GivensJob job;
-    if ((st = multiaxpy_nrm(c, w, V, n, j + 1, hd + 560, -1.0, n, hd, c->gmd, j, m, c->hest_dev, &job))) return st;
+    if ((st = multiaxpy_nrm(c, w, V, n, j + 1, hd + 560, -1.0, n, hd, c->gmd, j, m, c->hest_dev, &job, skip)))
+      return st;
     tstop(c, slot);
     if (j + 1 < m) {
       double* next = V + (int64_t)(j + 2) * n;
@@ -1072,9 +1101,10 @@ struct Solver {
   // The Givens rotations, the residual estimate and the triangular solve run on the device;
   // the host enqueues Arnoldi step j before it reads step j-1's residual estimate (stored by
   // the device in mapped host memory and tagged per cycle), so the stream never drains between
-  // steps.  A step enqueued after the
-  // one that converged is discarded: it only touches V_{j+1}, Z_j, column j and g_j, g_{j+1},
-  // none of which the solution over the first j columns reads.
+  // steps.  A step enqueued after the one that ended the cycle is discarded: its launches return
+  // at once on that step's end flag (and where the host alone ends the cycle, at the iteration
+  // limit, it only touches V_{j+1}, Z_j, column j and g_j, g_{j+1}, none of which the solution
+  // over the first j columns reads).
   int fgmres(const double* b, double* x, int* its, double beta_b = -1.0) {
     const int64_t n = c->nblock;
     const int m = std::max(1, std::min(o->restart, 64));
@@ -1102,14 +1132,13 @@ struct Solver {
       c->qd_ok[0] = true;
     }
     while (true) {
-      // V0 = r / beta (beta to hd[240] for the Givens update, s_0 = 1, the cycle's tag to hd[255]),
-      // z_0 = P V0
+      // V0 = r / beta (beta, the target and the cycle's tag to the device), z_0 = P V0
       const double tag = (c->est_tag += 1.0);
-      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd + 240, hd + 256, tag,
-                         hd + 255);
+      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd, target, tag);
       if ((st = precond(V, Z, V + n))) return st;
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
+      bool dev_end = false;  // the step's end flag is set on the device
       // read step jj's estimate; true when the cycle ends after it
       auto check = [&](int jj, bool& end) -> int {
         // wait for the tag the step's reduction stores after its estimate; the stream running
@@ -1133,6 +1162,7 @@ struct Solver {
         ++total;
         stop = res <= target || total >= o->gmres_maxit;
         end = stop || hn == 0.0;
+        dev_end = res <= target || hn == 0.0;  // the test the device made (its end flag)
         return ILH_OK;
       };
       bool end = false;
@@ -1142,12 +1172,17 @@ struct Solver {
           if ((st = graph_for(j, m, &ex))) return st;
           ILH_HIP(c, hipGraphLaunch(ex, c->stream));
           ++jvp_calls;
+          skippable = j > 0;  // timing is off in graph replay
+          skip_slot = -1;
         } else if ((st = arnoldi_step(j, m))) {
           return st;
         }
         if (j >= 1) {
           if ((st = check(j - 1, end))) return st;
-          if (end) j_end = j;  // step j was speculative
+          if (end) {
+            j_end = j;  // step j was speculative
+            if (dev_end) drop_skipped();  // and its launches returned at once
+          }
         }
       }
       if (!end) {  // the cycle filled the basis: read its last step

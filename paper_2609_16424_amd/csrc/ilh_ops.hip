@@ -185,7 +185,8 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
 // out[j] = s_j sum_b part[j][b] (s = null: s_j = 1); outs (nullable) receives s_j out[j], the
 // coefficient of the stored vector when V_j = s_j x (stored vector)
 __global__ void __launch_bounds__(TPB) k_mdot_final(const double* part, int nb, int m, double* out,
-                                                    const double* s, double* outs) {
+                                                    const double* s, double* outs, const double* skip) {
+  if (skip && *skip != 0.0) return;
   const int j = blockIdx.x;
   double acc = 0;
   for (int i = threadIdx.x; i < nb; i += TPB) acc += part[(int64_t)j * nb + i];
@@ -285,7 +286,9 @@ __device__ __forceinline__ void store_block_sums(const double (&acc)[JC], int j0
 
 // part[j][b] = block b's share of V_j . w, j < m (w read once per MDOT_JC vectors)
 __global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V, int64_t ldv, int m,
-                                                    const double* __restrict__ w, int64_t n, double* part) {
+                                                    const double* __restrict__ w, int64_t n, double* part,
+                                                    const double* skip) {
+  if (skip && *skip != 0.0) return;
   const int64_t stride = (int64_t)gridDim.x * KTILE;
   for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
     double acc[MDOT_JC];
@@ -309,7 +312,8 @@ __global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V
 // thread revisits only its own indices, so the later chunks read back its own updates.
 __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k_maxpy_mdot_part(double* __restrict__ w, const double* __restrict__ V,
                                                          int64_t ldv, int m, const double* __restrict__ cf,
-                                                         int64_t n, double* part) {
+                                                         int64_t n, double* part, const double* skip) {
+  if (skip && *skip != 0.0) return;
   const int64_t stride = (int64_t)gridDim.x * KTILE;
   for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
     double acc[MDOT_JC];
@@ -364,7 +368,9 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k
 // w += sign sum_j h[j] V_j; part[b] = block b's share of |w|^2 of the result
 __global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(double* __restrict__ w, const double* __restrict__ V,
                                                         int64_t ldv, int m, const double* __restrict__ h,
-                                                        double sign, int64_t n, double* part) {
+                                                        double sign, int64_t n, double* part,
+                                                        const double* skip) {
+  if (skip && *skip != 0.0) return;
   double ss = 0.0;
   const int64_t stride = (int64_t)gridDim.x * KTILE;
   for (int64_t t0 = (int64_t)blockIdx.x * KTILE; t0 < n; t0 += stride) {
@@ -393,23 +399,23 @@ static int fused_blocks(int64_t n) {
 }
 
 int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out,
-                   const double* s, double* d_outs) {
+                   const double* s, double* d_outs, const double* skip) {
   if (m <= 0) return ILH_OK;
   if (m > 64) return fail(c, ILH_EINVAL, "multidot: at most 64 vectors");
   const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_mdot_part8, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red);
-  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs);
+  hipLaunchKernelGGL(k_mdot_part8, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red, skip);
+  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs, skip);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
 
 int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, int64_t n,
-                   const double* s, double* d_out, double* d_outs) {
+                   const double* s, double* d_out, double* d_outs, const double* skip) {
   if (m <= 0) return ILH_OK;
   if (m > 64) return fail(c, ILH_EINVAL, "multidot: at most 64 vectors");
   const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_maxpy_mdot_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, n, c->red);
-  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs);
+  hipLaunchKernelGGL(k_maxpy_mdot_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, n, c->red, skip);
+  hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs, skip);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -422,6 +428,7 @@ __device__ void givens_update(double* h, double* G, int j, int m);
 // (hest, mapped and coherent), followed by the cycle's tag h[255] at hest[128 + j], which the
 // host polls: no copy and no event are enqueued behind the step.
 __device__ __forceinline__ void sum_givens_block(const GivensJob& g) {
+  if (g.skip && *g.skip != 0.0) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < g.np; i += TPB) acc += g.part[i];
   acc = block_sum<TPB>(acc);
@@ -432,6 +439,9 @@ __device__ __forceinline__ void sum_givens_block(const GivensJob& g) {
     givens_update(h, g.G, j, g.m);
     const double hn = sqrt(fmax(acc, 0.0));
     h[256 + j + 1] = (hn > 0.0 && hn <= 1.7e308) ? 1.0 / hn : 1.0;
+    // the end test the host makes on the same two numbers (estimate at most the target, or a
+    // zero norm), so a step the host discards does no work
+    h[HDEV_FLAG + j] = (h[352 + 2 * j] <= h[252] || h[353 + 2 * j] == 0.0) ? 1.0 : 0.0;
     if (g.hest) {
       g.hest[2 * j] = h[352 + 2 * j];
       g.hest[2 * j + 1] = h[353 + 2 * j];
@@ -472,11 +482,12 @@ int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n) {
 }
 
 int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double sign,
-                  int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job) {
+                  int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job,
+                  const double* skip) {
   const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, sign, n, c->red);
+  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, sign, n, c->red, skip);
   ILH_HIP(c, hipGetLastError());
-  *job = GivensJob{c->red, nb, h, G, j, mm, hest};
+  *job = GivensJob{c->red, nb, h, G, j, mm, hest, skip};
   return ILH_OK;
 }
 
@@ -551,6 +562,7 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
                           const double* __restrict__ Minv, const double* __restrict__ escale, double* z, float* z32,
                           double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v,
                           const double* tau_dev, const double* rs, const GivensJob g) {
+  if (g.skip && *g.skip != 0.0) return;
   if (g.part && blockIdx.x == gridDim.x - 1) {
     sum_givens_block(g);
     return;
@@ -733,6 +745,7 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
                                 const double* __restrict__ Binv, double* z, float* z32, double tau, int coupled,
                                 int64_t nh1, int64_t Ne, int Nl, double* zero_v, const double* tau_dev,
                                 const double* rs, const GivensJob g) {
+  if (g.skip && *g.skip != 0.0) return;
   if (g.part && blockIdx.x == gridDim.x - 1) {
     sum_givens_block(g);
     return;
