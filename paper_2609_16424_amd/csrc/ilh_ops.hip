@@ -420,7 +420,8 @@ int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, c
   return ILH_OK;
 }
 
-__device__ void givens_update(double* h, double* G, int j, int m);
+__device__ void givens_update(double* h, double* G, int j, int m, const double* csl, const double* snl,
+                              const double* coll);
 
 // final sum of the norm partials into h[144], the Givens update of Arnoldi step j, and the
 // scale of the next basis vector, h[256 + j + 1] = 1 / |w| (1 for a zero or non-finite norm:
@@ -429,14 +430,23 @@ __device__ void givens_update(double* h, double* G, int j, int m);
 // host polls: no copy and no event are enqueued behind the step.
 __device__ __forceinline__ void sum_givens_block(const GivensJob& g) {
   if (g.skip && *g.skip != 0.0) return;
+  // the earlier rotations and the new Hessenberg column go to LDS while the partials are summed,
+  // so the one thread that applies the rotations reads no global memory in its chain
+  __shared__ double csl[64], snl[64], coll[64];
+  double* h = g.h;
+  const int j = g.j;
+  const double* cs = g.G + 64 * 64;
+  if ((int)threadIdx.x < j) {
+    csl[threadIdx.x] = cs[threadIdx.x];
+    snl[threadIdx.x] = cs[64 + threadIdx.x];
+  }
+  if ((int)threadIdx.x <= j) coll[threadIdx.x] = h[threadIdx.x] + h[72 + threadIdx.x];
   double acc = 0.0;
   for (int i = threadIdx.x; i < g.np; i += TPB) acc += g.part[i];
-  acc = block_sum<TPB>(acc);
+  acc = block_sum<TPB>(acc);  // its barriers also publish the LDS stores
   if (threadIdx.x == 0) {
-    double* h = g.h;
-    const int j = g.j;
     h[144] = acc;
-    givens_update(h, g.G, j, g.m);
+    givens_update(h, g.G, j, g.m, csl, snl, coll);
     const double hn = sqrt(fmax(acc, 0.0));
     h[256 + j + 1] = (hn > 0.0 && hn <= 1.7e308) ? 1.0 / hn : 1.0;
     // the end test the host makes on the same two numbers (estimate at most the target, or a
@@ -499,12 +509,14 @@ int launch_sum_givens(ilh_ctx* c, const GivensJob& job) {
 
 
 // Givens update of Arnoldi step j on the device (one thread; j < m <= 64).  Column j of the
-// Hessenberg matrix is the sum of the two Gram-Schmidt passes (h[0..j], h[72..72+j]) with
+// Hessenberg matrix is the sum of the two Gram-Schmidt passes (coll[0..j] = h[0..j] +
+// h[72..72+j], staged by the caller with the earlier rotations csl, snl = cs[0..j), sn[0..j)) with
 // h_{j+1,j} = sqrt(h[144]); the earlier rotations are applied to it, the new one is formed and
 // applied to the right-hand side g (g = beta e_1 at j = 0, beta in h[240]); the residual
 // estimate |g_{j+1}| and h_{j+1,j} go to h[352 + 2j], h[353 + 2j].
 // G layout: H [64][64] row-major (upper triangle after the rotations), cs [64], sn [64], g [65].
-__device__ void givens_update(double* h, double* G, int j, int m) {
+__device__ void givens_update(double* h, double* G, int j, int m, const double* csl, const double* snl,
+                              const double* coll) {
   double* H = G;
   double* cs = G + 64 * 64;
   double* sn = cs + 64;
@@ -514,11 +526,11 @@ __device__ void givens_update(double* h, double* G, int j, int m) {
     for (int i = 1; i <= m; ++i) g[i] = 0.0;
   }
   const double hn = sqrt(fmax(h[144], 0.0));
-  double cur = h[0] + h[72];
+  double cur = coll[0];
   for (int i = 0; i < j; ++i) {
-    const double nx = h[i + 1] + h[72 + i + 1];
-    H[i * 64 + j] = cs[i] * cur + sn[i] * nx;
-    cur = -sn[i] * cur + cs[i] * nx;
+    const double nx = coll[i + 1];
+    H[i * 64 + j] = csl[i] * cur + snl[i] * nx;
+    cur = -snl[i] * cur + csl[i] * nx;
   }
   const double den = hypot(cur, hn);
   const double c_ = den > 0 ? cur / den : 1.0, s_ = den > 0 ? hn / den : 0.0;
@@ -555,7 +567,7 @@ int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
 // Block preconditioner of the Newton-Krylov solve (eq. blockdiag_prec with a Jacobi M_V):
 // z_v = r_v / diag(M_V) (1 on constrained rows), z_x = r_x + tau z_v (coupled) or r_x,
 // z_e = M_E^-1 r_e; z32 (nullable) receives the FP32 copy of z.  The input is sc r with
-// sc = *rs (rs nullable: 1).  With g.part set, the grid has one block more, which runs the norm
+// sc = *rs (rs nullable: 1).  With g.part set, the grid has one block more, block 0, which runs the norm
 // reduction and Givens update of the previous Arnoldi step, and every other block forms the
 // scale that reduction stores, sc = 1 / |r|, from the same partial sums.
 __global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
@@ -563,12 +575,12 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
                           double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v,
                           const double* tau_dev, const double* rs, const GivensJob g) {
   if (g.skip && *g.skip != 0.0) return;
-  if (g.part && blockIdx.x == gridDim.x - 1) {
+  if (g.part && blockIdx.x == 0) {  // first, so its serial chain overlaps the rest of the grid
     sum_givens_block(g);
     return;
   }
   const double sc = g.part ? scale_from_partials(g.part, g.np) : (rs ? *rs : 1.0);
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x - (g.part ? 1 : 0)) * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
   if (i < nh1) {
@@ -746,12 +758,12 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
                                 int64_t nh1, int64_t Ne, int Nl, double* zero_v, const double* tau_dev,
                                 const double* rs, const GivensJob g) {
   if (g.skip && *g.skip != 0.0) return;
-  if (g.part && blockIdx.x == gridDim.x - 1) {
+  if (g.part && blockIdx.x == 0) {  // first, so its serial chain overlaps the rest of the grid
     sum_givens_block(g);
     return;
   }
   const double sc = g.part ? scale_from_partials(g.part, g.np) : (rs ? *rs : 1.0);
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x - (g.part ? 1 : 0)) * (int64_t)blockDim.x + threadIdx.x;
   if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
   if (i < nh1) {
