@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 # reported as null.
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": "30af196afab503ffa3d76e43589a86fd7c8eda40d3244050794570bbf9437368",
+TRAFFIC_RECORD = {"sha256": "42eaca74a82b5b88fd054849b9be92583f2db95ffb9cb8ea4933ae9c746bb0cf",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16586.1, "fetch_scale": 262144.0 / 131082.2,
-                  "write_kib": 7084.6, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 16587.2, "fetch_scale": 262144.0 / 131081.3,
+                  "write_kib": 7084.5, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
@@ -58,7 +58,7 @@ def sources_sha256():
 # VALU instructions per launch of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU, same sources):
 # the issue peak of wave64 FP32 (unpacked) / FP64 VALU instructions is 1024 SIMDs x 2.4 GHz / 4.
 VALU_RECORD = {"sha256": TRAFFIC_RECORD["sha256"], "variant": "lin", "n": 128, "order": 3,
-               "instructions": 2620405.0}
+               "instructions": 2621791.7}
 VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
