@@ -92,6 +92,7 @@ struct ilh_ctx {
   double lin_tau = 0.0;
   // reduction scratch
   double* red = nullptr;        // device partials
+  double* dmin_part = nullptr;  // per-work-group det J minima of the strip residual
   double* red_host = nullptr;   // pinned host
   int red_blocks = 1024;
   // solver workspace
@@ -263,7 +264,12 @@ int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const doubl
 // Stage residual on the strip lane maps (2D k = 2, 3; 3D k = 2 without the TG source):
 // r = R(k; u, tau), the velocity rows of r zero on entry
 bool res2d_available(const ilh_ctx* c);
-int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r);
+// dmin (nullable, res2d_groups(c) entries): each work-group's smallest det J over its quadrature
+// points at the stage positions u_x + tau k_x
+int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin = nullptr);
+int res2d_groups(const ilh_ctx* c);
+// *out = min_i part[i], i < np (device)
+int launch_min_final(ilh_ctx* c, const double* part, int np, double* out);
 bool res3d_available(const ilh_ctx* c);
 int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, double* r);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);

@@ -274,7 +274,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
-                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres};
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres, c->dmin_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : c->qd)
@@ -606,6 +606,20 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   }
   tstop_k(c, slot);
   return st;
+}
+
+// The strip residual with the smallest det J of the stage positions in *d_min (device), one
+// pass for both; false (nothing launched) where no strip residual kernel applies
+static bool residual_detj_available(const ilh_ctx* c) { return c->jvp_variant != 1 && res2d_available(c); }
+static int residual_detj(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* d_min) {
+  int st;
+  if (!c->dmin_part && (st = dalloc(c, &c->dmin_part, (size_t)res2d_groups(c)))) return st;
+  if ((st = launch_fill(c, r + c->nh1, 0.0, c->nh1))) return st;
+  const int slot = tstart_k(c, 1);
+  st = launch_res2d(c, k, u, tau, r, c->dmin_part);
+  tstop_k(c, slot);
+  if (st) return st;
+  return launch_min_final(c, c->dmin_part, res2d_groups(c), d_min);
 }
 
 int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
@@ -1291,11 +1305,15 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
     bool ok = false, any_valid = false;
     for (int h = 0; h <= o->max_halvings; ++h) {
       if ((st = launch_waxpy(c, kt, k, alpha, dk, n))) return st;
-      if ((st = launch_waxpy(c, trial, u, tau, kt, c->nh1))) return st;
       // the trial residual is formed before det J > 0 is known (it is discarded otherwise), so
-      // that one synchronisation reads both
-      if ((st = min_detj_dev(c, trial, dsc))) return st;
-      if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
+      // that one synchronisation reads both; the strip residual kernel returns det J itself
+      if (residual_detj_available(c)) {
+        if ((st = residual_detj(c, kt, u, tau, rt, dsc))) return st;
+      } else {
+        if ((st = launch_waxpy(c, trial, u, tau, kt, c->nh1))) return st;
+        if ((st = min_detj_dev(c, trial, dsc))) return st;
+        if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
+      }
       if ((st = dot_dev(c, rt, rt, n, dsc + 1))) return st;
       double md, nrt2;
       if ((st = read_pair(c, &md, &nrt2))) return st;

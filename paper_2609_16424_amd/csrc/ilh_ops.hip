@@ -159,6 +159,12 @@ __global__ void __launch_bounds__(TPB) k_sum_final(const double* part, int np, d
   if (threadIdx.x == 0) *out = acc;
 }
 
+int launch_min_final(ilh_ctx* c, const double* part, int np, double* out) {
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, part, np, out, 1);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
 static int red_blocks(ilh_ctx* c, int64_t n) {
   int b = (int)std::min<int64_t>((n + TPB - 1) / TPB, c->red_blocks);
   return b < 1 ? 1 : b;

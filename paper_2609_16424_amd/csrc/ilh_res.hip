@@ -30,7 +30,7 @@ __device__ __forceinline__ double tg_source_c(double x, double y, double gam) {
 template <int D1D, int Q1D, int SRC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restrict__ u,
-        const double* __restrict__ kk, double tau, double* __restrict__ r) {
+        const double* __restrict__ kk, double tau, double* __restrict__ r, double* __restrict__ dmin) {
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
@@ -120,6 +120,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
   double TL[L1D];
 #pragma unroll
   for (int bl = 0; bl < L1D; ++bl) TL[bl] = 0.0;
+  double dm = 1e300;  // the lane's smallest det J (dmin set)
   if (active) {
     const int s0 = K * z;
     double Bq[D1D], Gq[D1D], BLq[L1D];
@@ -203,6 +204,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
         ke += tb.BL[qy][bl] * ALk[bl];
       }
       const double mq = wx * tb.W[qy];
+      if (dmin) dm = fmin(dm, J[0][0] * J[1][1] - J[0][1] * J[1][0]);
       double S[2][2], sq;
       qp_force<2, double>(P, gam, mq, dJ0, J, Gv, eq, S, sq);
       double cl = mq * ke - sq;
@@ -232,6 +234,11 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
           sO[lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
   }
   __syncthreads();
+  if (dmin) {  // the work-group's smallest det J of the stage positions w_x
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmin(dm, __shfl_xor(dm, o, 64));
+    if (lane == 0) dmin[blockIdx.y * gridDim.x + blockIdx.x] = dm;
+  }
 
   // velocity rows that are not constrained: the Q1D columns of the (one or two) elements of the
   // strip that hold the node, one atomic add per node and strip
@@ -573,7 +580,7 @@ bool res3d_available(const ilh_ctx* c) {
 }
 
 template <int K, int SRC>
-static void res_t(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
+static void res_t(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin) {
   constexpr int D1D = K + 1, Q1D = 2 * K, EPW = 64 / Q1D;
   Tab2<double, D1D, Q1D> tb;
   for (int q = 0; q < Q1D; ++q) {
@@ -585,7 +592,7 @@ static void res_t(ilh_ctx* c, const double* k, const double* u, double tau, doub
     tb.W[q] = c->h_w1[q];
   }
   const dim3 grid((c->n[0] + EPW - 1) / EPW, c->n[1]);
-  klaunch(c, k_res2d<D1D, Q1D, SRC>, grid, dim3(64), 0, c->kp, tb, u, k, tau, r);
+  klaunch(c, k_res2d<D1D, Q1D, SRC>, grid, dim3(64), 0, c->kp, tb, u, k, tau, r, dmin);
 }
 
 // r = R(k; u, tau); the velocity rows of r must be zero on entry
@@ -607,15 +614,20 @@ int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   return ILH_OK;
 }
 
+int res2d_groups(const ilh_ctx* c) {
+  const int EPW = 64 / (2 * c->k);
+  return ((c->n[0] + EPW - 1) / EPW) * c->n[1];
+}
+
 // r = R(k; u, tau); the velocity rows of r must be zero on entry
-int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
+int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin) {
   if (!res2d_available(c)) return ILH_EINVAL;
   const int code = 2 * c->k + (c->kp.tg_source ? 1 : 0);
   switch (code) {
-    case 4: res_t<2, 0>(c, k, u, tau, r); break;
-    case 5: res_t<2, 1>(c, k, u, tau, r); break;
-    case 6: res_t<3, 0>(c, k, u, tau, r); break;
-    case 7: res_t<3, 1>(c, k, u, tau, r); break;
+    case 4: res_t<2, 0>(c, k, u, tau, r, dmin); break;
+    case 5: res_t<2, 1>(c, k, u, tau, r, dmin); break;
+    case 6: res_t<3, 0>(c, k, u, tau, r, dmin); break;
+    case 7: res_t<3, 1>(c, k, u, tau, r, dmin); break;
     default: return ILH_EINVAL;
   }
   ILH_HIP(c, hipGetLastError());
