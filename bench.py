@@ -40,9 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # reported as null.
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": "42eaca74a82b5b88fd054849b9be92583f2db95ffb9cb8ea4933ae9c746bb0cf",
+TRAFFIC_RECORD = {"sha256": "9b6a8c3ee70f8b4fa5b81b69f38898e40f15a3e217accd8f8879e4bb99a6290c",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16587.2, "fetch_scale": 262144.0 / 131081.3,
+                  "fetch_kib": 16586.6, "fetch_scale": 262144.0 / 131081.2,
                   "write_kib": 7084.5, "write_scale": 262144.0 / 262144.0}
 
 
