@@ -49,6 +49,30 @@ def test_stage_failure_paths():
     assert torch.equal(uu, u)  # state untouched on failure
 
 
+def test_line_search_tangling_decision_matches_oracle():
+    """At dt = 2 on the 4x4 Q2 Taylor-Green mesh the full first Newton step of the oracle tangles
+    the stage mesh (no halving allowed: ETANGLED) and halving lets it go on.  The GPU line search,
+    whose det J comes out of the strip residual kernel, takes the same decisions: ETANGLED
+    without halvings, and at least one halving in its first iteration with them."""
+    from oracle import krylov
+    O, G = make_pair("tg2d", (4, 4), 2)
+    u0 = O.init_state()
+    with pytest.raises(krylov.NewtonFailure) as e:
+        krylov.implicit_midpoint_step(O, u0, 2.0, np.zeros_like(u0), krylov.NewtonOptions(max_halvings=0))
+    assert e.value.kind == "ETANGLED"
+    dmid = O.min_detj(u0)  # the initial mesh is untangled
+    assert dmid > 0.0
+    u = to_dev(u0)
+    opts = ilh.newton_options(tol=1e-10, max_halvings=0, ls_residual=0)
+    k, st = G.implicit_step(u.clone(), 2.0, opts=opts, raise_on_fail=False)
+    assert st["status"] == ilh._lib.ILH_ETANGLED
+    assert st["newton"] == 0
+    opts = ilh.newton_options(tol=1e-10, max_halvings=10, max_newton=1, ls_residual=0)
+    k, st = G.implicit_step(u.clone(), 2.0, opts=opts, raise_on_fail=False)
+    assert st["status"] == ilh._lib.ILH_ENOCONV  # one Newton iteration allowed, taken with a halving
+    assert st["newton"] == 1 and st["halvings"] >= 1
+
+
 @pytest.mark.parametrize("case", ["tg2d", "triple"])
 def test_graph_replay_matches_eager_launches(case):
     """Arnoldi steps replayed as captured HIP graphs give the trajectory of the kernel-by-kernel
