@@ -73,6 +73,27 @@ def test_line_search_tangling_decision_matches_oracle():
     assert st["newton"] == 1 and st["halvings"] >= 1
 
 
+def test_speculative_arnoldi_step_does_no_counted_work():
+    """The host enqueues Arnoldi step j before it reads step j-1's residual estimate; the step
+    after the one that ends a solve reads that step's end flag on the device and returns at once.
+    With cycles that never restart, the Jacobian actions counted are then exactly the GMRES
+    iterations, and the trajectory still matches the oracle's."""
+    from oracle import krylov
+    O, G = make_pair("tg2d", (8, 8), 2)
+    u0 = O.init_state()
+    states, _, _ = krylov.run_midpoint(O, u0, 0.01, 3)
+    u = to_dev(u0)
+    hist = []
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, restart=64)
+    for n in range(3):
+        g = G.plain_guess(u, hist)
+        k, st = G.implicit_step(u, 0.01, guess=g, opts=opts)
+        assert st["status"] == 0
+        assert st["jvp_calls"] == st["gmres"], st
+        hist = (hist + [k])[-2:]
+        assert rel(to_np(u), states[n + 1]) <= 1e-8
+
+
 @pytest.mark.parametrize("case", ["tg2d", "triple"])
 def test_graph_replay_matches_eager_launches(case):
     """Arnoldi steps replayed as captured HIP graphs give the trajectory of the kernel-by-kernel
