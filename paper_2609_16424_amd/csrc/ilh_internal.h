@@ -271,7 +271,8 @@ int res2d_groups(const ilh_ctx* c);
 // *out = min_i part[i], i < np (device)
 int launch_min_final(ilh_ctx* c, const double* part, int np, double* out);
 bool res3d_available(const ilh_ctx* c);
-int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, double* r);
+int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin = nullptr);
+int res3d_groups(const ilh_ctx* c);
 int min_detj_host(ilh_ctx* c, const double* x, double* out);
 int min_detj_dev(ilh_ctx* c, const double* x, double* d_out);  // result stays on the device (no sync)
 int dt_estimate_host(ilh_ctx* c, const double* u, double cfl, double* out);

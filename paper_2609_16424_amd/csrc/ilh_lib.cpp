@@ -610,16 +610,20 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
 
 // The strip residual with the smallest det J of the stage positions in *d_min (device), one
 // pass for both; false (nothing launched) where no strip residual kernel applies
-static bool residual_detj_available(const ilh_ctx* c) { return c->jvp_variant != 1 && res2d_available(c); }
+static bool residual_detj_available(const ilh_ctx* c) {
+  return c->jvp_variant != 1 && (res2d_available(c) || res3d_available(c));
+}
 static int residual_detj(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* d_min) {
   int st;
-  if (!c->dmin_part && (st = dalloc(c, &c->dmin_part, (size_t)res2d_groups(c)))) return st;
+  const bool d2 = res2d_available(c);
+  const int ng = d2 ? res2d_groups(c) : res3d_groups(c);
+  if (!c->dmin_part && (st = dalloc(c, &c->dmin_part, (size_t)ng))) return st;
   if ((st = launch_fill(c, r + c->nh1, 0.0, c->nh1))) return st;
   const int slot = tstart_k(c, 1);
-  st = launch_res2d(c, k, u, tau, r, c->dmin_part);
+  st = d2 ? launch_res2d(c, k, u, tau, r, c->dmin_part) : launch_res3d(c, k, u, tau, r, c->dmin_part);
   tstop_k(c, slot);
   if (st) return st;
-  return launch_min_final(c, c->dmin_part, res2d_groups(c), d_min);
+  return launch_min_final(c, c->dmin_part, ng, d_min);
 }
 
 int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {

@@ -287,7 +287,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
 template <int D1D, int Q1D>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1)))
 k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restrict__ u,
-        const double* __restrict__ kk, double tau, double* __restrict__ r) {
+        const double* __restrict__ kk, double tau, double* __restrict__ r, double* __restrict__ dmin) {
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D * L1D;
   constexpr int LPE = Q1D * Q1D, EPW = 64 / LPE;
   constexpr int NS = K * EPW + 1;
@@ -377,6 +377,7 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
     for (int cz = 0; cz < D1D; ++cz) Tx[c][cz] = Ty[c][cz] = Tz[c][cz] = 0.0;
 #pragma unroll
   for (int cl = 0; cl < L1D; ++cl) TL[cl] = 0.0;
+  double dm = 1e300;  // the lane's smallest det J (dmin set)
   if (active) {
     const int s0 = K * z;
     double Bx[D1D], Gx[D1D], By[D1D], Gy[D1D], BLx[L1D], BLy[L1D];
@@ -480,6 +481,10 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
         ke += tb.BL[qz][cl] * EK[cl];
       }
       const double mq = wxy * tb.W[qz];
+      if (dmin)
+        dm = fmin(dm, J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                          J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]));
       double S[3][3], sq;
       qp_force<3, double>(P, gam, mq, dJ0, J, Gv, eq, S, sq);
       const double cl_ = mq * ke - sq;
@@ -560,6 +565,11 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
         for (int al = 0; al < L1D; ++al) sO[lane][al + L1D * (bl + L1D * cl)] = BLx[al] * BLy[bl] * TL[cl];
   }
   __syncthreads();
+  if (dmin) {  // the work-group's smallest det J of the stage positions w_x
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmin(dm, __shfl_xor(dm, o, 64));
+    if (lane == 0) dmin[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = dm;
+  }
   if (active) {
     for (int t = rr; t < NLD; t += LPE) {
       double o = 0;
@@ -595,8 +605,13 @@ static void res_t(ilh_ctx* c, const double* k, const double* u, double tau, doub
   klaunch(c, k_res2d<D1D, Q1D, SRC>, grid, dim3(64), 0, c->kp, tb, u, k, tau, r, dmin);
 }
 
+int res3d_groups(const ilh_ctx* c) {
+  const int EPW = 64 / 16;
+  return ((c->n[0] + EPW - 1) / EPW) * c->n[1] * c->n[2];
+}
+
 // r = R(k; u, tau); the velocity rows of r must be zero on entry
-int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
+int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin) {
   if (!res3d_available(c)) return ILH_EINVAL;
   constexpr int D1D = 3, Q1D = 4, EPW = 64 / (Q1D * Q1D);
   Tab2<double, D1D, Q1D> tb;
@@ -609,7 +624,7 @@ int launch_res3d(ilh_ctx* c, const double* k, const double* u, double tau, doubl
     tb.W[q] = c->h_w1[q];
   }
   const dim3 grid((c->n[0] + EPW - 1) / EPW, c->n[1], c->n[2]);
-  klaunch(c, k_res3d<D1D, Q1D>, grid, dim3(64), 0, c->kp, tb, u, k, tau, r);
+  klaunch(c, k_res3d<D1D, Q1D>, grid, dim3(64), 0, c->kp, tb, u, k, tau, r, dmin);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }

@@ -34,6 +34,25 @@ def test_c1_trajectory_matches_oracle(prec):
     assert abs(Eg - Eo) <= 1e-10 * abs(Eo)
 
 
+@pytest.mark.parametrize("n", [(2, 2, 2), (5, 3, 2)])
+def test_3d_trajectory_matches_oracle(n):
+    """3D Taylor-Green Q2Q1: implicit midpoint steps with the 3D strip residual, whose det J of
+    the stage positions feeds the line search, match the oracle's (one and two partial strips)."""
+    from oracle import krylov
+    O, G = make_pair("tg3d", n, 2)
+    u0 = O.init_state()
+    states, _, _ = krylov.run_midpoint(O, u0, 0.01, 2)
+    u = to_dev(u0)
+    hist = []
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=64)
+    for i in range(2):
+        g = G.plain_guess(u, hist)
+        k, st = G.implicit_step(u, 0.01, guess=g, opts=opts)
+        assert st["status"] == 0 and st["halvings"] == 0
+        hist = (hist + [k])[-2:]
+        assert rel(to_np(u), states[i + 1]) <= 1e-8, (i, rel(to_np(u), states[i + 1]))
+
+
 def test_stage_failure_paths():
     O, G = make_pair("tg2d", (4, 4), 2)
     u = to_dev(O.init_state())
