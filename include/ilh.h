@@ -21,8 +21,9 @@
  *      L2 vector  [Ne][Nl] element-major; elements lexicographic, first direction fastest;
  *                          within an element the Bernstein basis is lexicographic.
  *      block      [x | v | e] = 2 H1 vectors followed by one L2 vector.
- *  - Boundary conditions: v.n = 0 on every box face.  Component c of a node on a face
- *    normal to direction c is "constrained".
+ *  - Boundary conditions: v.n = 0 on every wall face of the box (every face unless the set-up's
+ *    free_faces lists it; Sec. 4.2 states walls for its test).  Component c of a node on a wall
+ *    face normal to direction c is "constrained".
  *  - Return value: an ILH_* status code.  No C++ exception crosses the ABI.  On error
  *    ilh_last_error() describes the failure; outputs are unspecified.
  */
@@ -79,14 +80,27 @@ typedef struct {
   double h_coarse;      /* <= 0 selects h0 */
   double eps_e;         /* energy regularisation width, eq. energy_regularization (1e-6) */
   int tg_source;        /* TG2D only: add the energy source that keeps the vortex steady */
+  const double* x0;     /* host [dim][N] or NULL: initial node positions, an H1 vector in the layout
+                           below (Sec. 2.1: the mesh positions are a field of the kinematic space, so
+                           the initial mesh may be curved).  NULL: the box's affine nodes.  Given,
+                           det J0 and m_q = rho0 det J0 w_q are formed at every quadrature point and
+                           M_E^-1 per element; det J0 <= 0 anywhere is ILH_EINVAL.  The element-to-
+                           node numbering stays that of the box grid (its logical structure) */
+  int free_faces;       /* bit 2d set: no wall on the face x_d = lo_d (v.n = 0 is not imposed there);
+                           bit 2d+1: likewise on x_d = hi_d.  0: walls on every face (the paper's
+                           test problems).  x0 != NULL or free_faces != 0 selects the generic element
+                           kernels (kernel variant 1) for every operator; the transpose action is
+                           then not available */
 } ilh_setup;
 
 /* Fill *s with the defaults above for the given problem (dim, n, k set by the caller). */
 void ilh_setup_defaults(ilh_setup* s, int problem);
 
 /* Build the mesh, DOF maps, 1D basis tables, quadrature data m_q = rho0 detJ0 w_q
- * (strong mass conservation, Sec. 2.1) and the L2 mass inverse blocks on the device.
- * stream: a hipStream_t (NULL = default stream).  *out receives the context. */
+ * (pointwise mass conservation, Sec. 2.1, rho = rho0 / |J|) and the L2 mass inverse blocks on the device
+ * (Sec. 2.2).  stream: a hipStream_t (NULL = default stream).  *out receives the context (NULL
+ * on failure).  Errors: ILH_EINVAL for inconsistent set-ups (printed to stderr, as no context
+ * survives), ILH_ENOMEM when a host or device allocation fails, ILH_EHIP for other HIP errors. */
 int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out);
 void ilh_destroy(ilh_ctx* ctx);
 int ilh_set_stream(ilh_ctx* ctx, void* stream);
@@ -98,8 +112,11 @@ const char* ilh_status_string(int status);
 int ilh_sizes(const ilh_ctx* ctx, int64_t* n_h1vec, int64_t* n_l2, int64_t* n_block,
               int64_t* n_qp);
 
-/* Initial state u [block]: x0 = mesh nodes, v0 = nodal interpolation of the problem's
- * velocity (zero on constrained components), e0 = rho-weighted L2 projection. */
+/* Initial state u [block] (Sec. 2.1: x, v in the kinematic space, e in the thermodynamic space):
+ * x0 = mesh nodes (the set-up's x0 when given), v0 = nodal interpolation of the problem's
+ * velocity (zero on constrained components), e0 = rho-weighted L2 projection
+ * M_E e0 = int rho0 e0(x) phi (the paper leaves the projection to its references; this is the
+ * mass-weighted one).  Asynchronous; u is device memory of n_block doubles. */
 int ilh_init_state(ilh_ctx* ctx, double* u);
 
 /* Force actions at state w [block] (eq. matrices, eqs. v_semi/e_semi):
@@ -170,17 +187,24 @@ int ilh_mass_v_apply(ilh_ctx* ctx, const double* x, double* y);
 int ilh_mass_v_solve(ilh_ctx* ctx, const double* b, double* x, double rtol, int maxit,
                      int* iters, double* relres);
 
-/* x [L2] = M_E^{-1} b [L2], exactly, with the per-element inverse blocks. */
+/* x [L2] = M_E^{-1} b [L2], exactly, with the per-element inverse blocks (eq. matrices: M_E is
+ * block diagonal because the thermodynamic space is discontinuous).  Asynchronous. */
 int ilh_mass_e_inv(ilh_ctx* ctx, const double* b, double* x);
 
-/* Kinetic 1/2 v^T M_V v and internal 1^T M_E e energies of u (host outputs). */
+/* Kinetic 1/2 v^T M_V v and internal 1^T M_E e energies of u (host outputs), FP64.  Their sum
+ * is the total energy that eqs. v_semi and e_semi conserve exactly (F 1 paired with v equals
+ * 1 paired with F^T v); it is the energy check of the implicit step.  Synchronises. */
 int ilh_energy(ilh_ctx* ctx, const double* u, double* ke, double* ie);
 
-/* Minimum of det J over all quadrature points of the positions of w [block] (host). */
+/* Minimum of det J over all quadrature points of the positions of w [block] (host output;
+ * synchronises).  The Newton line search of Sec. 3.5 keeps this positive.  A non-finite position
+ * gives NaN (the minimum propagates NaN). */
 int ilh_min_detj(ilh_ctx* ctx, const double* w, double* min_detj);
 
 /* Explicit time-step estimate cfl * min_q h_min / (c_s + 2.5 mu / (rho h_min)),
- * h_min = smallest singular value of J_q / k (host output). */
+ * h_min = smallest singular value of J_q / k (host output; synchronises).  Sec. 4 measures
+ * implicit steps in multiples of the explicit CFL step ("FS-CFL") and refers to the explicit
+ * estimate of its references; this is that estimate as read here. */
 int ilh_dt_estimate(ilh_ctx* ctx, const double* u, double cfl, double* dt);
 
 /* TG2D only: int |v_h - v_exact(x)|_2 dx over the current mesh (host output). */

@@ -182,13 +182,18 @@ class ViscosityOptions:
 class Hydro:
     """Q_k Q_{k-1} Lagrangian hydrodynamics on a Cartesian box (paper Sec. 2.1, 2.2)."""
 
-    def __init__(self, problem_name, n, k, visc=None, source=True, perturb=None, nq1d=None):
+    def __init__(self, problem_name, n, k, visc=None, source=True, perturb=None, nq1d=None, x0=None,
+                 free_faces=0):
+        """x0 (optional, [dim][N]): initial node positions of a curved initial mesh, the positions
+        being a field of the kinematic space (Sec. 2.1); free_faces: box faces without walls."""
         dims = {"tg2d": 2, "tg3d": 3, "triple": 2, "sedov": 2, "uniform": len(n)}
         dim = dims[problem_name]
         boxes = {"tg2d": ((0, 0), (1, 1)), "tg3d": ((0, 0, 0), (1, 1, 1)),
                  "triple": ((0, 0), (7, 3)), "sedov": ((0, 0), (1, 1)), "uniform": ((0,) * dim, (1,) * dim)}
         lo, hi = boxes[problem_name]
-        self.mesh = m = BoxMesh(dim, n, lo, hi, k)
+        self.mesh = m = BoxMesh(dim, n, lo, hi, k, free_faces)
+        if x0 is not None:
+            m.x0 = np.array(x0, dtype=np.float64).reshape(dim, m.N)
         self.prob = make_problem(problem_name, m, perturb)
         self.dim, self.k = dim, k
         self.T = tensor_tables(dim, k, nq1d)
@@ -196,6 +201,10 @@ class Hydro:
         self.visc = visc if visc is not None else ViscosityOptions(on=False)
         if self.visc.h0 is None:
             vol = float(np.prod(m.hi - m.lo))
+            if x0 is not None:  # |Omega_0| of the curved mesh: the integral of det J0
+                X0 = m.x0[:, m.conn]
+                vol = float(np.einsum("q,eq->", self.T["qw"],
+                                      np.linalg.det(np.einsum("cen,qna->eqca", X0, self.T["dW"]))))
             self.visc.h0 = (vol / m.Ne) ** (1.0 / dim) / k
         if self.visc.h_coarse is None:
             self.visc.h_coarse = self.visc.h0

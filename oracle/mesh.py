@@ -12,7 +12,9 @@ from .basis import gll_points
 
 
 class BoxMesh:
-    def __init__(self, dim, n, lo, hi, k):
+    def __init__(self, dim, n, lo, hi, k, free_faces=0):
+        """free_faces: bit 2a set = no wall (v . n = 0 not imposed) on the face x_a = lo_a,
+        bit 2a+1 = likewise on x_a = hi_a."""
         self.dim = dim
         self.n = tuple(int(v) for v in n[:dim])
         self.lo = np.array(lo[:dim], dtype=float)
@@ -49,12 +51,14 @@ class BoxMesh:
             stride *= self.ng[a]
         self.conn = conn
         self.elem_index = eidx
-        # wall boundary: component c of node n is constrained when the node lies on a
-        # face normal to direction c (v . n = 0 on every box face)
+        # wall boundary: component c of node n is constrained when the node lies on a wall
+        # face normal to direction c (v . n = 0 on every box face not listed in free_faces)
         cons = np.zeros((dim, self.N), dtype=bool)
         for c in range(dim):
             gi = self.node_grid_index[c]
-            cons[c] = (gi == 0) | (gi == self.ng[c] - 1)
+            wall_lo = not (free_faces >> (2 * c)) & 1
+            wall_hi = not (free_faces >> (2 * c + 1)) & 1
+            cons[c] = ((gi == 0) & wall_lo) | ((gi == self.ng[c] - 1) & wall_hi)
         self.constrained = cons  # (dim, N)
 
     def element_centers(self):

@@ -47,7 +47,9 @@ class Hydro:
 
     def __init__(self, problem, n, k, visc=False, dscale_mode="const", dscale_width=1e-3, q1=0.5,
                  q2=1.0, psi0=0.5, h0=0.0, h_coarse=0.0, tg_source=None, rho0=None, gamma=None,
-                 e0=None, lo=None, hi=None, device="cuda"):
+                 e0=None, lo=None, hi=None, x0=None, free_faces=0, device="cuda"):
+        """x0 (host array of d * N positions, nullable): a curved initial mesh; free_faces: bit
+        mask of box faces without the wall condition (bit 2d: x_d = lo_d, bit 2d+1: x_d = hi_d)."""
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("ilh needs a ROCm GPU; none is visible")
@@ -78,6 +80,12 @@ class Hydro:
                 a = (C.c_double * len(arr))(*[float(x) for x in arr])
                 self._keep.append(a)
                 setattr(s, name, C.cast(a, C.POINTER(C.c_double)))
+        if x0 is not None:
+            import numpy as np
+            a = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).ravel())
+            self._keep.append(a)
+            s.x0 = a.ctypes.data_as(C.POINTER(C.c_double))
+        s.free_faces = int(free_faces)
         self.setup = s
         ctx = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -372,7 +380,8 @@ def make_sedov(n, k, visc=True, h_coarse=None):
 class ForceFn(torch.autograd.Function):
     """(F(w) 1, F(w)^T w_v) with a forward-mode derivative from the hand-written tangent kernel.
 
-    forward(hydro, w) -> (f1, ftv); jvp(dw) -> (d f1, d ftv) via ilh_force_jvp (FP64).
+    forward(hydro, w) -> (f1, ftv); jvp(dw) -> (d f1, d ftv) via ilh_force_jvp (FP64).  Forward
+    mode only (see backward).
     """
 
     @staticmethod
@@ -392,7 +401,11 @@ class ForceFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, *grads):
-        raise NotImplementedError("the transpose (VJP) action is not part of this library")
+        # The library's transpose action (ilh_vjp_lin) is that of the stage residual, which adds
+        # the masses and replaces the wall rows by the identity; the bare force actions carry no
+        # boundary conditions, so their transpose is not recoverable from it.  Reverse mode is
+        # provided for the residual (ResidualFn.backward), not for the force alone.
+        raise NotImplementedError("ForceFn has forward mode only; use ResidualFn for reverse mode")
 
 
 class ResidualFn(torch.autograd.Function):

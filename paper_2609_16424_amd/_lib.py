@@ -18,6 +18,7 @@ class Setup(C.Structure):
         ("visc_on", C.c_int), ("q1", C.c_double), ("q2", C.c_double), ("psi0", C.c_double),
         ("dscale_mode", C.c_int), ("dscale_width", C.c_double), ("h0", C.c_double),
         ("h_coarse", C.c_double), ("eps_e", C.c_double), ("tg_source", C.c_int),
+        ("x0", C.POINTER(C.c_double)), ("free_faces", C.c_int),
     ]
 
 

@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(Q1D* Q1D* NE) k_elem2d(const KParams P, const 
       atomic_add<T>(&A.out[gi], o);
     } else {
       const bool owner = (a < k || ex == n0 - 1) && (b < k || ey == n1 - 1);
-      const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
+      const bool cons = (c == 0) ? on_wall(P.walls, 0, I, ng0) : on_wall(P.walls, 1, J, ng1);
       const int li = a + D1D * b;
       if (!cons) atomic_add<T>(&A.out[nh1 + gi], o);
       if (owner) {
@@ -719,7 +719,7 @@ __global__ void __launch_bounds__(Q1D* Q1D* Q1D* NE) k_elem3d(const KParams P, c
       const bool owner = (a < k || ex == n0 - 1) && (b < k || ey == n1 - 1) && (cc < k || ez == n2 - 1);
       const int gc = (c == 0) ? I : (c == 1 ? J : K);
       const int ngc = (c == 0) ? ng0 : (c == 1 ? ng1 : ng2);
-      const bool cons = (gc == 0 || gc == ngc - 1);
+      const bool cons = on_wall(P.walls, c, gc, ngc);
       if (!cons) atomic_add<T>(&A.out[nh1 + gi], o);
       if (owner) {
         if constexpr (MODE == M_RESID) {

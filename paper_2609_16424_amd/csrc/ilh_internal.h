@@ -5,6 +5,7 @@
 #include <hip/hip_ext.h>
 
 #include <cstdint>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -33,7 +34,14 @@ struct KParams {
   double eps_e;
   int visc, dsc_mode, tg_source;
   double q1, q2, h0, hc_inv, dsc_w, psi_shift;
+  int walls;    // bit 2d: the face x_d = lo_d is a wall (v.n = 0), bit 2d + 1: the face x_d = hi_d
 };
+
+// Component c of the node with grid index g along direction c (of ngc) is constrained when the
+// node lies on a wall face normal to c.
+__host__ __device__ inline bool on_wall(int walls, int c, int64_t g, int64_t ngc) {
+  return (g == 0 && ((walls >> (2 * c)) & 1)) || (g == ngc - 1 && ((walls >> (2 * c + 1)) & 1));
+}
 
 // Pointers of one element-kernel launch.  The meaning depends on the mode:
 //  FORCE : x, v, e = state w;                      out = F 1 [H1], out2 = F^T v [L2]
@@ -80,7 +88,11 @@ struct ilh_ctx {
   double* gamma = nullptr;
   double* rho0 = nullptr;
   double* e0 = nullptr;
-  double* MEinv = nullptr;  // [Ne][Nl][Nl]
+  double* MEinv = nullptr;  // affine initial mesh: [Nl][Nl] reference inverse + [Ne] scales; curved: [Ne][Nl][Nl]
+  int64_t me_stride = 0;    // element stride of MEinv's blocks (0: one reference block)
+  const double* me_scale = nullptr;  // per-element scale of the reference block (nullptr: none)
+  double* x0 = nullptr;     // [nh1] initial node positions of a curved initial mesh (else nullptr)
+  bool general = false;     // curved initial mesh or faces without walls: generic element kernels only
   double* Mdiag = nullptr;  // [nh1] diag(M_V), 1 on constrained rows
   double* qw = nullptr;     // [Q] reference weights (host copy below)
   std::vector<double> h_qw, h_B, h_G, h_BL, h_gll, h_qpts, h_w1;
@@ -143,6 +155,31 @@ namespace ilh {
 // error helpers
 int fail(ilh_ctx* c, int code, const std::string& msg);
 int hip_fail(ilh_ctx* c, hipError_t e, const char* what);
+
+// Set the context's message without letting an exception escape (used on the ABI's
+// exception paths, where the allocation inside std::string may itself fail).
+inline int guard_fail(ilh_ctx* c, int code, const char* msg) noexcept {
+  if (c) {
+    try {
+      c->err = msg;
+    } catch (...) {
+    }
+  }
+  return code;
+}
+
+// Every extern "C" body that can allocate on the host runs inside ILH_TRY ... ILH_CATCH(ctx):
+// a failed host allocation becomes ILH_ENOMEM and any other C++ exception ILH_EINVAL, so no
+// exception crosses the ABI.
+#define ILH_TRY try {
+#define ILH_CATCH(ctx)                                                         \
+  }                                                                            \
+  catch (const std::bad_alloc&) {                                              \
+    return ilh::guard_fail(ctx, ILH_ENOMEM, "host allocation failed");         \
+  }                                                                            \
+  catch (...) {                                                                \
+    return ilh::guard_fail(ctx, ILH_EINVAL, "unexpected C++ exception");       \
+  }
 
 #define ILH_HIP(ctx, call)                               \
   do {                                                   \

@@ -453,7 +453,7 @@ static Tab2<T, D1D, Q1D> make_tab2(const ilh_ctx* c) {
 
 // 32-bit element offsets into the block vectors (byte offsets below 4 GiB in FP64)
 static bool lin2d_supported(const ilh_ctx* c) {
-  return c->dim == 2 && (c->k == 2 || c->k == 3) && c->nblock < (int64_t(1) << 29);
+  return c->dim == 2 && (c->k == 2 || c->k == 3) && c->nblock < (int64_t(1) << 29) && !c->general;
 }
 
 static dim3 lin2d_grid(const ilh_ctx* c) {

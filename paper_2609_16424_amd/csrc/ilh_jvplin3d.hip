@@ -510,7 +510,7 @@ static Tab2<T, D1D, Q1D> make_tab3(const ilh_ctx* c) {
 
 // 3D, Q2Q1 (4 elements per wave), no TG source; 32-bit element offsets into the block vectors
 bool lin3d_available(const ilh_ctx* c) {
-  return c->dim == 3 && c->k == 2 && !c->kp.tg_source && c->nblock < (int64_t(1) << 29);
+  return c->dim == 3 && c->k == 2 && !c->kp.tg_source && c->nblock < (int64_t(1) << 29) && !c->general;
 }
 
 static dim3 lin3d_grid(const ilh_ctx* c) {

@@ -257,9 +257,11 @@ void ilh_newton_defaults(ilh_newton_opts* o) {
 const char* ilh_last_error(const ilh_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 int ilh_set_stream(ilh_ctx* c, void* stream) {
+  ILH_TRY
   if (!c) return ILH_EINVAL;
   c->stream = (hipStream_t)stream;
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t* nq) {
@@ -273,7 +275,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
-  void* ptrs[] = {c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
+  void* ptrs[] = {c->x0, c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
                   c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres, c->dmin_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -288,10 +290,14 @@ void ilh_destroy(ilh_ctx* c) {
   delete c;
 }
 
-int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
+// Body of ilh_create; *made receives the context as soon as it exists, so that the exported
+// wrapper can release it when a host allocation throws part-way.  Every error return below
+// releases the context itself.
+static int create_ctx(const ilh_setup* s, void* stream, ilh_ctx** out, ilh_ctx** made) {
   if (!s || !out) return ILH_EINVAL;
   *out = nullptr;
   ilh_ctx* c = new ilh_ctx();
+  *made = c;
   c->s = *s;
   c->stream = (hipStream_t)stream;
   auto bad = [&](const std::string& m) {
@@ -316,6 +322,9 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
   if (s->eps_e <= 0) return bad("eps_e must be > 0");
   if (s->visc_on && s->dscale_mode == ILH_DSCALE_CONST && !(s->dscale_width > 0)) return bad("dscale_width must be > 0");
   if (s->visc_on && (s->psi0 <= 0 || s->psi0 >= 1)) return bad("psi0 must lie in (0, 1)");
+  if (s->free_faces < 0 || s->free_faces >= (1 << (2 * dim))) return bad("free_faces has bits beyond the box's faces");
+  c->general = s->x0 != nullptr || s->free_faces != 0;
+  const int walls = ((1 << (2 * dim)) - 1) & ~s->free_faces;
 
   c->dim = dim;
   c->k = k;
@@ -425,7 +434,8 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
   for (int64_t e = 0; e < c->Ne; ++e)
     if (!(rho0[e] > 0) || !(gam[e] > 1)) return bad("rho0 must be > 0 and gamma > 1");
 
-  // quadrature data: affine Cartesian elements, det J0 = prod h_d
+  // quadrature data: affine Cartesian elements, det J0 = prod h_d (a curved initial mesh x0
+  // replaces it per point below)
   double detJ0 = 1;
   for (int d = 0; d < dim; ++d) detJ0 *= h[d];
   const int Q = c->Q;
@@ -442,8 +452,53 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
   c->h_qw = qw;
   std::vector<double> mq(c->nqp), dj0(c->nqp, detJ0), rj0(c->Ne), j0e(c->Ne, detJ0);
   for (int64_t e = 0; e < c->Ne; ++e) rj0[e] = rho0[e] * detJ0;
+  const int Nh = c->Nh;
+  const int64_t s1 = c->ng[0], s2 = (int64_t)c->ng[0] * c->ng[1];
+  // global index of element-local H1 node li of element e
+  auto gnode = [&](int64_t e, int li) -> int64_t {
+    const int ex = (int)(e % c->n[0]), ey = (int)((e / c->n[0]) % c->n[1]),
+              ez = dim == 3 ? (int)(e / ((int64_t)c->n[0] * c->n[1])) : 0;
+    const int a = li % D1D, b = (li / D1D) % D1D, cc = dim == 3 ? li / (D1D * D1D) : 0;
+    return (k * ex + a) + s1 * (k * ey + b) + s2 * (k * ez + cc);
+  };
+  // reference gradient of local node li at quadrature point q (direction dd) and its value
+  auto wgrad = [&](int li, int q, int dd) {
+    const int a[3] = {li % D1D, (li / D1D) % D1D, dim == 3 ? li / (D1D * D1D) : 0};
+    const int qi[3] = {q % Q1D, (q / Q1D) % Q1D, dim == 3 ? q / (Q1D * Q1D) : 0};
+    double v = 1;
+    for (int d = 0; d < dim; ++d) v *= (d == dd ? G : B)[qi[d] * D1D + a[d]];
+    return v;
+  };
+  if (s->x0) {
+    // curved initial mesh (Sec. 2.1: the positions are an H1 field): J0 = sum_n x0_n (x) grad w_n
+    // and m_q = rho0 det J0 w_q at every quadrature point
+    for (int64_t e = 0; e < c->Ne; ++e) {
+      double jsum = 0;
+      for (int q = 0; q < Q; ++q) {
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int li = 0; li < Nh; ++li) {
+          const int64_t g = gnode(e, li);
+          for (int dd = 0; dd < dim; ++dd) {
+            const double gw = wgrad(li, q, dd);
+            for (int cc = 0; cc < dim; ++cc) J[cc][dd] += s->x0[cc * c->N + g] * gw;
+          }
+        }
+        const double dj = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                                   : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(dj > 0)) return bad("x0: det J0 <= 0 at a quadrature point");
+        dj0[e * Q + q] = dj;
+        jsum += dj * qw[q];
+      }
+      double wsum = 0;
+      for (int q = 0; q < Q; ++q) wsum += qw[q];
+      j0e[e] = jsum / wsum;  // not read by the generic kernels; kept meaningful
+      rj0[e] = rho0[e] * j0e[e];
+    }
+  }
   for (int64_t e = 0; e < c->Ne; ++e)
-    for (int q = 0; q < Q; ++q) mq[e * Q + q] = rho0[e] * detJ0 * qw[q];
+    for (int q = 0; q < Q; ++q) mq[e * Q + q] = rho0[e] * dj0[e * Q + q] * qw[q];
   // L2 mass: M_E,e = rho0_e detJ0 (M1 x M1 [x M1]) with the 1D Bernstein mass M1
   std::vector<double> M1(L1D * L1D, 0.0);
   for (int i = 0; i < L1D; ++i)
@@ -464,14 +519,45 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
       me[i * Nl + j] = v;
     }
   for (int64_t e = 0; e < c->Ne; ++e) me[Nl * Nl + e] = 1.0 / (rho0[e] * detJ0);
+  if (s->x0) {
+    // curved: the element blocks M_E,e(i, j) = sum_q m_q phi_i phi_j are not multiples of one
+    // reference block; each is inverted on its own
+    me.assign((size_t)c->Ne * Nl * Nl, 0.0);
+    std::vector<double> blk(Nl * Nl), phi(Nl);
+    for (int64_t e = 0; e < c->Ne; ++e) {
+      std::fill(blk.begin(), blk.end(), 0.0);
+      for (int q = 0; q < Q; ++q) {
+        const int qi[3] = {q % Q1D, (q / Q1D) % Q1D, dim == 3 ? q / (Q1D * Q1D) : 0};
+        for (int j = 0; j < Nl; ++j) {
+          const int jl[3] = {j % L1D, (j / L1D) % L1D, dim == 3 ? j / (L1D * L1D) : 0};
+          double v = 1;
+          for (int d = 0; d < dim; ++d) v *= BL[qi[d] * L1D + jl[d]];
+          phi[j] = v;
+        }
+        for (int i = 0; i < Nl; ++i)
+          for (int j = 0; j < Nl; ++j) blk[i * Nl + j] += mq[e * Q + q] * phi[i] * phi[j];
+      }
+      if (!invert(blk, Nl)) return bad("singular L2 mass block");
+      std::copy(blk.begin(), blk.end(), me.begin() + e * Nl * Nl);
+    }
+  }
   // H1 mass diagonal (tensor product of 1D sums) with ones on constrained rows
   std::vector<double> d1(D1D, 0.0);
   for (int a = 0; a < D1D; ++a)
     for (int q = 0; q < Q1D; ++q) d1[a] += wg[q] * B[q * D1D + a] * B[q * D1D + a];
   std::vector<double> diag(c->N, 0.0);
-  const int Nh = c->Nh;
-  const int64_t s1 = c->ng[0], s2 = (int64_t)c->ng[0] * c->ng[1];
-  for (int64_t e = 0; e < c->Ne; ++e) {
+  if (s->x0) {  // diag(M_s)(n) = sum over elements and points of m_q w_n(xi_q)^2
+    for (int64_t e = 0; e < c->Ne; ++e)
+      for (int li = 0; li < Nh; ++li) {
+        double v = 0;
+        for (int q = 0; q < Q; ++q) {
+          const double wv = wgrad(li, q, -1);
+          v += mq[e * Q + q] * wv * wv;
+        }
+        diag[gnode(e, li)] += v;
+      }
+  }
+  for (int64_t e = 0; e < (s->x0 ? 0 : c->Ne); ++e) {
     const int ex = (int)(e % c->n[0]), ey = (int)((e / c->n[0]) % c->n[1]),
               ez = dim == 3 ? (int)(e / ((int64_t)c->n[0] * c->n[1])) : 0;
     for (int li = 0; li < Nh; ++li) {
@@ -489,13 +575,18 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
         gi[d] = (int)(r % c->ng[d]);
         r /= c->ng[d];
       }
-      const bool cons = gi[cc] == 0 || gi[cc] == c->ng[cc] - 1;
+      const bool cons = on_wall(walls, cc, gi[cc], c->ng[cc]);
       Md[cc * c->N + node] = cons ? 1.0 : diag[node];
     }
 
   // viscosity parameters
   double vol = 1;
   for (int d = 0; d < dim; ++d) vol *= c->hi[d] - c->lo[d];
+  if (s->x0) {  // |Omega_0| of the curved mesh by quadrature
+    vol = 0;
+    for (int64_t e = 0; e < c->Ne; ++e)
+      for (int q = 0; q < Q; ++q) vol += dj0[e * Q + q] * qw[q];
+  }
   const double h0 = s->h0 > 0 ? s->h0 : std::pow(vol / c->Ne, 1.0 / dim) / k;
   const double hc = s->h_coarse > 0 ? s->h_coarse : h0;
 
@@ -506,7 +597,8 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
       (st = dalloc(c, &c->e0, c->Ne)) || (st = dalloc(c, &c->MEinv, me.size())) || (st = dalloc(c, &c->Mdiag, c->nh1)) ||
       (st = dalloc(c, &c->w64, c->nblock)) || (st = dalloc(c, &c->w32, c->nblock)) ||
       (st = dalloc(c, &c->red, (size_t)c->red_blocks * 66 + 256)) || (st = dalloc(c, &c->pcgbuf, 4 * c->nh1 + 16)) ||
-      (st = dalloc(c, &c->rj0, c->Ne)) || (st = dalloc(c, &c->j0e, c->Ne))) {
+      (st = dalloc(c, &c->rj0, c->Ne)) || (st = dalloc(c, &c->j0e, c->Ne)) ||
+      (s->x0 && (st = dalloc(c, &c->x0, c->nh1)))) {
     std::fprintf(stderr, "ilh_create: %s\n", c->err.c_str());
     ilh_destroy(c);
     return st;
@@ -525,7 +617,8 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
       up(c->detJ0, dj0.data(), c->nqp * 8) || up(c->gamma, gam.data(), c->Ne * 8) ||
       up(c->rho0, rho0.data(), c->Ne * 8) || up(c->e0, e0.data(), c->Ne * 8) ||
       up(c->MEinv, me.data(), me.size() * 8) || up(c->Mdiag, Md.data(), c->nh1 * 8) ||
-      up(c->rj0, rj0.data(), c->Ne * 8) || up(c->j0e, j0e.data(), c->Ne * 8)) {
+      up(c->rj0, rj0.data(), c->Ne * 8) || up(c->j0e, j0e.data(), c->Ne * 8) ||
+      (s->x0 && up(c->x0, s->x0, c->nh1 * 8))) {
     std::fprintf(stderr, "ilh_create: upload failed\n");
     ilh_destroy(c);
     return ILH_EHIP;
@@ -556,24 +649,55 @@ int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
   P.hc_inv = 1.0 / hc;
   P.dsc_w = s->dscale_width;
   P.psi_shift = s->visc_on ? std::atanh(1.0 - 2.0 * s->psi0) : 0.0;
+  P.walls = walls;
+  if (s->x0) {
+    c->me_stride = (int64_t)Nl * Nl;
+    c->me_scale = nullptr;
+  } else {
+    c->me_stride = 0;
+    c->me_scale = c->MEinv + Nl * Nl;
+  }
+  if (c->general) c->jvp_variant = 1;
   *out = c;
   return ILH_OK;
 }
 
+int ilh_create(const ilh_setup* s, void* stream, ilh_ctx** out) {
+  ilh_ctx* made = nullptr;
+  int st;
+  try {
+    return create_ctx(s, stream, out, &made);
+  } catch (const std::bad_alloc&) {
+    st = ILH_ENOMEM;
+  } catch (...) {
+    st = ILH_EINVAL;
+  }
+  // an exception left the context half-built (create_ctx frees it on every error return)
+  std::fprintf(stderr, "ilh_create: %s\n", st == ILH_ENOMEM ? "host allocation failed" : "unexpected C++ exception");
+  ilh_destroy(made);
+  if (out) *out = nullptr;
+  return st;
+}
+
 int ilh_init_state(ilh_ctx* c, double* u) {
+  ILH_TRY
   if (!c || !u) return ILH_EINVAL;
   return init_state_dev(c, u, nullptr);
+  ILH_CATCH(c)
 }
 
 int ilh_force(ilh_ctx* c, const double* w, double* f1, double* ftv) {
+  ILH_TRY
   if (!c || !w || !f1 || !ftv) return ILH_EINVAL;
   int st = launch_fill(c, f1, 0.0, c->nh1);
   if (st) return st;
   EArgs<double> a{w, w + c->nh1, w + 2 * c->nh1, nullptr, nullptr, 0.0, f1, ftv};
   return launch_elem(c, M_FORCE, 64, &a, nullptr);
+  ILH_CATCH(c)
 }
 
 int ilh_force_jvp(ilh_ctx* c, int prec, const double* w, const void* dw, void* df1, void* dftv) {
+  ILH_TRY
   if (!c || !w || !dw || !df1 || !dftv) return ILH_EINVAL;
   int st;
   if (prec == 64) {
@@ -589,9 +713,11 @@ int ilh_force_jvp(ilh_ctx* c, int prec, const double* w, const void* dw, void* d
     return launch_elem(c, M_FJVP, 32, nullptr, &a);
   }
   return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+  ILH_CATCH(c)
 }
 
 int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
+  ILH_TRY
   if (!c || !k || !u || !r) return ILH_EINVAL;
   int st = launch_fill(c, r + c->nh1, 0.0, c->nh1);
   if (st) return st;
@@ -606,6 +732,7 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   }
   tstop_k(c, slot);
   return st;
+  ILH_CATCH(c)
 }
 
 // The strip residual with the smallest det J of the stage positions in *d_min (device), one
@@ -627,6 +754,7 @@ static int residual_detj(ilh_ctx* c, const double* k, const double* u, double ta
 }
 
 int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
+  ILH_TRY
   if (!c || !k || !u) return ILH_EINVAL;
   int st;
   if ((st = launch_waxpy(c, c->w64, u, tau, k, c->nblock))) return st;
@@ -634,9 +762,11 @@ int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
   c->qd_ok[0] = c->qd_ok[1] = false;
   if (c->jvp_variant == 0 && (lin2d_available(c) || lin3d_available(c))) return ILH_OK;  // they read w64 only
   return launch_cast_d2f(c, c->w32, c->w64, c->nblock);
+  ILH_CATCH(c)
 }
 
 int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
+  ILH_TRY
   if (!c || !dk || !jdk) return ILH_EINVAL;
   if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
   int st;
@@ -676,15 +806,19 @@ int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
   if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 32, nullptr, &a);
   tstop_k(c, slot);
   return st;
+  ILH_CATCH(c)
 }
 
 int ilh_jvp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, const void* dk, void* jdk) {
+  ILH_TRY
   int st = ilh_linearize(c, k, u, tau);
   if (st) return st;
   return ilh_jvp_lin(c, prec, dk, jdk);
+  ILH_CATCH(c)
 }
 
 int ilh_vjp_lin(ilh_ctx* c, int prec, const void* y, void* jty) {
+  ILH_TRY
   if (!c || !y || !jty) return ILH_EINVAL;
   if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
   const bool d3 = c->dim == 3;
@@ -708,20 +842,26 @@ int ilh_vjp_lin(ilh_ctx* c, int prec, const void* y, void* jty) {
   st = d3 ? launch_vjp3d_q(c, prec, y, jty) : launch_vjp2d_q(c, prec, y, jty);
   tstop_k(c, slot);
   return st;
+  ILH_CATCH(c)
 }
 
 int ilh_vjp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, const void* y, void* jty) {
+  ILH_TRY
   int st = ilh_linearize(c, k, u, tau);
   if (st) return st;
   return ilh_vjp_lin(c, prec, y, jty);
+  ILH_CATCH(c)
 }
 
 int ilh_mass_v_apply(ilh_ctx* c, const double* x, double* y) {
+  ILH_TRY
   if (!c || !x || !y) return ILH_EINVAL;
   return launch_mass_v(c, x, y, 0);
+  ILH_CATCH(c)
 }
 
 int ilh_mass_v_solve(ilh_ctx* c, const double* b, double* x, double rtol, int maxit, int* iters, double* relres) {
+  ILH_TRY
   if (!c || !b || !x || maxit < 0) return ILH_EINVAL;
   int it = 0;
   double rel = 0;
@@ -731,36 +871,48 @@ int ilh_mass_v_solve(ilh_ctx* c, const double* b, double* x, double rtol, int ma
   if (relres) *relres = rel;
   if (rel > rtol) return fail(c, ILH_ENOCONV, "PCG did not reach rtol");
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_mass_e_inv(ilh_ctx* c, const double* b, double* x) {
+  ILH_TRY
   if (!c || !b || !x) return ILH_EINVAL;
   return launch_mass_e_inv(c, b, x);
+  ILH_CATCH(c)
 }
 
 int ilh_energy(ilh_ctx* c, const double* u, double* ke, double* ie) {
+  ILH_TRY
   if (!c || !u || !ke || !ie) return ILH_EINVAL;
   return energy_host(c, u, ke, ie);
+  ILH_CATCH(c)
 }
 
 int ilh_min_detj(ilh_ctx* c, const double* w, double* m) {
+  ILH_TRY
   if (!c || !w || !m) return ILH_EINVAL;
   return min_detj_host(c, w, m);
+  ILH_CATCH(c)
 }
 
 int ilh_dt_estimate(ilh_ctx* c, const double* u, double cfl, double* dt) {
+  ILH_TRY
   if (!c || !u || !dt || !(cfl > 0)) return ILH_EINVAL;
   return dt_estimate_host(c, u, cfl, dt);
+  ILH_CATCH(c)
 }
 
 int ilh_l1_velocity_error(ilh_ctx* c, const double* u, double* err) {
+  ILH_TRY
   if (!c || !u || !err) return ILH_EINVAL;
   if (c->s.problem != ILH_PROBLEM_TG2D && c->s.problem != ILH_PROBLEM_TG3D)
     return fail(c, ILH_EINVAL, "L1 error needs an analytic Taylor-Green velocity");
   return l1_error_host(c, u, err);
+  ILH_CATCH(c)
 }
 
 int ilh_rate(ilh_ctx* c, const double* u, double* f) {
+  ILH_TRY
   if (!c || !u || !f) return ILH_EINVAL;
   int st;
   const int64_t nh1 = c->nh1;
@@ -780,6 +932,7 @@ int ilh_rate(ilh_ctx* c, const double* u, double* f) {
   if ((st = pcg_mass_v(c, r + nh1, f + nh1, 1e-14, 500, 10, &it, &rel))) return st;
   ILH_HIP(c, hipMemcpyAsync(f, u + nh1, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 // a = -Mhat^-1 P_u F(w) 1 (the velocity rate, wall rows zero), using f1 [nh1] as scratch
@@ -801,6 +954,7 @@ static int energy_rate(ilh_ctx* c, const double* w, const double* vt, double* r,
 }
 
 int ilh_rk2avg_step(ilh_ctx* c, double* u, double dt) {
+  ILH_TRY
   if (!c || !u || !(dt > 0)) return ILH_EINVAL;
   if (c->dim != 2) return fail(c, ILH_EINVAL, "the explicit RK2-average step is built for 2D");
   int st;
@@ -828,10 +982,12 @@ int ilh_rk2avg_step(ilh_ctx* c, double* u, double dt) {
   if ((st = launch_axpby(c, e, dt, de, 1.0, nl2))) return st;
   if ((st = launch_axpby(c, x, dt, vb, 1.0, nh1))) return st;
   return launch_axpby(c, v, dt, a, 1.0, nh1);
+  ILH_CATCH(c)
 }
 
 int ilh_plain_guess(ilh_ctx* c, const double* u, const double* k1, const double* k2, int nhist, double tau,
                     double* out) {
+  ILH_TRY
   if (!c || !u || !out) return ILH_EINVAL;
   int st;
   if (nhist <= 0) {
@@ -847,6 +1003,7 @@ int ilh_plain_guess(ilh_ctx* c, const double* u, const double* k1, const double*
     if ((st = launch_axpby(c, out, tau, out + c->nh1, 1.0, c->nh1))) return st;
   }
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 }  // extern "C"
@@ -938,6 +1095,7 @@ struct Solver {
 
   const double* z32_of = nullptr;  // the vector whose FP32 copy is in kry32 (written by precond)
   const double* zeroed_v = nullptr;  // the FP64 vector whose velocity rows precond zeroed
+  bool took_direct = false;  // an action took the direct FP32 path (tau read from the device)
 
   // FP32 linearised 2D actions write the FP64 Krylov vector directly
   bool direct64() const { return o->jvp_prec == 32 && c->jvp_variant == 0 && lin2d_available(c); }
@@ -1009,6 +1167,7 @@ struct Solver {
           if (st) return st;
           c->qd_ok[0] = true;
         }
+        took_direct = true;
         const int slot = tstart_k(c, 0);
         st = launch_jvp2d_q_f32to64(c, x32, y, c->hdev + 250, skip);
         tstop_k(c, slot);
@@ -1089,6 +1248,13 @@ struct Solver {
       c->gkey = key;
     }
     if (!c->gexec[j]) {
+      // Step j - 1 (replayed, so its host-side records were not made) or the cycle start left the
+      // FP32 copy of z_j and zeroed the velocity rows of V_{j+1}: the captured action must take the
+      // direct FP32 path, which reads tau from the device (a captured host tau would go stale).
+      const int64_t n = c->nblock;
+      z32_of = c->kry + (int64_t)(m + 1) * n + (int64_t)j * n;
+      zeroed_v = c->kry + (int64_t)(j + 1) * n;
+      took_direct = false;
       if (!c->capstream) ILH_HIP(c, hipStreamCreateWithFlags(&c->capstream, hipStreamNonBlocking));
       hipStream_t saved = c->stream;
       c->stream = c->capstream;
@@ -1099,9 +1265,9 @@ struct Solver {
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(c->capstream, &g);
       c->stream = saved;
-      if (st) {
+      if (st || !took_direct) {
         if (g) (void)hipGraphDestroy(g);
-        return st;
+        return st ? st : fail(c, ILH_EINVAL, "graph capture: the Arnoldi step did not take the device-tau action");
       }
       ILH_HIP(c, e);
       hipGraphExec_t ex = nullptr;
@@ -1185,7 +1351,10 @@ struct Solver {
       };
       bool end = false;
       for (int j = 0; j < m && !end; ++j) {
-        if (use_graph) {
+        // step j - 1 is the last one the iteration limit allows: step j is not enqueued
+        const bool enqueue = !(j >= 1 && total + 1 >= o->gmres_maxit);
+        if (!enqueue) {
+        } else if (use_graph) {
           hipGraphExec_t ex;
           if ((st = graph_for(j, m, &ex))) return st;
           ILH_HIP(c, hipGraphLaunch(ex, c->stream));
@@ -1199,7 +1368,7 @@ struct Solver {
           if ((st = check(j - 1, end))) return st;
           if (end) {
             j_end = j;  // step j was speculative
-            if (dev_end) drop_skipped();  // and its launches returned at once
+            if (dev_end && enqueue) drop_skipped();  // and its launches returned at once
           }
         }
       }
@@ -1306,7 +1475,7 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
     // backtracking: det J > 0 at every quadrature point of the stage positions, and (when
     // enabled) sufficient decrease ||R(k + a dk)|| <= (1 - 1e-4 a) ||R(k)||
     double alpha = 1.0, best = INFINITY, best_alpha = 0.0;
-    bool ok = false, any_valid = false;
+    bool ok = false, any_valid = false, nonfinite = false;
     for (int h = 0; h <= o->max_halvings; ++h) {
       if ((st = launch_waxpy(c, kt, k, alpha, dk, n))) return st;
       // the trial residual is formed before det J > 0 is known (it is discarded otherwise), so
@@ -1321,7 +1490,10 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
       if ((st = dot_dev(c, rt, rt, n, dsc + 1))) return st;
       double md, nrt2;
       if ((st = read_pair(c, &md, &nrt2))) return st;
-      if (md > 0.0) {
+      // a NaN det J (non-finite stage positions) or a non-finite residual at valid positions
+      // is reported as ENONFINITE if no trial succeeds, not as tangling
+      if (std::isnan(md) || (md > 0.0 && !std::isfinite(nrt2))) nonfinite = true;
+      if (md > 0.0 && std::isfinite(nrt2)) {
         any_valid = true;
         const double nrt = std::sqrt(nrt2);
         if (!o->ls_residual || nrt <= (1.0 - 1e-4 * alpha) * nr) {
@@ -1347,8 +1519,9 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
       ok = true;
     }
     if (!ok) {
-      status = ILH_ETANGLED;
-      c->err = "line search could not keep det J > 0";
+      status = nonfinite ? ILH_ENONFINITE : ILH_ETANGLED;
+      c->err = nonfinite ? "line search: non-finite stage positions or residual"
+                         : "line search could not keep det J > 0";
       break;
     }
     std::swap(k, kt);
@@ -1371,22 +1544,29 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
 extern "C" {
 
 int ilh_set_apply_rows(ilh_ctx* c, int rows) {
+  ILH_TRY
   if (!c) return ILH_EINVAL;
   if (rows < 0) return fail(c, ILH_EINVAL, "apply rows must be >= 0");
   c->apply_rows = rows;
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_set_apply_waves(ilh_ctx* c, int waves) {
+  ILH_TRY
   if (!c) return ILH_EINVAL;
   if (waves < 0 || waves > 2) return fail(c, ILH_EINVAL, "apply waves must be 0, 1 or 2");
   c->apply_waves = waves;
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_set_kernel_variant(ilh_ctx* c, int variant) {
+  ILH_TRY
   if (!c) return ILH_EINVAL;
   if (variant < 0 || variant > 2) return fail(c, ILH_EINVAL, "kernel variant must be 0, 1 or 2");
+  if (c->general && variant != 1)
+    return fail(c, ILH_EINVAL, "curved initial meshes and faces without walls run on the generic kernels (variant 1)");
   if (variant != c->jvp_variant) c->qd_ok[0] = c->qd_ok[1] = false;
   // the recompute kernels read the FP32 shadow of w, which the linearised variant does not keep
   if (variant != 0 && c->w64) {
@@ -1395,9 +1575,11 @@ int ilh_set_kernel_variant(ilh_ctx* c, int variant) {
   }
   c->jvp_variant = variant;
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_timing_enable(ilh_ctx* c, int on) {
+  ILH_TRY
   if (!c) return ILH_EINVAL;
   int st = tflush(c);
   if (st) return st;
@@ -1412,9 +1594,11 @@ int ilh_timing_enable(ilh_ctx* c, int on) {
     c->tcnt[i] = 0;
   }
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_timing_read(ilh_ctx* c, double* ms, int64_t* cnt) {
+  ILH_TRY
   if (!c || !ms || !cnt) return ILH_EINVAL;
   int st = tflush(c);
   if (st) return st;
@@ -1423,18 +1607,22 @@ int ilh_timing_read(ilh_ctx* c, double* ms, int64_t* cnt) {
     cnt[i] = c->tcnt[i];
   }
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_stage_solve(ilh_ctx* c, const double* ubase, double tau, const double* k_guess, double* k_out,
                     const ilh_newton_opts* o, ilh_step_stats* st) {
+  ILH_TRY
   if (!c || !ubase || !o) return ILH_EINVAL;
   if (o->restart < 1 || o->gmres_maxit < 1 || o->max_newton < 0 || (o->jvp_prec != 32 && o->jvp_prec != 64))
     return fail(c, ILH_EINVAL, "bad Newton options");
   return stage_solve(c, ubase, tau, k_guess, k_out, o, st);
+  ILH_CATCH(c)
 }
 
 int ilh_implicit_step(ilh_ctx* c, double* u, double dt, const double* k_guess, double* k_out,
                       const ilh_newton_opts* o, ilh_step_stats* st) {
+  ILH_TRY
   if (!c || !u || !o || !(dt > 0)) return ILH_EINVAL;
   if (o->restart < 1 || o->gmres_maxit < 1 || o->max_newton < 0 || (o->jvp_prec != 32 && o->jvp_prec != 64))
     return fail(c, ILH_EINVAL, "bad Newton options");
@@ -1445,6 +1633,7 @@ int ilh_implicit_step(ilh_ctx* c, double* u, double dt, const double* k_guess, d
   if (s2) return s2;
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 // SDIRK tableaux of Sec. 4 from their published closed forms.  SD2: implicit midpoint.  SD3:
@@ -1498,6 +1687,7 @@ static bool sdirk_tab(int scheme, SdirkTab* t) {
 
 int ilh_guess_infer(ilh_ctx* c, const ilh_guess_model* m, const double* u, const double* base, double tau,
                     double* k, int* used) {
+  ILH_TRY
   if (!c || !m || !u || !base || !k || m->nl < 1 || m->nl > 7 || !m->W || !m->b) return ILH_EINVAL;
   auto pad = [](int w) { return (w + 31) / 32 * 32; };
   for (int l = 0; l <= m->nl; ++l)
@@ -1539,9 +1729,11 @@ int ilh_guess_infer(ilh_ctx* c, const ilh_guess_model* m, const double* u, const
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   if (used) *used = use ? 1 : 0;
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_probe_blocks(ilh_ctx* c, int mode, double* dv, double* einv) {
+  ILH_TRY
   if (!c || (mode != 1 && mode != 2)) return ILH_EINVAL;
   int st;
   if ((st = ensure_solver_ws(c, 1))) return st;
@@ -1551,10 +1743,12 @@ int ilh_probe_blocks(ilh_ctx* c, int mode, double* dv, double* einv) {
     ILH_HIP(c, hipMemcpyAsync(einv, c->peinv, (size_t)c->Ne * c->Nl * c->Nl * sizeof(double), hipMemcpyDeviceToDevice,
                               c->stream));
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k_guess, double* k_out,
                    const ilh_newton_opts* o, ilh_step_stats* st) {
+  ILH_TRY
   if (!c || !u || !o || !(dt > 0)) return ILH_EINVAL;
   if (o->restart < 1 || o->gmres_maxit < 1 || o->max_newton < 0 || (o->jvp_prec != 32 && o->jvp_prec != 64))
     return fail(c, ILH_EINVAL, "bad Newton options");
@@ -1600,11 +1794,13 @@ int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   if (st) *st = acc;
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_adaptive_step(ilh_ctx* c, double* u, double* dt, double dt_max, int scheme, const double* k_guess,
                       double* k_out, const ilh_newton_opts* o, ilh_step_stats* st, int max_reject, int* rejected,
                       double* dt_taken) {
+  ILH_TRY
   if (!c || !u || !dt || !o || !(*dt > 0) || !(dt_max > 0) || max_reject < 0) return ILH_EINVAL;
   SdirkTab T;
   if (!sdirk_tab(scheme, &T)) return fail(c, ILH_EINVAL, "scheme must be 2 (SD2), 3 (SD3) or 4 (SD4)");
@@ -1640,6 +1836,7 @@ int ilh_adaptive_step(ilh_ctx* c, double* u, double* dt, double dt_max, int sche
     }
     h *= 0.85;
   }
+  ILH_CATCH(c)
 }
 
 }  // extern "C"

@@ -300,7 +300,7 @@ __global__ void k_assemble_nodes(const KParams P, const double* acc, const doubl
   const int mx = (I % k == 0 && I > 0 && I < P.ng[0] - 1) ? 2 : 1;
   const int my = (J % k == 0 && J > 0 && J < P.ng[1] - 1) ? 2 : 1;
   const int gc = (c == 0) ? I : J, ngc = P.ng[c];
-  const bool cons = gc == 0 || gc == ngc - 1;
+  const bool cons = on_wall(P.walls, c, gc, ngc);
   const double kv = cons ? 0.0 : base[2 * N + i] + acc[i] / (mx * my);
   kout[2 * N + i] = kv;
   kout[i] = u[2 * N + i] + tau * kv;
@@ -366,6 +366,7 @@ extern "C" {
 
 int ilh_guess_features(ilh_ctx* c, const double* u, const double* base, double vs, double es, double xs,
                        double kvs, double kes, const float* mu, const float* sd, float* feat, int ld) {
+  ILH_TRY
   if (!c || !u || !feat || c->dim != 2) return fail(c, ILH_EINVAL, "guess features: 2D only, non-null u/feat");
   const int ND = (c->k + 1) * (c->k + 1), NL = c->k * c->k;
   const int nin = 2 * ND + NL + 8 + (base ? 2 * ND + NL : 0);
@@ -375,10 +376,12 @@ int ilh_guess_features(ilh_ctx* c, const double* u, const double* base, double v
                      xs, kvs, kes, mu, sd, feat, ld);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_guess_targets(ilh_ctx* c, const double* kk, const double* base, double kvs, double kes, const float* osc,
                       float* t, int ld) {
+  ILH_TRY
   if (!c || !kk || !t || c->dim != 2) return fail(c, ILH_EINVAL, "guess targets: 2D only");
   const int ND = (c->k + 1) * (c->k + 1), NL = c->k * c->k;
   if (ld < 2 * ND + NL || !(kvs > 0 && kes > 0)) return fail(c, ILH_EINVAL, "target stride/scales");
@@ -386,10 +389,12 @@ int ilh_guess_targets(ilh_ctx* c, const double* kk, const double* base, double k
                      osc, t, ld);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_guess_assemble(ilh_ctx* c, const float* pred, int ld, double kvs, double kes, const float* osc,
                        const double* base, const double* u, double tau, double* kout) {
+  ILH_TRY
   if (!c || !pred || !base || !u || !kout || c->dim != 2) return fail(c, ILH_EINVAL, "guess assemble: 2D only");
   const int ND = (c->k + 1) * (c->k + 1), NL = c->k * c->k;
   if (ld < 2 * ND + NL) return fail(c, ILH_EINVAL, "prediction stride too small");
@@ -404,10 +409,12 @@ int ilh_guess_assemble(ilh_ctx* c, const float* pred, int ld, double kvs, double
                      kes, osc, base, kout);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_mlp_forward(ilh_ctx* c, int nl, const int* widths, const uint16_t* W, const float* b, const float* x,
                     int batch, float* zs, float* acts) {
+  ILH_TRY
   if (!c || !widths || !W || !b || !x || !zs || !acts || batch < 0) return ILH_EINVAL;
   int st = check_widths(c, nl, widths);
   if (st) return st;
@@ -426,11 +433,13 @@ int ilh_mlp_forward(ilh_ctx* c, int nl, const int* widths, const uint16_t* W, co
   }
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_mlp_backward(ilh_ctx* c, int nl, const int* widths, const uint16_t* WT, const float* x, const float* zs,
                      const float* acts, const float* target, int batch, float* dW, float* db, float* work,
                      double* loss) {
+  ILH_TRY
   if (!c || !widths || !WT || !x || !zs || !acts || !target || !dW || !db || !work || batch <= 0) return ILH_EINVAL;
   int st = check_widths(c, nl, widths);
   if (st) return st;
@@ -475,19 +484,23 @@ int ilh_mlp_backward(ilh_ctx* c, int nl, const int* widths, const uint16_t* WT, 
     *loss = c->red_host[2];
   }
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_mlp_adam(ilh_ctx* c, int64_t n, float* p, const float* g, float* m1, float* m2, int step, double lr,
                  double beta1, double beta2, double eps) {
+  ILH_TRY
   if (!c || !p || !g || !m1 || !m2 || n < 0 || step < 1) return ILH_EINVAL;
   const double bc1 = 1.0 / (1.0 - std::pow(beta1, step)), bc2 = 1.0 / (1.0 - std::pow(beta2, step));
   hipLaunchKernelGGL(k_adam, dim3(1024), dim3(256), 0, c->stream, n, p, g, m1, m2, (float)beta1, (float)beta2,
                      (float)lr, (float)bc1, (float)bc2, (float)eps);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 int ilh_mlp_pack(ilh_ctx* c, int nl, const int* widths, const float* Wmaster, uint16_t* W, uint16_t* WT) {
+  ILH_TRY
   if (!c || !widths || !Wmaster || !W || !WT) return ILH_EINVAL;
   int st = check_widths(c, nl, widths);
   if (st) return st;
@@ -499,6 +512,7 @@ int ilh_mlp_pack(ilh_ctx* c, int nl, const int* widths, const float* Wmaster, ui
   }
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
+  ILH_CATCH(c)
 }
 
 }  // extern "C"

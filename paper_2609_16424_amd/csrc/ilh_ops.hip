@@ -91,7 +91,7 @@ __global__ void k_scale_free(double* y, double a, const double* x, KParams P) {
     g = node % P.ng[1];
   }
   if (c == 2) g = node / P.ng[1];
-  const bool cons = g == 0 || g == P.ng[c] - 1;
+  const bool cons = on_wall(P.walls, c, g, P.ng[c]);
   y[i] = cons ? 0.0 : a * x[i];
 }
 
@@ -133,14 +133,14 @@ __device__ __forceinline__ double block_sum(double v) {
 template <int BS>
 __device__ __forceinline__ double block_min(double v) {
   __shared__ double sh[BS / 64];
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+  for (int o = 32; o > 0; o >>= 1) v = nan_min(v, __shfl_down(v, o, 64));
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   double r = v;
   if (threadIdx.x == 0) {
     r = sh[0];
-    for (int i = 1; i < BS / 64; ++i) r = fmin(r, sh[i]);
+    for (int i = 1; i < BS / 64; ++i) r = nan_min(r, sh[i]);
   }
   __syncthreads();
   return r;
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(TPB) k_dot_part(const double* x, const double*
 }
 __global__ void __launch_bounds__(TPB) k_sum_final(const double* part, int np, double* out, int is_min) {
   double acc = is_min ? 1e300 : 0.0;
-  for (int i = threadIdx.x; i < np; i += TPB) acc = is_min ? fmin(acc, part[i]) : acc + part[i];
+  for (int i = threadIdx.x; i < np; i += TPB) acc = is_min ? nan_min(acc, part[i]) : acc + part[i];
   acc = is_min ? block_min<TPB>(acc) : block_sum<TPB>(acc);
   if (threadIdx.x == 0) *out = acc;
 }
@@ -577,7 +577,8 @@ int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
 // reduction and Givens update of the previous Arnoldi step, and every other block forms the
 // scale that reduction stores, sc = 1 / |r|, from the same partial sums.
 __global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
-                          const double* __restrict__ Minv, const double* __restrict__ escale, double* z, float* z32,
+                          const double* __restrict__ Minv, int64_t estride, const double* __restrict__ escale,
+                          double* z, float* z32,
                           double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v,
                           const double* tau_dev, const double* rs, const GivensJob g) {
   if (g.skip && *g.skip != 0.0) return;
@@ -601,9 +602,10 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
   } else if (i < nh1 + Ne * Nl) {
     const int64_t k = i - nh1, e = k / Nl;
     const int rr = (int)(k % Nl);
+    const double* Me = Minv + e * estride;
     double acc = 0;
-    for (int j = 0; j < Nl; ++j) acc += Minv[rr * Nl + j] * r[2 * nh1 + e * Nl + j];
-    const double x = sc * escale[e] * acc;
+    for (int j = 0; j < Nl; ++j) acc += Me[rr * Nl + j] * r[2 * nh1 + e * Nl + j];
+    const double x = sc * (escale ? escale[e] * acc : acc);
     z[2 * nh1 + k] = x;
     if (z32) z32[2 * nh1 + k] = (float)x;
   }
@@ -614,8 +616,8 @@ int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double ta
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   const GivensJob g = job ? *job : GivensJob{};
   const unsigned nb = (unsigned)((n + TPB - 1) / TPB) + (job ? 1u : 0u);
-  hipLaunchKernelGGL(k_precond, dim3(nb), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv, c->MEinv + c->Nl * c->Nl, z,
-                     z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs, g);
+  hipLaunchKernelGGL(k_precond, dim3(nb), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv, c->me_stride, c->me_scale,
+                     z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs, g);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -830,7 +832,7 @@ __global__ void __launch_bounds__(256) k_mass(const KParams P, const double* x, 
       const int ex = e % P.n[0], ey = (e / P.n[0]) % P.n[1], ez = (DIM == 3) ? e / (P.n[0] * P.n[1]) : 0;
       const int I = k * ex + a, J = k * ey + b, K = k * ez + cc;
       const int gc = (c == 0) ? I : (c == 1 ? J : K);
-      const bool cons = gc == 0 || gc == P.ng[c] - 1;
+      const bool cons = on_wall(P.walls, c, gc, P.ng[c]);
       val = (bc && cons) ? 0.0 : x[c * N + I + s1 * J + s2 * K];
     }
     sX[zz][c][li] = val;
@@ -924,7 +926,7 @@ __global__ void __launch_bounds__(256) k_mass(const KParams P, const double* x, 
     const int I = k * ex + a, J = k * ey + b, K = k * ez + cc;
     const int64_t gi = c * N + I + s1 * J + s2 * K;
     const int gc = (c == 0) ? I : (c == 1 ? J : K);
-    const bool cons = gc == 0 || gc == P.ng[c] - 1;
+    const bool cons = on_wall(P.walls, c, gc, P.ng[c]);
     if (bc && cons) {
       const bool owner = (a < k || ex == P.n[0] - 1) && (b < k || ey == P.n[1] - 1) &&
                          (DIM == 2 || cc < k || ez == P.n[2] - 1);
@@ -970,20 +972,25 @@ static int mass_apply(ilh_ctx* c, const double* x, double* y, int bc) {
 int launch_mass_v(ilh_ctx* c, const double* x, double* y, int bc) { return mass_apply(c, x, y, bc); }
 
 // x_e = s_e Minv_ref b_e  (M_E,e = rho0_e |J0| Mref on the affine initial mesh)
-__global__ void k_me_inv(const double* Minv, const double* scale, const double* b, double* x, int64_t Ne, int Nl) {
+// x_e = scale_e Minv_e b_e with Minv_e = Minv + e * stride (stride 0: one reference inverse for
+// every element of an affine initial mesh, scaled by 1 / (rho0 |J0|)_e; stride Nl^2: per-element
+// inverses of a curved initial mesh, scale nullptr)
+__global__ void k_me_inv(const double* Minv, int64_t stride, const double* scale, const double* b, double* x,
+                         int64_t Ne, int Nl) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= Ne * Nl) return;
   const int64_t e = i / Nl;
   const int r = (int)(i % Nl);
+  const double* Me = Minv + e * stride;
   double acc = 0;
-  for (int j = 0; j < Nl; ++j) acc += Minv[r * Nl + j] * b[e * Nl + j];
-  x[i] = scale[e] * acc;
+  for (int j = 0; j < Nl; ++j) acc += Me[r * Nl + j] * b[e * Nl + j];
+  x[i] = scale ? scale[e] * acc : acc;
 }
 int launch_mass_e_inv(ilh_ctx* c, const double* b, double* x) {
   const int64_t n = c->Ne * c->Nl;
   if (n == 0) return ILH_OK;
   hipLaunchKernelGGL(k_me_inv, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, c->stream, c->MEinv,
-                     c->MEinv + c->Nl * c->Nl, b, x, c->Ne, c->Nl);
+                     c->me_stride, c->me_scale, b, x, c->Ne, c->Nl);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -1266,7 +1273,7 @@ int energy_host(ilh_ctx* c, const double* u, double* ke, double* ie) {
 // nodes: x0 on the affine mesh, v0 = nodal interpolation of the problem velocity
 template <int DIM>
 __global__ void k_init_nodes(const KParams P, int prob, double lo0, double lo1, double lo2, double h0, double h1,
-                             double h2, double* u) {
+                             double h2, const double* x0, double* u) {
   const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (node >= P.N) return;
   const int k = P.k, Q1D = 2 * k, D1D = k + 1, L1D = k;
@@ -1283,9 +1290,11 @@ __global__ void k_init_nodes(const KParams P, int prob, double lo0, double lo1, 
     const int loc = gi[d] - k * ex;
     X[d] = lo[d] + hh[d] * (ex + gll[loc]);
   }
+  if (x0)
+    for (int d = 0; d < DIM; ++d) X[d] = x0[d * P.N + node];
   for (int c = 0; c < DIM; ++c) {
     u[c * P.N + node] = X[c];
-    const bool cons = gi[c] == 0 || gi[c] == P.ng[c] - 1;
+    const bool cons = on_wall(P.walls, c, gi[c], P.ng[c]);
     u[DIM * P.N + c * P.N + node] = cons ? 0.0 : prob_velocity(prob, c, X);
   }
 }
@@ -1306,7 +1315,7 @@ __device__ inline double prob_energy(int prob, const double* X, double gam, doub
 // rhs_j = sum_q m_q e0(x0_q) phi_j(xi_q), one thread per (element, j)
 template <int DIM>
 __global__ void k_init_rhs(const KParams P, int prob, const double* e0, double lo0, double lo1, double lo2,
-                           double h0, double h1, double h2, double* rhs) {
+                           double h0, double h1, double h2, const double* x0, double* rhs) {
   const int k = P.k, Q1D = 2 * k, D1D = k + 1, L1D = k;
   const int NLn = (DIM == 2) ? L1D * L1D : L1D * L1D * L1D;
   const int NQ = (DIM == 2) ? Q1D * Q1D : Q1D * Q1D * Q1D;
@@ -1327,6 +1336,21 @@ __global__ void k_init_rhs(const KParams P, int prob, const double* e0, double l
       X[d] = lo[d] + hh[d] * (ei[d] + xg[qi[d]]);
       ph *= BL[qi[d] * L1D + jl[d]];
     }
+    if (x0) {  // curved initial mesh: x0(xi_q) = sum_n x0_n w_n(xi_q)
+      const int NDn = (DIM == 2) ? D1D * D1D : D1D * D1D * D1D;
+      for (int d = 0; d < DIM; ++d) X[d] = 0;
+      for (int li = 0; li < NDn; ++li) {
+        const int a[3] = {li % D1D, (li / D1D) % D1D, (DIM == 3) ? li / (D1D * D1D) : 0};
+        double wn = 1;
+        int64_t node = 0, stride = 1;
+        for (int d = 0; d < DIM; ++d) {
+          wn *= P.tab[qi[d] * D1D + a[d]];
+          node += (int64_t)(k * ei[d] + a[d]) * stride;
+          stride *= P.ng[d];
+        }
+        for (int d = 0; d < DIM; ++d) X[d] += wn * x0[d * P.N + node];
+      }
+    }
     acc += P.mq[(int64_t)e * NQ + q] * prob_energy(prob, X, gam, e0[e]) * ph;
   }
   rhs[i] = acc;
@@ -1338,20 +1362,20 @@ int init_state_dev(ilh_ctx* c, double* u, const double*) {
   const int nb = (int)((c->N + 255) / 256);
   if (c->dim == 2)
     hipLaunchKernelGGL(k_init_nodes<2>, dim3(nb), dim3(256), 0, c->stream, c->kp, c->s.problem, c->lo[0], c->lo[1],
-                       c->lo[2], h[0], h[1], h[2], u);
+                       c->lo[2], h[0], h[1], h[2], c->x0, u);
   else
     hipLaunchKernelGGL(k_init_nodes<3>, dim3(nb), dim3(256), 0, c->stream, c->kp, c->s.problem, c->lo[0], c->lo[1],
-                       c->lo[2], h[0], h[1], h[2], u);
+                       c->lo[2], h[0], h[1], h[2], c->x0, u);
   const int64_t nl = c->Ne * c->Nl;
   double* rhs = c->ws;
   if (c->ws_len < nl) return fail(c, ILH_EINVAL, "workspace too small for the initial state");
   const int nb2 = (int)((nl + 255) / 256);
   if (c->dim == 2)
     hipLaunchKernelGGL(k_init_rhs<2>, dim3(nb2), dim3(256), 0, c->stream, c->kp, c->s.problem, c->e0, c->lo[0],
-                       c->lo[1], c->lo[2], h[0], h[1], h[2], rhs);
+                       c->lo[1], c->lo[2], h[0], h[1], h[2], c->x0, rhs);
   else
     hipLaunchKernelGGL(k_init_rhs<3>, dim3(nb2), dim3(256), 0, c->stream, c->kp, c->s.problem, c->e0, c->lo[0],
-                       c->lo[1], c->lo[2], h[0], h[1], h[2], rhs);
+                       c->lo[1], c->lo[2], h[0], h[1], h[2], c->x0, rhs);
   ILH_HIP(c, hipGetLastError());
   return launch_mass_e_inv(c, rhs, u + 2 * c->nh1);
 }

@@ -29,6 +29,10 @@ __device__ __forceinline__ float f_cbrt(float x) { return cbrtf(x); }
 __device__ __forceinline__ double f_tanh(double x) { return tanh(x); }
 __device__ __forceinline__ float f_tanh(float x) { return tanhf(x); }
 
+// Minimum that propagates NaN from either argument (fmin drops it), so that a non-finite
+// det J or time-step candidate is not mistaken for a valid one.
+__device__ __forceinline__ double nan_min(double a, double b) { return (a != a || a < b) ? a : b; }
+
 template <int D, typename T>
 __device__ __forceinline__ void inv_det(const T J[D][D], T Ji[D][D], T& det) {
   if constexpr (D == 2) {

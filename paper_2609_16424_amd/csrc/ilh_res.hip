@@ -204,7 +204,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
         ke += tb.BL[qy][bl] * ALk[bl];
       }
       const double mq = wx * tb.W[qy];
-      if (dmin) dm = fmin(dm, J[0][0] * J[1][1] - J[0][1] * J[1][0]);
+      if (dmin) dm = nan_min(dm, J[0][0] * J[1][1] - J[0][1] * J[1][0]);
       double S[2][2], sq;
       qp_force<2, double>(P, gam, mq, dJ0, J, Gv, eq, S, sq);
       double cl = mq * ke - sq;
@@ -236,7 +236,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
   __syncthreads();
   if (dmin) {  // the work-group's smallest det J of the stage positions w_x
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dm = fmin(dm, __shfl_xor(dm, o, 64));
+    for (int o = 32; o > 0; o >>= 1) dm = nan_min(dm, __shfl_xor(dm, o, 64));
     if (lane == 0) dmin[blockIdx.y * gridDim.x + blockIdx.x] = dm;
   }
 
@@ -482,7 +482,7 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
       }
       const double mq = wxy * tb.W[qz];
       if (dmin)
-        dm = fmin(dm, J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+        dm = nan_min(dm, J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]));
       double S[3][3], sq;
@@ -567,7 +567,7 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
   __syncthreads();
   if (dmin) {  // the work-group's smallest det J of the stage positions w_x
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dm = fmin(dm, __shfl_xor(dm, o, 64));
+    for (int o = 32; o > 0; o >>= 1) dm = nan_min(dm, __shfl_xor(dm, o, 64));
     if (lane == 0) dmin[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = dm;
   }
   if (active) {
@@ -582,11 +582,11 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
 
 // ---- host side ---------------------------------------------------------------------------
 bool res2d_available(const ilh_ctx* c) {
-  return c->dim == 2 && (c->k == 2 || c->k == 3) && c->nblock < (int64_t(1) << 28);
+  return c->dim == 2 && (c->k == 2 || c->k == 3) && c->nblock < (int64_t(1) << 28) && !c->general;
 }
 
 bool res3d_available(const ilh_ctx* c) {
-  return c->dim == 3 && c->k == 2 && !c->kp.tg_source && c->nblock < (int64_t(1) << 28);
+  return c->dim == 3 && c->k == 2 && !c->kp.tg_source && c->nblock < (int64_t(1) << 28) && !c->general;
 }
 
 template <int K, int SRC>

@@ -39,3 +39,18 @@ def zero_rows(d, mask_rows):
     d = np.array(d, copy=True)
     d[mask_rows] = 0.0
     return d
+
+
+def curved_positions(x0, lo, hi, amp):
+    """A smooth interior displacement of the node positions x0 [dim][N] of a box mesh:
+    x_c <- x_c + amp (hi_c - lo_c) prod_a sin(pi t_a), t_a = (x_a - lo_a)/(hi_a - lo_a).
+    It vanishes on the box faces, so the boundary nodes stay where they are."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    dim = x0.shape[0]
+    bump = np.ones(x0.shape[1])
+    for a in range(dim):
+        bump *= np.sin(np.pi * (x0[a] - lo[a]) / (hi[a] - lo[a]))
+    out = x0.copy()
+    for c in range(dim):
+        out[c] += amp * (hi[c] - lo[c]) * bump * (1.0 if c % 2 == 0 else -0.5)
+    return out

@@ -12,6 +12,27 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def maxrel(a, b):
+    """Entry-wise bound: max |a - b| over max |b| (a few wrong entries of a long vector show here
+    even when the 2-norm ratio hides them)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / (mb if mb > 0 else 1.0)) if b.size else 0.0
+
+
+def blocks_close(a, b, nh1, tol):
+    """Both bounds on every block [x | v | e] of a block vector: the 2-norm ratio and the
+    entry-wise max bound, each block against its own scale.  Returns the worst ratio to tol."""
+    worst = 0.0
+    for sl in (slice(0, nh1), slice(nh1, 2 * nh1), slice(2 * nh1, None)):
+        bb = np.asarray(b)[sl]
+        if bb.size == 0 or not np.any(bb):
+            continue
+        worst = max(worst, rel(np.asarray(a)[sl], bb) / tol, maxrel(np.asarray(a)[sl], bb) / tol)
+    return worst
+
+
 def to_dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 

@@ -53,3 +53,34 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+_ENOMEM_CHILD = r"""
+import ctypes, resource, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2609_16424_amd import _lib
+lib = _lib.load()
+s = _lib.Setup()
+s.dim = 2
+s.n[0] = s.n[1] = 5000          # Q4Q3: 2.5e7 elements x 64 points
+s.order_v = 4
+lib.ilh_setup_defaults(ctypes.byref(s), _lib.PROBLEMS["uniform"])
+# cap the address space so that the host arrays of 1.6e9 quadrature points (13 GB each) cannot
+# be allocated, while the per-element arrays (0.2 GB each) still can
+lim = 3 << 30
+resource.setrlimit(resource.RLIMIT_AS, (lim, lim))
+ctx = ctypes.c_void_p()
+st = lib.ilh_create(ctypes.byref(s), None, ctypes.byref(ctx))
+print("STATUS", st, ctx.value)
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libilh.so not built")
+def test_create_reports_enomem_instead_of_throwing():
+    """A host allocation failure inside ilh_create returns ILH_ENOMEM (3) and no context; the
+    std::bad_alloc does not reach the caller (the process would abort)."""
+    r = subprocess.run(["python", "-c", _ENOMEM_CHILD, ROOT], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = [l for l in r.stdout.splitlines() if l.startswith("STATUS")][-1].split()
+    assert line[1] == "3" and line[2] == "None", (r.stdout, r.stderr[-500:])
+    assert "host allocation failed" in r.stderr

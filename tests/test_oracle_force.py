@@ -216,3 +216,45 @@ def test_affinely_deformed_mesh_closed_form(dim, k, visc):
         interior &= ~m.constrained[c]
     if interior.any():
         assert np.abs(F1.reshape(dim, -1)[:, interior]).max() < 1e-10 * np.abs(F1).max()
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (2, 3), (3, 2)])
+@pytest.mark.parametrize("m", [1.0, -1.0, 2.0, -2.0])
+def test_viscosity_formula_scale_closed_form(dim, k, m):
+    """The paper's smoothing scale delta_scale = 2 (h / h_coarse) c_s (eq. visc_imp_scale) and the
+    switch psi = (1 + tanh((-delta_v - s) / (2 delta_scale))) / 2 (eq. visc_imp_switch, s = 0 at
+    psi0 = 1/2), pinned through the work of the force on an affinely compressed or expanded gas.
+
+    x = B x0 (diagonal B, det B != 1), v = a x, constant e: then rho = 1 / det B, h = h0 (det B)^(1/d),
+    grad v = a I and delta_v = h d a.  The velocity scale is chosen as a = m delta_scale / (h d), so
+    that delta_v = m delta_scale and the smoothed quantities take the values
+        |delta_v|_s = delta_scale sqrt(1 + m^2),   psi = (1 + tanh(-m / 2)) / 2,
+    and mu = rho h (q2 |delta_v|_s + q1 c_s psi).  The stress is (-p + mu a) I, so
+    (F^T v)_j = (-p + mu a) d a det B |Omega_e| / k^d.  h_coarse differs from h0, so the ratio
+    h / h_coarse matters; a factor 2 dropped from delta_scale or from the tanh width moves psi and
+    |delta_v|_s away from these values.
+    """
+    hc = 0.6 * (1.0 / 2) / k  # h_coarse != h0 = 1 / (2 k) on the 2^d mesh of the unit box
+    vo = ViscosityOptions(on=True, mode="formula", h_coarse=hc)
+    H = Hydro("uniform", (2,) * dim, k, visc=vo)
+    u = H.init_state()
+    x, _, e = H.split(u)
+    Bd = np.array([1.2, 0.9, 1.1][:dim])
+    detB = float(np.prod(Bd))
+    X = Bd[:, None] * x.reshape(dim, -1)
+    ep = 0.5 * (2.5 + np.sqrt(2.5 ** 2 + EPS_E ** 2))
+    gam = 1.4
+    rho = 1.0 / detB
+    p = (gam - 1.0) * rho * ep
+    cs = np.sqrt(gam * (gam - 1.0) * ep)
+    h0 = (1.0 / 2 ** dim) ** (1.0 / dim) / k
+    h = h0 * detB ** (1.0 / dim)
+    dscale = 2.0 * (h / hc) * cs
+    a = m * dscale / (h * dim)
+    V = a * X
+    F1, Ftv = H.force(np.concatenate([X.ravel(), V.ravel(), e]))
+    mu = rho * h * (1.0 * dscale * np.sqrt(1.0 + m * m) + 0.5 * cs * 0.5 * (1.0 + np.tanh(-m / 2.0)))
+    expect = (-p + mu * a) * dim * a * detB * (0.5 ** dim) / k ** dim
+    assert np.allclose(Ftv, expect, rtol=1e-12, atol=0), (Ftv[:2], expect)
+    # the viscous part is a sizeable share of the work, so the check sees mu
+    assert abs(mu * a) > 0.05 * p
