@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import paper_2609_16424_amd as ilh
-from gpu_common import make_pair, rel, to_dev, to_np
+from gpu_common import close, make_pair, rel, to_dev, to_np
 from oracle.mlp import MLP, adam_step, bf16_round, pad32
 
 pytestmark = pytest.mark.gpu
@@ -99,6 +99,37 @@ def test_mlp_forward_and_gradients(B):
     for l in range(len(db)):
         assert rel(g[off:off + db[l].size], db[l]) <= 1e-2, l
         off += db[l].size
+    # layer by layer: the oracle takes the GPU's own layer inputs (activations rounded where the
+    # GPU rounded them), so only the FP32 accumulation differs
+    P = [pad32(w) for w in widths]
+    zg, ag = to_np(zs), to_np(acts)
+    zl, al, o = [], [], 0
+    for l in range(len(widths) - 1):
+        zl.append(zg[o:o + B * P[l + 1]].reshape(B, P[l + 1]))
+        al.append(ag[o:o + B * P[l + 1]].reshape(B, P[l + 1]))
+        o += B * P[l + 1]
+    from oracle.mlp import gelu
+    for l in range(len(widths) - 1):
+        xin = x.astype(np.float64) if l == 0 else al[l - 1]
+        Ol = MLP([widths[l], widths[l + 1]], [W[l]], [b[l]])
+        z_ref = Ol.forward(xin)[0][0]
+        assert close(zl[l], z_ref, 1e-6), (l, rel(zl[l], z_ref))
+        if l < len(widths) - 2:
+            assert close(al[l], gelu(zl[l].astype(np.float64)), 1e-6), l
+    # gradients from the GPU's forward values: BF16 rounding of dZ can still differ at ties
+    # (FP32 vs FP64 arithmetic before the rounding), each such entry moving one of B terms of a
+    # sum by 2^-8, and the flips of one layer feed the next: 1.1e-4 measured at the first layer
+    # (three layers down) for B = 300, so the bound is 1e-3 (ten times tighter than end to end)
+    dW2, db2, loss2 = O.backward(x, [z.astype(np.float64) for z in zl], [a.astype(np.float64) for a in al],
+                                 t.astype(np.float64))
+    assert abs(loss.value - loss2) <= 1e-6 * loss2
+    off = 0
+    for l in range(len(dW2)):
+        assert rel(g[off:off + dW2[l].size], dW2[l].ravel()) <= 1e-3, (l, rel(g[off:off + dW2[l].size], dW2[l].ravel()))
+        off += dW2[l].size
+    for l in range(len(db2)):
+        assert rel(g[off:off + db2[l].size], db2[l]) <= 1e-3, l
+        off += db2[l].size
 
 
 def test_adam_step_matches_oracle():

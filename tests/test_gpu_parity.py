@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import make_pair, random_dir, random_state, rel, to_dev, to_np
+from gpu_common import close, make_pair, maxrel, random_dir, random_state, rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,9 @@ def test_init_state(pair):
     u = to_np(G.init_state())
     uo = O.init_state()
     assert rel(u, uo) <= 1e-13
+    # entry-wise at the FP64 bound: the projection of e0 goes through M_E^-1, whose Bernstein
+    # blocks at k = 4 (3D: k = 3) are conditioned ~1e3, so single entries carry ~1e-13
+    assert close(u, uo, 1e-12, O.nh1), maxrel(u, uo)
 
 
 def test_force(pair):
@@ -50,8 +53,8 @@ def test_force(pair):
     w = random_state(O, 1)
     f1, ftv = G.force(to_dev(w))
     o1, otv = O.force(w)
-    assert rel(to_np(f1), o1) <= FP64_TOL
-    assert rel(to_np(ftv), otv) <= FP64_TOL
+    assert close(to_np(f1), o1, FP64_TOL)
+    assert close(to_np(ftv), otv, FP64_TOL)
 
 
 def test_residual(pair):
@@ -61,7 +64,7 @@ def test_residual(pair):
     tau = 0.003
     r = to_np(G.residual(to_dev(k), to_dev(u), tau))
     ro = O.residual(k, u, tau)
-    assert rel(r, ro) <= FP64_TOL
+    assert close(r, ro, FP64_TOL, O.nh1)
 
 
 @pytest.mark.parametrize("prec,tol", [(64, FP64_TOL), (32, FP32_TOL)])
@@ -75,10 +78,10 @@ def test_jvp(pair, prec, tol):
     dt = torch.float64 if prec == 64 else torch.float32
     j = to_np(G.jvp(to_dev(k), to_dev(u), tau, to_dev(dk, dt), prec))
     jo = jvp_cs(lambda q: O.residual(q, u, tau), k, dk)
-    assert rel(j, jo) <= tol, rel(j, jo)
+    assert close(j, jo, tol, O.nh1), rel(j, jo)
     # block-wise too: the x, v and e rows separately
     for a, b in ((0, O.nh1), (O.nh1, 2 * O.nh1), (2 * O.nh1, O.nblock)):
-        assert rel(j[a:b], jo[a:b]) <= 10 * tol
+        assert close(j[a:b], jo[a:b], 10 * tol)
 
 
 @pytest.mark.parametrize("prec,tol", [(64, FP64_TOL), (32, FP32_TOL)])
@@ -91,21 +94,21 @@ def test_force_jvp(pair, prec, tol):
     d1, dtv = G.force_jvp(to_dev(w), to_dev(dw, dt), prec)
     o1 = jvp_cs(lambda q: O.force(q)[0], w, dw)
     otv = jvp_cs(lambda q: O.force(q)[1], w, dw)
-    assert rel(to_np(d1), o1) <= tol
-    assert rel(to_np(dtv), otv) <= tol
+    assert close(to_np(d1), o1, tol)
+    assert close(to_np(dtv), otv, tol)
 
 
 def test_mass_operators(pair):
     O, G = pair
     rng = np.random.default_rng(9)
     x = rng.standard_normal(O.nh1)
-    assert rel(to_np(G.mass_v_apply(to_dev(x))), O.mass_v(x)) <= 1e-13
+    assert close(to_np(G.mass_v_apply(to_dev(x))), O.mass_v(x), 1e-13)
     e = rng.standard_normal(O.nl2)
-    assert rel(to_np(G.mass_e_inv(to_dev(e))), O.mass_e_inv(e)) <= 1e-13
+    assert close(to_np(G.mass_e_inv(to_dev(e))), O.mass_e_inv(e), 1e-13)
     b = O.mass_v(x)
     sol, its, rr = G.mass_v_solve(to_dev(b), 1e-13, 1000)
     assert rr <= 1e-13
-    assert rel(to_np(sol), O.mass_v_solve(b)) <= 1e-11
+    assert close(to_np(sol), O.mass_v_solve(b), 1e-11)
 
 
 def test_diagnostics(pair):
@@ -125,7 +128,7 @@ def test_rate(pair):
     O, G = pair
     u = random_state(O, 11, amp=0.01)
     f = to_np(G.rate(to_dev(u)))
-    assert rel(f, O.rate(u)) <= 1e-11
+    assert close(f, O.rate(u), 1e-11)
 
 
 def test_zero_direction_gives_zero():
@@ -155,8 +158,8 @@ def test_jvp_variants_agree(prob, n, k, visc, prec, tol):
         assert G.lib.ilh_set_kernel_variant(G.ctx, v) == 0
         out.append(to_np(G.jvp_lin(to_dev(dk, dt), prec)))
     G.lib.ilh_set_kernel_variant(G.ctx, 0)
-    assert rel(out[0], out[1]) <= tol
-    assert rel(out[2], out[1]) <= tol
+    assert close(out[0], out[1], tol)
+    assert close(out[2], out[1], tol)
 
 
 @pytest.mark.parametrize("prob,n,k,visc", [("tg2d", (23, 7), 3, None), ("triple", (21, 9), 3, "const"),
@@ -180,8 +183,8 @@ def test_apply_rows_match_oracle(prob, n, k, visc):
             G.set_apply_rows(R)
             a64 = to_np(G.jvp_lin(to_dev(dk), 64))
             a32 = to_np(G.jvp_lin(to_dev(dk, torch.float32), 32))
-            assert rel(a64, ref) <= 1e-12, (W, R)
-            assert rel(a32, ref) <= 1e-5, (W, R)
+            assert close(a64, ref, 1e-12), (W, R)
+            assert close(a32, ref, 1e-5), (W, R)
     G.set_apply_rows(0)
     G.set_apply_waves(0)
     from paper_2609_16424_amd import IlhError
@@ -206,9 +209,9 @@ def test_linearised_coefficients_follow_the_point():
         a32 = to_np(G.jvp_lin(to_dev(dk, torch.float32), 32))
         b64 = to_np(G.jvp_lin(to_dev(dk), 64))
         ref = jvp_cs(lambda q: O.residual(q, u, tau), kk, dk)
-        assert rel(a64, ref) <= 1e-12
-        assert rel(b64, a64) <= 1e-15  # same coefficients; atomic summation order may differ
-        assert rel(a32, ref) <= 1e-5
+        assert close(a64, ref, 1e-12)
+        assert close(b64, a64, 1e-15)  # same coefficients; atomic summation order may differ
+        assert close(a32, ref, 1e-5)
 
 
 @pytest.mark.parametrize("n,k", [((130, 330), 3), ((64, 1040), 2)])
@@ -267,9 +270,9 @@ def test_strip_residual_matches_oracle_and_generic(prob, n, k, visc):
     G.set_kernel_variant("generic")
     r_gen = to_np(G.residual(to_dev(kk), to_dev(u), tau))
     G.set_kernel_variant("lin")
-    assert rel(r_strip, ro) <= FP64_TOL
-    assert rel(r_gen, ro) <= FP64_TOL
-    assert rel(r_strip, r_gen) <= FP64_TOL
+    assert close(r_strip, ro, FP64_TOL)
+    assert close(r_gen, ro, FP64_TOL)
+    assert close(r_strip, r_gen, FP64_TOL)
 
 
 @pytest.mark.parametrize("n,k", [((130, 330), 3), ((64, 1040), 2), ((40, 24, 16), 2)])

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import paper_2609_16424_amd as ilh
-from gpu_common import make_pair, random_dir, random_state, rel, to_dev, to_np
+from gpu_common import close, make_pair, random_dir, random_state, rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +29,8 @@ def test_probe_blocks_match_dense_jacobian(prob, n, k, visc, mode):
                          for e in range(ne)])
     G.linearize(to_dev(kk), to_dev(u), tau)
     dv, einv = G.probe_blocks(mode)
-    assert rel(to_np(dv), dv_ref) <= 1e-5, rel(to_np(dv), dv_ref)
-    assert rel(to_np(einv).ravel(), einv_ref.ravel()) <= 1e-5, rel(to_np(einv).ravel(), einv_ref.ravel())
+    assert close(to_np(dv), dv_ref, 1e-5), rel(to_np(dv), dv_ref)
+    assert close(to_np(einv).ravel(), einv_ref.ravel(), 1e-5), rel(to_np(einv).ravel(), einv_ref.ravel())
 
 
 def test_probe_preconditioner_same_solution():
@@ -47,5 +47,5 @@ def test_probe_preconditioner_same_solution():
             k, st = G.implicit_step(u, dt, guess=g, opts=opts)
             hist = (hist + [k])[-2:]
         out.append(u)
-    assert rel(to_np(out[0]), to_np(out[1])) <= 1e-9
-    assert rel(to_np(out[0]), to_np(out[2])) <= 1e-9
+    assert close(to_np(out[0]), to_np(out[1]), 1e-9)
+    assert close(to_np(out[0]), to_np(out[2]), 1e-9)

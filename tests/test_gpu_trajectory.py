@@ -113,6 +113,46 @@ def test_speculative_arnoldi_step_does_no_counted_work():
         assert rel(to_np(u), states[n + 1]) <= 1e-8
 
 
+def test_iteration_limit_enqueues_no_extra_step():
+    """When the iteration limit (not convergence) ends every FGMRES solve, the host knows in advance
+    which step is the last one and enqueues none after it: the Jacobian actions counted equal the
+    GMRES iterations (restart 64: no restart actions), for both precisions of the action."""
+    O, G = make_pair("tg2d", (8, 8), 2)
+    u = to_dev(O.init_state())
+    for prec in (32, 64):
+        opts = ilh.newton_options(tol=1e-10, jvp_prec=prec, restart=64, gmres_maxit=3, gmres_rtol=1e-14,
+                                  max_newton=8)
+        k, st = G.implicit_step(u.clone(), 0.01, opts=opts, raise_on_fail=False)
+        assert st["newton"] >= 2
+        assert st["gmres"] >= 6 and st["gmres"] % 3 == 0, st
+        assert st["jvp_calls"] == st["gmres"], st
+
+
+def test_graph_replay_with_changing_dt():
+    """Graph replay (graphs = 1) against the kernel-by-kernel path when the time step grows from step
+    to step, so that later solves need more Arnoldi steps than the first one and capture new steps
+    in later cycles: the captured actions read tau from the device, so the trajectories agree."""
+    states, gm = {}, {}
+    for graphs in (0, 1):
+        G = ilh.Hydro("tg2d", (24, 20), 3)
+        u = G.init_state()
+        dt0 = G.dt_estimate(u, 0.5)
+        opts = ilh.newton_options(graphs=graphs, tol=1e-10, jvp_prec=32)
+        hist, traj, its = [], [], []
+        for n in range(5):
+            dt = (1.0 + 1.5 * n) * dt0
+            g = G.plain_guess(u, hist, 0.5 * dt)
+            k, st = G.implicit_step(u, dt, guess=g, opts=opts)
+            assert st["status"] == 0
+            hist = (hist + [k])[-2:]
+            traj.append(to_np(u))
+            its.append(st["gmres"] / max(1, st["newton"]))
+        states[graphs], gm[graphs] = traj, its
+    assert max(gm[1][1:]) > gm[1][0]  # later solves took longer Krylov cycles
+    for a, b in zip(states[0], states[1]):
+        assert rel(a, b) <= 1e-9
+
+
 @pytest.mark.parametrize("case", ["tg2d", "triple"])
 def test_graph_replay_matches_eager_launches(case):
     """Arnoldi steps replayed as captured HIP graphs give the trajectory of the kernel-by-kernel

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import make_pair, random_dir, random_state, rel, to_dev, to_np
+from gpu_common import close, make_pair, random_dir, random_state, rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +29,8 @@ def test_vjp_matches_oracle(prob, n, k, visc):
     G.linearize(to_dev(kk), to_dev(u), tau)
     a64 = to_np(G.vjp_lin(to_dev(y), 64))
     a32 = to_np(G.vjp_lin(to_dev(y, torch.float32), 32))
-    assert rel(a64, ref) <= 1e-12
-    assert rel(a32, ref) <= 1e-5
+    assert close(a64, ref, 1e-12)
+    assert close(a32, ref, 1e-5)
     # the forward action keeps working after the transpose (same stored coefficients)
     dk = random_dir(O, 64)
     j64 = to_np(G.jvp_lin(to_dev(dk), 64))
@@ -72,9 +72,9 @@ def test_residual_autograd_backward():
     r = ilh.ResidualFn.apply(G, k_t, to_dev(u), tau)
     (grad,) = torch.autograd.grad(r, k_t, grad_outputs=to_dev(gy))
     ref = vjp_colored(O, lambda q: O.residual(q, u, tau), kk, gy)
-    assert rel(to_np(grad), ref) <= 1e-12
+    assert close(to_np(grad), ref, 1e-12)
     _, fn = torch.func.vjp(lambda q: ilh.ResidualFn.apply(G, q, to_dev(u), tau), to_dev(kk))
-    assert rel(to_np(fn(to_dev(gy))[0]), ref) <= 1e-12
+    assert close(to_np(fn(to_dev(gy))[0]), ref, 1e-12)
 
 
 @pytest.mark.parametrize("n,visc", [((5, 2, 1), None), ((6, 1, 2), "formula")])
@@ -88,8 +88,8 @@ def test_vjp_3d_matches_oracle(n, visc):
     tau = 0.003
     ref = vjp_colored(O, lambda q: O.residual(q, u, tau), kk, y)
     G.linearize(to_dev(kk), to_dev(u), tau)
-    assert rel(to_np(G.vjp_lin(to_dev(y), 64)), ref) <= 1e-12
-    assert rel(to_np(G.vjp_lin(to_dev(y, torch.float32), 32)), ref) <= 1e-5
+    assert close(to_np(G.vjp_lin(to_dev(y), 64)), ref, 1e-12)
+    assert close(to_np(G.vjp_lin(to_dev(y, torch.float32), 32)), ref, 1e-5)
 
 
 @pytest.mark.parametrize("visc", [False, True])

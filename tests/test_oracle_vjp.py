@@ -44,3 +44,38 @@ def test_vjp_adjoint_identity(name, n, k, visc):
         dk = si.block_direction(s, O.nh1, O.nl2, sx=h, sv=1.0, se=1.0)
         lhs = y @ jvp_cs(fun, kk, dk)
         assert abs(lhs - a @ dk) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("prob,n,k", [("tg2d", (5, 4), 3), ("tg3d", (3, 2, 2), 2)])
+def test_local_complex_step_rows_and_columns(prob, n, k):
+    """The full-size sampled checks evaluate the complex step on the elements that reach the
+    sampled rows (or hold the sampled column's dof) only: on a small mesh those rows equal the
+    whole-mesh complex step, and <y, J e_j> equals the coloured transpose action's entry j."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from gpu_common import elements_of_dof, jvp_local
+    from oracle.hydro import Hydro
+    from oracle.krylov import jvp_cs, vjp_colored
+    import seeded_inputs as si
+    O = Hydro(prob, n, k)
+    h = float(np.min(O.mesh.h)) / k
+    u = si.perturb_state(O.init_state(), 1, O.nh1, 0.03 * h, 0.3, 0.2)
+    kk = 0.1 * si.block_direction(2, O.nh1, O.nl2, h, 1.0, 1.0)
+    dk = si.block_direction(3, O.nh1, O.nl2, h, 1.0, 1.0)
+    y = si.block_direction(4, O.nh1, O.nl2)
+    tau = 0.003
+    full = jvp_cs(lambda q: O.residual(q, u, tau), kk, dk)
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(O.nblock, 10, replace=False))
+    adj = np.unique(np.concatenate([elements_of_dof(O, r) for r in rows]))
+    assert len(adj) < O.mesh.Ne
+    loc = jvp_local(O, kk, u, tau, dk, adj)
+    assert np.abs(loc[rows] - full[rows]).max() <= 1e-13 * np.abs(full).max()
+    if O.dim == 3:
+        return  # the coloured transpose of the 3D oracle is pinned elsewhere (and slow)
+    vt = vjp_colored(O, lambda q: O.residual(q, u, tau), kk, y)
+    for j in rows:
+        ej = np.zeros(O.nblock)
+        ej[j] = 1.0
+        val = float(y @ jvp_local(O, kk, u, tau, ej, elements_of_dof(O, j)))
+        assert abs(val - vt[j]) <= 1e-12 * np.abs(vt).max()
