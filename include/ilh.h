@@ -160,6 +160,24 @@ int ilh_jvp_lin(ilh_ctx* ctx, int prec, const void* dk, void* jdk);
 int ilh_jvp(ilh_ctx* ctx, int prec, const double* k, const double* u, double tau,
             const void* dk, void* jdk);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ilh_jvp with the same kernels and result, whose own
+ * storage -- the point w = u + tau k (FP64) and the tangent coefficients of precision prec (the
+ * FP32 shadow of w for the recomputing kernels) -- lives in a static device array of the library
+ * of ILH_NOALLOC_SCRATCH_BYTES per GPU instead of buffers the context allocates on first use.  The
+ * call allocates nothing (no hipMalloc or hipFree; the library makes no host allocation on success).  The array is
+ * held by every GPU the library runs on until the process ends; its address on a device is taken
+ * when the first context is created there.  Limit: 8 n_block bytes plus the coefficients (2D Q3Q2
+ * without viscosity: 48 (FP32) or 96 (FP64) bytes per quadrature point) must fit, e.g. 2D Q3Q2 up
+ * to 128x128 elements in either precision, 3D Q2Q1 up to 32^3 in FP32; larger meshes: ILH_EINVAL
+ * (nothing launched).  Every call on one GPU shares that GPU's array and leaves its contents
+ * there; calls that overlap on one GPU (from several contexts or streams) race.  Nothing in the
+ * array needs to start at zero.  The context's own linearisation point (ilh_linearize) is left
+ * as it was.  Arguments, precision and layouts as for ilh_jvp. */
+#define ILH_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+int ilh_jvp_noalloc(ilh_ctx* ctx, int prec, const double* k, const double* u, double tau,
+                    const void* dk, void* jdk);
+
 /* Transpose Jacobian action J^T y at the stored linearisation point (the transpose of
  * eq. pa_jac_action; Sec. 3.4 notes that transpose actions keep the gather - pointwise -
  * scatter structure):

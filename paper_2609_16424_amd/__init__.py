@@ -187,6 +187,19 @@ class Hydro:
                                          self._vec(o, self.nblock, dt, "out")))
         return o
 
+    def jvp_noalloc(self, k, u, tau, dk, prec=64, out=None):
+        """ilh_jvp_noalloc: the Jacobian action with the library's static scratch (allocates nothing
+        on the device; `out`, if given, receives the result so that the call makes no allocation
+        through torch either)."""
+        dt = torch.float64 if prec == 64 else torch.float32
+        o = self.new(dtype=dt) if out is None else out
+        self._stream()
+        self._check(self.lib.ilh_jvp_noalloc(self.ctx, prec, self._vec(k, self.nblock, name="k"),
+                                             self._vec(u, self.nblock, name="u"), float(tau),
+                                             self._vec(dk, self.nblock, dt, "dk"),
+                                             self._vec(o, self.nblock, dt, "out")))
+        return o
+
     def vjp(self, k, u, tau, y, prec=64):
         self.linearize(k, u, tau)
         return self.vjp_lin(y, prec)

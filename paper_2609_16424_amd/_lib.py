@@ -69,6 +69,7 @@ SIGNATURES = {
     "ilh_linearize": (I, [P, P, P, D]),
     "ilh_jvp_lin": (I, [P, I, P, P]),
     "ilh_jvp": (I, [P, I, P, P, D, P, P]),
+    "ilh_jvp_noalloc": (I, [P, I, P, P, D, P, P]),
     "ilh_mass_v_apply": (I, [P, P, P]),
     "ilh_mass_v_solve": (I, [P, P, P, D, I, C.POINTER(I), C.POINTER(D)]),
     "ilh_mass_e_inv": (I, [P, P, P]),

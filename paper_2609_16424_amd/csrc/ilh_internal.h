@@ -93,6 +93,7 @@ struct ilh_ctx {
   const double* me_scale = nullptr;  // per-element scale of the reference block (nullptr: none)
   double* x0 = nullptr;     // [nh1] initial node positions of a curved initial mesh (else nullptr)
   bool general = false;     // curved initial mesh or faces without walls: generic element kernels only
+  void* scratch = nullptr;  // this device's address of the library's static scratch array (ilh_jvp_noalloc)
   double* Mdiag = nullptr;  // [nh1] diag(M_V), 1 on constrained rows
   double* qw = nullptr;     // [Q] reference weights (host copy below)
   std::vector<double> h_qw, h_B, h_G, h_BL, h_gll, h_qpts, h_w1;
@@ -219,6 +220,9 @@ int launch_vjp2d_q(ilh_ctx* c, int prec, const void* y, void* out);
 int launch_vjp3d_q(ilh_ctx* c, int prec, const void* y, void* out);
 int lin2d_nqd(const ilh_ctx* c);
 int64_t lin2d_stride(const ilh_ctx* c);
+// bytes of the stored tangent coefficients of one precision (2D / 3D linearised kernels)
+int64_t lin2d_coef_bytes(const ilh_ctx* c, int prec);
+int64_t lin3d_coef_bytes(const ilh_ctx* c, int prec);
 // linearised 3D Jacobian action (Q2Q1, no source)
 bool lin3d_available(const ilh_ctx* c);
 int launch_lin3d(ilh_ctx* c, int prec);

@@ -578,4 +578,8 @@ int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const doubl
 
 bool lin2d_available(const ilh_ctx* c) { return lin2d_supported(c); }
 
+int64_t lin2d_coef_bytes(const ilh_ctx* c, int prec) {
+  return (int64_t)lin2d_nqd(c) * lin2d_stride(c) * (prec == 64 ? 8 : 4);
+}
+
 }  // namespace ilh

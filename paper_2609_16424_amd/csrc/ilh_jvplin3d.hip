@@ -557,6 +557,10 @@ int launch_lin3d(ilh_ctx* c, int prec) {
   return p ? lin3d_t<double>(c, (double*)c->qd[p]) : lin3d_t<float>(c, (float*)c->qd[p]);
 }
 
+int64_t lin3d_coef_bytes(const ilh_ctx* c, int prec) {
+  return (int64_t)lin3d_nqd(c) * lin3d_stride(c) * (prec == 64 ? 8 : 4);
+}
+
 int launch_jvp3d_q(ilh_ctx* c, int prec, const void* dk, void* out) {
   if (!lin3d_available(c)) return ILH_EINVAL;
   const int p = prec == 64 ? 1 : 0;

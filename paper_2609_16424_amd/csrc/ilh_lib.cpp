@@ -8,10 +8,37 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "ilh_internal.h"
+
+// Static scratch of ilh_jvp_noalloc: one array per GPU, held until the process ends.  Host code
+// never uses the name `scratch` as an address (on the host it is only a stand-in for the symbol):
+// each device's address comes from hipGetSymbolAddress, resolved once per device at context
+// creation with that device current, and kernels receive that address.
+static __device__ __align__(256) unsigned char scratch[ILH_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// This device's address of `scratch` (dev must be the current device).
+int resolve_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return ILH_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return ILH_EHIP;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return ILH_OK;
+}
+}  // namespace
 
 using ilh::EArgs;
 
@@ -650,6 +677,14 @@ static int create_ctx(const ilh_setup* s, void* stream, ilh_ctx** out, ilh_ctx**
   P.dsc_w = s->dscale_width;
   P.psi_shift = s->visc_on ? std::atanh(1.0 - 2.0 * s->psi0) : 0.0;
   P.walls = walls;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || resolve_scratch(dev, &c->scratch) != ILH_OK) {
+      std::fprintf(stderr, "ilh_create: could not resolve the static scratch array on this device\n");
+      ilh_destroy(c);
+      return ILH_EHIP;
+    }
+  }
   if (s->x0) {
     c->me_stride = (int64_t)Nl * Nl;
     c->me_scale = nullptr;
@@ -814,6 +849,48 @@ int ilh_jvp(ilh_ctx* c, int prec, const double* k, const double* u, double tau, 
   int st = ilh_linearize(c, k, u, tau);
   if (st) return st;
   return ilh_jvp_lin(c, prec, dk, jdk);
+  ILH_CATCH(c)
+}
+
+int ilh_jvp_noalloc(ilh_ctx* c, int prec, const double* k, const double* u, double tau, const void* dk,
+                    void* jdk) {
+  ILH_TRY
+  if (!c || !k || !u || !dk || !jdk) return ILH_EINVAL;
+  if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+  if (!c->scratch) return fail(c, ILH_EINVAL, "no static scratch on this context's device");
+  // scratch layout: w = u + tau k (FP64) | FP32 shadow of w (recomputing kernels) or the tangent
+  // coefficients of precision prec (linearised kernels), each part 256-byte aligned
+  auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const bool lin = c->jvp_variant == 0 && (lin2d_available(c) || lin3d_available(c));
+  const int64_t off1 = al(c->nblock * 8);
+  const int64_t part2 = lin ? (c->dim == 3 ? lin3d_coef_bytes(c, prec) : lin2d_coef_bytes(c, prec)) : c->nblock * 4;
+  const int64_t need = off1 + al(part2);
+  if (need > (int64_t)ILH_NOALLOC_SCRATCH_BYTES)
+    return fail(c, ILH_EINVAL, "ilh_jvp_noalloc: this mesh needs " + std::to_string(need) +
+                                   " bytes of scratch, the static array holds " +
+                                   std::to_string((long long)ILH_NOALLOC_SCRATCH_BYTES));
+  unsigned char* base = (unsigned char*)c->scratch;
+  const int p = prec == 64 ? 1 : 0;
+  // run ilh_jvp on the scratch buffers in place of the context's own, then restore the context's
+  // linearisation point (its buffers are not touched; enqueued kernels keep the addresses they got)
+  double* w64 = c->w64;
+  float* w32 = c->w32;
+  void* qd = c->qd[p];
+  const bool ok0 = c->qd_ok[0], ok1 = c->qd_ok[1];
+  const double tau0 = c->lin_tau;
+  c->w64 = (double*)base;
+  if (lin)
+    c->qd[p] = base + off1;
+  else
+    c->w32 = (float*)(base + off1);
+  const int st = ilh_jvp(c, prec, k, u, tau, dk, jdk);
+  c->w64 = w64;
+  c->w32 = w32;
+  c->qd[p] = qd;
+  c->qd_ok[0] = ok0;
+  c->qd_ok[1] = ok1;
+  c->lin_tau = tau0;
+  return st;
   ILH_CATCH(c)
 }
 
