@@ -15,11 +15,15 @@ Printed JSON line:
               kernel time plus that of the linearisation launches they used (HIP events
               attached by the library to each dispatch on its stream);
   ms_per_step wall time per implicit step (host synchronised at both ends);
-  roofline    algorithmic bytes of one Jacobian-action (apply) launch / its mean launch time,
-              vs 8 TB/s; traffic = counter-measured bytes per launch, and valu = counted VALU
-              instructions per launch with the fraction of the issue peak they occupy at the
-              measured launch time, when recorded for the current kernel sources;
-  cpu_baseline the CPU oracle's complex-step Jacobian action on the same state.
+  roofline    algorithmic bytes of one Jacobian-action (apply) launch -- the state, the direction
+              and the result (three block vectors) and m_q per point, 19 B per quadrature point in
+              FP32 -- over its mean launch time, vs 8 TB/s; design_bytes / bandwidth_frac count
+              what this implementation moves instead (its stored tangent coefficients included);
+              traffic = counter-measured bytes per launch, and valu = counted VALU instructions
+              per launch with the fraction of the issue peak they occupy at the measured launch
+              time, when recorded for the current kernel sources;
+  cpu_baseline the CPU oracle's complex-step Jacobian action at C2 on all cores of the CPU share
+              (cpu_oracle: 1 core and all cores, residual and Jacobian actions, C1-C4 and R-A).
 Run with --gpus N, N > 1: exits, this build runs on one GPU only.
 """
 import argparse
@@ -86,6 +90,8 @@ def parse():
     ap.add_argument("--order", type=int, default=3)
     ap.add_argument("--cfl-factor", type=float, default=4.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-ra", action="store_true",
+                    help="add the 1024^2 Q3Q2 shape to the CPU oracle legs (about 2-3 minutes more)")
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--jvp-variant", choices=("lin", "generic", "recompute"), default="lin",
                     help="Jacobian-action kernels: linearised (stored tangent coefficients), generic element "
@@ -131,6 +137,16 @@ def jvp_bytes(H, prec, variant="lin"):
     return state + 2 * vec + qdata
 
 
+def alg_bytes(H, prec):
+    """Algorithmic HBM bytes of one Jacobian action (or residual) by the method's own count: the
+    unique vectors it touches once each -- the state w, the direction dk and the result (three
+    block vectors) -- and the quadrature mass m_q per point (+ det J0 per point with viscosity);
+    nothing the implementation chooses to store (tangent coefficients) is counted.  2D Q3Q2:
+    19 (FP32) / 38 (FP64) bytes per point; 3D Q2Q1: 14.6 / 29.1."""
+    w = 4 if prec == 32 else 8
+    return 3 * H.nblock * w + H.nqp * w * (2 if H.setup.visc_on else 1)
+
+
 def lin_bytes(H, prec):
     """Algorithmic bytes of one linearisation launch: state w (FP64) read, coefficients written,
     per-element rho0 |J0|, |J0|, gamma read."""
@@ -154,9 +170,11 @@ def residual_rate(H, k, u, tau, launches):
     t = H.timing_read()
     H.timing(False)
     avg = 1e-3 * t["residual"][0] / max(t["residual"][1], 1)
-    b = res_bytes(H)
+    b = alg_bytes(H, 64)
+    bd = res_bytes(H)
     return {"avg_launch_us": 1e6 * avg, "qps": H.nqp / avg, "bytes_per_launch": b,
-            "achieved_GBs": b / avg / 1e9, "frac": b / avg / 1e9 / HBM_PEAK_GBS}
+            "achieved_GBs": b / avg / 1e9, "frac": b / avg / 1e9 / HBM_PEAK_GBS,
+            "design_bytes_per_launch": bd, "bandwidth_frac": bd / avg / 1e9 / HBM_PEAK_GBS}
 
 
 KERNEL_NAMES = {"lin": "k_jvp2d_q<4,6,float,visc=0,src=1,out=double,waves=1>", "generic": "k_elem2d<4,6,JVP,float,7>",
@@ -233,6 +251,47 @@ def triple_point_legs(ilh, torch):
     return res
 
 
+def c1_leg(ilh, torch):
+    """M1: the C1 configuration (2D TG 8x8 Q2Q1, 10 implicit midpoint steps, dt 0.01, tol 1e-10) on the
+    GPU, FP64 and FP32 Jacobian actions: s/step (latency-bound at 1,024 quadrature points)."""
+    out = {}
+    for prec in (64, 32):
+        H = ilh.Hydro("tg2d", (8, 8), 2)
+        u = H.init_state()
+        opts = ilh.newton_options(tol=1e-10, jvp_prec=prec)
+        e0 = sum(H.energy(u))
+        hist, newton, gmres = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            g = H.plain_guess(u, hist)
+            kk, st = H.implicit_step(u, 0.01, guess=g, opts=opts)
+            hist = (hist + [kk])[-2:]
+            newton.append(st["newton"])
+            gmres.append(st["gmres"])
+        torch.cuda.synchronize()
+        out["fp%d" % prec] = {"s_per_step": (time.perf_counter() - t0) / 10, "newton_per_step": float(np.mean(newton)),
+                              "gmres_per_step": float(np.mean(gmres)),
+                              "rel_energy_change": (sum(H.energy(u)) - e0) / e0}
+    out["workload"] = "C1: 2D Taylor-Green 8x8 Q2Q1, 10 implicit midpoint steps, dt 0.01, Newton tol 1e-10"
+    return out
+
+
+def oracle_step_estimate(cpu, name, newton, gmres):
+    """Oracle s/implicit step from its measured per-point rates and the iteration counts of the run:
+    (Newton + 1) residuals and one complex-step action per GMRES iteration (the mass solves of its
+    preconditioner and the orthogonalisation are left out, so this is a lower bound)."""
+    e = cpu["shapes"][name]
+    nqp = e["n_qp"]
+    res = {}
+    for tag in ("1core", "all_cores"):
+        res["s_per_step_" + tag] = ((newton + 1) * nqp / e["residual"]["qps_" + tag] +
+                                    gmres * nqp / e["jvp_cs"]["qps_" + tag])
+    res.update(newton_per_step=newton, gmres_per_step=gmres,
+               how="estimate: (Newton + 1) x residual + GMRES x complex-step action at the measured rates")
+    return res
+
+
 def _peak_density_radius(H, u):
     """Radius of the element with the largest mass / area (area from its boundary nodes)."""
     n, k = H.n[0], H.k
@@ -296,52 +355,130 @@ def sedov_leg(ilh, torch, n=16, k=3, T=0.8):
     return out
 
 
-def cpu_baseline(u_np, n, k, dt, budget_s=30.0):
-    """Oracle complex-step Jacobian action of the residual at the benchmark state."""
+# ---------------------------------------------------------------------------------------------
+# CPU oracle baseline.  Runs first, before the GPU is initialised, so that the worker processes are
+# forked from a process without a GPU context.  Every figure times the oracle as it stands (plain
+# NumPy FP64 / complex128): its element force evaluation (oracle.hydro.Hydro.force on a chunk of
+# elements, the whole per-element work of a residual or Jacobian action) on a bounded sample of
+# each workload, on one core and on all cores of the CPU share (one process per core, BLAS
+# threads 1, each process a different chunk of the same size: weak scaling), plus full implicit
+# steps of the oracle at C1.
+_CPU = {}
+
+
+def _cpu_worker(args):
+    """Time one oracle operation on one element chunk (runs in a forked worker or inline)."""
+    from threadpoolctl import threadpool_limits
+    op, lo, hi = args
+    O, w, dk, tau = _CPU["O"], _CPU["w"], _CPU["dk"], _CPU["tau"]
+    els = np.arange(lo, hi)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        if op == "residual":
+            O.force(w, elements=els)
+        elif op == "jvp_cs":
+            O.force(w + 1j * 1e-30 * tau * dk, elements=els)
+        else:  # two-residual central difference
+            O.force(w + 1e-7 * tau * dk, elements=els)
+            O.force(w - 1e-7 * tau * dk, elements=els)
+        return time.perf_counter() - t0
+
+
+def _cpu_info():
+    model = ""
     try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-    except Exception:
-        limiter = None
-    from oracle.hydro import Hydro as OHydro
-    from oracle.krylov import jvp_cs
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    return model, os.cpu_count(), share
+
+
+def cpu_legs(with_ra=False, target_s=0.7):
+    """The oracle on the host CPU: qp/s of its residual force kernel and of its Jacobian action
+    (complex step; two-residual central difference) at the C1-C4 shapes (and R-A with with_ra),
+    1 core and all cores; oracle s/implicit step at C1 (10 steps, dt 0.01, tol 1e-10)."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle.hydro import Hydro as OHydro, ViscosityOptions
+    from oracle import krylov
     import seeded_inputs as si
-    O = OHydro("tg2d", (n, n), k)
-    kk = np.zeros(O.nblock)
-    dk = si.block_direction(7, O.nh1, O.nl2, sx=1.0 / (n * k), sv=1.0, se=1.0)
-    times = []
-    t_all = time.time()
-    while True:
+    model, nproc, share = _cpu_info()
+    workers = max(1, min(16, share))  # the box's CPU share for one GPU is 16 cores
+    shapes = [("C1", "tg2d", (8, 8), 2, None), ("C2", "tg2d", (128, 128), 3, None),
+              ("C3", "tg3d", (32, 32, 32), 2, None), ("C4", "triple", (112, 48), 3, "formula")]
+    if with_ra:
+        # 1024^2: building the oracle takes ~40 s and each subset evaluation gathers the whole
+        # mesh (~1 s per call), so the sample takes larger chunks there
+        shapes.append(("R-A", "tg2d", (1024, 1024), 3, None))
+    out = {"cpu_model": model, "nproc": nproc, "cpu_share": share, "workers": workers, "shapes": {}}
+    t_all = time.perf_counter()
+    for name, prob, n, k, visc in shapes:
+        tb = time.perf_counter()
+        vo = ViscosityOptions(on=visc is not None, mode=visc or "const", h_coarse=(1.0 / k if prob == "triple" else None))
+        with threadpool_limits(1):
+            O = OHydro(prob, n, k, visc=vo)
+            u = O.init_state()
+        build_s = time.perf_counter() - tb
+        h = float(np.min(O.mesh.h)) / k
+        w = si.perturb_state(u, 3, O.nh1, 0.02 * h, 0.02, 0.01) if prob != "tg3d" else si.displace_positions(u, O.nh1, 0.05)
+        dk = si.block_direction(4, O.nh1, O.nl2, h, 1.0, 1.0)
+        _CPU.update(O=O, w=w, dk=dk, tau=0.5 * O.dt_estimate(w, 2.0))
+        entry = {"n_elements": O.mesh.Ne, "n_qp": O.mesh.Ne * O.Q, "oracle_build_s": build_s}
+        Q = O.Q
+        for op in ("residual", "jvp_cs", "jvp_fd"):
+            # chunk sized for about target_s of one core's work (at most the whole mesh): the
+            # oracle's subset evaluation gathers the whole mesh first, so a call costs a + b ne
+            m1 = min(O.mesh.Ne, 128)
+            m2 = min(O.mesh.Ne, 256)
+            ta = min(_cpu_worker((op, 0, m1)) for _ in range(2))
+            tb_ = min(_cpu_worker((op, 0, m2)) for _ in range(2))
+            slope = max((tb_ - ta) / max(m2 - m1, 1), 1e-7) if m2 > m1 else ta / m1
+            tgt = target_s if name != "R-A" else 8.0
+            ne = int(min(O.mesh.Ne, max(m1, (tgt - max(ta - m1 * slope, 0.0)) / slope)))
+            t1 = min(_cpu_worker((op, 0, ne)) for _ in range(2))
+            one = ne * Q / t1
+            chunks = [(op, (i * ne) % max(1, O.mesh.Ne - ne + 1), (i * ne) % max(1, O.mesh.Ne - ne + 1) + ne)
+                      for i in range(workers)]
+            ctx = mp.get_context("fork")
+            with ctx.Pool(workers) as pool:
+                pool.map(_cpu_worker, chunks[:workers])  # warm the workers
+                tw = time.perf_counter()
+                pool.map(_cpu_worker, chunks)
+                wall = time.perf_counter() - tw
+            entry[op] = {"qps_1core": one, "qps_all_cores": workers * ne * Q / wall, "chunk_elements": ne}
+        out["shapes"][name] = entry
+        _CPU.clear()
+        del O, u, w, dk
+    # full oracle implicit steps at C1 (the oracle's Newton-FGMRES with complex-step actions)
+    with threadpool_limits(1):
+        O = OHydro("tg2d", (8, 8), 2)
+        u0 = O.init_state()
         t0 = time.perf_counter()
-        jvp_cs(lambda q: O.residual(q, u_np, 0.5 * dt), kk, dk)
-        times.append(time.perf_counter() - t0)
-        if time.time() - t_all + times[-1] > budget_s or len(times) >= 3:
-            break
-    nqp = O.mesh.Ne * O.Q
-    return {"value": nqp / float(np.median(times)), "unit": "quad-pts/s", "cores": 1, "kind": "oracle",
-            "sample": "%d complex-step Jacobian action(s) of the stage residual on the full %dx%d Q%dQ%d "
-                      "benchmark state (%d qp), NumPy FP64/complex128, 1 thread; median" %
-                      (len(times), n, n, k, k - 1, nqp)}
+        _, _, st = krylov.run_midpoint(O, u0, 0.01, 10)
+        c1 = (time.perf_counter() - t0) / 10
+    out["oracle_s_per_step_C1_1core"] = c1
+    out["oracle_C1_newton_gmres_per_step"] = [float(np.mean([x["newton"] for x in st])),
+                                              float(np.mean([x["gmres"] for x in st]))]
+    out["wall_s"] = time.perf_counter() - t_all
+    return out
 
 
-def cpu_residual(u_np, k_np, n, k, dt, reps=3):
-    """The oracle's stage residual on the same state (NumPy FP64, one thread), median of reps."""
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-    except Exception:
-        limiter = None
-    from oracle.hydro import Hydro as OHydro
-    O = OHydro("tg2d", (n, n), k)
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        O.residual(k_np, u_np, 0.5 * dt)
-        times.append(time.perf_counter() - t0)
-    nqp = O.mesh.Ne * O.Q
-    return {"value": nqp / float(np.median(times)), "unit": "quad-pts/s", "cores": 1, "kind": "oracle",
-            "sample": "%d stage residual(s) on the %dx%d Q%dQ%d benchmark state (%d qp), NumPy FP64, 1 thread; "
-                      "median" % (reps, n, n, k, k - 1, nqp)}
+def cpu_baseline_line(cpu):
+    """The contract's cpu_baseline object: the oracle's complex-step Jacobian action at C2 on all cores."""
+    e = cpu["shapes"]["C2"]["jvp_cs"]
+    return {"value": e["qps_all_cores"], "unit": "quad-pts/s", "cores": cpu["workers"], "kind": "oracle",
+            "sample": "oracle complex-step Jacobian action (element force in complex128) on %d processes x %d "
+                      "elements of the 128x128 Q3Q2 Taylor-Green state (1 BLAS thread each); 1 core: %.3g qp/s; "
+                      "CPU %s, nproc %s, CPU share %s" % (cpu["workers"], e["chunk_elements"], e["qps_1core"],
+                                                          cpu["cpu_model"], cpu["nproc"], cpu["cpu_share"])}
 
 
 def _finite(v):
@@ -361,6 +498,9 @@ def main():
         print("bench.py: this build runs on exactly one GPU (no sharding or collectives); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_legs(with_ra=args.cpu_ra)  # before the GPU is initialised (forked workers)
     import torch
     import paper_2609_16424_amd as ilh
 
@@ -406,7 +546,8 @@ def main():
     bytes32 = jvp_bytes(H, 32, args.jvp_variant)
     # inside FGMRES the linearised FP32 action writes the FP64 Krylov vector itself
     bytes_loop = bytes32 + (4 * H.nblock if args.jvp_variant == "lin" else 0)
-    achieved = bytes_loop / jvp_avg_s / 1e9
+    alg32 = alg_bytes(H, 32)
+    achieved = alg32 / jvp_avg_s / 1e9
     # the same kernel back to back at the last linearisation point (no other kernels between)
     dkb = torch.randn(H.nblock, device=u.device, dtype=torch.float32,
                       generator=torch.Generator(device=u.device).manual_seed(7))
@@ -482,9 +623,11 @@ def main():
         HR.timing(False)
         avg = 1e-3 * tr["jvp"][0] / tr["jvp"][1]
         bR = jvp_bytes(HR, 32, args.jvp_variant)
+        aR = alg_bytes(HR, 32)
         roof_extra = {"shape": "%dx%d Q3Q2 TG (displaced)" % (m, m), "n_qp": HR.nqp,
-                      "jvp_qps": HR.nqp / avg, "achieved_GBs": bR / avg / 1e9,
-                      "frac": bR / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": bR, "avg_launch_us": 1e6 * avg}
+                      "jvp_qps": HR.nqp / avg, "achieved_GBs": aR / avg / 1e9,
+                      "frac": aR / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": aR, "avg_launch_us": 1e6 * avg,
+                      "design_bytes_per_launch": bR, "bandwidth_frac": bR / avg / 1e9 / HBM_PEAK_GBS}
         if tr["linearize"][1]:
             lavg = 1e-3 * tr["linearize"][0] / tr["linearize"][1]
             roof_extra["linearize"] = {"avg_launch_us": 1e6 * lavg, "bytes_per_launch": lin_bytes(HR, 32),
@@ -500,8 +643,12 @@ def main():
         HR.timing(False)
         a64 = 1e-3 * t64["jvp"][0] / t64["jvp"][1]
         b64 = jvp_bytes(HR, 64, args.jvp_variant)
-        roof_extra["fp64"] = {"avg_launch_us": 1e6 * a64, "jvp_qps": HR.nqp / a64, "bytes_per_launch": b64,
-                              "achieved_GBs": b64 / a64 / 1e9, "frac": b64 / a64 / 1e9 / HBM_PEAK_GBS}
+        al64 = alg_bytes(HR, 64)
+        roof_extra["fp64"] = {"avg_launch_us": 1e6 * a64, "jvp_qps": HR.nqp / a64, "bytes_per_launch": al64,
+                              "achieved_GBs": al64 / a64 / 1e9, "frac": al64 / a64 / 1e9 / HBM_PEAK_GBS,
+                              "design_bytes_per_launch": b64, "bandwidth_frac": b64 / a64 / 1e9 / HBM_PEAK_GBS}
+        # FP32 action against FP64 on the same direction (the FP32 path rounds dk too)
+        roof_extra["fp32_vs_fp64_rel_err"] = float(torch.linalg.norm(out32.double() - out64) / torch.linalg.norm(out64))
         kres = 1e-3 * dk  # a small stage increment for the residual
         roof_extra["residual"] = dict(residual_rate(HR, kres, uR, 0.5 * HR.dt_estimate(uR, 2.0), 10),
                                       kernel="k_res2d<4,6,src=1> (FP64)")
@@ -520,6 +667,7 @@ def main():
             k3 = torch.zeros_like(u3)
             H3.linearize(k3, u3, 0.5 * H3.dt_estimate(u3, 2.0))
             entry = {"shape": "%d^3 Q2Q1 3D TG (displaced)%s" % (m, ", viscosity" if visc else ""), "n_qp": H3.nqp}
+            outs3 = {}
             for prec in (32, 64):
                 dt_ = torch.float32 if prec == 32 else torch.float64
                 d3 = torch.randn(H3.nblock, device=u3.device, dtype=torch.float64,
@@ -537,12 +685,18 @@ def main():
                 H3.timing(False)
                 a3 = 1e-3 * t3["jvp"][0] / t3["jvp"][1]
                 b3 = jvp_bytes(H3, prec, kind)
+                al3 = alg_bytes(H3, prec)
+                outs3[prec] = o3.double().clone()
                 entry["fp%d" % prec] = {"kernel_variant": kind, "avg_launch_us": 1e6 * a3, "jvp_qps": H3.nqp / a3,
-                                        "bytes_per_launch": b3, "achieved_GBs": b3 / a3 / 1e9,
-                                        "frac": b3 / a3 / 1e9 / HBM_PEAK_GBS,
+                                        "bytes_per_launch": al3, "achieved_GBs": al3 / a3 / 1e9,
+                                        "frac": al3 / a3 / 1e9 / HBM_PEAK_GBS,
+                                        "design_bytes_per_launch": b3,
+                                        "bandwidth_frac": b3 / a3 / 1e9 / HBM_PEAK_GBS,
                                         "linearize_avg_us": (1e3 * tw["linearize"][0] / tw["linearize"][1]
                                                              if tw["linearize"][1] else None)}
                 del d3, o3
+            entry["fp32_vs_fp64_rel_err"] = float(torch.linalg.norm(outs3[32] - outs3[64]) / torch.linalg.norm(outs3[64]))
+            del outs3
             # the stage residual (FP64 strip kernel)
             k3r = 1e-3 * torch.randn(H3.nblock, device=u3.device, dtype=torch.float64,
                                      generator=torch.Generator(device=u3.device).manual_seed(6))
@@ -582,6 +736,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    c1 = c1_leg(ilh, torch)
     c4 = None
     if not args.no_c4:
         c4 = triple_point_legs(ilh, torch)
@@ -589,11 +744,6 @@ def main():
     if not args.no_sedov:
         sedov = sedov_leg(ilh, torch)
 
-    cpu = None
-    cpu_res = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(u_start.detach().cpu().numpy(), n, k, dt)
-        cpu_res = cpu_residual(u_start.detach().cpu().numpy(), hist[-1].detach().cpu().numpy(), n, k, dt)
 
     out = {
         "metric": "JVP quad-pts/s (% HBM roofline); s/implicit step, learned-guess vs plain",
@@ -615,21 +765,27 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(n, k, args.jvp_variant),
-                     "kernel": KERNEL_NAMES[args.jvp_variant], "bytes_per_launch": bytes_loop,
+                     "kernel": KERNEL_NAMES[args.jvp_variant], "bytes_per_launch": alg32,
+                     "bytes_count": "algorithmic: state, direction and result (3 block vectors) + m_q, "
+                                    "FP32: %.1f B per quadrature point" % (alg32 / H.nqp),
+                     "design_bytes_per_launch": bytes_loop,
+                     "bandwidth_frac": bytes_loop / jvp_avg_s / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_us": 1e6 * jvp_avg_s, "launches": jvp_n,
                      "avg_launch_us_back_to_back_fp32_output": burst_us,
                      "valu": recorded_valu(n, k, args.jvp_variant, jvp_avg_s)},
         "transpose_action": {"kernel": "k_vjp2d_q<4,6,float,visc=0,src=1>", "avg_launch_us_back_to_back": vjp_us,
-                             "qps": H.nqp / (1e-6 * vjp_us), "bytes_per_launch": bytes32,
-                             "frac": bytes32 / (1e-6 * vjp_us) / 1e9 / HBM_PEAK_GBS},
+                             "qps": H.nqp / (1e-6 * vjp_us), "bytes_per_launch": alg32,
+                             "frac": alg32 / (1e-6 * vjp_us) / 1e9 / HBM_PEAK_GBS,
+                             "design_bytes_per_launch": bytes32,
+                             "bandwidth_frac": bytes32 / (1e-6 * vjp_us) / 1e9 / HBM_PEAK_GBS},
         "jvp_variant": args.jvp_variant,
         "jvp_apply_qps": H.nqp / jvp_avg_s,
         "residual": res_c2,
-        "cpu_oracle_residual": cpu_res,
         "linearize": {"launches": lin_n, "avg_launch_us": 1e3 * lin_ms / max(lin_n, 1),
                       "bytes_per_launch": lin_bytes(H, 32) if lin_n else None,
                       "jvp_launches_per_linearization": jvp_n / lin_n if lin_n else None},
-        "cpu_baseline": cpu,
+        "cpu_baseline": cpu_baseline_line(cpu) if cpu else None,
+        "cpu_oracle": cpu,
         "s_per_implicit_step_plain": ms_per_step / 1e3,
         "ms_per_step_with_kernel_events": ms_per_step_events,
         "newton_per_step": float(np.mean(newton)),
@@ -637,6 +793,14 @@ def main():
         "kernel_ms_per_step": {kname: v[0] / args.steps for kname, v in tim.items()},
         "energy_after": ke + ie,
     }
+    out["c1_m1"] = c1
+    if cpu:
+        est = {"C2": oracle_step_estimate(cpu, "C2", float(np.mean(newton)), float(np.mean(gmres)))}
+        if c4:
+            f = c4["fixed_8x_fp32"]
+            est["C4"] = oracle_step_estimate(cpu, "C4", f["newton_per_step"], f["gmres_per_step"])
+        est["C1_measured_1core"] = cpu["oracle_s_per_step_C1_1core"]
+        out["oracle_s_per_implicit_step"] = est
     out.update(extra)
     out.update(learned)
     if "learned_guess_c5" in learned:
