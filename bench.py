@@ -292,6 +292,76 @@ def oracle_step_estimate(cpu, name, newton, gmres):
     return res
 
 
+def c4_configured_width_leg(ilh, torch, steps=20, widths=(1e-1, 3e-2, 1e-2, 3e-3)):
+    """C4 as configured: the triple point 112x48 Q3Q2 at 8x the explicit step with the smoothing
+    width delta_scale = 1e-3 (constant), FP32 Jacobian actions, probed block preconditioner.
+    (i) direct: each step solved at width 1e-3 from the plain iterate, until the first failure;
+    (ii) continuation in the width within each step: stage solves at the wider scales `widths`,
+    each from the previous one's solution, then the step at 1e-3 from that iterate.
+    Per step: status, Newton and GMRES iterations, line-search halvings, residual history."""
+    from paper_2609_16424_amd import learned as L
+    out = {"workload": "2D triple point 112x48 Q3Q2, delta_scale = 1e-3 (constant), 8x explicit CFL, "
+                       "FP32 Jacobian actions, tol 1e-10, probed block preconditioner (mode 2, lag 1)"}
+    for mode in ("direct", "continuation"):
+        H = L.make_triple(112, 48, 3)
+        H.set_viscosity_scale("const", 1e-3)
+        u = H.init_state()
+        dt = 8.0 * H.dt_estimate(u, 0.5)
+        opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=15, gmres_maxit=150,
+                                  prec_probe=2, prec_lag=1)
+        hist, recs = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok_steps = 0
+        for n in range(steps):
+            g = H.plain_guess(u, hist, 0.5 * dt)
+            cont = []
+            if mode == "continuation":
+                for w in widths:
+                    H.set_viscosity_scale("const", w)
+                    kc, stc = H.stage_solve(u, 0.5 * dt, guess=g, opts=opts)
+                    cont.append([w, stc["status"], stc["newton"]])
+                    if stc["status"] == 0:
+                        g = kc
+                H.set_viscosity_scale("const", 1e-3)
+            k, st = H.implicit_step(u, dt, guess=g, opts=opts, raise_on_fail=False)
+            recs.append({"status": st["status"], "newton": st["newton"], "gmres": st["gmres"],
+                         "halvings": st["halvings"], "res_hist": [float("%.3e" % x) for x in st["hist"][:12]]})
+            if cont:
+                recs[-1]["continuation"] = cont
+            if st["status"] != 0:
+                break
+            ok_steps += 1
+            hist = (hist + [k])[-2:]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[mode] = {"steps_converged": ok_steps, "steps_tried": len(recs),
+                     "s_per_step": el / max(1, len(recs)), "per_step": recs}
+        del H, u
+    # (iii) the paper's Newton-based step control (Sec. 4) from 8x at width 1e-3: how far the step
+    # has to shrink for Newton to converge within three iterations
+    H = L.make_triple(112, 48, 3)
+    H.set_viscosity_scale("const", 1e-3)
+    u = H.init_state()
+    dt_exp = H.dt_estimate(u, 0.5)
+    dt = 8.0 * dt_exp
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=15, gmres_maxit=150,
+                              prec_probe=2, prec_lag=1)
+    hist, ratios, rej = [], [], []
+    try:
+        for _ in range(10):
+            g = H.plain_guess(u, hist, 0.5 * dt)
+            k, st, taken, dt, nrej = H.adaptive_step(u, dt, 10.0, "sd2", guess=g, opts=opts, max_reject=40)
+            hist = (hist + [k])[-2:]
+            ratios.append(taken / dt_exp)
+            rej.append(nrej)
+        out["step_control_from_8x"] = {"accepted_dt_over_explicit": ratios, "rejected_trials": rej}
+    except Exception as e:  # the control gives up after max_reject trials
+        out["step_control_from_8x"] = {"accepted_dt_over_explicit": ratios, "rejected_trials": rej,
+                                       "failure": str(e)}
+    return out
+
+
 def _peak_density_radius(H, u):
     """Radius of the element with the largest mass / area (area from its boundary nodes)."""
     n, k = H.n[0], H.k
@@ -738,8 +808,10 @@ def main():
 
     c1 = c1_leg(ilh, torch)
     c4 = None
+    c4w = None
     if not args.no_c4:
         c4 = triple_point_legs(ilh, torch)
+        c4w = c4_configured_width_leg(ilh, torch)
     sedov = None
     if not args.no_sedov:
         sedov = sedov_leg(ilh, torch)
@@ -812,6 +884,8 @@ def main():
         out["roofline_3d"] = roof_3d
     if c4:
         out["c4_triple_point"] = c4
+    if c4w:
+        out["c4_configured_width"] = c4w
     if sedov:
         out["sedov_2d"] = sedov
     print(json.dumps(_finite(out), allow_nan=False))

@@ -345,6 +345,14 @@ int ilh_adaptive_step(ilh_ctx* ctx, double* u, double* dt, double dt_max, int sc
                       double* k_out, const ilh_newton_opts* o, ilh_step_stats* st, int max_reject,
                       int* rejected, double* dt_taken);
 
+/* Change the smoothing scale delta_scale of the viscosity (Sec. 3.4, eqs. visc_imp_abs,
+ * visc_imp_switch, visc_imp_scale) for the calls that follow: mode ILH_DSCALE_CONST with the given
+ * width, or ILH_DSCALE_FORMULA (2 (h/h_coarse) c_s; width ignored).  Used for a continuation in the
+ * smoothing width within a step (solve with a wide scale, then narrow it from that solution).
+ * Stored tangent coefficients are invalidated.  No effect without viscosity.  ILH_EINVAL for an
+ * unknown mode or a width <= 0. */
+int ilh_set_viscosity_scale(ilh_ctx* ctx, int mode, double width);
+
 /* ---- measurement --------------------------------------------------------------------- */
 /* Kernel timing with HIP events recorded on the context stream around each launch of the
  * timed kernel classes: 0 = Jacobian-action element kernel, 1 = residual element kernel,

@@ -271,19 +271,21 @@ def sdirk_step(hyd, u, dt, scheme, k_guess=None, opts=None, stats=None):
 
 # ---- Newton-based step-size control (Sec. 4, "Implicit time step control") ------------------
 
-def adaptive_run(hyd, u0, tf, fscfl, scheme="sd2", opts=None, max_reject=60):
+def adaptive_run(hyd, u0, tf, fscfl, scheme="sd2", opts=None, max_reject=60, zero_guess=False):
     """Integrate to tf with the paper's step control: the first step is fscfl times the explicit
     estimate; after a step whose stages needed at most one Newton iteration each the next step
     grows by 5 %; two or three keep it; a step needing four or more in some stage (or failing)
     is rejected and repeated with 85 % of its size.  Newton iterations are counted as updates
     (the maximum over the stages).  Stage 1 of every step starts from the explicit rate (first
-    step) or the last stage rate of the previous step.  Returns (u, accepted steps, rejected)."""
+    step) or the last stage rate of the previous step; with zero_guess every stage solve starts
+    from k = 0 instead (the paper's solver defaults of Sec. 3.5 leave the initial iterate to the
+    Newton solver, read here as its default zero iterate).  Returns (u, accepted steps, rejected)."""
     u = u0.copy()
     dt = hyd.dt_estimate(u, fscfl)
     t, steps, rejected, kg = 0.0, 0, 0, None
     while t < tf - 1e-12:
         dtt = min(dt, tf - t)
-        g = hyd.rate(u) if kg is None else kg
+        g = np.zeros_like(u) if zero_guess else (hyd.rate(u) if kg is None else kg)
         st = {}
         try:
             A, b = sdirk_tableau(scheme)
@@ -291,7 +293,8 @@ def adaptive_run(hyd, u0, tf, fscfl, scheme="sd2", opts=None, max_reject=60):
             for i in range(len(b)):
                 ubase = u + dtt * sum(A[i, j] * ks[j] for j in range(i)) if i else u
                 sti = {}
-                ks.append(newton_stage(hyd, ubase, A[i, i] * dtt, ks[-1] if i else g, opts, sti))
+                k0 = np.zeros_like(u) if zero_guess else (ks[-1] if i else g)
+                ks.append(newton_stage(hyd, ubase, A[i, i] * dtt, k0, opts, sti))
                 nmax = max(nmax, sti["newton"])
             ok = nmax < 4
         except NewtonFailure:

@@ -284,6 +284,10 @@ class Hydro:
 
     JVP_VARIANTS = {"lin": 0, "generic": 1, "recompute": 2}
 
+    def set_viscosity_scale(self, mode, width=0.0):
+        """delta_scale of the viscosity from now on: mode "const" (width) or "formula"."""
+        self._check(self.lib.ilh_set_viscosity_scale(self.ctx, {"const": 0, "formula": 1}[mode], float(width)))
+
     def set_kernel_variant(self, variant):
         """Jacobian-action kernels: "lin" (default), "generic" or "recompute" (or 0, 1, 2)."""
         v = self.JVP_VARIANTS[variant] if isinstance(variant, str) else int(variant)

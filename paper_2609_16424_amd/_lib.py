@@ -88,6 +88,7 @@ SIGNATURES = {
     "ilh_adaptive_step": (I, [P, P, C.POINTER(D), D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats), I,
                               C.POINTER(I), C.POINTER(D)]),
     "ilh_timing_enable": (I, [P, I]),
+    "ilh_set_viscosity_scale": (I, [P, I, D]),
     "ilh_set_kernel_variant": (I, [P, I]),
     "ilh_set_apply_rows": (I, [P, I]),
     "ilh_set_apply_waves": (I, [P, I]),

@@ -1620,6 +1620,20 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
 
 extern "C" {
 
+int ilh_set_viscosity_scale(ilh_ctx* c, int mode, double width) {
+  ILH_TRY
+  if (!c) return ILH_EINVAL;
+  if (mode != ILH_DSCALE_CONST && mode != ILH_DSCALE_FORMULA) return fail(c, ILH_EINVAL, "unknown delta_scale mode");
+  if (mode == ILH_DSCALE_CONST && !(width > 0)) return fail(c, ILH_EINVAL, "dscale width must be > 0");
+  c->kp.dsc_mode = mode;
+  if (mode == ILH_DSCALE_CONST) c->kp.dsc_w = width;
+  c->s.dscale_mode = mode;
+  c->s.dscale_width = c->kp.dsc_w;
+  c->qd_ok[0] = c->qd_ok[1] = false;  // the tangent coefficients depend on it
+  return ILH_OK;
+  ILH_CATCH(c)
+}
+
 int ilh_set_apply_rows(ilh_ctx* c, int rows) {
   ILH_TRY
   if (!c) return ILH_EINVAL;

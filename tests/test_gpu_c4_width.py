@@ -1,0 +1,50 @@
+"""The triple point as configured (112x48 Q3Q2, smoothing width delta_scale = 1e-3, 8x the explicit
+step, FP32 Jacobian actions): the first four implicit steps converge (each taking many Newton
+iterations with halvings when solved directly, two or three after a continuation in the width
+0.1 -> 1e-3 within the step), and the fifth step tangles the stage mesh (ETANGLED) with and
+without the continuation -- at this step size the failure is not the width's: the continuation's
+first solve at width 0.1 tangles too.  The same configuration runs under the paper's Newton-based
+step control at about a quarter of the explicit step (bench leg c4_configured_width)."""
+import pytest
+
+import paper_2609_16424_amd as ilh
+from paper_2609_16424_amd import learned as L
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(cont):
+    H = L.make_triple(112, 48, 3)
+    H.set_viscosity_scale("const", 1e-3)
+    u = H.init_state()
+    dt = 8.0 * H.dt_estimate(u, 0.5)
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, max_newton=30, restart=15, gmres_maxit=150,
+                              prec_probe=2, prec_lag=1)
+    hist, out = [], []
+    for _ in range(5):
+        g = H.plain_guess(u, hist, 0.5 * dt)
+        first = None
+        if cont:
+            for w in (1e-1, 3e-2, 1e-2, 3e-3):
+                H.set_viscosity_scale("const", w)
+                kc, stc = H.stage_solve(u, 0.5 * dt, guess=g, opts=opts)
+                first = stc["status"] if first is None else first
+                if stc["status"] == 0:
+                    g = kc
+            H.set_viscosity_scale("const", 1e-3)
+        k, st = H.implicit_step(u, dt, guess=g, opts=opts, raise_on_fail=False)
+        out.append((st["status"], st["newton"], first))
+        if st["status"] != 0:
+            break
+        hist = (hist + [k])[-2:]
+    return out
+
+
+def test_configured_width_direct_and_continuation():
+    direct = _run(False)
+    cont = _run(True)
+    assert [s for s, _, _ in direct[:4]] == [0] * 4 and [s for s, _, _ in cont[:4]] == [0] * 4
+    assert max(n for _, n, _ in direct[:4]) >= 6          # the sharp switch slows Newton
+    assert max(n for _, n, _ in cont[:4]) <= 4             # from the continued iterate: fast
+    assert direct[4][0] == ilh._lib.ILH_ETANGLED and cont[4][0] == ilh._lib.ILH_ETANGLED
+    assert cont[4][2] == ilh._lib.ILH_ETANGLED             # width 0.1 tangles there as well
