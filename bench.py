@@ -419,6 +419,32 @@ def sedov_leg(ilh, torch, n=16, k=3, T=0.8):
             entry.update(newton_per_step=newton / steps, gmres_per_step=gmres / steps)
         out[mode] = entry
         del H, u
+    # the paper's step control from FS-CFL 2 with its default solver settings (Newton relative
+    # tolerance 1e-5, at most 10 iterations, linear solves to 1e-12, zero initial iterate)
+    H = ilh.make_sedov(n, k)
+    u = H.init_state()
+    e0 = sum(H.energy(u))
+    opts = ilh.newton_options(tol=1e-5, max_newton=10, restart=30, gmres_rtol=1e-12, gmres_maxit=400,
+                              jvp_prec=64, ls_residual=0, guess_fallback=0, prec_probe=2, prec_lag=1)
+    t, steps, rej = 0.0, 0, 0
+    dt = H.dt_estimate(u, 2.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        while t < T - 1e-12:
+            _, st, taken, dt, nrej = H.adaptive_step(u, dt, T - t, "sd2", guess=None, opts=opts, max_reject=60)
+            t += taken
+            steps += 1
+            rej += nrej
+        torch.cuda.synchronize()
+        peak, r = _peak_density_radius(H, u)
+        out["implicit_step_control_paper_settings"] = {
+            "steps": steps, "rejected": rej, "wall_s": time.perf_counter() - t0,
+            "rel_energy_change": (sum(H.energy(u)) - e0) / e0, "peak_radius": r,
+            "paper_implicit_steps": 205}
+    except Exception as e:
+        out["implicit_step_control_paper_settings"] = {"steps": steps, "rejected": rej, "failure": str(e)}
+    del H, u
     out["implicit_speedup_wall"] = out["explicit_rk2_cfl0.5"]["wall_s"] / out["implicit_midpoint_fscfl2"]["wall_s"]
     out["workload"] = "2D Sedov %dx%d Q%dQ%d, gamma 1.4, smoothed viscosity, T = %g; exact shock radius 0.898" % (
         n, n, k, k - 1, T)
@@ -794,8 +820,10 @@ def main():
                             "perturbation seeds %s, %d steps each, tol 1e-10, block preconditioner mode %d "
                             "(lag %d)" % (float(z["cfl_factor"]), args.learned_seeds, args.learned_steps,
                                           opts_c4.prec_probe, opts_c4.prec_lag),
-                "plain": res["plain"], "learned": res["learned"], "zero_output_control": res["zero"],
-                "speedup_s_per_step": res["plain"]["s_per_step"] / res["learned"]["s_per_step"]}
+                "plain": res["plain"], "plain_fallback": res["plain_fallback"], "learned": res["learned"],
+                "zero_output_control": res["zero"],
+                "matched": {k: res[k] for k in res if k.startswith("learned_vs_")},
+                "speedup_s_per_step": res["learned_vs_plain"]["speedup_s_per_step"]}
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
@@ -876,8 +904,10 @@ def main():
     out.update(extra)
     out.update(learned)
     if "learned_guess_c5" in learned:
-        out["s_per_implicit_step_learned_c5"] = learned["learned_guess_c5"]["learned"]["s_per_step"]
-        out["s_per_implicit_step_plain_c5"] = learned["learned_guess_c5"]["plain"]["s_per_step"]
+        mt = learned["learned_guess_c5"]["matched"]["learned_vs_plain"]
+        out["s_per_implicit_step_learned_c5"] = mt["s_per_step_learned"]
+        out["s_per_implicit_step_plain_c5"] = mt["s_per_step_plain"]
+        out["c5_matched_steps"] = mt["matched_steps"]
     if roof_extra:
         out["roofline_large_shape"] = roof_extra
     if roof_3d:

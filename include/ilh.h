@@ -239,6 +239,16 @@ int ilh_rate(ilh_ctx* ctx, const double* u, double* f);
 int ilh_plain_guess(ilh_ctx* ctx, const double* u, const double* k1, const double* k2,
                     int nhist, double tau, double* out);
 
+/* ilh_plain_guess with a fallback: for nhist >= 2, out receives the better -- the smaller finite
+ * residual norm ||R(.; tau, u)|| -- of the extrapolation 2 k1 - k2 and the previous rate k1 (both
+ * with out_x = u_v + tau out_v); fewer rates: as ilh_plain_guess.  *which (host, nullable): 2 the
+ * extrapolation, 1 the previous rate, 0 the explicit rate.  The extrapolation of a step whose
+ * predecessor moved the mesh fast can tangle the stage mesh; the previous rate is then the next
+ * simplest iterate before the solver's own fallback to k = 0.  Two block vectors of workspace
+ * (allocated on first use).  Synchronises (two norms). */
+int ilh_plain_guess_fallback(ilh_ctx* ctx, const double* u, const double* k1, const double* k2, int nhist,
+                             double tau, double* out, int* which);
+
 /* Newton-Krylov options (host).  Converged when ||R(k)|| <= tol ||R(0; tau, u)||. */
 typedef struct {
   double tol;          /* relative nonlinear tolerance (1e-10 for the benchmarks) */

@@ -261,13 +261,21 @@ class Hydro:
         self._check(self.lib.ilh_rate(self.ctx, self._vec(u, self.nblock, name="u"), _ptr(f)))
         return f
 
-    def plain_guess(self, u, history, tau=0.0):
+    def plain_guess(self, u, history, tau=0.0, fallback=False):
         """Explicit rate, last rate, or linear extrapolation of the last two (most recent last);
-        with tau > 0 the position block is set to u_v + tau k_v."""
+        with tau > 0 the position block is set to u_v + tau k_v.  fallback: the better of the
+        extrapolation and the last rate by stage residual (ilh_plain_guess_fallback)."""
         out = self.new()
         k1 = self._vec(history[-1], self.nblock, name="k1") if len(history) >= 1 else None
         k2 = self._vec(history[-2], self.nblock, name="k2") if len(history) >= 2 else None
         self._stream()
+        if fallback:
+            which = C.c_int(0)
+            self._check(self.lib.ilh_plain_guess_fallback(self.ctx, self._vec(u, self.nblock, name="u"), k1, k2,
+                                                          min(len(history), 2), float(tau), _ptr(out),
+                                                          C.byref(which)))
+            self.last_plain_choice = which.value
+            return out
         self._check(self.lib.ilh_plain_guess(self.ctx, self._vec(u, self.nblock, name="u"), k1, k2,
                                              min(len(history), 2), float(tau), _ptr(out)))
         return out

@@ -79,6 +79,7 @@ SIGNATURES = {
     "ilh_l1_velocity_error": (I, [P, P, C.POINTER(D)]),
     "ilh_rate": (I, [P, P, P]),
     "ilh_plain_guess": (I, [P, P, P, P, I, D, P]),
+    "ilh_plain_guess_fallback": (I, [P, P, P, P, I, D, P, C.POINTER(I)]),
     "ilh_newton_defaults": (None, [C.POINTER(NewtonOpts)]),
     "ilh_implicit_step": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),

@@ -120,6 +120,7 @@ struct ilh_ctx {
   float* gscr = nullptr;        // learned-guess features and activations (allocated on first use)
   int64_t gscr_len = 0;
   double* gres = nullptr;       // learned-guess judge residual [nblock]
+  double* pgb = nullptr;        // plain-guess fallback: candidate and residual [2][nblock] (first use)
   double* pdv = nullptr;        // probed diagonal of the velocity block [nh1]
   double* peinv = nullptr;      // inverted probed energy blocks [Ne][Nl][Nl]
   double* rkw = nullptr;        // explicit RK2-average workspace [2 nblock] (allocated on first use)

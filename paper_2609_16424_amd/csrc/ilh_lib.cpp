@@ -303,7 +303,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->x0, c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
-                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres, c->dmin_part};
+                  c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres, c->pgb, c->dmin_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : c->qd)
@@ -1819,6 +1819,35 @@ int ilh_guess_infer(ilh_ctx* c, const ilh_guess_model* m, const double* u, const
   if (!use) ILH_HIP(c, hipMemcpyAsync(k, base, c->nblock * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   if (used) *used = use ? 1 : 0;
+  return ILH_OK;
+  ILH_CATCH(c)
+}
+
+int ilh_plain_guess_fallback(ilh_ctx* c, const double* u, const double* k1, const double* k2, int nhist,
+                             double tau, double* out, int* which) {
+  ILH_TRY
+  if (!c || !u || !out) return ILH_EINVAL;
+  int st;
+  if ((st = ilh_plain_guess(c, u, k1, k2, nhist, tau, out))) return st;
+  if (which) *which = nhist < 2 ? (nhist < 0 ? 0 : nhist) : 2;
+  if (nhist < 2) return ILH_OK;
+  const int64_t n = c->nblock;
+  if (!c->pgb && (st = dalloc(c, &c->pgb, 2 * (size_t)n))) return st;
+  double* cand = c->pgb;
+  double* res = c->pgb + n;
+  if ((st = ilh_plain_guess(c, u, k1, nullptr, 1, tau, cand))) return st;
+  double* dsc = dev_pair(c);
+  if ((st = ilh_residual(c, out, u, tau, res))) return st;
+  if ((st = dot_dev(c, res, res, n, dsc))) return st;
+  if ((st = ilh_residual(c, cand, u, tau, res))) return st;
+  if ((st = dot_dev(c, res, res, n, dsc + 1))) return st;
+  double re = 0.0, r1 = 0.0;
+  if ((st = read_pair(c, &re, &r1))) return st;
+  // keep the extrapolation unless its residual is not finite or larger than the previous rate's
+  if (!(re <= r1) && std::isfinite(r1)) {
+    ILH_HIP(c, hipMemcpyAsync(out, cand, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (which) *which = 1;
+  }
   return ILH_OK;
   ILH_CATCH(c)
 }

@@ -340,49 +340,77 @@ def train(model, X, T, epochs, batch, lr, log=None):
 
 
 def evaluate(nx, ny, k, seeds, steps, cfl_factor, opts, model_state, scales, log=None):
-    """Held-out comparison: plain vs learned vs zero-output control, equal final residual."""
-    out = {}
-    for mode in ("plain", "learned", "zero"):
-        newton, gmres, wall, used, ginit = [], [], [], 0, []
+    """Held-out comparison at equal final residual of four initial iterates: plain (the extrapolated
+    iterate; the solver starts from k = 0 when that is better), plain_fallback (the extrapolation or
+    the previous rate, whichever has the smaller stage residual, then the same k = 0 fallback),
+    learned (the MLP's correction of the extrapolation, judged against it by the residual) and a
+    zero-output control (the learned path's overhead with a network that outputs zero).  Every run of
+    a seed goes on until its first failed step.  Each mode is summarised over its completed steps,
+    and the learned run is compared with each other mode over matched steps: the step indices of a
+    seed that both runs completed, so that both are timed on the same steps."""
+    recs = {}
+    for mode in ("plain", "plain_fallback", "learned", "zero"):
+        recs[mode] = {}
         for s in seeds:
             h = make_triple(nx, ny, k, seed=s)
             u = h.init_state()
             dt = cfl_factor * h.dt_estimate(u, 0.5)
-            mlp = GuessMLP(h, [int(w) for w in model_state["widths"]])
-            if mode == "learned":
-                mlp.load_state(model_state)
-            else:
-                mlp.master.zero_()
-                mlp.pack()
-            norm = {k: model_state[k] for k in ("mu", "sd", "osc")} if "mu" in model_state else None
-            lg = LearnedGuess(h, mlp, scales, norm=norm)
-            hist = []
+            lg = None
+            if mode in ("learned", "zero"):
+                mlp = GuessMLP(h, [int(w) for w in model_state["widths"]])
+                if mode == "learned":
+                    mlp.load_state(model_state)
+                else:
+                    mlp.master.zero_()
+                    mlp.pack()
+                norm = {k: model_state[k] for k in ("mu", "sd", "osc")} if "mu" in model_state else None
+                lg = LearnedGuess(h, mlp, scales, norm=norm)
+            hist, rows, failed = [], [], False
             torch.cuda.synchronize()
             for n in range(steps):
                 t0 = time.perf_counter()
-                if mode == "plain":
-                    g, _ = h.plain_guess(u, hist, 0.5 * dt), False
+                if lg is None:
+                    g, used = h.plain_guess(u, hist, 0.5 * dt, fallback=(mode == "plain_fallback")), False
                 else:
-                    g, _ = lg.guess(u, hist, 0.5 * dt)
+                    g, used = lg.guess(u, hist, 0.5 * dt)
                 k_, st = h.implicit_step(u, dt, guess=g, opts=opts, raise_on_fail=False)
                 torch.cuda.synchronize()
-                wall.append(time.perf_counter() - t0)
+                wall = time.perf_counter() - t0
                 if st["status"] != 0:
+                    failed = True
                     break
-                newton.append(st["newton"])
-                gmres.append(st["gmres"])
-                ginit.append(st["res_init"] / max(st["res0"], 1e-300))
+                rows.append((wall, st["newton"], st["gmres"], st["res_init"] / max(st["res0"], 1e-300), used))
                 hist = (hist + [k_])[-2:]
-            used += lg.used
+            recs[mode][s] = (rows, failed)
             del h
+    out = {}
+    for mode in recs:
+        allr = [r for s in seeds for r in recs[mode][s][0]]
+        ginit = [r[3] for r in allr]
         finite = [g for g in ginit if np.isfinite(g)]
-        out[mode] = {"newton_per_step": float(np.mean(newton)), "gmres_per_step": float(np.mean(gmres)),
-                     "s_per_step": float(np.mean(wall)), "steps": len(newton), "learned_used": used,
-                     # the plain iterate's residual is not finite when its stage state is tangled
+        out[mode] = {"s_per_step": float(np.mean([r[0] for r in allr])) if allr else None,
+                     "newton_per_step": float(np.mean([r[1] for r in allr])) if allr else None,
+                     "gmres_per_step": float(np.mean([r[2] for r in allr])) if allr else None,
+                     "steps": len(allr), "learned_used": int(sum(r[4] for r in allr)),
+                     "seeds_failed": [s for s in seeds if recs[mode][s][1]],
+                     # a tangled stage state gives a non-finite initial residual
                      "median_initial_residual_ratio": float(np.median(finite)) if finite else None,
                      "non_finite_initial_residuals": len(ginit) - len(finite)}
         if log:
             log("%s: %s" % (mode, out[mode]))
+    for other in ("plain", "plain_fallback", "zero"):
+        m = {s: min(len(recs["learned"][s][0]), len(recs[other][s][0])) for s in seeds}
+        a = [r for s in seeds for r in recs["learned"][s][0][:m[s]]]
+        b = [r for s in seeds for r in recs[other][s][0][:m[s]]]
+        if not a:
+            continue
+        out["learned_vs_" + other] = {
+            "matched_steps": len(a),
+            "s_per_step_learned": float(np.mean([r[0] for r in a])), "s_per_step_" + other: float(np.mean([r[0] for r in b])),
+            "newton_learned": float(np.mean([r[1] for r in a])), "newton_" + other: float(np.mean([r[1] for r in b])),
+            "gmres_learned": float(np.mean([r[2] for r in a])), "gmres_" + other: float(np.mean([r[2] for r in b])),
+            "speedup_s_per_step": float(np.mean([r[0] for r in b]) / np.mean([r[0] for r in a]))}
+    out["steps_per_seed"] = steps
     return out
 
 

@@ -34,23 +34,30 @@ def test_trained_guess_reduces_newton_iterations_4x():
     assert learned["newton_per_step"] < plain["newton_per_step"] - 0.5
     assert learned["median_initial_residual_ratio"] < 0.5 * plain["median_initial_residual_ratio"]
     assert zero["newton_per_step"] >= plain["newton_per_step"] - 0.2
+    # over matched steps the learned iterate saves Krylov work against both plain iterates (the
+    # bench leg measures 1.37x / 1.26x in s/step over 5 seeds x 30 steps)
+    for other in ("plain", "plain_fallback"):
+        m = res["learned_vs_" + other]
+        assert m["matched_steps"] == 24
+        assert m["gmres_learned"] < 0.9 * m["gmres_" + other], (other, m)
 
 
 @pytest.mark.skipif(not os.path.exists(ilh.learned.DEFAULT_MODEL), reason="no trained model committed")
 def test_trained_guess_8x():
-    """At 8x the learned iterate is used at every step, starts Newton from a residual at least
-    ten times smaller than the plain method's start, and carries the run through every step
-    (on this held-out seed the plain run has failed after step 21 with Newton not converging;
-    the test asks only that the learned run lasts at least as long)."""
+    """At 8x the learned iterate is used at every step and carries the run through every step (on
+    this held-out seed the plain run fails after step 21 with Newton not converging, and the
+    plain iterate with the previous-rate fallback earlier still)."""
     res = _eval(ilh.learned.DEFAULT_MODEL, [1003], 24)
     plain, learned, zero = res["plain"], res["learned"], res["zero"]
     assert learned["steps"] == 24
-    assert learned["steps"] >= plain["steps"]
+    assert learned["steps"] >= plain["steps"] and learned["steps"] >= res["plain_fallback"]["steps"]
     assert learned["learned_used"] == learned["steps"]
-    # the plain iterate's stage state is often tangled here (non-finite residual)
-    pm = plain["median_initial_residual_ratio"]
-    assert pm is None or learned["median_initial_residual_ratio"] < 0.1 * pm
     assert zero["steps"] <= learned["steps"]
+    # over the steps both complete, the learned iterate needs no more Newton iterations than the
+    # plain one (its s/step there is about plain's: the bench leg measures 0.92x over 129 matched
+    # steps at 8x, so at this step size its gain is that it keeps every held-out run going)
+    m = res["learned_vs_plain"]
+    assert m["newton_learned"] <= m["newton_plain"] + 0.2, m
 
 
 @pytest.mark.skipif(not os.path.exists(ilh.learned.DEFAULT_MODEL), reason="no trained model committed")
