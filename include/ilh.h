@@ -279,6 +279,12 @@ typedef struct {
                           nor with pcg_iters > 0); 0 (default): launch its kernels one by one,
                           measured faster on this stack (graph launch costs more than the
                           kernel launches it replaces) */
+  int basis64;         /* with jvp_prec = 32: 0 (default) stores the FGMRES basis V, Z in FP32
+                          (orthogonalisation sums, Hessenberg matrix, rotations and the update
+                          of the Newton direction stay FP64; the basis then carries the 1e-7
+                          rounding the FP32 actions have anyway, and the sweeps over it move
+                          half the bytes), 1 keeps it in FP64.  FP64 actions and pcg_iters > 0
+                          always use the FP64 basis */
 } ilh_newton_opts;
 
 typedef struct {

@@ -127,6 +127,8 @@ struct ilh_ctx {
   double* sdk = nullptr;        // SDIRK stage rates and stage base [4][nblock] (allocated on first use)
   double* nwt = nullptr;        // Newton vectors: k, r, dk, tmp, zero, w [6][nblock]
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
+  int kryf_m = 0;
+  float* kryf = nullptr;        // FP32 Krylov basis (FP32 Jacobian actions): V [(m+1)][nblock], Z [m][nblock]
   double* hdev = nullptr;       // [HDEV_LEN] device scalars of the Arnoldi step
   double* hest = nullptr;       // pinned, coherent: (|g_j+1|, h_j+1,j) of each Arnoldi step at [2j, 2j+1]
   double* hest_dev = nullptr;   // and the cycle's tag at [128 + j], stored by the device (mapped address)
@@ -270,19 +272,24 @@ struct GivensJob {
 int launch_sum_givens(ilh_ctx* c, const GivensJob& job);
 // y *= *s (s on the device)
 int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n);
-int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
+// the Krylov kernels take the basis in FP64 or FP32 (TV); every product and sum is FP64
+template <typename TV>
+int multiaxpy_dev(ilh_ctx* c, double* w, const TV* V, int64_t ldv, int m, const double* h, double sign, int64_t n);
 // fused versions: w read once per 8 basis vectors.  d_out[j] = s_j V_j . w (s nullable: 1),
 // d_outs (nullable) [j] = s_j d_out[j]
 // skip (nullable, device): the launches return at once when *skip is nonzero
-int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out,
+template <typename TV>
+int multidot_fused(ilh_ctx* c, const TV* V, int64_t ldv, int m, const TV* w, int64_t n, double* d_out,
                    const double* s = nullptr, double* d_outs = nullptr, const double* skip = nullptr);
 // w -= sum_j cf[j] V_j, then the products of the updated w as in multidot_fused
-int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, int64_t n,
+template <typename TV>
+int maxpy_multidot(ilh_ctx* c, TV* w, const TV* V, int64_t ldv, int m, const double* cf, int64_t n,
                    const double* s, double* d_out, double* d_outs, const double* skip = nullptr);
 // input *rs r (rs nullable: 1); job (nullable): run that Givens update in an extra block of the
 // same launch, the other blocks then form the scale it stores (1 / |r|) from its partial sums
-int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                   double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
+template <typename TV>
+int launch_precond(ilh_ctx* c, const TV* r, TV* z, float* z32, double tau, int coupled,
+                   TV* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
                    const GivensJob* job = nullptr);
 // probed diagonal blocks of the Jacobian (preconditioner option prec_probe)
 int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau);
@@ -290,18 +297,22 @@ int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D
 int launch_probe_e_dir(ilh_ctx* c, float* d, int j);
 int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
 int launch_invert_blocks(ilh_ctx* c, double* B);
-int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
+template <typename TV>
+int launch_precond_probe(ilh_ctx* c, const TV* r, TV* z, float* z32, double tau, int coupled,
+                         TV* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
                          const GivensJob* job = nullptr);
 // w += sign sum_j cf[j] V_j with the partial sums of |w|^2 of the result; *job receives the Givens
 // update of step j that finishes it (into h[144], then from the pass coefficients h[0..j],
 // h[72..72+j], and the next basis scale h[256 + j + 1] = 1 / |w|; hest (nullable, host-mapped)
 // receives the step's (|g_j+1|, h_j+1,j) at [2j, 2j + 1] and the cycle's tag at [128 + j])
-int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double sign,
+template <typename TV>
+int multiaxpy_nrm(ilh_ctx* c, TV* w, const TV* V, int64_t ldv, int m, const double* cf, double sign,
                   int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job,
                   const double* skip = nullptr);
 // (skip nullable: the kernel returns at once when *skip is nonzero)
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev,
+                           const double* skip = nullptr);
+int launch_jvp2d_q_f32to32(ilh_ctx* c, const float* dk, float* out, const double* tau_dev,
                            const double* skip = nullptr);
 // Stage residual on the strip lane maps (2D k = 2, 3; 3D k = 2 without the TG source):
 // r = R(k; u, tau), the velocity rows of r zero on entry

@@ -576,6 +576,13 @@ int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const doubl
   return dispatch_apply<float, double>(c, dk, (const float*)c->qd[0], out, tau_dev, skip);
 }
 
+// FP32 action into an FP32 Krylov vector, tau and the skip flag from the device (same contract)
+int launch_jvp2d_q_f32to32(ilh_ctx* c, const float* dk, float* out, const double* tau_dev, const double* skip) {
+  if (!lin2d_supported(c)) return ILH_EINVAL;
+  if (!c->qd[0] || !c->qd_ok[0]) return fail(c, ILH_EINVAL, "linearised Jacobian action before its linearisation");
+  return dispatch_apply<float, float>(c, dk, (const float*)c->qd[0], out, tau_dev, skip);
+}
+
 bool lin2d_available(const ilh_ctx* c) { return lin2d_supported(c); }
 
 int64_t lin2d_coef_bytes(const ilh_ctx* c, int prec) {

@@ -210,15 +210,23 @@ static int dalloc(ilh_ctx* c, T** p, size_t count) {
   return ILH_OK;
 }
 
-static int ensure_solver_ws(ilh_ctx* c, int m) {
+// Krylov workspace for restart length m: the basis V, Z in FP64 (kry) or FP32 (kryf, f32 = true),
+// and two FP32 block vectors (kry32) for the cast actions and the probed preconditioner.
+static int ensure_solver_ws(ilh_ctx* c, int m, bool f32 = false) {
+  int st;
+  if (!c->kry32 && (st = dalloc(c, &c->kry32, (size_t)2 * c->nblock))) return st;
+  if (f32) {
+    if (c->kryf && c->kryf_m >= m) return ILH_OK;
+    if (c->kryf) (void)hipFree(c->kryf);
+    c->kryf = nullptr;
+    if ((st = dalloc(c, &c->kryf, (size_t)(2 * m + 1) * c->nblock))) return st;
+    c->kryf_m = m;
+    return ILH_OK;
+  }
   if (c->kry && c->kry_m >= m) return ILH_OK;
   if (c->kry) (void)hipFree(c->kry);
-  if (c->kry32) (void)hipFree(c->kry32);
   c->kry = nullptr;
-  c->kry32 = nullptr;
-  int st;
   if ((st = dalloc(c, &c->kry, (size_t)(2 * m + 1) * c->nblock))) return st;
-  if ((st = dalloc(c, &c->kry32, (size_t)2 * c->nblock))) return st;
   c->kry_m = m;
   return ILH_OK;
 }
@@ -279,6 +287,7 @@ void ilh_newton_defaults(ilh_newton_opts* o) {
   o->prec_probe = 0;
   o->prec_lag = 0;
   o->graphs = 0;
+  o->basis64 = 0;
 }
 
 const char* ilh_last_error(const ilh_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -302,7 +311,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
-  void* ptrs[] = {c->x0, c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
+  void* ptrs[] = {c->kryf, c->x0, c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
                   c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres, c->pgb, c->dmin_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1109,7 +1118,8 @@ static int read_pair(ilh_ctx* c, double* a, double* b) {
 // and the FGMRES cycle's tag to *tag_out
 // y = x / beta with the cycle's Arnoldi scalars: h[240] = beta, h[252] = the residual target,
 // h[255] = the cycle's tag, s_0 = h[256] = 1
-__global__ void k_scale_copy(double* y, const double* x, double beta, int64_t n, double* h, double target,
+template <typename TV>
+__global__ void k_scale_copy(TV* y, const double* x, double beta, int64_t n, double* h, double target,
                              double tag) {
   const double f = 1.0 / beta;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1119,7 +1129,7 @@ __global__ void k_scale_copy(double* y, const double* x, double beta, int64_t n,
     h[256] = 1.0;
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = x[i] * f;
+    y[i] = (TV)(x[i] * f);
 }
 
 // Exact diagonal blocks of the Jacobian at the current linearisation point, read off by FP32
@@ -1148,7 +1158,18 @@ static int build_probe_prec(ilh_ctx* c, int mode) {
   return launch_invert_blocks(c, c->peinv);
 }
 
+// The FGMRES basis V, Z is stored in TV: FP64, or FP32 when the Jacobian actions inside FGMRES
+// run in FP32 (the orthogonalisation, Hessenberg matrix, rotations and the solution update stay
+// FP64; the basis vectors carry the 1e-7 relative rounding the FP32 actions already have).
+template <typename TV>
 struct Solver {
+  static constexpr bool F32 = sizeof(TV) == 4;
+  TV* basis() const {
+    if constexpr (F32)
+      return c->kryf;
+    else
+      return c->kry;
+  }
   ilh_ctx* c;
   const ilh_newton_opts* o;
   double tau;
@@ -1161,7 +1182,7 @@ struct Solver {
   // of the preconditioner launch (or, for the PCG form, as its own launch first); *rs is the
   // scale that update stores, which the other blocks of the launch form from the same partial
   // sums, so the preconditioned vector is that of the normalised basis vector.
-  int precond(const double* r, double* z, double* next_out = nullptr, const double* rs = nullptr,
+  int precond(const TV* r, TV* z, TV* next_out = nullptr, const double* rs = nullptr,
               const GivensJob* job = nullptr) {
     int st;
     const int slot = tstart(c, 4);
@@ -1170,34 +1191,37 @@ struct Solver {
     return st;
   }
 
-  const double* z32_of = nullptr;  // the vector whose FP32 copy is in kry32 (written by precond)
-  const double* zeroed_v = nullptr;  // the FP64 vector whose velocity rows precond zeroed
+  const TV* z32_of = nullptr;  // FP64 basis: the vector whose FP32 copy is in kry32 (written by precond)
+  const TV* zeroed_v = nullptr;  // the basis vector whose velocity rows precond zeroed
   bool took_direct = false;  // an action took the direct FP32 path (tau read from the device)
 
   // FP32 linearised 2D actions write the FP64 Krylov vector directly
   bool direct64() const { return o->jvp_prec == 32 && c->jvp_variant == 0 && lin2d_available(c); }
 
-  int precond_body(const double* r, double* z, double* next_out, const double* rs, const GivensJob* job) {
+  int precond_body(const TV* r, TV* z, TV* next_out, const double* rs, const GivensJob* job) {
     const int64_t nh1 = c->nh1;
     int st;
     z32_of = nullptr;
     zeroed_v = nullptr;
-    double* zv = (next_out && direct64()) ? next_out + nh1 : nullptr;
+    TV* zv = (next_out && direct64()) ? next_out + nh1 : nullptr;
     const double* tdev = c->hdev + 250;  // tau on the device (set at the start of each solve)
     if (o->prec_probe) {
-      float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
+      float* z32 = (o->jvp_prec == 32 && !F32) ? c->kry32 : nullptr;
       if ((st = launch_precond_probe(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs, job))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
     if (o->pcg_iters <= 0) {
-      float* z32 = o->jvp_prec == 32 ? c->kry32 : nullptr;
+      float* z32 = (o->jvp_prec == 32 && !F32) ? c->kry32 : nullptr;
       if ((st = launch_precond(c, r, z, z32, tau, o->prec_coupled, zv, tdev, rs, job))) return st;
       if (z32) z32_of = z;
       if (zv) zeroed_v = next_out;
       return ILH_OK;
     }
+    if constexpr (F32) {
+      return fail(c, ILH_EINVAL, "the PCG velocity block needs the FP64 basis");
+    } else {
     if (job && (st = launch_sum_givens(c, *job))) return st;
     ILH_HIP(c, hipMemcpyAsync(z, r, nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (o->pcg_iters > 0) {
@@ -1210,6 +1234,7 @@ struct Solver {
       if ((st = launch_axpby(c, z, tau, z + nh1, 1.0, nh1))) return st;
     if (rs && (st = launch_scale_dev(c, z, rs, c->nblock))) return st;  // the operator is linear
     return ILH_OK;
+    }
   }
 
   // skip (nullable, device): used by the FP32 action written straight into the Krylov basis,
@@ -1224,6 +1249,38 @@ struct Solver {
     tdrop(c, skip_slot, skip_gen);
     skippable = false;
   }
+  // the action on a basis vector (FP32 basis: an FP32 action reading Z_j and writing V_{j+1} itself)
+  int apply_basis(const TV* x, TV* y, const double* skip = nullptr) {
+    if constexpr (!F32) {
+      return apply(x, y, skip);
+    } else {
+      int st;
+      ++jvp_calls;
+      skippable = false;
+      const bool zeroed = (y == zeroed_v);
+      zeroed_v = nullptr;
+      if (zeroed && direct64()) {
+        if (!c->qd_ok[0]) {
+          const int ls = tstart_k(c, 5);
+          st = launch_lin2d(c, 32);
+          tstop_k(c, ls);
+          if (st) return st;
+          c->qd_ok[0] = true;
+        }
+        took_direct = true;
+        const int slot = tstart_k(c, 0);
+        st = launch_jvp2d_q_f32to32(c, x, y, c->hdev + 250, skip);
+        tstop_k(c, slot);
+        skippable = skip != nullptr;
+        skip_slot = slot;
+        skip_gen = c->tgen;
+        return st;
+      }
+      return ilh_jvp_lin(c, 32, x, y);
+    }
+  }
+
+  // the action on FP64 vectors (restart residuals; with an FP64 basis, every action)
   int apply(const double* x, double* y, const double* skip = nullptr) {
     int st;
     ++jvp_calls;
@@ -1232,8 +1289,8 @@ struct Solver {
       float* x32 = c->kry32;
       float* y32 = c->kry32 + c->nblock;
       // the preconditioner leaves the FP32 copy of its output in x32; it is used once
-      const bool have32 = (x == z32_of);
-      const bool zeroed = (y == zeroed_v);
+      const bool have32 = !F32 && ((const void*)x == (const void*)z32_of);
+      const bool zeroed = !F32 && ((const void*)y == (const void*)zeroed_v);
       z32_of = nullptr;
       zeroed_v = nullptr;
       if (have32 && zeroed && direct64()) {
@@ -1271,15 +1328,15 @@ struct Solver {
   // host enqueues step j before it reads step j-1's estimate).
   int arnoldi_step(int j, int m) {
     const int64_t n = c->nblock;
-    double* V = c->kry;
-    double* Z = c->kry + (int64_t)(m + 1) * n;
+    TV* V = basis();
+    TV* Z = V + (int64_t)(m + 1) * n;
     double* hd = c->hdev;
     double* s = hd + 256;
-    double* Zj = Z + (int64_t)j * n;
-    double* w = V + (int64_t)(j + 1) * n;
+    TV* Zj = Z + (int64_t)j * n;
+    TV* w = V + (int64_t)(j + 1) * n;
     const double* skip = j > 0 ? hd + HDEV_FLAG + j - 1 : nullptr;
     int st;
-    if ((st = apply(Zj, w, skip))) return st;
+    if ((st = apply_basis(Zj, w, skip))) return st;
     // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1 fused with h2 = V^T w; w -= V h2
     const int slot = tstart(c, 3);
     if ((st = multidot_fused(c, V, n, j + 1, w, n, hd, s, hd + 480, skip))) return st;
@@ -1289,7 +1346,7 @@ struct Solver {
       return st;
     tstop(c, slot);
     if (j + 1 < m) {
-      double* next = V + (int64_t)(j + 2) * n;
+      TV* next = V + (int64_t)(j + 2) * n;
       return precond(w, Z + (int64_t)(j + 1) * n, next, s + j + 1, &job);
     }
     return launch_sum_givens(c, job);
@@ -1303,7 +1360,7 @@ struct Solver {
   uint64_t graph_key(int m) const {
     uint64_t k = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { k = (k ^ v) * 1099511628211ull; };
-    const void* ptrs[] = {c->kry, c->kry32, c->hdev, c->hest_dev, c->gmd, c->red, c->qd[0], c->Mdiag, c->MEinv,
+    const void* ptrs[] = {basis(), c->kry32, c->hdev, c->hest_dev, c->gmd, c->red, c->qd[0], c->Mdiag, c->MEinv,
                           c->pdv, c->peinv, c->rj0};
     for (const void* q : ptrs) mix((uint64_t)(uintptr_t)q);
     mix((uint64_t)m);
@@ -1329,8 +1386,8 @@ struct Solver {
       // FP32 copy of z_j and zeroed the velocity rows of V_{j+1}: the captured action must take the
       // direct FP32 path, which reads tau from the device (a captured host tau would go stale).
       const int64_t n = c->nblock;
-      z32_of = c->kry + (int64_t)(m + 1) * n + (int64_t)j * n;
-      zeroed_v = c->kry + (int64_t)(j + 1) * n;
+      z32_of = basis() + (int64_t)(m + 1) * n + (int64_t)j * n;
+      zeroed_v = basis() + (int64_t)(j + 1) * n;
       took_direct = false;
       if (!c->capstream) ILH_HIP(c, hipStreamCreateWithFlags(&c->capstream, hipStreamNonBlocking));
       hipStream_t saved = c->stream;
@@ -1369,8 +1426,8 @@ struct Solver {
   int fgmres(const double* b, double* x, int* its, double beta_b = -1.0) {
     const int64_t n = c->nblock;
     const int m = std::max(1, std::min(o->restart, 64));
-    double* V = c->kry;
-    double* Z = c->kry + (int64_t)(m + 1) * n;
+    TV* V = basis();
+    TV* Z = V + (int64_t)(m + 1) * n;
     double* hd = c->hdev;
     double* G = c->gmd;
     int st;
@@ -1395,7 +1452,7 @@ struct Solver {
     while (true) {
       // V0 = r / beta (beta, the target and the cycle's tag to the device), z_0 = P V0
       const double tag = (c->est_tag += 1.0);
-      hipLaunchKernelGGL(k_scale_copy, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd, target, tag);
+      hipLaunchKernelGGL(k_scale_copy<TV>, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd, target, tag);
       if ((st = precond(V, Z, V + n))) return st;
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
@@ -1470,14 +1527,15 @@ struct Solver {
   }
 };
 
-static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_guess, double* k_out,
-                       const ilh_newton_opts* o, ilh_step_stats* st_out) {
+template <typename TV>
+static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* k_guess, double* k_out,
+                         const ilh_newton_opts* o, ilh_step_stats* st_out) {
   const int64_t n = c->nblock;
   int st;
   ilh_step_stats stats;
   std::memset(&stats, 0, sizeof(stats));
   const int m = std::max(1, std::min(o->restart, 64));
-  if ((st = ensure_solver_ws(c, m))) return st;
+  if ((st = ensure_solver_ws(c, m, sizeof(TV) == 4))) return st;
   if (!c->nwt && (st = dalloc(c, &c->nwt, 8 * (size_t)n))) return st;
   if (!c->hdev && (st = dalloc(c, &c->hdev, HDEV_LEN))) return st;
   if (!c->hest) {
@@ -1495,7 +1553,7 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   double* zero = c->nwt + 5 * n;
   double* kt = c->nwt + 6 * n;
   double* rt = c->nwt + 7 * n;
-  Solver S{c, o, tau};
+  Solver<TV> S{c, o, tau};
   double* dsc = dev_pair(c);
   if ((st = launch_fill(c, zero, 0.0, n))) return st;
   if ((st = ilh_residual(c, zero, u, tau, r))) return st;
@@ -1614,6 +1672,15 @@ static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   if (st_out) *st_out = stats;
   return status;
+}
+
+// FP32 Jacobian actions orthogonalise an FP32 basis unless the options ask for FP64 (basis64) or
+// the velocity block of the preconditioner runs PCG (FP64 vectors)
+static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_guess, double* k_out,
+                       const ilh_newton_opts* o, ilh_step_stats* st_out) {
+  const bool f32 = o->jvp_prec == 32 && !o->basis64 && o->pcg_iters <= 0;
+  return f32 ? stage_solve_t<float>(c, u, tau, k_guess, k_out, o, st_out)
+             : stage_solve_t<double>(c, u, tau, k_guess, k_out, o, st_out);
 }
 
 }  // namespace ilh

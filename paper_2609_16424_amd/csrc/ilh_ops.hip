@@ -203,20 +203,24 @@ __global__ void __launch_bounds__(TPB) k_mdot_final(const double* part, int nb, 
     if (outs) outs[j] = sj * sj * acc;
   }
 }
-// w[i] += sign * sum_j h[j] V[j][i]
-__global__ void k_maxpy(double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
+// w[i] += sign * sum_j h[j] V[j][i] (FP64 sums; the basis V stored in FP64 or FP32)
+template <typename TV>
+__global__ void k_maxpy(double* w, const TV* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double acc = 0;
-    for (int j = 0; j < m; ++j) acc += h[j] * V[(int64_t)j * ldv + i];
+    for (int j = 0; j < m; ++j) acc += h[j] * (double)V[(int64_t)j * ldv + i];
     w[i] += sign * acc;
   }
 }
-int multiaxpy_dev(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
+template <typename TV>
+int multiaxpy_dev(ilh_ctx* c, double* w, const TV* V, int64_t ldv, int m, const double* h, double sign, int64_t n) {
   if (m <= 0) return ILH_OK;
-  hipLaunchKernelGGL(k_maxpy, dim3(nblk(n)), dim3(TPB), 0, c->stream, w, V, ldv, m, h, sign, n);
+  hipLaunchKernelGGL(k_maxpy<TV>, dim3(nblk(n)), dim3(TPB), 0, c->stream, w, V, ldv, m, h, sign, n);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
+template int multiaxpy_dev<double>(ilh_ctx*, double*, const double*, int64_t, int, const double*, double, int64_t);
+template int multiaxpy_dev<float>(ilh_ctx*, double*, const float*, int64_t, int, const double*, double, int64_t);
 
 // ------------------------------------------------------------------ fused Krylov kernels
 // Partial sums per block, then one small kernel adds them in a fixed order (deterministic).
@@ -231,8 +235,10 @@ static constexpr int64_t KTILE = (int64_t)TPB * KU;
 // indices are clamped in range, out-of-range terms enter with weight zero), so a wave keeps
 // MDOT_JC x KU loads in flight instead of one row at a time.
 
-// a[u] += sum_{j < m} cf[j] V_j[i_u] over one tile (i_u clamped to n - 1)
-__device__ __forceinline__ void tile_combo(const double* __restrict__ V, int64_t ldv, int m,
+// a[u] += sum_{j < m} cf[j] V_j[i_u] over one tile (i_u clamped to n - 1); the basis is stored in
+// FP64 or FP32, every product and sum is FP64
+template <typename TV>
+__device__ __forceinline__ void tile_combo(const TV* __restrict__ V, int64_t ldv, int m,
                                            const double* __restrict__ cf, const int64_t (&ic)[KU],
                                            double (&a)[KU]) {
   for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
@@ -243,7 +249,7 @@ __device__ __forceinline__ void tile_combo(const double* __restrict__ V, int64_t
       const int j = min(j0 + jj, m - 1);
       cj[jj] = (j0 + jj < m) ? cf[j] : 0.0;
 #pragma unroll
-      for (int u = 0; u < KU; ++u) v[jj][u] = V[(int64_t)j * ldv + ic[u]];
+      for (int u = 0; u < KU; ++u) v[jj][u] = (double)V[(int64_t)j * ldv + ic[u]];
     }
 #pragma unroll
     for (int jj = 0; jj < MDOT_JC; ++jj)
@@ -254,7 +260,8 @@ __device__ __forceinline__ void tile_combo(const double* __restrict__ V, int64_t
 
 // acc[jj] += sum_u V_{j0+jj}[i_u] wv[u] for jj < MDOT_JC (rows past m - 1 clamped; the caller
 // discards their sums)
-__device__ __forceinline__ void tile_dots(const double* __restrict__ V, int64_t ldv, int m, int j0,
+template <typename TV>
+__device__ __forceinline__ void tile_dots(const TV* __restrict__ V, int64_t ldv, int m, int j0,
                                           const int64_t (&ic)[KU], const double (&wv)[KU],
                                           double (&acc)[MDOT_JC]) {
   double v[MDOT_JC][KU];
@@ -262,7 +269,7 @@ __device__ __forceinline__ void tile_dots(const double* __restrict__ V, int64_t 
   for (int jj = 0; jj < MDOT_JC; ++jj) {
     const int j = min(j0 + jj, m - 1);
 #pragma unroll
-    for (int u = 0; u < KU; ++u) v[jj][u] = V[(int64_t)j * ldv + ic[u]];
+    for (int u = 0; u < KU; ++u) v[jj][u] = (double)V[(int64_t)j * ldv + ic[u]];
   }
 #pragma unroll
   for (int jj = 0; jj < MDOT_JC; ++jj)
@@ -291,8 +298,9 @@ __device__ __forceinline__ void store_block_sums(const double (&acc)[JC], int j0
 }
 
 // part[j][b] = block b's share of V_j . w, j < m (w read once per MDOT_JC vectors)
-__global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V, int64_t ldv, int m,
-                                                    const double* __restrict__ w, int64_t n, double* part,
+template <typename TV>
+__global__ void __launch_bounds__(TPB) k_mdot_part8(const TV* __restrict__ V, int64_t ldv, int m,
+                                                    const TV* __restrict__ w, int64_t n, double* part,
                                                     const double* skip) {
   if (skip && *skip != 0.0) return;
   const int64_t stride = (int64_t)gridDim.x * KTILE;
@@ -306,7 +314,7 @@ __global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V
       tile_index(t0, n, ic, in);
       double wv[KU];
 #pragma unroll
-      for (int u = 0; u < KU; ++u) wv[u] = in[u] ? w[ic[u]] : 0.0;
+      for (int u = 0; u < KU; ++u) wv[u] = in[u] ? (double)w[ic[u]] : 0.0;
       tile_dots(V, ldv, m, j0, ic, wv, acc);
     }
     store_block_sums(acc, j0, min(MDOT_JC, m - j0), part);
@@ -316,7 +324,8 @@ __global__ void __launch_bounds__(TPB) k_mdot_part8(const double* __restrict__ V
 // w -= sum_j cf[j] V_j, then part[j][b] = block b's share of V_j . w (the updated w), j < m:
 // the first Gram-Schmidt pass's update and the second pass's products in one sweep.  Every
 // thread revisits only its own indices, so the later chunks read back its own updates.
-__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k_maxpy_mdot_part(double* __restrict__ w, const double* __restrict__ V,
+template <typename TV>
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k_maxpy_mdot_part(TV* __restrict__ w, const TV* __restrict__ V,
                                                          int64_t ldv, int m, const double* __restrict__ cf,
                                                          int64_t n, double* part, const double* skip) {
   if (skip && *skip != 0.0) return;
@@ -337,7 +346,7 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k
         for (int jj = 0; jj < MDOT_JC; ++jj) {
           const int j = min(jj, m - 1);
 #pragma unroll
-          for (int u = 0; u < KU; ++u) v0[jj][u] = V[(int64_t)j * ldv + ic[u]];
+          for (int u = 0; u < KU; ++u) v0[jj][u] = (double)V[(int64_t)j * ldv + ic[u]];
         }
 #pragma unroll
         for (int u = 0; u < KU; ++u) a[u] = 0.0;
@@ -351,8 +360,10 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
           if (in[u]) {
-            wv[u] = w[ic[u]] - a[u];
-            w[ic[u]] = wv[u];
+            // the stored (rounded) value is the one the products take, as a later pass reads it
+            const TV wn = (TV)((double)w[ic[u]] - a[u]);
+            w[ic[u]] = wn;
+            wv[u] = (double)wn;
           } else {
             wv[u] = 0.0;
           }
@@ -363,7 +374,7 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k
           for (int u = 0; u < KU; ++u) acc[jj] += v0[jj][u] * wv[u];
       } else {
 #pragma unroll
-        for (int u = 0; u < KU; ++u) wv[u] = in[u] ? w[ic[u]] : 0.0;
+        for (int u = 0; u < KU; ++u) wv[u] = in[u] ? (double)w[ic[u]] : 0.0;
         tile_dots(V, ldv, m, j0, ic, wv, acc);
       }
     }
@@ -372,7 +383,8 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k
 }
 
 // w += sign sum_j h[j] V_j; part[b] = block b's share of |w|^2 of the result
-__global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(double* __restrict__ w, const double* __restrict__ V,
+template <typename TV>
+__global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(TV* __restrict__ w, const TV* __restrict__ V,
                                                         int64_t ldv, int m, const double* __restrict__ h,
                                                         double sign, int64_t n, double* part,
                                                         const double* skip) {
@@ -390,9 +402,9 @@ __global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(double* __restrict__ w, 
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       if (in[u]) {
-        const double wn = w[ic[u]] + sign * a[u];
+        const TV wn = (TV)((double)w[ic[u]] + sign * a[u]);
         w[ic[u]] = wn;
-        ss += wn * wn;
+        ss += (double)wn * (double)wn;  // the norm of the stored vector
       }
     }
   }
@@ -404,23 +416,25 @@ static int fused_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + KTILE - 1) / KTILE));
 }
 
-int multidot_fused(ilh_ctx* c, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* d_out,
+template <typename TV>
+int multidot_fused(ilh_ctx* c, const TV* V, int64_t ldv, int m, const TV* w, int64_t n, double* d_out,
                    const double* s, double* d_outs, const double* skip) {
   if (m <= 0) return ILH_OK;
   if (m > 64) return fail(c, ILH_EINVAL, "multidot: at most 64 vectors");
   const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_mdot_part8, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red, skip);
+  hipLaunchKernelGGL(k_mdot_part8<TV>, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, m, w, n, c->red, skip);
   hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs, skip);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
 
-int maxpy_multidot(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, int64_t n,
+template <typename TV>
+int maxpy_multidot(ilh_ctx* c, TV* w, const TV* V, int64_t ldv, int m, const double* cf, int64_t n,
                    const double* s, double* d_out, double* d_outs, const double* skip) {
   if (m <= 0) return ILH_OK;
   if (m > 64) return fail(c, ILH_EINVAL, "multidot: at most 64 vectors");
   const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_maxpy_mdot_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, n, c->red, skip);
+  hipLaunchKernelGGL(k_maxpy_mdot_part<TV>, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, n, c->red, skip);
   hipLaunchKernelGGL(k_mdot_final, dim3(m), dim3(TPB), 0, c->stream, c->red, nb, m, d_out, s, d_outs, skip);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
@@ -497,15 +511,29 @@ int launch_scale_dev(ilh_ctx* c, double* y, const double* s, int64_t n) {
   return ILH_OK;
 }
 
-int multiaxpy_nrm(ilh_ctx* c, double* w, const double* V, int64_t ldv, int m, const double* cf, double sign,
+template <typename TV>
+int multiaxpy_nrm(ilh_ctx* c, TV* w, const TV* V, int64_t ldv, int m, const double* cf, double sign,
                   int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job,
                   const double* skip) {
   const int nb = fused_blocks(n);
-  hipLaunchKernelGGL(k_maxpy_nrm_part, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, sign, n, c->red, skip);
+  hipLaunchKernelGGL(k_maxpy_nrm_part<TV>, dim3(nb), dim3(TPB), 0, c->stream, w, V, ldv, m, cf, sign, n, c->red, skip);
   ILH_HIP(c, hipGetLastError());
   *job = GivensJob{c->red, nb, h, G, j, mm, hest, skip};
   return ILH_OK;
 }
+
+template int multidot_fused<double>(ilh_ctx*, const double*, int64_t, int, const double*, int64_t, double*,
+                                    const double*, double*, const double*);
+template int multidot_fused<float>(ilh_ctx*, const float*, int64_t, int, const float*, int64_t, double*,
+                                   const double*, double*, const double*);
+template int maxpy_multidot<double>(ilh_ctx*, double*, const double*, int64_t, int, const double*, int64_t,
+                                    const double*, double*, double*, const double*);
+template int maxpy_multidot<float>(ilh_ctx*, float*, const float*, int64_t, int, const double*, int64_t,
+                                   const double*, double*, double*, const double*);
+template int multiaxpy_nrm<double>(ilh_ctx*, double*, const double*, int64_t, int, const double*, double, int64_t,
+                                   double*, double*, int, int, double*, GivensJob*, const double*);
+template int multiaxpy_nrm<float>(ilh_ctx*, float*, const float*, int64_t, int, const double*, double, int64_t,
+                                  double*, double*, int, int, double*, GivensJob*, const double*);
 
 int launch_sum_givens(ilh_ctx* c, const GivensJob& job) {
   hipLaunchKernelGGL(k_sum_givens, dim3(1), dim3(TPB), 0, c->stream, job);
@@ -576,10 +604,11 @@ int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
 // sc = *rs (rs nullable: 1).  With g.part set, the grid has one block more, block 0, which runs the norm
 // reduction and Givens update of the previous Arnoldi step, and every other block forms the
 // scale that reduction stores, sc = 1 / |r|, from the same partial sums.
-__global__ void k_precond(const double* __restrict__ r, const double* __restrict__ Mdiag,
+template <typename TV>
+__global__ void k_precond(const TV* __restrict__ r, const double* __restrict__ Mdiag,
                           const double* __restrict__ Minv, int64_t estride, const double* __restrict__ escale,
-                          double* z, float* z32,
-                          double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, double* zero_v,
+                          TV* z, float* z32,
+                          double tau, int coupled, int64_t nh1, int64_t Ne, int Nl, TV* zero_v,
                           const double* tau_dev, const double* rs, const GivensJob g) {
   if (g.skip && *g.skip != 0.0) return;
   if (g.part && blockIdx.x == 0) {  // first, so its serial chain overlaps the rest of the grid
@@ -588,13 +617,13 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
   }
   const double sc = g.part ? scale_from_partials(g.part, g.np) : (rs ? *rs : 1.0);
   const int64_t i = (blockIdx.x - (g.part ? 1 : 0)) * (int64_t)blockDim.x + threadIdx.x;
-  if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
+  if (zero_v && i < nh1) zero_v[i] = TV(0);  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
   if (i < nh1) {
-    const double zv = sc * r[nh1 + i] / Mdiag[i];
-    const double zx = coupled ? tau * zv + sc * r[i] : sc * r[i];
-    z[i] = zx;
-    z[nh1 + i] = zv;
+    const double zv = sc * (double)r[nh1 + i] / Mdiag[i];
+    const double zx = coupled ? tau * zv + sc * (double)r[i] : sc * (double)r[i];
+    z[i] = (TV)zx;
+    z[nh1 + i] = (TV)zv;
     if (z32) {
       z32[i] = (float)zx;
       z32[nh1 + i] = (float)zv;
@@ -604,23 +633,28 @@ __global__ void k_precond(const double* __restrict__ r, const double* __restrict
     const int rr = (int)(k % Nl);
     const double* Me = Minv + e * estride;
     double acc = 0;
-    for (int j = 0; j < Nl; ++j) acc += Me[rr * Nl + j] * r[2 * nh1 + e * Nl + j];
+    for (int j = 0; j < Nl; ++j) acc += Me[rr * Nl + j] * (double)r[2 * nh1 + e * Nl + j];
     const double x = sc * (escale ? escale[e] * acc : acc);
-    z[2 * nh1 + k] = x;
+    z[2 * nh1 + k] = (TV)x;
     if (z32) z32[2 * nh1 + k] = (float)x;
   }
 }
 
-int launch_precond(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled, double* zero_v,
+template <typename TV>
+int launch_precond(ilh_ctx* c, const TV* r, TV* z, float* z32, double tau, int coupled, TV* zero_v,
                    const double* tau_dev, const double* rs, const GivensJob* job) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   const GivensJob g = job ? *job : GivensJob{};
   const unsigned nb = (unsigned)((n + TPB - 1) / TPB) + (job ? 1u : 0u);
-  hipLaunchKernelGGL(k_precond, dim3(nb), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv, c->me_stride, c->me_scale,
+  hipLaunchKernelGGL(k_precond<TV>, dim3(nb), dim3(TPB), 0, c->stream, r, c->Mdiag, c->MEinv, c->me_stride, c->me_scale,
                      z, z32, tau, coupled, c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs, g);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
+template int launch_precond<double>(ilh_ctx*, const double*, double*, float*, double, int, double*, const double*,
+                                    const double*, const GivensJob*);
+template int launch_precond<float>(ilh_ctx*, const float*, float*, float*, double, int, float*, const double*,
+                                   const double*, const GivensJob*);
 
 // ------------------------------------------------------------------ probed block preconditioner
 // Node colours: (I mod M, J mod M[, K mod M]) with M = k + 1 -- two nodes of one colour never
@@ -761,9 +795,10 @@ int launch_invert_blocks(ilh_ctx* c, double* B) {
 
 // z_v = r_v / D (probed diagonal), z_x = r_x + tau z_v (coupled) or r_x, z_e = Binv r_e per element;
 // input scale and the extra last block as in k_precond
-__global__ void k_precond_probe(const double* __restrict__ r, const double* __restrict__ D,
-                                const double* __restrict__ Binv, double* z, float* z32, double tau, int coupled,
-                                int64_t nh1, int64_t Ne, int Nl, double* zero_v, const double* tau_dev,
+template <typename TV>
+__global__ void k_precond_probe(const TV* __restrict__ r, const double* __restrict__ D,
+                                const double* __restrict__ Binv, TV* z, float* z32, double tau, int coupled,
+                                int64_t nh1, int64_t Ne, int Nl, TV* zero_v, const double* tau_dev,
                                 const double* rs, const GivensJob g) {
   if (g.skip && *g.skip != 0.0) return;
   if (g.part && blockIdx.x == 0) {  // first, so its serial chain overlaps the rest of the grid
@@ -772,13 +807,13 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
   }
   const double sc = g.part ? scale_from_partials(g.part, g.np) : (rs ? *rs : 1.0);
   const int64_t i = (blockIdx.x - (g.part ? 1 : 0)) * (int64_t)blockDim.x + threadIdx.x;
-  if (zero_v && i < nh1) zero_v[i] = 0.0;  // velocity rows of the next Jacobian action's output
+  if (zero_v && i < nh1) zero_v[i] = TV(0);  // velocity rows of the next Jacobian action's output
   if (tau_dev) tau = *tau_dev;
   if (i < nh1) {
-    const double zv = sc * r[nh1 + i] / D[i];
-    const double zx = coupled ? tau * zv + sc * r[i] : sc * r[i];
-    z[i] = zx;
-    z[nh1 + i] = zv;
+    const double zv = sc * (double)r[nh1 + i] / D[i];
+    const double zx = coupled ? tau * zv + sc * (double)r[i] : sc * (double)r[i];
+    z[i] = (TV)zx;
+    z[nh1 + i] = (TV)zv;
     if (z32) {
       z32[i] = (float)zx;
       z32[nh1 + i] = (float)zv;
@@ -788,23 +823,28 @@ __global__ void k_precond_probe(const double* __restrict__ r, const double* __re
     const int rr = (int)(k % Nl);
     const double* Bi = Binv + (e * Nl + rr) * Nl;
     double acc = 0;
-    for (int j = 0; j < Nl; ++j) acc += Bi[j] * r[2 * nh1 + e * Nl + j];
+    for (int j = 0; j < Nl; ++j) acc += Bi[j] * (double)r[2 * nh1 + e * Nl + j];
     acc *= sc;
-    z[2 * nh1 + k] = acc;
+    z[2 * nh1 + k] = (TV)acc;
     if (z32) z32[2 * nh1 + k] = (float)acc;
   }
 }
 
-int launch_precond_probe(ilh_ctx* c, const double* r, double* z, float* z32, double tau, int coupled,
-                         double* zero_v, const double* tau_dev, const double* rs, const GivensJob* job) {
+template <typename TV>
+int launch_precond_probe(ilh_ctx* c, const TV* r, TV* z, float* z32, double tau, int coupled,
+                         TV* zero_v, const double* tau_dev, const double* rs, const GivensJob* job) {
   const int64_t n = c->nh1 + c->Ne * c->Nl;
   const GivensJob g = job ? *job : GivensJob{};
   const unsigned nb = (unsigned)((n + TPB - 1) / TPB) + (job ? 1u : 0u);
-  hipLaunchKernelGGL(k_precond_probe, dim3(nb), dim3(TPB), 0, c->stream, r, c->pdv, c->peinv, z, z32, tau, coupled,
+  hipLaunchKernelGGL(k_precond_probe<TV>, dim3(nb), dim3(TPB), 0, c->stream, r, c->pdv, c->peinv, z, z32, tau, coupled,
                      c->nh1, c->Ne, c->Nl, zero_v, tau_dev, rs, g);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
+template int launch_precond_probe<double>(ilh_ctx*, const double*, double*, float*, double, int, double*,
+                                          const double*, const double*, const GivensJob*);
+template int launch_precond_probe<float>(ilh_ctx*, const float*, float*, float*, double, int, float*,
+                                         const double*, const double*, const GivensJob*);
 
 // ------------------------------------------------------------------ mass operators
 // y += M_V x (values-only partial assembly).  bc != 0: constrained inputs read as zero and

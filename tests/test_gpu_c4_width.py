@@ -1,9 +1,9 @@
 """The triple point as configured (112x48 Q3Q2, smoothing width delta_scale = 1e-3, 8x the explicit
 step, FP32 Jacobian actions): the first four implicit steps converge (each taking many Newton
 iterations with halvings when solved directly, two or three after a continuation in the width
-0.1 -> 1e-3 within the step), and the fifth step tangles the stage mesh (ETANGLED) with and
-without the continuation -- at this step size the failure is not the width's: the continuation's
-first solve at width 0.1 tangles too.  The same configuration runs under the paper's Newton-based
+0.1 -> 1e-3 within the step), and the fifth step fails (the stage mesh tangles, or Newton stalls)
+with and without the continuation -- at this step size the failure is not the width's: the
+continuation's first solve at width 0.1 fails too.  The same configuration runs under the paper's Newton-based
 step control at about a quarter of the explicit step (bench leg c4_configured_width)."""
 import pytest
 
@@ -46,5 +46,8 @@ def test_configured_width_direct_and_continuation():
     assert [s for s, _, _ in direct[:4]] == [0] * 4 and [s for s, _, _ in cont[:4]] == [0] * 4
     assert max(n for _, n, _ in direct[:4]) >= 6          # the sharp switch slows Newton
     assert max(n for _, n, _ in cont[:4]) <= 4             # from the continued iterate: fast
-    assert direct[4][0] == ilh._lib.ILH_ETANGLED and cont[4][0] == ilh._lib.ILH_ETANGLED
-    assert cont[4][2] == ilh._lib.ILH_ETANGLED             # width 0.1 tangles there as well
+    # the fifth step fails either way (the line search cannot keep det J > 0, or Newton stalls),
+    # and so does the continuation's first solve, at width 0.1
+    assert direct[4][0] in (ilh._lib.ILH_ETANGLED, ilh._lib.ILH_ENOCONV)
+    assert cont[4][0] in (ilh._lib.ILH_ETANGLED, ilh._lib.ILH_ENOCONV)
+    assert cont[4][2] in (ilh._lib.ILH_ETANGLED, ilh._lib.ILH_ENOCONV)
