@@ -37,17 +37,18 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of one FP32 Jacobian-action launch at 128x128 Q3Q2 without viscosity, from two
+# HBM traffic of one FP32 Jacobian-action launch (FP32 output: the FP32 Krylov basis) at 128x128
+# Q3Q2 without viscosity, from two
 # rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
 # the same counter reads for a copy-shaped kernel of known size (--copy-probe-mib).  The record
 # holds only while the kernel sources hash to the value it was taken with; otherwise traffic is
 # reported as null.
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
-TRAFFIC_RECORD = {"sha256": "3512a049aaa31f4643a1952279bb2c782990bf1b9a85ae1536c5359fb25097fa",
+TRAFFIC_RECORD = {"sha256": "1743b8497b54c27cf59b950c147694ea9f96a49bc6533cda2dd6957c75f6e1b2",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16587.1, "fetch_scale": 262144.0 / 131081.1,
-                  "write_kib": 7084.5, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 16579.4, "fetch_scale": 262144.0 / 131080.06,
+                  "write_kib": 3837.8, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
@@ -62,7 +63,7 @@ def sources_sha256():
 # VALU instructions per launch of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU, same sources):
 # the issue peak of wave64 FP32 (unpacked) / FP64 VALU instructions is 1024 SIMDs x 2.4 GHz / 4.
 VALU_RECORD = {"sha256": TRAFFIC_RECORD["sha256"], "variant": "lin", "n": 128, "order": 3,
-               "instructions": 2621791.7}
+               "instructions": 2603606.1}
 VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
@@ -177,7 +178,7 @@ def residual_rate(H, k, u, tau, launches):
             "design_bytes_per_launch": bd, "bandwidth_frac": bd / avg / 1e9 / HBM_PEAK_GBS}
 
 
-KERNEL_NAMES = {"lin": "k_jvp2d_q<4,6,float,visc=0,src=1,out=double,waves=1>", "generic": "k_elem2d<4,6,JVP,float,7>",
+KERNEL_NAMES = {"lin": "k_jvp2d_q<4,6,float,visc=0,src=1,out=float,waves=1>", "generic": "k_elem2d<4,6,JVP,float,7>",
                 "recompute": "k_jvp2d<4,6,float,visc=0,src=1>"}
 
 
@@ -640,8 +641,8 @@ def main():
     # Jacobian actions per second of kernel time, the linearisation launches charged to them
     value = H.nqp * jvp_n / (1e-3 * (jvp_ms + lin_ms))
     bytes32 = jvp_bytes(H, 32, args.jvp_variant)
-    # inside FGMRES the linearised FP32 action writes the FP64 Krylov vector itself
-    bytes_loop = bytes32 + (4 * H.nblock if args.jvp_variant == "lin" else 0)
+    # inside FGMRES the linearised FP32 action writes the (FP32) Krylov basis vector itself
+    bytes_loop = bytes32
     alg32 = alg_bytes(H, 32)
     achieved = alg32 / jvp_avg_s / 1e9
     # the same kernel back to back at the last linearisation point (no other kernels between)

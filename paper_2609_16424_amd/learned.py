@@ -373,13 +373,16 @@ def evaluate(nx, ny, k, seeds, steps, cfl_factor, opts, model_state, scales, log
                     g, used = h.plain_guess(u, hist, 0.5 * dt, fallback=(mode == "plain_fallback")), False
                 else:
                     g, used = lg.guess(u, hist, 0.5 * dt)
+                torch.cuda.synchronize()
+                t_guess = time.perf_counter() - t0
                 k_, st = h.implicit_step(u, dt, guess=g, opts=opts, raise_on_fail=False)
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t0
                 if st["status"] != 0:
                     failed = True
                     break
-                rows.append((wall, st["newton"], st["gmres"], st["res_init"] / max(st["res0"], 1e-300), used))
+                rows.append((wall, st["newton"], st["gmres"], st["res_init"] / max(st["res0"], 1e-300), used,
+                             t_guess))
                 hist = (hist + [k_])[-2:]
             recs[mode][s] = (rows, failed)
             del h
@@ -392,6 +395,9 @@ def evaluate(nx, ny, k, seeds, steps, cfl_factor, opts, model_state, scales, log
                      "newton_per_step": float(np.mean([r[1] for r in allr])) if allr else None,
                      "gmres_per_step": float(np.mean([r[2] for r in allr])) if allr else None,
                      "steps": len(allr), "learned_used": int(sum(r[4] for r in allr)),
+                     # the initial iterate's share of the step: plain extrapolation, or features,
+                     # MLP inference, assembly and the residual judge (synchronised)
+                     "guess_s_per_step": float(np.mean([r[5] for r in allr])) if allr else None,
                      "seeds_failed": [s for s in seeds if recs[mode][s][1]],
                      # a tangled stage state gives a non-finite initial residual
                      "median_initial_residual_ratio": float(np.median(finite)) if finite else None,
@@ -416,7 +422,7 @@ def evaluate(nx, ny, k, seeds, steps, cfl_factor, opts, model_state, scales, log
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval", "probe"])
+    ap.add_argument("cmd", choices=["train", "eval", "probe", "mlpbench"])
     ap.add_argument("--nx", type=int, default=112)
     ap.add_argument("--ny", type=int, default=48)
     ap.add_argument("--order", type=int, default=3)
@@ -444,6 +450,31 @@ def main(argv=None):
                           pcg_iters=a.pcg_iters, prec_probe=a.prec_probe, prec_lag=a.prec_lag)
     lo, hi = [int(v) for v in a.eval_seeds.split("-")]
     eval_seeds = list(range(lo, hi + 1))
+    if a.cmd == "mlpbench":
+        # the MLP kernels alone, for counter and timing passes: two epochs of training on 32,768
+        # random samples (batch 4,096) and three learned guesses of the triple point (5,376 elements)
+        z = np.load(a.model)
+        widths = [int(w) for w in z["widths"]]
+        h = make_triple(a.nx, a.ny, a.order, seed=1000)
+        m = GuessMLP(h, widths, seed=0)
+        g = torch.Generator(device=h.device).manual_seed(0)
+        X = torch.randn(32768, pad32(widths[0]), device=h.device, generator=g)
+        T = torch.randn(32768, pad32(widths[-1]), device=h.device, generator=g)
+        t0 = time.time()
+        train(m, X, T, 2, 4096, 1e-3)
+        torch.cuda.synchronize()
+        log("training: 2 epochs x 8 batches of 4096 in %.3f s" % (time.time() - t0))
+        scales = dict(zip(("vs", "es", "xs", "kvs", "kes"), z["scales"].tolist()))
+        m2 = GuessMLP(h, widths)
+        m2.load_state({k: z[k] for k in ("widths", "master")})
+        lg = LearnedGuess(h, m2, scales, norm={k: z[k] for k in ("mu", "sd", "osc")})
+        u = h.init_state()
+        dt = a.cfl_factor * h.dt_estimate(u, 0.5)
+        for _ in range(3):
+            lg.guess(u, [], 0.5 * dt)
+        torch.cuda.synchronize()
+        log("inference: 3 learned guesses on %d elements" % h.Ne)
+        return
     if a.cmd == "probe":
         h = make_triple(a.nx, a.ny, a.order, seed=None)
         u = h.init_state()
