@@ -2,9 +2,10 @@
 step, FP32 Jacobian actions): the first four implicit steps converge (each taking many Newton
 iterations with halvings when solved directly, two or three after a continuation in the width
 0.1 -> 1e-3 within the step), and the fifth step fails (the stage mesh tangles, or Newton stalls)
-with and without the continuation -- at this step size the failure is not the width's: the
-continuation's first solve at width 0.1 fails too.  The same configuration runs under the paper's Newton-based
-step control at about a quarter of the explicit step (bench leg c4_configured_width)."""
+with and without the continuation.  Whether the continuation's first solve at width 0.1 also
+fails at the fifth step turns on rounding (it failed in some runs and converged in others), so
+it is recorded, not asserted.  The same configuration runs under the paper's Newton-based step
+control at about a quarter of the explicit step (bench leg c4_configured_width)."""
 import pytest
 
 import paper_2609_16424_amd as ilh
@@ -46,8 +47,7 @@ def test_configured_width_direct_and_continuation():
     assert [s for s, _, _ in direct[:4]] == [0] * 4 and [s for s, _, _ in cont[:4]] == [0] * 4
     assert max(n for _, n, _ in direct[:4]) >= 6          # the sharp switch slows Newton
     assert max(n for _, n, _ in cont[:4]) <= 4             # from the continued iterate: fast
-    # the fifth step fails either way (the line search cannot keep det J > 0, or Newton stalls),
-    # and so does the continuation's first solve, at width 0.1
+    # the fifth step fails either way (the line search cannot keep det J > 0, or Newton stalls)
     assert direct[4][0] in (ilh._lib.ILH_ETANGLED, ilh._lib.ILH_ENOCONV)
     assert cont[4][0] in (ilh._lib.ILH_ETANGLED, ilh._lib.ILH_ENOCONV)
-    assert cont[4][2] in (ilh._lib.ILH_ETANGLED, ilh._lib.ILH_ENOCONV)
+    print("fifth step, continuation's first solve (width 0.1): status", cont[4][2])
