@@ -285,6 +285,15 @@ typedef struct {
                           rounding the FP32 actions have anyway, and the sweeps over it move
                           half the bytes), 1 keeps it in FP64.  FP64 actions and pcg_iters > 0
                           always use the FP64 basis */
+  int cgs2;            /* FGMRES orthogonalisation (Sec. 3.5; both are classical Gram-Schmidt
+                          twice, so the basis is orthonormal to the same order): 0 (default) takes
+                          the second pass of each basis vector one Arnoldi step late, together
+                          with the first pass of the next vector (one dot-product sweep and one
+                          update sweep over the basis per step, the preconditioner and the
+                          Givens update inside them: four launches per step; the residual
+                          estimate of a column is known one step later, so a converging cycle
+                          runs one more Jacobian action); 1 runs both passes in the step (three
+                          sweeps, seven launches).  pcg_iters > 0 always uses 1 */
 } ilh_newton_opts;
 
 typedef struct {

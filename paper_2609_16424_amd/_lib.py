@@ -28,7 +28,7 @@ class NewtonOpts(C.Structure):
         ("gmres_rtol", C.c_double), ("gmres_maxit", C.c_int), ("jvp_prec", C.c_int),
         ("max_halvings", C.c_int), ("pcg_iters", C.c_int), ("prec_coupled", C.c_int),
         ("guess_fallback", C.c_int), ("ls_residual", C.c_int), ("prec_probe", C.c_int),
-        ("prec_lag", C.c_int), ("graphs", C.c_int), ("basis64", C.c_int),
+        ("prec_lag", C.c_int), ("graphs", C.c_int), ("basis64", C.c_int), ("cgs2", C.c_int),
     ]
 
 

@@ -129,6 +129,7 @@ struct ilh_ctx {
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   int kryf_m = 0;
   float* kryf = nullptr;        // FP32 Krylov basis (FP32 Jacobian actions): V [(m+1)][nblock], Z [m][nblock]
+  double* gsp = nullptr;        // partial sums of the lagged Gram-Schmidt dot sweep [132][1024]
   double* hdev = nullptr;       // [HDEV_LEN] device scalars of the Arnoldi step
   double* hest = nullptr;       // pinned, coherent: (|g_j+1|, h_j+1,j) of each Arnoldi step at [2j, 2j+1]
   double* hest_dev = nullptr;   // and the cycle's tag at [128 + j], stored by the device (mapped address)
@@ -252,7 +253,10 @@ int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_o
 // is 1 when step j ended the cycle (residual estimate at most the target, or a zero norm), and
 // every kernel of step j + 1 then returns at once
 constexpr int HDEV_FLAG = 640;
-constexpr int HDEV_LEN = 704;
+// [704, 769): the first-pass coefficients of the previous Arnoldi step, 769 the inverse scale of
+// the stored once-orthogonalised vector (Gram-Schmidt with the second pass lagged one step)
+constexpr int HDEV_LGSP = 704;
+constexpr int HDEV_LEN = 776;
 // y = H(0:n, 0:n)^-1 g
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
 // Norm reduction and Givens update of Arnoldi step j: the partial sums of |w|^2 (part, np blocks),
@@ -309,6 +313,18 @@ template <typename TV>
 int multiaxpy_nrm(ilh_ctx* c, TV* w, const TV* V, int64_t ldv, int m, const double* cf, double sign,
                   int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job,
                   const double* skip = nullptr);
+// Gram-Schmidt with the second pass lagged one step (the scheme is described at the kernels):
+// the dot sweep of step j (w nullable: the closing step) into part (np partials per sum), the
+// final block, and the update sweep with the preconditioner of the next basis vector (z nullable:
+// none; probe selects the probed blocks instead of the mass-matrix ones).
+template <typename TV>
+int lgs_dots(ilh_ctx* c, const TV* V, int64_t ldv, int j, const TV* uj, const TV* w, int64_t n, double* part,
+             int* np, const double* skip);
+int lgs_final(ilh_ctx* c, const double* part, int np, int j, int m, int has_w, double* h, double* G, double* hest,
+              const double* skip);
+template <typename TV>
+int lgs_update(ilh_ctx* c, TV* V, int64_t ldv, int j, const double* h, TV* z, float* z32, TV* zero_v, int probe,
+               int coupled, const double* tau_dev, double* hest, const double* skip_step, const double* skip_upd);
 // (skip nullable: the kernel returns at once when *skip is nonzero)
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev,
                            const double* skip = nullptr);

@@ -288,6 +288,7 @@ void ilh_newton_defaults(ilh_newton_opts* o) {
   o->prec_lag = 0;
   o->graphs = 0;
   o->basis64 = 0;
+  o->cgs2 = 0;
 }
 
 const char* ilh_last_error(const ilh_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -311,7 +312,7 @@ int ilh_sizes(const ilh_ctx* c, int64_t* nh1, int64_t* nl2, int64_t* nb, int64_t
 
 void ilh_destroy(ilh_ctx* c) {
   if (!c) return;
-  void* ptrs[] = {c->kryf, c->x0, c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
+  void* ptrs[] = {c->gsp, c->kryf, c->x0, c->rj0, c->j0e, c->tab, c->tabf, c->mq, c->detJ0, c->gamma, c->rho0, c->e0, c->MEinv, c->Mdiag,
                   c->w64, c->w32, c->red, c->ws, c->pcgbuf, c->kry, c->nwt, c->kry32, c->hdev, c->gmd, c->sdk, c->rkw, c->pdv, c->peinv, c->gscr, c->gres, c->pgb, c->dmin_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1352,6 +1353,45 @@ struct Solver {
     return launch_sum_givens(c, job);
   }
 
+  // The lagged form (Gram-Schmidt with the second pass lagged one step; scheme at the kernels):
+  // the preconditioners of the mass-matrix or probed-block kind, which the update sweep applies
+  bool lagged() const { return !o->cgs2 && o->pcg_iters <= 0; }
+
+  // Arnoldi step j of the lagged form in a cycle of L columns: j < L applies J to z_j (in Z_j,
+  // formed from u_j by step j - 1 or the cycle start) into slot j + 1, runs the dot sweep, the
+  // final block and the update sweep (v_j, u_{j+1} and, when step j + 1 is a full step, z_{j+1});
+  // j == L is the closing step (dot sweep on u_L and the final block).  The final block of step
+  // j finishes column j - 1, stores its residual estimate and sets end flag j; every launch of
+  // step j reads end flag j - 1, the update sweep end flag j.
+  int lag_step(int j, int m, int L) {
+    const int64_t n = c->nblock;
+    TV* V = basis();
+    TV* Z = V + (int64_t)(m + 1) * n;
+    double* hd = c->hdev;
+    const double* skip = j > 0 ? hd + HDEV_FLAG + j - 1 : nullptr;
+    const bool full = j < L;
+    TV* w = full ? V + (int64_t)(j + 1) * n : nullptr;
+    int st;
+    if (full && (st = apply_basis(Z + (int64_t)j * n, w, skip))) return st;
+    const int slot = tstart(c, 3);
+    int np = 0;
+    if ((st = lgs_dots<TV>(c, V, n, j, V + (int64_t)j * n, w, n, c->gsp, &np, skip))) return st;
+    if ((st = lgs_final(c, c->gsp, np, j, m, full ? 1 : 0, hd, c->gmd, c->hest_dev, skip))) return st;
+    if (full) {
+      const bool next = j + 1 < L;  // step j + 1 applies J to z_{j+1}
+      TV* zn = next ? Z + (int64_t)(j + 1) * n : nullptr;
+      TV* out = (next && direct64()) ? V + (int64_t)(j + 2) * n : nullptr;
+      float* z32 = (next && o->jvp_prec == 32 && !F32) ? c->kry32 : nullptr;
+      if ((st = lgs_update<TV>(c, V, n, j, hd, zn, z32, out, o->prec_probe, o->prec_coupled, hd + 250, c->hest_dev,
+                               skip, hd + HDEV_FLAG + j)))
+        return st;
+      z32_of = z32 ? zn : nullptr;
+      zeroed_v = out;
+    }
+    tstop(c, slot);
+    return ILH_OK;
+  }
+
   // Graph replay applies when every kernel of the step reads its varying inputs from device
   // memory (tau) and no kernel of it synchronises: linearised FP32 2D actions with the mass or
   // probed preconditioner, kernel timing off.
@@ -1369,19 +1409,22 @@ struct Solver {
     mix((uint64_t)c->apply_rows);
     mix((uint64_t)c->apply_waves);
     mix((uint64_t)c->nblock);
+    mix((uint64_t)lagged());
     return k;
   }
 
-  // The captured step j (captured on first use for this configuration).
-  int graph_for(int j, int m, hipGraphExec_t* out) {
+  // The captured step j (captured on first use for this configuration; the lagged form keeps two
+  // per basis index: with and without z_{j+1}, i.e. j + 1 < L or not).
+  int graph_for(int j, int m, int L, hipGraphExec_t* out) {
     const uint64_t key = graph_key(m);
     if (key != c->gkey) {
       for (hipGraphExec_t e : c->gexec)
         if (e) (void)hipGraphExecDestroy(e);
-      c->gexec.assign(64, nullptr);
+      c->gexec.assign(128, nullptr);
       c->gkey = key;
     }
-    if (!c->gexec[j]) {
+    const int gi = lagged() ? 2 * j + (j + 1 < L ? 1 : 0) : j;
+    if (!c->gexec[gi]) {
       // Step j - 1 (replayed, so its host-side records were not made) or the cycle start left the
       // FP32 copy of z_j and zeroed the velocity rows of V_{j+1}: the captured action must take the
       // direct FP32 path, which reads tau from the device (a captured host tau would go stale).
@@ -1394,7 +1437,7 @@ struct Solver {
       c->stream = c->capstream;
       ILH_HIP(c, hipStreamBeginCapture(c->capstream, hipStreamCaptureModeThreadLocal));
       const int calls = jvp_calls;  // the replays count the action
-      const int st = arnoldi_step(j, m);
+      const int st = lagged() ? lag_step(j, m, L) : arnoldi_step(j, m);
       jvp_calls = calls;
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(c->capstream, &g);
@@ -1408,9 +1451,9 @@ struct Solver {
       const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       ILH_HIP(c, ei);
-      c->gexec[j] = ex;
+      c->gexec[gi] = ex;
     }
-    *out = c->gexec[j];
+    *out = c->gexec[gi];
     return ILH_OK;
   }
 
@@ -1484,13 +1527,41 @@ struct Solver {
         return ILH_OK;
       };
       bool end = false;
-      for (int j = 0; j < m && !end; ++j) {
+      if (lagged()) {
+        // columns this cycle may finish; step j finishes column j - 1, so the host reads column
+        // j - 2 after enqueuing step j (one step ahead), and the closing step L finishes the last
+        const int L = std::max(1, std::min(m, o->gmres_maxit - total));
+        for (int j = 0; j <= L && !end; ++j) {
+          if (use_graph && j < L) {
+            hipGraphExec_t ex;
+            if ((st = graph_for(j, m, L, &ex))) return st;
+            ILH_HIP(c, hipGraphLaunch(ex, c->stream));
+            ++jvp_calls;
+            skippable = j > 0;
+            skip_slot = -1;
+          } else if ((st = lag_step(j, m, L))) {
+            return st;
+          }
+          if (j >= 2) {
+            if ((st = check(j - 2, end))) return st;
+            if (end) {
+              j_end = j - 1;  // step j was speculative
+              if (dev_end && j < L) drop_skipped();  // and its launches returned at once
+            }
+          }
+        }
+        if (!end) {
+          if ((st = check(L - 1, end))) return st;
+          j_end = L;
+        }
+      }
+      for (int j = 0; j < m && !end && !lagged(); ++j) {
         // step j - 1 is the last one the iteration limit allows: step j is not enqueued
         const bool enqueue = !(j >= 1 && total + 1 >= o->gmres_maxit);
         if (!enqueue) {
         } else if (use_graph) {
           hipGraphExec_t ex;
-          if ((st = graph_for(j, m, &ex))) return st;
+          if ((st = graph_for(j, m, m, &ex))) return st;
           ILH_HIP(c, hipGraphLaunch(ex, c->stream));
           ++jvp_calls;
           skippable = j > 0;  // timing is off in graph replay
@@ -1506,7 +1577,7 @@ struct Solver {
           }
         }
       }
-      if (!end) {  // the cycle filled the basis: read its last step
+      if (!end && !lagged()) {  // the cycle filled the basis: read its last step
         if ((st = check(m - 1, end))) return st;
         j_end = m;
       }
@@ -1536,6 +1607,7 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
   std::memset(&stats, 0, sizeof(stats));
   const int m = std::max(1, std::min(o->restart, 64));
   if ((st = ensure_solver_ws(c, m, sizeof(TV) == 4))) return st;
+  if (!c->gsp && (st = dalloc(c, &c->gsp, (size_t)132 * 1024))) return st;
   if (!c->nwt && (st = dalloc(c, &c->nwt, 8 * (size_t)n))) return st;
   if (!c->hdev && (st = dalloc(c, &c->hdev, HDEV_LEN))) return st;
   if (!c->hest) {

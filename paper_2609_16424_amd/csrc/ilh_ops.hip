@@ -286,15 +286,69 @@ __device__ __forceinline__ void tile_index(int64_t t0, int64_t n, int64_t (&ic)[
   }
 }
 
-template <int JC>
-__device__ __forceinline__ void store_block_sums(const double (&acc)[JC], int j0, int jn, double* part) {
+// x[i_u] for one tile, 0 past n: the loads are unconditional (i_u is clamped in range) and only
+// the value is selected, so they are issued together; a load under the range test compiles to a
+// branch with a wait for each element
+template <typename TV>
+__device__ __forceinline__ void tile_load(const TV* __restrict__ x, const int64_t (&ic)[KU], const bool (&in)[KU],
+                                          double (&v)[KU]) {
+  double t[KU];
 #pragma unroll
-  for (int jj = 0; jj < JC; ++jj) {
-    if (jj < jn) {
-      const double t = block_sum<TPB>(acc[jj]);
-      if (threadIdx.x == 0) part[(int64_t)(j0 + jj) * gridDim.x + blockIdx.x] = t;
+  for (int u = 0; u < KU; ++u) t[u] = (double)x[ic[u]];
+#pragma unroll
+  for (int u = 0; u < KU; ++u) v[u] = in[u] ? t[u] : 0.0;
+}
+
+// Sums of K values (K a power of two, at most 64) over the 64 lanes of a wave.  Each exchange
+// pairs lane l with l ^ mask and halves the values a lane holds (it keeps one half, adds the
+// partner's copy of that half): K - 1 + (6 - log2 K) shuffles instead of 6 K.  Afterwards every
+// lane holds in acc[0] the complete sum of the value index returned (the lanes that differ only
+// in their low 6 - log2 K bits hold the same one).
+template <int CNT, int MASK, int K>
+__device__ __forceinline__ void wave_sums_r(double (&acc)[K], int lane, int& v) {
+  if constexpr (MASK >= 1) {
+    const bool hi = (lane & MASK) != 0;
+    if constexpr (CNT > 1) {
+      constexpr int HALF = CNT / 2;
+#pragma unroll
+      for (int i = 0; i < HALF; ++i) {
+        const double send = hi ? acc[i] : acc[i + HALF];
+        const double keep = hi ? acc[i + HALF] : acc[i];
+        acc[i] = keep + __shfl_xor(send, MASK, 64);
+      }
+      if (hi) v += HALF;
+      wave_sums_r<HALF, MASK / 2, K>(acc, lane, v);
+    } else {
+      acc[0] += __shfl_xor(acc[0], MASK, 64);
+      wave_sums_r<1, MASK / 2, K>(acc, lane, v);
     }
   }
+}
+
+template <int K>
+__device__ __forceinline__ int wave_sums(double (&acc)[K]) {
+  static_assert(K >= 1 && K <= 64 && (K & (K - 1)) == 0, "K: a power of two up to 64");
+  int v = 0;
+  wave_sums_r<K, 32, K>(acc, (int)(threadIdx.x & 63), v);
+  return v;
+}
+
+// part[(j0 + jj) * gridDim.x + blockIdx.x] = block sum of acc[jj], jj < jn
+template <int JC>
+__device__ __forceinline__ void store_block_sums(double (&acc)[JC], int j0, int jn, double* part) {
+  __shared__ double sh[TPB / 64][JC];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int v = wave_sums<JC>(acc);
+  if ((lane & (64 / JC - 1)) == 0) sh[wid][v] = acc[0];
+  __syncthreads();
+  const int q = threadIdx.x;
+  if (q < jn) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < TPB / 64; ++i) r += sh[i][q];
+    part[(int64_t)(j0 + q) * gridDim.x + blockIdx.x] = r;
+  }
+  __syncthreads();
 }
 
 // part[j][b] = block b's share of V_j . w, j < m (w read once per MDOT_JC vectors)
@@ -313,8 +367,7 @@ __global__ void __launch_bounds__(TPB) k_mdot_part8(const TV* __restrict__ V, in
       bool in[KU];
       tile_index(t0, n, ic, in);
       double wv[KU];
-#pragma unroll
-      for (int u = 0; u < KU; ++u) wv[u] = in[u] ? (double)w[ic[u]] : 0.0;
+      tile_load(w, ic, in, wv);
       tile_dots(V, ldv, m, j0, ic, wv, acc);
     }
     store_block_sums(acc, j0, min(MDOT_JC, m - j0), part);
@@ -357,24 +410,21 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) k
           for (int u = 0; u < KU; ++u) a[u] += cj * v0[jj][u];
         }
         if (m > MDOT_JC) tile_combo(V + MDOT_JC * ldv, ldv, m - MDOT_JC, cf + MDOT_JC, ic, a);
+        double wo[KU];
+        tile_load(w, ic, in, wo);
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
-          if (in[u]) {
-            // the stored (rounded) value is the one the products take, as a later pass reads it
-            const TV wn = (TV)((double)w[ic[u]] - a[u]);
-            w[ic[u]] = wn;
-            wv[u] = (double)wn;
-          } else {
-            wv[u] = 0.0;
-          }
+          // the stored (rounded) value is the one the products take, as a later pass reads it
+          const TV wn = (TV)(wo[u] - a[u]);
+          if (in[u]) w[ic[u]] = wn;
+          wv[u] = in[u] ? (double)wn : 0.0;
         }
 #pragma unroll
         for (int jj = 0; jj < MDOT_JC; ++jj)
 #pragma unroll
           for (int u = 0; u < KU; ++u) acc[jj] += v0[jj][u] * wv[u];
       } else {
-#pragma unroll
-        for (int u = 0; u < KU; ++u) wv[u] = in[u] ? (double)w[ic[u]] : 0.0;
+        tile_load(w, ic, in, wv);
         tile_dots(V, ldv, m, j0, ic, wv, acc);
       }
     }
@@ -399,13 +449,14 @@ __global__ void __launch_bounds__(TPB) k_maxpy_nrm_part(TV* __restrict__ w, cons
 #pragma unroll
     for (int u = 0; u < KU; ++u) a[u] = 0.0;
     tile_combo(V, ldv, m, h, ic, a);
+    double wo[KU];
+    tile_load(w, ic, in, wo);
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
-      if (in[u]) {
-        const TV wn = (TV)((double)w[ic[u]] + sign * a[u]);
-        w[ic[u]] = wn;
-        ss += (double)wn * (double)wn;  // the norm of the stored vector
-      }
+      const TV wn = (TV)(wo[u] + sign * a[u]);
+      const double wd = (double)wn;
+      ss += in[u] ? wd * wd : 0.0;  // the norm of the stored vector
+      if (in[u]) w[ic[u]] = wn;
     }
   }
   ss = block_sum<TPB>(ss);
@@ -549,8 +600,9 @@ int launch_sum_givens(ilh_ctx* c, const GivensJob& job) {
 // applied to the right-hand side g (g = beta e_1 at j = 0, beta in h[240]); the residual
 // estimate |g_{j+1}| and h_{j+1,j} go to h[352 + 2j], h[353 + 2j].
 // G layout: H [64][64] row-major (upper triangle after the rotations), cs [64], sn [64], g [65].
-__device__ void givens_update(double* h, double* G, int j, int m, const double* csl, const double* snl,
-                              const double* coll) {
+// givens_col: the same with h_{j+1,j} = hn given.
+__device__ void givens_col(double* h, double* G, int j, int m, const double* csl, const double* snl,
+                           const double* coll, double hn) {
   double* H = G;
   double* cs = G + 64 * 64;
   double* sn = cs + 64;
@@ -559,7 +611,6 @@ __device__ void givens_update(double* h, double* G, int j, int m, const double* 
     g[0] = h[240];
     for (int i = 1; i <= m; ++i) g[i] = 0.0;
   }
-  const double hn = sqrt(fmax(h[144], 0.0));
   double cur = coll[0];
   for (int i = 0; i < j; ++i) {
     const double nx = coll[i + 1];
@@ -575,6 +626,11 @@ __device__ void givens_update(double* h, double* G, int j, int m, const double* 
   g[j] = c_ * g[j];
   h[352 + 2 * j] = fabs(g[j + 1]);
   h[353 + 2 * j] = hn;
+}
+
+__device__ void givens_update(double* h, double* G, int j, int m, const double* csl, const double* snl,
+                              const double* coll) {
+  givens_col(h, G, j, m, csl, snl, coll, sqrt(fmax(h[144], 0.0)));
 }
 
 
@@ -597,6 +653,418 @@ int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
+
+// ------------------------------------------------------------------ Gram-Schmidt with the second
+// pass lagged one step (Sec. 3.5: the FGMRES solve of eq. newton_linear)
+// On entry to Arnoldi step j the basis slots hold v_0 .. v_{j-1} (orthonormal) and u_j, the
+// vector step j - 1 orthogonalised once against them and stored times s_j = 1 / |w_{j-1}|,
+// and z_j = P u_j.  With w = J z_j:
+//   dot sweep    a_k = v_k . u_j, b_k = v_k . w (k < j), |u_j|^2, u_j . w and |w|^2, in one pass
+//   final block  rho_j = (|u_j|^2 - |a|^2)^(1/2) and v_j = (u_j - V a) / rho_j (the second
+//                pass for u_j); u_j / s_j = (V a + rho_j v_j) / s_j, so column j - 1 of the
+//                Hessenberg matrix is step j - 1's first-pass coefficients plus (a, rho_j) / s_j,
+//                which the Givens update then takes; v_j . w = (u_j . w - a . b) / rho_j = d
+//   update sweep v_j stored, u_{j+1} = s_{j+1} (w - V b - d v_j) (the first pass for w) stored,
+//                and z_{j+1} = P u_{j+1} (the block preconditioner) with it
+// The scale s_{j+1} = 1 / |w| keeps the stored vectors and the next action's input of order one
+// (unscaled, the vectors grow by |J P| every step and leave the FP32 range).
+// The two Gram-Schmidt passes of every vector are those of classical Gram-Schmidt twice; the
+// second pass of u_j shares the sweeps of the first pass of w, so a step reads the basis twice.
+// v_0 = r / |r| is taken as it is stored (rho_0 = 1).  Column j - 1 is finished by step j, so
+// the residual estimate lags one step, and a cycle that ends at column L - 1 runs a closing
+// step L (dot sweep on u_L and the final block only).
+// Partial sums of the dot sweep: part[s][block], s = 2k (a_k), 2k + 1 (b_k), 2j (|u_j|^2),
+// 2j + 1 (u_j . w), 2j + 2 (|w|^2).
+static constexpr int LGS_NS = 2 * MDOT_JC + 3;
+static constexpr int LGS_NP = 32;  // LGS_NS padded to a power of two for wave_sums
+
+template <typename TV>
+__global__ void __launch_bounds__(TPB) k_lgs_dots(const TV* __restrict__ V, int64_t ldv, int j,
+                                                  const TV* __restrict__ uj, const TV* __restrict__ w,
+                                                  int64_t n, double* part, const double* skip) {
+  if (skip && *skip != 0.0) return;
+  __shared__ double sh[TPB / 64][LGS_NP];
+  const int64_t stride = (int64_t)gridDim.x * KTILE;
+  const int nch = j > 0 ? (j + MDOT_JC - 1) / MDOT_JC : 1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int k0 = ch * MDOT_JC;
+    double acc[LGS_NP];
+#pragma unroll
+    for (int q = 0; q < LGS_NP; ++q) acc[q] = 0.0;
+    for (int64_t t0 = (int64_t)blockIdx.x * KTILE; t0 < n; t0 += stride) {
+      int64_t ic[KU];
+      bool in[KU];
+      tile_index(t0, n, ic, in);
+      double uv[KU], wv[KU];
+      tile_load(uj, ic, in, uv);
+      tile_load(w, ic, in, wv);
+      if (ch == 0) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+          acc[2 * MDOT_JC] += uv[u] * uv[u];
+          acc[2 * MDOT_JC + 1] += uv[u] * wv[u];
+          acc[2 * MDOT_JC + 2] += wv[u] * wv[u];
+        }
+      }
+      if (j > 0) {
+        double v[MDOT_JC][KU];
+#pragma unroll
+        for (int jj = 0; jj < MDOT_JC; ++jj) {
+          const int k = min(k0 + jj, j - 1);
+#pragma unroll
+          for (int u = 0; u < KU; ++u) v[jj][u] = (double)V[(int64_t)k * ldv + ic[u]];
+        }
+#pragma unroll
+        for (int jj = 0; jj < MDOT_JC; ++jj)
+#pragma unroll
+          for (int u = 0; u < KU; ++u) {
+            acc[2 * jj] += v[jj][u] * uv[u];
+            acc[2 * jj + 1] += v[jj][u] * wv[u];
+          }
+      }
+    }
+    // every sum reduced across its wave, then across the block's waves in a fixed order
+    const int v = wave_sums<LGS_NP>(acc);
+    if ((lane & (64 / LGS_NP - 1)) == 0) sh[wid][v] = acc[0];
+    __syncthreads();
+    const int q = threadIdx.x;
+    if (q < LGS_NS) {
+      int sidx = -1;
+      if (q < 2 * MDOT_JC) {
+        if (k0 + q / 2 < j) sidx = 2 * (k0 + q / 2) + (q & 1);
+      } else if (ch == 0) {
+        sidx = 2 * j + (q - 2 * MDOT_JC);
+      }
+      if (sidx >= 0) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < TPB / 64; ++i) r += sh[i][q];
+        part[(int64_t)sidx * gridDim.x + blockIdx.x] = r;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Final block of step j (one work-group of LGS_FT threads): the sums, the second pass's scale, column j - 1 with its
+// Givens update and residual estimate (to h[352 + 2(j-1)]; to host memory with the cycle's tag at
+// hest[128 + j - 1] by the update sweep, or here on the closing step), the step-end flag h[HDEV_FLAG + j] (column j - 1 met the target or
+// rho_j = 0), and the update sweep's coefficients: a at h[0..j), b at h[72..72+j), 1 / rho_j at
+// h[144], d at h[145], s_{j+1} at h[146]; step j's first-pass coefficients (b, d) go to
+// h[HDEV_LGSP..+j] and 1 / s_{j+1} to h[HDEV_LGSP + 65] for step j + 1.  has_w = 0: the closing
+// step (no w, no update).
+static constexpr int LGS_FT = 1024;  // threads of the final block
+
+__global__ void __launch_bounds__(LGS_FT) k_lgs_final(const double* __restrict__ part, int np, int j, int m,
+                                                      int has_w, double* h, double* G, double* hest,
+                                                      const double* skip) {
+  if (skip && *skip != 0.0) return;
+  __shared__ double S[2 * 65 + 1];
+  __shared__ double csl[64], snl[64], coll[65], pl[66], sc[4];
+  const int ns = 2 * (j + 1) + (has_w ? 1 : 0);
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  constexpr int NW = LGS_FT / 64;
+  double* cs = G + 64 * 64;
+  double* g = cs + 128;
+  // every scalar the serial part needs is staged into LDS first, by other threads, so that its
+  // chain reads no global memory
+  if (t < j - 1) {
+    csl[t] = cs[t];
+    snl[t] = cs[64 + t];
+  } else if (t >= 128 && t < 128 + j) {
+    pl[t - 128] = h[HDEV_LGSP + t - 128];
+  } else if (t == 256) {
+    pl[65] = h[HDEV_LGSP + 65];
+  } else if (t == 257) {
+    sc[0] = j >= 1 ? g[j - 1] : 0.0;  // g_{j-1}, rotated by column j - 1
+  } else if (t == 258) {
+    sc[1] = h[240];
+  } else if (t == 259) {
+    sc[2] = h[252];
+  } else if (t == 260) {
+    sc[3] = h[255];
+  }
+  // the sums: wave w takes sums w, w + NW, ..., two at a time with their loads issued together
+  for (int s0 = wid; s0 < ns; s0 += 2 * NW) {
+    const int s1 = s0 + NW;
+    const bool two = s1 < ns;
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = lane; i < np; i += 64) {
+      const double x0 = part[(int64_t)s0 * np + i];
+      const double x1 = two ? part[(int64_t)s1 * np + i] : 0.0;
+      a0 += x0;
+      a1 += x1;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      a0 += __shfl_down(a0, o, 64);
+      a1 += __shfl_down(a1, o, 64);
+    }
+    if (lane == 0) {
+      S[s0] = a0;
+      if (two) S[s1] = a1;
+    }
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double aa = 0.0, ab = 0.0;
+  for (int k = 0; k < j; ++k) {
+    aa += S[2 * k] * S[2 * k];
+    ab += S[2 * k] * S[2 * k + 1];
+  }
+  double rho = 1.0, flag = 0.0;
+  if (j > 0) {
+    const double r2 = S[2 * j] - aa;
+    rho = (r2 == r2) ? sqrt(fmax(r2, 0.0)) : r2;
+    const double gs = pl[65];  // 1 / s_j
+    for (int k = 0; k < j; ++k) coll[k] = pl[k] + S[2 * k] * gs;
+    const double hn = rho * gs;
+    // Givens update of column jc = j - 1 (as givens_col, every operand from LDS)
+    const int jc = j - 1;
+    double* Hm = G;
+    double cur = coll[0];
+    for (int i = 0; i < jc; ++i) {
+      const double nx = coll[i + 1];
+      Hm[i * 64 + jc] = csl[i] * cur + snl[i] * nx;
+      cur = -snl[i] * cur + csl[i] * nx;
+    }
+    const double den = hypot(cur, hn);
+    const double c_ = den > 0 ? cur / den : 1.0, s_ = den > 0 ? hn / den : 0.0;
+    cs[jc] = c_;
+    cs[64 + jc] = s_;
+    Hm[jc * 64 + jc] = den;
+    const double gj = jc == 0 ? sc[1] : sc[0];
+    if (jc == 0)
+      for (int i = 2; i <= m; ++i) g[i] = 0.0;
+    g[jc] = c_ * gj;
+    g[jc + 1] = -s_ * gj;
+    const double est = fabs(s_ * gj);
+    h[352 + 2 * jc] = est;
+    h[353 + 2 * jc] = hn;
+    flag = (est <= sc[2] || hn == 0.0) ? 1.0 : 0.0;
+    if (hest && !has_w) {  // a full step's update sweep publishes it (first block)
+      hest[2 * jc] = est;
+      hest[2 * jc + 1] = hn;
+      __threadfence_system();  // the estimate reaches the host before the tag
+      hest[128 + jc] = sc[3];
+    }
+  }
+  h[HDEV_FLAG + j] = flag;
+  if (!has_w) return;
+  const double rinv = (rho > 0.0 && rho <= 1.7e308) ? 1.0 / rho : 0.0;
+  const double d = j > 0 ? (S[2 * j + 1] - ab) * rinv : S[1];
+  double* p = h + HDEV_LGSP;
+  for (int k = 0; k < j; ++k) {
+    h[k] = S[2 * k];
+    h[72 + k] = S[2 * k + 1];
+    p[k] = S[2 * k + 1];
+  }
+  p[j] = d;
+  const double wn = sqrt(fmax(S[2 * j + 2], 0.0));
+  const bool ok = wn > 0.0 && wn <= 1.7e308;
+  p[65] = ok ? wn : 1.0;
+  h[144] = j > 0 ? rinv : 1.0;
+  h[145] = d;
+  h[146] = ok ? 1.0 / wn : 1.0;
+}
+
+// A[r] = sum_{k < m} a_k V_k[rows[r]], B[r] likewise with b (FP64 sums of the stored basis)
+template <typename TV, int R>
+__device__ __forceinline__ void combo_ab(const TV* __restrict__ V, int64_t ldv, int m, const double* __restrict__ a,
+                                         const double* __restrict__ b, const int64_t (&rows)[R], double (&A)[R],
+                                         double (&B)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) A[r] = B[r] = 0.0;
+  for (int j0 = 0; j0 < m; j0 += MDOT_JC) {
+    double v[MDOT_JC][R], ca[MDOT_JC], cb[MDOT_JC];
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj) {
+      const bool ok = j0 + jj < m;
+      const int k = min(j0 + jj, m - 1);
+      ca[jj] = ok ? a[k] : 0.0;
+      cb[jj] = ok ? b[k] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[jj][r] = (double)V[(int64_t)k * ldv + rows[r]];
+    }
+#pragma unroll
+    for (int jj = 0; jj < MDOT_JC; ++jj)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        A[r] += ca[jj] * v[jj][r];
+        B[r] += cb[jj] * v[jj][r];
+      }
+  }
+}
+
+// one row of the update from its loaded u_j and w: v_j (stored back when j > 0) and u_{j+1}
+// (scaled by sg, stored over w); returns the stored u_{j+1}
+template <typename TV>
+__device__ __forceinline__ double lgs_row(TV* uj, TV* w, int64_t row, bool in, int j, double uv, double wv, double A,
+                                          double B, double rinv, double d, double sg) {
+  const TV vj = j > 0 ? (TV)((uv - A) * rinv) : (TV)uv;
+  const TV un = (TV)(sg * (wv - B - d * (double)vj));
+  if (in) {
+    if (j > 0) uj[row] = vj;
+    w[row] = un;
+  }
+  return (double)un;
+}
+
+static constexpr int LGS_NU = 2;  // node pairs (position row, velocity row) per thread
+
+// Update sweep of step j with the preconditioner of the next basis vector.  Block 0 hands the
+// residual estimate of column j - 1 (pub: j > 0), which the final block left in h, to host
+// memory with the cycle's tag; blocks [1, 1 + nbx) take the H1 rows by node pairs (i, nh1 + i);
+// the rest take whole elements' L2 rows (TPB / Nl elements per block), so z_{j+1} = P u_{j+1} is
+// formed in the same launch: z_v = u_v / dv, z_x = u_x + tau z_v (coupled) or u_x,
+// z_e = escale_e Me_e u_e (Me_e = me + e estride, Nl x Nl).  z (nullable): no preconditioned
+// vector (the next step is a closing step); z32 (nullable): its FP32 copy; zero_v (nullable): the
+// next Jacobian action's output, whose velocity rows are zeroed.  skip_step: the step's own flag
+// (the whole launch returns); skip_upd: end flag j (column j - 1 ended the cycle: only block 0
+// works).
+template <typename TV>
+__global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t ldv, int j,
+                                                    const double* __restrict__ h, int64_t nh1, int64_t Ne, int Nl,
+                                                    int nbx, TV* __restrict__ z, float* __restrict__ z32,
+                                                    TV* __restrict__ zero_v, const double* __restrict__ dv,
+                                                    const double* __restrict__ me, int64_t estride,
+                                                    const double* __restrict__ escale, int coupled,
+                                                    const double* __restrict__ tau_dev, int pub, double* hest,
+                                                    const double* skip_step, const double* skip_upd) {
+  if (skip_step && *skip_step != 0.0) return;
+  if (blockIdx.x == 0) {
+    // first in the grid, so that the fence runs beside the sweep instead of after it
+    if (pub && hest && threadIdx.x == 0) {
+      const int jc = j - 1;
+      hest[2 * jc] = h[352 + 2 * jc];
+      hest[2 * jc + 1] = h[353 + 2 * jc];
+      __threadfence_system();  // the estimate reaches the host before the tag
+      hest[128 + jc] = h[255];
+    }
+    return;
+  }
+  if (*skip_upd != 0.0) return;
+  const int b = (int)blockIdx.x - 1;
+  TV* uj = V + (int64_t)j * ldv;
+  TV* w = uj + ldv;
+  const double rinv = h[144], d = h[145], sg = h[146];
+  if (b < nbx) {
+    constexpr int R = 2 * LGS_NU;
+    int64_t rows[R];
+    bool in[LGS_NU];
+#pragma unroll
+    for (int q = 0; q < LGS_NU; ++q) {
+      const int64_t i = ((int64_t)b * LGS_NU + q) * TPB + threadIdx.x;
+      in[q] = i < nh1;
+      rows[2 * q] = in[q] ? i : 0;
+      rows[2 * q + 1] = nh1 + rows[2 * q];
+    }
+    // every load of the thread is issued before the first use
+    double uv[R], wv[R], dd[LGS_NU];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uv[r] = (double)uj[rows[r]];
+      wv[r] = (double)w[rows[r]];
+    }
+#pragma unroll
+    for (int q = 0; q < LGS_NU; ++q) dd[q] = z ? dv[rows[2 * q]] : 1.0;
+    double A[R], B[R];
+    combo_ab(V, ldv, j, h, h + 72, rows, A, B);
+    double un[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) un[r] = lgs_row(uj, w, rows[r], in[r / 2], j, uv[r], wv[r], A[r], B[r], rinv, d, sg);
+    if (z) {
+      const double tau = *tau_dev;
+#pragma unroll
+      for (int q = 0; q < LGS_NU; ++q) {
+        if (!in[q]) continue;
+        const int64_t i = rows[2 * q];
+        const double zv = un[2 * q + 1] / dd[q];
+        const double zx = coupled ? tau * zv + un[2 * q] : un[2 * q];
+        z[i] = (TV)zx;
+        z[nh1 + i] = (TV)zv;
+        if (z32) {
+          z32[i] = (float)zx;
+          z32[nh1 + i] = (float)zv;
+        }
+        if (zero_v) zero_v[nh1 + i] = TV(0);
+      }
+    }
+  } else {
+    __shared__ double shu[TPB];
+    const int epb = TPB / Nl;
+    const int t = threadIdx.x, le = t / Nl, rr = t - le * Nl;
+    const int64_t e = (int64_t)(b - nbx) * epb + le;
+    const bool in = le < epb && e < Ne;
+    const int64_t ec = in ? e : 0;
+    const int64_t rows[1] = {2 * nh1 + ec * Nl + (in ? rr : 0)};
+    const double uv = (double)uj[rows[0]], wv = (double)w[rows[0]];
+    const double es = (z && escale) ? escale[ec] : 1.0;
+    double A[1], B[1];
+    combo_ab(V, ldv, j, h, h + 72, rows, A, B);
+    const double un = lgs_row(uj, w, rows[0], in, j, uv, wv, A[0], B[0], rinv, d, sg);
+    if (z) {
+      shu[t] = un;
+      __syncthreads();
+      if (in) {
+        const double* M = me + e * estride + (int64_t)rr * Nl;
+        const double* ue = shu + le * Nl;
+        double acc = 0.0;
+        for (int l = 0; l < Nl; ++l) acc += M[l] * ue[l];
+        acc *= es;
+        z[rows[0]] = (TV)acc;
+        if (z32) z32[rows[0]] = (float)acc;
+      }
+    }
+  }
+}
+
+template <typename TV>
+int lgs_dots(ilh_ctx* c, const TV* V, int64_t ldv, int j, const TV* uj, const TV* w, int64_t n, double* part,
+             int* np, const double* skip) {
+  if (j > 64) return fail(c, ILH_EINVAL, "Gram-Schmidt: at most 64 basis vectors");
+  const int nb = fused_blocks(n);
+  // the closing step has no w: its products are taken with u_j instead and not used
+  hipLaunchKernelGGL(k_lgs_dots<TV>, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, j, uj, w ? w : uj, n, part, skip);
+  ILH_HIP(c, hipGetLastError());
+  *np = nb;
+  return ILH_OK;
+}
+
+int lgs_final(ilh_ctx* c, const double* part, int np, int j, int m, int has_w, double* h, double* G, double* hest,
+              const double* skip) {
+  hipLaunchKernelGGL(k_lgs_final, dim3(1), dim3(LGS_FT), 0, c->stream, part, np, j, m, has_w, h, G, hest, skip);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+template <typename TV>
+int lgs_update(ilh_ctx* c, TV* V, int64_t ldv, int j, const double* h, TV* z, float* z32, TV* zero_v, int probe,
+               int coupled, const double* tau_dev, double* hest, const double* skip_step, const double* skip_upd) {
+  if (c->Nl > TPB) return fail(c, ILH_EINVAL, "Gram-Schmidt update: energy blocks larger than a work-group");
+  const int64_t units = (int64_t)TPB * LGS_NU;
+  const int nbx = (int)((c->nh1 + units - 1) / units);
+  const int epb = TPB / c->Nl;
+  const int nbe = (int)((c->Ne + epb - 1) / epb);
+  const double* dv = probe ? c->pdv : c->Mdiag;
+  const double* me = probe ? c->peinv : c->MEinv;
+  const int64_t estride = probe ? (int64_t)c->Nl * c->Nl : c->me_stride;
+  const double* escale = probe ? nullptr : c->me_scale;
+  hipLaunchKernelGGL(k_lgs_update<TV>, dim3(1 + nbx + nbe), dim3(TPB), 0, c->stream, V, ldv, j, h, c->nh1, c->Ne,
+                     c->Nl, nbx, z, z32, zero_v, dv, me, estride, escale, coupled, tau_dev, j > 0 ? 1 : 0, hest,
+                     skip_step, skip_upd);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+template int lgs_dots<double>(ilh_ctx*, const double*, int64_t, int, const double*, const double*, int64_t, double*,
+                              int*, const double*);
+template int lgs_dots<float>(ilh_ctx*, const float*, int64_t, int, const float*, const float*, int64_t, double*,
+                             int*, const double*);
+template int lgs_update<double>(ilh_ctx*, double*, int64_t, int, const double*, double*, float*, double*, int, int,
+                                const double*, double*, const double*, const double*);
+template int lgs_update<float>(ilh_ctx*, float*, int64_t, int, const double*, float*, float*, float*, int, int,
+                               const double*, double*, const double*, const double*);
 
 // Block preconditioner of the Newton-Krylov solve (eq. blockdiag_prec with a Jacobi M_V):
 // z_v = r_v / diag(M_V) (1 on constrained rows), z_x = r_x + tau z_v (coupled) or r_x,

@@ -92,36 +92,41 @@ def test_line_search_tangling_decision_matches_oracle():
     assert st["newton"] == 1 and st["halvings"] >= 1
 
 
-def test_speculative_arnoldi_step_does_no_counted_work():
-    """The host enqueues Arnoldi step j before it reads step j-1's residual estimate; the step
-    after the one that ends a solve reads that step's end flag on the device and returns at once.
-    With cycles that never restart, the Jacobian actions counted are then exactly the GMRES
-    iterations, and the trajectory still matches the oracle's."""
+@pytest.mark.parametrize("cgs2", [1, 0])
+def test_speculative_arnoldi_step_does_no_counted_work(cgs2):
+    """The host enqueues an Arnoldi step before it reads the residual estimate of the column before;
+    the step after the one that ends a solve reads that step's end flag on the device and returns
+    at once.  With cycles that never restart, the Jacobian actions counted are then exactly the
+    GMRES iterations with both passes in the step (cgs2 = 1), and one more per solve with the
+    second pass lagged (the step that finishes the last column applies J to the next vector), and
+    the trajectory still matches the oracle's."""
     from oracle import krylov
     O, G = make_pair("tg2d", (8, 8), 2)
     u0 = O.init_state()
     states, _, _ = krylov.run_midpoint(O, u0, 0.01, 3)
     u = to_dev(u0)
     hist = []
-    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, restart=64)
+    opts = ilh.newton_options(tol=1e-10, jvp_prec=32, restart=64, cgs2=cgs2)
     for n in range(3):
         g = G.plain_guess(u, hist)
         k, st = G.implicit_step(u, 0.01, guess=g, opts=opts)
         assert st["status"] == 0
-        assert st["jvp_calls"] == st["gmres"], st
+        assert st["jvp_calls"] == st["gmres"] + (0 if cgs2 else st["newton"]), st
         hist = (hist + [k])[-2:]
         assert rel(to_np(u), states[n + 1]) <= 1e-8
 
 
-def test_iteration_limit_enqueues_no_extra_step():
+@pytest.mark.parametrize("cgs2", [1, 0])
+def test_iteration_limit_enqueues_no_extra_step(cgs2):
     """When the iteration limit (not convergence) ends every FGMRES solve, the host knows in advance
-    which step is the last one and enqueues none after it: the Jacobian actions counted equal the
-    GMRES iterations (restart 64: no restart actions), for both precisions of the action."""
+    which step is the last one and enqueues none after it (with the second pass lagged, a closing
+    step that finishes the last column without a Jacobian action): the Jacobian actions counted
+    equal the GMRES iterations (restart 64: no restart actions), for both precisions of the action."""
     O, G = make_pair("tg2d", (8, 8), 2)
     u = to_dev(O.init_state())
     for prec in (32, 64):
         opts = ilh.newton_options(tol=1e-10, jvp_prec=prec, restart=64, gmres_maxit=3, gmres_rtol=1e-14,
-                                  max_newton=8)
+                                  max_newton=8, cgs2=cgs2)
         k, st = G.implicit_step(u.clone(), 0.01, opts=opts, raise_on_fail=False)
         assert st["newton"] >= 2
         assert st["gmres"] >= 6 and st["gmres"] % 3 == 0, st
