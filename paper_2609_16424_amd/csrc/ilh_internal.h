@@ -254,8 +254,11 @@ int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_o
 // every kernel of step j + 1 then returns at once
 constexpr int HDEV_FLAG = 640;
 // [704, 769): the first-pass coefficients of the previous Arnoldi step, 769 the inverse scale of
-// the stored once-orthogonalised vector (Gram-Schmidt with the second pass lagged one step)
+// the stored once-orthogonalised vector, 770 the cycle-end flag (0 while the cycle runs, s + 1
+// once the final block of step s found the end) (Gram-Schmidt with the second pass lagged one
+// step)
 constexpr int HDEV_LGSP = 704;
+constexpr int HDEV_LGSE = 770;
 constexpr int HDEV_LEN = 776;
 // y = H(0:n, 0:n)^-1 g
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
@@ -324,7 +327,7 @@ int lgs_final(ilh_ctx* c, const double* part, int np, int j, int m, int has_w, d
               const double* skip);
 template <typename TV>
 int lgs_update(ilh_ctx* c, TV* V, int64_t ldv, int j, const double* h, TV* z, float* z32, TV* zero_v, int probe,
-               int coupled, const double* tau_dev, double* hest, const double* skip_step, const double* skip_upd);
+               int coupled, const double* tau_dev, double* hest, const double* end);
 // (skip nullable: the kernel returns at once when *skip is nonzero)
 int launch_jvp2d_q_f32to64(ilh_ctx* c, const float* dk, double* out, const double* tau_dev,
                            const double* skip = nullptr);

@@ -1128,6 +1128,7 @@ __global__ void k_scale_copy(TV* y, const double* x, double beta, int64_t n, dou
     h[252] = target;
     h[255] = tag;
     h[256] = 1.0;
+    h[HDEV_LGSE] = 0.0;
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (TV)(x[i] * f);
@@ -1361,14 +1362,14 @@ struct Solver {
   // formed from u_j by step j - 1 or the cycle start) into slot j + 1, runs the dot sweep, the
   // final block and the update sweep (v_j, u_{j+1} and, when step j + 1 is a full step, z_{j+1});
   // j == L is the closing step (dot sweep on u_L and the final block).  The final block of step
-  // j finishes column j - 1, stores its residual estimate and sets end flag j; every launch of
-  // step j reads end flag j - 1, the update sweep end flag j.
+  // j finishes column j - 1 and stores its residual estimate; when the cycle ends there it sets
+  // the cycle-end flag, and every launch enqueued after it returns at once.
   int lag_step(int j, int m, int L) {
     const int64_t n = c->nblock;
     TV* V = basis();
     TV* Z = V + (int64_t)(m + 1) * n;
     double* hd = c->hdev;
-    const double* skip = j > 0 ? hd + HDEV_FLAG + j - 1 : nullptr;
+    const double* skip = hd + HDEV_LGSE;
     const bool full = j < L;
     TV* w = full ? V + (int64_t)(j + 1) * n : nullptr;
     int st;
@@ -1383,7 +1384,7 @@ struct Solver {
       TV* out = (next && direct64()) ? V + (int64_t)(j + 2) * n : nullptr;
       float* z32 = (next && o->jvp_prec == 32 && !F32) ? c->kry32 : nullptr;
       if ((st = lgs_update<TV>(c, V, n, j, hd, zn, z32, out, o->prec_probe, o->prec_coupled, hd + 250, c->hest_dev,
-                               skip, hd + HDEV_FLAG + j)))
+                               hd + HDEV_LGSE)))
         return st;
       z32_of = z32 ? zn : nullptr;
       zeroed_v = out;
@@ -1528,31 +1529,52 @@ struct Solver {
       };
       bool end = false;
       if (lagged()) {
-        // columns this cycle may finish; step j finishes column j - 1, so the host reads column
-        // j - 2 after enqueuing step j (one step ahead), and the closing step L finishes the last
+        // columns this cycle may finish; step j finishes column j - 1 (its update sweep hands the
+        // estimate to the host), and the closing step L finishes the last.  The host keeps
+        // `ahead` steps enqueued beyond the one whose estimate it waits for, so that the stream
+        // has work while it reads; the steps after the one that ends the cycle return at once
+        // (two with the direct FP32 action, which reads the flag; else one, whose action runs).
+        const int ahead = direct64() ? 2 : 1;
         const int L = std::max(1, std::min(m, o->gmres_maxit - total));
-        for (int j = 0; j <= L && !end; ++j) {
-          if (use_graph && j < L) {
-            hipGraphExec_t ex;
-            if ((st = graph_for(j, m, L, &ex))) return st;
-            ILH_HIP(c, hipGraphLaunch(ex, c->stream));
-            ++jvp_calls;
-            skippable = j > 0;
-            skip_slot = -1;
-          } else if ((st = lag_step(j, m, L))) {
-            return st;
-          }
-          if (j >= 2) {
-            if ((st = check(j - 2, end))) return st;
-            if (end) {
-              j_end = j - 1;  // step j was speculative
-              if (dev_end && j < L) drop_skipped();  // and its launches returned at once
+        struct Rec {
+          bool sk;  // the step's action returns at once once the flag is set
+          int slot;
+          int64_t gen;
+        };
+        Rec rec[65];
+        int next = 0;  // next step to enqueue
+        int col = 0;   // next column to read
+        while (true) {
+          while (next <= L && next <= col + 1 + ahead) {
+            if (use_graph && next < L) {
+              hipGraphExec_t ex;
+              if ((st = graph_for(next, m, L, &ex))) return st;
+              ILH_HIP(c, hipGraphLaunch(ex, c->stream));
+              ++jvp_calls;
+              rec[next] = Rec{true, -1, -1};
+            } else {
+              if ((st = lag_step(next, m, L))) return st;
+              rec[next] = Rec{skippable, skip_slot, skip_gen};
             }
+            ++next;
           }
-        }
-        if (!end) {
-          if ((st = check(L - 1, end))) return st;
-          j_end = L;
+          if ((st = check(col, end))) return st;
+          ++col;
+          if (end) {
+            // step col's final block ended the cycle at column col - 1; the full steps enqueued
+            // after it returned at once (a host-only end, at the iteration limit, is column L - 1)
+            for (int s2 = col + 1; s2 < next; ++s2)
+              if (s2 < L && rec[s2].sk) {
+                --jvp_calls;
+                tdrop(c, rec[s2].slot, rec[s2].gen);
+              }
+            j_end = col;
+            break;
+          }
+          if (col == L) {
+            j_end = L;
+            break;
+          }
         }
       }
       for (int j = 0; j < m && !end && !lagged(); ++j) {

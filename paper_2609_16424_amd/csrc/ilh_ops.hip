@@ -747,10 +747,11 @@ __global__ void __launch_bounds__(TPB) k_lgs_dots(const TV* __restrict__ V, int6
   }
 }
 
-// Final block of step j (one work-group of LGS_FT threads): the sums, the second pass's scale, column j - 1 with its
-// Givens update and residual estimate (to h[352 + 2(j-1)]; to host memory with the cycle's tag at
-// hest[128 + j - 1] by the update sweep, or here on the closing step), the step-end flag h[HDEV_FLAG + j] (column j - 1 met the target or
-// rho_j = 0), and the update sweep's coefficients: a at h[0..j), b at h[72..72+j), 1 / rho_j at
+// Final block of step j (one work-group of LGS_FT threads): the sums, the second pass's scale,
+// column j - 1 with its Givens update and residual estimate (to h[352 + 2(j-1)]; to host memory
+// with the cycle's tag at hest[128 + j - 1] by the update sweep, or here on the closing step), the
+// cycle-end flag h[HDEV_LGSE] = j + 1 when column j - 1 met the target or rho_j = 0 (every later
+// launch of the cycle then returns at once), and the update sweep's coefficients: a at h[0..j), b at h[72..72+j), 1 / rho_j at
 // h[144], d at h[145], s_{j+1} at h[146]; step j's first-pass coefficients (b, d) go to
 // h[HDEV_LGSP..+j] and 1 / s_{j+1} to h[HDEV_LGSP + 65] for step j + 1.  has_w = 0: the closing
 // step (no w, no update).
@@ -849,7 +850,7 @@ __global__ void __launch_bounds__(LGS_FT) k_lgs_final(const double* __restrict__
       hest[128 + jc] = sc[3];
     }
   }
-  h[HDEV_FLAG + j] = flag;
+  if (flag != 0.0) h[HDEV_LGSE] = j + 1;
   if (!has_w) return;
   const double rinv = (rho > 0.0 && rho <= 1.7e308) ? 1.0 / rho : 0.0;
   const double d = j > 0 ? (S[2 * j + 1] - ab) * rinv : S[1];
@@ -919,9 +920,9 @@ static constexpr int LGS_NU = 2;  // node pairs (position row, velocity row) per
 // formed in the same launch: z_v = u_v / dv, z_x = u_x + tau z_v (coupled) or u_x,
 // z_e = escale_e Me_e u_e (Me_e = me + e estride, Nl x Nl).  z (nullable): no preconditioned
 // vector (the next step is a closing step); z32 (nullable): its FP32 copy; zero_v (nullable): the
-// next Jacobian action's output, whose velocity rows are zeroed.  skip_step: the step's own flag
-// (the whole launch returns); skip_upd: end flag j (column j - 1 ended the cycle: only block 0
-// works).
+// next Jacobian action's output, whose velocity rows are zeroed.  end: the cycle-end flag; the
+// launch returns at once when an earlier step ended the cycle, and only block 0 works when this
+// step's final block ended it (end = j + 1).
 template <typename TV>
 __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t ldv, int j,
                                                     const double* __restrict__ h, int64_t nh1, int64_t Ne, int Nl,
@@ -930,8 +931,9 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
                                                     const double* __restrict__ me, int64_t estride,
                                                     const double* __restrict__ escale, int coupled,
                                                     const double* __restrict__ tau_dev, int pub, double* hest,
-                                                    const double* skip_step, const double* skip_upd) {
-  if (skip_step && *skip_step != 0.0) return;
+                                                    const double* end) {
+  const double ended = *end;
+  if (ended != 0.0 && ended != (double)(j + 1)) return;
   if (blockIdx.x == 0) {
     // first in the grid, so that the fence runs beside the sweep instead of after it
     if (pub && hest && threadIdx.x == 0) {
@@ -943,7 +945,7 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
     }
     return;
   }
-  if (*skip_upd != 0.0) return;
+  if (ended != 0.0) return;
   const int b = (int)blockIdx.x - 1;
   TV* uj = V + (int64_t)j * ldv;
   TV* w = uj + ldv;
@@ -1040,7 +1042,7 @@ int lgs_final(ilh_ctx* c, const double* part, int np, int j, int m, int has_w, d
 
 template <typename TV>
 int lgs_update(ilh_ctx* c, TV* V, int64_t ldv, int j, const double* h, TV* z, float* z32, TV* zero_v, int probe,
-               int coupled, const double* tau_dev, double* hest, const double* skip_step, const double* skip_upd) {
+               int coupled, const double* tau_dev, double* hest, const double* end) {
   if (c->Nl > TPB) return fail(c, ILH_EINVAL, "Gram-Schmidt update: energy blocks larger than a work-group");
   const int64_t units = (int64_t)TPB * LGS_NU;
   const int nbx = (int)((c->nh1 + units - 1) / units);
@@ -1052,7 +1054,7 @@ int lgs_update(ilh_ctx* c, TV* V, int64_t ldv, int j, const double* h, TV* z, fl
   const double* escale = probe ? nullptr : c->me_scale;
   hipLaunchKernelGGL(k_lgs_update<TV>, dim3(1 + nbx + nbe), dim3(TPB), 0, c->stream, V, ldv, j, h, c->nh1, c->Ne,
                      c->Nl, nbx, z, z32, zero_v, dv, me, estride, escale, coupled, tau_dev, j > 0 ? 1 : 0, hest,
-                     skip_step, skip_upd);
+                     end);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -1062,9 +1064,9 @@ template int lgs_dots<double>(ilh_ctx*, const double*, int64_t, int, const doubl
 template int lgs_dots<float>(ilh_ctx*, const float*, int64_t, int, const float*, const float*, int64_t, double*,
                              int*, const double*);
 template int lgs_update<double>(ilh_ctx*, double*, int64_t, int, const double*, double*, float*, double*, int, int,
-                                const double*, double*, const double*, const double*);
+                                const double*, double*, const double*);
 template int lgs_update<float>(ilh_ctx*, float*, int64_t, int, const double*, float*, float*, float*, int, int,
-                               const double*, double*, const double*, const double*);
+                               const double*, double*, const double*);
 
 // Block preconditioner of the Newton-Krylov solve (eq. blockdiag_prec with a Jacobi M_V):
 // z_v = r_v / diag(M_V) (1 on constrained rows), z_x = r_x + tau z_v (coupled) or r_x,
