@@ -86,6 +86,7 @@ SIGNATURES = {
     "ilh_sdirk_step": (I, [P, P, D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_probe_blocks": (I, [P, I, P, P]),
     "ilh_guess_infer": (I, [P, C.POINTER(GuessModel), P, P, D, P, C.POINTER(I)]),
+    "ilh_guess_mlp_fused": (I, [P, C.POINTER(GuessModel), P, P, P, I]),
     "ilh_adaptive_step": (I, [P, P, C.POINTER(D), D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats), I,
                               C.POINTER(I), C.POINTER(D)]),
     "ilh_timing_enable": (I, [P, I]),

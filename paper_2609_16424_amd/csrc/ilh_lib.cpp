@@ -1958,16 +1958,27 @@ int ilh_guess_infer(ilh_ctx* c, const ilh_guess_model* m, const double* u, const
     c->gscr_len = need;
   }
   if (!c->gres && (st = dalloc(c, &c->gres, (size_t)c->nblock))) return st;
-  // the features are written for all p0 columns; zero them once so padding stays zero
   float* feat = c->gscr;
   float* zs = feat + ne * p0;
   float* acts = zs + tot;
-  ILH_HIP(c, hipMemsetAsync(feat, 0, ne * p0 * sizeof(float), c->stream));
-  if ((st = ilh_guess_features(c, u, m->with_base ? base : nullptr, m->vscale, m->escale, m->xscale, m->kvscale,
-                               m->kescale, m->mu, m->sd, feat, p0)))
-    return st;
-  if ((st = ilh_mlp_forward(c, m->nl, m->widths, m->W, m->b, feat, (int)ne, zs, acts))) return st;
-  const float* out = acts + tot - ne * pl;
+  float* out = acts + tot - ne * pl;
+  // one launch (features and every layer, weights in LDS) where the model fits, else the
+  // features and the layer-by-layer forward
+  const int ND = (c->k + 1) * (c->k + 1), NLd = c->k * c->k;
+  const bool widths_ok = m->widths[0] == 2 * ND + NLd + 8 + (m->with_base ? 2 * ND + NLd : 0) &&
+                         m->widths[m->nl] == 2 * ND + NLd;
+  int64_t lds = 0;
+  for (int l = 0; l < m->nl; ++l) lds += (int64_t)pad(m->widths[l + 1]) * (pad(m->widths[l]) + 8);
+  const bool fused = widths_ok && lds <= 57344 && (reinterpret_cast<uintptr_t>(m->W) & 15) == 0;
+  if (fused) {
+    if ((st = ilh_guess_mlp_fused(c, m, u, base, out, pl))) return st;
+  } else {
+    // the features are written for all p0 columns (padding zero)
+    if ((st = ilh_guess_features(c, u, m->with_base ? base : nullptr, m->vscale, m->escale, m->xscale, m->kvscale,
+                                 m->kescale, m->mu, m->sd, feat, p0)))
+      return st;
+    if ((st = ilh_mlp_forward(c, m->nl, m->widths, m->W, m->b, feat, (int)ne, zs, acts))) return st;
+  }
   if ((st = ilh_guess_assemble(c, out, pl, m->kvscale, m->kescale, m->osc, base, u, tau, k))) return st;
   // judge: residual norms of the learned and the plain iterate
   if ((st = ilh_residual(c, k, u, tau, c->gres))) return st;

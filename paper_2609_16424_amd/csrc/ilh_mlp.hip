@@ -215,41 +215,144 @@ __global__ void k_sum_part(const double* part, int np, double* out) {
 // Learned-guess features and targets (2D).  Per element e with local H1 node (a, b) and
 // L2 dof j:  features = [v_c(a,b)/vs (c = 0, 1) | e_j/es | corner_c - centre_c)/xs (4 corners)
 //                        | optionally base_v/kvs | base_e/kes],  row stride ld, zero padded.
-__global__ void k_features(const KParams P, const double* u, const double* base, double vs, double es, double xs,
-                           double kvs, double kes, const float* mu, const float* sd, float* feat, int ld) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.y + threadIdx.y;
-  if (e >= P.Ne) return;
+struct FeatArgs {
+  const double* u;
+  const double* base;  // nullable: no base block
+  double vs, es, xs, kvs, kes;
+  const float* mu;  // nullable: no normalisation
+  const float* sd;
+};
+
+// feature i of element e (0 past the feature count)
+__device__ __forceinline__ float feature_value(const KParams& P, const FeatArgs& A, int64_t e, int i) {
   const int k = P.k, D1D = k + 1, ND = D1D * D1D, NL = k * k;
   const int ex = (int)(e % P.n[0]), ey = (int)(e / P.n[0]);
   const int64_t N = P.N, nh1 = 2 * N, ng0 = P.ng[0];
-  float* f = feat + e * ld;
-  const int nbase = base ? 2 * ND + NL : 0;
+  const double* u = A.u;
+  const int nbase = A.base ? 2 * ND + NL : 0;
   const int nin = 2 * ND + NL + 8 + nbase;
-  for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-    double val = 0.0;
-    if (i < 2 * ND) {
-      const int c = i / ND, li = i % ND, a = li % D1D, b = li / D1D;
-      val = u[nh1 + c * N + (int64_t)(k * ey + b) * ng0 + k * ex + a] / vs;
-    } else if (i < 2 * ND + NL) {
-      val = u[2 * nh1 + e * NL + (i - 2 * ND)] / es;
-    } else if (i < 2 * ND + NL + 8) {
-      const int j = i - 2 * ND - NL, corner = j / 2, c = j % 2;
-      const int a = (corner & 1) ? k : 0, b = (corner & 2) ? k : 0;
-      double cen = 0;
-      for (int q = 0; q < 4; ++q)
-        cen += u[c * N + (int64_t)(k * ey + ((q & 2) ? k : 0)) * ng0 + k * ex + ((q & 1) ? k : 0)];
-      val = (u[c * N + (int64_t)(k * ey + b) * ng0 + k * ex + a] - 0.25 * cen) / xs;
-    } else if (i < nin) {
-      const int j = i - 2 * ND - NL - 8;
-      if (j < 2 * ND) {
-        const int c = j / ND, li = j % ND, a = li % D1D, b = li / D1D;
-        val = base[nh1 + c * N + (int64_t)(k * ey + b) * ng0 + k * ex + a] / kvs;
-      } else {
-        val = base[2 * nh1 + e * NL + (j - 2 * ND)] / kes;
+  double val = 0.0;
+  if (i < 2 * ND) {
+    const int c = i / ND, li = i % ND, a = li % D1D, b = li / D1D;
+    val = u[nh1 + c * N + (int64_t)(k * ey + b) * ng0 + k * ex + a] / A.vs;
+  } else if (i < 2 * ND + NL) {
+    val = u[2 * nh1 + e * NL + (i - 2 * ND)] / A.es;
+  } else if (i < 2 * ND + NL + 8) {
+    const int j = i - 2 * ND - NL, corner = j / 2, c = j % 2;
+    const int a = (corner & 1) ? k : 0, b = (corner & 2) ? k : 0;
+    double cen = 0;
+    for (int q = 0; q < 4; ++q)
+      cen += u[c * N + (int64_t)(k * ey + ((q & 2) ? k : 0)) * ng0 + k * ex + ((q & 1) ? k : 0)];
+    val = (u[c * N + (int64_t)(k * ey + b) * ng0 + k * ex + a] - 0.25 * cen) / A.xs;
+  } else if (i < nin) {
+    const int j = i - 2 * ND - NL - 8;
+    if (j < 2 * ND) {
+      const int c = j / ND, li = j % ND, a = li % D1D, b = li / D1D;
+      val = A.base[nh1 + c * N + (int64_t)(k * ey + b) * ng0 + k * ex + a] / A.kvs;
+    } else {
+      val = A.base[2 * nh1 + e * NL + (j - 2 * ND)] / A.kes;
+    }
+  }
+  if (A.mu && i < nin) val = (val - (double)A.mu[i]) / (double)A.sd[i];
+  return (float)val;
+}
+
+__global__ void k_features(const KParams P, const FeatArgs A, float* feat, int ld) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.y + threadIdx.y;
+  if (e >= P.Ne) return;
+  float* f = feat + e * ld;
+  for (int i = threadIdx.x; i < ld; i += blockDim.x) f[i] = feature_value(P, A, e, i);
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused inference: the features of 64 elements per tile, every layer and the store of the
+// network output in one launch.  Each work-group first copies all weights (BF16) and biases
+// into LDS, once, and then walks element tiles (4 waves x 16 rows); activations pass from layer
+// to layer through a per-wave LDS tile in the MFMA operand layout.  The operand rounding (BF16),
+// the accumulation order and the epilogue are those of k_dense_fwd, so the output is the layered
+// forward's.  Weight rows are padded by 8 BF16 (16 bytes) in LDS, so the 16 lanes of a quarter
+// wave read 16 different rows from 16 different bank groups.
+constexpr int FZ_MAXL = 8;
+constexpr int FZ_WLDS = 57344;  // BF16 weight elements in LDS (padded rows): 112 KiB
+constexpr int FZ_BLDS = FZ_MAXL * 128;
+constexpr int FZ_ALD = 128 + 8;  // activation tile row (BF16, padded)
+
+struct FusedNet {
+  int nl;
+  int kp[FZ_MAXL], np[FZ_MAXL];  // padded widths of each layer
+  int wg[FZ_MAXL];                // offset of layer l in the global W (KP x NP blocks)
+  int ws[FZ_MAXL];                // offset of layer l in the LDS copy (rows of KP + 8)
+  int bo[FZ_MAXL];                // offset of layer l's bias
+};
+
+__global__ void __launch_bounds__(256) k_guess_fused(const KParams P, const FeatArgs FA, const FusedNet F,
+                                                     const uint16_t* __restrict__ W, const float* __restrict__ bias,
+                                                     float* __restrict__ pred, int ld_out) {
+  __shared__ __attribute__((aligned(16))) uint16_t sW[FZ_WLDS];
+  __shared__ float sB[FZ_BLDS];
+  __shared__ __attribute__((aligned(16))) uint16_t sA[4][16][FZ_ALD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // weights: 8 BF16 (16 bytes) per copy, rows of KP to rows of KP + 8
+  for (int l = 0; l < F.nl; ++l) {
+    const int KP = F.kp[l], NP = F.np[l], KC = KP / 8;
+    for (int i = tid; i < NP * KC; i += 256) {
+      const int n = i / KC, kc = i - n * KC;
+      const uint4 v = *reinterpret_cast<const uint4*>(W + F.wg[l] + n * KP + kc * 8);
+      *reinterpret_cast<uint4*>(sW + F.ws[l] + n * (KP + 8) + kc * 8) = v;
+    }
+    for (int i = tid; i < NP; i += 256) sB[F.bo[l] + i] = bias[F.bo[l] + i];
+  }
+  __syncthreads();
+  const int64_t ntiles = (P.Ne + 63) / 64;
+  const int kb = (lane >> 4) * 8;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * 64 + wave * 16;
+    const int64_t r = row0 + (lane & 15);
+    // layer 0 operand: the features of the lane's row
+    bf16x8 af[4];
+    const int KP0 = F.kp[0];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s < KP0 / 32) {
+        float v[8];
+        for (int j = 0; j < 8; ++j) v[j] = (r < P.Ne) ? feature_value(P, FA, r, s * 32 + kb + j) : 0.0f;
+        af[s] = pack8(v);
       }
     }
-    if (mu && i < nin) val = (val - (double)mu[i]) / (double)sd[i];
-    f[i] = (float)val;
+    for (int l = 0; l < F.nl; ++l) {
+      const int KP = F.kp[l], NP = F.np[l];
+      const bool last = l == F.nl - 1;
+      const uint16_t* Wl = sW + F.ws[l];
+      for (int t = 0; t < NP / 16; ++t) {
+        const int n = t * 16 + (lane & 15);
+        f32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          if (s < KP / 32) {
+            const bf16x8 bf = *reinterpret_cast<const bf16x8*>(Wl + n * (KP + 8) + s * 32 + kb);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bf, acc, 0, 0, 0);
+          }
+        }
+        const float bn = sB[F.bo[l] + n];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rl = (lane >> 4) * 4 + j;
+          const float z = acc[j] + bn;
+          if (last) {
+            const int64_t rr = row0 + rl;
+            if (rr < P.Ne && n < ld_out) pred[rr * ld_out + n] = z;
+          } else {
+            sA[wave][rl][n] = f2bf(gelu(z));
+          }
+        }
+      }
+      if (last) break;
+      __syncthreads();  // the wave's activation tile is complete
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (s < NP / 32) af[s] = *reinterpret_cast<const bf16x8*>(&sA[wave][lane & 15][s * 32 + kb]);
+      __syncthreads();  // read before the next layer overwrites it
+    }
   }
 }
 
@@ -372,8 +475,8 @@ int ilh_guess_features(ilh_ctx* c, const double* u, const double* base, double v
   const int nin = 2 * ND + NL + 8 + (base ? 2 * ND + NL : 0);
   if (ld < nin) return fail(c, ILH_EINVAL, "feature row stride too small");
   if (!(vs > 0 && es > 0 && xs > 0 && kvs > 0 && kes > 0)) return fail(c, ILH_EINVAL, "scales must be > 0");
-  hipLaunchKernelGGL(k_features, dim3((unsigned)((c->Ne + 3) / 4)), dim3(64, 4), 0, c->stream, c->kp, u, base, vs, es,
-                     xs, kvs, kes, mu, sd, feat, ld);
+  const FeatArgs fa{u, base, vs, es, xs, kvs, kes, mu, sd};
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((c->Ne + 3) / 4)), dim3(64, 4), 0, c->stream, c->kp, fa, feat, ld);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
   ILH_CATCH(c)
@@ -431,6 +534,44 @@ int ilh_mlp_forward(ilh_ctx* c, int nl, const int* widths, const uint16_t* W, co
     bo += NP;
     ao += (int64_t)batch * NP;
   }
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+  ILH_CATCH(c)
+}
+
+int ilh_guess_mlp_fused(ilh_ctx* c, const ilh_guess_model* m, const double* u, const double* base, float* pred,
+                        int ld) {
+  ILH_TRY
+  if (!c || !m || !u || !pred || !m->W || !m->b || c->dim != 2) return fail(c, ILH_EINVAL, "fused guess MLP: 2D, non-null");
+  int st = check_widths(c, m->nl, m->widths);
+  if (st) return st;
+  if (m->nl > FZ_MAXL) return fail(c, ILH_EINVAL, "fused guess MLP: at most 8 layers");
+  const int ND = (c->k + 1) * (c->k + 1), NL = c->k * c->k;
+  const int nin = 2 * ND + NL + 8 + (m->with_base ? 2 * ND + NL : 0);
+  if (m->widths[0] != nin || m->widths[m->nl] != 2 * ND + NL)
+    return fail(c, ILH_EINVAL, "fused guess MLP: widths do not match the features and outputs of this mesh");
+  if (m->with_base && !base) return fail(c, ILH_EINVAL, "fused guess MLP: the model takes the base iterate");
+  FusedNet F{};
+  F.nl = m->nl;
+  int wg = 0, ws = 0, bo = 0;
+  for (int l = 0; l < m->nl; ++l) {
+    F.kp[l] = pad32(m->widths[l]);
+    F.np[l] = pad32(m->widths[l + 1]);
+    F.wg[l] = wg;
+    F.ws[l] = ws;
+    F.bo[l] = bo;
+    wg += F.kp[l] * F.np[l];
+    ws += F.np[l] * (F.kp[l] + 8);
+    bo += F.np[l];
+  }
+  if (ws > FZ_WLDS) return fail(c, ILH_EINVAL, "fused guess MLP: the weights exceed the LDS budget");
+  if (ld < F.np[m->nl - 1]) return fail(c, ILH_EINVAL, "prediction stride below the padded output width");
+  if ((reinterpret_cast<uintptr_t>(m->W) & 15) != 0) return fail(c, ILH_EINVAL, "fused guess MLP: W not 16-byte aligned");
+  const FeatArgs fa{u, m->with_base ? base : nullptr, m->vscale, m->escale, m->xscale, m->kvscale, m->kescale,
+                    m->mu, m->sd};
+  const int64_t ntiles = (c->Ne + 63) / 64;
+  const unsigned nb = (unsigned)std::min<int64_t>(ntiles, 256);
+  hipLaunchKernelGGL(k_guess_fused, dim3(nb), dim3(256), 0, c->stream, c->kp, fa, F, m->W, m->b, pred, ld);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
   ILH_CATCH(c)

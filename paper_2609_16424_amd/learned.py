@@ -215,6 +215,22 @@ class LearnedGuess:
                                                     self.h._vec(u, self.h.nblock), float(tau), C.c_void_p(k.data_ptr())))
         return k
 
+    def predict_fused(self, u, base):
+        """Network output [Ne][P(w_nl)] from ilh_guess_mlp_fused (features and every layer in one
+        launch, the weights in LDS)."""
+        out = torch.zeros(self.h.Ne, self.ld_out, dtype=torch.float32, device=self.h.device)
+        self.h._stream()
+        self.h._check(self.h.lib.ilh_guess_mlp_fused(self.h.ctx, C.byref(self.model()), self.h._vec(u, self.h.nblock),
+                                                     self.h._vec(base, self.h.nblock) if self.with_base else None,
+                                                     C.c_void_p(out.data_ptr()), self.ld_out))
+        return out
+
+    def predict_layered(self, u, base):
+        """The same network output from ilh_guess_features and the layer-by-layer forward."""
+        x = self.features(u, base)
+        _, _, out = self.mlp.forward(x)
+        return out
+
     def model(self):
         """Descriptor of this guess for ilh_guess_infer (device pointers stay owned here)."""
         m = _lib.GuessModel()
