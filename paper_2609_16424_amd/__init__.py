@@ -265,7 +265,7 @@ class Hydro:
         """Explicit rate, last rate, or linear extrapolation of the last two (most recent last);
         with tau > 0 the position block is set to u_v + tau k_v.  fallback: the better of the
         extrapolation and the last rate by stage residual (ilh_plain_guess_fallback)."""
-        out = self.new()
+        out = torch.empty(self.nblock, dtype=torch.float64, device=self.device)  # every block is written
         k1 = self._vec(history[-1], self.nblock, name="k1") if len(history) >= 1 else None
         k2 = self._vec(history[-2], self.nblock, name="k2") if len(history) >= 2 else None
         self._stream()
@@ -335,7 +335,7 @@ class Hydro:
     def implicit_step(self, u, dt, guess=None, opts=None, raise_on_fail=True):
         """u <- u + dt k with k = f(u + dt/2 k) (in place); returns (k, stats dict)."""
         opts = opts or newton_options()
-        k = self.new()
+        k = torch.empty(self.nblock, dtype=torch.float64, device=self.device)  # written by the library
         st = StepStats()
         self._stream()
         g = self._vec(guess, self.nblock, name="guess") if guess is not None else None

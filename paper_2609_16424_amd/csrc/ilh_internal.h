@@ -129,6 +129,7 @@ struct ilh_ctx {
   float* kry32 = nullptr;       // z32, w32 [2][nblock]
   int kryf_m = 0;
   float* kryf = nullptr;        // FP32 Krylov basis (FP32 Jacobian actions): V [(m+1)][nblock], Z [m][nblock]
+  bool zero_ok = false;          // the zero block vector of the Newton workspace is filled
   double* gsp = nullptr;        // partial sums of the lagged Gram-Schmidt dot sweep [132][1024]
   double* hdev = nullptr;       // [HDEV_LEN] device scalars of the Arnoldi step
   double* hest = nullptr;       // pinned, coherent: (|g_j+1|, h_j+1,j) of each Arnoldi step at [2j, 2j+1]
@@ -245,6 +246,13 @@ int launch_scale_free(ilh_ctx* c, double* y, double a, const double* x);  // H1:
 int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* out);
 // device-side dot into d_out (no sync)
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
+// the block partial sums of x . y into part (*np of them)
+int dot_part(ilh_ctx* c, const double* x, const double* y, int64_t n, double* part, int* np);
+// out[0], out[1] = sum (mode 0) or minimum (mode 1) of each partial set, one launch
+int launch_pair_final(ilh_ctx* c, const double* pa, int na, int ma, const double* pb, int nb, int mb, double* out);
+// out = k1 or 2 k1 - k2 (nhist 1 or 2), position block u_v + tau out_v when tau > 0
+int launch_extrap(ilh_ctx* c, double* out, const double* u, const double* k1, const double* k2, int nhist,
+                  double tau);
 // Arnoldi scalars: [0, 72) and [72, 144) the two Gram-Schmidt passes, 144 the norm, [160, 224)
 // the update coefficients, 240 beta, 250 tau, 252 the cycle's residual target, 255 the cycle's
 // tag, [256, 321) the basis scales s_j (basis vector j = s_j x the stored vector), [352, 480)

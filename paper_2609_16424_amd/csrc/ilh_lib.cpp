@@ -780,23 +780,25 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   ILH_CATCH(c)
 }
 
-// The strip residual with the smallest det J of the stage positions in *d_min (device), one
-// pass for both; false (nothing launched) where no strip residual kernel applies
+// The strip residual with the smallest det J of the stage positions, one pass for both; false
+// (nothing launched) where no strip residual kernel applies
 static bool residual_detj_available(const ilh_ctx* c) {
   return c->jvp_variant != 1 && (res2d_available(c) || res3d_available(c));
 }
-static int residual_detj(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* d_min) {
+// the same, with the per-work-group minima left in c->dmin_part (*ng of them) for the caller's
+// final reduction
+static int residual_detj_part(ilh_ctx* c, const double* k, const double* u, double tau, double* r, int* ng) {
   int st;
   const bool d2 = res2d_available(c);
-  const int ng = d2 ? res2d_groups(c) : res3d_groups(c);
-  if (!c->dmin_part && (st = dalloc(c, &c->dmin_part, (size_t)ng))) return st;
+  *ng = d2 ? res2d_groups(c) : res3d_groups(c);
+  if (!c->dmin_part && (st = dalloc(c, &c->dmin_part, (size_t)*ng))) return st;
   if ((st = launch_fill(c, r + c->nh1, 0.0, c->nh1))) return st;
   const int slot = tstart_k(c, 1);
   st = d2 ? launch_res2d(c, k, u, tau, r, c->dmin_part) : launch_res3d(c, k, u, tau, r, c->dmin_part);
   tstop_k(c, slot);
-  if (st) return st;
-  return launch_min_final(c, c->dmin_part, ng, d_min);
+  return st;
 }
+
 
 int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
   ILH_TRY
@@ -1077,13 +1079,11 @@ int ilh_plain_guess(ilh_ctx* c, const double* u, const double* k1, const double*
   ILH_TRY
   if (!c || !u || !out) return ILH_EINVAL;
   int st;
-  if (nhist <= 0) {
-    if ((st = ilh_rate(c, u, out))) return st;
-  } else {
+  if (nhist > 0) {
     if (!k1 || (nhist >= 2 && !k2)) return fail(c, ILH_EINVAL, "missing history vector");
-    ILH_HIP(c, hipMemcpyAsync(out, k1, c->nblock * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    if (nhist >= 2 && (st = launch_axpby(c, out, -1.0, k2, 2.0, c->nblock))) return st;
+    return launch_extrap(c, out, u, k1, k2, nhist >= 2 ? 2 : 1, tau);  // one pass, position block included
   }
+  if ((st = ilh_rate(c, u, out))) return st;
   if (tau > 0.0) {
     // out_x = u_v + tau out_v
     ILH_HIP(c, hipMemcpyAsync(out, u + c->nh1, c->nh1 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1512,8 +1512,23 @@ struct Solver {
           if ((spins & 1023) == 0) {
             const hipError_t q = hipStreamQuery(c->stream);
             if (q != hipSuccess && q != hipErrorNotReady) ILH_HIP(c, q);
-            if (q == hipSuccess && !(est[128 + jj] == tag))
-              return fail(c, ILH_EHIP, "FGMRES: a finished step left no residual estimate");
+            if (q == hipSuccess && !(est[128 + jj] == tag)) {
+              // the stream is done: the tag must arrive (host-mapped stores can trail the
+              // completion the stream reports); give it 10 ms before calling it missing
+              const auto td = std::chrono::steady_clock::now();
+              while (!(est[128 + jj] == tag) && std::chrono::steady_clock::now() - td < std::chrono::milliseconds(10))
+                __builtin_ia32_pause();
+            }
+            if (q == hipSuccess && !(est[128 + jj] == tag)) {
+              double flag = 0.0;  // the lagged form's cycle-end flag
+              (void)hipMemcpy(&flag, hd + HDEV_LGSE, sizeof(double), hipMemcpyDeviceToHost);
+              char msg[256];
+              std::snprintf(msg, sizeof msg,
+                            "FGMRES: a finished step left no residual estimate (column %d, tag %.17g, found %.17g, "
+                            "columns read %d, end flag %g)",
+                            jj, tag, (double)est[128 + jj], total, flag);
+              return fail(c, ILH_EHIP, msg);
+            }
             if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
               return fail(c, ILH_EHIP, "FGMRES: timed out waiting for a residual estimate");
           }
@@ -1640,43 +1655,62 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
     ILH_HIP(c, hipHostGetDevicePointer((void**)&c->hest_dev, c->hest, 0));
   }
   if (!c->gmd && (st = dalloc(c, &c->gmd, 64 * 64 + 3 * 65))) return st;
-  double* k = c->nwt;
+  // The iterate k is only read: every Newton update writes a trial buffer (kA or kB), which then
+  // becomes the iterate; the guess and the zero vector serve as iterates without a copy.
+  double* kA = c->nwt;
+  double* kB = c->nwt + 6 * n;
+  const double* k = nullptr;
   double* r = c->nwt + n;
   double* dk = c->nwt + 2 * n;
   double* trial = c->nwt + 4 * n;
   double* zero = c->nwt + 5 * n;
-  double* kt = c->nwt + 6 * n;
   double* rt = c->nwt + 7 * n;
   Solver<TV> S{c, o, tau};
   double* dsc = dev_pair(c);
-  if ((st = launch_fill(c, zero, 0.0, n))) return st;
-  if ((st = ilh_residual(c, zero, u, tau, r))) return st;
-  if ((st = dot_dev(c, r, r, n, dsc))) return st;
+  double* pa = c->red;                   // partial sums of the first norm of a pair
+  double* pb = c->red + c->red_blocks;   // and of the second
+  double* hp = c->hest_dev + 240;        // the pair, in mapped host memory
+  auto read_hp = [&](double* a, double* b) -> int {
+    ILH_HIP(c, hipStreamSynchronize(c->stream));
+    *a = c->hest[240];
+    *b = c->hest[241];
+    return ILH_OK;
+  };
+  if (!c->zero_ok) {
+    if ((st = launch_fill(c, zero, 0.0, n))) return st;
+    c->zero_ok = true;  // nothing else writes this part of the workspace
+  }
+  int npa = 0, npb = 0;
+  if ((st = ilh_residual(c, zero, u, tau, rt))) return st;  // R(0) in rt
+  if ((st = dot_part(c, rt, rt, n, pa, &npa))) return st;
   double r0 = 0.0, nr = 0.0;
   if (k_guess) {
     // |R(0)| and |R(k_guess)| read together
-    ILH_HIP(c, hipMemcpyAsync(k, k_guess, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    if ((st = ilh_residual(c, k, u, tau, r))) return st;
-    if ((st = dot_dev(c, r, r, n, dsc + 1))) return st;
-    if ((st = read_pair(c, &r0, &nr))) return st;
+    if ((st = ilh_residual(c, k_guess, u, tau, r))) return st;
+    if ((st = dot_part(c, r, r, n, pb, &npb))) return st;
+    if ((st = launch_pair_final(c, pa, npa, 0, pb, npb, 0, hp))) return st;
+    if ((st = read_hp(&r0, &nr))) return st;
     r0 = std::sqrt(r0);
     nr = std::sqrt(nr);
     stats.res0 = r0;
     stats.res_init = nr;
+    k = k_guess;
     if (o->guess_fallback && !(nr <= r0)) {
-      // the initial iterate is worse than k = 0: start from zero instead
+      // the initial iterate is worse than k = 0: start from zero instead (its residual is in rt)
       stats.guess_rejected = 1;
-      if ((st = launch_fill(c, k, 0.0, n))) return st;
-      if ((st = ilh_residual(c, k, u, tau, r))) return st;
+      k = zero;
+      std::swap(r, rt);
       nr = r0;
     }
   } else {
     double unused;
-    if ((st = read_pair(c, &r0, &unused))) return st;
+    if ((st = launch_pair_final(c, pa, npa, 0, pa, npa, 0, hp))) return st;
+    if ((st = read_hp(&r0, &unused))) return st;
     r0 = std::sqrt(r0);
     nr = r0;
     stats.res0 = r0;
-    if ((st = launch_fill(c, k, 0.0, n))) return st;
+    k = zero;
+    std::swap(r, rt);
     stats.res_init = r0;
   }
   int status = ILH_OK;
@@ -1697,28 +1731,34 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
     }
     if ((st = ilh_linearize(c, k, u, tau))) return st;
     if (o->prec_probe && (it == 0 || !o->prec_lag) && (st = build_probe_prec(c, o->prec_probe))) return st;
-    if ((st = launch_axpby(c, r, 0.0, r, -1.0, n))) return st;  // r <- -r (right-hand side)
+    // the Newton direction is -x with J x = R(k): the solve takes r as its right-hand side and
+    // the trials step by -alpha x
     int gits = 0;
-    if ((st = S.fgmres(r, dk, &gits, nr))) return st;  // |-r| = nr
+    if ((st = S.fgmres(r, dk, &gits, nr))) return st;
     stats.gmres_iters += gits;
+    double* kt = (k == kB) ? kA : kB;
     // backtracking: det J > 0 at every quadrature point of the stage positions, and (when
     // enabled) sufficient decrease ||R(k + a dk)|| <= (1 - 1e-4 a) ||R(k)||
     double alpha = 1.0, best = INFINITY, best_alpha = 0.0;
     bool ok = false, any_valid = false, nonfinite = false;
     for (int h = 0; h <= o->max_halvings; ++h) {
-      if ((st = launch_waxpy(c, kt, k, alpha, dk, n))) return st;
+      if ((st = launch_waxpy(c, kt, k, -alpha, dk, n))) return st;
       // the trial residual is formed before det J > 0 is known (it is discarded otherwise), so
       // that one synchronisation reads both; the strip residual kernel returns det J itself
+      double md, nrt2;
       if (residual_detj_available(c)) {
-        if ((st = residual_detj(c, kt, u, tau, rt, dsc))) return st;
+        int ng = 0;
+        if ((st = residual_detj_part(c, kt, u, tau, rt, &ng))) return st;
+        if ((st = dot_part(c, rt, rt, n, pb, &npb))) return st;
+        if ((st = launch_pair_final(c, c->dmin_part, ng, 1, pb, npb, 0, hp))) return st;
+        if ((st = read_hp(&md, &nrt2))) return st;
       } else {
         if ((st = launch_waxpy(c, trial, u, tau, kt, c->nh1))) return st;
         if ((st = min_detj_dev(c, trial, dsc))) return st;
         if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
+        if ((st = dot_dev(c, rt, rt, n, dsc + 1))) return st;
+        if ((st = read_pair(c, &md, &nrt2))) return st;
       }
-      if ((st = dot_dev(c, rt, rt, n, dsc + 1))) return st;
-      double md, nrt2;
-      if ((st = read_pair(c, &md, &nrt2))) return st;
       // a NaN det J (non-finite stage positions) or a non-finite residual at valid positions
       // is reported as ENONFINITE if no trial succeeds, not as tangling
       if (std::isnan(md) || (md > 0.0 && !std::isfinite(nrt2))) nonfinite = true;
@@ -1741,7 +1781,7 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
     if (!ok && any_valid && std::isfinite(best)) {
       // no sufficient decrease within the halvings: take the best valid trial
       alpha = best_alpha;
-      if ((st = launch_waxpy(c, kt, k, alpha, dk, n))) return st;
+      if ((st = launch_waxpy(c, kt, k, -alpha, dk, n))) return st;
       if ((st = ilh_residual(c, kt, u, tau, rt))) return st;
       nr = nrm2(c, rt, n, &st);
       if (st) return st;
@@ -1753,16 +1793,19 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
                          : "line search could not keep det J > 0";
       break;
     }
-    std::swap(k, kt);
+    k = kt;
     std::swap(r, rt);
   }
   stats.newton_iters = it;
   stats.newton_max = it;
   stats.jvp_calls = S.jvp_calls;
   stats.status = status;
-  if (k_out) ILH_HIP(c, hipMemcpyAsync(k_out, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  // leave the final iterate at the head of the Newton workspace for ilh_implicit_step
-  if (k != c->nwt) ILH_HIP(c, hipMemcpyAsync(c->nwt, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (k_out) {
+    if (k_out != k) ILH_HIP(c, hipMemcpyAsync(k_out, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  } else if (k != c->nwt) {
+    // without k_out, the final iterate is left at the head of the Newton workspace
+    ILH_HIP(c, hipMemcpyAsync(c->nwt, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   if (st_out) *st_out = stats;
   return status;
@@ -1880,8 +1923,8 @@ int ilh_implicit_step(ilh_ctx* c, double* u, double dt, const double* k_guess, d
     return fail(c, ILH_EINVAL, "bad Newton options");
   int status = stage_solve(c, u, 0.5 * dt, k_guess, k_out, o, st);
   if (status != ILH_OK) return status;
-  // u <- u + dt k
-  int s2 = launch_axpby(c, u, dt, c->nwt, 1.0, c->nblock);
+  // u <- u + dt k (the stage rate is in k_out, else at the head of the Newton workspace)
+  int s2 = launch_axpby(c, u, dt, k_out ? k_out : c->nwt, 1.0, c->nblock);
   if (s2) return s2;
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   return ILH_OK;

@@ -128,6 +128,8 @@ __global__ void __launch_bounds__(256) k_dense_bwd_data(const float* __restrict_
 
 // dW[n][k] += sum_b bf(dZ[b][n]) bf(X[b][k]) over a chunk of 256 batch rows per work-group
 // (A operand = dZ^T: rows n, k-dim = batch; B operand = X: cols k).  db[n] += sum_b dZ[b][n].
+// Grid: x = batch chunks, y = groups of output tiles (each wave one 16 x 16 tile at a time), so
+// that a batch of a few thousand rows still spreads over the whole chip.
 template <int KP, int NP>
 __global__ void __launch_bounds__(256) k_dense_bwd_weight(const float* __restrict__ dZ, const float* __restrict__ X,
                                                           int batch, float* __restrict__ dW, float* __restrict__ db) {
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(256) k_dense_bwd_weight(const float* __restric
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int b0 = blockIdx.x * 256;
   const int kb = (lane >> 4) * 8;
-  for (int t = wave; t < NT; t += 4) {
+  for (int t = blockIdx.y * 4 + wave; t < NT; t += 4 * gridDim.y) {
     const int tn = t / (KP / 16), tk = t % (KP / 16);
     const int n = tn * 16 + (lane & 15), k = tk * 16 + (lane & 15);
     f32x4 acc = {0, 0, 0, 0};
@@ -154,7 +156,8 @@ __global__ void __launch_bounds__(256) k_dense_bwd_weight(const float* __restric
       unsafeAtomicAdd(&dW[(int64_t)nn * KP + k], acc[j]);
     }
   }
-  // bias gradient
+  // bias gradient (first tile group)
+  if (blockIdx.y != 0) return;
   for (int n = threadIdx.x; n < NP; n += 256) {
     float acc = 0;
     for (int bb = b0; bb < b0 + 256 && bb < batch; ++bb) acc += dZ[(int64_t)bb * NP + n];
@@ -432,8 +435,9 @@ static void bwdd_t(ilh_ctx* c, const float* dZ, const uint16_t* WT, int batch, c
 }
 template <int KP, int NP>
 static void bwdw_t(ilh_ctx* c, const float* dZ, const float* X, int batch, float* dW, float* db) {
-  hipLaunchKernelGGL((k_dense_bwd_weight<KP, NP>), dim3((batch + 255) / 256), dim3(256), 0, c->stream, dZ, X, batch,
-                     dW, db);
+  constexpr int NT = (NP / 16) * (KP / 16);
+  hipLaunchKernelGGL((k_dense_bwd_weight<KP, NP>), dim3((batch + 255) / 256, (NT + 3) / 4), dim3(256), 0, c->stream, dZ,
+                     X, batch, dW, db);
 }
 
 // dispatch on padded (KP, NP) in {32, 64, 96, 128}^2

@@ -44,6 +44,27 @@ __global__ void k_f2d(double* y, const float* x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (double)x[i];
 }
+// out = k1 (nhist 1) or 2 k1 - k2 (nhist 2); with tau > 0 the position block is u_v + tau out_v
+__global__ void k_extrap(double* out, const double* u, const double* k1, const double* k2, int nhist, double tau,
+                         int64_t nh1, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (tau > 0.0 && i < nh1) {
+      const int64_t iv = nh1 + i;
+      const double kv = nhist >= 2 ? 2.0 * k1[iv] - k2[iv] : k1[iv];
+      out[i] = u[iv] + tau * kv;
+    } else {
+      out[i] = nhist >= 2 ? 2.0 * k1[i] - k2[i] : k1[i];
+    }
+  }
+}
+int launch_extrap(ilh_ctx* c, double* out, const double* u, const double* k1, const double* k2, int nhist,
+                  double tau) {
+  const int64_t n = c->nblock;
+  hipLaunchKernelGGL(k_extrap, dim3(nblk(n, 4096)), dim3(TPB), 0, c->stream, out, u, k1, k2, nhist, tau, c->nh1, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
 __global__ void k_jacobi(const double* r, const double* d, double* z, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     z[i] = r[i] / d[i];
@@ -174,6 +195,37 @@ int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_o
   const int nb = red_blocks(c, n);
   hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(TPB), 0, c->stream, x, y, n, c->red);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, d_out, 0);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+
+int dot_part(ilh_ctx* c, const double* x, const double* y, int64_t n, double* part, int* np) {
+  const int nb = red_blocks(c, n);
+  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(TPB), 0, c->stream, x, y, n, part);
+  ILH_HIP(c, hipGetLastError());
+  *np = nb;
+  return ILH_OK;
+}
+
+// Two reductions of partial sums finished in one launch: out[0] = the sum (ma = 0) or the
+// minimum (ma = 1) of pa[0..na), out[1] likewise of pb; out may be host-mapped memory, read once
+// the stream has synchronised
+__global__ void __launch_bounds__(TPB) k_pair_final(const double* pa, int na, int ma, const double* pb, int nb,
+                                                    int mb, double* out) {
+  double a = ma ? 1e300 : 0.0, b = mb ? 1e300 : 0.0;
+  for (int i = threadIdx.x; i < na; i += TPB) a = ma ? nan_min(a, pa[i]) : a + pa[i];
+  for (int i = threadIdx.x; i < nb; i += TPB) b = mb ? nan_min(b, pb[i]) : b + pb[i];
+  a = ma ? block_min<TPB>(a) : block_sum<TPB>(a);
+  b = mb ? block_min<TPB>(b) : block_sum<TPB>(b);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+    __threadfence_system();
+  }
+}
+
+int launch_pair_final(ilh_ctx* c, const double* pa, int na, int ma, const double* pb, int nb, int mb, double* out) {
+  hipLaunchKernelGGL(k_pair_final, dim3(1), dim3(TPB), 0, c->stream, pa, na, ma, pb, nb, mb, out);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -528,6 +580,7 @@ __device__ __forceinline__ void sum_givens_block(const GivensJob& g) {
       g.hest[2 * j + 1] = h[353 + 2 * j];
       __threadfence_system();  // the estimate reaches the host before the tag
       g.hest[128 + j] = h[255];
+      __threadfence_system();  // and the tag before the kernel can complete
     }
   }
 }
@@ -848,6 +901,7 @@ __global__ void __launch_bounds__(LGS_FT) k_lgs_final(const double* __restrict__
       hest[2 * jc + 1] = hn;
       __threadfence_system();  // the estimate reaches the host before the tag
       hest[128 + jc] = sc[3];
+      __threadfence_system();  // and the tag before the kernel can complete
     }
   }
   if (flag != 0.0) h[HDEV_LGSE] = j + 1;
@@ -942,6 +996,7 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
       hest[2 * jc + 1] = h[353 + 2 * jc];
       __threadfence_system();  // the estimate reaches the host before the tag
       hest[128 + jc] = h[255];
+      __threadfence_system();  // and the tag before the kernel can complete
     }
     return;
   }
