@@ -132,8 +132,9 @@ struct ilh_ctx {
   bool zero_ok = false;          // the zero block vector of the Newton workspace is filled
   double* gsp = nullptr;        // partial sums of the lagged Gram-Schmidt dot sweep [132][1024]
   double* hdev = nullptr;       // [HDEV_LEN] device scalars of the Arnoldi step
-  double* hest = nullptr;       // pinned, coherent: (|g_j+1|, h_j+1,j) of each Arnoldi step at [2j, 2j+1]
-  double* hest_dev = nullptr;   // and the cycle's tag at [128 + j], stored by the device (mapped address)
+  double* hest = nullptr;       // pinned, coherent: per Arnoldi column j the records {|g_j+1|, tag} and
+                                // {h_j+1,j, tag} at [4j, 4j + 4); [256, 258) a pair of norms
+  double* hest_dev = nullptr;   // its device (mapped) address
   double est_tag = 0.0;         // tag of the current FGMRES cycle (host counter)
   double* gmd = nullptr;        // device Givens state of FGMRES: H [64][64], cs, sn [64], g [65]
   hipStream_t capstream = nullptr;         // stream the Arnoldi-step graphs are captured on
@@ -270,6 +271,9 @@ constexpr int HDEV_LGSE = 770;
 constexpr int HDEV_LEN = 776;
 // y = H(0:n, 0:n)^-1 g
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
+// x += Z y with y = H(0:jn, 0:jn)^-1 g, one launch
+template <typename TV>
+int launch_trisolve_maxpy(ilh_ctx* c, double* x, const TV* Z, int64_t ldz, const double* G, int jn, int64_t n);
 // Norm reduction and Givens update of Arnoldi step j: the partial sums of |w|^2 (part, np blocks),
 // the Arnoldi scalars h, the rotations G (layout at givens_update), and the mapped host buffer of
 // residual estimates (hest, nullable).  Runs as its own one-block kernel, or as the extra last
@@ -319,7 +323,7 @@ int launch_precond_probe(ilh_ctx* c, const TV* r, TV* z, float* z32, double tau,
 // w += sign sum_j cf[j] V_j with the partial sums of |w|^2 of the result; *job receives the Givens
 // update of step j that finishes it (into h[144], then from the pass coefficients h[0..j],
 // h[72..72+j], and the next basis scale h[256 + j + 1] = 1 / |w|; hest (nullable, host-mapped)
-// receives the step's (|g_j+1|, h_j+1,j) at [2j, 2j + 1] and the cycle's tag at [128 + j])
+// receives the step's (|g_j+1|, h_j+1,j) with the cycle's tag, records {value, tag} at [4j, 4j + 4))
 template <typename TV>
 int multiaxpy_nrm(ilh_ctx* c, TV* w, const TV* V, int64_t ldv, int m, const double* cf, double sign,
                   int64_t n, double* h, double* G, int j, int mm, double* hest, GivensJob* job,

@@ -1507,26 +1507,32 @@ struct Solver {
         // dry without it (every enqueued kernel done) is an error, so the wait always ends
         const volatile double* est = c->hest;
         const auto t0 = std::chrono::steady_clock::now();
-        for (unsigned spins = 1; !(est[128 + jj] == tag); ++spins) {
+        auto arrived = [&]() { return est[4 * jj + 1] == tag && est[4 * jj + 3] == tag; };
+        for (unsigned spins = 1; !arrived(); ++spins) {
           __builtin_ia32_pause();
           if ((spins & 1023) == 0) {
             const hipError_t q = hipStreamQuery(c->stream);
             if (q != hipSuccess && q != hipErrorNotReady) ILH_HIP(c, q);
-            if (q == hipSuccess && !(est[128 + jj] == tag)) {
+            if (q == hipSuccess && !arrived()) {
               // the stream is done: the tag must arrive (host-mapped stores can trail the
               // completion the stream reports); give it 10 ms before calling it missing
               const auto td = std::chrono::steady_clock::now();
-              while (!(est[128 + jj] == tag) && std::chrono::steady_clock::now() - td < std::chrono::milliseconds(10))
+              while (!arrived() && std::chrono::steady_clock::now() - td < std::chrono::milliseconds(10))
                 __builtin_ia32_pause();
             }
-            if (q == hipSuccess && !(est[128 + jj] == tag)) {
-              double flag = 0.0;  // the lagged form's cycle-end flag
-              (void)hipMemcpy(&flag, hd + HDEV_LGSE, sizeof(double), hipMemcpyDeviceToHost);
-              char msg[256];
+            if (q == hipSuccess && !arrived()) {
+              // the device's view: cycle-end flag, target, and the previous column's estimate
+              double dv[HDEV_LEN];
+              (void)hipMemcpy(dv, hd, sizeof(dv), hipMemcpyDeviceToHost);
+              const int pj = jj > 0 ? jj - 1 : 0;
+              char msg[512];
               std::snprintf(msg, sizeof msg,
                             "FGMRES: a finished step left no residual estimate (column %d, tag %.17g, found %.17g, "
-                            "columns read %d, end flag %g)",
-                            jj, tag, (double)est[128 + jj], total, flag);
+                            "columns read %d, end flag %g; column %d: host %.17g %.17g tag %.17g, device %.17g "
+                            "%.17g; target host %.17g device %.17g)",
+                            jj, tag, (double)est[4 * jj + 1], total, dv[HDEV_LGSE], pj, (double)est[4 * pj],
+                            (double)est[4 * pj + 2], (double)est[4 * pj + 1], dv[352 + 2 * pj], dv[353 + 2 * pj],
+                            target, dv[252]);
               return fail(c, ILH_EHIP, msg);
             }
             if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
@@ -1534,7 +1540,7 @@ struct Solver {
           }
         }
         std::atomic_thread_fence(std::memory_order_acquire);
-        const double res = est[2 * jj], hn = est[2 * jj + 1];
+        const double res = est[4 * jj], hn = est[4 * jj + 2];
         if (!std::isfinite(hn) || !std::isfinite(res)) return fail(c, ILH_ENONFINITE, "non-finite Krylov vector");
         ++total;
         stop = res <= target || total >= o->gmres_maxit;
@@ -1619,8 +1625,7 @@ struct Solver {
         j_end = m;
       }
       // y = H^-1 g (upper triangular), x += Z y
-      if ((st = launch_trisolve(c, G, m, j_end, hd + 160))) return st;
-      if ((st = multiaxpy_dev(c, x, Z, n, j_end, hd + 160, 1.0, n))) return st;
+      if ((st = launch_trisolve_maxpy<TV>(c, x, Z, n, G, j_end, n))) return st;
       if (stop) break;
       // restart: r = b - J x
       if ((st = apply(x, rbuf))) return st;
@@ -1648,10 +1653,10 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
   if (!c->nwt && (st = dalloc(c, &c->nwt, 8 * (size_t)n))) return st;
   if (!c->hdev && (st = dalloc(c, &c->hdev, HDEV_LEN))) return st;
   if (!c->hest) {
-    if (hipHostMalloc((void**)&c->hest, 256 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+    if (hipHostMalloc((void**)&c->hest, 272 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
         hipSuccess)
       return fail(c, ILH_ENOMEM, "pinned host buffer");
-    std::memset(c->hest, 0, 256 * sizeof(double));  // no tag (tags start at 1)
+    std::memset(c->hest, 0, 272 * sizeof(double));  // no tag (tags start at 1)
     ILH_HIP(c, hipHostGetDevicePointer((void**)&c->hest_dev, c->hest, 0));
   }
   if (!c->gmd && (st = dalloc(c, &c->gmd, 64 * 64 + 3 * 65))) return st;
@@ -1669,11 +1674,11 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
   double* dsc = dev_pair(c);
   double* pa = c->red;                   // partial sums of the first norm of a pair
   double* pb = c->red + c->red_blocks;   // and of the second
-  double* hp = c->hest_dev + 240;        // the pair, in mapped host memory
+  double* hp = c->hest_dev + 256;        // the pair, in mapped host memory
   auto read_hp = [&](double* a, double* b) -> int {
     ILH_HIP(c, hipStreamSynchronize(c->stream));
-    *a = c->hest[240];
-    *b = c->hest[241];
+    *a = c->hest[256];
+    *b = c->hest[257];
     return ILH_OK;
   };
   if (!c->zero_ok) {

@@ -546,11 +546,21 @@ int maxpy_multidot(ilh_ctx* c, TV* w, const TV* V, int64_t ldv, int m, const dou
 __device__ void givens_update(double* h, double* G, int j, int m, const double* csl, const double* snl,
                               const double* coll);
 
+// The residual estimate and h_{j+1,j} of column j to host memory (mapped, coherent) as two 16-byte
+// records {estimate, tag} and {h_{j+1,j}, tag}: each record is one store, so the host never pairs
+// a new tag with an old value whatever order the two stores become visible in
+__device__ __forceinline__ void publish_estimate(double* hest, int j, double est, double hn, double tag) {
+  double2* rec = reinterpret_cast<double2*>(hest + 4 * j);
+  rec[0] = make_double2(est, tag);
+  rec[1] = make_double2(hn, tag);
+  __threadfence_system();
+}
+
 // final sum of the norm partials into h[144], the Givens update of Arnoldi step j, and the
 // scale of the next basis vector, h[256 + j + 1] = 1 / |w| (1 for a zero or non-finite norm:
 // the cycle ends at that step).  The residual estimate also goes straight to host memory
-// (hest, mapped and coherent), followed by the cycle's tag h[255] at hest[128 + j], which the
-// host polls: no copy and no event are enqueued behind the step.
+// (hest, mapped and coherent) with the cycle's tag h[255] (publish_estimate), which the host
+// polls: no copy and no event are enqueued behind the step.
 __device__ __forceinline__ void sum_givens_block(const GivensJob& g) {
   if (g.skip && *g.skip != 0.0) return;
   // the earlier rotations and the new Hessenberg column go to LDS while the partials are summed,
@@ -576,11 +586,7 @@ __device__ __forceinline__ void sum_givens_block(const GivensJob& g) {
     // zero norm), so a step the host discards does no work
     h[HDEV_FLAG + j] = (h[352 + 2 * j] <= h[252] || h[353 + 2 * j] == 0.0) ? 1.0 : 0.0;
     if (g.hest) {
-      g.hest[2 * j] = h[352 + 2 * j];
-      g.hest[2 * j + 1] = h[353 + 2 * j];
-      __threadfence_system();  // the estimate reaches the host before the tag
-      g.hest[128 + j] = h[255];
-      __threadfence_system();  // and the tag before the kernel can complete
+      publish_estimate(g.hest, j, h[352 + 2 * j], h[353 + 2 * j], h[255]);
     }
   }
 }
@@ -700,6 +706,49 @@ __global__ void k_trisolve(const double* G, int n, double* y) {
 }
 
 
+// x += sum_{j < jn} y_j Z_j with y = H(0:jn, 0:jn)^-1 g(0:jn): every block repeats the small
+// triangular solve (operands staged in LDS; one wave back-substitutes column by column, lane l
+// holding row l of the right-hand side) and then takes its share of the update
+template <typename TV>
+__global__ void __launch_bounds__(TPB) k_trisolve_maxpy(double* __restrict__ x, const TV* __restrict__ Z,
+                                                        int64_t ldz, const double* __restrict__ G, int jn, int64_t n) {
+  extern __shared__ double tsh[];  // H (jn x jn, row-major), then y (jn)
+  double* Hs = tsh;
+  double* ys = tsh + jn * jn;
+  for (int t = threadIdx.x; t < jn * jn; t += TPB) Hs[t] = G[(t / jn) * 64 + t % jn];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double rhs = lane < jn ? G[64 * 64 + 128 + lane] : 0.0;
+    for (int i = jn - 1; i >= 0; --i) {
+      const double num = __shfl(rhs, i, 64);
+      const double hii = Hs[i * jn + i];
+      const double yi = hii != 0.0 ? num / hii : 0.0;
+      if (lane == i) ys[i] = yi;
+      if (lane < i) rhs -= Hs[lane * jn + i] * yi;
+    }
+  }
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int j = 0; j < jn; ++j) acc += ys[j] * (double)Z[(int64_t)j * ldz + i];
+    x[i] += acc;
+  }
+}
+
+template <typename TV>
+int launch_trisolve_maxpy(ilh_ctx* c, double* x, const TV* Z, int64_t ldz, const double* G, int jn, int64_t n) {
+  if (jn <= 0) return ILH_OK;
+  if (jn > 64) return fail(c, ILH_EINVAL, "triangular solve: at most 64 columns");
+  const size_t shm = (size_t)(jn * jn + jn) * sizeof(double);
+  hipLaunchKernelGGL(k_trisolve_maxpy<TV>, dim3(std::min(nblk(n), 1024)), dim3(TPB), shm, c->stream, x, Z, ldz, G, jn,
+                     n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+template int launch_trisolve_maxpy<double>(ilh_ctx*, double*, const double*, int64_t, const double*, int, int64_t);
+template int launch_trisolve_maxpy<float>(ilh_ctx*, double*, const float*, int64_t, const double*, int, int64_t);
+
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
   (void)m;
   hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, c->stream, G, n, y);
@@ -731,13 +780,18 @@ int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
 static constexpr int LGS_NS = 2 * MDOT_JC + 3;
 static constexpr int LGS_NP = 32;  // LGS_NS padded to a power of two for wave_sums
 
+// LGS_DB threads per work-group: a quarter as many partial sums as 256-thread groups would leave
+// for the final block, with the same number of waves
+static constexpr int LGS_DB = 1024;
+static constexpr int64_t LGS_DT = (int64_t)LGS_DB * KU;
+
 template <typename TV>
-__global__ void __launch_bounds__(TPB) k_lgs_dots(const TV* __restrict__ V, int64_t ldv, int j,
+__global__ void __launch_bounds__(LGS_DB) k_lgs_dots(const TV* __restrict__ V, int64_t ldv, int j,
                                                   const TV* __restrict__ uj, const TV* __restrict__ w,
                                                   int64_t n, double* part, const double* skip) {
   if (skip && *skip != 0.0) return;
-  __shared__ double sh[TPB / 64][LGS_NP];
-  const int64_t stride = (int64_t)gridDim.x * KTILE;
+  __shared__ double sh[LGS_DB / 64][LGS_NP];
+  const int64_t stride = (int64_t)gridDim.x * LGS_DT;
   const int nch = j > 0 ? (j + MDOT_JC - 1) / MDOT_JC : 1;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int ch = 0; ch < nch; ++ch) {
@@ -745,10 +799,15 @@ __global__ void __launch_bounds__(TPB) k_lgs_dots(const TV* __restrict__ V, int6
     double acc[LGS_NP];
 #pragma unroll
     for (int q = 0; q < LGS_NP; ++q) acc[q] = 0.0;
-    for (int64_t t0 = (int64_t)blockIdx.x * KTILE; t0 < n; t0 += stride) {
+    for (int64_t t0 = (int64_t)blockIdx.x * LGS_DT; t0 < n; t0 += stride) {
       int64_t ic[KU];
       bool in[KU];
-      tile_index(t0, n, ic, in);
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int64_t i = t0 + (int64_t)u * LGS_DB + threadIdx.x;
+        in[u] = i < n;
+        ic[u] = in[u] ? i : n - 1;
+      }
       double uv[KU], wv[KU];
       tile_load(uj, ic, in, uv);
       tile_load(w, ic, in, wv);
@@ -792,7 +851,7 @@ __global__ void __launch_bounds__(TPB) k_lgs_dots(const TV* __restrict__ V, int6
       if (sidx >= 0) {
         double r = 0.0;
 #pragma unroll
-        for (int i = 0; i < TPB / 64; ++i) r += sh[i][q];
+        for (int i = 0; i < LGS_DB / 64; ++i) r += sh[i][q];
         part[(int64_t)sidx * gridDim.x + blockIdx.x] = r;
       }
     }
@@ -802,7 +861,7 @@ __global__ void __launch_bounds__(TPB) k_lgs_dots(const TV* __restrict__ V, int6
 
 // Final block of step j (one work-group of LGS_FT threads): the sums, the second pass's scale,
 // column j - 1 with its Givens update and residual estimate (to h[352 + 2(j-1)]; to host memory
-// with the cycle's tag at hest[128 + j - 1] by the update sweep, or here on the closing step), the
+// with the cycle's tag (publish_estimate) by the update sweep, or here on the closing step), the
 // cycle-end flag h[HDEV_LGSE] = j + 1 when column j - 1 met the target or rho_j = 0 (every later
 // launch of the cycle then returns at once), and the update sweep's coefficients: a at h[0..j), b at h[72..72+j), 1 / rho_j at
 // h[144], d at h[145], s_{j+1} at h[146]; step j's first-pass coefficients (b, d) go to
@@ -897,11 +956,7 @@ __global__ void __launch_bounds__(LGS_FT) k_lgs_final(const double* __restrict__
     h[353 + 2 * jc] = hn;
     flag = (est <= sc[2] || hn == 0.0) ? 1.0 : 0.0;
     if (hest && !has_w) {  // a full step's update sweep publishes it (first block)
-      hest[2 * jc] = est;
-      hest[2 * jc + 1] = hn;
-      __threadfence_system();  // the estimate reaches the host before the tag
-      hest[128 + jc] = sc[3];
-      __threadfence_system();  // and the tag before the kernel can complete
+      publish_estimate(hest, jc, est, hn, sc[3]);
     }
   }
   if (flag != 0.0) h[HDEV_LGSE] = j + 1;
@@ -992,11 +1047,7 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
     // first in the grid, so that the fence runs beside the sweep instead of after it
     if (pub && hest && threadIdx.x == 0) {
       const int jc = j - 1;
-      hest[2 * jc] = h[352 + 2 * jc];
-      hest[2 * jc + 1] = h[353 + 2 * jc];
-      __threadfence_system();  // the estimate reaches the host before the tag
-      hest[128 + jc] = h[255];
-      __threadfence_system();  // and the tag before the kernel can complete
+      publish_estimate(hest, jc, h[352 + 2 * jc], h[353 + 2 * jc], h[255]);
     }
     return;
   }
@@ -1080,9 +1131,9 @@ template <typename TV>
 int lgs_dots(ilh_ctx* c, const TV* V, int64_t ldv, int j, const TV* uj, const TV* w, int64_t n, double* part,
              int* np, const double* skip) {
   if (j > 64) return fail(c, ILH_EINVAL, "Gram-Schmidt: at most 64 basis vectors");
-  const int nb = fused_blocks(n);
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + LGS_DT - 1) / LGS_DT));
   // the closing step has no w: its products are taken with u_j instead and not used
-  hipLaunchKernelGGL(k_lgs_dots<TV>, dim3(nb), dim3(TPB), 0, c->stream, V, ldv, j, uj, w ? w : uj, n, part, skip);
+  hipLaunchKernelGGL(k_lgs_dots<TV>, dim3(nb), dim3(LGS_DB), 0, c->stream, V, ldv, j, uj, w ? w : uj, n, part, skip);
   ILH_HIP(c, hipGetLastError());
   *np = nb;
   return ILH_OK;
