@@ -466,7 +466,7 @@ int ilh_guess_infer(ilh_ctx* ctx, const ilh_guess_model* m, const double* u, con
 /* Features of (u, base) and the whole MLP of m in one launch: pred [Ne][ld] (float, device)
  * receives the network output of every element, equal to ilh_guess_features followed by
  * ilh_mlp_forward (same BF16 rounding, accumulation order and epilogue).  Each work-group keeps
- * every layer's BF16 weights and biases in LDS and walks tiles of 64 elements.  ILH_EINVAL when
+ * every layer's BF16 weights and biases in LDS and walks tiles of 16 elements.  ILH_EINVAL when
  * the widths do not match this mesh's features (widths[0]) and outputs (widths[nl]), when the
  * padded weights exceed 112 KiB of LDS (rows padded by 8 entries), when ld is below the padded
  * output width, or when m->W is not 16-byte aligned.  ilh_guess_infer takes this path when the

@@ -268,11 +268,12 @@ __global__ void k_features(const KParams P, const FeatArgs A, float* feat, int l
 }
 
 // ---------------------------------------------------------------------------------------
-// Fused inference: the features of 64 elements per tile, every layer and the store of the
-// network output in one launch.  Each work-group first copies all weights (BF16) and biases
-// into LDS, once, and then walks element tiles (4 waves x 16 rows); activations pass from layer
-// to layer through a per-wave LDS tile in the MFMA operand layout.  The operand rounding (BF16),
-// the accumulation order and the epilogue are those of k_dense_fwd, so the output is the layered
+// Fused inference: the features of a tile of 16 elements, every layer and the store of the
+// network output in one launch.  Each work-group first copies all weights (BF16) and biases into
+// LDS and then walks element tiles; the eight waves compute the features of the tile together and
+// split each layer's 16-column output tiles, the activations passing between layers through two
+// alternating LDS tiles in the MFMA operand layout.  The operand rounding (BF16), the
+// accumulation order and the epilogue are those of k_dense_fwd, so the output is the layered
 // forward's.  Weight rows are padded by 8 BF16 (16 bytes) in LDS, so the 16 lanes of a quarter
 // wave read 16 different rows from 16 different bank groups.
 constexpr int FZ_MAXL = 8;
@@ -288,45 +289,59 @@ struct FusedNet {
   int bo[FZ_MAXL];                // offset of layer l's bias
 };
 
-__global__ void __launch_bounds__(256) k_guess_fused(const KParams P, const FeatArgs FA, const FusedNet F,
+constexpr int FZ_T = 512;  // threads of the work-group (8 waves)
+
+__global__ void __launch_bounds__(FZ_T) k_guess_fused(const KParams P, const FeatArgs FA, const FusedNet F,
                                                      const uint16_t* __restrict__ W, const float* __restrict__ bias,
                                                      float* __restrict__ pred, int ld_out) {
   __shared__ __attribute__((aligned(16))) uint16_t sW[FZ_WLDS];
   __shared__ float sB[FZ_BLDS];
-  __shared__ __attribute__((aligned(16))) uint16_t sA[4][16][FZ_ALD];
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][16][FZ_ALD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // weights: 8 BF16 (16 bytes) per copy, rows of KP to rows of KP + 8
+  // weights: 8 BF16 (16 bytes) per copy, rows of KP to rows of KP + 8, eight copies in flight
   for (int l = 0; l < F.nl; ++l) {
-    const int KP = F.kp[l], NP = F.np[l], KC = KP / 8;
-    for (int i = tid; i < NP * KC; i += 256) {
-      const int n = i / KC, kc = i - n * KC;
-      const uint4 v = *reinterpret_cast<const uint4*>(W + F.wg[l] + n * KP + kc * 8);
-      *reinterpret_cast<uint4*>(sW + F.ws[l] + n * (KP + 8) + kc * 8) = v;
-    }
-    for (int i = tid; i < NP; i += 256) sB[F.bo[l] + i] = bias[F.bo[l] + i];
-  }
-  __syncthreads();
-  const int64_t ntiles = (P.Ne + 63) / 64;
-  const int kb = (lane >> 4) * 8;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t row0 = tile * 64 + wave * 16;
-    const int64_t r = row0 + (lane & 15);
-    // layer 0 operand: the features of the lane's row
-    bf16x8 af[4];
-    const int KP0 = F.kp[0];
+    const int KP = F.kp[l], NP = F.np[l], KC = KP / 8, tot = NP * KC;
+    for (int i0 = tid; i0 < tot; i0 += FZ_T * 8) {
+      uint4 v[8];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if (s < KP0 / 32) {
-        float v[8];
-        for (int j = 0; j < 8; ++j) v[j] = (r < P.Ne) ? feature_value(P, FA, r, s * 32 + kb + j) : 0.0f;
-        af[s] = pack8(v);
+      for (int u = 0; u < 8; ++u) {
+        const int i = min(i0 + FZ_T * u, tot - 1);
+        const int n = i / KC, kc = i - n * KC;
+        v[u] = *reinterpret_cast<const uint4*>(W + F.wg[l] + n * KP + kc * 8);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + FZ_T * u;
+        if (i < tot) {
+          const int n = i / KC, kc = i - n * KC;
+          *reinterpret_cast<uint4*>(sW + F.ws[l] + n * (KP + 8) + kc * 8) = v[u];
+        }
       }
     }
+    for (int i = tid; i < NP; i += FZ_T) sB[F.bo[l] + i] = bias[F.bo[l] + i];
+  }
+  const int64_t ntiles = (P.Ne + 15) / 16;
+  const int kb = (lane >> 4) * 8;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * 16;
+    // layer 0 input: the features of the tile's 16 elements, BF16, all threads
+    const int KP0 = F.kp[0];
+    for (int i = tid; i < 16 * KP0; i += FZ_T) {
+      const int r = i / KP0, f = i - r * KP0;
+      const int64_t e = row0 + r;
+      sA[0][r][f] = f2bf(e < P.Ne ? feature_value(P, FA, e, f) : 0.0f);
+    }
+    __syncthreads();  // the weights (first tile) and the features are in place
     for (int l = 0; l < F.nl; ++l) {
       const int KP = F.kp[l], NP = F.np[l];
       const bool last = l == F.nl - 1;
       const uint16_t* Wl = sW + F.ws[l];
-      for (int t = 0; t < NP / 16; ++t) {
+      const int cur = l & 1;
+      bf16x8 af[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (s < KP / 32) af[s] = *reinterpret_cast<const bf16x8*>(&sA[cur][lane & 15][s * 32 + kb]);
+      for (int t = wave; t < NP / 16; t += FZ_T / 64) {
         const int n = t * 16 + (lane & 15);
         f32x4 acc = {0, 0, 0, 0};
 #pragma unroll
@@ -345,16 +360,11 @@ __global__ void __launch_bounds__(256) k_guess_fused(const KParams P, const Feat
             const int64_t rr = row0 + rl;
             if (rr < P.Ne && n < ld_out) pred[rr * ld_out + n] = z;
           } else {
-            sA[wave][rl][n] = f2bf(gelu(z));
+            sA[cur ^ 1][rl][n] = f2bf(gelu(z));
           }
         }
       }
-      if (last) break;
-      __syncthreads();  // the wave's activation tile is complete
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        if (s < NP / 32) af[s] = *reinterpret_cast<const bf16x8*>(&sA[wave][lane & 15][s * 32 + kb]);
-      __syncthreads();  // read before the next layer overwrites it
+      __syncthreads();  // the next layer's input is complete, this layer's is no longer read
     }
   }
 }
@@ -573,9 +583,10 @@ int ilh_guess_mlp_fused(ilh_ctx* c, const ilh_guess_model* m, const double* u, c
   if ((reinterpret_cast<uintptr_t>(m->W) & 15) != 0) return fail(c, ILH_EINVAL, "fused guess MLP: W not 16-byte aligned");
   const FeatArgs fa{u, m->with_base ? base : nullptr, m->vscale, m->escale, m->xscale, m->kvscale, m->kescale,
                     m->mu, m->sd};
-  const int64_t ntiles = (c->Ne + 63) / 64;
+  // one work-group per compute unit at most (the LDS holds one), each walking several tiles
+  const int64_t ntiles = (c->Ne + 15) / 16;
   const unsigned nb = (unsigned)std::min<int64_t>(ntiles, 256);
-  hipLaunchKernelGGL(k_guess_fused, dim3(nb), dim3(256), 0, c->stream, c->kp, fa, F, m->W, m->b, pred, ld);
+  hipLaunchKernelGGL(k_guess_fused, dim3(nb), dim3(FZ_T), 0, c->stream, c->kp, fa, F, m->W, m->b, pred, ld);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
   ILH_CATCH(c)

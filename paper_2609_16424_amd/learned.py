@@ -488,8 +488,12 @@ def main(argv=None):
         dt = a.cfl_factor * h.dt_estimate(u, 0.5)
         for _ in range(3):
             lg.guess(u, [], 0.5 * dt)
+        base = h.plain_guess(u, [], 0.5 * dt)
+        for _ in range(3):  # the same network output through the features and layer-by-layer kernels
+            lg.predict_layered(u, base)
         torch.cuda.synchronize()
-        log("inference: 3 learned guesses on %d elements" % h.Ne)
+        log("inference: 3 learned guesses (fused network launch) and 3 layer-by-layer forwards on %d elements"
+            % h.Ne)
         return
     if a.cmd == "probe":
         h = make_triple(a.nx, a.ny, a.order, seed=None)

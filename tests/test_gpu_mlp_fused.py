@@ -2,9 +2,9 @@
 every MLP layer in one kernel, BF16 weights and biases held in LDS) against the features kernel
 followed by the layer-by-layer MFMA forward.  Both round the same operands to BF16, accumulate
 in the same order and apply the same epilogue, so the outputs must agree bit for bit; the cases
-cover one partial tile of 64 elements, many tiles with a partial last one, the base block and
+cover a few tiles of 16 elements, many tiles with a partial last one, the base block and
 the standardisation on or off, two to four layers (padded widths the layered forward takes), and
-the committed trained model on a triple-point state (84 tiles)."""
+the committed trained model on a triple-point state (336 tiles)."""
 import os
 
 import numpy as np
