@@ -167,29 +167,31 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
 // W = 2 (FP32, small meshes): the two waves of a work-group share the strip, each takes half
 // of the quadrature rows; the gathers and the node sums are spread over both, which halves the
 // wave's chain of dependent row steps where the one-wave grid leaves most SIMDs idle.
-template <int D1D, int Q1D, typename T, int VISC, int SRC, typename TO, int W>
+template <int D1D, int Q1D, typename T, int VISC, int SRC, typename TO, int W, bool R1>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VISC && sizeof(T) == 8 ? 1 : 2))) k_jvp2d_q(const KParams P, const Tab2<T, D1D, Q1D> tb,
                                                 const T* __restrict__ dk, const T* __restrict__ qd,
                                                 int64_t qs, double tau_, TO* __restrict__ out, int R,
                                                 const double* __restrict__ tau_dev,
                                                 const double* __restrict__ skip) {
-  if (skip && *skip != 0.0) return;  // the Krylov cycle ended at the previous step
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
   constexpr int NQD = LinLayout<2, VISC, SRC>::NQD;
+  // node groups: GS lanes hold the NS nodes of one strip row (31 for Q3, 33 for Q2 strips)
+  constexpr int GS = NS <= 32 ? 32 : 64;
   constexpr int NVO = 2 * D1D * D1D;  // velocity outputs per element (energy: NLD < NVO, later)
   constexpr int NOP = NVO | 1;        // odd LDS row length (bank spread)
   static_assert(Q1D % W == 0, "the quadrature rows split evenly over the waves");
   constexpr int NT = 64 * W;          // threads of the work-group
   constexpr int QW = Q1D / W;         // quadrature rows per wave
 
-  __shared__ T sS[4][D1D][NS];  // dkx0 dkx1 dkv0 dkv1 strips
+  __shared__ T sS[4][D1D][GS];  // dkx0 dkx1 dkv0 dkv1 strips (rows padded to the node group)
   __shared__ T sE[EPW * NLD];   // dk_e
   __shared__ T sO[W][64][NOP];  // per-lane contributions to the element's outputs (velocity, then energy)
   __shared__ T sC[2][2][NS];    // carried velocity sums of node row K (parity of the element row)
   __shared__ T sBG[2][Q1D][D1D];
   __shared__ T sBLt[Q1D][L1D];
+  __shared__ T sW[Q1D];
 
   const int tid = threadIdx.x, hw = W == 1 ? 0 : tid / 64, lane = tid - 64 * hw;
   const uint32_t tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -202,15 +204,13 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
   const uint32_t N = (uint32_t)P.N, nh1 = 2 * N;
   const T tau = T(tau_dev ? *tau_dev : tau_);
   const bool last_x = (ex0 + E == nx);
-  const int ey0 = sy * R, ey1 = min(ey0 + R, ny);
+  const int ey0 = sy * R, ey1 = R1 ? ey0 + 1 : min(ey0 + R, ny);
   const int z = lane / Q1D, qx = lane - z * Q1D;
   const bool active = z < E;
-
-  for (int i = tid; i < Q1D * D1D; i += NT) {
-    sBG[0][i / D1D][i % D1D] = tb.B[i / D1D][i % D1D];
-    sBG[1][i / D1D][i % D1D] = tb.G[i / D1D][i % D1D];
-  }
-  for (int i = tid; i < Q1D * L1D; i += NT) sBLt[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
+  constexpr int NG = NT / GS, PG = 4 * D1D / NG;
+  static_assert(4 % NG == 0 || NG % 4 == 0, "node groups split the four fields evenly");
+  const int gs = tid % GS, gg = tid / GS;
+  const int sn = min(gs, ns - 1);  // this lane's node of the strip row (clamped)
 
 #pragma unroll 1
   for (int ey = ey0; ey < ey1; ++ey) {
@@ -219,32 +219,45 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
     const uint32_t ebase = (uint32_t)ey * nx + ex0;
     const uint32_t row0 = (uint32_t)(K * ey) * ng0 + (uint32_t)(K * ex0);  // first node of the strip
 
-    constexpr int NTS = 4 * D1D * NS, RT = (NTS + NT - 1) / NT;
     constexpr int NLS = EPW * NLD, RL = (NLS + NT - 1) / NT;
-    // branch-free gathers: lanes past the strip re-read its last node (their LDS slots feed no
-    // output), so all loads of the element row are in flight together
-    T tr[RT], lr[RL];
+    // branch-free gathers, one node of the strip per lane of a node group (GS lanes); pass p
+    // of group g reads field f = g + NG p mod 4 (x0 x1 v0 v1 at f N) of node row (NG p) / 4,
+    // so every address is the lane's base plus a per-pass scalar.  Lanes past the strip re-read
+    // its last node (their LDS slots feed no output): all loads of the element row are in
+    // flight together.
+    T tr[PG], lr[RL];
+    const uint32_t gbase = (uint32_t)gg * N + row0 + (uint32_t)sn;
 #pragma unroll
-    for (int q = 0; q < RT; ++q) {
-      const int i = tid + NT * q, si = min(i % NS, ns - 1), t = min(i / NS, 4 * D1D - 1), b = t % D1D,
-                f = t / D1D;
-      tr[q] = ld32(dk, (f < 2 ? f * N : nh1 + (f - 2) * N) + row0 + (uint32_t)b * ng0 + si);
+    for (int p = 0; p < PG; ++p) {
+      const int fo = (NG * p) & 3, bo = (NG * p) >> 2;
+      tr[p] = ld32(dk, gbase + (uint32_t)fo * N + (uint32_t)bo * ng0);
     }
 #pragma unroll
     for (int q = 0; q < RL; ++q) lr[q] = ld32(dk, 2 * nh1 + ebase * NLD + min(tid + NT * q, E * NLD - 1));
     const double rj_l = P.rj0[ebase + (active ? z : 0)];
-    __syncthreads();  // the previous element row's readers of sS, sE and sO are done
+    if (r == 0) {
+      // the end-of-cycle flag is read while the first gathers are in flight (loads of a
+      // launch that then returns are harmless), then the 1D tables go to LDS
+      if (skip && *skip != 0.0) return;  // the Krylov cycle ended at the previous step
+      for (int i = tid; i < Q1D * D1D; i += NT) {
+        sBG[0][i / D1D][i % D1D] = tb.B[i / D1D][i % D1D];
+        sBG[1][i / D1D][i % D1D] = tb.G[i / D1D][i % D1D];
+      }
+      for (int i = tid; i < Q1D * L1D; i += NT) sBLt[i / L1D][i % L1D] = tb.BL[i / L1D][i % L1D];
+      if (tid < Q1D) sW[tid] = tb.W[tid];
+    }
+    lds_barrier();  // the previous element row's readers of sS, sE and sO are done
 #pragma unroll
-    for (int q = 0; q < RT; ++q) {
-      const int i = tid + NT * q;
-      if (i < NTS) (&sS[0][0][0])[i] = tr[q];
+    for (int p = 0; p < PG; ++p) {
+      const int fo = (NG * p) & 3, bo = (NG * p) >> 2;
+      (&sS[0][0][0])[(gg * D1D) * GS + gs + (fo * D1D + bo) * GS] = tr[p];
     }
 #pragma unroll
     for (int q = 0; q < RL; ++q) {
       const int i = tid + NT * q;
       if (i < NLS) sE[i] = lr[q];
     }
-    __syncthreads();
+    lds_barrier();
 
     T TL[L1D];  // energy sums of the lane's column
 #pragma unroll
@@ -287,7 +300,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int b = 0; b < D1D; ++b) T0[c][b] = T1[c][b] = T(0);
-      const T wx = tb.W[qx] * T(rj_l);
+      const T wx = sW[qx] * T(rj_l);
       // coefficient rows of this element row: field f at qd[((blk Q1D + qy) NQD + f) 64 + lane]
       const T* __restrict__ qb = qd + ((int64_t)ey * gridDim.x + sx) * (Q1D * NQD * 64);
       auto ldrow = [&](const int qy, T* cf) {
@@ -370,68 +383,102 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
           for (int a = 0; a < D1D; ++a)
             sO[hw][lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
     }
-    __syncthreads();
+    vm_drained();  // every load is consumed and no store is issued yet
+    lds_barrier();
 
     // node rows of the strip: position rows (dk_x - tau dk_v) and constrained velocity rows
     // (dk_v) by the node's single owner; every other velocity row sums the Q1D columns of the
-    // (one or two) elements of the strip that hold the node
+    // (one or two) elements of the strip that hold the node.  Lane gs of node group g takes
+    // node gs of the rows (component c, node row b) = ((g + NG p) mod 2, (g + NG p) / 2) over
+    // the passes p: the LDS and global addresses are per-lane bases plus per-pass constants.
+    // All LDS reads are issued before the first sum (clamped addresses; the terms a node does
+    // not have are dropped by selection), then the stores and atomics follow.
     T* const cw = &sC[r & 1][0][0];
     const T* const cr = &sC[(r + 1) & 1][0][0];
-#pragma unroll 1
-    for (int i = tid; i < 2 * D1D * NS; i += NT) {
-      const int s = i % NS, t = i / NS, b = t % D1D, c = t / D1D;
-      if (s >= ns) continue;
-      const uint32_t I = K * ex0 + s, J = K * ey + b;
-      const uint32_t gi = c * N + row0 + (uint32_t)b * ng0 + s;
-      const bool own = (s < K * E || last_x) && (b < K || last_y);
-      const T dkv = sS[2 + c][b][s];
-      if (own) out[gi] = TO(sS[c][b][s] - tau * dkv);
-      const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
-      if (cons) {
-        if (own) out[nh1 + gi] = TO(dkv);
-        continue;
-      }
-      const int zz = s / K, a = s - K * zz;
-      T f = T(0);
-      if (zz < E) {
+    constexpr int NCB = 2 * D1D, PN = NCB / NG;
+    static_assert(NCB % NG == 0, "node groups split the (component, node row) pairs evenly");
+    int tn = gs, gn = gg;  // lane constants of the node phase, not held through the row loop
+    asm volatile("" : "+v"(tn), "+v"(gn));
+    // pass p of group g: component c = lc + cp(p), node row b = lb + bp(p)
+    const int lc = NG == 1 ? 0 : (gn & 1), lb = NG <= 2 ? 0 : (gn >> 1);
+    const int zz = tn / K, a = tn - K * zz, sc = min(tn, ns - 1);
+    const bool left = zz < E, shared = a == 0 && zz > 0;
+    const int oR = min(zz, E - 1) * Q1D * NOP + lc * D1D * D1D + lb * D1D + a;
+    const int oL = max(zz - 1, 0) * Q1D * NOP + lc * D1D * D1D + lb * D1D + K;
+    const int oS = (lc * D1D + lb) * GS + sc;
+    const T* const sOf = &sO[0][0][0];
+    const T* const sSf = &sS[0][0][0];
+    T fv[PN], xv[PN], vv[PN];
 #pragma unroll
-        for (int h = 0; h < W; ++h)
+    for (int p = 0; p < PN; ++p) {
+      const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : (NG / 2) * p;
+      const int po = cp * D1D * D1D + bp * D1D;
+      T f0 = T(0), f1 = T(0);
 #pragma unroll
-          for (int q = 0; q < Q1D; ++q) f += sO[h][zz * Q1D + q][c * D1D * D1D + b * D1D + a];
-      }
-      if (a == 0 && zz > 0) {
+      for (int h = 0; h < W; ++h)
 #pragma unroll
-        for (int h = 0; h < W; ++h)
+        for (int q = 0; q < Q1D; ++q) {
+          f0 += sOf[oR + po + (h * 64 + q) * NOP];
+          f1 += sOf[oL + po + (h * 64 + q) * NOP];
+        }
+      fv[p] = (left ? f0 : T(0)) + (shared ? f1 : T(0));
+      xv[p] = sSf[oS + (cp * D1D + bp) * GS];
+      vv[p] = sSf[oS + (cp * D1D + bp) * GS + 2 * D1D * GS];
+    }
+    const uint32_t I = K * ex0 + tn;
+    const bool consI = I == 0 || I == ng0 - 1, own_s = tn < K * E || last_x;
+    const uint32_t gb = (uint32_t)lc * N + (uint32_t)lb * ng0 + row0 + tn;
+    if (tn < ns) {
 #pragma unroll
-          for (int q = 0; q < Q1D; ++q) f += sO[h][(zz - 1) * Q1D + q][c * D1D * D1D + b * D1D + K];
+      for (int p = 0; p < PN; ++p) {
+        const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : (NG / 2) * p;
+        const int c = lc + cp, b = lb + bp;
+        const uint32_t gi = gb + (uint32_t)cp * N + (uint32_t)bp * ng0;
+        const bool own = own_s && (b < K || last_y);
+        const T dkv = vv[p];
+        if (own) out[gi] = TO(xv[p] - tau * dkv);
+        const uint32_t J = K * ey + b;
+        const bool cons = (c == 0) ? consI : (J == 0 || J == ng1 - 1);
+        if (cons) {
+          if (own) out[nh1 + gi] = TO(dkv);
+          continue;
+        }
+        T f = fv[p];
+        if (b == K && !last_y && ey + 1 < ey1) {  // completed by the next element row of this wave
+          cw[c * NS + tn] = f;
+          continue;
+        }
+        if (b == 0 && r > 0) f += cr[c * NS + tn];
+        // atomics also where no other wave adds to the node: plain stores of the partial cache
+        // lines of a strip cost more than the atomic updates on this chip
+        unsafeAtomicAdd(&out[nh1 + gi], TO(f));
       }
-      if (b == K && !last_y && ey + 1 < ey1) {  // completed by the next element row of this wave
-        cw[c * NS + s] = f;
-        continue;
-      }
-      if (b == 0 && r > 0) f += cr[c * NS + s];
-      // atomics also where no other wave adds to the node: plain stores of the partial cache
-      // lines of a strip cost more than the atomic updates on this chip
-      unsafeAtomicAdd(&out[nh1 + gi], TO(f));
     }
     // energy rows (element-owned): the column sums go through sO once the velocity is done
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
       for (int bl = 0; bl < L1D; ++bl)
 #pragma unroll
         for (int al = 0; al < L1D; ++al) sO[hw][lane][bl * L1D + al] = sBLt[qx][al] * TL[bl];
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int i = tid; i < E * NLD; i += NT) {
-      const int zz = i / NLD, t = i % NLD;
+    lds_barrier();
+    constexpr int NET = EPW * NLD, NE = (NET + NT - 1) / NT;
+    T ev[NE];
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int i = min(tid + NT * it, E * NLD - 1), zz = i / NLD, t = i % NLD;
       T o = 0;
 #pragma unroll
       for (int h = 0; h < W; ++h)
 #pragma unroll
         for (int q = 0; q < Q1D; ++q) o += sO[h][zz * Q1D + q][t];
-      out[2 * nh1 + ebase * NLD + i] = TO(o);
+      ev[it] = o;
+    }
+#pragma unroll
+    for (int it = 0; it < NE; ++it) {
+      const int i = tid + NT * it;
+      if (i < E * NLD) out[2 * nh1 + ebase * NLD + i] = TO(ev[it]);
     }
   }
 }
@@ -502,15 +549,18 @@ static void apply_t(ilh_ctx* c, const T* dk, const T* qd, TO* out, const double*
   constexpr int D1D = K + 1, Q1D = 2 * K;
   const int R = apply_rows(c);
   const dim3 g = lin2d_grid(c), grid(g.x, (g.y + R - 1) / R);
+  // one element row per wave: the kernel instance without the row loop
   if constexpr (sizeof(T) == 4) {
     if (apply_waves(c, true) == 2) {
-      klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 2>, grid, dim3(128), 0, c->kp, make_tab2<T, D1D, Q1D>(c),
-              dk, qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev, skip);
+      klaunch(c, R == 1 ? k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 2, true> : k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 2, false>,
+              grid, dim3(128), 0, c->kp, make_tab2<T, D1D, Q1D>(c), dk, qd, lin2d_stride(c), c->lin_tau, out, R,
+              tau_dev, skip);
       return;
     }
   }
-  klaunch(c, k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 1>, grid, dim3(64), 0, c->kp, make_tab2<T, D1D, Q1D>(c), dk,
-          qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev, skip);
+  klaunch(c, R == 1 ? k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 1, true> : k_jvp2d_q<D1D, Q1D, T, VISC, SRC, TO, 1, false>,
+          grid, dim3(64), 0, c->kp, make_tab2<T, D1D, Q1D>(c), dk, qd, lin2d_stride(c), c->lin_tau, out, R, tau_dev,
+          skip);
 }
 
 template <typename T>

@@ -309,6 +309,21 @@ __device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i) {
   return *(const T __attribute__((address_space(1)))*)p;
 }
 
+// Work-group barrier ordering LDS only: its release and acquire fences name the local address
+// space, so a wave's global stores and atomics still in flight are not drained first (the
+// fences of __syncthreads cover global memory too and wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Wait for every vector memory operation of the wave.  Placed where all loads have been
+// consumed and no store has been issued, it costs nothing and tells the compiler's wait
+// insertion that no load is pending, so later register reuse does not wait on the stores
+// and atomics issued after it.
+__device__ __forceinline__ void vm_drained() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Work-group -> tile map for a chip of 8 XCDs, each with its own L2: work-groups are handed to
 // the XCDs in turn (w mod 8), so neighbouring tiles would sit on different L2s and the cache
 // lines they share (node rows at strip ends, the direction's overlapping strips) would be
