@@ -362,13 +362,19 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
       const int q0 = hw * QW, q1 = q0 + QW;
       T ca[NQD], cb[NQD];
       ldrow(q0, ca);
-#pragma unroll 1
-      for (int qy = q0; qy < q1; qy += 2) {
+      auto pass = [&](const int qy) {
         constexpr bool ODD = QW % 2 != 0;  // the last pass of an odd count has one row
         if (!ODD || qy + 1 < q1) ldrow(qy + 1, cb);
         row(qy, ca);
         if (qy + 2 < q1) ldrow(qy + 2, ca);
         if (!ODD || qy + 1 < q1) row(qy + 1, cb);
+      };
+      if constexpr (R1 && W == 1) {  // straight-line rows (the multi-row instance keeps the loop)
+#pragma unroll
+        for (int qy = 0; qy < Q1D; qy += 2) pass(qy);
+      } else {
+#pragma unroll 1
+        for (int qy = q0; qy < q1; qy += 2) pass(qy);
       }
 #pragma unroll
       for (int a = 0; a < D1D; ++a) {  // reloaded: not kept live through the row loop
