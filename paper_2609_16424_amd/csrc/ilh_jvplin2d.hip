@@ -235,6 +235,14 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
 #pragma unroll
     for (int q = 0; q < RL; ++q) lr[q] = ld32(dk, 2 * nh1 + ebase * NLD + min(tid + NT * q, E * NLD - 1));
     const double rj_l = P.rj0[ebase + (active ? z : 0)];
+    // coefficient rows of this element row: field f at qd[((blk Q1D + qy) NQD + f) 64 + lane]
+    const T* __restrict__ qb = qd + ((int64_t)ey * gridDim.x + sx) * (Q1D * NQD * 64);
+    auto ldrow = [&](const int qy, T* cf) {
+      const T* rb = sbase(qb + qy * (NQD * 64));
+#pragma unroll
+      for (int f = 0; f < NQD; ++f) cf[f] = ld32(rb, (uint32_t)(f * 64 + lane));
+    };
+    T ca[NQD], cb[NQD];
     if (r == 0) {
       // the end-of-cycle flag is read while the first gathers are in flight (loads of a
       // launch that then returns are harmless), then the 1D tables go to LDS
@@ -301,13 +309,6 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
 #pragma unroll
         for (int b = 0; b < D1D; ++b) T0[c][b] = T1[c][b] = T(0);
       const T wx = sW[qx] * T(rj_l);
-      // coefficient rows of this element row: field f at qd[((blk Q1D + qy) NQD + f) 64 + lane]
-      const T* __restrict__ qb = qd + ((int64_t)ey * gridDim.x + sx) * (Q1D * NQD * 64);
-      auto ldrow = [&](const int qy, T* cf) {
-        const T* rb = sbase(qb + qy * (NQD * 64));
-#pragma unroll
-        for (int f = 0; f < NQD; ++f) cf[f] = ld32(rb, (uint32_t)(f * 64 + lane));
-      };
       auto row = [&](const int qy, const T* cf) {
         // tau is folded into the coefficients: the contractions enter unscaled
         T dJ[2][2], dGv[2][2], dkv[2];
@@ -360,7 +361,6 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
       // this wave's quadrature rows [q0, q0 + QW); two coefficient buffers: the loads of one
       // row are in flight during the other's arithmetic
       const int q0 = hw * QW, q1 = q0 + QW;
-      T ca[NQD], cb[NQD];
       ldrow(q0, ca);
       auto pass = [&](const int qy) {
         constexpr bool ODD = QW % 2 != 0;  // the last pass of an odd count has one row
@@ -410,7 +410,8 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
     const int zz = tn / K, a = tn - K * zz, sc = min(tn, ns - 1);
     const bool left = zz < E, shared = a == 0 && zz > 0;
     const int oR = min(zz, E - 1) * Q1D * NOP + lc * D1D * D1D + lb * D1D + a;
-    const int oL = max(zz - 1, 0) * Q1D * NOP + lc * D1D * D1D + lb * D1D + K;
+    int oL = max(zz - 1, 0) * Q1D * NOP + lc * D1D * D1D + lb * D1D + K;
+    asm volatile("" : "+v"(oL));  // its own base (not oR minus a constant): immediate LDS offsets
     const int oS = (lc * D1D + lb) * GS + sc;
     const T* const sOf = &sO[0][0][0];
     const T* const sSf = &sS[0][0][0];
@@ -419,20 +420,20 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
     for (int p = 0; p < PN; ++p) {
       const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : (NG / 2) * p;
       const int po = cp * D1D * D1D + bp * D1D;
-      T f0 = T(0), f1 = T(0);
+      T f0 = sOf[oR + po], f1 = sOf[oL + po];
 #pragma unroll
-      for (int h = 0; h < W; ++h)
-#pragma unroll
-        for (int q = 0; q < Q1D; ++q) {
-          f0 += sOf[oR + po + (h * 64 + q) * NOP];
-          f1 += sOf[oL + po + (h * 64 + q) * NOP];
-        }
+      for (int hq = 1; hq < W * Q1D; ++hq) {
+        const int h = hq / Q1D, q = hq % Q1D;
+        f0 += sOf[oR + po + (h * 64 + q) * NOP];
+        f1 += sOf[oL + po + (h * 64 + q) * NOP];
+      }
       fv[p] = (left ? f0 : T(0)) + (shared ? f1 : T(0));
       xv[p] = sSf[oS + (cp * D1D + bp) * GS];
       vv[p] = sSf[oS + (cp * D1D + bp) * GS + 2 * D1D * GS];
     }
     const uint32_t I = K * ex0 + tn;
     const bool consI = I == 0 || I == ng0 - 1, own_s = tn < K * E || last_x;
+    const bool cI = lc == 0 && consI, isv = lc != 0;  // constrained-row tests of the lane's component
     const uint32_t gb = (uint32_t)lc * N + (uint32_t)lb * ng0 + row0 + tn;
     if (tn < ns) {
 #pragma unroll
@@ -442,22 +443,19 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
         const uint32_t gi = gb + (uint32_t)cp * N + (uint32_t)bp * ng0;
         const bool own = own_s && (b < K || last_y);
         const T dkv = vv[p];
-        if (own) out[gi] = TO(xv[p] - tau * dkv);
         const uint32_t J = K * ey + b;
-        const bool cons = (c == 0) ? consI : (J == 0 || J == ng1 - 1);
-        if (cons) {
-          if (own) out[nh1 + gi] = TO(dkv);
-          continue;
-        }
+        const bool consJ = J == 0 || J == ng1 - 1;
+        const bool cons = NG == 1 ? (cp == 0 ? consI : consJ) : (cI || (isv && consJ));
+        // node row K completed by the next element row of this wave
+        const bool carry = !R1 && b == K && !last_y && ey + 1 < ey1;
         T f = fv[p];
-        if (b == K && !last_y && ey + 1 < ey1) {  // completed by the next element row of this wave
-          cw[c * NS + tn] = f;
-          continue;
-        }
-        if (b == 0 && r > 0) f += cr[c * NS + tn];
+        if (!R1 && b == 0 && r > 0) f += cr[c * NS + tn];
+        if (own) st32(out, gi, TO(xv[p] - tau * dkv));
+        if (cons && own) st32(out, nh1 + gi, TO(dkv));
+        if (!cons && carry) cw[c * NS + tn] = f;
         // atomics also where no other wave adds to the node: plain stores of the partial cache
         // lines of a strip cost more than the atomic updates on this chip
-        unsafeAtomicAdd(&out[nh1 + gi], TO(f));
+        if (!cons && !carry) atomic_add32(out, nh1 + gi, TO(f));
       }
     }
     // energy rows (element-owned): the column sums go through sO once the velocity is done
@@ -484,7 +482,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
 #pragma unroll
     for (int it = 0; it < NE; ++it) {
       const int i = tid + NT * it;
-      if (i < E * NLD) out[2 * nh1 + ebase * NLD + i] = TO(ev[it]);
+      if (i < E * NLD) st32(out, 2 * nh1 + ebase * NLD + i, TO(ev[it]));
     }
   }
 }

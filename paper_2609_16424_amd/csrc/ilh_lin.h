@@ -309,6 +309,19 @@ __device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i) {
   return *(const T __attribute__((address_space(1)))*)p;
 }
 
+// Store and no-return atomic add at a 32-bit element offset from a uniform base (the
+// scalar-base + vector-offset forms; byte offsets below 4 GiB, checked on the host).
+typedef char __attribute__((address_space(1))) * gbytes_w;
+template <typename T>
+__device__ __forceinline__ void st32(T* __restrict__ base, uint32_t i, T v) {
+  *(T __attribute__((address_space(1)))*)((gbytes_w)base + (uint64_t)(i * (uint32_t)sizeof(T))) = v;
+}
+template <typename T>
+__device__ __forceinline__ void atomic_add32(T* base, uint32_t i, T v) {
+  __hip_atomic_fetch_add((T __attribute__((address_space(1)))*)((gbytes_w)base + (uint64_t)(i * (uint32_t)sizeof(T))), v,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Work-group barrier ordering LDS only: its release and acquire fences name the local address
 // space, so a wave's global stores and atomics still in flight are not drained first (the
 // fences of __syncthreads cover global memory too and wait for them).
