@@ -39,9 +39,20 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
   constexpr int NNE = 2 * D1D * NS, RG = (NNE + 63) / 64;  // node entries (c, b, s) of the strip
   constexpr int NLS = EPW * NLD, RL = (NLS + 63) / 64;
 
-  __shared__ double sW[6][D1D][NS];  // w_x (2), w_v (2), k_v (2)
-  __shared__ double sE[2][NLS];      // w_e, k_e
-  __shared__ double sO[64][NOP];     // per-lane contributions (velocity, then energy)
+  // The gathered strips are read by the xi-contractions only, the per-lane contributions are
+  // written after the quadrature rows: one LDS block serves both (the wave's LDS operations
+  // complete in program order), which keeps a C2-sized grid resident in one round.
+  union StripLds {
+    struct {
+      double W[6][D1D][NS];  // w_x (2), w_v (2), k_v (2)
+      double E[2][NLS];      // w_e, k_e
+    } in;
+    double O[64][NOP];  // per-lane contributions (velocity, then energy)
+  };
+  __shared__ StripLds sm;
+  auto& sW = sm.in.W;
+  auto& sE = sm.in.E;
+  auto& sO = sm.O;
   __shared__ double sBG[2][Q1D][D1D];
   __shared__ double sBLt[Q1D][L1D];
 
@@ -115,7 +126,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
       sE[1][i] = gke[q];
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   double TL[L1D];
 #pragma unroll
@@ -225,6 +236,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
       Bq[a] = sBG[0][qx][a];
       Gq[a] = sBG[1][qx][a];
     }
+    asm volatile("" ::: "memory");  // sO overlays the strips read above: keep the order
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -233,7 +245,8 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
         for (int a = 0; a < D1D; ++a)
           sO[lane][c * D1D * D1D + b * D1D + a] = Gq[a] * T0[c][b] + Bq[a] * T1[c][b];
   }
-  __syncthreads();
+  vm_drained();  // every load is consumed; the position-row stores were issued long before
+  lds_barrier();
   if (dmin) {  // the work-group's smallest det J of the stage positions w_x
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dm = nan_min(dm, __shfl_xor(dm, o, 64));
@@ -241,42 +254,70 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
   }
 
   // velocity rows that are not constrained: the Q1D columns of the (one or two) elements of the
-  // strip that hold the node, one atomic add per node and strip
-#pragma unroll 1
-  for (int i = lane; i < NNE; i += 64) {
-    const int s = i % NS, t = i / NS, b = t % D1D, c = t / D1D;
-    if (s >= ns) continue;
-    const uint32_t I = K * ex0 + s, J = K * ey + b;
-    const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
-    if (cons) continue;
-    const int zz = s / K, a = s - K * zz;
-    double f = 0.0;
-    if (zz < E) {
+  // strip that hold the node, one atomic add per node and strip.  Lane gs of half g takes node
+  // gs of the rows (component g, node row p): per-lane LDS bases plus per-pass constants, all
+  // LDS reads issued before the first sum.
+  {
+    constexpr int GS = NS <= 32 ? 32 : 64, NG = 64 / GS, PN = 2 * D1D / NG;
+    int tn = lane % GS, gn = lane / GS;
+    asm volatile("" : "+v"(tn), "+v"(gn));
+    const int lc = NG == 1 ? 0 : gn;
+    const int zz = tn / K, a = tn - K * zz;
+    const bool left = zz < E, shared = a == 0 && zz > 0;
+    const int oR = min(zz, E - 1) * Q1D * NOP + lc * D1D * D1D + a;
+    int oL = max(zz - 1, 0) * Q1D * NOP + lc * D1D * D1D + K;
+    asm volatile("" : "+v"(oL));
+    const double* const sOf = &sO[0][0];
+    double fv[PN];
 #pragma unroll
-      for (int q = 0; q < Q1D; ++q) f += sO[zz * Q1D + q][c * D1D * D1D + b * D1D + a];
-    }
-    if (a == 0 && zz > 0) {
+    for (int p = 0; p < PN; ++p) {
+      const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : p;
+      const int po = cp * D1D * D1D + bp * D1D;
+      double f0 = sOf[oR + po], f1 = sOf[oL + po];
 #pragma unroll
-      for (int q = 0; q < Q1D; ++q) f += sO[(zz - 1) * Q1D + q][c * D1D * D1D + b * D1D + K];
+      for (int q = 1; q < Q1D; ++q) {
+        f0 += sOf[oR + po + q * NOP];
+        f1 += sOf[oL + po + q * NOP];
+      }
+      fv[p] = (left ? f0 : 0.0) + (shared ? f1 : 0.0);
     }
-    unsafeAtomicAdd(&r[nh1 + c * N + row0 + (uint32_t)b * ng0 + s], f);
+    const uint32_t I = K * ex0 + tn;
+    const bool cI = lc == 0 && (I == 0 || I == ng0 - 1), isv = lc != 0;
+    const uint32_t gb = nh1 + (uint32_t)lc * N + row0 + tn;
+    if (tn < ns) {
+#pragma unroll
+      for (int p = 0; p < PN; ++p) {
+        const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : p;
+        const uint32_t J = K * ey + bp;
+        const bool consJ = J == 0 || J == ng1 - 1;
+        const bool cons = NG == 1 ? (cp == 0 ? (I == 0 || I == ng0 - 1) : consJ) : (cI || (isv && consJ));
+        if (!cons) atomic_add32(r, gb + (uint32_t)cp * N + (uint32_t)bp * ng0, fv[p]);
+      }
+    }
   }
   // energy rows (element-owned): the column sums go through sO once the velocity is done
-  __syncthreads();
+  lds_barrier();
   if (active) {
 #pragma unroll
     for (int bl = 0; bl < L1D; ++bl)
 #pragma unroll
       for (int al = 0; al < L1D; ++al) sO[lane][bl * L1D + al] = sBLt[qx][al] * TL[bl];
   }
-  __syncthreads();
-#pragma unroll 1
-  for (int i = lane; i < E * NLD; i += 64) {
-    const int zz = i / NLD, t = i % NLD;
-    double o = 0;
+  lds_barrier();
+  constexpr int NE = (NLS + 63) / 64;
+  double ev[NE];
 #pragma unroll
-    for (int q = 0; q < Q1D; ++q) o += sO[zz * Q1D + q][t];
-    r[2 * nh1 + ebase * NLD + i] = o;
+  for (int it = 0; it < NE; ++it) {
+    const int i = min(lane + 64 * it, E * NLD - 1), zz = i / NLD, t = i % NLD;
+    double o = sO[zz * Q1D][t];
+#pragma unroll
+    for (int q = 1; q < Q1D; ++q) o += sO[zz * Q1D + q][t];
+    ev[it] = o;
+  }
+#pragma unroll
+  for (int it = 0; it < NE; ++it) {
+    const int i = lane + 64 * it;
+    if (i < E * NLD) st32(r, 2 * nh1 + ebase * NLD + i, ev[it]);
   }
 }
 
