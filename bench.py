@@ -49,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
 TRAFFIC_SOURCE_END = {"paper_2609_16424_amd/csrc/ilh_internal.h": b"struct ilh_ctx {"}
-TRAFFIC_RECORD = {"sha256": "e56a4e69ae18feca1a9a9df8a15daac37a655f9c875adff8ab7aef3965ded388",
+TRAFFIC_RECORD = {"sha256": "66f3785848d2f0a82998954cd41e7faef9dea69999fa46fec236ca0afad50095",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16579.5, "fetch_scale": 262144.0 / 131079.29,
-                  "write_kib": 3837.9, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 16607.8, "fetch_scale": 262144.0 / 131079.27,
+                  "write_kib": 3704.4, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
@@ -71,7 +71,7 @@ def sources_sha256():
 # VALU instructions per launch of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU, same sources):
 # the issue peak of wave64 FP32 (unpacked) / FP64 VALU instructions is 1024 SIMDs x 2.4 GHz / 4.
 VALU_RECORD = {"sha256": TRAFFIC_RECORD["sha256"], "variant": "lin", "n": 128, "order": 3,
-               "instructions": 2603787.3}
+               "instructions": 2140375.3}
 VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
