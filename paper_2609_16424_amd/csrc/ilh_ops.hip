@@ -6,9 +6,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <utility>
 
 #include "ilh_internal.h"
 #include "ilh_pointwise.h"
+#include "ilh_lin.h"
 
 namespace ilh {
 
@@ -859,6 +861,98 @@ __global__ void __launch_bounds__(LGS_DB) k_lgs_dots(const TV* __restrict__ V, i
   }
 }
 
+// The same sweep with the basis count fixed at compile time: one pass over u_j, w and the basis,
+// no loads for the missing vectors of a padded chunk.  Up to 7 vectors are one group of sums;
+// j = N0 + N1 vectors beyond that are two chunks side by side (grid row 0: vectors [0, N0), the
+// norms and u_j . w; row 1: vectors [N0, j)), so u_j and w are read twice but in parallel.
+// Sums in the layout above (part[s][block]).
+static constexpr int LGS_NVMAX = 14;
+
+template <typename TV, int NV, bool NORMS>
+__device__ __forceinline__ void lgs_dots_tile(const TV* __restrict__ V, int64_t ldv, int k0, int j,
+                                              const TV* __restrict__ uj, const TV* __restrict__ w, int64_t n,
+                                              double* part) {
+  constexpr int NA = 2 * NV + (NORMS ? 3 : 0);
+  constexpr int NP = NA <= 4 ? 4 : NA <= 8 ? 8 : NA <= 16 ? 16 : 32;
+  static_assert(NA <= 32, "at most 32 sums per group");
+  __shared__ double sh[LGS_DB / 64][NP];
+  const int64_t stride = (int64_t)gridDim.x * LGS_DT;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+  for (int64_t t0 = (int64_t)blockIdx.x * LGS_DT; t0 < n; t0 += stride) {
+    // 32-bit offsets from wave-uniform bases (n sizeof(TV) < 4 GiB, checked on the host); the
+    // basis loads first, then u_j and w, all in flight before the first product
+    uint32_t io[KU];
+    bool in[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int64_t i = t0 + (int64_t)u * LGS_DB + threadIdx.x;
+      in[u] = i < n;
+      io[u] = (uint32_t)(in[u] ? i : n - 1);
+    }
+    TV vr[NV > 0 ? NV : 1][KU];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const TV* vk = sbase(V + (int64_t)(k0 + k) * ldv);
+#pragma unroll
+      for (int u = 0; u < KU; ++u) vr[k][u] = ld32(vk, io[u]);
+    }
+    TV ur[KU], wr[KU];
+    const TV* ub = sbase(uj);
+    const TV* wb = sbase(w);
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      ur[u] = ld32(ub, io[u]);
+      wr[u] = ld32(wb, io[u]);
+    }
+    double uv[KU], wv[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      uv[u] = in[u] ? (double)ur[u] : 0.0;
+      wv[u] = in[u] ? (double)wr[u] : 0.0;
+    }
+    if constexpr (NORMS) {
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        acc[2 * NV] += uv[u] * uv[u];
+        acc[2 * NV + 1] += uv[u] * wv[u];
+        acc[2 * NV + 2] += wv[u] * wv[u];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        acc[2 * k] += (double)vr[k][u] * uv[u];
+        acc[2 * k + 1] += (double)vr[k][u] * wv[u];
+      }
+  }
+  const int v = wave_sums<NP>(acc);
+  if ((lane & (64 / NP - 1)) == 0) sh[wid][v] = acc[0];
+  __syncthreads();
+  const int q = threadIdx.x;
+  if (q < NA) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < LGS_DB / 64; ++i) r += sh[i][q];
+    const int sidx = q < 2 * NV ? 2 * k0 + q : 2 * j + (q - 2 * NV);
+    part[(int64_t)sidx * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+template <typename TV, int N0, int N1>
+__global__ void __launch_bounds__(LGS_DB) k_lgs_dots_n(const TV* __restrict__ V, int64_t ldv,
+                                                    const TV* __restrict__ uj, const TV* __restrict__ w,
+                                                    int64_t n, double* part, const double* skip) {
+  if (skip && *skip != 0.0) return;
+  if (N1 == 0 || blockIdx.y == 0)
+    lgs_dots_tile<TV, N0, true>(V, ldv, 0, N0 + N1, uj, w, n, part);
+  else
+    lgs_dots_tile<TV, N1, false>(V, ldv, N0, N0 + N1, uj, w, n, part);
+}
+
 // Final block of step j (one work-group of LGS_FT threads): the sums, the second pass's scale,
 // column j - 1 with its Givens update and residual estimate (to h[352 + 2(j-1)]; to host memory
 // with the cycle's tag (publish_estimate) by the update sweep, or here on the closing step), the
@@ -1006,6 +1100,29 @@ __device__ __forceinline__ void combo_ab(const TV* __restrict__ V, int64_t ldv, 
   }
 }
 
+// combo_ab with the basis count fixed at compile time: every load issued before the first use
+template <typename TV, int R, int M>
+__device__ __forceinline__ void combo_ab_n(const TV* __restrict__ V, int64_t ldv, const double* __restrict__ a,
+                                           const double* __restrict__ b, const int64_t (&rows)[R], double (&A)[R],
+                                           double (&B)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) A[r] = B[r] = 0.0;
+  TV v[M > 0 ? M : 1][R];
+#pragma unroll
+  for (int k = 0; k < M; ++k)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[k][r] = V[(int64_t)k * ldv + rows[r]];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const double ca = a[k], cb = b[k];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      A[r] += ca * (double)v[k][r];
+      B[r] += cb * (double)v[k][r];
+    }
+  }
+}
+
 // one row of the update from its loaded u_j and w: v_j (stored back when j > 0) and u_{j+1}
 // (scaled by sg, stored over w); returns the stored u_{j+1}
 template <typename TV>
@@ -1032,7 +1149,8 @@ static constexpr int LGS_NU = 2;  // node pairs (position row, velocity row) per
 // next Jacobian action's output, whose velocity rows are zeroed.  end: the cycle-end flag; the
 // launch returns at once when an earlier step ended the cycle, and only block 0 works when this
 // step's final block ended it (end = j + 1).
-template <typename TV>
+// M >= 0: the instance for j = M (compile-time basis count); M = -1: any j
+template <typename TV, int M>
 __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t ldv, int j,
                                                     const double* __restrict__ h, int64_t nh1, int64_t Ne, int Nl,
                                                     int nbx, TV* __restrict__ z, float* __restrict__ z32,
@@ -1077,7 +1195,10 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
 #pragma unroll
     for (int q = 0; q < LGS_NU; ++q) dd[q] = z ? dv[rows[2 * q]] : 1.0;
     double A[R], B[R];
-    combo_ab(V, ldv, j, h, h + 72, rows, A, B);
+    if constexpr (M >= 0)
+      combo_ab_n<TV, R, M>(V, ldv, h, h + 72, rows, A, B);
+    else
+      combo_ab(V, ldv, j, h, h + 72, rows, A, B);
     double un[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) un[r] = lgs_row(uj, w, rows[r], in[r / 2], j, uv[r], wv[r], A[r], B[r], rinv, d, sg);
@@ -1109,16 +1230,19 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
     const double uv = (double)uj[rows[0]], wv = (double)w[rows[0]];
     const double es = (z && escale) ? escale[ec] : 1.0;
     double A[1], B[1];
-    combo_ab(V, ldv, j, h, h + 72, rows, A, B);
+    if constexpr (M >= 0)
+      combo_ab_n<TV, 1, M>(V, ldv, h, h + 72, rows, A, B);
+    else
+      combo_ab(V, ldv, j, h, h + 72, rows, A, B);
     const double un = lgs_row(uj, w, rows[0], in, j, uv, wv, A[0], B[0], rinv, d, sg);
     if (z) {
       shu[t] = un;
       __syncthreads();
       if (in) {
-        const double* M = me + e * estride + (int64_t)rr * Nl;
+        const double* Me = me + e * estride + (int64_t)rr * Nl;
         const double* ue = shu + le * Nl;
         double acc = 0.0;
-        for (int l = 0; l < Nl; ++l) acc += M[l] * ue[l];
+        for (int l = 0; l < Nl; ++l) acc += Me[l] * ue[l];
         acc *= es;
         z[rows[0]] = (TV)acc;
         if (z32) z32[rows[0]] = (float)acc;
@@ -1127,13 +1251,47 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
   }
 }
 
+// instance tables indexed by the basis count: one group up to 6 vectors, two chunks beyond
+template <int J>
+struct LgsSplit {
+  static constexpr int N0 = J <= 6 ? J : (J + 1) / 2, N1 = J - N0;
+};
+template <typename TV, int... I>
+static auto lgs_dots_table(std::integer_sequence<int, I...>) {
+  using F = void (*)(const TV*, int64_t, const TV*, const TV*, int64_t, double*, const double*);
+  static const F t[] = {k_lgs_dots_n<TV, LgsSplit<I>::N0, LgsSplit<I>::N1>...};
+  return t;
+}
+template <typename TV>
+static auto lgs_dots_kernel(int j) {
+  return lgs_dots_table<TV>(std::make_integer_sequence<int, LGS_NVMAX + 1>())[j];
+}
+template <typename TV, int... I>
+static auto lgs_update_table(std::integer_sequence<int, I...>) {
+  using F = decltype(&k_lgs_update<TV, -1>);
+  static const F t[] = {k_lgs_update<TV, I>...};
+  return t;
+}
+template <typename TV>
+static auto lgs_update_kernel(int j) {
+  return j <= LGS_NVMAX ? lgs_update_table<TV>(std::make_integer_sequence<int, LGS_NVMAX + 1>())[j]
+                        : &k_lgs_update<TV, -1>;
+}
+
 template <typename TV>
 int lgs_dots(ilh_ctx* c, const TV* V, int64_t ldv, int j, const TV* uj, const TV* w, int64_t n, double* part,
              int* np, const double* skip) {
   if (j > 64) return fail(c, ILH_EINVAL, "Gram-Schmidt: at most 64 basis vectors");
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + LGS_DT - 1) / LGS_DT));
   // the closing step has no w: its products are taken with u_j instead and not used
-  hipLaunchKernelGGL(k_lgs_dots<TV>, dim3(nb), dim3(LGS_DB), 0, c->stream, V, ldv, j, uj, w ? w : uj, n, part, skip);
+  // fixed-count instances up to 14 vectors in FP32, 12 in FP64 (beyond, their registers spill)
+  if (j <= (sizeof(TV) == 4 ? LGS_NVMAX : 12) && n * (int64_t)sizeof(TV) <= (int64_t)UINT32_MAX) {
+    hipLaunchKernelGGL(lgs_dots_kernel<TV>(j), dim3(nb, j <= 6 ? 1 : 2), dim3(LGS_DB), 0, c->stream, V, ldv, uj,
+                       w ? w : uj, n, part, skip);
+  } else {
+    hipLaunchKernelGGL(k_lgs_dots<TV>, dim3(nb), dim3(LGS_DB), 0, c->stream, V, ldv, j, uj, w ? w : uj, n, part,
+                       skip);
+  }
   ILH_HIP(c, hipGetLastError());
   *np = nb;
   return ILH_OK;
@@ -1158,7 +1316,7 @@ int lgs_update(ilh_ctx* c, TV* V, int64_t ldv, int j, const double* h, TV* z, fl
   const double* me = probe ? c->peinv : c->MEinv;
   const int64_t estride = probe ? (int64_t)c->Nl * c->Nl : c->me_stride;
   const double* escale = probe ? nullptr : c->me_scale;
-  hipLaunchKernelGGL(k_lgs_update<TV>, dim3(1 + nbx + nbe), dim3(TPB), 0, c->stream, V, ldv, j, h, c->nh1, c->Ne,
+  hipLaunchKernelGGL(lgs_update_kernel<TV>(j), dim3(1 + nbx + nbe), dim3(TPB), 0, c->stream, V, ldv, j, h, c->nh1, c->Ne,
                      c->Nl, nbx, z, z32, zero_v, dv, me, estride, escale, coupled, tau_dev, j > 0 ? 1 : 0, hest,
                      end);
   ILH_HIP(c, hipGetLastError());
