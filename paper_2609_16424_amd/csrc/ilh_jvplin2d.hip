@@ -142,7 +142,16 @@ __global__ void __launch_bounds__(64) k_lin2d(const KParams P, const Tab2<double
         xq1 += tb.B[qy][b] * AB[1][b];
       }
       double gx, gy;
-      tg_source_grad<double>(xq0, xq1, gam, gx, gy);
+      if constexpr (sizeof(T) == 4) {
+        // the pair is stored in FP32: the source gradient is evaluated in FP32 (positions O(1),
+        // a few ulp of FP32 in the sines and cosines)
+        float gxf, gyf;
+        tg_source_grad<float>((float)xq0, (float)xq1, (float)gam, gxf, gyf);
+        gx = gxf;
+        gy = gyf;
+      } else {
+        tg_source_grad<double>(xq0, xq1, gam, gx, gy);
+      }
       cf[NQD - 2] = mq * gx;
       cf[NQD - 1] = mq * gy;
     }
