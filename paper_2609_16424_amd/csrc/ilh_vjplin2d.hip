@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(64) k_vjp2d_q(const KParams P, const Tab2<T, D
     const int i = lane + 64 * q;
     if (i < NLS) sE[i] = lr[q];
   }
-  __syncthreads();
+  lds_barrier();
 
   // per-lane sums over the column: X (position rows), V (velocity rows), both as the
   // coefficients of (G_a B_b, B_a G_b + B_a B_b) like the forward kernel; TL energy rows
@@ -187,58 +187,89 @@ __global__ void __launch_bounds__(64) k_vjp2d_q(const KParams P, const Tab2<T, D
     }
   }
 
-  // H1 rows, position part then velocity part: per-lane contributions to sO, node sums over
-  // the (one or two) elements of the strip holding the node, the owner's identity terms, one
-  // atomic add per node
-#pragma unroll 1
+  vm_drained();  // every load is consumed and no store is issued yet
+
+  // H1 rows, position part then velocity part: per-lane contributions to sO, node sums over the
+  // (one or two) elements of the strip holding the node, the owner's identity terms, one atomic
+  // add per node.  Lane gs of node group g takes node gs of the rows (component g, node row p):
+  // per-lane LDS bases plus per-pass constants, all LDS reads issued before the first sum.
+  constexpr int GS = NS <= 32 ? 32 : 64, NG = 64 / GS, PN = 2 * D1D / NG;
+  int tn = lane % GS, gn = lane / GS;
+  asm volatile("" : "+v"(tn), "+v"(gn));
+  const int lc = NG == 1 ? 0 : gn;
+  const int zz = tn / K, a = tn - K * zz, sc = min(tn, ns - 1);
+  const bool left = zz < E, shared = a == 0 && zz > 0;
+  const int oR = min(zz, E - 1) * Q1D * NOP + lc * D1D * D1D + a;
+  int oL = max(zz - 1, 0) * Q1D * NOP + lc * D1D * D1D + K;
+  asm volatile("" : "+v"(oL));
+  const int oS = lc * D1D * NS + sc;
+  const uint32_t I = K * ex0 + tn;
+  const bool consI = lc == 0 && (I == 0 || I == ng0 - 1), isv = lc != 0, own_s = tn < K * E || last_x;
+  const uint32_t gb = (uint32_t)lc * N + row0 + (uint32_t)sc;
+  const T* const sOf = &sO[0][0];
+  const T* const sSf = &sS[0][0][0];
+#pragma unroll
   for (int part = 0; part < 2; ++part) {
     if (active) {
       T Bq[D1D], Gq[D1D];
 #pragma unroll
-      for (int a = 0; a < D1D; ++a) {
-        Bq[a] = sBG[0][qx][a];
-        Gq[a] = sBG[1][qx][a];
+      for (int a2 = 0; a2 < D1D; ++a2) {
+        Bq[a2] = sBG[0][qx][a2];
+        Gq[a2] = sBG[1][qx][a2];
       }
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int b = 0; b < D1D; ++b)
 #pragma unroll
-          for (int a = 0; a < D1D; ++a)
-            sO[lane][c * D1D * D1D + b * D1D + a] =
-                part == 0 ? Gq[a] * X0[c][b] + Bq[a] * X1[c][b] : Gq[a] * V0[c][b] + Bq[a] * V1[c][b];
+          for (int a2 = 0; a2 < D1D; ++a2)
+            sO[lane][c * D1D * D1D + b * D1D + a2] =
+                part == 0 ? Gq[a2] * X0[c][b] + Bq[a2] * X1[c][b] : Gq[a2] * V0[c][b] + Bq[a2] * V1[c][b];
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int i = lane; i < 2 * D1D * NS; i += 64) {
-      const int s = i % NS, t = i / NS, b = t % D1D, c = t / D1D;
-      if (s >= ns) continue;
-      const int zz = s / K, a = s - K * zz;
-      T f = T(0);
-      if (zz < E) {
+    lds_barrier();
+    // constrained velocity rows: the owner adds y_v (zeroed in the strips), read up front
+    T yc[PN];
+    if (part == 1) {
 #pragma unroll
-        for (int q = 0; q < Q1D; ++q) f += sO[zz * Q1D + q][c * D1D * D1D + b * D1D + a];
+      for (int p = 0; p < PN; ++p) {
+        const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : p;
+        yc[p] = ld32(y, nh1 + gb + (uint32_t)cp * N + (uint32_t)bp * ng0);
       }
-      if (a == 0 && zz > 0) {
+    }
+    T fv[PN], yx[PN];
 #pragma unroll
-        for (int q = 0; q < Q1D; ++q) f += sO[(zz - 1) * Q1D + q][c * D1D * D1D + b * D1D + K];
+    for (int p = 0; p < PN; ++p) {
+      const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : p;
+      const int po = cp * D1D * D1D + bp * D1D;
+      T f0 = sOf[oR + po], f1 = sOf[oL + po];
+#pragma unroll
+      for (int q = 1; q < Q1D; ++q) {
+        f0 += sOf[oR + po + q * NOP];
+        f1 += sOf[oL + po + q * NOP];
       }
-      const uint32_t gi = c * N + row0 + (uint32_t)b * ng0 + s;
-      const bool own = (s < K * E || last_x) && (b < K || last_y);
-      if (own) {
-        const T yx = sS[c][b][s];
+      fv[p] = (left ? f0 : T(0)) + (shared ? f1 : T(0));
+      yx[p] = sSf[oS + (cp * D1D + bp) * NS];
+    }
+    if (tn < ns) {
+#pragma unroll
+      for (int p = 0; p < PN; ++p) {
+        const int cp = NG == 1 ? (p & 1) : 0, bp = NG == 1 ? (p >> 1) : p;
+        const int b = bp;
+        const bool own = own_s && (b < K || last_y);
+        T f = fv[p];
         if (part == 0) {
-          f += yx;
+          if (own) f += yx[p];
         } else {
-          f -= tau * yx;
-          const uint32_t I = K * ex0 + s, J = K * ey + b;
-          const bool cons = (c == 0) ? (I == 0 || I == ng0 - 1) : (J == 0 || J == ng1 - 1);
-          if (cons) f += y[nh1 + gi];
+          const uint32_t J = K * ey + b;
+          const bool consJ = J == 0 || J == ng1 - 1;
+          const bool cons = NG == 1 ? (cp == 0 ? (I == 0 || I == ng0 - 1) : consJ) : (consI || (isv && consJ));
+          if (own) f -= tau * yx[p];
+          if (own && cons) f += yc[p];
         }
+        atomic_add32(out, part * nh1 + gb + (uint32_t)cp * N + (uint32_t)bp * ng0, f);
       }
-      unsafeAtomicAdd(&out[part * nh1 + gi], f);
     }
-    __syncthreads();
+    lds_barrier();
   }
   // energy rows (element-owned)
   if (active) {
@@ -247,13 +278,21 @@ __global__ void __launch_bounds__(64) k_vjp2d_q(const KParams P, const Tab2<T, D
 #pragma unroll
       for (int al = 0; al < L1D; ++al) sO[lane][bl * L1D + al] = sBLt[qx][al] * TL[bl];
   }
-  __syncthreads();
-  for (int i = lane; i < E * NLD; i += 64) {
-    const int zz = i / NLD, t = i % NLD;
-    T o = 0;
+  lds_barrier();
+  constexpr int NE = (NLS + 63) / 64;
+  T ev[NE];
 #pragma unroll
-    for (int q = 0; q < Q1D; ++q) o += sO[zz * Q1D + q][t];
-    out[2 * nh1 + ebase * NLD + i] = o;
+  for (int it = 0; it < NE; ++it) {
+    const int i = min(lane + 64 * it, E * NLD - 1), ze = i / NLD, t = i % NLD;
+    T o = sO[ze * Q1D][t];
+#pragma unroll
+    for (int q = 1; q < Q1D; ++q) o += sO[ze * Q1D + q][t];
+    ev[it] = o;
+  }
+#pragma unroll
+  for (int it = 0; it < NE; ++it) {
+    const int i = lane + 64 * it;
+    if (i < E * NLD) st32(out, 2 * nh1 + ebase * NLD + i, ev[it]);
   }
 }
 
