@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(64) k_lin3d(const KParams P, const Tab2<double
     const int i = lane + 64 * r;
     if (i < NTS) (&sS[0][0][0][0])[i] = tr[r];
   }
-  __syncthreads();
+  lds_barrier();
 
   const int z = lane / LPE, rr = lane - z * LPE, qy = rr / Q1D, qx = rr - qy * Q1D;
   if (z >= E) return;  // no barrier follows
@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
     const int i = lane + 64 * r;
     if (i < NLS) sE[i] = lr[r];
   }
-  __syncthreads();
+  lds_barrier();
 
   const int z = lane / LPE, rr = lane - z * LPE, qy = rr / Q1D, qx = rr - qy * Q1D;
   const bool active = z < E;
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
         for (int b = 0; b < D1D; ++b) sO[lane][(cz * D1D + b) * D1D + a] = By[b] * q1 + Gy[b] * q2;
       }
     }
-    __syncthreads();
+    lds_barrier();
     for (int i = lane; i < D1D * D1D * NS; i += 64) {
       const int s = i % NS, t = i / NS, b = t % D1D, cz = t / D1D;
       if (s >= ns) continue;
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
       }
       unsafeAtomicAdd(&out[nh1 + r * N + row0 + cz * ng01 + b * ng0 + s], o);
     }
-    __syncthreads();
+    lds_barrier();
   }
   } else {  // FP64: per-element sums over the element's lanes, one atomic per node and element
   // velocity rows, one component at a time: column contributions to the element's nodes,
@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
             }
           sO[lane][(cz * D1D + b) * D1D + a] = Gx[a] * By[b] * tx + Bx[a] * Gy[b] * ty + Bx[a] * By[b] * tz;
         }
-    __syncthreads();
+    lds_barrier();
     if (active) {
       for (int t = rr; t < NND; t += LPE) {
         T o = 0;
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
         if (idx != 0 && idx != ngr - 1) unsafeAtomicAdd(&out[nh1 + r * N + Kz * ng01 + J * ng0 + I], o);
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   }
   // energy rows (element-owned)
@@ -469,7 +469,7 @@ __global__ void __launch_bounds__(64) k_jvp3d_q(const KParams P, const Tab2<T, D
     for (int bl = 0; bl < L1D; ++bl)
 #pragma unroll
       for (int al = 0; al < L1D; ++al) sO[lane][al + L1D * (bl + L1D * cl)] = BLx[al] * BLy[bl] * TL[cl];
-  __syncthreads();
+  lds_barrier();
   if (active) {
     for (int t = rr; t < NLD; t += LPE) {
       T o = 0;

@@ -409,7 +409,7 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
       sE[1][i] = gke[q];
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   double Tx[3][D1D], Ty[3][D1D], Tz[3][D1D], TL[L1D];
 #pragma unroll
@@ -575,7 +575,7 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
           for (int a = 0; a < D1D; ++a)
             sO[lane][(cz * D1D + b) * D1D + a] = Gx[a] * By[b] * tx + Bx[a] * Gy[b] * ty + Bx[a] * By[b] * tz;
       }
-      __syncthreads();
+      lds_barrier();
       if (active) {
         for (int t = rr; t < NND; t += LPE) {
           double o = 0;
@@ -587,7 +587,7 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
           if (idx != 0 && idx != ngc - 1) unsafeAtomicAdd(&r[nh1 + c * N + Kz * ng01 + J * ng0 + I], o);
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
   // energy rows (element-owned)
@@ -605,7 +605,7 @@ k_res3d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
 #pragma unroll
         for (int al = 0; al < L1D; ++al) sO[lane][al + L1D * (bl + L1D * cl)] = BLx[al] * BLy[bl] * TL[cl];
   }
-  __syncthreads();
+  lds_barrier();
   if (dmin) {  // the work-group's smallest det J of the stage positions w_x
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dm = nan_min(dm, __shfl_xor(dm, o, 64));

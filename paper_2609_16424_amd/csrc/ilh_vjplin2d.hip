@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(64) k_vjp3d_q(const KParams P, const Tab2<T, D
     const int i = lane + 64 * r;
     if (i < NLS) sE[i] = lr[r];
   }
-  __syncthreads();
+  lds_barrier();
 
   const int z = lane / LPE, rr = lane - z * LPE, qy = rr / Q1D, qx = rr - qy * Q1D;
   const bool active = z < E;
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(64) k_vjp3d_q(const KParams P, const Tab2<T, D
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     for (int i = lane; i < D1D * D1D * NS; i += 64) {
       const int s = i % NS, t = i / NS, b = t % D1D, cz = t / D1D;
       if (s >= ns) continue;
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(64) k_vjp3d_q(const KParams P, const Tab2<T, D
       }
       unsafeAtomicAdd(&out[part * nh1 + gi], o);
     }
-    __syncthreads();
+    lds_barrier();
   }
   // energy rows (element-owned)
   if (active) {
@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(64) k_vjp3d_q(const KParams P, const Tab2<T, D
 #pragma unroll
         for (int al = 0; al < L1D; ++al) sO[lane][al + L1D * (bl + L1D * cl)] = sBL[qx][al] * sBL[qy][bl] * TL[cl];
   }
-  __syncthreads();
+  lds_barrier();
   if (active) {
     for (int t = rr; t < NLD; t += LPE) {
       T o = 0;
