@@ -49,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
 TRAFFIC_SOURCE_END = {"paper_2609_16424_amd/csrc/ilh_internal.h": b"struct ilh_ctx {"}
-TRAFFIC_RECORD = {"sha256": "66f3785848d2f0a82998954cd41e7faef9dea69999fa46fec236ca0afad50095",
+TRAFFIC_RECORD = {"sha256": "15fe3db1ce199bf513ad6c40aacba2d925e49a2c2e8fcdda9ebc10e54bef4e09",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16607.8, "fetch_scale": 262144.0 / 131079.27,
-                  "write_kib": 3704.4, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 16607.0, "fetch_scale": 262144.0 / 131080.10,
+                  "write_kib": 3704.3, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
