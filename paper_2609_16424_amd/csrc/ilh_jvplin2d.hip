@@ -211,9 +211,8 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
   const int ns = K * E + 1;
   const uint32_t ng0 = P.ng[0], ng1 = P.ng[1];
   const uint32_t N = (uint32_t)P.N, nh1 = 2 * N;
-  const T tau = T(tau_dev ? *tau_dev : tau_);
   const bool last_x = (ex0 + E == nx);
-  const int ey0 = sy * R, ey1 = R1 ? ey0 + 1 : min(ey0 + R, ny);
+  const int ey0 = R1 ? sy : sy * R, ey1 = R1 ? ey0 + 1 : min(ey0 + R, ny);  // R1: R == 1
   const int z = lane / Q1D, qx = lane - z * Q1D;
   const bool active = z < E;
   constexpr int NG = NT / GS, PG = 4 * D1D / NG;
@@ -440,6 +439,8 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
       xv[p] = sSf[oS + (cp * D1D + bp) * GS];
       vv[p] = sSf[oS + (cp * D1D + bp) * GS + 2 * D1D * GS];
     }
+    // the stage factor is first needed here (its load is not waited for before the gathers)
+    const T tau = T(tau_dev ? *tau_dev : tau_);
     const uint32_t I = K * ex0 + tn;
     const bool consI = I == 0 || I == ng0 - 1, own_s = tn < K * E || last_x;
     const bool cI = lc == 0 && consI, isv = lc != 0;  // constrained-row tests of the lane's component

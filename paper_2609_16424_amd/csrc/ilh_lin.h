@@ -346,7 +346,9 @@ __device__ __forceinline__ void vm_drained() { __builtin_amdgcn_s_waitcnt(0x0F70
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t w, uint32_t nb) {
   constexpr uint32_t NX = 8;
   const uint32_t x = w % NX, slot = w / NX, q = nb / NX, rem = nb % NX;
-  return x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
+  // x (q + 1) + slot for the first rem XCDs, rem (q + 1) + (x - rem) q + slot after them; in one
+  // branch-free expression (the kernels' first scalar loads then issue together)
+  return x * q + min(x, rem) + slot;
 }
 
 // A wave-uniform pointer made opaque to the compiler (scalar registers): loads from it take the
