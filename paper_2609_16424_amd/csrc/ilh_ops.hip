@@ -946,6 +946,8 @@ template <typename TV, int N0, int N1>
 __global__ void __launch_bounds__(LGS_DB) k_lgs_dots_n(const TV* __restrict__ V, int64_t ldv,
                                                     const TV* __restrict__ uj, const TV* __restrict__ w,
                                                     int64_t n, double* part, const double* skip) {
+  // (the flag is read first: the sweep is bound by its loads, which a launch after the end of
+  // the cycle would otherwise still wait for)
   if (skip && *skip != 0.0) return;
   if (N1 == 0 || blockIdx.y == 0)
     lgs_dots_tile<TV, N0, true>(V, ldv, 0, N0 + N1, uj, w, n, part);
@@ -1159,17 +1161,18 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
                                                     const double* __restrict__ escale, int coupled,
                                                     const double* __restrict__ tau_dev, int pub, double* hest,
                                                     const double* end) {
-  const double ended = *end;
-  if (ended != 0.0 && ended != (double)(j + 1)) return;
   if (blockIdx.x == 0) {
     // first in the grid, so that the fence runs beside the sweep instead of after it
+    const double ended = *end;
+    if (ended != 0.0 && ended != (double)(j + 1)) return;
     if (pub && hest && threadIdx.x == 0) {
       const int jc = j - 1;
       publish_estimate(hest, jc, h[352 + 2 * jc], h[353 + 2 * jc], h[255]);
     }
     return;
   }
-  if (ended != 0.0) return;
+  // the other blocks read the cycle-end flag behind their loads and return before any store
+  // once an earlier step (or this step's final block) ended the cycle
   const int b = (int)blockIdx.x - 1;
   TV* uj = V + (int64_t)j * ldv;
   TV* w = uj + ldv;
@@ -1199,6 +1202,7 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
       combo_ab_n<TV, R, M>(V, ldv, h, h + 72, rows, A, B);
     else
       combo_ab(V, ldv, j, h, h + 72, rows, A, B);
+    if (*end != 0.0) return;
     double un[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) un[r] = lgs_row(uj, w, rows[r], in[r / 2], j, uv[r], wv[r], A[r], B[r], rinv, d, sg);
@@ -1234,6 +1238,7 @@ __global__ void __launch_bounds__(TPB) k_lgs_update(TV* __restrict__ V, int64_t 
       combo_ab_n<TV, 1, M>(V, ldv, h, h + 72, rows, A, B);
     else
       combo_ab(V, ldv, j, h, h + 72, rows, A, B);
+    if (*end != 0.0) return;  // uniform over the block: no thread reaches the barrier below
     const double un = lgs_row(uj, w, rows[0], in, j, uv, wv, A[0], B[0], rinv, d, sg);
     if (z) {
       shu[t] = un;
