@@ -49,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
 TRAFFIC_SOURCE_END = {"paper_2609_16424_amd/csrc/ilh_internal.h": b"struct ilh_ctx {"}
-TRAFFIC_RECORD = {"sha256": "15fe3db1ce199bf513ad6c40aacba2d925e49a2c2e8fcdda9ebc10e54bef4e09",
+TRAFFIC_RECORD = {"sha256": "13dd24693ec3b9c091aa2b7a7ea9f8b023466dedc57811fcbc18c9e78c25e0f4",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16607.0, "fetch_scale": 262144.0 / 131080.10,
-                  "write_kib": 3704.3, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 16609.0, "fetch_scale": 262144.0 / 131079.94,
+                  "write_kib": 3704.7, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():
@@ -71,7 +71,7 @@ def sources_sha256():
 # VALU instructions per launch of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU, same sources):
 # the issue peak of wave64 FP32 (unpacked) / FP64 VALU instructions is 1024 SIMDs x 2.4 GHz / 4.
 VALU_RECORD = {"sha256": TRAFFIC_RECORD["sha256"], "variant": "lin", "n": 128, "order": 3,
-               "instructions": 2140375.3}
+               "instructions": 2137047.3}
 VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
