@@ -271,9 +271,11 @@ constexpr int HDEV_LGSE = 770;
 constexpr int HDEV_LEN = 776;
 // y = H(0:n, 0:n)^-1 g
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);
-// x += Z y with y = H(0:jn, 0:jn)^-1 g, one launch
+// x += Z y with y = H(0:jn, 0:jn)^-1 g, one launch (accumulate = false: x = Z y, x need not be
+// initialised; with jn = 0 it is zeroed)
 template <typename TV>
-int launch_trisolve_maxpy(ilh_ctx* c, double* x, const TV* Z, int64_t ldz, const double* G, int jn, int64_t n);
+int launch_trisolve_maxpy(ilh_ctx* c, double* x, const TV* Z, int64_t ldz, const double* G, int jn, int64_t n,
+                          bool accumulate = true);
 // Norm reduction and Givens update of Arnoldi step j: the partial sums of |w|^2 (part, np blocks),
 // the Arnoldi scalars h, the rotations G (layout at givens_update), and the mapped host buffer of
 // residual estimates (hest, nullable).  Runs as its own one-block kernel, or as the extra last

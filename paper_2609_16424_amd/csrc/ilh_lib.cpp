@@ -1118,12 +1118,14 @@ static int read_pair(ilh_ctx* c, double* a, double* b) {
 // y = x / beta; beta is also stored to *beta_out, the scale of the stored vector y, 1, to *s0
 // and the FGMRES cycle's tag to *tag_out
 // y = x / beta with the cycle's Arnoldi scalars: h[240] = beta, h[252] = the residual target,
-// h[255] = the cycle's tag, s_0 = h[256] = 1
+// h[255] = the cycle's tag, s_0 = h[256] = 1, and the stage factor h[250] = tau that the step
+// kernels read
 template <typename TV>
 __global__ void k_scale_copy(TV* y, const double* x, double beta, int64_t n, double* h, double target,
-                             double tag) {
+                             double tag, double tau) {
   const double f = 1.0 / beta;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    h[250] = tau;
     h[240] = beta;
     h[252] = target;
     h[255] = tag;
@@ -1475,19 +1477,20 @@ struct Solver {
     double* hd = c->hdev;
     double* G = c->gmd;
     int st;
-    if ((st = launch_fill(c, x, 0.0, n))) return st;
+    // x is written by the first cycle's x = Z y (no zero fill ahead of it); every return path
+    // before that writes zeros
+    bool x_set = false;
     double beta = beta_b;
     if (!(beta >= 0.0)) {
       beta = nrm2(c, b, n, &st);
       if (st) return st;
     }
     *its = 0;
-    if (beta == 0.0) return ILH_OK;
+    if (beta == 0.0) return launch_fill(c, x, 0.0, n);
     const double target = o->gmres_rtol * beta;
     const double* rhs = b;
     double* rbuf = c->nwt + 3 * n;  // tmp vector
     int total = 0;
-    if ((st = launch_fill(c, hd + 250, tau, 1))) return st;  // tau on the device for the step kernels
     const bool use_graph = graphable();
     if (use_graph && !c->qd_ok[0]) {  // the linearisation stays outside the captured steps
       if ((st = launch_lin2d(c, 32))) return st;
@@ -1496,7 +1499,8 @@ struct Solver {
     while (true) {
       // V0 = r / beta (beta, the target and the cycle's tag to the device), z_0 = P V0
       const double tag = (c->est_tag += 1.0);
-      hipLaunchKernelGGL(k_scale_copy<TV>, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd, target, tag);
+      hipLaunchKernelGGL(k_scale_copy<TV>, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd, target, tag,
+                         tau);
       if ((st = precond(V, Z, V + n))) return st;
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
@@ -1624,8 +1628,9 @@ struct Solver {
         if ((st = check(m - 1, end))) return st;
         j_end = m;
       }
-      // y = H^-1 g (upper triangular), x += Z y
-      if ((st = launch_trisolve_maxpy<TV>(c, x, Z, n, G, j_end, n))) return st;
+      // y = H^-1 g (upper triangular), x += Z y (x = Z y in the first cycle)
+      if ((st = launch_trisolve_maxpy<TV>(c, x, Z, n, G, j_end, n, x_set))) return st;
+      x_set = true;
       if (stop) break;
       // restart: r = b - J x
       if ((st = apply(x, rbuf))) return st;

@@ -713,7 +713,8 @@ __global__ void k_trisolve(const double* G, int n, double* y) {
 // holding row l of the right-hand side) and then takes its share of the update
 template <typename TV>
 __global__ void __launch_bounds__(TPB) k_trisolve_maxpy(double* __restrict__ x, const TV* __restrict__ Z,
-                                                        int64_t ldz, const double* __restrict__ G, int jn, int64_t n) {
+                                                        int64_t ldz, const double* __restrict__ G, int jn, int64_t n,
+                                                        int accumulate) {
   extern __shared__ double tsh[];  // H (jn x jn, row-major), then y (jn)
   double* Hs = tsh;
   double* ys = tsh + jn * jn;
@@ -734,22 +735,25 @@ __global__ void __launch_bounds__(TPB) k_trisolve_maxpy(double* __restrict__ x, 
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double acc = 0;
     for (int j = 0; j < jn; ++j) acc += ys[j] * (double)Z[(int64_t)j * ldz + i];
-    x[i] += acc;
+    x[i] = accumulate ? x[i] + acc : acc;
   }
 }
 
 template <typename TV>
-int launch_trisolve_maxpy(ilh_ctx* c, double* x, const TV* Z, int64_t ldz, const double* G, int jn, int64_t n) {
-  if (jn <= 0) return ILH_OK;
+int launch_trisolve_maxpy(ilh_ctx* c, double* x, const TV* Z, int64_t ldz, const double* G, int jn, int64_t n,
+                          bool accumulate) {
+  if (jn <= 0) return accumulate ? ILH_OK : launch_fill(c, x, 0.0, n);
   if (jn > 64) return fail(c, ILH_EINVAL, "triangular solve: at most 64 columns");
   const size_t shm = (size_t)(jn * jn + jn) * sizeof(double);
   hipLaunchKernelGGL(k_trisolve_maxpy<TV>, dim3(std::min(nblk(n), 1024)), dim3(TPB), shm, c->stream, x, Z, ldz, G, jn,
-                     n);
+                     n, accumulate ? 1 : 0);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
-template int launch_trisolve_maxpy<double>(ilh_ctx*, double*, const double*, int64_t, const double*, int, int64_t);
-template int launch_trisolve_maxpy<float>(ilh_ctx*, double*, const float*, int64_t, const double*, int, int64_t);
+template int launch_trisolve_maxpy<double>(ilh_ctx*, double*, const double*, int64_t, const double*, int, int64_t,
+                                          bool);
+template int launch_trisolve_maxpy<float>(ilh_ctx*, double*, const float*, int64_t, const double*, int, int64_t,
+                                         bool);
 
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y) {
   (void)m;
