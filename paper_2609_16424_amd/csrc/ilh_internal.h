@@ -234,9 +234,12 @@ bool lin3d_available(const ilh_ctx* c);
 int launch_lin3d(ilh_ctx* c, int prec);
 int launch_jvp3d_q(ilh_ctx* c, int prec, const void* dk, void* out);
 int launch_fill(ilh_ctx* c, double* p, double v, int64_t n);
+int launch_fill2(ilh_ctx* c, double* p, double* q, double v, int64_t n);  // p = q = v, one launch
 int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n);
 int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int64_t n);  // y = a x + b y
-int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double* k, int64_t n);  // w = u + t k
+// w = u + t k; with z, its first nz (<= n) entries are zeroed by the same launch
+int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double* k, int64_t n, double* z = nullptr,
+                 int64_t nz = 0);
 int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n);
 int launch_cast_f2d(ilh_ctx* c, double* y, const float* x, int64_t n);
 int launch_mass_v(ilh_ctx* c, const double* x, double* y, int zero_first);

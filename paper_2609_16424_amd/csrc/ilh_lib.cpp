@@ -761,10 +761,10 @@ int ilh_force_jvp(ilh_ctx* c, int prec, const double* w, const void* dw, void* d
   ILH_CATCH(c)
 }
 
-int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
-  ILH_TRY
-  if (!c || !k || !u || !r) return ILH_EINVAL;
-  int st = launch_fill(c, r + c->nh1, 0.0, c->nh1);
+// The stage residual; the kernels accumulate the velocity rows of r, so they start from zero:
+// zeroed here unless the caller has zeroed them already (zero_v false)
+static int residual_into(ilh_ctx* c, const double* k, const double* u, double tau, double* r, bool zero_v) {
+  int st = zero_v ? launch_fill(c, r + c->nh1, 0.0, c->nh1) : ILH_OK;
   if (st) return st;
   const int slot = tstart_k(c, 1);
   if (c->jvp_variant != 1 && res2d_available(c)) {
@@ -777,6 +777,12 @@ int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, doubl
   }
   tstop_k(c, slot);
   return st;
+}
+
+int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
+  ILH_TRY
+  if (!c || !k || !u || !r) return ILH_EINVAL;
+  return residual_into(c, k, u, tau, r, true);
   ILH_CATCH(c)
 }
 
@@ -786,13 +792,12 @@ static bool residual_detj_available(const ilh_ctx* c) {
   return c->jvp_variant != 1 && (res2d_available(c) || res3d_available(c));
 }
 // the same, with the per-work-group minima left in c->dmin_part (*ng of them) for the caller's
-// final reduction
+// final reduction; the velocity rows of r must be zero on entry
 static int residual_detj_part(ilh_ctx* c, const double* k, const double* u, double tau, double* r, int* ng) {
   int st;
   const bool d2 = res2d_available(c);
   *ng = d2 ? res2d_groups(c) : res3d_groups(c);
   if (!c->dmin_part && (st = dalloc(c, &c->dmin_part, (size_t)*ng))) return st;
-  if ((st = launch_fill(c, r + c->nh1, 0.0, c->nh1))) return st;
   const int slot = tstart_k(c, 1);
   st = d2 ? launch_res2d(c, k, u, tau, r, c->dmin_part) : launch_res3d(c, k, u, tau, r, c->dmin_part);
   tstop_k(c, slot);
@@ -1691,12 +1696,15 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
     c->zero_ok = true;  // nothing else writes this part of the workspace
   }
   int npa = 0, npb = 0;
-  if ((st = ilh_residual(c, zero, u, tau, rt))) return st;  // R(0) in rt
+  // the velocity rows of both residual buffers zeroed by one launch
+  if ((st = k_guess ? launch_fill2(c, rt + c->nh1, r + c->nh1, 0.0, c->nh1) : launch_fill(c, rt + c->nh1, 0.0, c->nh1)))
+    return st;
+  if ((st = residual_into(c, zero, u, tau, rt, false))) return st;  // R(0) in rt
   if ((st = dot_part(c, rt, rt, n, pa, &npa))) return st;
   double r0 = 0.0, nr = 0.0;
   if (k_guess) {
     // |R(0)| and |R(k_guess)| read together
-    if ((st = ilh_residual(c, k_guess, u, tau, r))) return st;
+    if ((st = residual_into(c, k_guess, u, tau, r, false))) return st;
     if ((st = dot_part(c, r, r, n, pb, &npb))) return st;
     if ((st = launch_pair_final(c, pa, npa, 0, pb, npb, 0, hp))) return st;
     if ((st = read_hp(&r0, &nr))) return st;
@@ -1752,17 +1760,19 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
     double alpha = 1.0, best = INFINITY, best_alpha = 0.0;
     bool ok = false, any_valid = false, nonfinite = false;
     for (int h = 0; h <= o->max_halvings; ++h) {
-      if ((st = launch_waxpy(c, kt, k, -alpha, dk, n))) return st;
       // the trial residual is formed before det J > 0 is known (it is discarded otherwise), so
       // that one synchronisation reads both; the strip residual kernel returns det J itself
       double md, nrt2;
       if (residual_detj_available(c)) {
+        // the trial iterate and the zero velocity rows of its residual in one launch
+        if ((st = launch_waxpy(c, kt, k, -alpha, dk, n, rt + c->nh1, c->nh1))) return st;
         int ng = 0;
         if ((st = residual_detj_part(c, kt, u, tau, rt, &ng))) return st;
         if ((st = dot_part(c, rt, rt, n, pb, &npb))) return st;
         if ((st = launch_pair_final(c, c->dmin_part, ng, 1, pb, npb, 0, hp))) return st;
         if ((st = read_hp(&md, &nrt2))) return st;
       } else {
+        if ((st = launch_waxpy(c, kt, k, -alpha, dk, n))) return st;
         if ((st = launch_waxpy(c, trial, u, tau, kt, c->nh1))) return st;
         if ((st = min_detj_dev(c, trial, dsc))) return st;
         if ((st = ilh_residual(c, kt, u, tau, rt))) return st;

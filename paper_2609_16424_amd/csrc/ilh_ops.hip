@@ -27,6 +27,13 @@ static inline int nblk(int64_t n, int cap = 65535 * 4) {
 __global__ void k_fill(double* p, double v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
+// two arrays of one length set in one launch
+__global__ void k_fill2(double* p, double* q, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    p[i] = v;
+    q[i] = v;
+  }
+}
 __global__ void k_fillf(float* p, float v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -34,9 +41,12 @@ __global__ void k_axpby(double* y, double a, const double* x, double b, int64_t 
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = a * x[i] + b * y[i];
 }
-__global__ void k_waxpy(double* w, const double* u, double t, const double* k, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+// w = u + t k; the first nz (<= n) entries of z are zeroed in the same pass (nz = 0: none)
+__global__ void k_waxpy(double* w, const double* u, double t, const double* k, int64_t n, double* z, int64_t nz) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     w[i] = u[i] + t * k[i];
+    if (i < nz) z[i] = 0.0;
+  }
 }
 __global__ void k_d2f(float* y, const double* x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -78,6 +88,12 @@ int launch_fill(ilh_ctx* c, double* p, double v, int64_t n) {
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
+int launch_fill2(ilh_ctx* c, double* p, double* q, double v, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_fill2, dim3(nblk(n)), dim3(TPB), 0, c->stream, p, q, v, n);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
 int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n) {
   if (n <= 0) return ILH_OK;
   hipLaunchKernelGGL(k_fillf, dim3(nblk(n)), dim3(TPB), 0, c->stream, p, v, n);
@@ -90,9 +106,11 @@ int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
-int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double* k, int64_t n) {
+int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double* k, int64_t n, double* z,
+                 int64_t nz) {
+  if (nz > n || nz < 0 || (nz > 0 && !z)) return fail(c, ILH_EINVAL, "waxpy: zero target longer than the vector");
   if (n <= 0) return ILH_OK;
-  hipLaunchKernelGGL(k_waxpy, dim3(nblk(n)), dim3(TPB), 0, c->stream, w, u, t, k, n);
+  hipLaunchKernelGGL(k_waxpy, dim3(nblk(n)), dim3(TPB), 0, c->stream, w, u, t, k, n, z, nz);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
