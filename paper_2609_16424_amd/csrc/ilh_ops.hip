@@ -990,42 +990,62 @@ static constexpr int LGS_FT = 1024;  // threads of the final block
 __global__ void __launch_bounds__(LGS_FT) k_lgs_final(const double* __restrict__ part, int np, int j, int m,
                                                       int has_w, double* h, double* G, double* hest,
                                                       const double* skip) {
-  if (skip && *skip != 0.0) return;
   __shared__ double S[2 * 65 + 1];
-  __shared__ double csl[64], snl[64], coll[65], pl[66], sc[4];
+  __shared__ double csl[64], snl[64], coll[65], pl[65], sc[6];
   const int ns = 2 * (j + 1) + (has_w ? 1 : 0);
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   constexpr int NW = LGS_FT / 64;
   double* cs = G + 64 * 64;
   double* g = cs + 128;
   // every scalar the serial part needs is staged into LDS first, by other threads, so that its
-  // chain reads no global memory
-  if (t < j - 1) {
-    csl[t] = cs[t];
-    snl[t] = cs[64 + t];
-  } else if (t >= 128 && t < 128 + j) {
-    pl[t - 128] = h[HDEV_LGSP + t - 128];
-  } else if (t == 256) {
-    pl[65] = h[HDEV_LGSP + 65];
-  } else if (t == 257) {
-    sc[0] = j >= 1 ? g[j - 1] : 0.0;  // g_{j-1}, rotated by column j - 1
-  } else if (t == 258) {
-    sc[1] = h[240];
-  } else if (t == 259) {
-    sc[2] = h[252];
-  } else if (t == 260) {
-    sc[3] = h[255];
+  // chain reads no global memory.  The staged values are loaded by every lane of waves 0, 2 and 3
+  // (two loads each, addresses chosen per lane, a harmless address elsewhere) before the partial
+  // sums' loads and written to LDS after them, so that a wave waits for memory once: one round
+  // trip before the serial part.  The cycle-end flag comes with them and is tested once they are
+  // in (a launch after the end of the cycle only reads, and stores nothing).
+  const double* sa = h + 240;
+  const double* sb = h + 240;
+  const int q = t - 192;
+  if (wid == 0) {
+    sa = cs + lane;  // c_i, s_i of the previous columns
+    sb = cs + 64 + lane;
+  } else if (wid == 2) {
+    sa = h + HDEV_LGSP + lane;  // step j - 1's first-pass coefficients
+  } else if (wid == 3) {
+    // sc: g_{j-1} (rotated by column j - 1), the target h[240], h[252], the cycle tag h[255],
+    // 1 / s_j, the flag
+    sa = q == 0   ? g + (j >= 1 ? j - 1 : 0)
+         : q == 1 ? h + 240
+         : q == 2 ? h + 252
+         : q == 3 ? h + 255
+         : q == 4 ? h + HDEV_LGSP + 65
+         : q == 5 ? (skip ? skip : h + 240)
+                  : h + 240;
   }
-  // the sums: wave w takes sums w, w + NW, ..., two at a time with their loads issued together
+  const double va = *sa, vb = *sb;
+  // the sums: wave w takes sums w, w + NW, ..., two at a time, 256 partials of each per pass with
+  // all their loads issued together (one pass for up to 256 partials)
   for (int s0 = wid; s0 < ns; s0 += 2 * NW) {
     const int s1 = s0 + NW;
     const bool two = s1 < ns;
+    const double* p0 = part + (int64_t)s0 * np;
+    const double* p1 = part + (int64_t)(two ? s1 : s0) * np;
     double a0 = 0.0, a1 = 0.0;
-    for (int i = lane; i < np; i += 64) {
-      const double x0 = part[(int64_t)s0 * np + i];
-      const double x1 = two ? part[(int64_t)s1 * np + i] : 0.0;
-      a0 += x0;
-      a1 += x1;
+    for (int i0 = lane; i0 < np; i0 += 256) {
+      double x0[4], x1[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 64 * q;
+        const int ic = i < np ? i : i0;
+        x0[q] = p0[ic];
+        x1[q] = p1[ic];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool in = i0 + 64 * q < np;
+        a0 += in ? x0[q] : 0.0;
+        a1 += (in && two) ? x1[q] : 0.0;
+      }
     }
     for (int o = 32; o > 0; o >>= 1) {
       a0 += __shfl_down(a0, o, 64);
@@ -1036,8 +1056,14 @@ __global__ void __launch_bounds__(LGS_FT) k_lgs_final(const double* __restrict__
       if (two) S[s1] = a1;
     }
   }
+  if (t < j - 1) {
+    csl[t] = va;
+    snl[t] = vb;
+  }
+  if (t >= 128 && t < 128 + j) pl[t - 128] = va;
+  if (t >= 192 && t < 198) sc[q] = ((q == 0 && j < 1) || (q == 5 && !skip)) ? 0.0 : va;
   __syncthreads();
-  if (t != 0) return;
+  if (sc[5] != 0.0 || t != 0) return;
   double aa = 0.0, ab = 0.0;
   for (int k = 0; k < j; ++k) {
     aa += S[2 * k] * S[2 * k];
@@ -1047,7 +1073,7 @@ __global__ void __launch_bounds__(LGS_FT) k_lgs_final(const double* __restrict__
   if (j > 0) {
     const double r2 = S[2 * j] - aa;
     rho = (r2 == r2) ? sqrt(fmax(r2, 0.0)) : r2;
-    const double gs = pl[65];  // 1 / s_j
+    const double gs = sc[4];  // 1 / s_j
     for (int k = 0; k < j; ++k) coll[k] = pl[k] + S[2 * k] * gs;
     const double hn = rho * gs;
     // Givens update of column jc = j - 1 (as givens_col, every operand from LDS)
