@@ -1560,11 +1560,13 @@ struct Solver {
       bool end = false;
       if (lagged()) {
         // columns this cycle may finish; step j finishes column j - 1 (its update sweep hands the
-        // estimate to the host), and the closing step L finishes the last.  The host keeps
-        // `ahead` steps enqueued beyond the one whose estimate it waits for, so that the stream
-        // has work while it reads; the steps after the one that ends the cycle return at once
-        // (two with the direct FP32 action, which reads the flag; else one, whose action runs).
-        const int ahead = direct64() ? 2 : 1;
+        // estimate to the host), and the closing step L finishes the last.  The host keeps one
+        // step enqueued beyond the one whose estimate it waits for, so that the stream has work
+        // while it reads and enqueues the next (one step is 30 us or more of kernels, four
+        // launches take less); the step after the one that ends the cycle returns at once (its
+        // action too when it is the direct FP32 one, which reads the flag).  Two steps ahead
+        // measured slower: 0.612 vs 0.602 ms per C2 step, 8.5 vs 8.2 ms on the triple point.
+        const int ahead = 1;
         const int L = std::max(1, std::min(m, o->gmres_maxit - total));
         struct Rec {
           bool sk;  // the step's action returns at once once the flag is set
