@@ -152,6 +152,7 @@ struct ilh_ctx {
   int tused = 0;
   int64_t tgen = 0;  // flushes so far (a pending slot index is valid within one generation)
   hipEvent_t xev0 = nullptr, xev1 = nullptr;  // open single-kernel slot, taken by the next klaunch
+  hipEvent_t pev = nullptr;  // end of the Newton solve's first norm pair (read while later work runs)
   double tms[ILH_TIMING_CLASSES] = {};
   int64_t tcnt[ILH_TIMING_CLASSES] = {};
   std::string err;
@@ -235,6 +236,8 @@ int launch_lin3d(ilh_ctx* c, int prec);
 int launch_jvp3d_q(ilh_ctx* c, int prec, const void* dk, void* out);
 int launch_fill(ilh_ctx* c, double* p, double v, int64_t n);
 int launch_fill2(ilh_ctx* c, double* p, double* q, double v, int64_t n);  // p = q = v, one launch
+// u <- u + dt k; with kc, k copied there by the same launch
+int launch_step_update(ilh_ctx* c, double* u, double dt, const double* k, double* kc, int64_t n);
 int launch_fillf(ilh_ctx* c, float* p, float v, int64_t n);
 int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int64_t n);  // y = a x + b y
 // w = u + t k; with z, its first nz (<= n) entries are zeroed by the same launch

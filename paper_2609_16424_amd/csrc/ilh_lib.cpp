@@ -319,6 +319,7 @@ void ilh_destroy(ilh_ctx* c) {
   for (void* p : c->qd)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  if (c->pev) (void)hipEventDestroy(c->pev);
   for (hipGraphExec_t e : c->gexec)
     if (e) (void)hipGraphExecDestroy(e);
   if (c->capstream) (void)hipStreamDestroy(c->capstream);
@@ -1652,9 +1653,24 @@ struct Solver {
   }
 };
 
+// The linearisation at k (state u + tau k) with its tangent coefficients formed at once for the
+// action precision prec (the linearised variant; else the state copies only)
+static int linearize_now(ilh_ctx* c, const double* k, const double* u, double tau, int prec) {
+  int st;
+  if ((st = ilh_linearize(c, k, u, tau))) return st;
+  if (c->jvp_variant == 0 && (lin2d_available(c) || lin3d_available(c))) {
+    const int ls = tstart_k(c, 5);
+    st = c->dim == 3 ? launch_lin3d(c, prec) : launch_lin2d(c, prec);
+    tstop_k(c, ls);
+    if (st) return st;
+    c->qd_ok[prec == 64 ? 1 : 0] = true;
+  }
+  return ILH_OK;
+}
+
 template <typename TV>
 static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* k_guess, double* k_out,
-                         const ilh_newton_opts* o, ilh_step_stats* st_out) {
+                         const ilh_newton_opts* o, ilh_step_stats* st_out, const double** k_final) {
   const int64_t n = c->nblock;
   int st;
   ilh_step_stats stats;
@@ -1693,6 +1709,24 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
     *b = c->hest[257];
     return ILH_OK;
   };
+  // The first pair (|R(0)|, |R(guess)|) is read while the stream already runs the linearisation
+  // at the first iterate, which is then taken in the common case (the iterate kept and not yet
+  // within the tolerance): an event marks the end of the pair's reduction, the linearisation
+  // is enqueued behind it, and the host waits for the event only.  A rejected guess or a met
+  // tolerance discards that linearisation (the next one overwrites it).
+  const double* k_lin = nullptr;  // the iterate the stream has been linearised at
+  auto read_first = [&](const double* kspec, double* a, double* b) -> int {
+    int s1;
+    if (o->max_newton < 1) return read_hp(a, b);
+    if (!c->pev) ILH_HIP(c, hipEventCreateWithFlags(&c->pev, hipEventDisableTiming));
+    ILH_HIP(c, hipEventRecord(c->pev, c->stream));
+    if ((s1 = linearize_now(c, kspec, u, tau, o->jvp_prec))) return s1;
+    k_lin = kspec;
+    ILH_HIP(c, hipEventSynchronize(c->pev));
+    *a = c->hest[256];
+    *b = c->hest[257];
+    return ILH_OK;
+  };
   if (!c->zero_ok) {
     if ((st = launch_fill(c, zero, 0.0, n))) return st;
     c->zero_ok = true;  // nothing else writes this part of the workspace
@@ -1709,7 +1743,7 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
     if ((st = residual_into(c, k_guess, u, tau, r, false))) return st;
     if ((st = dot_part(c, r, r, n, pb, &npb))) return st;
     if ((st = launch_pair_final(c, pa, npa, 0, pb, npb, 0, hp))) return st;
-    if ((st = read_hp(&r0, &nr))) return st;
+    if ((st = read_first(k_guess, &r0, &nr))) return st;
     r0 = std::sqrt(r0);
     nr = std::sqrt(nr);
     stats.res0 = r0;
@@ -1725,7 +1759,7 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
   } else {
     double unused;
     if ((st = launch_pair_final(c, pa, npa, 0, pa, npa, 0, hp))) return st;
-    if ((st = read_hp(&r0, &unused))) return st;
+    if ((st = read_first(zero, &r0, &unused))) return st;
     r0 = std::sqrt(r0);
     nr = r0;
     stats.res0 = r0;
@@ -1749,7 +1783,7 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
       c->err = "Newton reached max_newton";
       break;
     }
-    if ((st = ilh_linearize(c, k, u, tau))) return st;
+    if (!(it == 0 && k == k_lin) && (st = ilh_linearize(c, k, u, tau))) return st;
     if (o->prec_probe && (it == 0 || !o->prec_lag) && (st = build_probe_prec(c, o->prec_probe))) return st;
     // the Newton direction is -x with J x = R(k): the solve takes r as its right-hand side and
     // the trials step by -alpha x
@@ -1822,6 +1856,13 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
   stats.newton_max = it;
   stats.jvp_calls = S.jvp_calls;
   stats.status = status;
+  if (k_final && status == ILH_OK) {
+    // the caller finishes the step from the final iterate (its buffer stays valid until the
+    // context's next call): no copy and no synchronisation here
+    *k_final = k;
+    if (st_out) *st_out = stats;
+    return status;
+  }
   if (k_out) {
     if (k_out != k) ILH_HIP(c, hipMemcpyAsync(k_out, k, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   } else if (k != c->nwt) {
@@ -1835,11 +1876,13 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
 
 // FP32 Jacobian actions orthogonalise an FP32 basis unless the options ask for FP64 (basis64) or
 // the velocity block of the preconditioner runs PCG (FP64 vectors)
+// k_final (nullable): on success the final iterate's address is returned there instead of being
+// copied to k_out (or the workspace), and the stream is not synchronised
 static int stage_solve(ilh_ctx* c, const double* u, double tau, const double* k_guess, double* k_out,
-                       const ilh_newton_opts* o, ilh_step_stats* st_out) {
+                       const ilh_newton_opts* o, ilh_step_stats* st_out, const double** k_final = nullptr) {
   const bool f32 = o->jvp_prec == 32 && !o->basis64 && o->pcg_iters <= 0;
-  return f32 ? stage_solve_t<float>(c, u, tau, k_guess, k_out, o, st_out)
-             : stage_solve_t<double>(c, u, tau, k_guess, k_out, o, st_out);
+  return f32 ? stage_solve_t<float>(c, u, tau, k_guess, k_out, o, st_out, k_final)
+             : stage_solve_t<double>(c, u, tau, k_guess, k_out, o, st_out, k_final);
 }
 
 }  // namespace ilh
@@ -1943,10 +1986,11 @@ int ilh_implicit_step(ilh_ctx* c, double* u, double dt, const double* k_guess, d
   if (!c || !u || !o || !(dt > 0)) return ILH_EINVAL;
   if (o->restart < 1 || o->gmres_maxit < 1 || o->max_newton < 0 || (o->jvp_prec != 32 && o->jvp_prec != 64))
     return fail(c, ILH_EINVAL, "bad Newton options");
-  int status = stage_solve(c, u, 0.5 * dt, k_guess, k_out, o, st);
+  const double* kf = nullptr;
+  int status = stage_solve(c, u, 0.5 * dt, k_guess, k_out, o, st, &kf);
   if (status != ILH_OK) return status;
-  // u <- u + dt k (the stage rate is in k_out, else at the head of the Newton workspace)
-  int s2 = launch_axpby(c, u, dt, k_out ? k_out : c->nwt, 1.0, c->nblock);
+  // u <- u + dt k, and the stage rate to k_out, in one pass
+  int s2 = launch_step_update(c, u, dt, kf, (k_out && k_out != kf) ? k_out : nullptr, c->nblock);
   if (s2) return s2;
   ILH_HIP(c, hipStreamSynchronize(c->stream));
   return ILH_OK;

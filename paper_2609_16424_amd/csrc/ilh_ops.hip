@@ -48,6 +48,14 @@ __global__ void k_waxpy(double* w, const double* u, double t, const double* k, i
     if (i < nz) z[i] = 0.0;
   }
 }
+// u <- u + dt k, and k copied to kc (nullable) in the same pass
+__global__ void k_step_update(double* u, double dt, const double* k, double* kc, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double ki = k[i];
+    u[i] += dt * ki;
+    if (kc) kc[i] = ki;
+  }
+}
 __global__ void k_d2f(float* y, const double* x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
@@ -111,6 +119,12 @@ int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double*
   if (nz > n || nz < 0 || (nz > 0 && !z)) return fail(c, ILH_EINVAL, "waxpy: zero target longer than the vector");
   if (n <= 0) return ILH_OK;
   hipLaunchKernelGGL(k_waxpy, dim3(nblk(n)), dim3(TPB), 0, c->stream, w, u, t, k, n, z, nz);
+  ILH_HIP(c, hipGetLastError());
+  return ILH_OK;
+}
+int launch_step_update(ilh_ctx* c, double* u, double dt, const double* k, double* kc, int64_t n) {
+  if (n <= 0) return ILH_OK;
+  hipLaunchKernelGGL(k_step_update, dim3(nblk(n)), dim3(TPB), 0, c->stream, u, dt, k, kc, n);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
