@@ -49,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_2609_16424_amd/csrc/ilh_jvplin2d.hip", "paper_2609_16424_amd/csrc/ilh_lin.h",
                    "paper_2609_16424_amd/csrc/ilh_pointwise.h", "paper_2609_16424_amd/csrc/ilh_internal.h")
 TRAFFIC_SOURCE_END = {"paper_2609_16424_amd/csrc/ilh_internal.h": b"struct ilh_ctx {"}
-TRAFFIC_RECORD = {"sha256": "13dd24693ec3b9c091aa2b7a7ea9f8b023466dedc57811fcbc18c9e78c25e0f4",
+TRAFFIC_RECORD = {"sha256": "27386b64d2e5349a588d80bf98687b40352c5154e35d5c37b3c61c3dacac98fb",
                   "variant": "lin", "n": 128, "order": 3,
-                  "fetch_kib": 16609.0, "fetch_scale": 262144.0 / 131079.94,
-                  "write_kib": 3704.7, "write_scale": 262144.0 / 262144.0}
+                  "fetch_kib": 16609.3, "fetch_scale": 262144.0 / 131080.04,
+                  "write_kib": 3704.6, "write_scale": 262144.0 / 262144.0}
 
 
 def sources_sha256():

@@ -245,10 +245,20 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(VIS
     const double rj_l = P.rj0[ebase + (active ? z : 0)];
     // coefficient rows of this element row: field f at qd[((blk Q1D + qy) NQD + f) 64 + lane]
     const T* __restrict__ qb = qd + ((int64_t)ey * gridDim.x + sx) * (Q1D * NQD * 64);
+    // The row-loop instance (large meshes) streams them with the non-temporal hint: at 1024^2
+    // they are 1.8 GB read once per launch, and unhinted they evict the direction's and the
+    // output's lines, which neighbouring strips reuse (FP32 apply 534 -> 499 us, FP64 995 -> 970).
+    // The one-row instance (small meshes, whose coefficients stay in the caches between the
+    // Krylov iterations) keeps the plain load: the hint measured slower there.
     auto ldrow = [&](const int qy, T* cf) {
       const T* rb = sbase(qb + qy * (NQD * 64));
 #pragma unroll
-      for (int f = 0; f < NQD; ++f) cf[f] = ld32(rb, (uint32_t)(f * 64 + lane));
+      for (int f = 0; f < NQD; ++f) {
+        if constexpr (R1)
+          cf[f] = ld32(rb, (uint32_t)(f * 64 + lane));
+        else
+          cf[f] = ld32_nt(rb, (uint32_t)(f * 64 + lane));
+      }
     };
     T ca[NQD], cb[NQD];
     if (r == 0) {

@@ -309,6 +309,14 @@ __device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i) {
   return *(const T __attribute__((address_space(1)))*)p;
 }
 
+// The same load with the non-temporal hint (streamed data read once per launch: the hint keeps it
+// from evicting the lines that are reused, at the cost of the 64-bit address form)
+template <typename T>
+__device__ __forceinline__ T ld32_nt(const T* __restrict__ base, uint32_t i) {
+  const gbytes p = (gbytes)base + (uint64_t)(i * (uint32_t)sizeof(T));
+  return __builtin_nontemporal_load((const T __attribute__((address_space(1)))*)p);
+}
+
 // Store and no-return atomic add at a 32-bit element offset from a uniform base (the
 // scalar-base + vector-offset forms; byte offsets below 4 GiB, checked on the host).
 typedef char __attribute__((address_space(1))) * gbytes_w;
