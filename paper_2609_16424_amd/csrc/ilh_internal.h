@@ -358,7 +358,9 @@ int launch_jvp2d_q_f32to32(ilh_ctx* c, const float* dk, float* out, const double
 bool res2d_available(const ilh_ctx* c);
 // dmin (nullable, res2d_groups(c) entries): each work-group's smallest det J over its quadrature
 // points at the stage positions u_x + tau k_x
-int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin = nullptr);
+// (k2, r2 nullable: a second residual R(k2) into r2 by the same launch, without det J)
+int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin = nullptr,
+                 const double* k2 = nullptr, double* r2 = nullptr);
 int res2d_groups(const ilh_ctx* c);
 // *out = min_i part[i], i < np (device)
 int launch_min_final(ilh_ctx* c, const double* part, int np, double* out);

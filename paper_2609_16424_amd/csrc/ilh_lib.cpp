@@ -780,6 +780,20 @@ static int residual_into(ilh_ctx* c, const double* k, const double* u, double ta
   return st;
 }
 
+// R(k1) into r1 and R(k2) into r2 at the same u and tau, the velocity rows of both zero on entry:
+// one launch where the 2D strip kernel applies, else two
+static int residual_pair(ilh_ctx* c, const double* k1, double* r1, const double* k2, double* r2, const double* u,
+                         double tau) {
+  if (c->jvp_variant != 1 && res2d_available(c)) {
+    const int slot = tstart_k(c, 1);
+    const int st = launch_res2d(c, k1, u, tau, r1, nullptr, k2, r2);
+    tstop_k(c, slot);
+    return st;
+  }
+  const int st = residual_into(c, k1, u, tau, r1, false);
+  return st ? st : residual_into(c, k2, u, tau, r2, false);
+}
+
 int ilh_residual(ilh_ctx* c, const double* k, const double* u, double tau, double* r) {
   ILH_TRY
   if (!c || !k || !u || !r) return ILH_EINVAL;
@@ -1735,12 +1749,13 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
   // the velocity rows of both residual buffers zeroed by one launch
   if ((st = k_guess ? launch_fill2(c, rt + c->nh1, r + c->nh1, 0.0, c->nh1) : launch_fill(c, rt + c->nh1, 0.0, c->nh1)))
     return st;
-  if ((st = residual_into(c, zero, u, tau, rt, false))) return st;  // R(0) in rt
+  // R(0) in rt, and R(k_guess) in r (one launch for the two where the 2D strip kernel applies)
+  if ((st = k_guess ? residual_pair(c, zero, rt, k_guess, r, u, tau) : residual_into(c, zero, u, tau, rt, false)))
+    return st;
   if ((st = dot_part(c, rt, rt, n, pa, &npa))) return st;
   double r0 = 0.0, nr = 0.0;
   if (k_guess) {
     // |R(0)| and |R(k_guess)| read together
-    if ((st = residual_into(c, k_guess, u, tau, r, false))) return st;
     if ((st = dot_part(c, r, r, n, pb, &npb))) return st;
     if ((st = launch_pair_final(c, pa, npa, 0, pb, npb, 0, hp))) return st;
     if ((st = read_first(k_guess, &r0, &nr))) return st;

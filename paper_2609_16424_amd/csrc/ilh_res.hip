@@ -30,7 +30,8 @@ __device__ __forceinline__ double tg_source_c(double x, double y, double gam) {
 template <int D1D, int Q1D, int SRC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restrict__ u,
-        const double* __restrict__ kk, double tau, double* __restrict__ r, double* __restrict__ dmin) {
+        const double* __restrict__ kk1, double tau, double* __restrict__ r1, double* __restrict__ dmin1,
+        const double* __restrict__ kk2, double* __restrict__ r2) {
   constexpr int K = D1D - 1, L1D = K, NLD = L1D * L1D;
   constexpr int EPW = 64 / Q1D;
   constexpr int NS = K * EPW + 1;
@@ -57,7 +58,15 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
   __shared__ double sBLt[Q1D][L1D];
 
   const int lane = threadIdx.x;
-  const uint32_t tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  // grid.z = 2: a second residual, R(kk2) into r2, at the same u and tau, by a second set of
+  // work-groups (one launch for the two; the XCD map spreads the combined set)
+  const uint32_t nt = gridDim.x * gridDim.y;
+  const uint32_t tz = xcd_tile((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, nt * gridDim.z);
+  const bool second = tz >= nt;
+  const uint32_t tile = second ? tz - nt : tz;
+  const double* __restrict__ kk = second ? kk2 : kk1;
+  double* __restrict__ r = second ? r2 : r1;
+  double* __restrict__ dmin = second ? nullptr : dmin1;
   const int sx = tile % gridDim.x, ey = tile / gridDim.x;
   const int ex0 = sx * EPW;
   const int nx = P.n[0], ny = P.n[1];
@@ -250,7 +259,7 @@ k_res2d(const KParams P, const Tab2<double, D1D, Q1D> tb, const double* __restri
   if (dmin) {  // the work-group's smallest det J of the stage positions w_x
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dm = nan_min(dm, __shfl_xor(dm, o, 64));
-    if (lane == 0) dmin[blockIdx.y * gridDim.x + blockIdx.x] = dm;
+    if (lane == 0) dmin[tile] = dm;
   }
 
   // velocity rows that are not constrained: the Q1D columns of the (one or two) elements of the
@@ -631,7 +640,8 @@ bool res3d_available(const ilh_ctx* c) {
 }
 
 template <int K, int SRC>
-static void res_t(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin) {
+static void res_t(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin,
+                  const double* k2, double* r2) {
   constexpr int D1D = K + 1, Q1D = 2 * K, EPW = 64 / Q1D;
   Tab2<double, D1D, Q1D> tb;
   for (int q = 0; q < Q1D; ++q) {
@@ -642,8 +652,8 @@ static void res_t(ilh_ctx* c, const double* k, const double* u, double tau, doub
     for (int d = 0; d < D1D - 1; ++d) tb.BL[q][d] = c->h_BL[q * (D1D - 1) + d];
     tb.W[q] = c->h_w1[q];
   }
-  const dim3 grid((c->n[0] + EPW - 1) / EPW, c->n[1]);
-  klaunch(c, k_res2d<D1D, Q1D, SRC>, grid, dim3(64), 0, c->kp, tb, u, k, tau, r, dmin);
+  const dim3 grid((c->n[0] + EPW - 1) / EPW, c->n[1], k2 ? 2 : 1);
+  klaunch(c, k_res2d<D1D, Q1D, SRC>, grid, dim3(64), 0, c->kp, tb, u, k, tau, r, dmin, k2, r2);
 }
 
 int res3d_groups(const ilh_ctx* c) {
@@ -676,14 +686,17 @@ int res2d_groups(const ilh_ctx* c) {
 }
 
 // r = R(k; u, tau); the velocity rows of r must be zero on entry
-int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin) {
+int launch_res2d(ilh_ctx* c, const double* k, const double* u, double tau, double* r, double* dmin, const double* k2,
+                 double* r2) {
   if (!res2d_available(c)) return ILH_EINVAL;
+  if ((k2 == nullptr) != (r2 == nullptr) || (r2 && (r2 == r || dmin)))
+    return fail(c, ILH_EINVAL, "residual pair: both or neither of k2, r2; distinct outputs; no det J");
   const int code = 2 * c->k + (c->kp.tg_source ? 1 : 0);
   switch (code) {
-    case 4: res_t<2, 0>(c, k, u, tau, r, dmin); break;
-    case 5: res_t<2, 1>(c, k, u, tau, r, dmin); break;
-    case 6: res_t<3, 0>(c, k, u, tau, r, dmin); break;
-    case 7: res_t<3, 1>(c, k, u, tau, r, dmin); break;
+    case 4: res_t<2, 0>(c, k, u, tau, r, dmin, k2, r2); break;
+    case 5: res_t<2, 1>(c, k, u, tau, r, dmin, k2, r2); break;
+    case 6: res_t<3, 0>(c, k, u, tau, r, dmin, k2, r2); break;
+    case 7: res_t<3, 1>(c, k, u, tau, r, dmin, k2, r2); break;
     default: return ILH_EINVAL;
   }
   ILH_HIP(c, hipGetLastError());
