@@ -255,6 +255,9 @@ int dot_host(ilh_ctx* c, const double* x, const double* y, int64_t n, double* ou
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out);
 // the block partial sums of x . y into part (*np of them)
 int dot_part(ilh_ctx* c, const double* x, const double* y, int64_t n, double* part, int* np);
+// x . y into part and x2 . y2 into part2 (np partials each) by one launch
+int dot_part2(ilh_ctx* c, const double* x, const double* y, const double* x2, const double* y2, int64_t n,
+              double* part, double* part2, int* np);
 // out[0], out[1] = sum (mode 0) or minimum (mode 1) of each partial set, one launch
 int launch_pair_final(ilh_ctx* c, const double* pa, int na, int ma, const double* pb, int nb, int mb, double* out);
 // out = k1 or 2 k1 - k2 (nhist 1 or 2), position block u_v + tau out_v when tau > 0

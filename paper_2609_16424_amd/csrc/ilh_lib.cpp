@@ -1752,11 +1752,11 @@ static int stage_solve_t(ilh_ctx* c, const double* u, double tau, const double* 
   // R(0) in rt, and R(k_guess) in r (one launch for the two where the 2D strip kernel applies)
   if ((st = k_guess ? residual_pair(c, zero, rt, k_guess, r, u, tau) : residual_into(c, zero, u, tau, rt, false)))
     return st;
-  if ((st = dot_part(c, rt, rt, n, pa, &npa))) return st;
+  if ((st = k_guess ? dot_part2(c, rt, rt, r, r, n, pa, pb, &npa) : dot_part(c, rt, rt, n, pa, &npa))) return st;
+  npb = npa;
   double r0 = 0.0, nr = 0.0;
   if (k_guess) {
     // |R(0)| and |R(k_guess)| read together
-    if ((st = dot_part(c, r, r, n, pb, &npb))) return st;
     if ((st = launch_pair_final(c, pa, npa, 0, pb, npb, 0, hp))) return st;
     if ((st = read_first(k_guess, &r0, &nr))) return st;
     r0 = std::sqrt(r0);

@@ -201,7 +201,14 @@ __device__ __forceinline__ double block_min(double v) {
   return r;
 }
 
-__global__ void __launch_bounds__(TPB) k_dot_part(const double* x, const double* y, int64_t n, double* part) {
+// partial sums of x . y, one per block; grid.y = 2: the blocks of row 1 take x2 . y2 into part2
+__global__ void __launch_bounds__(TPB) k_dot_part(const double* x, const double* y, int64_t n, double* part,
+                                                  const double* x2, const double* y2, double* part2) {
+  if (blockIdx.y != 0) {
+    x = x2;
+    y = y2;
+    part = part2;
+  }
   double acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) acc += x[i] * y[i];
   acc = block_sum<TPB>(acc);
@@ -227,7 +234,7 @@ static int red_blocks(ilh_ctx* c, int64_t n) {
 
 int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_out) {
   const int nb = red_blocks(c, n);
-  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(TPB), 0, c->stream, x, y, n, c->red);
+  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(TPB), 0, c->stream, x, y, n, c->red, x, y, c->red);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, c->stream, c->red, nb, d_out, 0);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
@@ -235,7 +242,15 @@ int dot_dev(ilh_ctx* c, const double* x, const double* y, int64_t n, double* d_o
 
 int dot_part(ilh_ctx* c, const double* x, const double* y, int64_t n, double* part, int* np) {
   const int nb = red_blocks(c, n);
-  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(TPB), 0, c->stream, x, y, n, part);
+  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(TPB), 0, c->stream, x, y, n, part, x, y, part);
+  ILH_HIP(c, hipGetLastError());
+  *np = nb;
+  return ILH_OK;
+}
+int dot_part2(ilh_ctx* c, const double* x, const double* y, const double* x2, const double* y2, int64_t n,
+              double* part, double* part2, int* np) {
+  const int nb = red_blocks(c, n);
+  hipLaunchKernelGGL(k_dot_part, dim3(nb, 2), dim3(TPB), 0, c->stream, x, y, n, part, x2, y2, part2);
   ILH_HIP(c, hipGetLastError());
   *np = nb;
   return ILH_OK;
