@@ -332,6 +332,13 @@ int ilh_stage_solve(ilh_ctx* ctx, const double* ubase, double tau, const double*
  * M_E - tau dF^T/de (row-major).  Device pointers, nullable.  Other modes: ILH_EINVAL. */
 int ilh_probe_blocks(ilh_ctx* ctx, int mode, double* dv, double* einv);
 
+/* The inversion that ilh_probe_blocks and the probed preconditioner apply to the element blocks
+ * of eq. blockdiag_prec, on caller data: blocks [N_e][N_l][N_l] (device, row-major, the
+ * context's N_e and N_l) are replaced in place by their inverses (Gauss-Jordan elimination with
+ * partial pivoting in FP64); a block with a zero pivot column is replaced by the identity.
+ * Asynchronous. */
+int ilh_invert_blocks(ilh_ctx* ctx, double* blocks);
+
 /* One SDIRK step of Sec. 4 (scheme 2 = SD2, the implicit midpoint rule; 3 = SD3, the
  * three-stage L-stable third-order method of Alexander; 4 = SD4, the three-stage fourth-order
  * method of Crouzeix).  Stage i solves R(k_i; a_ii dt, u + dt sum_{j<i} a_ij k_j) = 0 by the

@@ -290,6 +290,16 @@ class Hydro:
         self._check(self.lib.ilh_probe_blocks(self.ctx, int(mode), _ptr(dv), _ptr(einv)))
         return dv, einv.view(self.Ne, nl, nl)
 
+    def invert_blocks(self, blocks):
+        """In place: each [Nl, Nl] block of blocks [Ne, Nl, Nl] (FP64, on the device) replaced by
+        its inverse, as the probed preconditioner inverts its element blocks (a block with a zero
+        pivot column becomes the identity)."""
+        nl = self.nl2 // self.Ne
+        self._stream()
+        self._check(self.lib.ilh_invert_blocks(self.ctx, self._vec(blocks.view(-1), self.Ne * nl * nl,
+                                                                     name="blocks")))
+        return blocks
+
     JVP_VARIANTS = {"lin": 0, "generic": 1, "recompute": 2}
 
     def set_viscosity_scale(self, mode, width=0.0):

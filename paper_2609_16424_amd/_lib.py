@@ -85,6 +85,7 @@ SIGNATURES = {
     "ilh_stage_solve": (I, [P, P, D, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_sdirk_step": (I, [P, P, D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats)]),
     "ilh_probe_blocks": (I, [P, I, P, P]),
+    "ilh_invert_blocks": (I, [P, P]),
     "ilh_guess_infer": (I, [P, C.POINTER(GuessModel), P, P, D, P, C.POINTER(I)]),
     "ilh_guess_mlp_fused": (I, [P, C.POINTER(GuessModel), P, P, P, I]),
     "ilh_adaptive_step": (I, [P, P, C.POINTER(D), D, I, P, P, C.POINTER(NewtonOpts), C.POINTER(StepStats), I,

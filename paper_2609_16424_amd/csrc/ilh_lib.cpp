@@ -2162,6 +2162,13 @@ int ilh_probe_blocks(ilh_ctx* c, int mode, double* dv, double* einv) {
   ILH_CATCH(c)
 }
 
+int ilh_invert_blocks(ilh_ctx* c, double* blocks) {
+  ILH_TRY
+  if (!c || !blocks) return ILH_EINVAL;
+  return launch_invert_blocks(c, blocks);
+  ILH_CATCH(c)
+}
+
 int ilh_sdirk_step(ilh_ctx* c, double* u, double dt, int scheme, const double* k_guess, double* k_out,
                    const ilh_newton_opts* o, ilh_step_stats* st) {
   ILH_TRY

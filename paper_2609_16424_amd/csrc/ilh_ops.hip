@@ -1602,9 +1602,97 @@ int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B) {
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
+// The same inversion with the block size fixed at compile time (N_l <= 9: the 2D and 3D energy
+// blocks of orders up to 3 in 2D, 2 in 3D): each work-group copies its 64 blocks to LDS with
+// coalesced loads, each lane inverts one block held in registers (the row exchanges of the
+// partial pivoting and the final column permutation as selects, so no register is indexed at
+// run time), and the results go back through LDS.  The arithmetic and its order are those of
+// k_invert_blocks; the per-lane global walk of that kernel took 190 us for the 5,376 blocks of
+// the triple point, most of it the latency of its dependent uncoalesced accesses.
+template <int NL>
+__global__ void __launch_bounds__(64) k_invert_blocks_n(double* B, int64_t Ne) {
+  constexpr int S = NL * NL;
+  __shared__ double sA[64 * S];
+  const int64_t e0 = (int64_t)blockIdx.x * 64;
+  const int nb = (int)(Ne - e0 < 64 ? Ne - e0 : 64);
+  double* base = B + e0 * S;
+  for (int i = threadIdx.x; i < nb * S; i += 64) sA[i] = base[i];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < nb) {
+    double A[NL][NL];
+    int piv[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      piv[r] = r;
+#pragma unroll
+      for (int q = 0; q < NL; ++q) A[r][q] = sA[t * S + r * NL + q];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) {
+      double best = fabs(A[c][c]);
+      int p = c;
+#pragma unroll
+      for (int r = c + 1; r < NL; ++r) {
+        const double v = fabs(A[r][c]);
+        if (v > best) {
+          best = v;
+          p = r;
+        }
+      }
+      ok = ok && best > 0.0;
+#pragma unroll
+      for (int r = c + 1; r < NL; ++r) {
+        const bool sw = r == p;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+          const double a = A[c][q], b = A[r][q];
+          A[c][q] = sw ? b : a;
+          A[r][q] = sw ? a : b;
+        }
+        const int pa = piv[c], pb = piv[r];
+        piv[c] = sw ? pb : pa;
+        piv[r] = sw ? pa : pb;
+      }
+      const double inv = 1.0 / A[c][c];
+      A[c][c] = 1.0;
+#pragma unroll
+      for (int q = 0; q < NL; ++q) A[c][q] *= inv;
+#pragma unroll
+      for (int r = 0; r < NL; ++r) {
+        if (r == c) continue;
+        const double f = A[r][c];
+        A[r][c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) A[r][q] -= f * A[c][q];
+      }
+    }
+    // (P A)^-1 P: column q of the result moves to column piv[q]; a singular block -> identity
+#pragma unroll
+    for (int r = 0; r < NL; ++r)
+#pragma unroll
+      for (int tc = 0; tc < NL; ++tc) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) v = piv[q] == tc ? A[r][q] : v;
+        sA[t * S + r * NL + tc] = ok ? v : (r == tc ? 1.0 : 0.0);
+      }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb * S; i += 64) base[i] = sA[i];
+}
+
 int launch_invert_blocks(ilh_ctx* c, double* B) {
   if (c->Nl > 32) return fail(c, ILH_EINVAL, "energy blocks larger than 32");
-  hipLaunchKernelGGL(k_invert_blocks, dim3((unsigned)((c->Ne + 63) / 64)), dim3(64), 0, c->stream, B, c->Ne, c->Nl);
+  const dim3 grid((unsigned)((c->Ne + 63) / 64));
+  switch (c->Nl) {
+    case 1: hipLaunchKernelGGL(k_invert_blocks_n<1>, grid, dim3(64), 0, c->stream, B, c->Ne); break;
+    case 4: hipLaunchKernelGGL(k_invert_blocks_n<4>, grid, dim3(64), 0, c->stream, B, c->Ne); break;
+    case 8: hipLaunchKernelGGL(k_invert_blocks_n<8>, grid, dim3(64), 0, c->stream, B, c->Ne); break;
+    case 9: hipLaunchKernelGGL(k_invert_blocks_n<9>, grid, dim3(64), 0, c->stream, B, c->Ne); break;
+    default: hipLaunchKernelGGL(k_invert_blocks, grid, dim3(64), 0, c->stream, B, c->Ne, c->Nl);
+  }
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }

@@ -49,3 +49,29 @@ def test_probe_preconditioner_same_solution():
         out.append(u)
     assert close(to_np(out[0]), to_np(out[1]), 1e-9)
     assert close(to_np(out[0]), to_np(out[2]), 1e-9)
+
+
+@pytest.mark.parametrize("prob,n,k", [("tg2d", (5, 4), 2), ("tg2d", (9, 8), 3), ("tg3d", (3, 2, 2), 2)])
+def test_invert_blocks_with_pivoting(prob, n, k):
+    """The element-block inversion of the probed preconditioner (ilh_invert_blocks) against
+    numpy's inverse on blocks that need row exchanges (a tiny or zero leading diagonal, rows in
+    reverse order of size), plus one singular block, which must come back as the identity.
+    More than 64 blocks (several work-groups with a partial last one) in the 2D cases."""
+    G = ilh.Hydro(prob, n, k)
+    nl = G.nl2 // G.Ne
+    rng = np.random.default_rng(100 + nl)
+    A = rng.standard_normal((G.Ne, nl, nl))
+    A[0::3] += 4.0 * np.eye(nl)[::-1]          # large anti-diagonal: a row exchange at every column
+    A[1::3, :, 0] *= 1e-3                        # small first column below a larger one
+    A[1::3, 0, 0] = 0.0                          # zero leading pivot
+    A[2] = np.outer(np.arange(1, nl + 1), np.arange(1, nl + 1))  # rank one: singular
+    ref = np.array([np.eye(nl) if i == 2 else np.linalg.inv(A[i]) for i in range(G.Ne)])
+    B = torch.from_numpy(A.copy()).to(G.device)
+    G.invert_blocks(B)
+    out = B.cpu().numpy()
+    assert np.isfinite(out).all()
+    np.testing.assert_array_equal(out[2], np.eye(nl))
+    cond = np.array([np.linalg.cond(A[i]) if i != 2 else 1.0 for i in range(G.Ne)])
+    for i in range(G.Ne):
+        tol = 1e-13 * cond[i]
+        assert np.abs(out[i] - ref[i]).max() <= tol * np.abs(ref[i]).max(), (i, np.abs(out[i] - ref[i]).max())
