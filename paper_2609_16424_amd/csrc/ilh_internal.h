@@ -321,10 +321,11 @@ template <typename TV>
 int launch_precond(ilh_ctx* c, const TV* r, TV* z, float* z32, double tau, int coupled,
                    TV* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
                    const GivensJob* job = nullptr);
-// probed diagonal blocks of the Jacobian (preconditioner option prec_probe)
-int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau);
+// probed diagonal blocks of the Jacobian (preconditioner option prec_probe); the direction
+// kernels also zero the velocity rows of yz (nullable: the output of the action they feed)
+int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau, float* yz = nullptr);
 int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D);
-int launch_probe_e_dir(ilh_ctx* c, float* d, int j);
+int launch_probe_e_dir(ilh_ctx* c, float* d, int j, float* yz = nullptr);
 int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
 int launch_invert_blocks(ilh_ctx* c, double* B);
 template <typename TV>

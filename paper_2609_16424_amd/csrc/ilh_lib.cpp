@@ -832,16 +832,9 @@ int ilh_linearize(ilh_ctx* c, const double* k, const double* u, double tau) {
   ILH_CATCH(c)
 }
 
-int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
-  ILH_TRY
-  if (!c || !dk || !jdk) return ILH_EINVAL;
-  if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+// The linearised action on an output whose velocity rows the caller has zeroed
+static int jvp_lin_zeroed(ilh_ctx* c, int prec, const void* dk, void* jdk) {
   int st;
-  if (prec == 64) {
-    if ((st = launch_fill(c, (double*)jdk + c->nh1, 0.0, c->nh1))) return st;
-  } else {
-    if ((st = launch_fillf(c, (float*)jdk + c->nh1, 0.0f, c->nh1))) return st;
-  }
   if (c->jvp_variant == 0 && (lin2d_available(c) || lin3d_available(c))) {
     const bool d3 = c->dim == 3;
     const int p = prec == 64 ? 1 : 0;
@@ -873,6 +866,19 @@ int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
   if (st == ILH_EINVAL) st = launch_elem(c, M_JVP, 32, nullptr, &a);
   tstop_k(c, slot);
   return st;
+}
+
+int ilh_jvp_lin(ilh_ctx* c, int prec, const void* dk, void* jdk) {
+  ILH_TRY
+  if (!c || !dk || !jdk) return ILH_EINVAL;
+  if (prec != 32 && prec != 64) return fail(c, ILH_EINVAL, "prec must be 32 or 64");
+  int st;
+  if (prec == 64) {
+    if ((st = launch_fill(c, (double*)jdk + c->nh1, 0.0, c->nh1))) return st;
+  } else {
+    if ((st = launch_fillf(c, (float*)jdk + c->nh1, 0.0f, c->nh1))) return st;
+  }
+  return jvp_lin_zeroed(c, prec, dk, jdk);
   ILH_CATCH(c)
 }
 
@@ -1170,13 +1176,14 @@ static int build_probe_prec(ilh_ctx* c, int mode) {
   const int ncol = c->dim == 3 ? M * M * M : M * M;
   for (int comp = 0; comp < c->dim; ++comp)
     for (int col = 0; col < ncol; ++col) {
-      if ((st = launch_probe_v_dir(c, d, comp, col, mode == 1 ? c->lin_tau : 0.0))) return st;
-      if ((st = ilh_jvp_lin(c, 32, d, y))) return st;
+      // (the direction kernel also zeroes the velocity rows of the action's output y)
+      if ((st = launch_probe_v_dir(c, d, comp, col, mode == 1 ? c->lin_tau : 0.0, y))) return st;
+      if ((st = jvp_lin_zeroed(c, 32, d, y))) return st;
       if ((st = launch_probe_v_take(c, y, comp, col, c->pdv))) return st;
     }
   for (int j = 0; j < c->Nl; ++j) {
-    if ((st = launch_probe_e_dir(c, d, j))) return st;
-    if ((st = ilh_jvp_lin(c, 32, d, y))) return st;
+    if ((st = launch_probe_e_dir(c, d, j, y))) return st;
+    if ((st = jvp_lin_zeroed(c, 32, d, y))) return st;
     if ((st = launch_probe_e_take(c, y, j, c->peinv))) return st;
   }
   return launch_invert_blocks(c, c->peinv);

@@ -917,7 +917,7 @@ __global__ void __launch_bounds__(LGS_DB) k_lgs_dots(const TV* __restrict__ V, i
 // j = N0 + N1 vectors beyond that are two chunks side by side (grid row 0: vectors [0, N0), the
 // norms and u_j . w; row 1: vectors [N0, j)), so u_j and w are read twice but in parallel.
 // Sums in the layout above (part[s][block]).
-static constexpr int LGS_NVMAX = 14;
+static constexpr int LGS_NVMAX = 15;
 
 template <typename TV, int NV, bool NORMS>
 __device__ __forceinline__ void lgs_dots_tile(const TV* __restrict__ V, int64_t ldv, int k0, int j,
@@ -1366,7 +1366,8 @@ int lgs_dots(ilh_ctx* c, const TV* V, int64_t ldv, int j, const TV* uj, const TV
   if (j > 64) return fail(c, ILH_EINVAL, "Gram-Schmidt: at most 64 basis vectors");
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + LGS_DT - 1) / LGS_DT));
   // the closing step has no w: its products are taken with u_j instead and not used
-  // fixed-count instances up to 14 vectors in FP32, 12 in FP64 (beyond, their registers spill)
+  // fixed-count instances up to 15 vectors in FP32 (a basis of restart length 15 and its
+  // closing step), 12 in FP64 (beyond, their registers spill)
   if (j <= (sizeof(TV) == 4 ? LGS_NVMAX : 12) && n * (int64_t)sizeof(TV) <= (int64_t)UINT32_MAX) {
     hipLaunchKernelGGL(lgs_dots_kernel<TV>(j), dim3(nb, j <= 6 ? 1 : 2), dim3(LGS_DB), 0, c->stream, V, ldv, uj,
                        w ? w : uj, n, part, skip);
@@ -1487,9 +1488,10 @@ struct NodeGrid {
 
 // direction: v component comp at the nodes of colour col = 1, x component comp there = tau
 __global__ void k_probe_v_dir(float* d, int64_t N, int dim, NodeGrid g, int M, int comp, int col, float tau,
-                              int64_t nblock) {
+                              int64_t nblock, float* yz) {
   const int64_t nh1 = (int64_t)dim * N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblock; i += (int64_t)gridDim.x * blockDim.x) {
+    if (yz && i >= nh1 && i < 2 * nh1) yz[i] = 0.f;  // the velocity rows of the action's output
     float v = 0.f;
     if (i < 2 * nh1) {
       const int64_t j = i < nh1 ? i : i - nh1;
@@ -1507,9 +1509,11 @@ __global__ void k_probe_v_take(const float* y, int64_t N, int dim, NodeGrid g, i
 }
 
 // direction: energy DOF j of every element = 1
-__global__ void k_probe_e_dir(float* d, int64_t nh1x2, int64_t nl2, int Nl, int j, int64_t nblock) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblock; i += (int64_t)gridDim.x * blockDim.x)
+__global__ void k_probe_e_dir(float* d, int64_t nh1x2, int64_t nl2, int Nl, int j, int64_t nblock, float* yz) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblock; i += (int64_t)gridDim.x * blockDim.x) {
     d[i] = (i >= nh1x2 && (i - nh1x2) % Nl == j) ? 1.f : 0.f;
+    if (yz && i >= nh1x2 / 2 && i < nh1x2) yz[i] = 0.f;  // the velocity rows of the action's output
+  }
 }
 
 // column j of every element's energy block
@@ -1576,10 +1580,10 @@ __global__ void k_invert_blocks(double* B, int64_t Ne, int Nl) {
   }
 }
 
-int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau) {
+int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau, float* yz) {
   NodeGrid g{{c->ng[0], c->ng[1], c->ng[2]}};
   hipLaunchKernelGGL(k_probe_v_dir, dim3(nblk(c->nblock, 8192)), dim3(TPB), 0, c->stream, d, c->N, c->dim, g,
-                     c->k + 1, comp, col, (float)tau, c->nblock);
+                     c->k + 1, comp, col, (float)tau, c->nblock, yz);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
@@ -1590,9 +1594,9 @@ int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
-int launch_probe_e_dir(ilh_ctx* c, float* d, int j) {
+int launch_probe_e_dir(ilh_ctx* c, float* d, int j, float* yz) {
   hipLaunchKernelGGL(k_probe_e_dir, dim3(nblk(c->nblock, 8192)), dim3(TPB), 0, c->stream, d, 2 * c->nh1, c->nl2, c->Nl,
-                     j, c->nblock);
+                     j, c->nblock, yz);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
