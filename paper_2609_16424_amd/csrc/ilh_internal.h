@@ -277,6 +277,8 @@ constexpr int HDEV_FLAG = 640;
 // step)
 constexpr int HDEV_LGSP = 704;
 constexpr int HDEV_LGSE = 770;
+// 771: |r|^2 of a restart residual, formed on the device and read by the next cycle's scaling
+constexpr int HDEV_RBETA2 = 771;
 constexpr int HDEV_LEN = 776;
 // y = H(0:n, 0:n)^-1 g
 int launch_trisolve(ilh_ctx* c, const double* G, int m, int n, double* y);

@@ -1146,10 +1146,13 @@ static int read_pair(ilh_ctx* c, double* a, double* b) {
 // y = x / beta with the cycle's Arnoldi scalars: h[240] = beta, h[252] = the residual target,
 // h[255] = the cycle's tag, s_0 = h[256] = 1, and the stage factor h[250] = tau that the step
 // kernels read
+// (beta2 nullable: beta = sqrt(*beta2), the norm of a restart residual formed on the device; a
+// zero norm gives a zero basis vector, whose cycle then ends at its first column)
 template <typename TV>
-__global__ void k_scale_copy(TV* y, const double* x, double beta, int64_t n, double* h, double target,
-                             double tag, double tau) {
-  const double f = 1.0 / beta;
+__global__ void k_scale_copy(TV* y, const double* x, double beta_h, int64_t n, double* h, double target,
+                             double tag, double tau, const double* beta2) {
+  const double beta = beta2 ? sqrt(*beta2) : beta_h;
+  const double f = beta > 0.0 ? 1.0 / beta : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     h[250] = tau;
     h[240] = beta;
@@ -1515,6 +1518,7 @@ struct Solver {
     *its = 0;
     if (beta == 0.0) return launch_fill(c, x, 0.0, n);
     const double target = o->gmres_rtol * beta;
+    const double* beta2_dev = nullptr;  // set once a restart forms the residual norm on the device
     const double* rhs = b;
     double* rbuf = c->nwt + 3 * n;  // tmp vector
     int total = 0;
@@ -1527,7 +1531,7 @@ struct Solver {
       // V0 = r / beta (beta, the target and the cycle's tag to the device), z_0 = P V0
       const double tag = (c->est_tag += 1.0);
       hipLaunchKernelGGL(k_scale_copy<TV>, dim3(1024), dim3(256), 0, c->stream, V, rhs, beta, n, hd, target, tag,
-                         tau);
+                         tau, beta2_dev);
       if ((st = precond(V, Z, V + n))) return st;
       int j_end = 0;
       bool stop = false;  // converged or out of iterations
@@ -1661,13 +1665,15 @@ struct Solver {
       if ((st = launch_trisolve_maxpy<TV>(c, x, Z, n, G, j_end, n, x_set))) return st;
       x_set = true;
       if (stop) break;
-      // restart: r = b - J x
+      // restart: r = b - J x, its |r|^2 left on the device for the next cycle's scaling kernel
+      // (no synchronisation; a restart residual that already meets the target, which the
+      // cycle's own estimates make rare, ends the next cycle at its first column)
+      if (total >= o->gmres_maxit) break;
       if ((st = apply(x, rbuf))) return st;
       if ((st = launch_axpby(c, rbuf, 1.0, b, -1.0, n))) return st;
       rhs = rbuf;
-      beta = nrm2(c, rbuf, n, &st);
-      if (st) return st;
-      if (beta <= target || total >= o->gmres_maxit) break;
+      if ((st = dot_dev(c, rbuf, rbuf, n, hd + HDEV_RBETA2))) return st;
+      beta2_dev = hd + HDEV_RBETA2;
     }
     *its = total;
     return ILH_OK;
