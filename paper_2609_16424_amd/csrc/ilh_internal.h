@@ -243,7 +243,8 @@ int launch_axpby(ilh_ctx* c, double* y, double a, const double* x, double b, int
 // w = u + t k; with z, its first nz (<= n) entries are zeroed by the same launch
 int launch_waxpy(ilh_ctx* c, double* w, const double* u, double t, const double* k, int64_t n, double* z = nullptr,
                  int64_t nz = 0);
-int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n);
+// y = (float) x; with z, its first nz (<= n) entries are zeroed by the same launch
+int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n, double* z = nullptr, int64_t nz = 0);
 int launch_cast_f2d(ilh_ctx* c, double* y, const float* x, int64_t n);
 int launch_mass_v(ilh_ctx* c, const double* x, double* y, int zero_first);
 int launch_mass_e_inv(ilh_ctx* c, const double* b, double* x);

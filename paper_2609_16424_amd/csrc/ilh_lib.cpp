@@ -1344,6 +1344,23 @@ struct Solver {
         skip_gen = c->tgen;
         return st;
       }
+      if (direct64()) {
+        // (restart residuals) the FP32 copy of x and the zero velocity rows of y in one launch,
+        // then the action writes the FP64 y itself at the host's tau
+        if (!have32 && (st = launch_cast_d2f(c, x32, x, c->nblock, y + c->nh1, c->nh1))) return st;
+        if (have32 && (st = launch_fill(c, y + c->nh1, 0.0, c->nh1))) return st;
+        if (!c->qd_ok[0]) {
+          const int ls = tstart_k(c, 5);
+          st = launch_lin2d(c, 32);
+          tstop_k(c, ls);
+          if (st) return st;
+          c->qd_ok[0] = true;
+        }
+        const int slot = tstart_k(c, 0);
+        st = launch_jvp2d_q_f32to64(c, x32, y, nullptr, nullptr);
+        tstop_k(c, slot);
+        return st;
+      }
       if (!have32 && (st = launch_cast_d2f(c, x32, x, c->nblock))) return st;
       if ((st = ilh_jvp_lin(c, 32, x32, y32))) return st;
       return launch_cast_f2d(c, y, y32, c->nblock);

@@ -56,9 +56,12 @@ __global__ void k_step_update(double* u, double dt, const double* k, double* kc,
     if (kc) kc[i] = ki;
   }
 }
-__global__ void k_d2f(float* y, const double* x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+// y = (float) x; the first nz (<= n) entries of z zeroed in the same pass (nz = 0: none)
+__global__ void k_d2f(float* y, const double* x, int64_t n, double* z, int64_t nz) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     y[i] = (float)x[i];
+    if (i < nz) z[i] = 0.0;
+  }
 }
 __global__ void k_f2d(double* y, const float* x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -128,9 +131,10 @@ int launch_step_update(ilh_ctx* c, double* u, double dt, const double* k, double
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
-int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n) {
+int launch_cast_d2f(ilh_ctx* c, float* y, const double* x, int64_t n, double* z, int64_t nz) {
+  if (nz > n || nz < 0 || (nz > 0 && !z)) return fail(c, ILH_EINVAL, "cast: zero target longer than the vector");
   if (n <= 0) return ILH_OK;
-  hipLaunchKernelGGL(k_d2f, dim3(nblk(n)), dim3(TPB), 0, c->stream, y, x, n);
+  hipLaunchKernelGGL(k_d2f, dim3(nblk(n)), dim3(TPB), 0, c->stream, y, x, n, z, nz);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
