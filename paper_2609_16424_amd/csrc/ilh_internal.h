@@ -325,10 +325,13 @@ int launch_precond(ilh_ctx* c, const TV* r, TV* z, float* z32, double tau, int c
                    TV* zero_v = nullptr, const double* tau_dev = nullptr, const double* rs = nullptr,
                    const GivensJob* job = nullptr);
 // probed diagonal blocks of the Jacobian (preconditioner option prec_probe); the direction
-// kernels also zero the velocity rows of yz (nullable: the output of the action they feed)
-int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau, float* yz = nullptr);
-int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D);
-int launch_probe_e_dir(ilh_ctx* c, float* d, int j, float* yz = nullptr);
+// kernels also zero the velocity rows of yz (nullable: the output of the action they feed),
+// after taking from it the previous probe's entries: the velocity diagonal of probe
+// (tcomp, tcol) into tD, column tj of the energy blocks into tB (each nullable)
+int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau, float* yz = nullptr, int tcomp = -1,
+                       int tcol = -1, double* tD = nullptr);
+int launch_probe_e_dir(ilh_ctx* c, float* d, int j, float* yz = nullptr, int tcomp = -1, int tcol = -1,
+                       double* tD = nullptr, int tj = -1, double* tB = nullptr);
 int launch_probe_e_take(ilh_ctx* c, const float* y, int j, double* B);
 int launch_invert_blocks(ilh_ctx* c, double* B);
 template <typename TV>

@@ -1177,18 +1177,25 @@ static int build_probe_prec(ilh_ctx* c, int mode) {
   float* y = c->kry32 + c->nblock;
   const int M = c->k + 1;
   const int ncol = c->dim == 3 ? M * M * M : M * M;
+  // each direction kernel first takes the previous probe's entries from the action output y,
+  // then zeroes y's velocity rows for the next action; the last probe is read off on its own
+  int pcomp = -1, pcol = -1;  // the previous velocity probe
   for (int comp = 0; comp < c->dim; ++comp)
     for (int col = 0; col < ncol; ++col) {
-      // (the direction kernel also zeroes the velocity rows of the action's output y)
-      if ((st = launch_probe_v_dir(c, d, comp, col, mode == 1 ? c->lin_tau : 0.0, y))) return st;
+      if ((st = launch_probe_v_dir(c, d, comp, col, mode == 1 ? c->lin_tau : 0.0, y, pcomp, pcol,
+                                   pcomp >= 0 ? c->pdv : nullptr)))
+        return st;
       if ((st = jvp_lin_zeroed(c, 32, d, y))) return st;
-      if ((st = launch_probe_v_take(c, y, comp, col, c->pdv))) return st;
+      pcomp = comp;
+      pcol = col;
     }
   for (int j = 0; j < c->Nl; ++j) {
-    if ((st = launch_probe_e_dir(c, d, j, y))) return st;
+    if ((st = launch_probe_e_dir(c, d, j, y, pcomp, pcol, j == 0 ? c->pdv : nullptr, j - 1,
+                                 j > 0 ? c->peinv : nullptr)))
+      return st;
     if ((st = jvp_lin_zeroed(c, 32, d, y))) return st;
-    if ((st = launch_probe_e_take(c, y, j, c->peinv))) return st;
   }
+  if ((st = launch_probe_e_take(c, y, c->Nl - 1, c->peinv))) return st;
   return launch_invert_blocks(c, c->peinv);
 }
 

@@ -1490,12 +1490,36 @@ struct NodeGrid {
   int ng[3];
 };
 
+// The previous probe's read-off, taken by the next probe's direction kernel from the action
+// output y before it zeroes y's velocity rows for the next action (each entry of y is read and
+// then zeroed by one thread): the velocity diagonal of probe (tcomp, tcol) into tD (nullable),
+// column tj of every element's energy block into tB (nullable)
+struct ProbeTake {
+  int tcomp, tcol;
+  double* tD;
+  int tj;
+  double* tB;
+};
+__device__ __forceinline__ void probe_take_zero(int64_t i, float* yz, int64_t N, int dim, const NodeGrid& g, int M,
+                                                int Nl, const ProbeTake& tk) {
+  const int64_t nh1 = (int64_t)dim * N;
+  if (i >= nh1 && i < 2 * nh1) {
+    const int64_t jv = i - nh1;
+    const int cc = (int)(jv / N);
+    if (tk.tD && cc == tk.tcomp && node_colour(jv - cc * N, dim, g.ng, M) == tk.tcol) tk.tD[jv] = (double)yz[i];
+    yz[i] = 0.f;  // the velocity rows of the next action's output
+  } else if (tk.tB && i >= 2 * nh1) {
+    const int64_t t = i - 2 * nh1;
+    tk.tB[t * Nl + tk.tj] = (double)yz[i];  // (e Nl + r) Nl + j with t = e Nl + r
+  }
+}
+
 // direction: v component comp at the nodes of colour col = 1, x component comp there = tau
 __global__ void k_probe_v_dir(float* d, int64_t N, int dim, NodeGrid g, int M, int comp, int col, float tau,
-                              int64_t nblock, float* yz) {
+                              int64_t nblock, float* yz, int Nl, ProbeTake tk) {
   const int64_t nh1 = (int64_t)dim * N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblock; i += (int64_t)gridDim.x * blockDim.x) {
-    if (yz && i >= nh1 && i < 2 * nh1) yz[i] = 0.f;  // the velocity rows of the action's output
+    if (yz) probe_take_zero(i, yz, N, dim, g, M, Nl, tk);
     float v = 0.f;
     if (i < 2 * nh1) {
       const int64_t j = i < nh1 ? i : i - nh1;
@@ -1506,17 +1530,13 @@ __global__ void k_probe_v_dir(float* d, int64_t N, int dim, NodeGrid g, int M, i
   }
 }
 
-__global__ void k_probe_v_take(const float* y, int64_t N, int dim, NodeGrid g, int M, int comp, int col, double* D) {
-  const int64_t nh1 = (int64_t)dim * N;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-    if (node_colour(i, dim, g.ng, M) == col) D[comp * N + i] = (double)y[nh1 + comp * N + i];
-}
-
 // direction: energy DOF j of every element = 1
-__global__ void k_probe_e_dir(float* d, int64_t nh1x2, int64_t nl2, int Nl, int j, int64_t nblock, float* yz) {
+__global__ void k_probe_e_dir(float* d, int64_t N, int dim, NodeGrid g, int M, int Nl, int j, int64_t nblock,
+                              float* yz, ProbeTake tk) {
+  const int64_t nh1x2 = 2 * (int64_t)dim * N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblock; i += (int64_t)gridDim.x * blockDim.x) {
     d[i] = (i >= nh1x2 && (i - nh1x2) % Nl == j) ? 1.f : 0.f;
-    if (yz && i >= nh1x2 / 2 && i < nh1x2) yz[i] = 0.f;  // the velocity rows of the action's output
+    if (yz) probe_take_zero(i, yz, N, dim, g, M, Nl, tk);
   }
 }
 
@@ -1584,23 +1604,21 @@ __global__ void k_invert_blocks(double* B, int64_t Ne, int Nl) {
   }
 }
 
-int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau, float* yz) {
+int launch_probe_v_dir(ilh_ctx* c, float* d, int comp, int col, double tau, float* yz, int tcomp, int tcol,
+                       double* tD) {
   NodeGrid g{{c->ng[0], c->ng[1], c->ng[2]}};
+  const ProbeTake tk{tcomp, tcol, yz ? tD : nullptr, 0, nullptr};
   hipLaunchKernelGGL(k_probe_v_dir, dim3(nblk(c->nblock, 8192)), dim3(TPB), 0, c->stream, d, c->N, c->dim, g,
-                     c->k + 1, comp, col, (float)tau, c->nblock, yz);
+                     c->k + 1, comp, col, (float)tau, c->nblock, yz, c->Nl, tk);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
-int launch_probe_v_take(ilh_ctx* c, const float* y, int comp, int col, double* D) {
+int launch_probe_e_dir(ilh_ctx* c, float* d, int j, float* yz, int tcomp, int tcol, double* tD, int tj,
+                       double* tB) {
   NodeGrid g{{c->ng[0], c->ng[1], c->ng[2]}};
-  hipLaunchKernelGGL(k_probe_v_take, dim3(nblk(c->N, 8192)), dim3(TPB), 0, c->stream, y, c->N, c->dim, g, c->k + 1,
-                     comp, col, D);
-  ILH_HIP(c, hipGetLastError());
-  return ILH_OK;
-}
-int launch_probe_e_dir(ilh_ctx* c, float* d, int j, float* yz) {
-  hipLaunchKernelGGL(k_probe_e_dir, dim3(nblk(c->nblock, 8192)), dim3(TPB), 0, c->stream, d, 2 * c->nh1, c->nl2, c->Nl,
-                     j, c->nblock, yz);
+  const ProbeTake tk{tcomp, tcol, yz ? tD : nullptr, tj, yz ? tB : nullptr};
+  hipLaunchKernelGGL(k_probe_e_dir, dim3(nblk(c->nblock, 8192)), dim3(TPB), 0, c->stream, d, c->N, c->dim, g, c->k + 1,
+                     c->Nl, j, c->nblock, yz, tk);
   ILH_HIP(c, hipGetLastError());
   return ILH_OK;
 }
